@@ -1,0 +1,298 @@
+"""Oracle, part 2: multigrid-preconditioned CG on assembled CSR (CPU, FP64).
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path may import this module.
+
+Follows the paper's Sec. 3 (Solvers):
+  * geometric prolongation P from the shape functions of the coarse grid
+    (bilinear / trilinear), restriction R = P^T, Galerkin coarse operators
+    A^{i+1} = P^T A^i P  (the Galerkin-projection equation of Sec. 3.2);
+  * the V-cycle of Algorithm 1 with weighted (point-block) Jacobi smoothing,
+    read as the standard recursion (the coarsest branch solves with the
+    coarsest operator; see the readings listed beside the oracle);
+  * the coarsest operator factorised once at setup (dense Cholesky here);
+  * conjugate gradients preconditioned by one V-cycle (Sec. 3.1).
+
+Readings of the paper that this code fixes (the paper is silent on them):
+  * coarse node I sits on fine node 2I; weights per axis w(0)=1, w(+-1)=1/2;
+  * supported fine dofs are dropped from P on level 0 (P~ = M P); coarse
+    levels carry no supports;
+  * a dof whose Galerkin diagonal is exactly zero gets a unit diagonal;
+  * "n levels" counts the fine grid; automatic level count stops at the first
+    level with fewer than `max_coarse` dofs.
+No zero dropping happens anywhere: every sparse product keeps its structural
+pattern.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from typing import List, Optional
+
+import numpy as np
+import scipy.linalg as sla
+import scipy.sparse as sp
+
+from . import fem
+
+
+# ------------------------------------------------------------ level planning
+def level_dofs(nel, L: int, ceil: bool = False) -> List[int]:
+    """dofs of levels 0..L-1 when each level halves the element counts
+    (ceil(n/2) for odd counts if `ceil`); constrained dofs are counted."""
+    out = []
+    cur = list(nel)
+    for _ in range(L):
+        out.append(len(nel) * int(np.prod([n + 1 for n in cur])))
+        cur = [(n + 1) // 2 if ceil else n // 2 for n in cur]
+    return out
+
+
+def plan_levels(nel, n_levels: int = 0, max_coarse: int = 1000) -> int:
+    """Number of geometric levels (fine grid included).  n_levels > 0 is taken
+    as given; otherwise coarsen while the current level has >= max_coarse dofs
+    and every element count is even."""
+    if n_levels > 0:
+        return n_levels
+    L = 1
+    cur = list(nel)
+    while len(nel) * int(np.prod([n + 1 for n in cur])) >= max_coarse and all(n % 2 == 0 and n >= 2 for n in cur):
+        cur = [n // 2 for n in cur]
+        L += 1
+    return L
+
+
+# ------------------------------------------------------------ sparse helpers
+def _ones(A: sp.csr_matrix) -> sp.csr_matrix:
+    B = A.copy().tocsr()
+    B.data = np.ones_like(B.data)
+    return B
+
+
+def structural_matmul(A: sp.spmatrix, B: sp.spmatrix) -> sp.csr_matrix:
+    """A @ B with the structural pattern (entries that cancel to zero are kept)."""
+    A = sp.csr_matrix(A)
+    B = sp.csr_matrix(B)
+    S = (_ones(A) @ _ones(B)).tocsr()       # positive sums never cancel
+    S.sort_indices()
+    C = (A @ B).tocsr()
+    C.sort_indices()
+    out = S.copy()
+    out.data = np.zeros_like(out.data, dtype=np.float64)
+    # scatter C's stored values into S's pattern
+    Cc = C.tocoo()
+    rows_S = np.repeat(np.arange(S.shape[0]), np.diff(S.indptr))
+    keyS = rows_S.astype(np.int64) * S.shape[1] + S.indices
+    keyC = Cc.row.astype(np.int64) * S.shape[1] + Cc.col
+    pos = np.searchsorted(keyS, keyC)
+    out.data[pos] = Cc.data
+    return out
+
+
+def structural_add(A: sp.spmatrix, B: sp.spmatrix) -> sp.csr_matrix:
+    """A + B on the union of the two patterns (no zero dropping)."""
+    A = sp.csr_matrix(A)
+    B = sp.csr_matrix(B)
+    S = (_ones(A) + _ones(B)).tocsr()
+    S.sort_indices()
+    out = S.copy()
+    out.data = np.zeros_like(out.data, dtype=np.float64)
+    rows_S = np.repeat(np.arange(S.shape[0]), np.diff(S.indptr))
+    keyS = rows_S.astype(np.int64) * S.shape[1] + S.indices
+    for M in (A, B):
+        Mc = M.tocoo()
+        key = Mc.row.astype(np.int64) * S.shape[1] + Mc.col
+        np.add.at(out.data, np.searchsorted(keyS, key), Mc.data)
+    return out
+
+
+def galerkin(P: sp.spmatrix, A: sp.spmatrix) -> sp.csr_matrix:
+    """A_c = P^T (A P), structural pattern; exactly-zero diagonals set to 1."""
+    Ac = structural_matmul(sp.csr_matrix(P.T), structural_matmul(A, P))
+    d = Ac.diagonal()
+    if np.any(d == 0.0):
+        Ac = Ac.tolil()
+        for i in np.nonzero(d == 0.0)[0]:
+            Ac[i, i] = 1.0
+        Ac = Ac.tocsr()
+    Ac.sort_indices()
+    return Ac
+
+
+# ------------------------------------------------------- geometric transfers
+def geometric_prolongator(nel, fixed: Optional[np.ndarray] = None) -> sp.csr_matrix:
+    """P (fine dofs x coarse dofs) from coarse-grid shape functions: fine node i
+    takes weight prod_axes w(i_a - 2 I_a) from coarse node I, w(0)=1,
+    w(+-1)=1/2, identity over components.  If `fixed` is given, the rows of
+    supported fine dofs are dropped (P~ = M P)."""
+    dim = len(nel)
+    cel = [n // 2 for n in nel]
+    fcoords = fem.node_coordinates(nel).astype(np.int64)
+    nf = fcoords.shape[0]
+    rows, cols, vals = [], [], []
+    for off in np.array(list(np.ndindex(*([3] * dim)))) - 1:
+        # coarse node 2I = i - off  requires (i - off) even and inside
+        c2 = fcoords - off[None, :]
+        ok = np.all((c2 % 2 == 0) & (c2 >= 0), axis=1)
+        C = c2 // 2
+        ok &= np.all(C <= np.array(cel)[None, :], axis=1)
+        w = np.prod(np.where(off == 0, 1.0, 0.5))
+        fi = np.nonzero(ok)[0]
+        ci = fem.node_index(cel, C[fi])
+        for c in range(dim):
+            rows.append(dim * fi + c)
+            cols.append(dim * ci + c)
+            vals.append(np.full(fi.shape[0], w))
+    r = np.concatenate(rows)
+    c = np.concatenate(cols)
+    v = np.concatenate(vals)
+    nc = dim * int(np.prod([n + 1 for n in cel]))
+    if fixed is not None and len(fixed) > 0:
+        m = fem.free_mask(dim * nf, fixed)
+        keep = m[r] > 0
+        r, c, v = r[keep], c[keep], v[keep]
+    P = sp.csr_matrix((v, (r, c)), shape=(dim * nf, nc))
+    P.sort_indices()
+    return P
+
+
+# ----------------------------------------------------------- smoothers
+def block_diag_inverse(A: sp.csr_matrix, bs: int) -> sp.csr_matrix:
+    """Inverse of the point-block diagonal of A (blocks of bs x bs) as a
+    block-diagonal CSR matrix."""
+    n = A.shape[0]
+    nb = n // bs
+    blocks = np.zeros((nb, bs, bs))
+    C = A.tocoo()
+    same = (C.row // bs) == (C.col // bs)
+    blocks[C.row[same] // bs, C.row[same] % bs, C.col[same] % bs] = C.data[same]
+    inv = np.linalg.inv(blocks)
+    base = np.arange(nb)[:, None, None] * bs
+    r = np.broadcast_to(base + np.arange(bs)[None, :, None], (nb, bs, bs))
+    c = np.broadcast_to(base + np.arange(bs)[None, None, :], (nb, bs, bs))
+    Dinv = sp.csr_matrix((inv.ravel(), (r.ravel(), c.ravel())), shape=(n, n))
+    Dinv.sort_indices()
+    return Dinv
+
+
+def point_diag_inverse(A: sp.csr_matrix) -> sp.csr_matrix:
+    return sp.diags(1.0 / A.diagonal()).tocsr()
+
+
+# ----------------------------------------------------------- hierarchy
+@dataclass
+class Hierarchy:
+    A: List[sp.csr_matrix]                 # level operators (A[0] = K~)
+    P: List[sp.csr_matrix]                 # P[l]: level l+1 -> level l
+    Dinv: List[sp.csr_matrix]              # smoother block inverses per level
+    bs: List[int]                          # block size per level
+    omega: float
+    nu_pre: int
+    nu_post: int
+    chol: Optional[tuple] = None           # factor of the coarsest operator
+    kinds: List[str] = field(default_factory=list)   # 'geo' or 'sa' per transfer
+    aggregates: List[Optional[np.ndarray]] = field(default_factory=list)
+    info: dict = field(default_factory=dict)
+
+    @property
+    def L(self) -> int:
+        return len(self.A)
+
+
+def build_geometric(nel, E: np.ndarray, KE: np.ndarray, fixed: np.ndarray, L: int,
+                    omega: float = 0.5, nu_pre: int = 1, nu_post: int = 1,
+                    point_jacobi: bool = False) -> Hierarchy:
+    """Pure geometric hierarchy with L levels (fine grid included)."""
+    dim = len(nel)
+    K = fem.assemble(nel, E, KE)
+    A0 = fem.apply_dirichlet(K, fixed)
+    As, Ps = [A0], []
+    cur = list(nel)
+    for l in range(L - 1):
+        if any(n % 2 for n in cur):
+            raise ValueError(f"element counts {cur} not divisible by 2 at level {l}")
+        P = geometric_prolongator(tuple(cur), fixed if l == 0 else None)
+        Ps.append(P)
+        As.append(galerkin(P, As[-1]))
+        cur = [n // 2 for n in cur]
+    return finish(As, Ps, [dim] * L, omega, nu_pre, nu_post, point_jacobi, ["geo"] * (L - 1))
+
+
+def finish(As, Ps, bss, omega, nu_pre, nu_post, point_jacobi=False, kinds=None,
+           aggregates=None) -> Hierarchy:
+    Dinv = [point_diag_inverse(A) if point_jacobi else block_diag_inverse(A, b)
+            for A, b in zip(As, bss)]
+    Ac = As[-1].toarray()
+    chol = sla.cho_factor(Ac, lower=True)
+    return Hierarchy(As, Ps, Dinv, list(bss), omega, nu_pre, nu_post, chol,
+                     kinds or [], aggregates or [None] * len(As))
+
+
+# ----------------------------------------------------------- V-cycle
+def vcycle(H: Hierarchy, b: np.ndarray, level: int = 0) -> np.ndarray:
+    """Algorithm 1 (standard recursion): zero start, nu_pre weighted block-Jacobi
+    sweeps, restrict the residual with P^T, recurse (or solve exactly on the
+    coarsest level), prolongate and add, nu_post sweeps."""
+    if level == H.L - 1:
+        return sla.cho_solve(H.chol, b)
+    A, Dinv, w = H.A[level], H.Dinv[level], H.omega
+    x = np.zeros_like(b)
+    for _ in range(H.nu_pre):
+        x = x + w * (Dinv @ (b - A @ x))
+    bc = H.P[level].T @ (b - A @ x)
+    x = x + H.P[level] @ vcycle(H, bc, level + 1)
+    for _ in range(H.nu_post):
+        x = x + w * (Dinv @ (b - A @ x))
+    return x
+
+
+# ----------------------------------------------------------- PCG
+@dataclass
+class SolveResult:
+    u: np.ndarray
+    iters: int
+    relres: float            # recursive residual / ||f||
+    true_relres: float       # ||f - K u|| / ||f||
+    compliance: float
+    converged: bool
+    history: List[float] = field(default_factory=list)
+
+
+def pcg(apply_A, precond, f: np.ndarray, rtol: float, u0: Optional[np.ndarray] = None,
+        max_iters: int = 5000) -> SolveResult:
+    """Preconditioned conjugate gradients (Hestenes-Stiefel form).  Stops when the
+    recursive residual satisfies ||r_k|| <= rtol ||f||."""
+    u = np.zeros_like(f) if u0 is None else u0.copy()
+    r = f - apply_A(u) if u0 is not None else f.copy()
+    nf = np.linalg.norm(f)
+    if nf == 0.0:
+        return SolveResult(u, 0, 0.0, 0.0, 0.0, True)
+    hist = [np.linalg.norm(r) / nf]
+    z = precond(r)
+    p = z.copy()
+    rz = r @ z
+    it = 0
+    while hist[-1] > rtol and it < max_iters:
+        q = apply_A(p)
+        alpha = rz / (p @ q)
+        u = u + alpha * p
+        r = r - alpha * q
+        it += 1
+        hist.append(np.linalg.norm(r) / nf)
+        if hist[-1] <= rtol:
+            break
+        z = precond(r)
+        rz_new = r @ z
+        p = z + (rz_new / rz) * p
+        rz = rz_new
+    true = np.linalg.norm(f - apply_A(u)) / nf
+    return SolveResult(u, it, hist[-1], true, float(f @ u), hist[-1] <= rtol, hist)
+
+
+def mg_pcg(H: Hierarchy, f: np.ndarray, rtol: float, u0=None, max_iters: int = 5000) -> SolveResult:
+    A0 = H.A[0]
+    return pcg(lambda v: A0 @ v, lambda r: vcycle(H, r), f, rtol, u0, max_iters)
+
+
+def dense_solve(A: sp.spmatrix, f: np.ndarray) -> np.ndarray:
+    """Direct solve by dense Cholesky (small systems only)."""
+    return sla.cho_solve(sla.cho_factor(A.toarray(), lower=True), f)

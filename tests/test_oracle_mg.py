@@ -1,0 +1,141 @@
+"""Pins of the oracle's multigrid layer (no GPU): the paper's stated level sizes,
+exact properties of shape-function transfers and Galerkin operators, the
+V-cycle as a symmetric positive definite preconditioner, and PCG against a
+dense direct solve."""
+import json
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import scipy.sparse as sp
+
+from oracle import fem, mg
+import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "level_sizes.json")
+
+
+def test_level_sizes_from_paper():
+    cases = json.load(open(GOLDEN))["cases"]
+    for c in cases:
+        nel = tuple(c["nel"])
+        for L, dofs in c.get("exact", {}).items():
+            got = mg.level_dofs(nel, int(L), ceil=c.get("ceil", False))[-1]
+            assert got == dofs, (c["cite"], L, got)
+        for limit, L in c.get("limits", {}).items():
+            assert mg.plan_levels(nel, 0, int(limit)) == L, (c["cite"], limit)
+        if "fine_about" in c:
+            fine = mg.level_dofs(nel, 1)[0]
+            assert abs(fine - c["fine_about"]) / c["fine_about"] < 0.05
+
+
+@pytest.mark.parametrize("nel", [(6, 4), (4, 2, 6)])
+def test_prolongator_reproduces_linear_fields(nel):
+    dim = len(nel)
+    P = mg.geometric_prolongator(nel)
+    # rows sum to one per component (partition of unity)
+    rs = np.asarray(P.sum(axis=1)).ravel()
+    assert np.all(rs == 1.0)
+    Xf = fem.node_coordinates(nel)
+    Xc = fem.node_coordinates([n // 2 for n in nel], 2.0)
+    G = np.array([[0.25, -1.0, 0.5], [2.0, 0.125, -0.75], [-0.5, 0.375, 1.5]])[:dim, :dim]
+    uc = (Xc @ G.T + 0.5).ravel()
+    uf = (Xf @ G.T + 0.5).ravel()
+    assert np.max(np.abs(P @ uc - uf)) == 0.0          # dyadic weights: exact
+    # rigid-body modes map to rigid-body modes
+    assert np.max(np.abs(P @ fem.rigid_body_modes(Xc) - fem.rigid_body_modes(Xf))) == 0.0
+
+
+@pytest.mark.parametrize("nel", [(8, 6), (4, 4, 6)])
+def test_galerkin_is_rediscretisation(nel):
+    """Uniform material, no supports: P^T K_h P equals the stiffness matrix of
+    the grid with twice the element size (nested spaces).  In 2D KE does not
+    depend on h; in 3D KE(2h) = 2 KE(h)."""
+    dim = len(nel)
+    KE = fem.element_stiffness(dim, 0.3)
+    Kh = fem.assemble(nel, np.ones(int(np.prod(nel))), KE)
+    cel = tuple(n // 2 for n in nel)
+    K2h = fem.assemble(cel, np.ones(int(np.prod(cel))), fem.element_stiffness(dim, 0.3, 2.0))
+    Ac = mg.galerkin(mg.geometric_prolongator(nel), Kh)
+    assert Ac.nnz == K2h.nnz
+    assert np.array_equal(Ac.indptr, K2h.indptr) and np.array_equal(Ac.indices, K2h.indices)
+    assert np.max(np.abs(Ac.data - K2h.data)) <= 1e-14 * np.max(np.abs(K2h.data))
+
+
+def _small_hier(dim=2, nel=(8, 4), L=3, seed=5, omega=0.5, nu=1):
+    p = synth.small_case(dim, nel, seed=seed)
+    KE = fem.element_stiffness(dim, p.nu)
+    E = fem.simp(p.rho, p.p, p.E0, p.Emin)
+    H = mg.build_geometric(p.nel, E, KE, p.fixed, L, omega=omega, nu_pre=nu, nu_post=nu)
+    return p, H
+
+
+@pytest.mark.parametrize("dim,nel,L", [(2, (16, 8), 4), (3, (8, 4, 4), 3)])
+def test_levels_symmetric_spd_and_stencil_pattern(dim, nel, L):
+    p, H = _small_hier(dim, nel, L)
+    for l, A in enumerate(H.A):
+        assert abs(A - A.T).max() <= 1e-14 * abs(A).max()
+        assert np.linalg.eigvalsh(A.toarray()).min() > 0
+        if l > 0:
+            # geometric coarse levels: full block stencil of nodes sharing an element
+            cel = tuple(n // 2 ** l for n in nel)
+            pat = fem.assemble(cel, np.ones(int(np.prod(cel))), fem.element_stiffness(dim, 0.3))
+            assert np.array_equal(A.indptr, pat.indptr) and np.array_equal(A.indices, pat.indices)
+
+
+def _dense_precond(H):
+    n = H.A[0].shape[0]
+    return np.column_stack([mg.vcycle(H, e) for e in np.eye(n)])
+
+
+def test_vcycle_symmetric_positive_definite():
+    p, H = _small_hier(2, (8, 4), 3)
+    M = _dense_precond(H)
+    assert np.max(np.abs(M - M.T)) <= 1e-12 * np.max(np.abs(M))
+    assert np.linalg.eigvalsh(0.5 * (M + M.T)).min() > 0
+
+
+def test_two_grid_contraction():
+    """Error propagation I - M A of a two-level cycle contracts in the A norm."""
+    p, H = _small_hier(2, (8, 4), 2)
+    A = H.A[0].toarray()
+    M = _dense_precond(H)
+    Lc = np.linalg.cholesky(A)
+    Eprop = Lc.T @ (np.eye(A.shape[0]) - M @ A) @ np.linalg.inv(Lc.T)
+    assert np.linalg.norm(Eprop, 2) < 1.0
+
+
+def test_single_level_is_exact():
+    p, H = _small_hier(2, (8, 4), 1)
+    r = mg.mg_pcg(H, p.loads[0], 1e-12)
+    assert r.iters == 1
+
+
+@pytest.mark.parametrize("uniform", [True, False])
+def test_mbb_pcg_matches_dense(uniform):
+    p = synth.mbb_2d(uniform)
+    KE = fem.element_stiffness(2, p.nu)
+    E = fem.simp(p.rho, p.p, p.E0, p.Emin)
+    H = mg.build_geometric(p.nel, E, KE, p.fixed, 3, omega=0.6, nu_pre=2, nu_post=2)
+    f = p.loads[0]
+    r = mg.mg_pcg(H, f, 1e-13)
+    ud = mg.dense_solve(H.A[0], f)
+    assert np.linalg.norm(r.u - ud) <= 1e-9 * np.linalg.norm(ud)
+    # with a zero start the CG iterate satisfies f.u = u.K u up to ||u|| ||r||
+    A0 = H.A[0]
+    res = np.linalg.norm(f - A0 @ r.u)
+    assert abs(f @ r.u - r.u @ (A0 @ r.u)) <= np.linalg.norm(r.u) * res * 1.01 + 1e-15
+    assert r.u[p.fixed].max() == 0.0 and r.u[p.fixed].min() == 0.0
+
+
+def test_rtol_1e8_compliance_close_to_exact():
+    p = synth.mbb_2d(False)
+    KE = fem.element_stiffness(2, p.nu)
+    E = fem.simp(p.rho, p.p, p.E0, p.Emin)
+    H = mg.build_geometric(p.nel, E, KE, p.fixed, 3, omega=0.6, nu_pre=2, nu_post=2)
+    ud = mg.dense_solve(H.A[0], p.loads[0])
+    r = mg.mg_pcg(H, p.loads[0], 1e-8)
+    assert r.converged and r.relres <= 1e-8
+    c_ref = p.loads[0] @ ud
+    assert abs(r.compliance - c_ref) <= 1e-9 * abs(c_ref)
