@@ -1,0 +1,184 @@
+/*
+ * topomg — multigrid-preconditioned conjugate gradients for SIMP-penalised
+ * linear elasticity on uniform quad (Q4) / hex (Hex8) grids, on one AMD
+ * Instinct MI355X (gfx950).
+ *
+ * The library solves K(rho) u = f, the finite-element equilibrium equation of
+ * the compliance problem (Sec. 2 of Peetz & Elbanna, "On the use of Multigrid
+ * Preconditioners for Topology Optimization"), with
+ *   K(rho)  = sum_e E(rho_e) L_e^T KE L_e,
+ *   E(rho)  = Emin + (E0 - Emin) rho^p              (modified SIMP, Sec. 2),
+ * by conjugate gradients (Sec. 3.1) preconditioned with one multigrid V-cycle
+ * (Algorithm 1) whose hierarchy uses shape-function prolongation and Galerkin
+ * coarse operators A^{i+1} = P^T A^i P on the finest levels (Sec. 3.2) and,
+ * optionally, smoothed aggregation on the coarser ones (the hybrid of
+ * Sec. 4.3 / 4.4).  The V-cycle may run in FP32 inside an FP64 flexible CG.
+ *
+ * Conventions shared by every entry point
+ *   mesh     nel[0..dim-1] elements per axis, square/cubic elements of edge h.
+ *            node (i,j[,k]) = i + (nx+1)(j + (ny+1)k);  dof = dim*node + c;
+ *            element (ex,ey[,ez]) = ex + nx(ey + ny ez).
+ *            Element local node order: 2D counter-clockwise from the lower-left
+ *            corner; 3D bottom face (z = ez) counter-clockwise, then top face.
+ *   2D       plane stress, unit thickness.
+ *   supports homogeneous Dirichlet conditions on a list of dof ids.  The
+ *            operator solved is K~ = M K M + (I - M) (M = mask of free dofs),
+ *            so u = 0 on supported dofs and loads given there are ignored.
+ *   memory   "_dev" pointers are device memory, everything else host memory.
+ *            The caller owns every buffer it passes; the library keeps no
+ *            caller pointer past the call that received it.  A hierarchy owns
+ *            the device memory it allocates (hipMalloc) until tm_destroy.
+ *   streams  `stream` is a hipStream_t (NULL = default stream).  All device
+ *            work of a call is ordered on that stream.  Calls that return
+ *            host-visible results synchronise that stream before returning.
+ *   errors   Negative status: the call failed and outputs are undefined;
+ *            tm_last_error() gives a message (per thread).  Positive status:
+ *            a warning, outputs are valid.  Arguments are validated before any
+ *            device work starts.
+ *   threads  Distinct hierarchies may be used from distinct threads.  One
+ *            hierarchy may run several solves at once only through distinct
+ *            solve states (tm_solve_begin) on distinct streams.
+ */
+#ifndef TOPOMG_H
+#define TOPOMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TM_OK = 0,
+    TM_NOT_CONVERGED = 1,      /* iteration limit reached; u is the last iterate   */
+    TM_ERR_ARG = -1,           /* invalid argument                                 */
+    TM_ERR_OOM = -2,           /* device allocation failed                         */
+    TM_ERR_DEVICE = -3,        /* HIP runtime error                                */
+    TM_ERR_NOT_SPD = -4,       /* coarsest operator is not positive definite       */
+    TM_ERR_BREAKDOWN = -5,     /* CG breakdown: p^T K p <= 0 or z^T r <= 0         */
+    TM_ERR_STATE = -6          /* call out of order (e.g. a state already ended)   */
+} tm_status;
+
+typedef struct { int32_t dim; int32_t nel[3]; double h; } tm_mesh;
+typedef struct { double p, E0, Emin, nu; } tm_material;
+typedef struct { int64_t n; const int64_t* dofs; } tm_bcs;      /* host array of n dof ids */
+
+enum { TM_SMOOTH_BLOCK_JACOBI = 0,   /* point-block (one block per node), Sec. 4.1 */
+       TM_SMOOTH_POINT_JACOBI = 1,   /* diag(A) as printed in Algorithm 1           */
+       TM_SMOOTH_CHEBYSHEV = 2 };    /* Jacobi-preconditioned Chebyshev, Sec. 4.1   */
+enum { TM_OUTER_FCG = 0,             /* flexible CG, beta = -z^T q / p^T q          */
+       TM_OUTER_PCG = 1 };           /* standard PCG, beta = z_k^T r_k / z_{k-1}^T r_{k-1} */
+enum { TM_LEVEL_FINE = 0, TM_LEVEL_GEOMETRIC = 1, TM_LEVEL_AGGREGATION = 2 };
+
+typedef struct {
+    int32_t n_levels;      /* levels including the fine grid; 0 = automatic                      */
+    int32_t n_geometric;   /* geometric levels including the fine grid; 0 = all geometric;
+                              otherwise smoothed aggregation continues below level n_geometric-1 */
+    int32_t max_coarse;    /* automatic depth: stop at the first level with fewer dofs (1000)    */
+    int32_t smoother;      /* TM_SMOOTH_*                                                        */
+    int32_t nu_pre;        /* pre-smoothing sweeps (>= 1)                                        */
+    int32_t nu_post;       /* post-smoothing sweeps (>= 1)                                       */
+    double  omega;         /* Jacobi weight (0.5)                                                */
+    double  sa_beta;       /* strength threshold beta (0.003)                                    */
+    int32_t vcycle_fp;     /* 32: FP32 V-cycle (FP64 outer loop); 64: FP64 everywhere            */
+    int32_t outer;         /* TM_OUTER_FCG or TM_OUTER_PCG                                        */
+    int32_t max_iters;     /* outer iteration limit (1000)                                        */
+    int32_t check_every;   /* host convergence check period in iterations; 0 = adaptive          */
+} tm_options;
+
+typedef struct tm_hierarchy tm_hierarchy;       /* opaque */
+typedef struct tm_solve_state tm_solve_state;   /* opaque */
+
+/* Fill `o` with the defaults listed above (FCG, FP32 V-cycle, block Jacobi 1/1, omega 0.5). */
+void tm_default_options(tm_options* o);
+
+/* Device bytes a hierarchy plus workspace for n_rhs concurrent right-hand sides
+ * will hold, computed on the host only (admission control). */
+tm_status tm_plan_bytes(const tm_mesh* mesh, const tm_options* opts, int32_t n_rhs, size_t* bytes);
+
+/* Build the multigrid hierarchy for densities rho_dev[n_el] (FP64, in [0,1]):
+ * SIMP moduli, fine point-block diagonal, geometric Galerkin levels, optional
+ * smoothed-aggregation levels, coarsest Cholesky factor (Secs. 2, 3.2, 4).
+ * Errors: TM_ERR_ARG (bad mesh/material/options, element counts not divisible
+ * by 2^(n_geometric-1), dof id out of range), TM_ERR_NOT_SPD, TM_ERR_OOM.
+ * rho values are checked on the device (finite and in [0,1]). */
+tm_status tm_setup(const tm_mesh* mesh, const tm_material* mat, const double* rho_dev,
+                   const tm_bcs* bcs, const tm_options* opts, void* stream, tm_hierarchy** out);
+
+/* Numeric re-setup for new densities on the same mesh, supports and options
+ * (a design iteration): the structure and all allocations are reused. */
+tm_status tm_update_density(tm_hierarchy* h, const double* rho_dev, void* stream);
+
+/* Solve K~ u_k = M f_k for k < n_rhs.  f_dev and u_dev hold n_rhs vectors of
+ * n_dof FP64 values, one after the other.  If use_u0, u_dev holds the start
+ * vectors (warm start, Sec. 4); otherwise the start is zero.  Stops when the
+ * recursive residual satisfies ||r|| <= rtol ||M f||.  Host outputs per
+ * right-hand side: iterations, compliance f^T u (Sec. 2), and the true
+ * relative residual ||M f - K~ u|| / ||M f||.  Any output pointer may be NULL.
+ * Returns TM_NOT_CONVERGED if some right-hand side hit max_iters. */
+tm_status tm_solve(tm_hierarchy* h, int32_t n_rhs, const double* f_dev, double rtol,
+                   int32_t use_u0, double* u_dev, int32_t* iters, double* compliance,
+                   double* relres, void* stream);
+
+/* Iteration-level control for a scheduler (continuous batching).
+ * begin:   copies f, sets up the start vector on `stream` and returns a state
+ *          bound to (h, stream, u_dev); u_dev must stay valid until end.
+ * advance: enqueues up to k further iterations without waiting.
+ * poll:    non-blocking; *done = 1 once every right-hand side has stopped.
+ * batch_advance: advance for n states at once (each on its own stream, so the
+ *          work of different requests overlaps on the device).
+ * end:     waits, writes the outputs of tm_solve and frees the state. */
+tm_status tm_solve_begin(tm_hierarchy* h, int32_t n_rhs, const double* f_dev, double rtol,
+                         int32_t use_u0, double* u_dev, void* stream, tm_solve_state** st);
+tm_status tm_solve_advance(tm_solve_state* st, int32_t k_iters);
+tm_status tm_solve_poll(tm_solve_state* st, int32_t* done);
+tm_status tm_batch_advance(int32_t n, tm_solve_state* const* st, int32_t k_iters);
+tm_status tm_solve_end(tm_solve_state* st, int32_t* iters, double* compliance, double* relres);
+
+/* ---- parity and inspection (tests) --------------------------------------- */
+/* y = A_level x on the device, FP64 (fp = 64) or FP32 (fp = 32) data.  Level 0
+ * is K~ (matrix-free), level l > 0 the stored coarse operator. */
+tm_status tm_apply(tm_hierarchy* h, int32_t level, int32_t fp, const void* x_dev, void* y_dev,
+                   void* stream);
+/* x = V(M b): one V-cycle of Algorithm 1 from x = 0 on level 0, in the given precision
+ * (as applied inside tm_solve: entries of b on supported dofs are ignored, and x
+ * is zero there). */
+tm_status tm_vcycle(tm_hierarchy* h, int32_t fp, const void* b_dev, void* x_dev, void* stream);
+/* Level shape: rows (dofs), stored nonzeros in CSR form, TM_LEVEL_*, dofs per node. */
+tm_status tm_level_info(const tm_hierarchy* h, int32_t level, int64_t* n_rows, int64_t* nnz,
+                        int32_t* kind, int32_t* block);
+int32_t tm_num_levels(const tm_hierarchy* h);
+/* Level operator (level >= 1) as CSR, FP64 values, ascending columns (host buffers
+ * of n_rows+1, nnz, nnz entries).  The fine level (matrix-free) is not exported. */
+tm_status tm_export_csr(const tm_hierarchy* h, int32_t level, int64_t* rowptr, int32_t* colidx,
+                        double* vals);
+/* Prolongator from level+1 to level as CSR (rows: dofs of `level`).  Call with
+ * NULL arrays to get *nnz first. */
+tm_status tm_export_prolongator(const tm_hierarchy* h, int32_t level, int64_t* n_rows,
+                                int64_t* nnz, int64_t* rowptr, int32_t* colidx, double* vals);
+/* Aggregate id of every node of an aggregation input level (host int32[n_nodes]). */
+tm_status tm_export_aggregates(const tm_hierarchy* h, int32_t level, int32_t* agg_of_node);
+/* Point-block diagonal inverse of a level, FP64, [node][bs*bs] row-major blocks. */
+tm_status tm_export_dinv(const tm_hierarchy* h, int32_t level, double* dinv);
+/* Element-to-node table of a mesh (host int32[n_el * 2^dim], local order above). */
+tm_status tm_export_connectivity(const tm_mesh* mesh, int32_t* conn);
+/* Device bytes held by the hierarchy (not counting solve states). */
+tm_status tm_hierarchy_bytes(const tm_hierarchy* h, size_t* bytes);
+
+/* Kernel timing for roofline reporting: when enabled, every launch of the fine
+ * operator apply (class 0) or of the coarse stencil operator (class 1) inside
+ * solves of `h` is bracketed by HIP events on its stream; read returns the
+ * launch count and the summed event time in milliseconds, then resets. */
+tm_status tm_kernel_timing(tm_hierarchy* h, int32_t kernel_class, int32_t enable);
+tm_status tm_kernel_timing_read(tm_hierarchy* h, int32_t kernel_class, int64_t* launches,
+                                double* total_ms);
+
+void tm_destroy(tm_hierarchy* h);
+const char* tm_status_string(tm_status s);
+const char* tm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TOPOMG_H */

@@ -1,0 +1,1233 @@
+// Host orchestration and the C ABI of libtopomg: argument checks, level plan,
+// hierarchy setup (Secs. 2, 3.2, 4), the V-cycle of Algorithm 1, the outer
+// CG loop driver, solve states for iteration-level scheduling, and exports.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "tm_internal.h"
+
+namespace tmi {
+
+// ------------------------------------------------------------------ errors
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+struct TmException : std::runtime_error {
+    tm_status code;
+    TmException(tm_status c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+void fail(tm_status code, const std::string& msg) { throw TmException(code, msg); }
+
+void check_hip(hipError_t e, const char* what) {
+    if (e == hipSuccess) return;
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
+        fail(TM_ERR_OOM, std::string(what) + ": " + hipGetErrorString(e));
+    fail(TM_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+template <typename F>
+static tm_status guarded(F&& f) {
+    try {
+        f();
+        return TM_OK;
+    } catch (const TmException& e) {
+        set_error(e.what());
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        set_error("host allocation failed");
+        return TM_ERR_OOM;
+    } catch (const std::exception& e) {
+        set_error(e.what());
+        return TM_ERR_DEVICE;
+    }
+}
+
+// ------------------------------------------------------------------ memory
+template <typename T>
+static T* dalloc(std::vector<void*>& list, size_t& bytes, size_t n) {
+    void* p = nullptr;
+    const size_t b = std::max<size_t>(n, 1) * sizeof(T);
+    const hipError_t e = hipMalloc(&p, b);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        fail(TM_ERR_OOM, "hipMalloc of " + std::to_string(b) + " bytes failed");
+    }
+    list.push_back(p);
+    bytes += b;
+    return (T*)p;
+}
+template <typename T>
+static T* halloc(tm_hierarchy* h, size_t n) { return dalloc<T>(h->allocs, h->bytes, n); }
+
+static void free_list(std::vector<void*>& list) {
+    for (void* p : list) (void)hipFree(p);
+    list.clear();
+}
+
+static hipStream_t S(void* s) { return (hipStream_t)s; }
+
+// ------------------------------------------------------------------ element stiffness
+// KE for E = 1 of the bilinear / trilinear element on a square / cube of edge h:
+// sum over the 2^dim Gauss points of B^T D B |J| (exact for these elements).
+// 2D plane stress with unit thickness; 3D isotropic.  Local corner order as
+// in loc2 / loc3.
+static void element_stiffness(int dim, double nu, double h, std::vector<double>& KE) {
+    const int npe = 1 << dim, nd = dim * npe;
+    KE.assign((size_t)nd * nd, 0.0);
+    int corner[8][3];
+    for (int z = 0; z < (dim == 3 ? 2 : 1); ++z)
+        for (int y = 0; y < 2; ++y)
+            for (int x = 0; x < 2; ++x) {
+                const int a = dim == 3 ? loc3(x, y, z) : loc2(x, y);
+                corner[a][0] = x;
+                corner[a][1] = y;
+                corner[a][2] = z;
+            }
+    const int nv = dim == 2 ? 3 : 6;
+    double D[6][6] = {};
+    if (dim == 2) {
+        const double c = 1.0 / (1.0 - nu * nu);
+        D[0][0] = D[1][1] = c;
+        D[0][1] = D[1][0] = c * nu;
+        D[2][2] = c * (1.0 - nu) / 2.0;
+    } else {
+        const double c = 1.0 / ((1.0 + nu) * (1.0 - 2.0 * nu));
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) D[i][j] = c * (i == j ? 1.0 - nu : nu);
+        for (int i = 3; i < 6; ++i) D[i][i] = c * (1.0 - 2.0 * nu) / 2.0;
+    }
+    const double g = 1.0 / std::sqrt(3.0);
+    const double jac = h / 2.0;
+    const double detJ = std::pow(jac, dim);
+    const int ngp = 1 << dim;
+    for (int gp = 0; gp < ngp; ++gp) {
+        double xi[3] = {(gp & 1) ? g : -g, (gp & 2) ? g : -g, (gp & 4) ? g : -g};
+        double grad[8][3];
+        for (int a = 0; a < npe; ++a)
+            for (int d = 0; d < dim; ++d) {
+                double v = 1.0 / (1 << dim);
+                for (int e = 0; e < dim; ++e) {
+                    const double sgn = corner[a][e] ? 1.0 : -1.0;
+                    v *= (e == d) ? sgn : (1.0 + sgn * xi[e]);
+                }
+                grad[a][d] = v / jac;
+            }
+        double B[6][24] = {};
+        for (int a = 0; a < npe; ++a) {
+            if (dim == 2) {
+                B[0][2 * a] = grad[a][0];
+                B[1][2 * a + 1] = grad[a][1];
+                B[2][2 * a] = grad[a][1];
+                B[2][2 * a + 1] = grad[a][0];
+            } else {
+                B[0][3 * a] = grad[a][0];
+                B[1][3 * a + 1] = grad[a][1];
+                B[2][3 * a + 2] = grad[a][2];
+                B[3][3 * a + 1] = grad[a][2];
+                B[3][3 * a + 2] = grad[a][1];
+                B[4][3 * a] = grad[a][2];
+                B[4][3 * a + 2] = grad[a][0];
+                B[5][3 * a] = grad[a][1];
+                B[5][3 * a + 1] = grad[a][0];
+            }
+        }
+        for (int i = 0; i < nd; ++i)
+            for (int j = 0; j < nd; ++j) {
+                double s = 0.0;
+                for (int p = 0; p < nv; ++p)
+                    for (int q = 0; q < nv; ++q) s += B[p][i] * D[p][q] * B[q][j];
+                KE[(size_t)i * nd + j] += s * detJ;
+            }
+    }
+    for (int i = 0; i < nd; ++i)
+        for (int j = 0; j < i; ++j) {
+            const double s = 0.5 * (KE[(size_t)i * nd + j] + KE[(size_t)j * nd + i]);
+            KE[(size_t)i * nd + j] = KE[(size_t)j * nd + i] = s;
+        }
+}
+
+// Q[c][a][b]: weight of parent corner b at child c's corner a (coarse shape
+// functions), child c at offsets (c&1, c>>1&1, c>>2&1) inside its parent.
+static void child_weights(int dim, std::vector<double>& Q) {
+    const int npe = 1 << dim;
+    Q.assign((size_t)npe * npe * npe, 0.0);
+    int off[8][3];
+    for (int z = 0; z < (dim == 3 ? 2 : 1); ++z)
+        for (int y = 0; y < 2; ++y)
+            for (int x = 0; x < 2; ++x) {
+                const int a = dim == 3 ? loc3(x, y, z) : loc2(x, y);
+                off[a][0] = x;
+                off[a][1] = y;
+                off[a][2] = z;
+            }
+    auto phi = [](int d) { return d == 0 ? 1.0 : (d == 1 || d == -1) ? 0.5 : 0.0; };
+    for (int c = 0; c < npe; ++c) {
+        const int cp[3] = {c & 1, (c >> 1) & 1, (c >> 2) & 1};
+        for (int a = 0; a < npe; ++a)
+            for (int b = 0; b < npe; ++b) {
+                double w = 1.0;
+                for (int k = 0; k < dim; ++k) w *= phi(cp[k] + off[a][k] - 2 * off[b][k]);
+                Q[((size_t)c * npe + a) * npe + b] = w;
+            }
+    }
+}
+
+// ------------------------------------------------------------------ validation / plan
+static int64_t nodes_of(const int* nel, int dim) {
+    int64_t n = 1;
+    for (int d = 0; d < dim; ++d) n *= (int64_t)nel[d] + 1;
+    return n;
+}
+
+static void check_mesh(const tm_mesh* m) {
+    if (!m) fail(TM_ERR_ARG, "mesh is NULL");
+    if (m->dim != 2 && m->dim != 3) fail(TM_ERR_ARG, "mesh.dim must be 2 or 3");
+    for (int d = 0; d < m->dim; ++d)
+        if (m->nel[d] < 1 || m->nel[d] > (1 << 20)) fail(TM_ERR_ARG, "mesh.nel out of range");
+    if (!(m->h > 0.0) || !std::isfinite(m->h)) fail(TM_ERR_ARG, "mesh.h must be positive");
+    if (nodes_of(m->nel, m->dim) * m->dim >= ((int64_t)1 << 31))
+        fail(TM_ERR_ARG, "mesh too large (dofs must fit in int32)");
+}
+
+static void check_opts(const tm_options* o) {
+    if (!o) fail(TM_ERR_ARG, "options are NULL");
+    if (o->n_levels < 0 || o->n_levels > 24) fail(TM_ERR_ARG, "n_levels out of range");
+    if (o->n_geometric < 0 || o->n_geometric > 24) fail(TM_ERR_ARG, "n_geometric out of range");
+    if (o->n_geometric == 1) fail(TM_ERR_ARG, "aggregation needs an assembled level: n_geometric >= 2");
+    if (o->max_coarse < 1) fail(TM_ERR_ARG, "max_coarse must be >= 1");
+    if (o->smoother != TM_SMOOTH_BLOCK_JACOBI && o->smoother != TM_SMOOTH_POINT_JACOBI)
+        fail(TM_ERR_ARG, "smoother not supported");
+    if (o->nu_pre < 1 || o->nu_post < 1 || o->nu_pre > 16 || o->nu_post > 16)
+        fail(TM_ERR_ARG, "nu_pre / nu_post must be in 1..16");
+    if (!(o->omega > 0.0 && o->omega < 2.0)) fail(TM_ERR_ARG, "omega must be in (0, 2)");
+    if (!(o->sa_beta >= 0.0 && o->sa_beta < 1.0)) fail(TM_ERR_ARG, "sa_beta must be in [0, 1)");
+    if (o->vcycle_fp != 32 && o->vcycle_fp != 64) fail(TM_ERR_ARG, "vcycle_fp must be 32 or 64");
+    if (o->outer != TM_OUTER_FCG && o->outer != TM_OUTER_PCG) fail(TM_ERR_ARG, "outer must be FCG or PCG");
+    if (o->max_iters < 1) fail(TM_ERR_ARG, "max_iters must be >= 1");
+    if (o->check_every < 0) fail(TM_ERR_ARG, "check_every must be >= 0");
+    if (o->n_levels > 0 && o->n_geometric > o->n_levels) fail(TM_ERR_ARG, "n_geometric > n_levels");
+}
+
+static void check_material(const tm_material* m) {
+    if (!m) fail(TM_ERR_ARG, "material is NULL");
+    if (!(m->E0 > 0.0) || !std::isfinite(m->E0)) fail(TM_ERR_ARG, "E0 must be positive");
+    if (!(m->Emin > 0.0) || !(m->Emin <= m->E0)) fail(TM_ERR_ARG, "Emin must be in (0, E0]");
+    if (!(m->p >= 1.0 && m->p <= 16.0)) fail(TM_ERR_ARG, "p must be in [1, 16]");
+    if (!(m->nu > -1.0 && m->nu < 0.5)) fail(TM_ERR_ARG, "nu must be in (-1, 0.5)");
+}
+
+// number of geometric levels (fine grid included) and whether aggregation follows
+struct Plan {
+    int Lg = 1;
+    bool sa = false;
+    int L_total = 1;        // known for pure geometric hierarchies
+};
+
+static Plan plan_levels(const tm_mesh* m, const tm_options* o) {
+    Plan p;
+    const int dim = m->dim;
+    int cur[3] = {m->nel[0], m->nel[1], dim == 3 ? m->nel[2] : 1};
+    auto dofs = [&](const int* c) { return nodes_of(c, dim) * dim; };
+    auto even = [&](const int* c) {
+        for (int d = 0; d < dim; ++d)
+            if (c[d] % 2 || c[d] < 2) return false;
+        return true;
+    };
+    if (o->n_geometric > 0) {
+        p.Lg = o->n_geometric;
+        p.sa = (o->n_levels == 0) || (o->n_levels > o->n_geometric);
+    } else if (o->n_levels > 0) {
+        p.Lg = o->n_levels;
+    } else {
+        p.Lg = 1;
+        while (dofs(cur) >= o->max_coarse && even(cur)) {
+            for (int d = 0; d < dim; ++d) cur[d] /= 2;
+            ++p.Lg;
+        }
+        cur[0] = m->nel[0];
+        cur[1] = m->nel[1];
+        cur[2] = dim == 3 ? m->nel[2] : 1;
+    }
+    for (int l = 0; l + 1 < p.Lg; ++l) {
+        if (!even(cur))
+            fail(TM_ERR_ARG, "element counts must be divisible by 2^(geometric levels - 1)");
+        for (int d = 0; d < dim; ++d) cur[d] /= 2;
+    }
+    p.L_total = p.Lg;
+    return p;
+}
+
+}  // namespace tmi
+
+using namespace tmi;
+
+// ============================================================================ setup
+namespace tmi {
+
+static void alloc_level_geo(tm_hierarchy* h, Level& L, int l) {
+    const int dim = h->dim;
+    L.dim = dim;
+    L.bs = dim;
+    for (int d = 0; d < 3; ++d) {
+        L.nel[d] = d < dim ? (h->mesh.nel[d] >> l) : 1;
+        L.nn[d] = d < dim ? L.nel[d] + 1 : 1;
+    }
+    L.n_nodes = nodes_of(L.nel, dim);
+    L.n = L.n_nodes * dim;
+    const int bb = dim * dim;
+    L.dinv64 = halloc<double>(h, (size_t)bb * L.n_nodes);
+    L.dinv32 = halloc<float>(h, (size_t)bb * L.n_nodes);
+    if (l == 0) {
+        L.kind = TM_LEVEL_FINE;
+        L.E64 = halloc<double>(h, h->n_el);
+        L.E32 = halloc<float>(h, h->n_el);
+        L.nmask = halloc<uint8_t>(h, L.n_nodes);
+    } else {
+        L.kind = TM_LEVEL_GEOMETRIC;
+        L.nst = dim == 3 ? 27 : 9;
+        L.st64 = halloc<double>(h, (size_t)L.nst * bb * L.n_nodes);
+        L.st32 = halloc<float>(h, (size_t)L.nst * bb * L.n_nodes);
+    }
+}
+
+static int64_t level_elems(const Level& L, int dim) {
+    return (int64_t)L.nel[0] * L.nel[1] * (dim == 3 ? L.nel[2] : 1);
+}
+
+static void read_flags(tm_hierarchy* h, hipStream_t s, const char* phase) {
+    int f = 0;
+    TM_HIP(hipMemcpyAsync(&f, h->flags, sizeof(int), hipMemcpyDeviceToHost, s));
+    TM_HIP(hipStreamSynchronize(s));
+    if (f & FLAG_BAD_RHO) fail(TM_ERR_ARG, "densities must be finite and in [0, 1]");
+    if (f & FLAG_NOT_SPD) fail(TM_ERR_NOT_SPD, std::string("operator not positive definite (") + phase + ")");
+}
+
+void build_sa_levels(tm_hierarchy* h, hipStream_t s);      // kernels_sa / host_sa
+void numeric_sa_levels(tm_hierarchy* h, hipStream_t s);
+
+static void numeric_setup(tm_hierarchy* h, const double* rho, hipStream_t s) {
+    TM_HIP(hipMemsetAsync(h->flags, 0, sizeof(int), s));
+    Level& F = h->lv[0];
+    launch_simp(rho, h->n_el, h->mat.p, h->mat.E0, h->mat.Emin, F.E64, F.E32, h->flags, s);
+    const int point = h->opt.smoother == TM_SMOOTH_POINT_JACOBI;
+    launch_fine_dinv(F, h->KE64, point, h->flags, s);
+    read_flags(h, s, "fine diagonal");
+    int Lg = 0;
+    for (auto& L : h->lv)
+        if (L.kind != TM_LEVEL_AGGREGATION) ++Lg;
+    double* prev = nullptr;
+    double* bufs[2] = {h->elem_a, h->elem_b};
+    for (int l = 1; l < Lg; ++l) {
+        double* cur = bufs[(l - 1) & 1];
+        launch_galerkin_elems(h, l - 1, prev, cur, s);
+        launch_stencil_assemble(h->lv[l], cur, s);
+        launch_stencil_dinv(h->lv[l], point, h->flags, s);
+        prev = cur;
+    }
+    if (h->sa) numeric_sa_levels(h, s);
+    // coarsest operator: dense FP64, Cholesky, explicit inverse
+    Level& C = h->lv.back();
+    const int64_t nc = C.n;
+    h->nc = nc;
+    std::vector<void*> tmp;
+    size_t tb = 0;
+    double* Ad = dalloc<double>(tmp, tb, (size_t)nc * nc);
+    TM_HIP(hipMemsetAsync(Ad, 0, (size_t)nc * nc * sizeof(double), s));
+    if (C.kind == TM_LEVEL_AGGREGATION)
+        launch_dense_from_bsr(C, Ad, s);
+    else if (C.kind == TM_LEVEL_GEOMETRIC)
+        launch_dense_from_stencil(C, Ad, s);
+    else
+        fail(TM_ERR_ARG, "a hierarchy needs at least two levels");
+    if (h->ainv_cap < (size_t)nc * nc) {
+        h->ainv = halloc<double>(h, (size_t)nc * nc);
+        h->ainv_cap = (size_t)nc * nc;
+    }
+    try {
+        launch_cholesky_inverse(Ad, h->ainv, nc, h->flags, s);
+        read_flags(h, s, "coarsest Cholesky");
+    } catch (...) {
+        TM_HIP(hipStreamSynchronize(s));
+        free_list(tmp);
+        throw;
+    }
+    TM_HIP(hipStreamSynchronize(s));
+    free_list(tmp);
+}
+
+static void destroy_hierarchy(tm_hierarchy* h);
+
+}  // namespace tmi
+
+// ============================================================================ V-cycle
+namespace tmi {
+
+template <typename T> static T* vb(Vcyc& V, int l) { return (T*)V.b[l]; }
+template <typename T> static T* vx(Vcyc& V, int l) { return (T*)V.x[l]; }
+template <typename T> static T* vt(Vcyc& V, int l) { return (T*)V.t[l]; }
+
+static void timed_begin(tm_hierarchy* h, int cls, hipStream_t s, hipEvent_t* e0) {
+    if (!h->timing[cls]) return;
+    TM_HIP(hipEventCreate(e0));
+    TM_HIP(hipEventRecord(*e0, s));
+}
+static void timed_end(tm_hierarchy* h, int cls, hipStream_t s, hipEvent_t e0) {
+    if (!h->timing[cls]) return;
+    hipEvent_t e1;
+    TM_HIP(hipEventCreate(&e1));
+    TM_HIP(hipEventRecord(e1, s));
+    h->tev[cls].push_back({e0, e1});
+}
+
+template <typename T>
+static void level_op(tm_hierarchy* h, int l, int op, const T* x, const T* b, T* y, const int* done,
+                     hipStream_t s) {
+    Level& L = h->lv[l];
+    const T w = (T)h->opt.omega;
+    hipEvent_t e0 = nullptr;
+    if (L.kind == TM_LEVEL_FINE) {
+        timed_begin(h, 0, s, &e0);
+        launch_fine_op<T>(h, op, false, x, b, y, w, done, nullptr, s);
+        timed_end(h, 0, s, e0);
+    } else if (L.kind == TM_LEVEL_GEOMETRIC) {
+        timed_begin(h, 1, s, &e0);
+        launch_stencil_op<T>(L, op, x, b, y, w, done, s);
+        timed_end(h, 1, s, e0);
+    } else {
+        launch_bsr_op<T>(L, op, x, b, y, w, done, s);
+    }
+}
+
+template <typename T>
+static void restrict_to(tm_hierarchy* h, int l, const T* r, T* bc, T* xc_first, const int* done,
+                        hipStream_t s) {
+    Level& F = h->lv[l];
+    Level& C = h->lv[l + 1];
+    const T w = (T)h->opt.omega;
+    if (F.xfer_bsr)
+        launch_bsr_restrict<T>(F, r, bc, C, xc_first, w, done, s);
+    else
+        launch_restrict<T>(F, C, r, bc, xc_first, w, done, s);
+}
+
+template <typename T>
+static void prolong_from(tm_hierarchy* h, int l, const T* xc, T* xf, const int* done, hipStream_t s) {
+    Level& F = h->lv[l];
+    if (F.xfer_bsr)
+        launch_bsr_prolong<T>(F, xc, xf, done, s);
+    else
+        launch_prolong<T>(F, h->lv[l + 1], xc, xf, done, s);
+}
+
+// z = V(b0) on level 0 (Algorithm 1 from x = 0).  Work vectors of level l:
+// V.b[l] (l > 0), V.x[l], V.t[l].  The last post-smoothing sweep writes z.
+template <typename T>
+static void vcycle(tm_hierarchy* h, Vcyc& V, const T* b0, T* z, const int* done, hipStream_t s) {
+    const int L = (int)h->lv.size();
+    const int npre = h->opt.nu_pre, npost = h->opt.nu_post;
+    const T w = (T)h->opt.omega;
+    std::vector<T*> xr(L), tr(L);
+    for (int l = 0; l < L - 1; ++l) {
+        const T* b = l == 0 ? b0 : vb<T>(V, l);
+        T* x = vx<T>(V, l);
+        T* t = vt<T>(V, l);
+        if (l == 0) launch_first_smooth<T>(h->lv[0], b, x, w, done, s);
+        for (int k = 1; k < npre; ++k) {
+            level_op<T>(h, l, OP_SMOOTH, x, b, t, done, s);
+            std::swap(x, t);
+        }
+        level_op<T>(h, l, OP_RESID, x, b, t, done, s);
+        T* xc_first = (l + 1 < L - 1) ? vx<T>(V, l + 1) : nullptr;
+        restrict_to<T>(h, l, t, vb<T>(V, l + 1), xc_first, done, s);
+        xr[l] = x;
+        tr[l] = t;
+    }
+    launch_dense_solve<T>(h->ainv, h->nc, vb<T>(V, L - 1), vx<T>(V, L - 1), done, s);
+    xr[L - 1] = vx<T>(V, L - 1);
+    for (int l = L - 2; l >= 0; --l) {
+        const T* b = l == 0 ? b0 : vb<T>(V, l);
+        T* x = xr[l];
+        T* t = tr[l];
+        prolong_from<T>(h, l, xr[l + 1], x, done, s);
+        for (int k = 0; k < npost; ++k) {
+            T* dst = (l == 0 && k == npost - 1) ? z : t;
+            level_op<T>(h, l, OP_SMOOTH, x, b, dst, done, s);
+            if (!(l == 0 && k == npost - 1)) std::swap(x, t);
+        }
+        xr[l] = x;
+        tr[l] = t;
+    }
+}
+
+template <typename T>
+static void alloc_vcyc(tm_hierarchy* h, Vcyc& V, std::vector<void*>& list, size_t& bytes) {
+    const int L = (int)h->lv.size();
+    V.b.assign(L, nullptr);
+    V.x.assign(L, nullptr);
+    V.t.assign(L, nullptr);
+    for (int l = 0; l < L; ++l) {
+        const size_t n = (size_t)h->lv[l].n;
+        if (l > 0) V.b[l] = dalloc<T>(list, bytes, n);
+        V.x[l] = dalloc<T>(list, bytes, n);
+        if (l < L - 1) V.t[l] = dalloc<T>(list, bytes, n);
+    }
+}
+
+}  // namespace tmi
+
+// ============================================================================ solve states
+namespace tmi {
+
+static bool mixed_of(const tm_hierarchy* h) { return h->opt.vcycle_fp == 32; }
+
+static int nparts_cap(const tm_hierarchy* h) {
+    return std::max(fine_op_blocks(h), krylov_blocks(h->n_dof));
+}
+
+static tm_solve_state* new_state(tm_hierarchy* h, int nrhs) {
+    auto* st = new tm_solve_state();
+    st->h = h;
+    st->nrhs = nrhs;
+    const int64_t n = h->n_dof;
+    const bool mixed = mixed_of(h);
+    try {
+        for (int k = 0; k < nrhs; ++k) {
+            Lane* ln = new Lane();
+            st->lanes.push_back(ln);
+            ln->f = dalloc<double>(st->allocs, st->bytes, n);
+            ln->r = dalloc<double>(st->allocs, st->bytes, n);
+            ln->p = dalloc<double>(st->allocs, st->bytes, n);
+            ln->q = dalloc<double>(st->allocs, st->bytes, n);
+            ln->part = dalloc<double>(st->allocs, st->bytes, (size_t)2 * nparts_cap(h));
+            if (mixed) {
+                ln->r32 = dalloc<float>(st->allocs, st->bytes, n);
+                ln->z32 = dalloc<float>(st->allocs, st->bytes, n);
+                alloc_vcyc<float>(h, ln->v32, st->allocs, st->bytes);
+            } else {
+                ln->z64 = dalloc<double>(st->allocs, st->bytes, n);
+                alloc_vcyc<double>(h, ln->v64, st->allocs, st->bytes);
+            }
+        }
+        st->sc = dalloc<KScal>(st->allocs, st->bytes, nrhs);
+        TM_HIP(hipHostMalloc((void**)&st->sc_host, sizeof(KScal) * nrhs, hipHostMallocDefault));
+        TM_HIP(hipEventCreateWithFlags(&st->ev, hipEventDisableTiming));
+    } catch (...) {
+        free_list(st->allocs);
+        for (Lane* ln : st->lanes) delete ln;
+        if (st->sc_host) (void)hipHostFree(st->sc_host);
+        delete st;
+        throw;
+    }
+    return st;
+}
+
+static void delete_state(tm_solve_state* st) {
+    if (!st) return;
+    free_list(st->allocs);
+    for (Lane* ln : st->lanes) delete ln;
+    if (st->sc_host) (void)hipHostFree(st->sc_host);
+    if (st->ev) (void)hipEventDestroy(st->ev);
+    delete st;
+}
+
+static void enqueue_vcycle_into_z(tm_hierarchy* h, Lane& ln, const int* done, hipStream_t s) {
+    if (mixed_of(h))
+        vcycle<float>(h, ln.v32, ln.r32, ln.z32, done, s);
+    else
+        vcycle<double>(h, ln.v64, ln.r, ln.z64, done, s);
+}
+
+static void enqueue_begin(tm_solve_state* st, const double* f, int use_u0) {
+    tm_hierarchy* h = st->h;
+    hipStream_t s = st->s;
+    const int64_t n = h->n_dof;
+    const bool mixed = mixed_of(h);
+    for (int k = 0; k < st->nrhs; ++k) {
+        Lane& ln = *st->lanes[k];
+        KScal* sc = st->sc + k;
+        double* u = st->u + (size_t)k * n;
+        launch_mask_copy<double>(h, f + (size_t)k * n, ln.f, s);
+        launch_fcg_init(h, ln, sc, use_u0, u, st->rtol, h->opt.max_iters, h->opt.outer, s);
+        if (mixed) launch_cast(ln.r, ln.r32, n, s);
+        const int* done = &sc->done;
+        enqueue_vcycle_into_z(h, ln, done, s);
+        launch_zdots(h, ln, sc, mixed, s);
+        launch_reduce_beta(sc, ln.part, krylov_blocks(n), s);
+        TM_HIP(hipMemsetAsync(ln.p, 0, n * sizeof(double), s));
+        launch_update_p(h, ln, sc, mixed, s);
+    }
+}
+
+static void enqueue_iteration(tm_solve_state* st, int k) {
+    tm_hierarchy* h = st->h;
+    hipStream_t s = st->s;
+    const int64_t n = h->n_dof;
+    const bool mixed = mixed_of(h);
+    Lane& ln = *st->lanes[k];
+    KScal* sc = st->sc + k;
+    const int* done = &sc->done;
+    double* u = st->u + (size_t)k * n;
+    hipEvent_t e0 = nullptr;
+    timed_begin(h, 0, s, &e0);
+    launch_fine_op<double>(h, OP_QDOT, false, ln.p, ln.r, ln.q, 0.0, done, ln.part, s);
+    timed_end(h, 0, s, e0);
+    launch_reduce_alpha(sc, ln.part, fine_op_blocks(h), s);
+    launch_update_ur(h, ln, sc, u, mixed, s);
+    launch_reduce_rr(sc, ln.part, krylov_blocks(n), s);
+    enqueue_vcycle_into_z(h, ln, done, s);
+    launch_zdots(h, ln, sc, mixed, s);
+    launch_reduce_beta(sc, ln.part, krylov_blocks(n), s);
+    launch_update_p(h, ln, sc, mixed, s);
+}
+
+static void enqueue_advance(tm_solve_state* st, int k_iters) {
+    for (int it = 0; it < k_iters; ++it)
+        for (int k = 0; k < st->nrhs; ++k) enqueue_iteration(st, k);
+    TM_HIP(hipMemcpyAsync(st->sc_host, st->sc, sizeof(KScal) * st->nrhs, hipMemcpyDeviceToHost, st->s));
+    TM_HIP(hipEventRecord(st->ev, st->s));
+    st->pending = true;
+}
+
+static bool state_done(tm_solve_state* st) {
+    for (int k = 0; k < st->nrhs; ++k)
+        if (!st->sc_host[k].done) return false;
+    return true;
+}
+
+static void wait_state(tm_solve_state* st) {
+    if (st->pending) {
+        TM_HIP(hipEventSynchronize(st->ev));
+        st->pending = false;
+    }
+}
+
+// run to completion: chunks of iterations between host checks; the chunk
+// length follows the observed convergence rate (extra iterations past the
+// stop are empty launches).
+static void run_to_completion(tm_solve_state* st) {
+    tm_hierarchy* h = st->h;
+    int k = h->opt.check_every > 0 ? h->opt.check_every : 6;
+    double last_rr = -1.0;
+    int last_iter = 0;
+    for (;;) {
+        enqueue_advance(st, k);
+        wait_state(st);
+        if (state_done(st)) break;
+        if (h->opt.check_every > 0) continue;
+        // adapt: estimate iterations left for the slowest right-hand side
+        double need = 2.0;
+        for (int q = 0; q < st->nrhs; ++q) {
+            const KScal& c = st->sc_host[q];
+            if (c.done) continue;
+            const int di = c.iter - last_iter;
+            if (last_rr > 0.0 && di > 0 && c.rr < last_rr && c.rr > 0.0) {
+                const double rate = std::log(c.rr / last_rr) / di;         // per iteration (< 0)
+                need = std::max(need, std::log(c.rr_stop / c.rr) / rate);
+            } else {
+                need = std::max(need, (double)k);
+            }
+        }
+        last_rr = st->sc_host[0].rr;
+        last_iter = st->sc_host[0].iter;
+        k = (int)std::min(64.0, std::max(2.0, std::ceil(need)));
+    }
+}
+
+static tm_status finish_state(tm_solve_state* st, int32_t* iters, double* compliance, double* relres) {
+    tm_hierarchy* h = st->h;
+    wait_state(st);
+    const int64_t n = h->n_dof;
+    for (int k = 0; k < st->nrhs; ++k)
+        launch_final_residual(h, *st->lanes[k], st->sc + k, st->u + (size_t)k * n, st->s);
+    TM_HIP(hipMemcpyAsync(st->sc_host, st->sc, sizeof(KScal) * st->nrhs, hipMemcpyDeviceToHost, st->s));
+    TM_HIP(hipStreamSynchronize(st->s));
+    tm_status worst = TM_OK;
+    for (int k = 0; k < st->nrhs; ++k) {
+        const KScal& c = st->sc_host[k];
+        if (iters) iters[k] = c.iter;
+        if (compliance) compliance[k] = c.zq;
+        if (relres) relres[k] = c.ff > 0.0 ? std::sqrt(c.pq / c.ff) : 0.0;
+        const tm_status stt = (tm_status)c.status;
+        if (stt < 0) worst = stt;
+        else if (stt == TM_NOT_CONVERGED && worst == TM_OK) worst = TM_NOT_CONVERGED;
+    }
+    st->ended = true;
+    return worst;
+}
+
+}  // namespace tmi
+
+// ============================================================================ exports helpers
+namespace tmi {
+
+static const Level& level_at(const tm_hierarchy* h, int level) {
+    if (!h) fail(TM_ERR_ARG, "hierarchy is NULL");
+    if (level < 0 || level >= (int)h->lv.size()) fail(TM_ERR_ARG, "level out of range");
+    return h->lv[level];
+}
+
+// CSR of a geometric level from its FP64 stencil (host copy)
+static void stencil_csr(const Level& L, std::vector<int64_t>& rp, std::vector<int32_t>& ci,
+                        std::vector<double>& v, bool want_values) {
+    const int dim = L.dim, bb = dim * dim;
+    std::vector<double> st;
+    if (want_values) {
+        st.resize((size_t)L.nst * bb * L.n_nodes);
+        TM_HIP(hipMemcpy(st.data(), L.st64, st.size() * sizeof(double), hipMemcpyDeviceToHost));
+    }
+    rp.assign(L.n + 1, 0);
+    ci.clear();
+    v.clear();
+    const int NX = L.nn[0], NY = L.nn[1], NZ = dim == 3 ? L.nn[2] : 1;
+    for (int64_t node = 0; node < L.n_nodes; ++node) {
+        const int i = (int)(node % NX), j = (int)((node / NX) % NY), k = (int)(node / ((int64_t)NX * NY));
+        for (int r = 0; r < dim; ++r) {
+            for (int dz = (dim == 3 ? -1 : 0); dz <= (dim == 3 ? 1 : 0); ++dz)
+                for (int dy = -1; dy <= 1; ++dy)
+                    for (int dx = -1; dx <= 1; ++dx) {
+                        const int ii = i + dx, jj = j + dy, kk = k + dz;
+                        if (ii < 0 || ii >= NX || jj < 0 || jj >= NY || kk < 0 || kk >= NZ) continue;
+                        const int o = dim == 3 ? (dz + 1) * 9 + (dy + 1) * 3 + dx + 1 : (dy + 1) * 3 + dx + 1;
+                        const int64_t J = ((int64_t)kk * NY + jj) * NX + ii;
+                        for (int c = 0; c < dim; ++c) {
+                            ci.push_back((int32_t)(dim * J + c));
+                            if (want_values) v.push_back(st[((size_t)o * bb + r * dim + c) * L.n_nodes + node]);
+                        }
+                    }
+            rp[dim * node + r + 1] = (int64_t)ci.size();
+        }
+    }
+}
+
+static void bsr_csr(const BSR& B, std::vector<int64_t>& rp, std::vector<int32_t>& ci,
+                    std::vector<double>& v) {
+    std::vector<int32_t> brp(B.nbr + 1), bci(B.nnzb);
+    std::vector<double> bv((size_t)B.nnzb * B.br * B.bc);
+    TM_HIP(hipMemcpy(brp.data(), B.rp, brp.size() * 4, hipMemcpyDeviceToHost));
+    if (B.nnzb) {
+        TM_HIP(hipMemcpy(bci.data(), B.ci, bci.size() * 4, hipMemcpyDeviceToHost));
+        TM_HIP(hipMemcpy(bv.data(), B.v64, bv.size() * 8, hipMemcpyDeviceToHost));
+    }
+    rp.assign(B.nbr * B.br + 1, 0);
+    ci.clear();
+    v.clear();
+    for (int64_t br = 0; br < B.nbr; ++br)
+        for (int r = 0; r < B.br; ++r) {
+            for (int32_t q = brp[br]; q < brp[br + 1]; ++q)
+                for (int c = 0; c < B.bc; ++c) {
+                    ci.push_back((int32_t)((int64_t)bci[q] * B.bc + c));
+                    v.push_back(bv[((size_t)q * B.br + r) * B.bc + c]);
+                }
+            rp[br * B.br + r + 1] = (int64_t)ci.size();
+        }
+}
+
+// geometric prolongator from level l+1 to level l (host), supported fine dofs dropped on level 0
+static void geo_prolongator(const tm_hierarchy* h, int l, std::vector<int64_t>& rp,
+                            std::vector<int32_t>& ci, std::vector<double>& v) {
+    const Level& F = h->lv[l];
+    const Level& C = h->lv[l + 1];
+    const int dim = F.dim;
+    std::vector<uint8_t> nm;
+    if (l == 0) {
+        nm.resize(F.n_nodes);
+        TM_HIP(hipMemcpy(nm.data(), F.nmask, F.n_nodes, hipMemcpyDeviceToHost));
+    }
+    rp.assign(F.n + 1, 0);
+    ci.clear();
+    v.clear();
+    const int FX = F.nn[0], FY = F.nn[1];
+    const int CX = C.nn[0], CY = C.nn[1];
+    for (int64_t node = 0; node < F.n_nodes; ++node) {
+        const int i = (int)(node % FX), j = (int)((node / FX) % FY), k = (int)(node / ((int64_t)FX * FY));
+        for (int r = 0; r < dim; ++r) {
+            const bool dropped = l == 0 && (nm[node] & (1u << r));
+            if (!dropped) {
+                // coarse nodes in ascending id order: z, then y, then x
+                for (int c2 = 0; c2 < ((dim == 3 && (k & 1)) ? 2 : 1); ++c2)
+                    for (int b2 = 0; b2 < ((j & 1) ? 2 : 1); ++b2)
+                        for (int a2 = 0; a2 < ((i & 1) ? 2 : 1); ++a2) {
+                            const int I = (i >> 1) + a2, J = (j >> 1) + b2, K = (k >> 1) + c2;
+                            const double w = ((i & 1) ? 0.5 : 1.0) * ((j & 1) ? 0.5 : 1.0) *
+                                             ((dim == 3 && (k & 1)) ? 0.5 : 1.0);
+                            const int64_t Cn = ((int64_t)K * CY + J) * CX + I;
+                            ci.push_back((int32_t)(dim * Cn + r));
+                            v.push_back(w);
+                        }
+            }
+            rp[dim * node + r + 1] = (int64_t)ci.size();
+        }
+    }
+}
+
+}  // namespace tmi
+
+// ============================================================================ C ABI
+extern "C" {
+
+void tm_default_options(tm_options* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->n_levels = 0;
+    o->n_geometric = 0;
+    o->max_coarse = 1000;
+    o->smoother = TM_SMOOTH_BLOCK_JACOBI;
+    o->nu_pre = 1;
+    o->nu_post = 1;
+    o->omega = 0.5;
+    o->sa_beta = 0.003;
+    o->vcycle_fp = 32;
+    o->outer = TM_OUTER_FCG;
+    o->max_iters = 1000;
+    o->check_every = 0;
+}
+
+const char* tm_status_string(tm_status s) {
+    switch (s) {
+        case TM_OK: return "ok";
+        case TM_NOT_CONVERGED: return "not converged";
+        case TM_ERR_ARG: return "invalid argument";
+        case TM_ERR_OOM: return "out of device memory";
+        case TM_ERR_DEVICE: return "device error";
+        case TM_ERR_NOT_SPD: return "operator not positive definite";
+        case TM_ERR_BREAKDOWN: return "Krylov breakdown";
+        case TM_ERR_STATE: return "call out of order";
+    }
+    return "unknown status";
+}
+
+const char* tm_last_error(void) { return tmi::g_last_error.c_str(); }
+
+tm_status tm_plan_bytes(const tm_mesh* mesh, const tm_options* opts, int32_t n_rhs, size_t* bytes) {
+    return guarded([&] {
+        check_mesh(mesh);
+        check_opts(opts);
+        if (n_rhs < 0) fail(TM_ERR_ARG, "n_rhs must be >= 0");
+        if (!bytes) fail(TM_ERR_ARG, "bytes is NULL");
+        const Plan p = plan_levels(mesh, opts);
+        const int dim = mesh->dim, bb = dim * dim, nd = dim * (1 << dim);
+        const int64_t n_el = (int64_t)mesh->nel[0] * mesh->nel[1] * (dim == 3 ? mesh->nel[2] : 1);
+        const int64_t nodes0 = nodes_of(mesh->nel, dim);
+        size_t b = (size_t)n_el * 12 + nodes0 * (1 + bb * 12);
+        size_t vec = 0, el1 = 0, el2 = 0;
+        int nel[3] = {mesh->nel[0], mesh->nel[1], dim == 3 ? mesh->nel[2] : 1};
+        const bool mixed = opts->vcycle_fp == 32;
+        int64_t last_n = nodes0 * dim;
+        for (int l = 1; l < p.Lg; ++l) {
+            for (int d = 0; d < dim; ++d) nel[d] /= 2;
+            const int64_t nn = nodes_of(nel, dim);
+            const int64_t ne = (int64_t)nel[0] * nel[1] * (dim == 3 ? nel[2] : 1);
+            b += (size_t)nn * bb * 12 * ((dim == 3 ? 27 : 9) + 1);
+            vec += (size_t)nn * dim * (mixed ? 4 : 8) * 3;
+            if (l == 1) el1 = (size_t)ne * nd * nd * 8;
+            if (l == 2) el2 = (size_t)ne * nd * nd * 8;
+            last_n = nn * dim;
+        }
+        if (p.sa) last_n = std::min<int64_t>(last_n, opts->max_coarse * 8);
+        b += (size_t)last_n * last_n * 8 * 2 + el1 + el2;
+        const size_t per_rhs = (size_t)nodes0 * dim * (8 * 4 + (mixed ? 4 * 4 : 8 * 3)) + vec;
+        *bytes = b + per_rhs * (size_t)n_rhs;
+    });
+}
+
+static void destroy_impl(tm_hierarchy* h) {
+    if (!h) return;
+    if (h->cached) tmi::delete_state(h->cached);
+    for (int c = 0; c < 2; ++c)
+        for (auto& pr : h->tev[c]) {
+            (void)hipEventDestroy(pr.first);
+            (void)hipEventDestroy(pr.second);
+        }
+    tmi::free_list(h->allocs);
+    delete h;
+}
+
+tm_status tm_setup(const tm_mesh* mesh, const tm_material* mat, const double* rho_dev,
+                   const tm_bcs* bcs, const tm_options* opts, void* stream, tm_hierarchy** out) {
+    tm_hierarchy* h = nullptr;
+    tm_status st = guarded([&] {
+        if (!out) fail(TM_ERR_ARG, "out is NULL");
+        *out = nullptr;
+        check_mesh(mesh);
+        check_material(mat);
+        check_opts(opts);
+        if (!rho_dev) fail(TM_ERR_ARG, "rho_dev is NULL");
+        const Plan plan = plan_levels(mesh, opts);
+        const int dim = mesh->dim;
+        const int64_t n_nodes = nodes_of(mesh->nel, dim), n_dof = n_nodes * dim;
+        std::vector<int64_t> fixed;
+        if (bcs && bcs->n > 0) {
+            if (!bcs->dofs) fail(TM_ERR_ARG, "bcs.dofs is NULL");
+            fixed.assign(bcs->dofs, bcs->dofs + bcs->n);
+            for (int64_t d : fixed)
+                if (d < 0 || d >= n_dof) fail(TM_ERR_ARG, "support dof id out of range");
+            std::sort(fixed.begin(), fixed.end());
+            fixed.erase(std::unique(fixed.begin(), fixed.end()), fixed.end());
+        }
+        if (plan.Lg < 2 && !plan.sa) fail(TM_ERR_ARG, "a hierarchy needs at least two levels");
+        hipStream_t s = S(stream);
+        h = new tm_hierarchy();
+        h->mesh = *mesh;
+        if (dim == 2) h->mesh.nel[2] = 1;
+        h->mat = *mat;
+        h->opt = *opts;
+        h->dim = dim;
+        h->n_el = (int64_t)mesh->nel[0] * mesh->nel[1] * (dim == 3 ? mesh->nel[2] : 1);
+        h->n_nodes = n_nodes;
+        h->n_dof = n_dof;
+        h->fixed = fixed;
+        h->flags = halloc<int>(h, 4);
+        // constants
+        std::vector<double> KE, Q;
+        element_stiffness(dim, mat->nu, mesh->h, KE);
+        child_weights(dim, Q);
+        std::vector<float> KE32(KE.begin(), KE.end());
+        h->KE64 = halloc<double>(h, KE.size());
+        h->KE32 = halloc<float>(h, KE.size());
+        h->Q64 = halloc<double>(h, Q.size());
+        TM_HIP(hipMemcpyAsync(h->KE64, KE.data(), KE.size() * 8, hipMemcpyHostToDevice, s));
+        TM_HIP(hipMemcpyAsync(h->KE32, KE32.data(), KE32.size() * 4, hipMemcpyHostToDevice, s));
+        TM_HIP(hipMemcpyAsync(h->Q64, Q.data(), Q.size() * 8, hipMemcpyHostToDevice, s));
+        // levels
+        h->lv.resize(plan.Lg);
+        for (int l = 0; l < plan.Lg; ++l) alloc_level_geo(h, h->lv[l], l);
+        std::vector<uint8_t> nm(n_nodes, 0);
+        for (int64_t d : fixed) nm[d / dim] |= (uint8_t)(1u << (d % dim));
+        TM_HIP(hipMemcpyAsync(h->lv[0].nmask, nm.data(), n_nodes, hipMemcpyHostToDevice, s));
+        const int nd = dim * (1 << dim);
+        if (plan.Lg > 1) h->elem_a = halloc<double>(h, (size_t)level_elems(h->lv[1], dim) * nd * nd);
+        if (plan.Lg > 2) h->elem_b = halloc<double>(h, (size_t)level_elems(h->lv[2], dim) * nd * nd);
+        h->sa = plan.sa;
+        if (plan.sa) build_sa_levels(h, s);
+        numeric_setup(h, rho_dev, s);
+        TM_HIP(hipStreamSynchronize(s));
+        *out = h;
+    });
+    if (st != TM_OK && h) destroy_impl(h);
+    return st;
+}
+
+tm_status tm_update_density(tm_hierarchy* h, const double* rho_dev, void* stream) {
+    return guarded([&] {
+        if (!h) fail(TM_ERR_ARG, "hierarchy is NULL");
+        if (!rho_dev) fail(TM_ERR_ARG, "rho_dev is NULL");
+        numeric_setup(h, rho_dev, S(stream));
+    });
+}
+
+void tm_destroy(tm_hierarchy* h) { destroy_impl(h); }
+
+int32_t tm_num_levels(const tm_hierarchy* h) { return h ? (int32_t)h->lv.size() : 0; }
+
+tm_status tm_hierarchy_bytes(const tm_hierarchy* h, size_t* bytes) {
+    return guarded([&] {
+        if (!h || !bytes) fail(TM_ERR_ARG, "NULL argument");
+        *bytes = h->bytes;
+    });
+}
+
+static tm_status begin_impl(tm_hierarchy* h, int32_t n_rhs, const double* f_dev, double rtol,
+                            int32_t use_u0, double* u_dev, void* stream, tm_solve_state** out,
+                            bool cached) {
+    return guarded([&] {
+        if (!h) fail(TM_ERR_ARG, "hierarchy is NULL");
+        if (n_rhs < 1 || n_rhs > 64) fail(TM_ERR_ARG, "n_rhs must be in 1..64");
+        if (!f_dev || !u_dev) fail(TM_ERR_ARG, "f_dev / u_dev is NULL");
+        if (!(rtol > 0.0 && rtol < 1.0)) fail(TM_ERR_ARG, "rtol must be in (0, 1)");
+        tm_solve_state* st = nullptr;
+        if (cached) {
+            if (h->cached && h->cached->nrhs != n_rhs) {
+                delete_state(h->cached);
+                h->cached = nullptr;
+            }
+            if (!h->cached) {
+                h->cached = new_state(h, n_rhs);
+                h->cached->owned_by_h = true;
+            }
+            st = h->cached;
+        } else {
+            st = new_state(h, n_rhs);
+        }
+        st->s = S(stream);
+        st->rtol = rtol;
+        st->use_u0 = use_u0;
+        st->u = u_dev;
+        st->ended = false;
+        st->pending = false;
+        try {
+            enqueue_begin(st, f_dev, use_u0);
+        } catch (...) {
+            if (!cached) delete_state(st);
+            throw;
+        }
+        *out = st;
+    });
+}
+
+tm_status tm_solve(tm_hierarchy* h, int32_t n_rhs, const double* f_dev, double rtol, int32_t use_u0,
+                   double* u_dev, int32_t* iters, double* compliance, double* relres, void* stream) {
+    tm_solve_state* st = nullptr;
+    tm_status s0 = begin_impl(h, n_rhs, f_dev, rtol, use_u0, u_dev, stream, &st, true);
+    if (s0 != TM_OK) return s0;
+    tm_status res = TM_OK;
+    const tm_status g = guarded([&] {
+        run_to_completion(st);
+        res = finish_state(st, iters, compliance, relres);
+    });
+    return g != TM_OK ? g : res;
+}
+
+tm_status tm_solve_begin(tm_hierarchy* h, int32_t n_rhs, const double* f_dev, double rtol,
+                         int32_t use_u0, double* u_dev, void* stream, tm_solve_state** st) {
+    if (!st) {
+        set_error("st is NULL");
+        return TM_ERR_ARG;
+    }
+    return begin_impl(h, n_rhs, f_dev, rtol, use_u0, u_dev, stream, st, false);
+}
+
+tm_status tm_solve_advance(tm_solve_state* st, int32_t k_iters) {
+    return guarded([&] {
+        if (!st || st->ended) fail(TM_ERR_STATE, "state is NULL or ended");
+        if (k_iters < 1) fail(TM_ERR_ARG, "k_iters must be >= 1");
+        enqueue_advance(st, k_iters);
+    });
+}
+
+tm_status tm_batch_advance(int32_t n, tm_solve_state* const* sts, int32_t k_iters) {
+    return guarded([&] {
+        if (n < 0 || (n > 0 && !sts)) fail(TM_ERR_ARG, "bad state list");
+        if (k_iters < 1) fail(TM_ERR_ARG, "k_iters must be >= 1");
+        for (int i = 0; i < n; ++i)
+            if (!sts[i] || sts[i]->ended) fail(TM_ERR_STATE, "state is NULL or ended");
+        // interleave: one iteration of every state at a time, each on its own stream
+        for (int it = 0; it < k_iters; ++it)
+            for (int i = 0; i < n; ++i)
+                for (int k = 0; k < sts[i]->nrhs; ++k) enqueue_iteration(sts[i], k);
+        for (int i = 0; i < n; ++i) {
+            tm_solve_state* st = sts[i];
+            TM_HIP(hipMemcpyAsync(st->sc_host, st->sc, sizeof(KScal) * st->nrhs, hipMemcpyDeviceToHost,
+                                  st->s));
+            TM_HIP(hipEventRecord(st->ev, st->s));
+            st->pending = true;
+        }
+    });
+}
+
+tm_status tm_solve_poll(tm_solve_state* st, int32_t* done) {
+    return guarded([&] {
+        if (!st || st->ended) fail(TM_ERR_STATE, "state is NULL or ended");
+        if (!done) fail(TM_ERR_ARG, "done is NULL");
+        *done = 0;
+        if (st->pending) {
+            const hipError_t q = hipEventQuery(st->ev);
+            if (q == hipErrorNotReady) return;
+            TM_HIP(q);
+            st->pending = false;
+        }
+        *done = state_done(st) ? 1 : 0;
+    });
+}
+
+tm_status tm_solve_end(tm_solve_state* st, int32_t* iters, double* compliance, double* relres) {
+    if (!st || st->ended) {
+        set_error("state is NULL or ended");
+        return TM_ERR_STATE;
+    }
+    tm_status res = TM_OK;
+    const tm_status g = guarded([&] { res = finish_state(st, iters, compliance, relres); });
+    if (!st->owned_by_h) delete_state(st);
+    return g != TM_OK ? g : res;
+}
+
+tm_status tm_apply(tm_hierarchy* h, int32_t level, int32_t fp, const void* x_dev, void* y_dev,
+                   void* stream) {
+    return guarded([&] {
+        const Level& L = level_at(h, level);
+        if (fp != 32 && fp != 64) fail(TM_ERR_ARG, "fp must be 32 or 64");
+        if (!x_dev || !y_dev) fail(TM_ERR_ARG, "NULL vector");
+        hipStream_t s = S(stream);
+        if (fp == 64) {
+            if (L.kind == TM_LEVEL_FINE)
+                launch_fine_op<double>(h, OP_APPLY, true, (const double*)x_dev, nullptr, (double*)y_dev, 0.0,
+                                       nullptr, nullptr, s);
+            else
+                level_op<double>(h, level, OP_APPLY, (const double*)x_dev, nullptr, (double*)y_dev, nullptr, s);
+        } else {
+            if (L.kind == TM_LEVEL_FINE)
+                launch_fine_op<float>(h, OP_APPLY, true, (const float*)x_dev, nullptr, (float*)y_dev, 0.f,
+                                      nullptr, nullptr, s);
+            else
+                level_op<float>(h, level, OP_APPLY, (const float*)x_dev, nullptr, (float*)y_dev, nullptr, s);
+        }
+        TM_HIP(hipStreamSynchronize(s));
+    });
+}
+
+tm_status tm_vcycle(tm_hierarchy* h, int32_t fp, const void* b_dev, void* x_dev, void* stream) {
+    return guarded([&] {
+        if (!h) fail(TM_ERR_ARG, "hierarchy is NULL");
+        if (fp != 32 && fp != 64) fail(TM_ERR_ARG, "fp must be 32 or 64");
+        if (!b_dev || !x_dev) fail(TM_ERR_ARG, "NULL vector");
+        hipStream_t s = S(stream);
+        std::vector<void*> list;
+        size_t bytes = 0;
+        Vcyc V;
+        try {
+            if (fp == 64) {
+                alloc_vcyc<double>(h, V, list, bytes);
+                double* bm = dalloc<double>(list, bytes, h->n_dof);
+                launch_mask_copy<double>(h, (const double*)b_dev, bm, s);
+                vcycle<double>(h, V, bm, (double*)x_dev, nullptr, s);
+            } else {
+                alloc_vcyc<float>(h, V, list, bytes);
+                float* bm = dalloc<float>(list, bytes, h->n_dof);
+                launch_mask_copy<float>(h, (const float*)b_dev, bm, s);
+                vcycle<float>(h, V, bm, (float*)x_dev, nullptr, s);
+            }
+            TM_HIP(hipStreamSynchronize(s));
+        } catch (...) {
+            (void)hipStreamSynchronize(s);
+            free_list(list);
+            throw;
+        }
+        free_list(list);
+    });
+}
+
+tm_status tm_level_info(const tm_hierarchy* h, int32_t level, int64_t* n_rows, int64_t* nnz,
+                        int32_t* kind, int32_t* block) {
+    return guarded([&] {
+        const Level& L = level_at(h, level);
+        if (n_rows) *n_rows = L.n;
+        if (kind) *kind = L.kind;
+        if (block) *block = L.bs;
+        if (nnz) {
+            if (L.kind == TM_LEVEL_AGGREGATION) {
+                *nnz = L.A.nnzb * L.bs * L.bs;
+            } else {
+                // structured stencil: count neighbour blocks inside the grid
+                int64_t blocks = 1;
+                for (int d = 0; d < L.dim; ++d) blocks *= (int64_t)3 * L.nn[d] - 2;
+                *nnz = blocks * L.bs * L.bs;
+            }
+        }
+    });
+}
+
+tm_status tm_export_csr(const tm_hierarchy* h, int32_t level, int64_t* rowptr, int32_t* colidx,
+                        double* vals) {
+    return guarded([&] {
+        const Level& L = level_at(h, level);
+        if (L.kind == TM_LEVEL_FINE) fail(TM_ERR_ARG, "the fine level is matrix-free");
+        std::vector<int64_t> rp;
+        std::vector<int32_t> ci;
+        std::vector<double> v;
+        if (L.kind == TM_LEVEL_GEOMETRIC)
+            stencil_csr(L, rp, ci, v, vals != nullptr);
+        else
+            bsr_csr(L.A, rp, ci, v);
+        if (rowptr) std::memcpy(rowptr, rp.data(), rp.size() * 8);
+        if (colidx) std::memcpy(colidx, ci.data(), ci.size() * 4);
+        if (vals) std::memcpy(vals, v.data(), v.size() * 8);
+    });
+}
+
+tm_status tm_export_prolongator(const tm_hierarchy* h, int32_t level, int64_t* n_rows, int64_t* nnz,
+                                int64_t* rowptr, int32_t* colidx, double* vals) {
+    return guarded([&] {
+        const Level& L = level_at(h, level);
+        if (level + 1 >= (int)h->lv.size()) fail(TM_ERR_ARG, "the coarsest level has no prolongator");
+        std::vector<int64_t> rp;
+        std::vector<int32_t> ci;
+        std::vector<double> v;
+        if (L.xfer_bsr)
+            bsr_csr(L.P, rp, ci, v);
+        else
+            geo_prolongator(h, level, rp, ci, v);
+        if (n_rows) *n_rows = (int64_t)rp.size() - 1;
+        if (nnz) *nnz = (int64_t)ci.size();
+        if (rowptr) std::memcpy(rowptr, rp.data(), rp.size() * 8);
+        if (colidx) std::memcpy(colidx, ci.data(), ci.size() * 4);
+        if (vals) std::memcpy(vals, v.data(), v.size() * 8);
+    });
+}
+
+tm_status tm_export_aggregates(const tm_hierarchy* h, int32_t level, int32_t* agg_of_node) {
+    return guarded([&] {
+        const Level& L = level_at(h, level);
+        if (!L.agg) fail(TM_ERR_ARG, "level is not an aggregation input level");
+        if (!agg_of_node) fail(TM_ERR_ARG, "agg_of_node is NULL");
+        TM_HIP(hipMemcpy(agg_of_node, L.agg, L.n_nodes * 4, hipMemcpyDeviceToHost));
+    });
+}
+
+tm_status tm_export_dinv(const tm_hierarchy* h, int32_t level, double* dinv) {
+    return guarded([&] {
+        const Level& L = level_at(h, level);
+        if (!dinv) fail(TM_ERR_ARG, "dinv is NULL");
+        const int bb = L.bs * L.bs;
+        std::vector<double> t((size_t)bb * L.n_nodes);
+        TM_HIP(hipMemcpy(t.data(), L.dinv64, t.size() * 8, hipMemcpyDeviceToHost));
+        for (int64_t node = 0; node < L.n_nodes; ++node)
+            for (int e = 0; e < bb; ++e) dinv[node * bb + e] = t[(size_t)e * L.n_nodes + node];
+    });
+}
+
+tm_status tm_export_connectivity(const tm_mesh* mesh, int32_t* conn) {
+    return guarded([&] {
+        check_mesh(mesh);
+        if (!conn) fail(TM_ERR_ARG, "conn is NULL");
+        const int dim = mesh->dim, npe = 1 << dim;
+        const int nx = mesh->nel[0], ny = mesh->nel[1], nz = dim == 3 ? mesh->nel[2] : 1;
+        const int NX = nx + 1, NY = ny + 1;
+        int64_t e = 0;
+        for (int k = 0; k < nz; ++k)
+            for (int j = 0; j < ny; ++j)
+                for (int i = 0; i < nx; ++i, ++e)
+                    for (int z = 0; z < (dim == 3 ? 2 : 1); ++z)
+                        for (int y = 0; y < 2; ++y)
+                            for (int x = 0; x < 2; ++x) {
+                                const int a = dim == 3 ? loc3(x, y, z) : loc2(x, y);
+                                conn[e * npe + a] = (int32_t)(((int64_t)(k + z) * NY + (j + y)) * NX + i + x);
+                            }
+    });
+}
+
+tm_status tm_kernel_timing(tm_hierarchy* h, int32_t kernel_class, int32_t enable) {
+    return guarded([&] {
+        if (!h) fail(TM_ERR_ARG, "hierarchy is NULL");
+        if (kernel_class < 0 || kernel_class > 1) fail(TM_ERR_ARG, "kernel_class must be 0 or 1");
+        h->timing[kernel_class] = enable != 0;
+    });
+}
+
+tm_status tm_kernel_timing_read(tm_hierarchy* h, int32_t kernel_class, int64_t* launches,
+                                double* total_ms) {
+    return guarded([&] {
+        if (!h) fail(TM_ERR_ARG, "hierarchy is NULL");
+        if (kernel_class < 0 || kernel_class > 1) fail(TM_ERR_ARG, "kernel_class must be 0 or 1");
+        double tot = 0.0;
+        auto& v = h->tev[kernel_class];
+        for (auto& pr : v) {
+            TM_HIP(hipEventSynchronize(pr.second));
+            float ms = 0.f;
+            TM_HIP(hipEventElapsedTime(&ms, pr.first, pr.second));
+            tot += ms;
+            (void)hipEventDestroy(pr.first);
+            (void)hipEventDestroy(pr.second);
+        }
+        if (launches) *launches = (int64_t)v.size();
+        if (total_ms) *total_ms = tot;
+        v.clear();
+    });
+}
+
+}  // extern "C"

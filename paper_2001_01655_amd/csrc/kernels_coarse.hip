@@ -1,0 +1,443 @@
+// Geometric coarse levels.
+//
+// Galerkin operators A^{l+1} = P^T A^l P (Sec. 3.2) are formed element by
+// element: every coarse element E holds the dense matrix
+//     K_E = sum_{children c} Q~_c^T K_c Q~_c,
+// where Q_c interpolates E's corner values to child c's corners with the
+// coarse shape functions (the restriction of P to one element, exact because
+// a fine element's corners only interpolate from its parent's corners) and
+// Q~_c drops supported fine dofs on the finest level.  The level operator is
+// then stored as a structured stencil: node I keeps, for each of its 3^dim
+// neighbour offsets, the dense dim x dim block (zero outside the grid), laid
+// out [offset][entry][node] so consecutive threads read consecutive words.
+#include "tm_device.h"
+
+namespace tmi {
+
+// --------------------------------------------------------------- Galerkin
+template <int DIM>
+__global__ void k_galerkin(const double* __restrict__ child, const double* __restrict__ E,
+                           const double* __restrict__ KE, const uint8_t* __restrict__ nm,
+                           const double* __restrict__ Q, int cnx, int cny, int cnz,
+                           double* __restrict__ parent) {
+    constexpr int NPE = 1 << DIM, ND = DIM * NPE;
+    __shared__ double Kc[ND * ND];
+    __shared__ double Tm[ND * ND];
+    __shared__ double q[NPE * NPE];
+    __shared__ double msk[NPE * DIM];
+    const int64_t pe = blockIdx.x;
+    const int X = (int)(pe % cnx);
+    const int Y = (int)((pe / cnx) % cny);
+    const int Z = DIM == 3 ? (int)(pe / ((int64_t)cnx * cny)) : 0;
+    const int fnx = 2 * cnx, fny = 2 * cny;
+    const int t = threadIdx.x;
+    const int r = t / ND, s = t % ND;
+    double acc = 0.0;
+    for (int c = 0; c < NPE; ++c) {
+        const int cx = c & 1, cy = (c >> 1) & 1, cz = (c >> 2) & 1;   // child position bits
+        const int gx = 2 * X + cx, gy = 2 * Y + cy, gz = 2 * Z + cz;
+        const int64_t ce = DIM == 3 ? ((int64_t)gz * fny + gy) * fnx + gx : (int64_t)gy * fnx + gx;
+        if (child) {
+            Kc[t] = child[ce * ND * ND + t];
+        } else {
+            Kc[t] = E[ce] * KE[t];
+        }
+        if (t < NPE * NPE) q[t] = Q[c * NPE * NPE + t];
+        if (t < NPE * DIM) {
+            const int a = t / DIM, comp = t % DIM;
+            double m = 1.0;
+            if (nm) {
+                // child-local corner a -> fine node
+                const int ax = (a == 1 || a == 2 || a == 5 || a == 6) ? 1 : 0;
+                const int ay = (a == 2 || a == 3 || a == 6 || a == 7) ? 1 : 0;
+                const int az = a >= 4 ? 1 : 0;
+                const int64_t fnode = DIM == 3
+                    ? ((int64_t)(gz + az) * (fny + 1) + (gy + ay)) * (fnx + 1) + gx + ax
+                    : (int64_t)(gy + ay) * (fnx + 1) + gx + ax;
+                if (nm[fnode] & (1u << comp)) m = 0.0;
+            }
+            msk[t] = m;
+        }
+        __syncthreads();
+        {   // T[r][s] = sum_a' Kc[r][DIM a' + j] m[a'][j] q[a'][b'],  s = DIM b' + j
+            const int bp = s / DIM, j = s % DIM;
+            double v = 0.0;
+#pragma unroll
+            for (int ap = 0; ap < NPE; ++ap)
+                v += Kc[r * ND + DIM * ap + j] * (msk[ap * DIM + j] * q[ap * NPE + bp]);
+            Tm[r * ND + s] = v;
+        }
+        __syncthreads();
+        {   // K_E[r'][s] += sum_a q[a][b] m[a][i] T[DIM a + i][s],  r' = DIM b + i
+            const int b = r / DIM, i = r % DIM;
+            double v = 0.0;
+#pragma unroll
+            for (int a = 0; a < NPE; ++a) v += (q[a * NPE + b] * msk[a * DIM + i]) * Tm[(DIM * a + i) * ND + s];
+            acc += v;
+        }
+        __syncthreads();
+    }
+    parent[pe * ND * ND + t] = acc;
+}
+
+void launch_galerkin_elems(const tm_hierarchy* h, int fine_level, const double* child,
+                           double* parent, hipStream_t s) {
+    const Level& F = h->lv[fine_level];
+    const Level& C = h->lv[fine_level + 1];
+    const int64_t n_par = (int64_t)C.nel[0] * C.nel[1] * (h->dim == 3 ? C.nel[2] : 1);
+    const uint8_t* nm = fine_level == 0 ? F.nmask : nullptr;
+    if (h->dim == 3)
+        hipLaunchKernelGGL(k_galerkin<3>, dim3((unsigned)n_par), dim3(576), 0, s, child, F.E64,
+                           h->KE64, nm, h->Q64, C.nel[0], C.nel[1], C.nel[2], parent);
+    else
+        hipLaunchKernelGGL(k_galerkin<2>, dim3((unsigned)n_par), dim3(64), 0, s, child, F.E64,
+                           h->KE64, nm, h->Q64, C.nel[0], C.nel[1], 1, parent);
+}
+
+// --------------------------------------------------------------- stencil assembly
+// thread per (node I, neighbour offset o): block (I, I+o) = sum over the elements
+// holding both nodes, in a fixed order.
+template <int DIM>
+__global__ void k_stencil_assemble(const double* __restrict__ elem, int nx, int ny, int nz,
+                                   int64_t N, double* __restrict__ st64, float* __restrict__ st32) {
+    constexpr int NPE = 1 << DIM, ND = DIM * NPE, NST = DIM == 3 ? 27 : 9;
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (tid >= N * NST) return;
+    const int o = (int)(tid / N);
+    const int64_t node = tid % N;
+    const int NX = nx + 1, NY = ny + 1;
+    const int i = (int)(node % NX);
+    const int j = (int)((node / NX) % NY);
+    const int k = DIM == 3 ? (int)(node / ((int64_t)NX * NY)) : 0;
+    const int ox = o % 3 - 1, oy = (o / 3) % 3 - 1, oz = DIM == 3 ? o / 9 - 1 : 0;
+    double blk[DIM * DIM] = {};
+#pragma unroll
+    for (int ez = 0; ez < (DIM == 3 ? 2 : 1); ++ez)
+#pragma unroll
+        for (int ey = 0; ey < 2; ++ey)
+#pragma unroll
+            for (int ex = 0; ex < 2; ++ex) {
+                // element with lower corner (i-1+ex, ...): our corner (1-ex, ...), neighbour (1-ex+ox, ...)
+                const int lx = 1 - ex, ly = 1 - ey, lz = DIM == 3 ? 1 - ez : 0;
+                const int mx = lx + ox, my = ly + oy, mz = lz + oz;
+                if (mx < 0 || mx > 1 || my < 0 || my > 1 || mz < 0 || mz > 1) continue;
+                const int gx = i - 1 + ex, gy = j - 1 + ey, gz = k - 1 + ez;
+                if (gx < 0 || gx >= nx || gy < 0 || gy >= ny) continue;
+                if (DIM == 3 && (gz < 0 || gz >= nz)) continue;
+                const int64_t e = DIM == 3 ? ((int64_t)gz * ny + gy) * nx + gx : (int64_t)gy * nx + gx;
+                const int a = DIM == 3 ? loc3(lx, ly, lz) : loc2(lx, ly);
+                const int bb = DIM == 3 ? loc3(mx, my, mz) : loc2(mx, my);
+                const double* Ke = elem + e * ND * ND;
+#pragma unroll
+                for (int r = 0; r < DIM; ++r)
+#pragma unroll
+                    for (int c = 0; c < DIM; ++c) blk[r * DIM + c] += Ke[(DIM * a + r) * ND + DIM * bb + c];
+            }
+    if (o == (NST - 1) / 2) {
+        // a dof with no coupling at all (exactly zero diagonal) gets a unit diagonal
+#pragma unroll
+        for (int r = 0; r < DIM; ++r)
+            if (blk[r * DIM + r] == 0.0) blk[r * DIM + r] = 1.0;
+    }
+#pragma unroll
+    for (int q = 0; q < DIM * DIM; ++q) {
+        st64[((int64_t)o * DIM * DIM + q) * N + node] = blk[q];
+        st32[((int64_t)o * DIM * DIM + q) * N + node] = (float)blk[q];
+    }
+}
+
+void launch_stencil_assemble(const Level& L, const double* elem, hipStream_t s) {
+    const int64_t nt = L.n_nodes * L.nst;
+    if (L.dim == 3)
+        hipLaunchKernelGGL(k_stencil_assemble<3>, dim3(grid_for(nt)), dim3(WG), 0, s, elem, L.nel[0],
+                           L.nel[1], L.nel[2], L.n_nodes, L.st64, L.st32);
+    else
+        hipLaunchKernelGGL(k_stencil_assemble<2>, dim3(grid_for(nt)), dim3(WG), 0, s, elem, L.nel[0],
+                           L.nel[1], 1, L.n_nodes, L.st64, L.st32);
+}
+
+// --------------------------------------------------------------- stencil diagonal
+template <int DIM>
+__global__ void k_stencil_dinv(const double* __restrict__ st, int64_t N, int point,
+                               double* __restrict__ d64, float* __restrict__ d32, int* flags) {
+    constexpr int SELF = DIM == 3 ? 13 : 4;
+    const int64_t node = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (node >= N) return;
+    double D[DIM][DIM];
+#pragma unroll
+    for (int r = 0; r < DIM; ++r)
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) D[r][c] = st[((int64_t)SELF * DIM * DIM + r * DIM + c) * N + node];
+    // a dof whose diagonal is exactly zero (no coarse coupling at all) gets a unit row
+#pragma unroll
+    for (int r = 0; r < DIM; ++r)
+        if (D[r][r] == 0.0) D[r][r] = 1.0;
+    store_dinv<DIM>(D, point, node, N, d64, d32, flags);
+}
+
+void launch_stencil_dinv(const Level& L, int point_jacobi, int* flags, hipStream_t s) {
+    if (L.dim == 3)
+        hipLaunchKernelGGL(k_stencil_dinv<3>, dim3(grid_for(L.n_nodes)), dim3(WG), 0, s, L.st64,
+                           L.n_nodes, point_jacobi, L.dinv64, L.dinv32, flags);
+    else
+        hipLaunchKernelGGL(k_stencil_dinv<2>, dim3(grid_for(L.n_nodes)), dim3(WG), 0, s, L.st64,
+                           L.n_nodes, point_jacobi, L.dinv64, L.dinv32, flags);
+}
+
+// --------------------------------------------------------------- stencil operator
+template <typename T, int DIM, int OP>
+__global__ __launch_bounds__(WG) void k_stencil_op(const T* __restrict__ st, int nx, int ny, int nz,
+                                                   int64_t N, const T* __restrict__ x,
+                                                   const T* __restrict__ b, T* __restrict__ y,
+                                                   const T* __restrict__ dinv, T omega,
+                                                   const int* __restrict__ done) {
+    if (done && *done) return;
+    const int64_t node = xcd_block() * WG + threadIdx.x;
+    if (node >= N) return;
+    constexpr int BB = DIM * DIM;
+    const int NX = nx + 1, NY = ny + 1, NZ = nz + 1;
+    const int i = (int)(node % NX);
+    const int j = (int)((node / NX) % NY);
+    const int k = DIM == 3 ? (int)(node / ((int64_t)NX * NY)) : 0;
+    T acc[DIM] = {};
+#pragma unroll
+    for (int dz = (DIM == 3 ? -1 : 0); dz <= (DIM == 3 ? 1 : 0); ++dz)
+#pragma unroll
+        for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+            for (int dx = -1; dx <= 1; ++dx) {
+                const int o = DIM == 3 ? (dz + 1) * 9 + (dy + 1) * 3 + dx + 1 : (dy + 1) * 3 + dx + 1;
+                const int ii = i + dx, jj = j + dy, kk = k + dz;
+                const bool ok = ii >= 0 && ii < NX && jj >= 0 && jj < NY && (DIM == 2 || (kk >= 0 && kk < NZ));
+                if (!ok) continue;
+                const int64_t J = DIM == 3 ? ((int64_t)kk * NY + jj) * NX + ii : (int64_t)jj * NX + ii;
+                T xv[DIM];
+#pragma unroll
+                for (int c = 0; c < DIM; ++c) xv[c] = x[DIM * J + c];
+#pragma unroll
+                for (int r = 0; r < DIM; ++r)
+#pragma unroll
+                    for (int c = 0; c < DIM; ++c) acc[r] += st[((int64_t)o * BB + r * DIM + c) * N + node] * xv[c];
+            }
+    T xo[DIM];
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) xo[c] = x[DIM * node + c];
+    double dots[2];
+    finish_node<T, DIM, OP>(node, N, acc, xo, 0, b, y, dinv, omega, dots);
+}
+
+template <typename T>
+static const T* st_of(const Level& L);
+template <>
+const double* st_of<double>(const Level& L) { return L.st64; }
+template <>
+const float* st_of<float>(const Level& L) { return L.st32; }
+template <typename T>
+static const T* dinv_of(const Level& L);
+template <>
+const double* dinv_of<double>(const Level& L) { return L.dinv64; }
+template <>
+const float* dinv_of<float>(const Level& L) { return L.dinv32; }
+
+template <typename T, int DIM>
+static void stencil_dispatch(const Level& L, int op, const T* x, const T* b, T* y, T omega,
+                             const int* done, hipStream_t s) {
+    const dim3 g(grid_for(L.n_nodes)), blk(WG);
+    const T* st = st_of<T>(L);
+    const T* dv = dinv_of<T>(L);
+    const int nz = DIM == 3 ? L.nel[2] : 0;
+    switch (op) {
+        case OP_APPLY:
+            hipLaunchKernelGGL((k_stencil_op<T, DIM, OP_APPLY>), g, blk, 0, s, st, L.nel[0], L.nel[1], nz,
+                               L.n_nodes, x, b, y, dv, omega, done);
+            break;
+        case OP_RESID:
+            hipLaunchKernelGGL((k_stencil_op<T, DIM, OP_RESID>), g, blk, 0, s, st, L.nel[0], L.nel[1], nz,
+                               L.n_nodes, x, b, y, dv, omega, done);
+            break;
+        default:
+            hipLaunchKernelGGL((k_stencil_op<T, DIM, OP_SMOOTH>), g, blk, 0, s, st, L.nel[0], L.nel[1], nz,
+                               L.n_nodes, x, b, y, dv, omega, done);
+            break;
+    }
+}
+
+template <typename T>
+void launch_stencil_op(const Level& L, int op, const T* x, const T* b, T* y, T omega,
+                       const int* done, hipStream_t s) {
+    if (L.dim == 3)
+        stencil_dispatch<T, 3>(L, op, x, b, y, omega, done, s);
+    else
+        stencil_dispatch<T, 2>(L, op, x, b, y, omega, done, s);
+}
+template void launch_stencil_op<double>(const Level&, int, const double*, const double*, double*,
+                                        double, const int*, hipStream_t);
+template void launch_stencil_op<float>(const Level&, int, const float*, const float*, float*, float,
+                                       const int*, hipStream_t);
+
+// --------------------------------------------------------------- transfers
+// restriction b_c = P~^T r_f: coarse node I gathers fine nodes 2I + d, d in {-1,0,1}^dim,
+// with weight prod w(d_a), w(0) = 1, w(+-1) = 1/2; supported fine dofs contribute 0.
+// Optionally also x_c = omega D_c^-1 b_c (the first sweep of the coarse level from zero).
+template <typename T, int DIM, bool FIRST>
+__global__ __launch_bounds__(WG) void k_restrict(const T* __restrict__ rf, const uint8_t* __restrict__ nm,
+                                                 int fnx, int fny, int fnz, int cnx, int cny, int cnz,
+                                                 T* __restrict__ bc, T* __restrict__ xc,
+                                                 const T* __restrict__ dinv, T omega,
+                                                 const int* __restrict__ done) {
+    if (done && *done) return;
+    const int CX = cnx + 1, CY = cny + 1, CZ = cnz + 1;
+    const int64_t Nc = (int64_t)CX * CY * (DIM == 3 ? CZ : 1);
+    const int64_t node = xcd_block() * WG + threadIdx.x;
+    if (node >= Nc) return;
+    const int FX = fnx + 1, FY = fny + 1, FZ = fnz + 1;
+    const int I = (int)(node % CX);
+    const int J = (int)((node / CX) % CY);
+    const int K = DIM == 3 ? (int)(node / ((int64_t)CX * CY)) : 0;
+    T acc[DIM] = {};
+#pragma unroll
+    for (int dz = (DIM == 3 ? -1 : 0); dz <= (DIM == 3 ? 1 : 0); ++dz)
+#pragma unroll
+        for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+            for (int dx = -1; dx <= 1; ++dx) {
+                const int fi = 2 * I + dx, fj = 2 * J + dy, fk = 2 * K + dz;
+                if (fi < 0 || fi >= FX || fj < 0 || fj >= FY) continue;
+                if (DIM == 3 && (fk < 0 || fk >= FZ)) continue;
+                const int64_t f = DIM == 3 ? ((int64_t)fk * FY + fj) * FX + fi : (int64_t)fj * FX + fi;
+                const T w = (dx ? T(0.5) : T(1)) * (dy ? T(0.5) : T(1)) * (dz ? T(0.5) : T(1));
+                const uint8_t m = nm ? nm[f] : 0;
+#pragma unroll
+                for (int c = 0; c < DIM; ++c)
+                    if (!(m & (1u << c))) acc[c] += w * rf[DIM * f + c];
+            }
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) bc[DIM * node + c] = acc[c];
+    if (FIRST) {
+#pragma unroll
+        for (int r = 0; r < DIM; ++r) {
+            T t = 0;
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) t += dinv[(int64_t)(r * DIM + c) * Nc + node] * acc[c];
+            xc[DIM * node + r] = omega * t;
+        }
+    }
+}
+
+template <typename T>
+void launch_restrict(const Level& fine, const Level& coarse, const T* rf, T* bc, T* xc_first,
+                     T omega, const int* done, hipStream_t s) {
+    const dim3 g(grid_for(coarse.n_nodes)), blk(WG);
+    const uint8_t* nm = fine.kind == TM_LEVEL_FINE ? fine.nmask : nullptr;
+    const T* dv = dinv_of<T>(coarse);
+    if (fine.dim == 3) {
+        if (xc_first)
+            hipLaunchKernelGGL((k_restrict<T, 3, true>), g, blk, 0, s, rf, nm, fine.nel[0], fine.nel[1],
+                               fine.nel[2], coarse.nel[0], coarse.nel[1], coarse.nel[2], bc, xc_first, dv,
+                               omega, done);
+        else
+            hipLaunchKernelGGL((k_restrict<T, 3, false>), g, blk, 0, s, rf, nm, fine.nel[0], fine.nel[1],
+                               fine.nel[2], coarse.nel[0], coarse.nel[1], coarse.nel[2], bc, xc_first, dv,
+                               omega, done);
+    } else {
+        if (xc_first)
+            hipLaunchKernelGGL((k_restrict<T, 2, true>), g, blk, 0, s, rf, nm, fine.nel[0], fine.nel[1], 0,
+                               coarse.nel[0], coarse.nel[1], 0, bc, xc_first, dv, omega, done);
+        else
+            hipLaunchKernelGGL((k_restrict<T, 2, false>), g, blk, 0, s, rf, nm, fine.nel[0], fine.nel[1], 0,
+                               coarse.nel[0], coarse.nel[1], 0, bc, xc_first, dv, omega, done);
+    }
+}
+template void launch_restrict<double>(const Level&, const Level&, const double*, double*, double*,
+                                      double, const int*, hipStream_t);
+template void launch_restrict<float>(const Level&, const Level&, const float*, float*, float*, float,
+                                     const int*, hipStream_t);
+
+// prolongation x_f += M P x_c: fine node i interpolates from the coarse nodes
+// around it (1, 2, 4 or 8 of them), weights 1 or 1/2 per axis.
+template <typename T, int DIM>
+__global__ __launch_bounds__(WG) void k_prolong(const T* __restrict__ xc, const uint8_t* __restrict__ nm,
+                                                int fnx, int fny, int fnz, T* __restrict__ xf,
+                                                const int* __restrict__ done) {
+    if (done && *done) return;
+    const int FX = fnx + 1, FY = fny + 1, FZ = fnz + 1;
+    const int64_t Nf = (int64_t)FX * FY * (DIM == 3 ? FZ : 1);
+    const int64_t node = xcd_block() * WG + threadIdx.x;
+    if (node >= Nf) return;
+    const int CX = fnx / 2 + 1, CY = fny / 2 + 1;
+    const int i = (int)(node % FX);
+    const int j = (int)((node / FX) % FY);
+    const int k = DIM == 3 ? (int)(node / ((int64_t)FX * FY)) : 0;
+    const int i0 = i >> 1, j0 = j >> 1, k0 = k >> 1;
+    const int ni = (i & 1) ? 2 : 1, nj = (j & 1) ? 2 : 1, nk = (DIM == 3 && (k & 1)) ? 2 : 1;
+    const T wi = (i & 1) ? T(0.5) : T(1), wj = (j & 1) ? T(0.5) : T(1), wk = (k & 1) ? T(0.5) : T(1);
+    T acc[DIM] = {};
+    for (int c2 = 0; c2 < nk; ++c2)
+        for (int b2 = 0; b2 < nj; ++b2)
+            for (int a2 = 0; a2 < ni; ++a2) {
+                const int64_t C = DIM == 3 ? ((int64_t)(k0 + c2) * CY + (j0 + b2)) * CX + i0 + a2
+                                           : (int64_t)(j0 + b2) * CX + i0 + a2;
+                const T w = wi * wj * (DIM == 3 ? wk : T(1));
+#pragma unroll
+                for (int c = 0; c < DIM; ++c) acc[c] += w * xc[DIM * C + c];
+            }
+    const uint8_t m = nm ? nm[node] : 0;
+#pragma unroll
+    for (int c = 0; c < DIM; ++c)
+        if (!(m & (1u << c))) xf[DIM * node + c] += acc[c];
+}
+
+template <typename T>
+void launch_prolong(const Level& fine, const Level& coarse, const T* xc, T* xf, const int* done,
+                    hipStream_t s) {
+    (void)coarse;
+    const dim3 g(grid_for(fine.n_nodes)), blk(WG);
+    const uint8_t* nm = fine.kind == TM_LEVEL_FINE ? fine.nmask : nullptr;
+    if (fine.dim == 3)
+        hipLaunchKernelGGL((k_prolong<T, 3>), g, blk, 0, s, xc, nm, fine.nel[0], fine.nel[1], fine.nel[2],
+                           xf, done);
+    else
+        hipLaunchKernelGGL((k_prolong<T, 2>), g, blk, 0, s, xc, nm, fine.nel[0], fine.nel[1], 0, xf, done);
+}
+template void launch_prolong<double>(const Level&, const Level&, const double*, double*, const int*,
+                                     hipStream_t);
+template void launch_prolong<float>(const Level&, const Level&, const float*, float*, const int*,
+                                    hipStream_t);
+
+// first smoothing sweep from x = 0:  x = omega D^-1 b  (block per node)
+template <typename T, int BS>
+__global__ __launch_bounds__(WG) void k_first_smooth(const T* __restrict__ b, const T* __restrict__ dinv,
+                                                     int64_t N, T omega, T* __restrict__ x,
+                                                     const int* __restrict__ done) {
+    if (done && *done) return;
+    const int64_t node = xcd_block() * WG + threadIdx.x;
+    if (node >= N) return;
+    T bv[BS];
+#pragma unroll
+    for (int c = 0; c < BS; ++c) bv[c] = b[(int64_t)BS * node + c];
+#pragma unroll
+    for (int r = 0; r < BS; ++r) {
+        T t = 0;
+#pragma unroll
+        for (int c = 0; c < BS; ++c) t += dinv[(int64_t)(r * BS + c) * N + node] * bv[c];
+        x[(int64_t)BS * node + r] = omega * t;
+    }
+}
+
+template <typename T>
+void launch_first_smooth(const Level& L, const T* b, T* x, T omega, const int* done, hipStream_t s) {
+    const dim3 g(grid_for(L.n_nodes)), blk(WG);
+    const T* dv = dinv_of<T>(L);
+    switch (L.bs) {
+        case 2: hipLaunchKernelGGL((k_first_smooth<T, 2>), g, blk, 0, s, b, dv, L.n_nodes, omega, x, done); break;
+        case 3: hipLaunchKernelGGL((k_first_smooth<T, 3>), g, blk, 0, s, b, dv, L.n_nodes, omega, x, done); break;
+        case 6: hipLaunchKernelGGL((k_first_smooth<T, 6>), g, blk, 0, s, b, dv, L.n_nodes, omega, x, done); break;
+        default: fail(TM_ERR_ARG, "unsupported block size");
+    }
+}
+template void launch_first_smooth<double>(const Level&, const double*, double*, double, const int*,
+                                          hipStream_t);
+template void launch_first_smooth<float>(const Level&, const float*, float*, float, const int*,
+                                         hipStream_t);
+
+}  // namespace tmi

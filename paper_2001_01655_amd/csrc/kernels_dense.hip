@@ -1,0 +1,157 @@
+// Coarsest level: the operator is factorised once at setup (Sec. 3.2: the
+// coarse operator is factorised when the hierarchy is built; the paper uses LU
+// on one process, an SPD operator allows Cholesky).  The V-cycle then applies
+// the explicit FP64 inverse A_c^-1 = L^-T L^-1 as one matrix-vector product,
+// which keeps the per-cycle coarse solve a short, fully parallel kernel
+// instead of 2 n_c dependent substitution steps.
+#include "tm_device.h"
+
+namespace tmi {
+
+// dense row-major A (n x n) from the stencil of a geometric level
+template <int DIM>
+__global__ void k_dense_from_stencil(const double* __restrict__ st, int nx, int ny, int nz,
+                                     int64_t N, double* __restrict__ A) {
+    constexpr int NST = DIM == 3 ? 27 : 9, BB = DIM * DIM;
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (tid >= N * NST) return;
+    const int o = (int)(tid / N);
+    const int64_t node = tid % N;
+    const int NX = nx + 1, NY = ny + 1, NZ = nz + 1;
+    const int i = (int)(node % NX);
+    const int j = (int)((node / NX) % NY);
+    const int k = DIM == 3 ? (int)(node / ((int64_t)NX * NY)) : 0;
+    const int dx = o % 3 - 1, dy = (o / 3) % 3 - 1, dz = DIM == 3 ? o / 9 - 1 : 0;
+    const int ii = i + dx, jj = j + dy, kk = k + dz;
+    if (ii < 0 || ii >= NX || jj < 0 || jj >= NY || kk < 0 || (DIM == 3 && kk >= NZ)) return;
+    const int64_t J = DIM == 3 ? ((int64_t)kk * NY + jj) * NX + ii : (int64_t)jj * NX + ii;
+    const int64_t n = DIM * N;
+#pragma unroll
+    for (int r = 0; r < DIM; ++r)
+#pragma unroll
+        for (int c = 0; c < DIM; ++c)
+            A[(DIM * node + r) * n + DIM * J + c] = st[((int64_t)o * BB + r * DIM + c) * N + node];
+}
+
+void launch_dense_from_stencil(const Level& L, double* Ad, hipStream_t s) {
+    const int64_t nt = L.n_nodes * L.nst;
+    if (L.dim == 3)
+        hipLaunchKernelGGL(k_dense_from_stencil<3>, dim3(grid_for(nt)), dim3(WG), 0, s, L.st64,
+                           L.nel[0], L.nel[1], L.nel[2], L.n_nodes, Ad);
+    else
+        hipLaunchKernelGGL(k_dense_from_stencil<2>, dim3(grid_for(nt)), dim3(WG), 0, s, L.st64,
+                           L.nel[0], L.nel[1], 0, L.n_nodes, Ad);
+}
+
+// dense row-major A from a BSR level operator
+__global__ void k_dense_from_bsr(const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                                 const double* __restrict__ v, int64_t nbr, int bs,
+                                 double* __restrict__ A) {
+    const int64_t br = blockIdx.x;
+    if (br >= nbr) return;
+    const int64_t n = nbr * bs;
+    for (int64_t q = rp[br] * (int64_t)bs * bs + threadIdx.x; q < (int64_t)rp[br + 1] * bs * bs;
+         q += blockDim.x) {
+        const int64_t blk = q / (bs * bs);
+        const int e = (int)(q % (bs * bs));
+        const int r = e / bs, c = e % bs;
+        A[(br * bs + r) * n + (int64_t)ci[blk] * bs + c] = v[q];
+    }
+}
+
+void launch_dense_from_bsr(const Level& L, double* Ad, hipStream_t s) {
+    hipLaunchKernelGGL(k_dense_from_bsr, dim3((unsigned)L.A.nbr), dim3(64), 0, s, L.A.rp, L.A.ci,
+                       L.A.v64, L.A.nbr, L.bs, Ad);
+}
+
+// In-place right-looking Cholesky of a row-major SPD matrix by one workgroup;
+// a non-positive pivot raises FLAG_NOT_SPD.
+__global__ __launch_bounds__(1024) void k_cholesky(double* __restrict__ A, int64_t n, int* flags) {
+    __shared__ int bad;
+    const int t = threadIdx.x, nt = blockDim.x;
+    if (t == 0) bad = 0;
+    for (int64_t k = 0; k < n; ++k) {
+        __syncthreads();
+        if (t == 0) {
+            double d = A[k * n + k];
+            if (!(d > 0.0)) {
+                bad = 1;
+                d = 1.0;
+            }
+            A[k * n + k] = sqrt(d);
+        }
+        __syncthreads();
+        if (bad) break;
+        const double dk = A[k * n + k];
+        for (int64_t i = k + 1 + t; i < n; i += nt) A[i * n + k] /= dk;
+        __syncthreads();
+        for (int64_t j = k + 1 + t; j < n; j += nt) {
+            const double ljk = A[j * n + k];
+            for (int64_t i = j; i < n; ++i) A[i * n + j] -= A[i * n + k] * ljk;
+        }
+    }
+    __syncthreads();
+    if (t == 0 && bad) atomicOr(flags, FLAG_NOT_SPD);
+}
+
+// Column c of A^-1 from the factor L (lower part of Lf): solve L y = e_c, then
+// L^T x = y; by symmetry x is also row c, which is stored.
+__global__ __launch_bounds__(256) void k_chol_inverse(const double* __restrict__ Lf, int64_t n,
+                                                      double* __restrict__ Ainv) {
+    extern __shared__ double y[];
+    const int64_t c = blockIdx.x;
+    const int t = threadIdx.x, nt = blockDim.x;
+    for (int64_t i = t; i < n; i += nt) y[i] = (i == c) ? 1.0 : 0.0;
+    __syncthreads();
+    for (int64_t i = c; i < n; ++i) {            // forward: y_i /= L_ii; y_k -= L_ki y_i (k > i)
+        const double yi = y[i] / Lf[i * n + i];
+        __syncthreads();
+        if (t == 0) y[i] = yi;
+        for (int64_t k = i + 1 + t; k < n; k += nt) y[k] -= Lf[k * n + i] * yi;
+        __syncthreads();
+    }
+    for (int64_t i = n - 1; i >= 0; --i) {       // backward: x_i = y_i / L_ii; y_k -= L_ik x_i (k < i)
+        const double xi = y[i] / Lf[i * n + i];
+        __syncthreads();
+        if (t == 0) y[i] = xi;
+        for (int64_t k = t; k < i; k += nt) y[k] -= Lf[i * n + k] * xi;
+        __syncthreads();
+    }
+    for (int64_t i = t; i < n; i += nt) Ainv[c * n + i] = y[i];
+}
+
+void launch_cholesky_inverse(double* A, double* Ainv, int64_t n, int* flags, hipStream_t s) {
+    if (n > 4096) fail(TM_ERR_ARG, "coarsest level too large for the dense solve (> 4096 dofs)");
+    hipLaunchKernelGGL(k_cholesky, dim3(1), dim3(1024), 0, s, A, n, flags);
+    hipLaunchKernelGGL(k_chol_inverse, dim3((unsigned)n), dim3(256), (size_t)n * sizeof(double), s,
+                       (const double*)A, n, Ainv);
+}
+
+// x = A^-1 b in FP64 (one wave per row, fixed shuffle tree)
+template <typename T>
+__global__ __launch_bounds__(256) void k_dense_solve(const double* __restrict__ Ainv, int64_t n,
+                                                     const T* __restrict__ b, T* __restrict__ x,
+                                                     const int* __restrict__ done) {
+    if (done && *done) return;
+    const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (row >= n) return;
+    double a = 0.0;
+    for (int64_t c = lane; c < n; c += 64) a += Ainv[row * n + c] * (double)b[c];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) a += __shfl_down(a, o, 64);
+    if (lane == 0) x[row] = (T)a;
+}
+
+template <typename T>
+void launch_dense_solve(const double* Ainv, int64_t n, const T* b, T* x, const int* done,
+                        hipStream_t s) {
+    hipLaunchKernelGGL((k_dense_solve<T>), dim3((unsigned)ceil_div(n, 4)), dim3(256), 0, s, Ainv, n,
+                       b, x, done);
+}
+template void launch_dense_solve<double>(const double*, int64_t, const double*, double*, const int*,
+                                         hipStream_t);
+template void launch_dense_solve<float>(const double*, int64_t, const float*, float*, const int*,
+                                        hipStream_t);
+
+}  // namespace tmi

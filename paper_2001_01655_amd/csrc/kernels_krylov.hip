@@ -1,0 +1,315 @@
+// Outer Krylov loop (Sec. 3.1): conjugate gradients preconditioned by one
+// V-cycle, in FP64.  Every scalar (alpha, beta, residual norms, the stop
+// decision) stays on the device, so the host can enqueue many iterations
+// without reading anything back; every kernel returns at once when its
+// right-hand side has stopped.  Reductions: fixed per-block partial sums, then
+// one block sums the partials in a fixed order (bitwise reproducible).
+//
+// Flexible CG (the V-cycle in FP32 is not an exactly fixed linear operator):
+//   alpha = p^T r / p^T q,  beta = - z^T q / p^T q   (p_k K-orthogonal to p_{k-1}).
+// Standard PCG: alpha = p^T r / p^T q,  beta = z_k^T r_k / z_{k-1}^T r_{k-1}.
+#include "tm_device.h"
+
+namespace tmi {
+
+constexpr int KB_MAX = 2048;   // blocks of the grid-stride vector kernels
+
+int krylov_blocks(int64_t n) { return (int)std::min<int64_t>(ceil_div(n > 0 ? n : 1, WG), KB_MAX); }
+
+__device__ __forceinline__ double block_sum_all(double v) {
+    __shared__ double red[WG / 64];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double a = 0.0;
+#pragma unroll
+    for (int w = 0; w < WG / 64; ++w) a += red[w];
+    __syncthreads();
+    return a;
+}
+
+// sum of nparts partials per quantity, fixed order, one block
+__device__ __forceinline__ double sum_parts(const double* part, int nparts, int q) {
+    double a = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += WG) a += part[(int64_t)q * nparts + i];
+    return block_sum_all(a);
+}
+
+// ---------------------------------------------------------------- masks, casts
+template <typename T>
+__global__ void k_mask_copy(const T* src, T* dst, const uint8_t* __restrict__ nm, int bs,
+                            int64_t n) {   // src may equal dst
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint8_t m = nm[i / bs];
+    dst[i] = (m & (1u << (i % bs))) ? T(0) : src[i];
+}
+
+template <typename T>
+void launch_mask_copy(const tm_hierarchy* h, const T* src, T* dst, hipStream_t s) {
+    const Level& L = h->lv[0];
+    hipLaunchKernelGGL(k_mask_copy<T>, dim3(grid_for(L.n)), dim3(WG), 0, s, src, dst, L.nmask, L.bs, L.n);
+}
+template void launch_mask_copy<double>(const tm_hierarchy*, const double*, double*, hipStream_t);
+template void launch_mask_copy<float>(const tm_hierarchy*, const float*, float*, hipStream_t);
+
+__global__ void k_cast(const double* __restrict__ a, float* __restrict__ b, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = (float)a[i];
+}
+__global__ void k_cast_back(const float* __restrict__ a, double* __restrict__ b, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = (double)a[i];
+}
+void launch_cast(const double* a, float* b, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_cast, dim3(grid_for(n)), dim3(WG), 0, s, a, b, n);
+}
+void launch_cast_back(const float* a, double* b, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_cast_back, dim3(grid_for(n)), dim3(WG), 0, s, a, b, n);
+}
+__global__ void k_fill(uint32_t* p, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+void launch_fill(void* p, int64_t n_bytes, hipStream_t s) {
+    const int64_t n = n_bytes / 4;
+    hipLaunchKernelGGL(k_fill, dim3(grid_for(n)), dim3(WG), 0, s, (uint32_t*)p, n);
+}
+
+// ---------------------------------------------------------------- init
+// partials: ||f||^2, ||r||^2 (r = f - K~ u0 or f)
+__global__ void k_init_dots(const double* __restrict__ f, const double* __restrict__ r, int64_t n,
+                            double* part) {
+    double a = 0.0, b = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += (int64_t)gridDim.x * WG) {
+        a += f[i] * f[i];
+        b += r[i] * r[i];
+    }
+    a = block_sum_all(a);
+    b = block_sum_all(b);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = a;
+        part[gridDim.x + blockIdx.x] = b;
+    }
+}
+
+__global__ void k_init_scalars(KScal* sc, const double* part, int nparts, double rtol,
+                               int max_iters, int outer) {
+    const double ff = sum_parts(part, nparts, 0);
+    const double rr = sum_parts(part, nparts, 1);
+    if (threadIdx.x == 0) {
+        sc->ff = ff;
+        sc->rr = rr;
+        sc->rr_last = rr;
+        sc->rr_stop = rtol * rtol * ff;
+        sc->iter = 0;
+        sc->max_iters = max_iters;
+        sc->outer = outer;
+        sc->status = TM_OK;
+        sc->done = (rr <= sc->rr_stop) ? 1 : 0;
+        sc->alpha = sc->beta = 0.0;
+        sc->zr_old = 1.0;
+    }
+}
+
+void launch_fcg_init(const tm_hierarchy* h, Lane& ln, KScal* sc, int use_u0, double* u, double rtol,
+                     int max_iters, int outer, hipStream_t s) {
+    const int64_t n = h->n_dof;
+    if (use_u0) {
+        launch_mask_copy<double>(h, u, u, s);
+        launch_fine_op<double>(h, OP_RESID, false, u, ln.f, ln.r, 0.0, nullptr, nullptr, s);
+    } else {
+        TM_HIP(hipMemsetAsync(u, 0, n * sizeof(double), s));
+        TM_HIP(hipMemcpyAsync(ln.r, ln.f, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    }
+    const int nb = krylov_blocks(n);
+    hipLaunchKernelGGL(k_init_dots, dim3(nb), dim3(WG), 0, s, ln.f, ln.r, n, ln.part);
+    hipLaunchKernelGGL(k_init_scalars, dim3(1), dim3(WG), 0, s, sc, ln.part, nb, rtol, max_iters,
+                       outer);
+}
+
+// ---------------------------------------------------------------- alpha
+__global__ void k_reduce_alpha(KScal* sc, const double* part, int nparts) {
+    if (sc->done) return;
+    const double pq = sum_parts(part, nparts, 0);
+    const double pr = sum_parts(part, nparts, 1);
+    if (threadIdx.x == 0) {
+        sc->pq = pq;
+        sc->pr = pr;
+        if (!(pq > 0.0)) {
+            sc->status = TM_ERR_BREAKDOWN;
+            sc->done = 1;
+            sc->alpha = 0.0;
+        } else {
+            sc->alpha = pr / pq;
+        }
+    }
+}
+void launch_reduce_alpha(KScal* sc, const double* part, int nparts, hipStream_t s) {
+    hipLaunchKernelGGL(k_reduce_alpha, dim3(1), dim3(WG), 0, s, sc, part, nparts);
+}
+
+// ---------------------------------------------------------------- u, r update
+template <bool MIXED>
+__global__ void k_update_ur(double* __restrict__ u, double* __restrict__ r, const double* __restrict__ p,
+                            const double* __restrict__ q, float* __restrict__ r32, int64_t n,
+                            const KScal* __restrict__ sc, double* part) {
+    if (sc->done) return;
+    const double alpha = sc->alpha;
+    double a = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += (int64_t)gridDim.x * WG) {
+        u[i] += alpha * p[i];
+        const double ri = r[i] - alpha * q[i];
+        r[i] = ri;
+        if (MIXED) r32[i] = (float)ri;
+        a += ri * ri;
+    }
+    a = block_sum_all(a);
+    if (threadIdx.x == 0) part[blockIdx.x] = a;
+}
+
+void launch_update_ur(const tm_hierarchy* h, Lane& ln, KScal* sc, double* u, bool mixed,
+                      hipStream_t s) {
+    const int64_t n = h->n_dof;
+    const int nb = krylov_blocks(n);
+    if (mixed)
+        hipLaunchKernelGGL(k_update_ur<true>, dim3(nb), dim3(WG), 0, s, u, ln.r, ln.p, ln.q, ln.r32, n,
+                           sc, ln.part);
+    else
+        hipLaunchKernelGGL(k_update_ur<false>, dim3(nb), dim3(WG), 0, s, u, ln.r, ln.p, ln.q, ln.r32, n,
+                           sc, ln.part);
+}
+
+__global__ void k_reduce_rr(KScal* sc, const double* part, int nparts) {
+    if (sc->done) return;
+    const double rr = sum_parts(part, nparts, 0);
+    if (threadIdx.x == 0) {
+        sc->rr = rr;
+        sc->rr_last = rr;
+        sc->iter += 1;
+        if (rr <= sc->rr_stop) {
+            sc->done = 1;
+            sc->status = TM_OK;
+        } else if (!(rr == rr)) {
+            sc->done = 1;
+            sc->status = TM_ERR_BREAKDOWN;
+        } else if (sc->iter >= sc->max_iters) {
+            sc->done = 1;
+            sc->status = TM_NOT_CONVERGED;
+        }
+    }
+}
+void launch_reduce_rr(KScal* sc, const double* part, int nparts, hipStream_t s) {
+    hipLaunchKernelGGL(k_reduce_rr, dim3(1), dim3(WG), 0, s, sc, part, nparts);
+}
+
+// ---------------------------------------------------------------- z dots, beta, p
+template <typename TZ>
+__global__ void k_zdots(const TZ* __restrict__ z, const double* __restrict__ q,
+                        const double* __restrict__ r, int64_t n, const KScal* __restrict__ sc,
+                        double* part) {
+    if (sc->done) return;
+    double a = 0.0, b = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += (int64_t)gridDim.x * WG) {
+        const double zi = (double)z[i];
+        a += zi * q[i];
+        b += zi * r[i];
+    }
+    a = block_sum_all(a);
+    b = block_sum_all(b);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = a;
+        part[gridDim.x + blockIdx.x] = b;
+    }
+}
+
+void launch_zdots(const tm_hierarchy* h, Lane& ln, KScal* sc, bool mixed, hipStream_t s) {
+    const int64_t n = h->n_dof;
+    const int nb = krylov_blocks(n);
+    if (mixed)
+        hipLaunchKernelGGL(k_zdots<float>, dim3(nb), dim3(WG), 0, s, ln.z32, ln.q, ln.r, n, sc, ln.part);
+    else
+        hipLaunchKernelGGL(k_zdots<double>, dim3(nb), dim3(WG), 0, s, ln.z64, ln.q, ln.r, n, sc, ln.part);
+}
+
+// beta; on the first call (iter == 0, p not yet set) it only records z^T r.
+__global__ void k_reduce_beta(KScal* sc, const double* part, int nparts) {
+    if (sc->done) return;
+    const double zq = sum_parts(part, nparts, 0);
+    const double zr = sum_parts(part, nparts, 1);
+    if (threadIdx.x == 0) {
+        sc->zq = zq;
+        sc->zr = zr;
+        if (sc->outer == TM_OUTER_PCG && !(zr > 0.0)) {
+            sc->status = TM_ERR_BREAKDOWN;
+            sc->done = 1;
+            return;
+        }
+        if (sc->iter == 0) {
+            sc->beta = 0.0;
+        } else if (sc->outer == TM_OUTER_PCG) {
+            sc->beta = zr / sc->zr_old;
+        } else {
+            sc->beta = -zq / sc->pq;
+        }
+        sc->zr_old = zr;
+    }
+}
+void launch_reduce_beta(KScal* sc, const double* part, int nparts, hipStream_t s) {
+    hipLaunchKernelGGL(k_reduce_beta, dim3(1), dim3(WG), 0, s, sc, part, nparts);
+}
+
+template <typename TZ>
+__global__ void k_update_p(double* __restrict__ p, const TZ* __restrict__ z, int64_t n,
+                           const KScal* __restrict__ sc) {
+    if (sc->done) return;
+    const double beta = sc->beta;
+    for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += (int64_t)gridDim.x * WG)
+        p[i] = (double)z[i] + beta * p[i];
+}
+
+void launch_update_p(const tm_hierarchy* h, Lane& ln, KScal* sc, bool mixed, hipStream_t s) {
+    const int64_t n = h->n_dof;
+    const int nb = krylov_blocks(n);
+    if (mixed)
+        hipLaunchKernelGGL(k_update_p<float>, dim3(nb), dim3(WG), 0, s, ln.p, ln.z32, n, sc);
+    else
+        hipLaunchKernelGGL(k_update_p<double>, dim3(nb), dim3(WG), 0, s, ln.p, ln.z64, n, sc);
+}
+
+// ---------------------------------------------------------------- outputs
+// true residual and compliance: partials of ||f - K~u||^2 and f^T u
+__global__ void k_final_dots(const double* __restrict__ f, const double* __restrict__ t,
+                             const double* __restrict__ u, int64_t n, double* part) {
+    double a = 0.0, b = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += (int64_t)gridDim.x * WG) {
+        a += t[i] * t[i];
+        b += f[i] * u[i];
+    }
+    a = block_sum_all(a);
+    b = block_sum_all(b);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = a;
+        part[gridDim.x + blockIdx.x] = b;
+    }
+}
+__global__ void k_final_scalars(KScal* sc, const double* part, int nparts) {
+    const double tt = sum_parts(part, nparts, 0);
+    const double fu = sum_parts(part, nparts, 1);
+    if (threadIdx.x == 0) {
+        sc->pq = tt;        // true ||f - K~ u||^2 (reuses the slot once the loop is over)
+        sc->zq = fu;        // compliance f^T u
+    }
+}
+
+void launch_final_residual(const tm_hierarchy* h, Lane& ln, KScal* sc, const double* u,
+                           hipStream_t s) {
+    const int64_t n = h->n_dof;
+    launch_fine_op<double>(h, OP_RESID, false, u, ln.f, ln.q, 0.0, nullptr, nullptr, s);
+    const int nb = krylov_blocks(n);
+    hipLaunchKernelGGL(k_final_dots, dim3(nb), dim3(WG), 0, s, ln.f, ln.q, u, n, ln.part);
+    hipLaunchKernelGGL(k_final_scalars, dim3(1), dim3(WG), 0, s, sc, ln.part, nb);
+}
+
+}  // namespace tmi

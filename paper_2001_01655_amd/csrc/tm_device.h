@@ -1,0 +1,141 @@
+// Device helpers shared by the HIP translation units of libtopomg.
+#pragma once
+#include "tm_internal.h"
+
+namespace tmi {
+
+// ------------------------------------------------------------ block reduce
+template <int NV>
+__device__ __forceinline__ void block_reduce_store(double (&v)[NV], double* partials) {
+    // fixed-shape tree: wave shuffles, then one wave over the wave sums
+    __shared__ double red[NV][WG / 64];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        double a = v[q];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) a += __shfl_down(a, o, 64);
+        if ((threadIdx.x & 63) == 0) red[q][threadIdx.x >> 6] = a;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+            double a = 0.0;
+#pragma unroll
+            for (int w = 0; w < WG / 64; ++w) a += red[q][w];
+            partials[(int64_t)q * gridDim.x + blockIdx.x] = a;
+        }
+    }
+}
+
+// ------------------------------------------------------------ small SPD inverse
+// Inverse of a symmetric positive definite BS x BS block through its Cholesky
+// factor: A^-1 = L^-T L^-1.  Returns false on a non-positive pivot.
+template <int BS>
+__device__ bool spd_inverse(const double (&A)[BS][BS], double (&X)[BS][BS]) {
+    double L[BS][BS];
+    bool ok = true;
+#pragma unroll
+    for (int j = 0; j < BS; ++j) {
+        double d = A[j][j];
+#pragma unroll
+        for (int k = 0; k < j; ++k) d -= L[j][k] * L[j][k];
+        ok = ok && (d > 0.0);
+        double ljj = d > 0.0 ? sqrt(d) : 1.0;
+        L[j][j] = ljj;
+#pragma unroll
+        for (int i = j + 1; i < BS; ++i) {
+            double t = A[i][j];
+#pragma unroll
+            for (int k = 0; k < j; ++k) t -= L[i][k] * L[j][k];
+            L[i][j] = t / ljj;
+        }
+#pragma unroll
+        for (int i = 0; i < j; ++i) L[i][j] = 0.0;
+    }
+    // W = L^-1 (lower triangular)
+    double W[BS][BS];
+#pragma unroll
+    for (int c = 0; c < BS; ++c) {
+#pragma unroll
+        for (int i = 0; i < BS; ++i) {
+            double t = (i == c) ? 1.0 : 0.0;
+#pragma unroll
+            for (int k = 0; k < i; ++k) t -= L[i][k] * W[k][c];
+            W[i][c] = (i < c) ? 0.0 : t / L[i][i];
+        }
+    }
+    // X = W^T W
+#pragma unroll
+    for (int i = 0; i < BS; ++i)
+#pragma unroll
+        for (int j = 0; j < BS; ++j) {
+            double t = 0.0;
+#pragma unroll
+            for (int k = 0; k < BS; ++k) t += W[k][i] * W[k][j];
+            X[i][j] = t;
+        }
+    return ok;
+}
+
+template <int BS>
+__device__ void store_dinv(double (&D)[BS][BS], int point, int64_t node, int64_t N,
+                          double* __restrict__ d64, float* __restrict__ d32, int* flags) {
+    double X[BS][BS];
+    if (point) {
+#pragma unroll
+        for (int i = 0; i < BS; ++i)
+#pragma unroll
+            for (int j = 0; j < BS; ++j) X[i][j] = (i == j) ? 1.0 / D[i][i] : 0.0;
+        bool ok = true;
+#pragma unroll
+        for (int i = 0; i < BS; ++i) ok = ok && D[i][i] > 0.0;
+        if (!ok) atomicOr(flags, FLAG_NOT_SPD);
+    } else if (!spd_inverse<BS>(D, X)) {
+        atomicOr(flags, FLAG_NOT_SPD);
+    }
+#pragma unroll
+    for (int i = 0; i < BS; ++i)
+#pragma unroll
+        for (int j = 0; j < BS; ++j) {
+            d64[(int64_t)(i * BS + j) * N + node] = X[i][j];
+            d32[(int64_t)(i * BS + j) * N + node] = (float)X[i][j];
+        }
+}
+
+// ------------------------------------------------------------ operator kernels
+template <typename T, int BS, int OP>
+__device__ __forceinline__ void finish_node(int64_t node, int64_t N, T (&kx)[BS], const T (&xo)[BS],
+                                            uint8_t m, const T* __restrict__ b, T* __restrict__ y,
+                                            const T* __restrict__ dinv, T omega, double (&dots)[2]) {
+#pragma unroll
+    for (int c = 0; c < BS; ++c)
+        if (m & (1u << c)) kx[c] = xo[c];               // unit row of a supported dof
+    if (OP == OP_APPLY) {
+#pragma unroll
+        for (int c = 0; c < BS; ++c) y[BS * node + c] = kx[c];
+    } else if (OP == OP_RESID) {
+#pragma unroll
+        for (int c = 0; c < BS; ++c) y[BS * node + c] = b[BS * node + c] - kx[c];
+    } else if (OP == OP_SMOOTH) {
+        T rr[BS];
+#pragma unroll
+        for (int c = 0; c < BS; ++c) rr[c] = b[BS * node + c] - kx[c];
+#pragma unroll
+        for (int r = 0; r < BS; ++r) {
+            T t = 0;
+#pragma unroll
+            for (int c = 0; c < BS; ++c) t += dinv[(int64_t)(r * BS + c) * N + node] * rr[c];
+            y[BS * node + r] = xo[r] + omega * t;
+        }
+    } else {  // OP_QDOT: q = K~ p, partial p.q and p.r (b holds r)
+#pragma unroll
+        for (int c = 0; c < BS; ++c) {
+            y[BS * node + c] = kx[c];
+            dots[0] += (double)xo[c] * (double)kx[c];
+            dots[1] += (double)xo[c] * (double)b[BS * node + c];
+        }
+    }
+}
+
+}  // namespace tmi

@@ -1,0 +1,222 @@
+// Internal declarations shared by the HIP translation units of libtopomg.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "topomg.h"
+
+namespace tmi {
+
+constexpr int WG = 256;                 // threads per workgroup for node-parallel kernels
+
+// ----------------------------------------------------------------- errors
+struct Error {
+    tm_status code;
+    std::string msg;
+};
+void set_error(const std::string& msg);
+[[noreturn]] void fail(tm_status code, const std::string& msg);
+void check_hip(hipError_t e, const char* what);
+#define TM_HIP(call) ::tmi::check_hip((call), #call)
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+inline unsigned grid_for(int64_t n, int wg = WG) { return (unsigned)ceil_div(n > 0 ? n : 1, wg); }
+
+// ----------------------------------------------------------------- device helpers
+// Logical workgroup index such that consecutive logical indices run on the same
+// XCD (hardware dispatches workgroups round-robin over the 8 XCDs).
+__device__ __forceinline__ int64_t xcd_block() {
+    const uint32_t nb = gridDim.x, b = blockIdx.x;
+    const uint32_t q = nb >> 3, r = nb & 7u, x = b & 7u, k = b >> 3;
+    return (int64_t)(x * q + (x < r ? x : r) + k);
+}
+
+// local index of the element corner at offsets (lx, ly[, lz]) in {0,1}: 2D
+// counter-clockwise from the lower-left corner, 3D bottom face then top face.
+__host__ __device__ constexpr int loc2(int lx, int ly) { return ly ? (lx ? 2 : 3) : (lx ? 1 : 0); }
+__host__ __device__ constexpr int loc3(int lx, int ly, int lz) { return 4 * lz + loc2(lx, ly); }
+
+// Status flags written by kernels (checked by the host after setup phases).
+enum : int { FLAG_BAD_RHO = 1, FLAG_NOT_SPD = 2, FLAG_OVERFLOW = 4 };
+
+// Per right-hand-side Krylov scalars, resident on the device.
+struct KScal {
+    double pq, pr, rr, zq, zr, zr_old;
+    double alpha, beta;
+    double rr_stop;         // (rtol ||M f||)^2
+    double ff;              // ||M f||^2
+    double rr_last;         // ||r||^2 after the last completed iteration
+    int32_t iter, done, status, max_iters;
+    int32_t outer;          // TM_OUTER_*
+    int32_t pad[3];
+};
+
+// ----------------------------------------------------------------- structures
+struct BSR {                // block sparse rows, int32 block columns
+    int64_t nbr = 0, nbc = 0, nnzb = 0;
+    int br = 0, bc = 0;     // block shape
+    int32_t* rp = nullptr;  // nbr + 1
+    int32_t* ci = nullptr;  // nnzb
+    double* v64 = nullptr;  // nnzb * br * bc, row-major blocks
+    float* v32 = nullptr;
+};
+
+struct Level {
+    int kind = TM_LEVEL_FINE;     // TM_LEVEL_*
+    int dim = 0;
+    int nel[3] = {1, 1, 1};       // elements per axis (geometric levels)
+    int nn[3] = {1, 1, 1};        // nodes per axis
+    int64_t n_nodes = 0;          // block rows
+    int bs = 0;                   // dofs per block row
+    int64_t n = 0;                // dofs
+    // fine level
+    double* E64 = nullptr;
+    float* E32 = nullptr;
+    uint8_t* nmask = nullptr;     // per node: bit c set <=> dof c supported
+    // geometric coarse level: stencil [nst][bs*bs][n_nodes]
+    int nst = 0;
+    double* st64 = nullptr;
+    float* st32 = nullptr;
+    // aggregation level operator
+    BSR A;
+    // point-block Jacobi inverse [bs*bs][n_nodes]
+    double* dinv64 = nullptr;
+    float* dinv32 = nullptr;
+    // transfer to the next coarser level: geometric stencil or explicit P / P^T
+    bool xfer_bsr = false;
+    BSR P, PT;
+    int32_t* agg = nullptr;       // aggregates of this level's nodes (if xfer_bsr)
+    int64_t n_agg = 0;
+    double* coords = nullptr;     // candidate vectors for aggregation [n][k] (setup only)
+};
+
+struct Vcyc {                     // V-cycle work vectors of one precision, per level
+    std::vector<void*> b, x, t;   // rhs, iterate, scratch (same length per level)
+};
+
+struct Lane;                      // one right-hand side of a solve state
+
+}  // namespace tmi
+
+struct tm_hierarchy {
+    tm_mesh mesh{};
+    tm_material mat{};
+    tm_options opt{};
+    int dim = 0;
+    int64_t n_el = 0, n_nodes = 0, n_dof = 0;
+    std::vector<int64_t> fixed;
+    std::vector<tmi::Level> lv;
+    double* KE64 = nullptr;        // element stiffness for E = 1 (device)
+    float* KE32 = nullptr;
+    double* Q64 = nullptr;         // coarse-from-fine interpolation weights per child [2^d][2^d][2^d]
+    double* ainv = nullptr;        // inverse of the coarsest operator (FP64, dense)
+    float* ainv32 = nullptr;
+    int64_t nc = 0;                // coarsest dofs
+    size_t ainv_cap = 0;
+    bool sa = false;               // smoothed-aggregation levels below the geometric ones
+    int* flags = nullptr;          // device status flags
+    double* elem_a = nullptr;      // setup workspace: element matrices (ping)
+    double* elem_b = nullptr;      // (pong)
+    size_t bytes = 0;
+    std::vector<void*> allocs;
+    // kernel timing hooks
+    bool timing[2] = {false, false};
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> tev[2];
+    // default solve state (tm_solve)
+    tm_solve_state* cached = nullptr;
+};
+
+struct tm_solve_state {
+    tm_hierarchy* h = nullptr;
+    hipStream_t s = nullptr;
+    int32_t nrhs = 0;
+    double rtol = 0.0;
+    int use_u0 = 0;
+    double* u = nullptr;           // caller's output (n_dof * nrhs)
+    std::vector<tmi::Lane*> lanes;
+    tmi::KScal* sc = nullptr;      // device scalars [nrhs]
+    tmi::KScal* sc_host = nullptr; // pinned mirror
+    hipEvent_t ev = nullptr;
+    bool ended = false, pending = false;
+    bool owned_by_h = false;
+    size_t bytes = 0;
+    std::vector<void*> allocs;
+};
+
+namespace tmi {
+
+struct Lane {
+    double *f = nullptr, *r = nullptr, *p = nullptr, *q = nullptr, *z64 = nullptr;
+    float *r32 = nullptr, *z32 = nullptr;
+    double* part = nullptr;        // reduction partials
+    Vcyc v32, v64;
+};
+
+// ----------------------------------------------------------------- launchers
+// fine level (kernels_fine.hip)
+enum { OP_APPLY = 0, OP_RESID = 1, OP_SMOOTH = 2, OP_QDOT = 3 };
+void launch_simp(const double* rho, int64_t n_el, double p, double E0, double Emin, double* E64,
+                 float* E32, int* flags, hipStream_t s);
+void launch_fine_dinv(const Level& L, const double* KE64, int point_jacobi, int* flags,
+                      hipStream_t s);
+template <typename T>
+void launch_fine_op(const tm_hierarchy* h, int op, bool mask_in, const T* x, const T* b, T* y,
+                    T omega, const int* done, double* partials, hipStream_t s);
+int fine_op_blocks(const tm_hierarchy* h);
+// coarse geometric levels (kernels_coarse.hip)
+void launch_galerkin_elems(const tm_hierarchy* h, int fine_level, const double* child,
+                           double* parent, hipStream_t s);
+void launch_stencil_assemble(const Level& L, const double* elem, hipStream_t s);
+void launch_stencil_dinv(const Level& L, int point_jacobi, int* flags, hipStream_t s);
+template <typename T>
+void launch_stencil_op(const Level& L, int op, const T* x, const T* b, T* y, T omega,
+                       const int* done, hipStream_t s);
+template <typename T>
+void launch_restrict(const Level& fine, const Level& coarse, const T* rf, T* bc, T* xc_first,
+                     T omega, const int* done, hipStream_t s);
+template <typename T>
+void launch_prolong(const Level& fine, const Level& coarse, const T* xc, T* xf, const int* done,
+                    hipStream_t s);
+template <typename T>
+void launch_first_smooth(const Level& L, const T* b, T* x, T omega, const int* done, hipStream_t s);
+// dense coarsest level (kernels_dense.hip)
+void launch_dense_from_stencil(const Level& L, double* Ad, hipStream_t s);
+void launch_dense_from_bsr(const Level& L, double* Ad, hipStream_t s);
+void launch_cholesky_inverse(double* A, double* Ainv, int64_t n, int* flags, hipStream_t s);
+template <typename T>
+void launch_dense_solve(const double* Ainv, int64_t n, const T* b, T* x, const int* done,
+                        hipStream_t s);
+// aggregation levels (kernels_sa.hip)
+template <typename T>
+void launch_bsr_op(const Level& L, int op, const T* x, const T* b, T* y, T omega, const int* done,
+                   hipStream_t s);
+template <typename T>
+void launch_bsr_restrict(const Level& fine, const T* rf, T* bc, const Level& coarse, T* xc_first,
+                         T omega, const int* done, hipStream_t s);
+template <typename T>
+void launch_bsr_prolong(const Level& fine, const T* xc, T* xf, const int* done, hipStream_t s);
+void launch_bsr_dinv(const Level& L, int point_jacobi, int* flags, hipStream_t s);
+// Krylov (kernels_krylov.hip)
+template <typename T>
+void launch_mask_copy(const tm_hierarchy* h, const T* src, T* dst, hipStream_t s);
+void launch_fcg_init(const tm_hierarchy* h, Lane& ln, KScal* sc, int use_u0, double* u,
+                     double rtol, int max_iters, int outer, hipStream_t s);
+void launch_reduce_alpha(KScal* sc, const double* part, int nparts, hipStream_t s);
+void launch_update_ur(const tm_hierarchy* h, Lane& ln, KScal* sc, double* u, bool mixed,
+                      hipStream_t s);
+void launch_reduce_rr(KScal* sc, const double* part, int nparts, hipStream_t s);
+void launch_zdots(const tm_hierarchy* h, Lane& ln, KScal* sc, bool mixed, hipStream_t s);
+void launch_reduce_beta(KScal* sc, const double* part, int nparts, hipStream_t s);
+void launch_update_p(const tm_hierarchy* h, Lane& ln, KScal* sc, bool mixed, hipStream_t s);
+void launch_final_residual(const tm_hierarchy* h, Lane& ln, KScal* sc, const double* u,
+                           hipStream_t s);
+void launch_cast(const double* a, float* b, int64_t n, hipStream_t s);
+void launch_cast_back(const float* a, double* b, int64_t n, hipStream_t s);
+void launch_fill(void* p, int64_t n_bytes, hipStream_t s);
+int krylov_blocks(int64_t n);
+
+}  // namespace tmi
