@@ -429,7 +429,8 @@ static void prolong_from(tm_hierarchy* h, int l, const T* xc, T* xf, const int* 
 // z = V(b0) on level 0 (Algorithm 1 from x = 0).  Work vectors of level l:
 // V.b[l] (l > 0), V.x[l], V.t[l].  The last post-smoothing sweep writes z.
 template <typename T>
-static void vcycle(tm_hierarchy* h, Vcyc& V, const T* b0, T* z, const int* done, hipStream_t s) {
+static void vcycle(tm_hierarchy* h, Vcyc& V, const T* b0, T* z, const int* done, hipStream_t s,
+                   bool first_done = false) {
     const int L = (int)h->lv.size();
     const int npre = h->opt.nu_pre, npost = h->opt.nu_post;
     const T w = (T)h->opt.omega;
@@ -438,7 +439,7 @@ static void vcycle(tm_hierarchy* h, Vcyc& V, const T* b0, T* z, const int* done,
         const T* b = l == 0 ? b0 : vb<T>(V, l);
         T* x = vx<T>(V, l);
         T* t = vt<T>(V, l);
-        if (l == 0) launch_first_smooth<T>(h->lv[0], b, x, w, done, s);
+        if (l == 0 && !first_done) launch_first_smooth<T>(h->lv[0], b, x, w, done, s);
         for (int k = 1; k < npre; ++k) {
             level_op<T>(h, l, OP_SMOOTH, x, b, t, done, s);
             std::swap(x, t);
@@ -516,6 +517,7 @@ static tm_solve_state* new_state(tm_hierarchy* h, int nrhs) {
             }
         }
         st->sc = dalloc<KScal>(st->allocs, st->bytes, nrhs);
+        TM_HIP(hipMemset(st->sc, 0, sizeof(KScal) * nrhs));
         TM_HIP(hipHostMalloc((void**)&st->sc_host, sizeof(KScal) * nrhs, hipHostMallocDefault));
         TM_HIP(hipEventCreateWithFlags(&st->ev, hipEventDisableTiming));
     } catch (...) {
@@ -537,11 +539,13 @@ static void delete_state(tm_solve_state* st) {
     delete st;
 }
 
-static void enqueue_vcycle_into_z(tm_hierarchy* h, Lane& ln, const int* done, hipStream_t s) {
+// z = V(r); with first_done the fine level's first sweep was produced by the u, r update
+static void enqueue_vcycle_into_z(tm_hierarchy* h, Lane& ln, const int* done, hipStream_t s,
+                                  bool first_done) {
     if (mixed_of(h))
-        vcycle<float>(h, ln.v32, ln.r32, ln.z32, done, s);
+        vcycle<float>(h, ln.v32, ln.r32, ln.z32, done, s, first_done);
     else
-        vcycle<double>(h, ln.v64, ln.r, ln.z64, done, s);
+        vcycle<double>(h, ln.v64, ln.r, ln.z64, done, s, first_done);
 }
 
 static void enqueue_begin(tm_solve_state* st, const double* f, int use_u0) {
@@ -557,9 +561,9 @@ static void enqueue_begin(tm_solve_state* st, const double* f, int use_u0) {
         launch_fcg_init(h, ln, sc, use_u0, u, st->rtol, h->opt.max_iters, h->opt.outer, s);
         if (mixed) launch_cast(ln.r, ln.r32, n, s);
         const int* done = &sc->done;
-        enqueue_vcycle_into_z(h, ln, done, s);
+        enqueue_vcycle_into_z(h, ln, done, s, false);
         launch_zdots(h, ln, sc, mixed, s);
-        launch_reduce_beta(sc, ln.part, krylov_blocks(n), s);
+        launch_finalize(sc, ln.part, krylov_blocks(n), FIN_BETA, s);
         TM_HIP(hipMemsetAsync(ln.p, 0, n * sizeof(double), s));
         launch_update_p(h, ln, sc, mixed, s);
     }
@@ -578,12 +582,12 @@ static void enqueue_iteration(tm_solve_state* st, int k) {
     timed_begin(h, 0, s, &e0);
     launch_fine_op<double>(h, OP_QDOT, false, ln.p, ln.r, ln.q, 0.0, done, ln.part, s);
     timed_end(h, 0, s, e0);
-    launch_reduce_alpha(sc, ln.part, fine_op_blocks(h), s);
+    launch_finalize(sc, ln.part, fine_op_blocks(h), FIN_ALPHA, s);
     launch_update_ur(h, ln, sc, u, mixed, s);
-    launch_reduce_rr(sc, ln.part, krylov_blocks(n), s);
-    enqueue_vcycle_into_z(h, ln, done, s);
+    launch_finalize(sc, ln.part, fine_op_blocks(h), FIN_RR, s);
+    enqueue_vcycle_into_z(h, ln, done, s, true);
     launch_zdots(h, ln, sc, mixed, s);
-    launch_reduce_beta(sc, ln.part, krylov_blocks(n), s);
+    launch_finalize(sc, ln.part, krylov_blocks(n), FIN_BETA, s);
     launch_update_p(h, ln, sc, mixed, s);
 }
 

@@ -199,18 +199,25 @@ __global__ __launch_bounds__(WG) void k_stencil_op(const T* __restrict__ st, int
     const int i = (int)(node % NX);
     const int j = (int)((node / NX) % NY);
     const int k = DIM == 3 ? (int)(node / ((int64_t)NX * NY)) : 0;
+    // Neighbours outside the grid carry zero blocks, so their (clamped, in-bounds)
+    // x loads contribute nothing; no branches keep all loads in flight at once.
     T acc[DIM] = {};
+    int ci[3], cj[3], ck[3];
 #pragma unroll
-    for (int dz = (DIM == 3 ? -1 : 0); dz <= (DIM == 3 ? 1 : 0); ++dz)
+    for (int d = 0; d < 3; ++d) {
+        ci[d] = min(max(i + d - 1, 0), NX - 1);
+        cj[d] = min(max(j + d - 1, 0), NY - 1);
+        ck[d] = DIM == 3 ? min(max(k + d - 1, 0), NZ - 1) : 0;
+    }
 #pragma unroll
-        for (int dy = -1; dy <= 1; ++dy)
+    for (int dz = 0; dz < (DIM == 3 ? 3 : 1); ++dz)
 #pragma unroll
-            for (int dx = -1; dx <= 1; ++dx) {
-                const int o = DIM == 3 ? (dz + 1) * 9 + (dy + 1) * 3 + dx + 1 : (dy + 1) * 3 + dx + 1;
-                const int ii = i + dx, jj = j + dy, kk = k + dz;
-                const bool ok = ii >= 0 && ii < NX && jj >= 0 && jj < NY && (DIM == 2 || (kk >= 0 && kk < NZ));
-                if (!ok) continue;
-                const int64_t J = DIM == 3 ? ((int64_t)kk * NY + jj) * NX + ii : (int64_t)jj * NX + ii;
+        for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+            for (int dx = 0; dx < 3; ++dx) {
+                const int o = DIM == 3 ? dz * 9 + dy * 3 + dx : dy * 3 + dx;
+                const int64_t J = DIM == 3 ? ((int64_t)ck[dz] * NY + cj[dy]) * NX + ci[dx]
+                                           : (int64_t)cj[dy] * NX + ci[dx];
                 T xv[DIM];
 #pragma unroll
                 for (int c = 0; c < DIM; ++c) xv[c] = x[DIM * J + c];
@@ -302,14 +309,14 @@ __global__ __launch_bounds__(WG) void k_restrict(const T* __restrict__ rf, const
 #pragma unroll
             for (int dx = -1; dx <= 1; ++dx) {
                 const int fi = 2 * I + dx, fj = 2 * J + dy, fk = 2 * K + dz;
-                if (fi < 0 || fi >= FX || fj < 0 || fj >= FY) continue;
-                if (DIM == 3 && (fk < 0 || fk >= FZ)) continue;
-                const int64_t f = DIM == 3 ? ((int64_t)fk * FY + fj) * FX + fi : (int64_t)fj * FX + fi;
-                const T w = (dx ? T(0.5) : T(1)) * (dy ? T(0.5) : T(1)) * (dz ? T(0.5) : T(1));
+                const bool in = fi >= 0 && fi < FX && fj >= 0 && fj < FY && (DIM == 2 || (fk >= 0 && fk < FZ));
+                const int gi = min(max(fi, 0), FX - 1), gj = min(max(fj, 0), FY - 1);
+                const int gk = DIM == 3 ? min(max(fk, 0), FZ - 1) : 0;
+                const int64_t f = DIM == 3 ? ((int64_t)gk * FY + gj) * FX + gi : (int64_t)gj * FX + gi;
+                const T w = in ? (dx ? T(0.5) : T(1)) * (dy ? T(0.5) : T(1)) * (dz ? T(0.5) : T(1)) : T(0);
                 const uint8_t m = nm ? nm[f] : 0;
 #pragma unroll
-                for (int c = 0; c < DIM; ++c)
-                    if (!(m & (1u << c))) acc[c] += w * rf[DIM * f + c];
+                for (int c = 0; c < DIM; ++c) acc[c] += ((m >> c) & 1u) ? T(0) : w * rf[DIM * f + c];
             }
 #pragma unroll
     for (int c = 0; c < DIM; ++c) bc[DIM * node + c] = acc[c];
@@ -368,16 +375,24 @@ __global__ __launch_bounds__(WG) void k_prolong(const T* __restrict__ xc, const 
     const int i = (int)(node % FX);
     const int j = (int)((node / FX) % FY);
     const int k = DIM == 3 ? (int)(node / ((int64_t)FX * FY)) : 0;
-    const int i0 = i >> 1, j0 = j >> 1, k0 = k >> 1;
-    const int ni = (i & 1) ? 2 : 1, nj = (j & 1) ? 2 : 1, nk = (DIM == 3 && (k & 1)) ? 2 : 1;
-    const T wi = (i & 1) ? T(0.5) : T(1), wj = (j & 1) ? T(0.5) : T(1), wk = (k & 1) ? T(0.5) : T(1);
+    const int CZ = fnz / 2 + 1;
+    // per axis: coarse nodes i>>1 and (i>>1)+1 (clamped), weights (1, 0) or (1/2, 1/2)
+    const int ia[2] = {i >> 1, min((i >> 1) + 1, CX - 1)};
+    const int ja[2] = {j >> 1, min((j >> 1) + 1, CY - 1)};
+    const int ka[2] = {k >> 1, DIM == 3 ? min((k >> 1) + 1, CZ - 1) : 0};
+    const T wi[2] = {(i & 1) ? T(0.5) : T(1), (i & 1) ? T(0.5) : T(0)};
+    const T wj[2] = {(j & 1) ? T(0.5) : T(1), (j & 1) ? T(0.5) : T(0)};
+    const T wk[2] = {(k & 1) ? T(0.5) : T(1), (k & 1) ? T(0.5) : T(0)};
     T acc[DIM] = {};
-    for (int c2 = 0; c2 < nk; ++c2)
-        for (int b2 = 0; b2 < nj; ++b2)
-            for (int a2 = 0; a2 < ni; ++a2) {
-                const int64_t C = DIM == 3 ? ((int64_t)(k0 + c2) * CY + (j0 + b2)) * CX + i0 + a2
-                                           : (int64_t)(j0 + b2) * CX + i0 + a2;
-                const T w = wi * wj * (DIM == 3 ? wk : T(1));
+#pragma unroll
+    for (int c2 = 0; c2 < (DIM == 3 ? 2 : 1); ++c2)
+#pragma unroll
+        for (int b2 = 0; b2 < 2; ++b2)
+#pragma unroll
+            for (int a2 = 0; a2 < 2; ++a2) {
+                const int64_t C = DIM == 3 ? ((int64_t)ka[c2] * CY + ja[b2]) * CX + ia[a2]
+                                           : (int64_t)ja[b2] * CX + ia[a2];
+                const T w = wi[a2] * wj[b2] * (DIM == 3 ? wk[c2] : T(1));
 #pragma unroll
                 for (int c = 0; c < DIM; ++c) acc[c] += w * xc[DIM * C + c];
             }

@@ -85,9 +85,11 @@ __global__ __launch_bounds__(1024) void k_cholesky(double* __restrict__ A, int64
         const double dk = A[k * n + k];
         for (int64_t i = k + 1 + t; i < n; i += nt) A[i * n + k] /= dk;
         __syncthreads();
-        for (int64_t j = k + 1 + t; j < n; j += nt) {
-            const double ljk = A[j * n + k];
-            for (int64_t i = j; i < n; ++i) A[i * n + j] -= A[i * n + k] * ljk;
+        // trailing update of the lower triangle, all threads over (i, j) pairs
+        const int64_t m = n - k - 1;
+        for (int64_t q = t; q < m * m; q += nt) {
+            const int64_t i = k + 1 + q / m, j = k + 1 + q % m;
+            if (j <= i) A[i * n + j] -= A[i * n + k] * A[j * n + k];
         }
     }
     __syncthreads();

@@ -280,7 +280,10 @@ void launch_fine_op(const tm_hierarchy* h, int op, bool mask_in, const T* x, con
         case OP_APPLY: fine_dispatch<T, OP_APPLY, false>(h, x, b, y, omega, done, partials, s); break;
         case OP_RESID: fine_dispatch<T, OP_RESID, false>(h, x, b, y, omega, done, partials, s); break;
         case OP_SMOOTH: fine_dispatch<T, OP_SMOOTH, false>(h, x, b, y, omega, done, partials, s); break;
-        default: fine_dispatch<T, OP_QDOT, false>(h, x, b, y, omega, done, partials, s); break;
+        default:
+            if (!partials) fail(TM_ERR_ARG, "q = K~p needs a partial-sum buffer");
+            fine_dispatch<T, OP_QDOT, false>(h, x, b, y, omega, done, partials, s);
+            break;
     }
 }
 template void launch_fine_op<double>(const tm_hierarchy*, int, bool, const double*, const double*,

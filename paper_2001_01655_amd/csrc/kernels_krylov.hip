@@ -16,26 +16,6 @@ constexpr int KB_MAX = 2048;   // blocks of the grid-stride vector kernels
 
 int krylov_blocks(int64_t n) { return (int)std::min<int64_t>(ceil_div(n > 0 ? n : 1, WG), KB_MAX); }
 
-__device__ __forceinline__ double block_sum_all(double v) {
-    __shared__ double red[WG / 64];
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-    __syncthreads();
-    double a = 0.0;
-#pragma unroll
-    for (int w = 0; w < WG / 64; ++w) a += red[w];
-    __syncthreads();
-    return a;
-}
-
-// sum of nparts partials per quantity, fixed order, one block
-__device__ __forceinline__ double sum_parts(const double* part, int nparts, int q) {
-    double a = 0.0;
-    for (int i = threadIdx.x; i < nparts; i += WG) a += part[(int64_t)q * nparts + i];
-    return block_sum_all(a);
-}
-
 // ---------------------------------------------------------------- masks, casts
 template <typename T>
 __global__ void k_mask_copy(const T* src, T* dst, const uint8_t* __restrict__ nm, int bs,
@@ -77,27 +57,98 @@ void launch_fill(void* p, int64_t n_bytes, hipStream_t s) {
     hipLaunchKernelGGL(k_fill, dim3(grid_for(n)), dim3(WG), 0, s, (uint32_t*)p, n);
 }
 
-// ---------------------------------------------------------------- init
-// partials: ||f||^2, ||r||^2 (r = f - K~ u0 or f)
-__global__ void k_init_dots(const double* __restrict__ f, const double* __restrict__ r, int64_t n,
-                            double* part) {
-    double a = 0.0, b = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += (int64_t)gridDim.x * WG) {
-        a += f[i] * f[i];
-        b += r[i] * r[i];
-    }
-    a = block_sum_all(a);
-    b = block_sum_all(b);
-    if (threadIdx.x == 0) {
-        part[blockIdx.x] = a;
-        part[gridDim.x + blockIdx.x] = b;
+// ---------------------------------------------------------------- finalisation
+// One block of FB threads sums the per-block partials in a fixed order and
+// updates the scalars of its right-hand side.
+constexpr int FB = 1024;
+
+__device__ __forceinline__ double fin_sum(const double* part, int nparts, int q) {
+    __shared__ double red[FB / 64];
+    double a = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += FB) a += part[(int64_t)q * nparts + i];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) a += __shfl_down(a, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = a;
+    __syncthreads();
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < FB / 64; ++w) t += red[w];
+    __syncthreads();
+    return t;
+}
+
+__global__ __launch_bounds__(FB) void k_finalize(KScal* sc, const double* part, int nparts, int what) {
+    if (sc->done) return;
+    if (what == FIN_ALPHA) {
+        const double pq = fin_sum(part, nparts, 0), pr = fin_sum(part, nparts, 1);
+        if (threadIdx.x == 0) {
+            sc->pq = pq;
+            sc->pr = pr;
+            if (!(pq > 0.0)) {
+                sc->status = TM_ERR_BREAKDOWN;
+                sc->done = 1;
+                sc->alpha = 0.0;
+            } else {
+                sc->alpha = pr / pq;
+            }
+        }
+    } else if (what == FIN_RR) {
+        const double rr = fin_sum(part, nparts, 0);
+        if (threadIdx.x == 0) {
+            sc->rr = rr;
+            sc->rr_last = rr;
+            sc->iter += 1;
+            if (rr <= sc->rr_stop) {
+                sc->done = 1;
+                sc->status = TM_OK;
+            } else if (!(rr == rr)) {
+                sc->done = 1;
+                sc->status = TM_ERR_BREAKDOWN;
+            } else if (sc->iter >= sc->max_iters) {
+                sc->done = 1;
+                sc->status = TM_NOT_CONVERGED;
+            }
+        }
+    } else {
+        // beta; on the first call (iter == 0, no previous direction) only z^T r is kept
+        const double zq = fin_sum(part, nparts, 0), zr = fin_sum(part, nparts, 1);
+        if (threadIdx.x == 0) {
+            sc->zq = zq;
+            sc->zr = zr;
+            if (sc->outer == TM_OUTER_PCG && !(zr > 0.0)) {
+                sc->status = TM_ERR_BREAKDOWN;
+                sc->done = 1;
+                return;
+            }
+            if (sc->iter == 0)
+                sc->beta = 0.0;
+            else if (sc->outer == TM_OUTER_PCG)
+                sc->beta = zr / sc->zr_old;
+            else
+                sc->beta = -zq / sc->pq;
+            sc->zr_old = zr;
+        }
     }
 }
 
-__global__ void k_init_scalars(KScal* sc, const double* part, int nparts, double rtol,
-                               int max_iters, int outer) {
-    const double ff = sum_parts(part, nparts, 0);
-    const double rr = sum_parts(part, nparts, 1);
+void launch_finalize(KScal* sc, const double* part, int nparts, int what, hipStream_t s) {
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(FB), 0, s, sc, part, nparts, what);
+}
+
+// init: ||f||^2 and ||r||^2, then the scalars of a fresh solve
+__global__ void k_init_dots(const double* __restrict__ f, const double* __restrict__ r, int64_t n,
+                            double* part) {
+    double v[2] = {0.0, 0.0};
+    for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += (int64_t)gridDim.x * WG) {
+        v[0] += f[i] * f[i];
+        v[1] += r[i] * r[i];
+    }
+    block_reduce_store<2>(v, part);
+}
+
+__global__ __launch_bounds__(FB) void k_init_scalars(KScal* sc, const double* part, int nparts,
+                                                    double rtol, int max_iters, int outer) {
+    const double ff = fin_sum(part, nparts, 0), rr = fin_sum(part, nparts, 1);
     if (threadIdx.x == 0) {
         sc->ff = ff;
         sc->rr = rr;
@@ -125,83 +176,66 @@ void launch_fcg_init(const tm_hierarchy* h, Lane& ln, KScal* sc, int use_u0, dou
     }
     const int nb = krylov_blocks(n);
     hipLaunchKernelGGL(k_init_dots, dim3(nb), dim3(WG), 0, s, ln.f, ln.r, n, ln.part);
-    hipLaunchKernelGGL(k_init_scalars, dim3(1), dim3(WG), 0, s, sc, ln.part, nb, rtol, max_iters,
-                       outer);
-}
-
-// ---------------------------------------------------------------- alpha
-__global__ void k_reduce_alpha(KScal* sc, const double* part, int nparts) {
-    if (sc->done) return;
-    const double pq = sum_parts(part, nparts, 0);
-    const double pr = sum_parts(part, nparts, 1);
-    if (threadIdx.x == 0) {
-        sc->pq = pq;
-        sc->pr = pr;
-        if (!(pq > 0.0)) {
-            sc->status = TM_ERR_BREAKDOWN;
-            sc->done = 1;
-            sc->alpha = 0.0;
-        } else {
-            sc->alpha = pr / pq;
-        }
-    }
-}
-void launch_reduce_alpha(KScal* sc, const double* part, int nparts, hipStream_t s) {
-    hipLaunchKernelGGL(k_reduce_alpha, dim3(1), dim3(WG), 0, s, sc, part, nparts);
+    hipLaunchKernelGGL(k_init_scalars, dim3(1), dim3(FB), 0, s, sc, ln.part, nb, rtol, max_iters, outer);
 }
 
 // ---------------------------------------------------------------- u, r update
-template <bool MIXED>
-__global__ void k_update_ur(double* __restrict__ u, double* __restrict__ r, const double* __restrict__ p,
-                            const double* __restrict__ q, float* __restrict__ r32, int64_t n,
-                            const KScal* __restrict__ sc, double* part) {
+// Node-parallel: u += alpha p, r -= alpha q, ||r||^2; the r copy handed to the
+// V-cycle (FP32 in the mixed path) and the V-cycle's first fine-level sweep
+// from zero, x0 = omega D^-1 r, are produced in the same pass.
+template <typename TV, int BS>
+__global__ __launch_bounds__(WG) void k_update_ur(double* __restrict__ u, double* __restrict__ r,
+                                                  const double* __restrict__ p, const double* __restrict__ q,
+                                                  TV* __restrict__ rv, TV* __restrict__ x0,
+                                                  const TV* __restrict__ dinv, TV omega, int64_t N,
+                                                  const KScal* __restrict__ sc, double* part) {
     if (sc->done) return;
     const double alpha = sc->alpha;
-    double a = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += (int64_t)gridDim.x * WG) {
-        u[i] += alpha * p[i];
-        const double ri = r[i] - alpha * q[i];
-        r[i] = ri;
-        if (MIXED) r32[i] = (float)ri;
-        a += ri * ri;
+    const int64_t node = xcd_block() * WG + threadIdx.x;
+    double v[1] = {0.0};
+    if (node < N) {
+        TV rl[BS];
+#pragma unroll
+        for (int c = 0; c < BS; ++c) {
+            const int64_t i = BS * node + c;
+            u[i] += alpha * p[i];
+            const double ri = r[i] - alpha * q[i];
+            r[i] = ri;
+            rl[c] = (TV)ri;
+            if (sizeof(TV) == 4) rv[i] = rl[c];
+            v[0] += ri * ri;
+        }
+#pragma unroll
+        for (int a = 0; a < BS; ++a) {
+            TV t = 0;
+#pragma unroll
+            for (int c = 0; c < BS; ++c) t += dinv[(int64_t)(a * BS + c) * N + node] * rl[c];
+            x0[BS * node + a] = omega * t;
+        }
     }
-    a = block_sum_all(a);
-    if (threadIdx.x == 0) part[blockIdx.x] = a;
+    block_reduce_store<1>(v, part);
+}
+
+template <typename TV>
+static void update_ur_t(const tm_hierarchy* h, Lane& ln, KScal* sc, double* u, TV* rv, TV* x0,
+                        const TV* dinv, hipStream_t s) {
+    const Level& L = h->lv[0];
+    const dim3 g(grid_for(L.n_nodes)), b(WG);
+    const TV w = (TV)h->opt.omega;
+    if (L.bs == 3)
+        hipLaunchKernelGGL((k_update_ur<TV, 3>), g, b, 0, s, u, ln.r, ln.p, ln.q, rv, x0, dinv, w, L.n_nodes,
+                           sc, ln.part);
+    else
+        hipLaunchKernelGGL((k_update_ur<TV, 2>), g, b, 0, s, u, ln.r, ln.p, ln.q, rv, x0, dinv, w, L.n_nodes,
+                           sc, ln.part);
 }
 
 void launch_update_ur(const tm_hierarchy* h, Lane& ln, KScal* sc, double* u, bool mixed,
                       hipStream_t s) {
-    const int64_t n = h->n_dof;
-    const int nb = krylov_blocks(n);
     if (mixed)
-        hipLaunchKernelGGL(k_update_ur<true>, dim3(nb), dim3(WG), 0, s, u, ln.r, ln.p, ln.q, ln.r32, n,
-                           sc, ln.part);
+        update_ur_t<float>(h, ln, sc, u, ln.r32, (float*)ln.v32.x[0], h->lv[0].dinv32, s);
     else
-        hipLaunchKernelGGL(k_update_ur<false>, dim3(nb), dim3(WG), 0, s, u, ln.r, ln.p, ln.q, ln.r32, n,
-                           sc, ln.part);
-}
-
-__global__ void k_reduce_rr(KScal* sc, const double* part, int nparts) {
-    if (sc->done) return;
-    const double rr = sum_parts(part, nparts, 0);
-    if (threadIdx.x == 0) {
-        sc->rr = rr;
-        sc->rr_last = rr;
-        sc->iter += 1;
-        if (rr <= sc->rr_stop) {
-            sc->done = 1;
-            sc->status = TM_OK;
-        } else if (!(rr == rr)) {
-            sc->done = 1;
-            sc->status = TM_ERR_BREAKDOWN;
-        } else if (sc->iter >= sc->max_iters) {
-            sc->done = 1;
-            sc->status = TM_NOT_CONVERGED;
-        }
-    }
-}
-void launch_reduce_rr(KScal* sc, const double* part, int nparts, hipStream_t s) {
-    hipLaunchKernelGGL(k_reduce_rr, dim3(1), dim3(WG), 0, s, sc, part, nparts);
+        update_ur_t<double>(h, ln, sc, u, nullptr, (double*)ln.v64.x[0], h->lv[0].dinv64, s);
 }
 
 // ---------------------------------------------------------------- z dots, beta, p
@@ -210,18 +244,13 @@ __global__ void k_zdots(const TZ* __restrict__ z, const double* __restrict__ q,
                         const double* __restrict__ r, int64_t n, const KScal* __restrict__ sc,
                         double* part) {
     if (sc->done) return;
-    double a = 0.0, b = 0.0;
+    double v[2] = {0.0, 0.0};
     for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += (int64_t)gridDim.x * WG) {
         const double zi = (double)z[i];
-        a += zi * q[i];
-        b += zi * r[i];
+        v[0] += zi * q[i];
+        v[1] += zi * r[i];
     }
-    a = block_sum_all(a);
-    b = block_sum_all(b);
-    if (threadIdx.x == 0) {
-        part[blockIdx.x] = a;
-        part[gridDim.x + blockIdx.x] = b;
-    }
+    block_reduce_store<2>(v, part);
 }
 
 void launch_zdots(const tm_hierarchy* h, Lane& ln, KScal* sc, bool mixed, hipStream_t s) {
@@ -231,33 +260,6 @@ void launch_zdots(const tm_hierarchy* h, Lane& ln, KScal* sc, bool mixed, hipStr
         hipLaunchKernelGGL(k_zdots<float>, dim3(nb), dim3(WG), 0, s, ln.z32, ln.q, ln.r, n, sc, ln.part);
     else
         hipLaunchKernelGGL(k_zdots<double>, dim3(nb), dim3(WG), 0, s, ln.z64, ln.q, ln.r, n, sc, ln.part);
-}
-
-// beta; on the first call (iter == 0, p not yet set) it only records z^T r.
-__global__ void k_reduce_beta(KScal* sc, const double* part, int nparts) {
-    if (sc->done) return;
-    const double zq = sum_parts(part, nparts, 0);
-    const double zr = sum_parts(part, nparts, 1);
-    if (threadIdx.x == 0) {
-        sc->zq = zq;
-        sc->zr = zr;
-        if (sc->outer == TM_OUTER_PCG && !(zr > 0.0)) {
-            sc->status = TM_ERR_BREAKDOWN;
-            sc->done = 1;
-            return;
-        }
-        if (sc->iter == 0) {
-            sc->beta = 0.0;
-        } else if (sc->outer == TM_OUTER_PCG) {
-            sc->beta = zr / sc->zr_old;
-        } else {
-            sc->beta = -zq / sc->pq;
-        }
-        sc->zr_old = zr;
-    }
-}
-void launch_reduce_beta(KScal* sc, const double* part, int nparts, hipStream_t s) {
-    hipLaunchKernelGGL(k_reduce_beta, dim3(1), dim3(WG), 0, s, sc, part, nparts);
 }
 
 template <typename TZ>
@@ -279,27 +281,22 @@ void launch_update_p(const tm_hierarchy* h, Lane& ln, KScal* sc, bool mixed, hip
 }
 
 // ---------------------------------------------------------------- outputs
-// true residual and compliance: partials of ||f - K~u||^2 and f^T u
+// true residual ||f - K~u||^2 and compliance f^T u (slots pq / zq once the loop is over)
 __global__ void k_final_dots(const double* __restrict__ f, const double* __restrict__ t,
                              const double* __restrict__ u, int64_t n, double* part) {
-    double a = 0.0, b = 0.0;
+    double v[2] = {0.0, 0.0};
     for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += (int64_t)gridDim.x * WG) {
-        a += t[i] * t[i];
-        b += f[i] * u[i];
+        v[0] += t[i] * t[i];
+        v[1] += f[i] * u[i];
     }
-    a = block_sum_all(a);
-    b = block_sum_all(b);
-    if (threadIdx.x == 0) {
-        part[blockIdx.x] = a;
-        part[gridDim.x + blockIdx.x] = b;
-    }
+    block_reduce_store<2>(v, part);
 }
-__global__ void k_final_scalars(KScal* sc, const double* part, int nparts) {
-    const double tt = sum_parts(part, nparts, 0);
-    const double fu = sum_parts(part, nparts, 1);
+
+__global__ __launch_bounds__(FB) void k_final_scalars(KScal* sc, const double* part, int nparts) {
+    const double tt = fin_sum(part, nparts, 0), fu = fin_sum(part, nparts, 1);
     if (threadIdx.x == 0) {
-        sc->pq = tt;        // true ||f - K~ u||^2 (reuses the slot once the loop is over)
-        sc->zq = fu;        // compliance f^T u
+        sc->pq = tt;
+        sc->zq = fu;
     }
 }
 
@@ -309,7 +306,7 @@ void launch_final_residual(const tm_hierarchy* h, Lane& ln, KScal* sc, const dou
     launch_fine_op<double>(h, OP_RESID, false, u, ln.f, ln.q, 0.0, nullptr, nullptr, s);
     const int nb = krylov_blocks(n);
     hipLaunchKernelGGL(k_final_dots, dim3(nb), dim3(WG), 0, s, ln.f, ln.q, u, n, ln.part);
-    hipLaunchKernelGGL(k_final_scalars, dim3(1), dim3(WG), 0, s, sc, ln.part, nb);
+    hipLaunchKernelGGL(k_final_scalars, dim3(1), dim3(FB), 0, s, sc, ln.part, nb);
 }
 
 }  // namespace tmi

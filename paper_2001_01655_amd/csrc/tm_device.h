@@ -28,6 +28,22 @@ __device__ __forceinline__ void block_reduce_store(double (&v)[NV], double* part
     }
 }
 
+// ------------------------------------------------------------ grid sums
+// Sum over the whole block (fixed wave-shuffle tree, then wave order); every
+// thread gets the result.
+__device__ __forceinline__ double block_sum_all(double v) {
+    __shared__ double red[WG / 64];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double a = 0.0;
+#pragma unroll
+    for (int w = 0; w < WG / 64; ++w) a += red[w];
+    __syncthreads();
+    return a;
+}
+
 // ------------------------------------------------------------ small SPD inverse
 // Inverse of a symmetric positive definite BS x BS block through its Cholesky
 // factor: A^-1 = L^-T L^-1.  Returns false on a non-positive pivot.

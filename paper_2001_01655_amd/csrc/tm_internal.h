@@ -205,12 +205,12 @@ template <typename T>
 void launch_mask_copy(const tm_hierarchy* h, const T* src, T* dst, hipStream_t s);
 void launch_fcg_init(const tm_hierarchy* h, Lane& ln, KScal* sc, int use_u0, double* u,
                      double rtol, int max_iters, int outer, hipStream_t s);
-void launch_reduce_alpha(KScal* sc, const double* part, int nparts, hipStream_t s);
 void launch_update_ur(const tm_hierarchy* h, Lane& ln, KScal* sc, double* u, bool mixed,
                       hipStream_t s);
-void launch_reduce_rr(KScal* sc, const double* part, int nparts, hipStream_t s);
 void launch_zdots(const tm_hierarchy* h, Lane& ln, KScal* sc, bool mixed, hipStream_t s);
-void launch_reduce_beta(KScal* sc, const double* part, int nparts, hipStream_t s);
+// single-block finalisation of the per-block partial sums (fixed order)
+enum { FIN_ALPHA = 0, FIN_RR = 1, FIN_BETA = 2 };
+void launch_finalize(KScal* sc, const double* part, int nparts, int what, hipStream_t s);
 void launch_update_p(const tm_hierarchy* h, Lane& ln, KScal* sc, bool mixed, hipStream_t s);
 void launch_final_residual(const tm_hierarchy* h, Lane& ln, KScal* sc, const double* u,
                            hipStream_t s);
