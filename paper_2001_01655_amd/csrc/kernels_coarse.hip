@@ -201,13 +201,17 @@ __global__ __launch_bounds__(WG) void k_stencil_op(const T* __restrict__ st, int
     const int k = DIM == 3 ? (int)(node / ((int64_t)NX * NY)) : 0;
     // Neighbours outside the grid carry zero blocks, so their (clamped, in-bounds)
     // x loads contribute nothing; no branches keep all loads in flight at once.
+    // 32-bit byte offsets through buffer descriptors (level sizes < 2 GB).
+    const auto sr = buf_rsrc(st, (int64_t)N * (DIM == 3 ? 27 : 9) * BB * sizeof(T));
+    const auto xr = buf_rsrc(x, (int64_t)N * DIM * sizeof(T));
+    const uint32_t un = (uint32_t)node, uN = (uint32_t)N;
     T acc[DIM] = {};
-    int ci[3], cj[3], ck[3];
+    uint32_t ci[3], cj[3], ck[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        ci[d] = min(max(i + d - 1, 0), NX - 1);
-        cj[d] = min(max(j + d - 1, 0), NY - 1);
-        ck[d] = DIM == 3 ? min(max(k + d - 1, 0), NZ - 1) : 0;
+        ci[d] = (uint32_t)min(max(i + d - 1, 0), NX - 1);
+        cj[d] = (uint32_t)min(max(j + d - 1, 0), NY - 1);
+        ck[d] = DIM == 3 ? (uint32_t)min(max(k + d - 1, 0), NZ - 1) : 0u;
     }
 #pragma unroll
     for (int dz = 0; dz < (DIM == 3 ? 3 : 1); ++dz)
@@ -216,15 +220,15 @@ __global__ __launch_bounds__(WG) void k_stencil_op(const T* __restrict__ st, int
 #pragma unroll
             for (int dx = 0; dx < 3; ++dx) {
                 const int o = DIM == 3 ? dz * 9 + dy * 3 + dx : dy * 3 + dx;
-                const int64_t J = DIM == 3 ? ((int64_t)ck[dz] * NY + cj[dy]) * NX + ci[dx]
-                                           : (int64_t)cj[dy] * NX + ci[dx];
+                const uint32_t J = (ck[dz] * (uint32_t)NY + cj[dy]) * (uint32_t)NX + ci[dx];
                 T xv[DIM];
 #pragma unroll
-                for (int c = 0; c < DIM; ++c) xv[c] = x[DIM * J + c];
+                for (int c = 0; c < DIM; ++c) xv[c] = bld<T>(xr, (DIM * J + c) * (uint32_t)sizeof(T));
 #pragma unroll
                 for (int r = 0; r < DIM; ++r)
 #pragma unroll
-                    for (int c = 0; c < DIM; ++c) acc[r] += st[((int64_t)o * BB + r * DIM + c) * N + node] * xv[c];
+                    for (int c = 0; c < DIM; ++c)
+                        acc[r] += bld<T>(sr, ((uint32_t)(o * BB + r * DIM + c) * uN + un) * (uint32_t)sizeof(T)) * xv[c];
             }
     T xo[DIM];
 #pragma unroll

@@ -85,48 +85,47 @@ void launch_fine_dinv(const Level& L, const double* KE64, int point_jacobi, int*
                            L.n_nodes, point_jacobi, L.dinv64, L.dinv32, flags);
 }
 
-// 3D: 27 neighbour nodes, 8 elements, 24x24 KE.
+// 3D: 27 neighbour nodes, 8 elements, 24x24 KE.  Indices are 32-bit (dofs <
+// 2^31 is checked at setup).  Neighbour loads use clamped coordinates and are
+// unconditional; an element outside the grid gets modulus 0, so the values
+// loaded for it (from a clamped, in-bounds node) contribute nothing.
 template <typename T, int OP, bool MASK_IN>
 __global__ __launch_bounds__(WG) void k_fine3(const T* __restrict__ E, const T* __restrict__ KE,
                                               const uint8_t* __restrict__ nm, int nx, int ny, int nz,
-                                              int64_t N, const T* __restrict__ x,
+                                              int64_t N64, const T* __restrict__ x,
                                               const T* __restrict__ b, T* __restrict__ y,
                                               const T* __restrict__ dinv, T omega,
                                               const int* __restrict__ done, double* partials) {
     if (done && *done) return;
-    const int64_t node = xcd_block() * WG + threadIdx.x;
+    const uint32_t N = (uint32_t)N64;
+    const uint32_t node = (uint32_t)xcd_block() * WG + threadIdx.x;
     const bool live = node < N;
-    const int NX = nx + 1, NY = ny + 1, NZ = nz + 1;
-    const int64_t nd = live ? node : 0;
-    const int i = (int)(nd % NX);
-    const int j = (int)((nd / NX) % NY);
-    const int k = (int)(nd / ((int64_t)NX * NY));
+    const uint32_t NX = nx + 1, NY = ny + 1, NZ = nz + 1;
+    const uint32_t nd = live ? node : 0u;
+    const uint32_t i = nd % NX, tq = nd / NX, j = tq % NY, k = tq / NY;
+    const uint32_t cx[3] = {i ? i - 1 : 0u, i, min(i + 1, NX - 1)};
+    const uint32_t cy[3] = {j ? j - 1 : 0u, j, min(j + 1, NY - 1)};
+    const uint32_t cz[3] = {k ? k - 1 : 0u, k, min(k + 1, NZ - 1)};
+    const auto xr = buf_rsrc(x, (int64_t)N * 3 * sizeof(T));
     T v[3][9][3];  // [plane dz+1][(dy+1)*3 + dx+1][component]
 #pragma unroll
     for (int dz = 0; dz < 3; ++dz)
 #pragma unroll
-        for (int dy = 0; dy < 3; ++dy)
+        for (int dy = 0; dy < 3; ++dy) {
+            const uint32_t row = (cz[dz] * NY + cy[dy]) * NX;
 #pragma unroll
             for (int dx = 0; dx < 3; ++dx) {
-                const int ii = i + dx - 1, jj = j + dy - 1, kk = k + dz - 1;
-                const bool ok = live && ii >= 0 && ii < NX && jj >= 0 && jj < NY && kk >= 0 && kk < NZ;
-                const int64_t id = ((int64_t)kk * NY + jj) * NX + ii;
-                T a0 = 0, a1 = 0, a2 = 0;
-                if (ok) {
-                    a0 = x[3 * id];
-                    a1 = x[3 * id + 1];
-                    a2 = x[3 * id + 2];
-                    if (MASK_IN) {
-                        const uint8_t m = nm[id];
-                        if (m & 1) a0 = 0;
-                        if (m & 2) a1 = 0;
-                        if (m & 4) a2 = 0;
-                    }
+                const uint32_t id = row + cx[dx];
+                T a[3];
+                bld3(xr, id * (3u * sizeof(T)), a);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    if (MASK_IN) a[c] = ((nm[id] >> c) & 1u) ? T(0) : a[c];
+                    v[dz][dy * 3 + dx][c] = a[c];
                 }
-                v[dz][dy * 3 + dx][0] = a0;
-                v[dz][dy * 3 + dx][1] = a1;
-                v[dz][dy * 3 + dx][2] = a2;
             }
+        }
+    const auto er = buf_rsrc(E, (int64_t)nx * ny * nz * sizeof(T));
     T acc[3] = {0, 0, 0};
 #pragma unroll
     for (int ez = 0; ez < 2; ++ez)
@@ -134,9 +133,14 @@ __global__ __launch_bounds__(WG) void k_fine3(const T* __restrict__ E, const T* 
         for (int ey = 0; ey < 2; ++ey)
 #pragma unroll
             for (int ex = 0; ex < 2; ++ex) {
-                const int gx = i - 1 + ex, gy = j - 1 + ey, gz = k - 1 + ez;
-                const bool ok = live && gx >= 0 && gx < nx && gy >= 0 && gy < ny && gz >= 0 && gz < nz;
-                const T Ee = ok ? E[((int64_t)gz * ny + gy) * nx + gx] : T(0);
+                // element with lower corner (i-1+ex, j-1+ey, k-1+ez)
+                const bool in = (ex || i) && (ex == 0 || i < (uint32_t)nx) && (ey || j) &&
+                                (ey == 0 || j < (uint32_t)ny) && (ez || k) && (ez == 0 || k < (uint32_t)nz);
+                const uint32_t gx = min(i + ex, (uint32_t)nx) - (i + ex > 0 ? 1u : 0u);
+                const uint32_t gy = min(j + ey, (uint32_t)ny) - (j + ey > 0 ? 1u : 0u);
+                const uint32_t gz = min(k + ez, (uint32_t)nz) - (k + ez > 0 ? 1u : 0u);
+                const T Ee = in ? bld<T>(er, ((gz * (uint32_t)ny + gy) * (uint32_t)nx + gx) * (uint32_t)sizeof(T))
+                                : T(0);
                 const int a = loc3(1 - ex, 1 - ey, 1 - ez);
                 T t[3] = {0, 0, 0};
 #pragma unroll
@@ -158,7 +162,7 @@ __global__ __launch_bounds__(WG) void k_fine3(const T* __restrict__ E, const T* 
             }
     double dots[2] = {0.0, 0.0};
     if (live) {
-        const T xo[3] = {x[3 * node], x[3 * node + 1], x[3 * node + 2]};
+        const T xo[3] = {x[3u * node], x[3u * node + 1], x[3u * node + 2]};
         finish_node<T, 3, OP>(node, N, acc, xo, nm[node], b, y, dinv, omega, dots);
     }
     if (OP == OP_QDOT) block_reduce_store<2>(dots, partials);

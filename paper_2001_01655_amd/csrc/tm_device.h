@@ -28,6 +28,35 @@ __device__ __forceinline__ void block_reduce_store(double (&v)[NV], double* part
     }
 }
 
+// ------------------------------------------------------------ buffer loads
+// Raw buffer loads take a 32-bit byte offset from a descriptor held in SGPRs,
+// which avoids per-load 64-bit address arithmetic in the gather kernels.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* p, int64_t bytes) {
+    const int nrec = (int)(bytes < 0x7fffffff ? bytes : 0x7fffffff);
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, nrec, 0x00020000);
+}
+template <typename T>
+__device__ __forceinline__ T bld(__amdgpu_buffer_rsrc_t r, uint32_t off);
+template <>
+__device__ __forceinline__ float bld<float>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+template <>
+__device__ __forceinline__ double bld<double>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+// three consecutive values starting at byte offset off
+__device__ __forceinline__ void bld3(__amdgpu_buffer_rsrc_t r, uint32_t off, float (&v)[3]) {
+    v[0] = bld<float>(r, off);
+    v[1] = bld<float>(r, off + 4);
+    v[2] = bld<float>(r, off + 8);
+}
+__device__ __forceinline__ void bld3(__amdgpu_buffer_rsrc_t r, uint32_t off, double (&v)[3]) {
+    v[0] = bld<double>(r, off);
+    v[1] = bld<double>(r, off + 8);
+    v[2] = bld<double>(r, off + 16);
+}
+
 // ------------------------------------------------------------ grid sums
 // Sum over the whole block (fixed wave-shuffle tree, then wave order); every
 // thread gets the result.
