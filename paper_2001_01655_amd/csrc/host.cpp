@@ -530,6 +530,16 @@ static tm_solve_state* new_state(tm_hierarchy* h, int nrhs) {
     return st;
 }
 
+static void delete_state(tm_solve_state* st);
+
+void delete_cached_state(tm_hierarchy* h) {
+    if (h && h->cached) {
+        (void)hipDeviceSynchronize();
+        delete_state(h->cached);
+        h->cached = nullptr;
+    }
+}
+
 static void delete_state(tm_solve_state* st) {
     if (!st) return;
     free_list(st->allocs);
@@ -850,6 +860,7 @@ static void destroy_impl(tm_hierarchy* h) {
             (void)hipEventDestroy(pr.second);
         }
     tmi::free_list(h->allocs);
+    tmi::free_list(h->sa_allocs);
     delete h;
 }
 

@@ -123,6 +123,8 @@ struct tm_hierarchy {
     double* elem_b = nullptr;      // (pong)
     size_t bytes = 0;
     std::vector<void*> allocs;
+    std::vector<void*> sa_allocs;  // aggregation levels (rebuilt by every numeric setup)
+    size_t sa_bytes = 0;
     // kernel timing hooks
     bool timing[2] = {false, false};
     std::vector<std::pair<hipEvent_t, hipEvent_t>> tev[2];
@@ -155,6 +157,8 @@ struct Lane {
     double* part = nullptr;        // reduction partials
     Vcyc v32, v64;
 };
+
+void delete_cached_state(tm_hierarchy* h);
 
 // ----------------------------------------------------------------- launchers
 // fine level (kernels_fine.hip)
