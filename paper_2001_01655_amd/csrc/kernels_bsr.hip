@@ -1,24 +1,28 @@
 // Operators of smoothed-aggregation levels, stored as block sparse rows
-// (one bs x bs block per pair of aggregates; int32 block columns).  These
-// levels are small (the coarse part of the hybrid hierarchy of Sec. 4.3 /
-// 4.4), so one thread handles one block row: it reads the row's blocks and the
-// needed x blocks and writes all bs outputs, which lets the smoother apply the
-// block inverse of the point-block Jacobi step directly.
+// (one bs x bs block per pair of aggregates; int32 block columns), and the
+// explicit prolongator P / restriction P^T of the aggregation steps.  Rows of
+// aggregation operators and of P^T are long (tens to hundreds of blocks), so
+// one wave works on one block row; P rows are short and get one thread each.
+// The row owner writes all bs outputs, so the smoother applies the block
+// inverse of the point-block Jacobi step directly.
 #include "tm_device.h"
 
 namespace tmi {
 
+// One 64-lane wave per block row: lanes split the row's blocks, then a fixed
+// shuffle tree sums the bs partial outputs (deterministic), lane 0 finishes.
 template <typename T, int BS, int OP>
-__global__ __launch_bounds__(WG) void k_bsr_op(const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
-                                               const T* __restrict__ v, int64_t nbr, const T* __restrict__ x,
-                                               const T* __restrict__ b, T* __restrict__ y,
-                                               const T* __restrict__ dinv, T omega,
-                                               const int* __restrict__ done) {
+__global__ __launch_bounds__(WG) void k_bsr_op_wave(const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                                                    const T* __restrict__ v, int64_t nbr, const T* __restrict__ x,
+                                                    const T* __restrict__ b, T* __restrict__ y,
+                                                    const T* __restrict__ dinv, T omega,
+                                                    const int* __restrict__ done) {
     if (done && *done) return;
-    const int64_t row = xcd_block() * WG + threadIdx.x;
+    const int64_t row = xcd_block() * (WG / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
     if (row >= nbr) return;
     T acc[BS] = {};
-    for (int32_t q = rp[row]; q < rp[row + 1]; ++q) {
+    for (int32_t q = rp[row] + lane; q < rp[row + 1]; q += 64) {
         const int64_t c0 = (int64_t)ci[q] * BS;
         T xv[BS];
 #pragma unroll
@@ -29,6 +33,11 @@ __global__ __launch_bounds__(WG) void k_bsr_op(const int32_t* __restrict__ rp, c
 #pragma unroll
             for (int c = 0; c < BS; ++c) acc[r] += blk[r * BS + c] * xv[c];
     }
+#pragma unroll
+    for (int r = 0; r < BS; ++r)
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) acc[r] += __shfl_down(acc[r], o, 64);
+    if (lane != 0) return;
     T xo[BS];
 #pragma unroll
     for (int c = 0; c < BS; ++c) xo[c] = x[(int64_t)BS * row + c];
@@ -52,17 +61,17 @@ const float* dinv_of<float>(const Level& L) { return L.dinv32; }
 template <typename T, int BS>
 static void bsr_op_bs(const Level& L, int op, const T* x, const T* b, T* y, T omega, const int* done,
                       hipStream_t s) {
-    const dim3 g(grid_for(L.A.nbr)), blk(WG);
+    const dim3 g(grid_for(L.A.nbr, WG / 64)), blk(WG);
     const T* v = vals_of<T>(L.A);
     const T* dv = dinv_of<T>(L);
     if (op == OP_APPLY)
-        hipLaunchKernelGGL((k_bsr_op<T, BS, OP_APPLY>), g, blk, 0, s, L.A.rp, L.A.ci, v, L.A.nbr, x, b, y, dv,
+        hipLaunchKernelGGL((k_bsr_op_wave<T, BS, OP_APPLY>), g, blk, 0, s, L.A.rp, L.A.ci, v, L.A.nbr, x, b, y, dv,
                            omega, done);
     else if (op == OP_RESID)
-        hipLaunchKernelGGL((k_bsr_op<T, BS, OP_RESID>), g, blk, 0, s, L.A.rp, L.A.ci, v, L.A.nbr, x, b, y, dv,
+        hipLaunchKernelGGL((k_bsr_op_wave<T, BS, OP_RESID>), g, blk, 0, s, L.A.rp, L.A.ci, v, L.A.nbr, x, b, y, dv,
                            omega, done);
     else
-        hipLaunchKernelGGL((k_bsr_op<T, BS, OP_SMOOTH>), g, blk, 0, s, L.A.rp, L.A.ci, v, L.A.nbr, x, b, y, dv,
+        hipLaunchKernelGGL((k_bsr_op_wave<T, BS, OP_SMOOTH>), g, blk, 0, s, L.A.rp, L.A.ci, v, L.A.nbr, x, b, y, dv,
                            omega, done);
 }
 
@@ -119,11 +128,60 @@ __global__ __launch_bounds__(WG) void k_bsr_mv(const int32_t* __restrict__ rp, c
     }
 }
 
+template <typename T, int BR, int BC, bool FIRST>
+__global__ __launch_bounds__(WG) void k_bsr_mv_wave(const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                                                    const T* __restrict__ v, int64_t nbr, const T* __restrict__ x,
+                                                    T* __restrict__ y, T* __restrict__ xf,
+                                                    const T* __restrict__ dinv, T omega,
+                                                    const int* __restrict__ done) {
+    if (done && *done) return;
+    const int64_t row = xcd_block() * (WG / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (row >= nbr) return;
+    T acc[BR] = {};
+    for (int32_t q = rp[row] + lane; q < rp[row + 1]; q += 64) {
+        const int64_t c0 = (int64_t)ci[q] * BC;
+        const T* blk = v + (int64_t)q * BR * BC;
+#pragma unroll
+        for (int c = 0; c < BC; ++c) {
+            const T xv = x[c0 + c];
+#pragma unroll
+            for (int r = 0; r < BR; ++r) acc[r] += blk[r * BC + c] * xv;
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < BR; ++r)
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) acc[r] += __shfl_down(acc[r], o, 64);
+    if (lane != 0) return;
+#pragma unroll
+    for (int r = 0; r < BR; ++r) y[(int64_t)BR * row + r] = acc[r];
+    if (FIRST) {
+#pragma unroll
+        for (int r = 0; r < BR; ++r) {
+            T t = 0;
+#pragma unroll
+            for (int c = 0; c < BR; ++c) t += dinv[(int64_t)(r * BR + c) * nbr + row] * acc[c];
+            xf[(int64_t)BR * row + r] = omega * t;
+        }
+    }
+}
+
 template <typename T, int BR, int BC>
 static void bsr_mv_shape(const BSR& B, const T* x, T* y, bool add, T* xfirst, const T* dinv, T omega,
                          const int* done, hipStream_t s) {
     const dim3 g(grid_for(B.nbr)), blk(WG);
     const T* v = vals_of<T>(B);
+    if (!add && B.nnzb >= 8 * B.nbr) {      // long rows (restriction): one wave per row
+        const dim3 gw(grid_for(B.nbr, WG / 64));
+        if (xfirst)
+            hipLaunchKernelGGL((k_bsr_mv_wave<T, BR, BC, true>), gw, blk, 0, s, B.rp, B.ci, v, B.nbr, x, y, xfirst,
+                               dinv, omega, done);
+        else
+            hipLaunchKernelGGL((k_bsr_mv_wave<T, BR, BC, false>), gw, blk, 0, s, B.rp, B.ci, v, B.nbr, x, y, xfirst,
+                               dinv, omega, done);
+        return;
+    }
     if (add)
         hipLaunchKernelGGL((k_bsr_mv<T, BR, BC, true, false>), g, blk, 0, s, B.rp, B.ci, v, B.nbr, x, y,
                            xfirst, dinv, omega, done);
