@@ -125,10 +125,13 @@ tm_status tm_solve(tm_hierarchy* h, int32_t n_rhs, const double* f_dev, double r
  * begin:   copies f, sets up the start vector on `stream` and returns a state
  *          bound to (h, stream, u_dev); u_dev must stay valid until end.
  * advance: enqueues up to k further iterations without waiting.
- * poll:    non-blocking; *done = 1 once every right-hand side has stopped.
+ * poll:    non-blocking; *done = 1 once every right-hand side has stopped, 0 when
+ *          the enqueued iterations have finished without that, -1 while they
+ *          are still running.
  * batch_advance: advance for n states at once (each on its own stream, so the
  *          work of different requests overlaps on the device).
- * end:     waits, writes the outputs of tm_solve and frees the state. */
+ * end:     waits, writes the outputs of tm_solve and releases the state (its
+ *          device buffers stay with the hierarchy for the next begin). */
 tm_status tm_solve_begin(tm_hierarchy* h, int32_t n_rhs, const double* f_dev, double rtol,
                          int32_t use_u0, double* u_dev, void* stream, tm_solve_state** st);
 tm_status tm_solve_advance(tm_solve_state* st, int32_t k_iters);

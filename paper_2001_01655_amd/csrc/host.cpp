@@ -532,12 +532,16 @@ static tm_solve_state* new_state(tm_hierarchy* h, int nrhs) {
 
 static void delete_state(tm_solve_state* st);
 
+// drop the states whose V-cycle work vectors follow the current level list
 void delete_cached_state(tm_hierarchy* h) {
-    if (h && h->cached) {
-        (void)hipDeviceSynchronize();
+    if (!h) return;
+    if (h->cached || !h->pool.empty()) (void)hipDeviceSynchronize();
+    if (h->cached) {
         delete_state(h->cached);
         h->cached = nullptr;
     }
+    for (tm_solve_state* st : h->pool) delete_state(st);
+    h->pool.clear();
 }
 
 static void delete_state(tm_solve_state* st) {
@@ -853,7 +857,7 @@ tm_status tm_plan_bytes(const tm_mesh* mesh, const tm_options* opts, int32_t n_r
 
 static void destroy_impl(tm_hierarchy* h) {
     if (!h) return;
-    if (h->cached) tmi::delete_state(h->cached);
+    tmi::delete_cached_state(h);
     for (int c = 0; c < 2; ++c)
         for (auto& pr : h->tev[c]) {
             (void)hipEventDestroy(pr.first);
@@ -968,7 +972,13 @@ static tm_status begin_impl(tm_hierarchy* h, int32_t n_rhs, const double* f_dev,
             }
             st = h->cached;
         } else {
-            st = new_state(h, n_rhs);
+            for (size_t i = 0; i < h->pool.size(); ++i)
+                if (h->pool[i]->nrhs == n_rhs) {
+                    st = h->pool[i];
+                    h->pool.erase(h->pool.begin() + i);
+                    break;
+                }
+            if (!st) st = new_state(h, n_rhs);
         }
         st->s = S(stream);
         st->rtol = rtol;
@@ -977,7 +987,13 @@ static tm_status begin_impl(tm_hierarchy* h, int32_t n_rhs, const double* f_dev,
         st->ended = false;
         st->pending = false;
         try {
+            if (st->ev) TM_HIP(hipEventSynchronize(st->ev));   // a reused state may still be draining
             enqueue_begin(st, f_dev, use_u0);
+            // the host mirror must describe this solve before the first poll
+            std::memset(st->sc_host, 0, sizeof(KScal) * st->nrhs);
+            TM_HIP(hipMemcpyAsync(st->sc_host, st->sc, sizeof(KScal) * st->nrhs, hipMemcpyDeviceToHost, st->s));
+            TM_HIP(hipEventRecord(st->ev, st->s));
+            st->pending = true;
         } catch (...) {
             if (!cached) delete_state(st);
             throw;
@@ -1040,7 +1056,7 @@ tm_status tm_solve_poll(tm_solve_state* st, int32_t* done) {
     return guarded([&] {
         if (!st || st->ended) fail(TM_ERR_STATE, "state is NULL or ended");
         if (!done) fail(TM_ERR_ARG, "done is NULL");
-        *done = 0;
+        *done = -1;
         if (st->pending) {
             const hipError_t q = hipEventQuery(st->ev);
             if (q == hipErrorNotReady) return;
@@ -1058,7 +1074,12 @@ tm_status tm_solve_end(tm_solve_state* st, int32_t* iters, double* compliance, d
     }
     tm_status res = TM_OK;
     const tm_status g = guarded([&] { res = finish_state(st, iters, compliance, relres); });
-    if (!st->owned_by_h) delete_state(st);
+    if (!st->owned_by_h) {
+        if (g == TM_OK)
+            st->h->pool.push_back(st);       // kept for the next solve on this hierarchy
+        else
+            delete_state(st);
+    }
     return g != TM_OK ? g : res;
 }
 

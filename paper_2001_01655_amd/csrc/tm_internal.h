@@ -128,8 +128,9 @@ struct tm_hierarchy {
     // kernel timing hooks
     bool timing[2] = {false, false};
     std::vector<std::pair<hipEvent_t, hipEvent_t>> tev[2];
-    // default solve state (tm_solve)
+    // default solve state (tm_solve) and ended states kept for reuse
     tm_solve_state* cached = nullptr;
+    std::vector<tm_solve_state*> pool;
 };
 
 struct tm_solve_state {

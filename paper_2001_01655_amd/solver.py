@@ -204,10 +204,12 @@ class SolveState:
     def advance(self, k: int):
         check(LIB.tm_solve_advance(self._st, k), "tm_solve_advance")
 
-    def poll(self) -> bool:
+    def poll(self) -> int:
+        """1: every load case stopped; 0: enqueued iterations done, not stopped;
+        -1: iterations still running."""
         d = C.c_int32()
         check(LIB.tm_solve_poll(self._st, C.byref(d)), "tm_solve_poll")
-        return bool(d.value)
+        return int(d.value)
 
     def end(self) -> SolveResult:
         if self.result is None:

@@ -264,6 +264,18 @@ def density_update(rho: np.ndarray, nel, seed: int, step: int, amp: float = 0.05
     return np.clip(rho + amp * g.ravel(), VOID, 1.0)
 
 
+def design_sequence(rho0: np.ndarray, nel, seed: int, amp: float = 0.05):
+    """Callable t -> densities of design t: rho0, then successive seeded updates."""
+    cache = [np.asarray(rho0, dtype=np.float64)]
+
+    def densities(t: int) -> np.ndarray:
+        while len(cache) <= t:
+            cache.append(density_update(cache[-1], nel, seed=seed, step=len(cache), amp=amp))
+        return cache[t]
+
+    return densities
+
+
 def poisson_arrivals(n: int, rate_per_s: float, seed: int = 5) -> np.ndarray:
     """Arrival times (s) of n requests of a Poisson process."""
     rng = np.random.default_rng([seed, 999])
