@@ -3,14 +3,19 @@
 One step = one full solve of K(rho) u = f (f resident in HBM -> u resident),
 setup excluded, on the 3D cantilever 192x96x96 Hex8 (5,447,811 dofs) with a
 6-level geometric hierarchy and an FP32 V-cycle inside FP64 flexible CG.  The
-FP64-everywhere PCG on the same hierarchy is timed beside it, and the oracle
-(CPU, FP64) on a bounded sample of the same recipe.
+FP64-everywhere PCG on the same problem is timed beside it, and the oracle
+(CPU, FP64, one thread) on a bounded sample of the same recipe.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+
+After the timed steps one more solve runs with HIP events around every launch
+of three kernel classes (outer FP64 operator, V-cycle fine operator, first
+coarse level operator); their mean durations give the roofline fractions.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import platform
@@ -21,16 +26,21 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 WORKLOADS = {
-    # name: (synth config, levels, label)
-    "cantilever3d": ("cantilever3d", 6, "3D cantilever 192x96x96 Hex8, 5,447,811 dofs, 6-level GMG "
-                                          "(coarsest 336 dofs), block Jacobi w=0.5 1/1, rtol 1e-8"),
-    "cantilever2d": ("cantilever2d", 7, "2D cantilever 1024x512 Q4, 1,051,650 dofs, 7-level GMG "
-                                          "(coarsest 306 dofs), block Jacobi w=0.5 1/1, rtol 1e-8"),
+    "cantilever3d": dict(cfg="cantilever3d", opts=dict(n_levels=6),
+                         label="3D cantilever 192x96x96 Hex8, 5,447,811 dofs, 6-level GMG (coarsest 336 dofs), "
+                               "block Jacobi w=0.5 1/1, rtol 1e-8"),
+    "cantilever2d": dict(cfg="cantilever2d", opts=dict(n_levels=7),
+                         label="2D cantilever 1024x512 Q4, 1,051,650 dofs, 7-level GMG (coarsest 306 dofs), "
+                               "block Jacobi w=0.5 1/1, rtol 1e-8"),
+    "bridge3d": dict(cfg="bridge3d", opts=dict(n_geometric=3, max_coarse=1000),
+                     label="3D bridge 256x128x128 Hex8, 12,830,211 dofs, 3 GMG levels + smoothed aggregation "
+                           "to <1000 dofs, block Jacobi w=0.5 1/1, rtol 1e-8"),
 }
 
-HBM_PEAK_GBS = 8000.0
-FP32_PEAK_TFLOPS = 157.3
-FP64_PEAK_TFLOPS = 78.6
+# MI355X published peaks (dense): HBM3E 8 TB/s; vector FP64 78.6 TFLOP/s; vector
+# FP32 157.3 TFLOP/s (reached only with packed FP32, which this build does not use)
+PEAK = {"hbm_GBs": 8000.0, "fp64_TFs": 78.6, "fp32_TFs": 157.3}
+KERNEL_SOURCES = {0: "kernels_fine.hip", 1: "kernels_fine.hip", 2: "kernels_coarse.hip"}
 
 
 def parse():
@@ -41,7 +51,15 @@ def parse():
     ap.add_argument("--workload", default="cantilever3d", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-profile", action="store_true", help="skip the event-timed solve")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="copy 256 MiB device-to-device first (counter calibration under rocprofv3 --pmc)")
     return ap.parse_args()
+
+
+def src_hash(name: str) -> str:
+    p = os.path.join(ROOT, "paper_2001_01655_amd", "csrc", name)
+    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
 
 
 def timed_solves(H, f, steps, warmup, rtol):
@@ -57,23 +75,73 @@ def timed_solves(H, f, steps, warmup, rtol):
     return time.perf_counter() - t0, res
 
 
+def algorithmic(cls, H, p):
+    """(flops, bytes) one launch of the class must do: the operator's own
+    arithmetic and each operand read or written once."""
+    dim, n_el, n_nodes = p.dim, p.n_el, p.n_nodes
+    nd = dim * 2 ** dim
+    if cls in (0, 1):
+        flops = 2.0 * nd * (nd + 1) * n_el                   # KE rows x U_e, then E_e scaling
+        w = 8 if cls == 0 else 4
+        # x, b (r), y per node, modulus per element, support mask per node;
+        # the smoothing sweep also reads the block inverse (half of class-1 launches)
+        byts = 3 * dim * w * n_nodes + w * n_el + n_nodes + (0 if cls == 0 else 0.5 * dim * dim * w * n_nodes)
+        return flops, byts
+    info = H.level_info(1)
+    n1 = info["n_rows"] // dim
+    nst = 27 if dim == 3 else 9
+    flops = 2.0 * nst * dim * dim * n1
+    byts = (nst * dim * dim + 3 * dim + 0.5 * dim * dim) * 4 * n1
+    return flops, byts
+
+
+def roofline_entry(cls, launches, total_ms, H, p):
+    avg_s = total_ms / 1e3 / max(launches, 1)
+    flops, byts = algorithmic(cls, H, p)
+    if cls == 2:
+        ach = byts / avg_s / 1e9
+        e = {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK["hbm_GBs"], "unit": "GB/s",
+             "frac": round(ach / PEAK["hbm_GBs"], 4)}
+    else:
+        peak = PEAK["fp64_TFs"] if cls == 0 else PEAK["fp32_TFs"]
+        ach = flops / avg_s / 1e12
+        e = {"bound": "alu", "achieved": round(ach, 2), "peak": peak, "unit": "TFLOP/s",
+             "frac": round(ach / peak, 4)}
+    e.update({"kernel": {0: "fine operator FP64 (q = K~p, outer loop)",
+                         1: "fine operator FP32 (V-cycle residual / smoothing)",
+                         2: "level-1 stencil operator FP32 (V-cycle)"}[cls],
+              "launches": launches, "avg_us": round(avg_s * 1e6, 2),
+              "algorithmic_flops_per_launch": flops, "algorithmic_bytes_per_launch": byts,
+              "traffic": None})
+    # HBM bytes per launch from committed rocprofv3 counter summaries, valid
+    # only while the kernel source is the one that was profiled
+    tp = os.path.join(ROOT, "profiles", f"traffic_class{cls}.json")
+    if os.path.exists(tp):
+        t = json.load(open(tp))
+        if t.get("source_sha") == src_hash(KERNEL_SOURCES[cls]):
+            e["traffic"] = t.get("bytes_per_launch")
+            e["traffic_ratio_to_algorithmic"] = round(t["bytes_per_launch"] / byts, 3)
+    return e
+
+
 def cpu_baseline(cfg_name):
-    """Oracle (CPU, FP64, single thread) on a bounded sample: the same recipe at
-    1/27 of the volume (64x32x32 for the 3D cantilever, 340x170 for 2D),
-    solve to rtol 1e-8 timed, setup excluded."""
-    import numpy as np
+    """Oracle (CPU, FP64, single thread) on a bounded sample of the same
+    recipe; solve to rtol 1e-8 timed, setup excluded."""
     from threadpoolctl import threadpool_limits
 
     import synth
     from oracle import fem, mg
     if cfg_name == "cantilever3d":
-        p = synth.cantilever_3d(nel=(64, 32, 32))
+        p = synth.cantilever_3d(nel=(128, 64, 64))
         L = 5
-        sample = "3D cantilever recipe at 64x32x32 (215,475 dofs), 5 levels, one solve to rtol 1e-8"
+        sample = ("3D cantilever recipe at 128x64x64 (1,623,075 dofs, 30% of the volume), 5 levels, "
+                  "one solve to rtol 1e-8")
+    elif cfg_name == "cantilever2d":
+        p = synth.cantilever_2d(nel=(512, 256))
+        L = 6
+        sample = "2D cantilever recipe at 512x256 (263,682 dofs), 6 levels, one solve to rtol 1e-8"
     else:
-        p = synth.cantilever_2d(nel=(352, 176))
-        L = 5
-        sample = "2D cantilever recipe at 352x176 (124,962 dofs), 5 levels, one solve to rtol 1e-8"
+        return None
     with threadpool_limits(limits=1):
         KE = fem.element_stiffness(p.dim, p.nu)
         E = fem.simp(p.rho, p.p, p.E0, p.Emin)
@@ -83,33 +151,36 @@ def cpu_baseline(cfg_name):
         dt = time.perf_counter() - t0
     return {"value": round(p.n_dof / dt / 1e6, 4), "unit": "MDoF/s", "cores": 1, "kind": "oracle",
             "sample": sample, "seconds": round(dt, 3), "iters": r.iters,
-            "host": platform.processor() or platform.machine()}
+            "host": platform.processor() or platform.machine(), "host_cpus": os.cpu_count()}
 
 
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU; multi-GPU runs are not part of "
-                                   "this build (the sharded design is described in DESIGN.md)",
-                          "n_gpus": args.gpus}))
+        print(json.dumps({"error": "this benchmark runs on one GPU: the multi-GPU decomposition is "
+                                   "described in DESIGN.md but not part of this build", "n_gpus": args.gpus}))
         sys.exit(2)
-    import numpy as np
     import torch
 
     import synth
     from paper_2001_01655_amd import Hierarchy
 
-    cfg, L, label = WORKLOADS[args.workload]
-    p = synth.get(cfg)
+    wl = WORKLOADS[args.workload]
+    p = synth.get(wl["cfg"])
+    if args.calibrate_copy:
+        a = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     f = torch.tensor(p.loads[0], device="cuda")
     rtol = 1e-8
-    out = {}
 
     def build(vfp, outer):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        H = Hierarchy(p.nel, p.rho, p.fixed, p=p.p, E0=p.E0, Emin=p.Emin, nu=p.nu, n_levels=L,
-                      omega=0.5, nu_pre=1, nu_post=1, vcycle_fp=vfp, outer=outer)
+        H = Hierarchy(p.nel, p.rho, p.fixed, p=p.p, E0=p.E0, Emin=p.Emin, nu=p.nu, omega=0.5, nu_pre=1,
+                      nu_post=1, vcycle_fp=vfp, outer=outer, **wl["opts"])
         torch.cuda.synchronize()
         return H, time.perf_counter() - t0
 
@@ -117,17 +188,8 @@ def main():
     dt, res = timed_solves(H, f, args.steps, args.warmup, rtol)
     ms = dt / args.steps * 1e3
     value = p.n_dof * args.steps / dt / 1e6
-    out["mixed"] = dict(iters=res.iters[0], relres=res.relres[0], compliance=res.compliance[0],
-                        setup_ms=round(t_setup * 1e3, 2))
-    u_mixed = res.u.clone()
-    if not args.no_fp64:
-        H64, t64s = build(64, 1)
-        dt64, r64 = timed_solves(H64, f, max(1, args.steps // 2), 1, rtol)
-        v64 = p.n_dof * max(1, args.steps // 2) / dt64 / 1e6
-        du = float((r64.u - u_mixed).norm() / r64.u.norm())
-        out["fp64"] = dict(value=round(v64, 2), iters=r64.iters[0], relres=r64.relres[0],
-                           setup_ms=round(t64s * 1e3, 2), rel_diff_u_vs_mixed=du)
-        H64.close()
+    detail = {"mixed": dict(iters=res.iters[0], relres=res.relres[0], compliance=res.compliance[0],
+                            setup_ms=round(t_setup * 1e3, 2), levels=H.num_levels())}
     line = {
         "metric": "MDoF/s to rtol 1e-8 (FP32 V-cycle vs FP64 PCG)",
         "value": round(value, 2),
@@ -139,17 +201,44 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64",
+        "dtype": "f32 V-cycle + f64 CG",
         "data": "synthetic",
-        "config": {"workload": label, "n_dof": p.n_dof, "outer": "FCG(1) FP64",
-                   "vcycle": "FP32", "iterations": out["mixed"]["iters"]},
-        "detail": out,
+        "config": {"workload": wl["label"], "n_dof": p.n_dof, "iterations": res.iters[0]},
     }
-    if "fp64" in out:
-        line["speedup_vs_fp64_pcg"] = round(value / out["fp64"]["value"], 3)
-    if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(cfg)
+    if not args.no_profile:
+        classes = [0, 1, 2]
+        for c in classes:
+            H.kernel_timing(c, True)
+        H.solve(f, rtol=rtol)
+        torch.cuda.synchronize()
+        ents = {}
+        for c in classes:
+            n, tot = H.kernel_timing_read(c)
+            H.kernel_timing(c, False)
+            if n:
+                ents[c] = roofline_entry(c, n, tot, H, p)
+                ents[c]["share_of_step_time"] = round(tot / ms, 4)
+        if ents:
+            dom = max(ents, key=lambda c: ents[c]["share_of_step_time"])
+            line["roofline"] = ents[dom]
+            line["roofline_other_kernels"] = [ents[c] for c in ents if c != dom]
+    u_mixed = res.u.clone()
     H.close()
+    if not args.no_fp64:
+        H64, t64s = build(64, 1)
+        k64 = max(1, args.steps // 2)
+        dt64, r64 = timed_solves(H64, f, k64, 1, rtol)
+        v64 = p.n_dof * k64 / dt64 / 1e6
+        du = float((r64.u - u_mixed).norm() / r64.u.norm())
+        detail["fp64_pcg"] = dict(value=round(v64, 2), unit="MDoF/s", iters=r64.iters[0], relres=r64.relres[0],
+                                  setup_ms=round(t64s * 1e3, 2), rel_diff_u_vs_mixed=du)
+        line["speedup_vs_fp64_pcg"] = round(value / v64, 3)
+        H64.close()
+    line["detail"] = detail
+    if not args.no_cpu_baseline:
+        cb = cpu_baseline(wl["cfg"])
+        if cb:
+            line["cpu_baseline"] = cb
     print(json.dumps(line), flush=True)
 
 

@@ -169,10 +169,13 @@ tm_status tm_export_connectivity(const tm_mesh* mesh, int32_t* conn);
 /* Device bytes held by the hierarchy (not counting solve states). */
 tm_status tm_hierarchy_bytes(const tm_hierarchy* h, size_t* bytes);
 
-/* Kernel timing for roofline reporting: when enabled, every launch of the fine
- * operator apply (class 0) or of the coarse stencil operator (class 1) inside
- * solves of `h` is bracketed by HIP events on its stream; read returns the
- * launch count and the summed event time in milliseconds, then resets. */
+/* Kernel timing for roofline reporting: when enabled, every launch of a kernel
+ * class inside solves of `h` is bracketed by HIP events on its own stream:
+ * class 0 = the outer FP64 operator q = K~p, class 1 = the fine-level operator
+ * of the V-cycle (residual / smoothing sweeps), class 2 = the operator of the
+ * first coarse level.  read returns the launch count and the summed event time
+ * in milliseconds, then resets.  Timing adds event records between launches;
+ * it is meant for a separate, profiled solve. */
 tm_status tm_kernel_timing(tm_hierarchy* h, int32_t kernel_class, int32_t enable);
 tm_status tm_kernel_timing_read(tm_hierarchy* h, int32_t kernel_class, int64_t* launches,
                                 double* total_ms);

@@ -393,13 +393,14 @@ static void level_op(tm_hierarchy* h, int l, int op, const T* x, const T* b, T* 
     const T w = (T)h->opt.omega;
     hipEvent_t e0 = nullptr;
     if (L.kind == TM_LEVEL_FINE) {
-        timed_begin(h, 0, s, &e0);
-        launch_fine_op<T>(h, op, false, x, b, y, w, done, nullptr, s);
-        timed_end(h, 0, s, e0);
-    } else if (L.kind == TM_LEVEL_GEOMETRIC) {
         timed_begin(h, 1, s, &e0);
-        launch_stencil_op<T>(L, op, x, b, y, w, done, s);
+        launch_fine_op<T>(h, op, false, x, b, y, w, done, nullptr, s);
         timed_end(h, 1, s, e0);
+    } else if (L.kind == TM_LEVEL_GEOMETRIC) {
+        const int cls = l == 1 ? 2 : -1;
+        if (cls >= 0) timed_begin(h, cls, s, &e0);
+        launch_stencil_op<T>(L, op, x, b, y, w, done, s);
+        if (cls >= 0) timed_end(h, cls, s, e0);
     } else {
         launch_bsr_op<T>(L, op, x, b, y, w, done, s);
     }
@@ -858,7 +859,7 @@ tm_status tm_plan_bytes(const tm_mesh* mesh, const tm_options* opts, int32_t n_r
 static void destroy_impl(tm_hierarchy* h) {
     if (!h) return;
     tmi::delete_cached_state(h);
-    for (int c = 0; c < 2; ++c)
+    for (int c = 0; c < 3; ++c)
         for (auto& pr : h->tev[c]) {
             (void)hipEventDestroy(pr.first);
             (void)hipEventDestroy(pr.second);
@@ -1240,7 +1241,7 @@ tm_status tm_export_connectivity(const tm_mesh* mesh, int32_t* conn) {
 tm_status tm_kernel_timing(tm_hierarchy* h, int32_t kernel_class, int32_t enable) {
     return guarded([&] {
         if (!h) fail(TM_ERR_ARG, "hierarchy is NULL");
-        if (kernel_class < 0 || kernel_class > 1) fail(TM_ERR_ARG, "kernel_class must be 0 or 1");
+        if (kernel_class < 0 || kernel_class > 2) fail(TM_ERR_ARG, "kernel_class must be 0, 1 or 2");
         h->timing[kernel_class] = enable != 0;
     });
 }
@@ -1249,7 +1250,7 @@ tm_status tm_kernel_timing_read(tm_hierarchy* h, int32_t kernel_class, int64_t* 
                                 double* total_ms) {
     return guarded([&] {
         if (!h) fail(TM_ERR_ARG, "hierarchy is NULL");
-        if (kernel_class < 0 || kernel_class > 1) fail(TM_ERR_ARG, "kernel_class must be 0 or 1");
+        if (kernel_class < 0 || kernel_class > 2) fail(TM_ERR_ARG, "kernel_class must be 0, 1 or 2");
         double tot = 0.0;
         auto& v = h->tev[kernel_class];
         for (auto& pr : v) {

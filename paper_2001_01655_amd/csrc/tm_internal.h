@@ -126,8 +126,8 @@ struct tm_hierarchy {
     std::vector<void*> sa_allocs;  // aggregation levels (rebuilt by every numeric setup)
     size_t sa_bytes = 0;
     // kernel timing hooks
-    bool timing[2] = {false, false};
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> tev[2];
+    bool timing[3] = {false, false, false};
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> tev[3];
     // default solve state (tm_solve) and ended states kept for reuse
     tm_solve_state* cached = nullptr;
     std::vector<tm_solve_state*> pool;
