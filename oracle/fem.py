@@ -192,7 +192,7 @@ def apply_matfree(nel, E: np.ndarray, KE: np.ndarray, fixed: np.ndarray,
         e = ed[s:s + chunk]
         ue = xm[e]
         ye = E[s:s + chunk, None] * (ue @ KE.T)
-        np.add.at(y, e.ravel(), ye.ravel())
+        y += np.bincount(e.ravel(), weights=ye.ravel(), minlength=y.shape[0])
     return m * y + (1.0 - m) * x
 
 

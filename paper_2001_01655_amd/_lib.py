@@ -9,6 +9,12 @@ from __future__ import annotations
 import ctypes as C
 import os
 
+# torch first: its bundled HIP runtime must be the one in the process before
+# the library is loaded, so that both resolve to a single runtime (loading the
+# library first would bring in a second copy from the system ROCm, and device
+# memory allocated by one would be unknown to the other)
+import torch  # noqa: F401
+
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libtopomg.so")
 

@@ -21,7 +21,7 @@ from dataclasses import dataclass, field
 from typing import Dict, List, Optional, Tuple
 
 import numpy as np
-from scipy.ndimage import gaussian_filter
+from scipy.ndimage import gaussian_filter, label
 
 VOID = 1e-3
 
@@ -142,13 +142,23 @@ def mbb_2d(uniform: bool = True, seed: int = 1, nel=(60, 20)) -> Problem:
                    opts=dict(n_levels=3, omega=0.6, nu_pre=2, nu_post=2, rtol=1e-8))
 
 
-def cantilever_2d(nel=(1024, 512), seed: int = 2, n_levels: int = 7) -> Problem:
+def cantilever_2d(nel=(1024, 512), seed: int = 2, n_levels: int = 7, chord: float = 0.06) -> Problem:
     """2D cantilever: left edge clamped, unit downward load at the middle of the
-    right edge.  Density: smoothed noise thresholded to {1e-3, 1}, with a solid
-    disc of radius 8 elements under the load so the load acts on material."""
+    right edge.  Density: smoothed noise thresholded at 0 to {1e-3, 1}, joined
+    to solid top and bottom chords and a solid right-edge band (each `chord` of
+    the height thick, so the load sits on material), after which every solid
+    piece not connected through element edges to the clamped edge is set to
+    void: like an optimised design, no material floats in the void."""
     nx, ny = nel
-    rho = threshold_density(smoothed_field(_zyx(nel), seed))
-    solid_ball(rho, (nx, ny / 2), 8.0)
+    solid = smoothed_field(_zyx(nel), seed) >= 0.0
+    c = max(1, int(round(chord * ny)))
+    solid[:c, :] = True
+    solid[ny - c:, :] = True
+    solid[:, nx - c:] = True
+    lab, _ = label(solid)
+    anchored = np.unique(lab[:, 0])
+    solid = np.isin(lab, anchored[anchored > 0])
+    rho = np.where(solid, 1.0, VOID)
     f = np.zeros((1, 2 * (nx + 1) * (ny + 1)))
     f[0, 2 * node_id(nel, nx, ny // 2) + 1] = -1.0
     return Problem("cantilever2d", 2, (nx, ny), rho.ravel(), clamp_x0(nel, 2), f,

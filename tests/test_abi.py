@@ -1,0 +1,95 @@
+"""The C-ABI library without a GPU: it loads, exports every function the
+header declares, validates arguments before any device work, and its host-side
+exports agree with the oracle."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2001_01655_amd as tm
+from paper_2001_01655_amd import _lib as L
+from oracle import fem, mg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "topomg.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(tm_[a-z_]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported():
+    names = _declared()
+    assert len(names) >= 25
+    lib = C.CDLL(L.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_status_strings():
+    for code in (0, 1, -1, -2, -3, -4, -5, -6):
+        assert L.LIB.tm_status_string(code).decode() not in ("", "unknown status")
+
+
+def _setup_status(nel=(8, 4), nu=0.3, Emin=1e-9, E0=1.0, dofs=(0, 1), **opts):
+    mesh = L.make_mesh(nel)
+    mat = L.make_material(3.0, E0, Emin, nu)
+    o = L.default_options(**opts)
+    arr = np.asarray(dofs, dtype=np.int64)
+    bcs = L.tm_bcs(len(arr), arr.ctypes.data_as(C.POINTER(C.c_int64)))
+    h = C.c_void_p()
+    # a non-null stand-in for the density buffer: argument checks fail before it is read
+    st = L.LIB.tm_setup(C.byref(mesh), C.byref(mat), C.c_void_p(16), C.byref(bcs), C.byref(o), None,
+                        C.byref(h))
+    return st, L.LIB.tm_last_error().decode()
+
+
+@pytest.mark.parametrize("kw,msg", [
+    (dict(nel=(7, 4), n_levels=3), "divisible"),
+    (dict(nu=0.5), "nu"),
+    (dict(Emin=2.0), "Emin"),
+    (dict(dofs=(0, 10 ** 9)), "out of range"),
+    (dict(omega=2.5), "omega"),
+    (dict(vcycle_fp=16), "vcycle_fp"),
+    (dict(smoother=2), "smoother"),
+    (dict(n_geometric=1), "n_geometric"),
+    (dict(nu_pre=0), "nu_pre"),
+])
+def test_setup_rejects_bad_arguments_before_device_work(kw, msg):
+    st, err = _setup_status(**kw)
+    assert st == L.TM_ERR_ARG
+    assert msg in err
+
+
+def test_null_arguments():
+    h = C.c_void_p()
+    assert L.LIB.tm_setup(None, None, None, None, None, None, C.byref(h)) == L.TM_ERR_ARG
+    assert L.LIB.tm_solve(None, 1, None, 1e-8, 0, None, None, None, None, None) == L.TM_ERR_ARG
+    assert L.LIB.tm_solve_end(None, None, None, None) == L.TM_ERR_STATE
+    assert L.LIB.tm_num_levels(None) == 0
+
+
+def test_plan_bytes():
+    m = L.make_mesh((64, 32, 32))
+    o = L.default_options(n_levels=4)
+    b1 = tm.tm_plan_bytes(m, o, 1)
+    b4 = tm.tm_plan_bytes(m, o, 4)
+    assert 0 < b1 < b4
+    with pytest.raises(tm.TmError):
+        tm.tm_plan_bytes(L.make_mesh((63, 32, 32)), o, 1)
+
+
+@pytest.mark.parametrize("nel", [(5, 3), (3, 4, 2)])
+def test_connectivity_export_matches_oracle(nel):
+    conn = tm.tm_export_connectivity(L.make_mesh(nel))
+    assert np.array_equal(conn, fem.connectivity(nel))
+
+
+def test_import_fails_loudly_without_library(tmp_path, monkeypatch):
+    import importlib
+    monkeypatch.setattr(L, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(ImportError):
+        L._load()

@@ -1,0 +1,71 @@
+"""The configurations at full size on the GPU, checked by properties the
+oracle evaluates at any size: true residual from the oracle's own element sum,
+compliance identity, supports, and agreement of the FP32-V-cycle and
+FP64-everywhere solutions."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import fem
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+CONFIGS = {
+    "cantilever2d": dict(n_levels=7, max_iters=20000),
+    "cantilever3d": dict(n_levels=6),
+    "bridge3d": dict(n_geometric=3, max_coarse=1000),
+}
+
+
+def _check(p, res, k=0):
+    u = res.u.cpu().numpy().reshape(-1, p.n_dof)[k]
+    f = p.loads[k].copy()
+    f[p.fixed] = 0.0
+    KE = fem.element_stiffness(p.dim, p.nu)
+    E = fem.simp(p.rho, p.p, p.E0, p.Emin)
+    r = f - fem.apply_matfree(p.nel, E, KE, p.fixed, u)
+    rel = np.linalg.norm(r) / np.linalg.norm(f)
+    print(f"  {p.name}: iters={res.iters[k]} oracle true relres={rel:.3e} (gpu {res.relres[k]:.3e})", flush=True)
+    # the GPU reports the true residual of its FP64 operator; the two element
+    # sums differ only by rounding, which is far below the tolerance
+    assert rel <= 2e-8 and res.relres[k] <= 2e-8
+    assert abs(rel - res.relres[k]) <= 0.05 * rel
+    assert abs(res.compliance[k] - f @ u) <= 1e-12 * abs(f @ u)
+    assert np.all(u[p.fixed] == 0.0)
+    return u
+
+
+@pytest.mark.parametrize("name", list(CONFIGS))
+def test_full_size_solve(name):
+    from paper_2001_01655_amd import Hierarchy
+    print(f"full size {name}", flush=True)
+    p = synth.get(name)
+    H = Hierarchy(p.nel, p.rho, p.fixed, p=p.p, E0=p.E0, Emin=p.Emin, nu=p.nu, **CONFIGS[name])
+    res = H.solve(torch.tensor(p.loads[0], device="cuda"), rtol=1e-8)
+    assert res.status == 0
+    _check(p, res)
+    if name == "bridge3d":
+        info = [H.level_info(l) for l in range(H.num_levels())]
+        lg = next(l for l, i in enumerate(info) if i["kind"] == 2) - 1
+        agg = H.export_aggregates(lg)
+        n_agg = info[lg + 1]["n_rows"] // info[lg + 1]["block"]
+        assert agg.min() == 0 and agg.max() == n_agg - 1
+        assert np.all(np.bincount(agg, minlength=n_agg) > 0)
+    H.close()
+
+
+def test_mixed_equals_fp64_at_full_size():
+    from paper_2001_01655_amd import Hierarchy
+    p = synth.get("cantilever3d")
+    f = torch.tensor(p.loads[0], device="cuda")
+    us = []
+    for vfp, outer in [(32, 0), (64, 1)]:
+        H = Hierarchy(p.nel, p.rho, p.fixed, n_levels=6, vcycle_fp=vfp, outer=outer)
+        r = H.solve(f, rtol=1e-8)
+        assert r.status == 0
+        us.append(r.u.clone())
+        H.close()
+    d = float((us[0] - us[1]).norm() / us[1].norm())
+    print(f"  mixed vs fp64: {d:.2e}", flush=True)
+    assert d <= 1e-7

@@ -31,3 +31,14 @@ def test_shapes_and_ranges():
     assert 1 <= s.loads.shape[0] <= 4
     t = synth.poisson_arrivals(50, 10.0)
     assert np.all(np.diff(t) > 0)
+
+
+def test_cantilever_2d_solid_is_anchored():
+    from scipy.ndimage import label
+    p = synth.cantilever_2d((128, 64))
+    nx, ny = p.nel
+    solid = (p.rho == 1.0).reshape(ny, nx)
+    lab, n = label(solid)
+    assert n == 1 and solid[:, 0].any()
+    # the element under the load node is solid and the field is not all solid
+    assert solid[ny // 2, nx - 1] and 0.3 < solid.mean() < 0.9
