@@ -52,6 +52,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip the event-timed solve")
+    ap.add_argument("--fine-mfma", type=int, default=0, choices=[0, 1],
+                    help="FP32 fine operator on the matrix cores (1) or vector FMAs (0)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="copy 256 MiB device-to-device first (counter calibration under rocprofv3 --pmc)")
     return ap.parse_args()
@@ -182,7 +184,7 @@ def main():
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         H = Hierarchy(p.nel, p.rho, p.fixed, p=p.p, E0=p.E0, Emin=p.Emin, nu=p.nu, omega=0.5, nu_pre=1,
-                      nu_post=1, vcycle_fp=vfp, outer=outer, **wl["opts"])
+                      nu_post=1, vcycle_fp=vfp, outer=outer, fine_mfma=args.fine_mfma, **wl["opts"])
         torch.cuda.synchronize()
         return H, time.perf_counter() - t0
 

@@ -85,6 +85,10 @@ typedef struct {
     int32_t outer;         /* TM_OUTER_FCG or TM_OUTER_PCG                                        */
     int32_t max_iters;     /* outer iteration limit (1000)                                        */
     int32_t check_every;   /* host convergence check period in iterations; 0 = adaptive          */
+    int32_t fine_mfma;     /* 1: FP32 3D fine operator contracts KE on the matrix cores
+                              (v_mfma_f32_4x4x1, KE broadcast from 12 registers); 0 (default):
+                              vector FMAs with KE symmetry-class values in scalar registers.
+                              Same operator either way; only the rounding order differs      */
 } tm_options;
 
 typedef struct tm_hierarchy tm_hierarchy;       /* opaque */

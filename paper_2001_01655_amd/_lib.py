@@ -41,7 +41,8 @@ class tm_options(C.Structure):
     _fields_ = [("n_levels", C.c_int32), ("n_geometric", C.c_int32), ("max_coarse", C.c_int32),
                 ("smoother", C.c_int32), ("nu_pre", C.c_int32), ("nu_post", C.c_int32),
                 ("omega", C.c_double), ("sa_beta", C.c_double), ("vcycle_fp", C.c_int32),
-                ("outer", C.c_int32), ("max_iters", C.c_int32), ("check_every", C.c_int32)]
+                ("outer", C.c_int32), ("max_iters", C.c_int32), ("check_every", C.c_int32),
+                ("fine_mfma", C.c_int32)]
 
 
 class TmError(RuntimeError):

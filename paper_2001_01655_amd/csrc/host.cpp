@@ -153,6 +153,37 @@ static void element_stiffness(int dim, double nu, double h, std::vector<double>&
         }
 }
 
+// Class values of KE under the symmetries of the square / cube (one value per
+// orbit, signs from the compile-time tables); every entry is checked against
+// its class value, so the fine operator applies exactly this KE.
+template <int DIM>
+static void ke_class_values(const KeClasses<DIM>& T, const std::vector<double>& KE, tm_hierarchy* h) {
+    constexpr int nd = DIM << DIM;
+    double amax = 0.0;
+    for (double v : KE) amax = std::max(amax, std::fabs(v));
+    bool seen[KE_MAX_CLASSES] = {};
+    double kv[KE_MAX_CLASSES] = {};
+    for (int r = 0; r < nd; ++r)
+        for (int c = 0; c < nd; ++c) {
+            const double v = KE[r * nd + c];
+            const int k = T.cls[r][c], sg = T.sgn[r][c];
+            if (sg == 0) {
+                if (std::fabs(v) > 1e-12 * amax) fail(TM_ERR_ARG, "element stiffness lacks its symmetry");
+                continue;
+            }
+            if (!seen[k]) {
+                seen[k] = true;
+                kv[k] = sg * v;
+            } else if (std::fabs(kv[k] - sg * v) > 1e-12 * amax) {
+                fail(TM_ERR_ARG, "element stiffness lacks its symmetry");
+            }
+        }
+    for (int k = 0; k < KE_MAX_CLASSES; ++k) {
+        h->kc64.k[k] = kv[k];
+        h->kc32.k[k] = (float)kv[k];
+    }
+}
+
 // Q[c][a][b]: weight of parent corner b at child c's corner a (coarse shape
 // functions), child c at offsets (c&1, c>>1&1, c>>2&1) inside its parent.
 static void child_weights(int dim, std::vector<double>& Q) {
@@ -212,6 +243,7 @@ static void check_opts(const tm_options* o) {
     if (o->outer != TM_OUTER_FCG && o->outer != TM_OUTER_PCG) fail(TM_ERR_ARG, "outer must be FCG or PCG");
     if (o->max_iters < 1) fail(TM_ERR_ARG, "max_iters must be >= 1");
     if (o->check_every < 0) fail(TM_ERR_ARG, "check_every must be >= 0");
+    if (o->fine_mfma != 0 && o->fine_mfma != 1) fail(TM_ERR_ARG, "fine_mfma must be 0 or 1");
     if (o->n_levels > 0 && o->n_geometric > o->n_levels) fail(TM_ERR_ARG, "n_geometric > n_levels");
 }
 
@@ -489,8 +521,10 @@ namespace tmi {
 
 static bool mixed_of(const tm_hierarchy* h) { return h->opt.vcycle_fp == 32; }
 
+// partial-sum slots per quantity: every kernel that writes block partials
+// launches one of these three grids
 static int nparts_cap(const tm_hierarchy* h) {
-    return std::max(fine_op_blocks(h), krylov_blocks(h->n_dof));
+    return std::max({fine_op_blocks(h), update_ur_blocks(h), krylov_blocks(h->n_dof)});
 }
 
 static tm_solve_state* new_state(tm_hierarchy* h, int nrhs) {
@@ -599,7 +633,7 @@ static void enqueue_iteration(tm_solve_state* st, int k) {
     timed_end(h, 0, s, e0);
     launch_finalize(sc, ln.part, fine_op_blocks(h), FIN_ALPHA, s);
     launch_update_ur(h, ln, sc, u, mixed, s);
-    launch_finalize(sc, ln.part, fine_op_blocks(h), FIN_RR, s);
+    launch_finalize(sc, ln.part, update_ur_blocks(h), FIN_RR, s);
     enqueue_vcycle_into_z(h, ln, done, s, true);
     launch_zdots(h, ln, sc, mixed, s);
     launch_finalize(sc, ln.part, krylov_blocks(n), FIN_BETA, s);
@@ -806,6 +840,7 @@ void tm_default_options(tm_options* o) {
     o->outer = TM_OUTER_FCG;
     o->max_iters = 1000;
     o->check_every = 0;
+    o->fine_mfma = 0;
 }
 
 const char* tm_status_string(tm_status s) {
@@ -907,13 +942,28 @@ tm_status tm_setup(const tm_mesh* mesh, const tm_material* mat, const double* rh
         // constants
         std::vector<double> KE, Q;
         element_stiffness(dim, mat->nu, mesh->h, KE);
+        if (dim == 3) ke_class_values(KE_CLS3, KE, h);
+        else ke_class_values(KE_CLS2, KE, h);
         child_weights(dim, Q);
-        std::vector<float> KE32(KE.begin(), KE.end());
         h->KE64 = halloc<double>(h, KE.size());
-        h->KE32 = halloc<float>(h, KE.size());
+        // A operand of the matrix-core operator: register q, lane L holds row
+        // L mod 4 (row 3 = 0) of KE column k = 16 q + L/4, k = 24 a + col for
+        // element corner slot a; entries rebuilt from the class values
+        std::vector<float> KA32;
+        if (dim == 3) {
+            KA32.assign(12 * 64, 0.f);
+            for (int q = 0; q < 12; ++q)
+                for (int L = 0; L < 64; ++L) {
+                    const int kk = 16 * q + L / 4, a = kk / 24, col = kk % 24, row = L % 4;
+                    if (row == 3) continue;
+                    const int r = 3 * a + row;
+                    KA32[q * 64 + L] = (float)KE_CLS3.sgn[r][col] * h->kc32.k[KE_CLS3.cls[r][col]];
+                }
+            h->KA32 = halloc<float>(h, KA32.size());
+        }
         h->Q64 = halloc<double>(h, Q.size());
         TM_HIP(hipMemcpyAsync(h->KE64, KE.data(), KE.size() * 8, hipMemcpyHostToDevice, s));
-        TM_HIP(hipMemcpyAsync(h->KE32, KE32.data(), KE32.size() * 4, hipMemcpyHostToDevice, s));
+        if (dim == 3) TM_HIP(hipMemcpyAsync(h->KA32, KA32.data(), KA32.size() * 4, hipMemcpyHostToDevice, s));
         TM_HIP(hipMemcpyAsync(h->Q64, Q.data(), Q.size() * 8, hipMemcpyHostToDevice, s));
         // levels
         h->lv.resize(plan.Lg);

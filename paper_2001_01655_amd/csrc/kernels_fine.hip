@@ -6,6 +6,8 @@
 // KE is read through uniform (scalar) loads; the work is one 2^dim*dim-row
 // slice of an element product per element per node, i.e. exactly the flops
 // of the element-by-element product, without redundancy.
+#include <type_traits>
+
 #include "tm_device.h"
 
 namespace tmi {
@@ -89,8 +91,70 @@ void launch_fine_dinv(const Level& L, const double* KE64, int point_jacobi, int*
 // 2^31 is checked at setup).  Neighbour loads use clamped coordinates and are
 // unconditional; an element outside the grid gets modulus 0, so the values
 // loaded for it (from a clamped, in-bounds node) contribute nothing.
+//
+// KE enters as its 12 symmetry-class values (kernel arguments, so they sit in
+// scalar registers for the whole kernel); each entry is a class value with a
+// compile-time sign.  The 27 neighbours are streamed one z-plane (9 nodes) at
+// a time: plane dz holds corner layer bz = dz - ez of the elements of layer
+// ez, so each (element, plane) pair gives a partial KE-row product that is
+// scaled by the element's modulus and added to the node's accumulator at
+// once, and only one plane of values is live.
+template <int R, int S, typename T>
+__device__ __forceinline__ void ke_fma3(const KeVals<T>& kc, T& t, T v) {
+    constexpr int sg = KE_CLS3.sgn[R][S];
+    constexpr int cl = KE_CLS3.cls[R][S];
+    if constexpr (sg > 0) t += kc.k[cl] * v;
+    else if constexpr (sg < 0) t -= kc.k[cl] * v;
+}
+
+template <int A, int BZ, int EY, int EX, typename T>
+__device__ __forceinline__ void elem_plane3(const KeVals<T>& kc, const T (&w)[9][3], T (&t)[3]) {
+    // corners (bx, by, BZ) of the element sit at plane offsets (EX+bx, EY+by)
+#define TM_CORNER(BX, BY)                                                                         \
+    {                                                                                              \
+        constexpr int bb = loc3(BX, BY, BZ);                                                       \
+        const T* vn = w[(EY + BY) * 3 + EX + BX];                                                  \
+        ke_fma3<3 * A + 0, 3 * bb + 0>(kc, t[0], vn[0]);                                            \
+        ke_fma3<3 * A + 0, 3 * bb + 1>(kc, t[0], vn[1]);                                            \
+        ke_fma3<3 * A + 0, 3 * bb + 2>(kc, t[0], vn[2]);                                            \
+        ke_fma3<3 * A + 1, 3 * bb + 0>(kc, t[1], vn[0]);                                            \
+        ke_fma3<3 * A + 1, 3 * bb + 1>(kc, t[1], vn[1]);                                            \
+        ke_fma3<3 * A + 1, 3 * bb + 2>(kc, t[1], vn[2]);                                            \
+        ke_fma3<3 * A + 2, 3 * bb + 0>(kc, t[2], vn[0]);                                            \
+        ke_fma3<3 * A + 2, 3 * bb + 1>(kc, t[2], vn[1]);                                            \
+        ke_fma3<3 * A + 2, 3 * bb + 2>(kc, t[2], vn[2]);                                            \
+    }
+    TM_CORNER(0, 0)
+    TM_CORNER(1, 0)
+    TM_CORNER(0, 1)
+    TM_CORNER(1, 1)
+#undef TM_CORNER
+}
+
+// all elements of layer EZ that have corners in plane DZ
+template <int DZ, int EZ, typename T>
+__device__ __forceinline__ void layer_plane3(const KeVals<T>& kc, const T (&w)[9][3], const T (&Ee)[2][2][2],
+                                             T (&acc)[3]) {
+    constexpr int BZ = DZ - EZ;
+    if constexpr (BZ >= 0 && BZ <= 1) {
+#define TM_ELEM(EY, EX)                                                                           \
+        {                                                                                          \
+            T t[3] = {0, 0, 0};                                                                    \
+            elem_plane3<loc3(1 - EX, 1 - EY, 1 - EZ), BZ, EY, EX>(kc, w, t);                       \
+            acc[0] += Ee[EZ][EY][EX] * t[0];                                                       \
+            acc[1] += Ee[EZ][EY][EX] * t[1];                                                       \
+            acc[2] += Ee[EZ][EY][EX] * t[2];                                                       \
+        }
+        TM_ELEM(0, 0)
+        TM_ELEM(0, 1)
+        TM_ELEM(1, 0)
+        TM_ELEM(1, 1)
+#undef TM_ELEM
+    }
+}
+
 template <typename T, int OP, bool MASK_IN>
-__global__ __launch_bounds__(WG) void k_fine3(const T* __restrict__ E, const T* __restrict__ KE,
+__global__ __launch_bounds__(WG) void k_fine3(const T* __restrict__ E, const KeVals<T> kc,
                                               const uint8_t* __restrict__ nm, int nx, int ny, int nz,
                                               int64_t N64, const T* __restrict__ x,
                                               const T* __restrict__ b, T* __restrict__ y,
@@ -107,26 +171,9 @@ __global__ __launch_bounds__(WG) void k_fine3(const T* __restrict__ E, const T* 
     const uint32_t cy[3] = {j ? j - 1 : 0u, j, min(j + 1, NY - 1)};
     const uint32_t cz[3] = {k ? k - 1 : 0u, k, min(k + 1, NZ - 1)};
     const auto xr = buf_rsrc(x, (int64_t)N * 3 * sizeof(T));
-    T v[3][9][3];  // [plane dz+1][(dy+1)*3 + dx+1][component]
-#pragma unroll
-    for (int dz = 0; dz < 3; ++dz)
-#pragma unroll
-        for (int dy = 0; dy < 3; ++dy) {
-            const uint32_t row = (cz[dz] * NY + cy[dy]) * NX;
-#pragma unroll
-            for (int dx = 0; dx < 3; ++dx) {
-                const uint32_t id = row + cx[dx];
-                T a[3];
-                bld3(xr, id * (3u * sizeof(T)), a);
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    if (MASK_IN) a[c] = ((nm[id] >> c) & 1u) ? T(0) : a[c];
-                    v[dz][dy * 3 + dx][c] = a[c];
-                }
-            }
-        }
     const auto er = buf_rsrc(E, (int64_t)nx * ny * nz * sizeof(T));
-    T acc[3] = {0, 0, 0};
+    // moduli of the 8 elements around the node, [ez][ey][ex]
+    T Ee[2][2][2];
 #pragma unroll
     for (int ez = 0; ez < 2; ++ez)
 #pragma unroll
@@ -139,27 +186,35 @@ __global__ __launch_bounds__(WG) void k_fine3(const T* __restrict__ E, const T* 
                 const uint32_t gx = min(i + ex, (uint32_t)nx) - (i + ex > 0 ? 1u : 0u);
                 const uint32_t gy = min(j + ey, (uint32_t)ny) - (j + ey > 0 ? 1u : 0u);
                 const uint32_t gz = min(k + ez, (uint32_t)nz) - (k + ez > 0 ? 1u : 0u);
-                const T Ee = in ? bld<T>(er, ((gz * (uint32_t)ny + gy) * (uint32_t)nx + gx) * (uint32_t)sizeof(T))
-                                : T(0);
-                const int a = loc3(1 - ex, 1 - ey, 1 - ez);
-                T t[3] = {0, 0, 0};
-#pragma unroll
-                for (int bz = 0; bz < 2; ++bz)
-#pragma unroll
-                    for (int by = 0; by < 2; ++by)
-#pragma unroll
-                        for (int bx = 0; bx < 2; ++bx) {
-                            const int bb = loc3(bx, by, bz);
-                            const T* vn = v[ez + bz][(ey + by) * 3 + ex + bx];
-#pragma unroll
-                            for (int c = 0; c < 3; ++c)
-#pragma unroll
-                                for (int d = 0; d < 3; ++d)
-                                    t[c] += KE[(3 * a + c) * 24 + 3 * bb + d] * vn[d];
-                        }
-#pragma unroll
-                for (int c = 0; c < 3; ++c) acc[c] += Ee * t[c];
+                Ee[ez][ey][ex] =
+                    in ? bld<T>(er, ((gz * (uint32_t)ny + gy) * (uint32_t)nx + gx) * (uint32_t)sizeof(T)) : T(0);
             }
+    T acc[3] = {0, 0, 0};
+    T w[9][3];
+    auto load_plane = [&](int dz) {
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy) {
+            const uint32_t row = (cz[dz] * NY + cy[dy]) * NX;
+#pragma unroll
+            for (int dx = 0; dx < 3; ++dx) {
+                const uint32_t id = row + cx[dx];
+                T a[3];
+                bld3(xr, id * (3u * sizeof(T)), a);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    if (MASK_IN) a[c] = ((nm[id] >> c) & 1u) ? T(0) : a[c];
+                    w[dy * 3 + dx][c] = a[c];
+                }
+            }
+        }
+    };
+    load_plane(0);
+    layer_plane3<0, 0>(kc, w, Ee, acc);
+    load_plane(1);
+    layer_plane3<1, 0>(kc, w, Ee, acc);
+    layer_plane3<1, 1>(kc, w, Ee, acc);
+    load_plane(2);
+    layer_plane3<2, 1>(kc, w, Ee, acc);
     double dots[2] = {0.0, 0.0};
     if (live) {
         const T xo[3] = {x[3u * node], x[3u * node + 1], x[3u * node + 2]};
@@ -168,9 +223,145 @@ __global__ __launch_bounds__(WG) void k_fine3(const T* __restrict__ E, const T* 
     if (OP == OP_QDOT) block_reduce_store<2>(dots, partials);
 }
 
+// 3D FP32 on the matrix cores: the same node-per-lane operator, with the
+// 24x24 KE contraction on v_mfma_f32_4x4x1 (16 blocks of 4 lanes).  In each
+// block, lane 4b+j supplies B = one neighbour value of its own node and gets
+// back D[i][j] = sum_k A[i][k] B[k][j] for rows i = 0..3, i.e. the three
+// KE-row products of its own node (row 3 is padding).  A is broadcast from one
+// block to all 16 (CBSZ = 4, ABID = k mod 16), so the 192 KE columns
+// (24 per element corner slot) x 4 rows sit in 12 registers per lane:
+// register q, block m holds column k = 16 q + m.  One accumulator per element
+// slot collects its 24 columns; the slots are then scaled by their moduli and
+// summed in a fixed order (deterministic, FP32 accumulation).
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+template <int K>
+__device__ __forceinline__ v4f mfma_col(const float (&ka)[12], float bv, v4f c) {
+    static_assert(K >= 0 && K < 192, "KE column");
+    return __builtin_amdgcn_mfma_f32_4x4x1f32(ka[K >> 4], bv, c, 4, K & 15, 0);
+}
+
+template <int DZ, int EZ>
+__device__ __forceinline__ void layer_plane3_mfma(const float (&ka)[12], const float (&w)[9][3], v4f (&C)[8]) {
+    constexpr int BZ = DZ - EZ;
+    if constexpr (BZ >= 0 && BZ <= 1) {
+        // consecutive instructions go to the 4 different accumulators of the layer
+#define TM_MF(EY, EX, BX, BY, D)                                                                  \
+    C[EZ * 4 + EY * 2 + EX] = mfma_col<24 * loc3(1 - EX, 1 - EY, 1 - EZ) + 3 * loc3(BX, BY, BZ) + D>( \
+        ka, w[(EY + BY) * 3 + EX + BX][D], C[EZ * 4 + EY * 2 + EX]);
+#define TM_MF4(BX, BY, D) TM_MF(0, 0, BX, BY, D) TM_MF(0, 1, BX, BY, D) TM_MF(1, 0, BX, BY, D) TM_MF(1, 1, BX, BY, D)
+#define TM_MF12(BX, BY) TM_MF4(BX, BY, 0) TM_MF4(BX, BY, 1) TM_MF4(BX, BY, 2)
+        TM_MF12(0, 0)
+        TM_MF12(1, 0)
+        TM_MF12(0, 1)
+        TM_MF12(1, 1)
+#undef TM_MF12
+#undef TM_MF4
+#undef TM_MF
+    }
+}
+
+template <int OP>
+__global__ __launch_bounds__(WG) void k_fine3_mfma(const float* __restrict__ E, const float* __restrict__ KA,
+                                                   const uint8_t* __restrict__ nm, int nx, int ny, int nz,
+                                                   int64_t N64, const float* __restrict__ x,
+                                                   const float* __restrict__ b, float* __restrict__ y,
+                                                   const float* __restrict__ dinv, float omega,
+                                                   const int* __restrict__ done) {
+    if (done && *done) return;
+    // every lane of the wave takes part in the matrix instructions: lanes past
+    // the last node work on node 0 and store nothing
+    const uint32_t lane = threadIdx.x & 63u;
+    float ka[12];
+#pragma unroll
+    for (int q = 0; q < 12; ++q) ka[q] = KA[q * 64 + lane];
+    const uint32_t N = (uint32_t)N64;
+    const uint32_t node = (uint32_t)xcd_block() * WG + threadIdx.x;
+    const bool live = node < N;
+    const uint32_t NX = nx + 1, NY = ny + 1, NZ = nz + 1;
+    const uint32_t nd = live ? node : 0u;
+    const uint32_t i = nd % NX, tq = nd / NX, j = tq % NY, k = tq / NY;
+    const uint32_t cx[3] = {i ? i - 1 : 0u, i, min(i + 1, NX - 1)};
+    const uint32_t cy[3] = {j ? j - 1 : 0u, j, min(j + 1, NY - 1)};
+    const uint32_t cz[3] = {k ? k - 1 : 0u, k, min(k + 1, NZ - 1)};
+    const auto xr = buf_rsrc(x, (int64_t)N * 12);
+    const auto er = buf_rsrc(E, (int64_t)nx * ny * nz * 4);
+    float Ee[8];
+#pragma unroll
+    for (int ez = 0; ez < 2; ++ez)
+#pragma unroll
+        for (int ey = 0; ey < 2; ++ey)
+#pragma unroll
+            for (int ex = 0; ex < 2; ++ex) {
+                const bool in = (ex || i) && (ex == 0 || i < (uint32_t)nx) && (ey || j) &&
+                                (ey == 0 || j < (uint32_t)ny) && (ez || k) && (ez == 0 || k < (uint32_t)nz);
+                const uint32_t gx = min(i + ex, (uint32_t)nx) - (i + ex > 0 ? 1u : 0u);
+                const uint32_t gy = min(j + ey, (uint32_t)ny) - (j + ey > 0 ? 1u : 0u);
+                const uint32_t gz = min(k + ez, (uint32_t)nz) - (k + ez > 0 ? 1u : 0u);
+                Ee[ez * 4 + ey * 2 + ex] = in ? bld<float>(er, ((gz * (uint32_t)ny + gy) * (uint32_t)nx + gx) * 4u) : 0.f;
+            }
+    v4f C[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) C[q] = v4f{0.f, 0.f, 0.f, 0.f};
+    float w[9][3];
+    auto load_plane = [&](int dz) {
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy) {
+            const uint32_t row = (cz[dz] * NY + cy[dy]) * NX;
+#pragma unroll
+            for (int dx = 0; dx < 3; ++dx) bld3(xr, (row + cx[dx]) * 12u, w[dy * 3 + dx]);
+        }
+    };
+    load_plane(0);
+    layer_plane3_mfma<0, 0>(ka, w, C);
+    load_plane(1);
+    layer_plane3_mfma<1, 0>(ka, w, C);
+    layer_plane3_mfma<1, 1>(ka, w, C);
+    load_plane(2);
+    layer_plane3_mfma<2, 1>(ka, w, C);
+    float acc[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        acc[0] += Ee[q] * C[q][0];
+        acc[1] += Ee[q] * C[q][1];
+        acc[2] += Ee[q] * C[q][2];
+    }
+    if (live) {
+        double dots[2] = {0.0, 0.0};
+        const float xo[3] = {x[3u * node], x[3u * node + 1], x[3u * node + 2]};
+        finish_node<float, 3, OP>(node, N, acc, xo, nm[node], b, y, dinv, omega, dots);
+    }
+}
+
 // 2D: 9 neighbour nodes, 4 elements, 8x8 KE.
+template <int R, int S, typename T>
+__device__ __forceinline__ void ke_fma2(const KeVals<T>& kc, T& t, T v) {
+    constexpr int sg = KE_CLS2.sgn[R][S];
+    constexpr int cl = KE_CLS2.cls[R][S];
+    if constexpr (sg > 0) t += kc.k[cl] * v;
+    else if constexpr (sg < 0) t -= kc.k[cl] * v;
+}
+
+template <int A, int EY, int EX, typename T>
+__device__ __forceinline__ void elem2(const KeVals<T>& kc, const T (&v)[9][2], T (&t)[2]) {
+#define TM_CORNER(BX, BY)                                                                         \
+    {                                                                                              \
+        constexpr int bb = loc2(BX, BY);                                                           \
+        const T* vn = v[(EY + BY) * 3 + EX + BX];                                                  \
+        ke_fma2<2 * A + 0, 2 * bb + 0>(kc, t[0], vn[0]);                                            \
+        ke_fma2<2 * A + 0, 2 * bb + 1>(kc, t[0], vn[1]);                                            \
+        ke_fma2<2 * A + 1, 2 * bb + 0>(kc, t[1], vn[0]);                                            \
+        ke_fma2<2 * A + 1, 2 * bb + 1>(kc, t[1], vn[1]);                                            \
+    }
+    TM_CORNER(0, 0)
+    TM_CORNER(1, 0)
+    TM_CORNER(0, 1)
+    TM_CORNER(1, 1)
+#undef TM_CORNER
+}
+
 template <typename T, int OP, bool MASK_IN>
-__global__ __launch_bounds__(WG) void k_fine2(const T* __restrict__ E, const T* __restrict__ KE,
+__global__ __launch_bounds__(WG) void k_fine2(const T* __restrict__ E, const KeVals<T> kc,
                                               const uint8_t* __restrict__ nm, int nx, int ny,
                                               int64_t N, const T* __restrict__ x,
                                               const T* __restrict__ b, T* __restrict__ y,
@@ -204,30 +395,25 @@ __global__ __launch_bounds__(WG) void k_fine2(const T* __restrict__ E, const T* 
             v[dy * 3 + dx][0] = a0;
             v[dy * 3 + dx][1] = a1;
         }
+    auto Eat = [&](int ex, int ey) -> T {
+        const int gx = i - 1 + ex, gy = j - 1 + ey;
+        const bool ok = live && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+        return ok ? E[(int64_t)gy * nx + gx] : T(0);
+    };
     T acc[2] = {0, 0};
-#pragma unroll
-    for (int ey = 0; ey < 2; ++ey)
-#pragma unroll
-        for (int ex = 0; ex < 2; ++ex) {
-            const int gx = i - 1 + ex, gy = j - 1 + ey;
-            const bool ok = live && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
-            const T Ee = ok ? E[(int64_t)gy * nx + gx] : T(0);
-            const int a = loc2(1 - ex, 1 - ey);
-            T t[2] = {0, 0};
-#pragma unroll
-            for (int by = 0; by < 2; ++by)
-#pragma unroll
-                for (int bx = 0; bx < 2; ++bx) {
-                    const int bb = loc2(bx, by);
-                    const T* vn = v[(ey + by) * 3 + ex + bx];
-#pragma unroll
-                    for (int c = 0; c < 2; ++c)
-#pragma unroll
-                        for (int d = 0; d < 2; ++d) t[c] += KE[(2 * a + c) * 8 + 2 * bb + d] * vn[d];
-                }
-#pragma unroll
-            for (int c = 0; c < 2; ++c) acc[c] += Ee * t[c];
-        }
+#define TM_ELEM(EY, EX)                                                                           \
+    {                                                                                              \
+        const T Ee = Eat(EX, EY);                                                                  \
+        T t[2] = {0, 0};                                                                           \
+        elem2<loc2(1 - EX, 1 - EY), EY, EX>(kc, v, t);                                             \
+        acc[0] += Ee * t[0];                                                                       \
+        acc[1] += Ee * t[1];                                                                       \
+    }
+    TM_ELEM(0, 0)
+    TM_ELEM(0, 1)
+    TM_ELEM(1, 0)
+    TM_ELEM(1, 1)
+#undef TM_ELEM
     double dots[2] = {0.0, 0.0};
     if (live) {
         const T xo[2] = {x[2 * node], x[2 * node + 1]};
@@ -245,11 +431,11 @@ const double* pick_E<double>(const Level& L) { return L.E64; }
 template <>
 const float* pick_E<float>(const Level& L) { return L.E32; }
 template <typename T>
-static const T* pick_KE(const tm_hierarchy* h);
+static const KeVals<T>& pick_kc(const tm_hierarchy* h);
 template <>
-const double* pick_KE<double>(const tm_hierarchy* h) { return h->KE64; }
+const KeVals<double>& pick_kc<double>(const tm_hierarchy* h) { return h->kc64; }
 template <>
-const float* pick_KE<float>(const tm_hierarchy* h) { return h->KE32; }
+const KeVals<float>& pick_kc<float>(const tm_hierarchy* h) { return h->kc32; }
 template <typename T>
 static const T* pick_dinv(const Level& L);
 template <>
@@ -262,12 +448,19 @@ static void fine_dispatch(const tm_hierarchy* h, const T* x, const T* b, T* y, T
                           const int* done, double* partials, hipStream_t s) {
     const Level& L = h->lv[0];
     const dim3 g(grid_for(L.n_nodes)), blk(WG);
+    if constexpr (std::is_same<T, float>::value && !MI && OP != OP_QDOT) {
+        if (L.dim == 3 && h->opt.fine_mfma) {
+            hipLaunchKernelGGL((k_fine3_mfma<OP>), g, blk, 0, s, L.E32, h->KA32, L.nmask, L.nel[0], L.nel[1],
+                               L.nel[2], L.n_nodes, x, b, y, L.dinv32, omega, done);
+            return;
+        }
+    }
     if (L.dim == 3)
-        hipLaunchKernelGGL((k_fine3<T, OP, MI>), g, blk, 0, s, pick_E<T>(L), pick_KE<T>(h), L.nmask,
+        hipLaunchKernelGGL((k_fine3<T, OP, MI>), g, blk, 0, s, pick_E<T>(L), pick_kc<T>(h), L.nmask,
                            L.nel[0], L.nel[1], L.nel[2], L.n_nodes, x, b, y, pick_dinv<T>(L), omega,
                            done, partials);
     else
-        hipLaunchKernelGGL((k_fine2<T, OP, MI>), g, blk, 0, s, pick_E<T>(L), pick_KE<T>(h), L.nmask,
+        hipLaunchKernelGGL((k_fine2<T, OP, MI>), g, blk, 0, s, pick_E<T>(L), pick_kc<T>(h), L.nmask,
                            L.nel[0], L.nel[1], L.n_nodes, x, b, y, pick_dinv<T>(L), omega, done,
                            partials);
 }

@@ -216,11 +216,14 @@ __global__ __launch_bounds__(WG) void k_update_ur(double* __restrict__ u, double
     block_reduce_store<1>(v, part);
 }
 
+// one block per WG nodes; its partial sums of |r|^2 are finalised with this count
+int update_ur_blocks(const tm_hierarchy* h) { return (int)grid_for(h->lv[0].n_nodes); }
+
 template <typename TV>
 static void update_ur_t(const tm_hierarchy* h, Lane& ln, KScal* sc, double* u, TV* rv, TV* x0,
                         const TV* dinv, hipStream_t s) {
     const Level& L = h->lv[0];
-    const dim3 g(grid_for(L.n_nodes)), b(WG);
+    const dim3 g(update_ur_blocks(h)), b(WG);
     const TV w = (TV)h->opt.omega;
     if (L.bs == 3)
         hipLaunchKernelGGL((k_update_ur<TV, 3>), g, b, 0, s, u, ln.r, ln.p, ln.q, rv, x0, dinv, w, L.n_nodes,

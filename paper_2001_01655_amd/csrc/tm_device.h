@@ -45,15 +45,21 @@ template <>
 __device__ __forceinline__ double bld<double>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
     return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
 }
-// three consecutive values starting at byte offset off
+// three consecutive values starting at byte offset off: one 12-byte load for
+// FP32, a 16-byte and an 8-byte load for FP64 (the vector assignments below
+// reinterpret the loaded bits; they convert no values)
 __device__ __forceinline__ void bld3(__amdgpu_buffer_rsrc_t r, uint32_t off, float (&v)[3]) {
-    v[0] = bld<float>(r, off);
-    v[1] = bld<float>(r, off + 4);
-    v[2] = bld<float>(r, off + 8);
+    typedef float f3 __attribute__((ext_vector_type(3)));
+    const f3 t = __builtin_amdgcn_raw_buffer_load_b96(r, off, 0, 0);
+    v[0] = t.x;
+    v[1] = t.y;
+    v[2] = t.z;
 }
 __device__ __forceinline__ void bld3(__amdgpu_buffer_rsrc_t r, uint32_t off, double (&v)[3]) {
-    v[0] = bld<double>(r, off);
-    v[1] = bld<double>(r, off + 8);
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    const d2 t = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+    v[0] = t.x;
+    v[1] = t.y;
     v[2] = bld<double>(r, off + 16);
 }
 

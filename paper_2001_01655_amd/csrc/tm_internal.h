@@ -40,6 +40,86 @@ __device__ __forceinline__ int64_t xcd_block() {
 __host__ __device__ constexpr int loc2(int lx, int ly) { return ly ? (lx ? 2 : 3) : (lx ? 1 : 0); }
 __host__ __device__ constexpr int loc3(int lx, int ly, int lz) { return 4 * lz + loc2(lx, ly); }
 
+// Symmetry classes of the element stiffness of a square / cube element of an
+// isotropic material.  Each symmetry of the square (8) or cube (48), an axis
+// permutation p with reflections m, maps corner a to corner g(a) and dof
+// component c to p(c) with sign -1 if axis c is reflected; KE is invariant,
+// KE[(a,c),(b,d)] = s_c s_d KE[(g a, p c),(g b, p d)], and symmetric.  The
+// orbits of the entries under these maps give cls[r][s] (the class of entry
+// (r, s)) and sgn[r][s] (its sign relative to the class value, 0 for an entry
+// the symmetries force to zero).  2D has 7 classes, 3D has 12, so the whole
+// 8x8 / 24x24 matrix lives in a handful of wave-uniform registers.
+template <int DIM>
+struct KeClasses {
+    static constexpr int NN = 1 << DIM, ND = DIM * NN;
+    int8_t cls[ND][ND];
+    int8_t sgn[ND][ND];
+    int n;
+};
+constexpr int KE_MAX_CLASSES = 12;
+
+__host__ __device__ constexpr int corner_coord(int a, int ax) {
+    const int q = a & 3;
+    return ax == 0 ? (q == 1 || q == 2) : ax == 1 ? (q >= 2) : (a >> 2);
+}
+
+template <int DIM>
+constexpr KeClasses<DIM> make_ke_classes() {
+    constexpr int NN = 1 << DIM, ND = DIM * NN;
+    constexpr int P3[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+    constexpr int P2[2][3] = {{0, 1, 2}, {1, 0, 2}};
+    const int np = DIM == 3 ? 6 : 2;
+    KeClasses<DIM> T{};
+    for (int r = 0; r < ND; ++r)
+        for (int s = 0; s < ND; ++s) {
+            T.cls[r][s] = -1;
+            T.sgn[r][s] = 0;
+        }
+    int n = 0;
+    for (int r = 0; r < ND; ++r)
+        for (int s = 0; s < ND; ++s) {
+            if (T.cls[r][s] >= 0) continue;
+            const int a = r / DIM, c = r % DIM, b = s / DIM, d = s % DIM;
+            bool zero = false;
+            for (int pi = 0; pi < np; ++pi)
+                for (int m = 0; m < NN; ++m) {
+                    const int* p = DIM == 3 ? P3[pi] : P2[pi];
+                    int qa[3] = {0, 0, 0}, qb[3] = {0, 0, 0};
+                    for (int ax = 0; ax < DIM; ++ax) {
+                        const int fl = (m >> ax) & 1;
+                        qa[p[ax]] = fl ? 1 - corner_coord(a, ax) : corner_coord(a, ax);
+                        qb[p[ax]] = fl ? 1 - corner_coord(b, ax) : corner_coord(b, ax);
+                    }
+                    const int a2 = DIM == 3 ? loc3(qa[0], qa[1], qa[2]) : loc2(qa[0], qa[1]);
+                    const int b2 = DIM == 3 ? loc3(qb[0], qb[1], qb[2]) : loc2(qb[0], qb[1]);
+                    const int sg = (((m >> c) & 1) ? -1 : 1) * (((m >> d) & 1) ? -1 : 1);
+                    const int r2 = DIM * a2 + p[c], s2 = DIM * b2 + p[d];
+                    const int rr[2] = {r2, s2}, ss[2] = {s2, r2};
+                    for (int t = 0; t < 2; ++t) {
+                        if (T.cls[rr[t]][ss[t]] == n && T.sgn[rr[t]][ss[t]] != sg) zero = true;
+                        T.cls[rr[t]][ss[t]] = (int8_t)n;
+                        T.sgn[rr[t]][ss[t]] = (int8_t)sg;
+                    }
+                }
+            if (zero)
+                for (int r3 = 0; r3 < ND; ++r3)
+                    for (int s3 = 0; s3 < ND; ++s3)
+                        if (T.cls[r3][s3] == n) T.sgn[r3][s3] = 0;
+            ++n;
+        }
+    T.n = n;
+    return T;
+}
+inline constexpr KeClasses<2> KE_CLS2 = make_ke_classes<2>();
+inline constexpr KeClasses<3> KE_CLS3 = make_ke_classes<3>();
+static_assert(KE_CLS2.n <= KE_MAX_CLASSES && KE_CLS3.n <= KE_MAX_CLASSES, "KE class count");
+
+// class values of KE (E = 1), passed to the fine kernels by value
+template <typename T>
+struct KeVals {
+    T k[KE_MAX_CLASSES];
+};
+
 // Status flags written by kernels (checked by the host after setup phases).
 enum : int { FLAG_BAD_RHO = 1, FLAG_NOT_SPD = 2, FLAG_OVERFLOW = 4 };
 
@@ -111,7 +191,9 @@ struct tm_hierarchy {
     std::vector<int64_t> fixed;
     std::vector<tmi::Level> lv;
     double* KE64 = nullptr;        // element stiffness for E = 1 (device)
-    float* KE32 = nullptr;
+    float* KA32 = nullptr;         // 3D: KE as the broadcast A operand of the matrix-core fine operator
+    tmi::KeVals<double> kc64{};       // KE symmetry-class values (fine operator arguments)
+    tmi::KeVals<float> kc32{};
     double* Q64 = nullptr;         // coarse-from-fine interpolation weights per child [2^d][2^d][2^d]
     double* ainv = nullptr;        // inverse of the coarsest operator (FP64, dense)
     float* ainv32 = nullptr;
@@ -171,6 +253,7 @@ void launch_fine_dinv(const Level& L, const double* KE64, int point_jacobi, int*
 template <typename T>
 void launch_fine_op(const tm_hierarchy* h, int op, bool mask_in, const T* x, const T* b, T* y,
                     T omega, const int* done, double* partials, hipStream_t s);
+int update_ur_blocks(const tm_hierarchy* h);
 int fine_op_blocks(const tm_hierarchy* h);
 // coarse geometric levels (kernels_coarse.hip)
 void launch_galerkin_elems(const tm_hierarchy* h, int fine_level, const double* child,

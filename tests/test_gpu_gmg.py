@@ -159,3 +159,39 @@ def test_warm_start_and_update():
     diff = (r_warm.u - r_cold.u).norm() / r_cold.u.norm()
     assert float(diff) < 1e-6
     G.close()
+
+
+@pytest.mark.parametrize("dim,nel,L", [c for c in CASES if c[0] == 3])
+def test_vcycle_fp32_matrix_cores(dim, nel, L):
+    """The FP32 fine operator on the matrix cores gives the V-cycle of the
+    oracle to FP32 accuracy, and agrees with the vector-FMA operator."""
+    _say(f"vcycle matrix cores {nel}")
+    p = synth.small_case(dim, nel, seed=26)
+    H, E, KE = _oracle(p, L)
+    b = H.A[0] @ np.random.default_rng(7).standard_normal(p.n_dof)
+    b[p.fixed] = 0.0
+    ref = mg.vcycle(H, b)
+    z = {}
+    for mf in (0, 1):
+        G = _gpu(p, L, vcycle_fp=32, fine_mfma=mf)
+        z[mf] = G.vcycle(torch.tensor(b, device="cuda", dtype=torch.float32), fp=32).cpu().numpy()
+        G.close()
+    assert _rel(z[1], ref) <= 1e-3
+    assert _rel(z[1], z[0]) <= 1e-4
+
+
+def test_solve_matrix_cores_vs_oracle():
+    """Mixed-precision solve with the matrix-core fine operator: u and
+    compliance at rtol 1e-8 against the oracle at rtol 1e-12."""
+    _say("solve matrix cores (16, 8, 8)")
+    p = synth.small_case(3, (16, 8, 8), seed=27, n_rhs=2)
+    H, E, KE = _oracle(p, 3)
+    G = _gpu(p, 3, vcycle_fp=32, outer=0, fine_mfma=1)
+    r = G.solve(torch.tensor(p.loads, device="cuda"), rtol=1e-8)
+    U = r.u.cpu().numpy()
+    for k in range(p.loads.shape[0]):
+        ref = mg.mg_pcg(H, p.loads[k], 1e-12)
+        assert r.converged and r.relres[k] <= 1.2e-8
+        assert np.linalg.norm(U[k] - ref.u) <= 1e-7 * np.linalg.norm(ref.u)
+        assert abs(r.compliance[k] - ref.compliance) <= 1e-9 * abs(ref.compliance)
+    G.close()
