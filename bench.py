@@ -89,11 +89,15 @@ def algorithmic(cls, H, p):
         # the smoothing sweep also reads the block inverse (half of class-1 launches)
         byts = 3 * dim * w * n_nodes + w * n_el + n_nodes + (0 if cls == 0 else 0.5 * dim * dim * w * n_nodes)
         return flops, byts
+    # level-1 operator, stored in symmetric form: the blocks towards the upper
+    # half of the neighbours plus the diagonal block's upper triangle; the
+    # lower blocks are the neighbours' stored ones (re-reads, not counted)
     info = H.level_info(1)
     n1 = info["n_rows"] // dim
     nst = 27 if dim == 3 else 9
+    nq = (nst - 1) // 2 * dim * dim + dim * (dim + 1) // 2
     flops = 2.0 * nst * dim * dim * n1
-    byts = (nst * dim * dim + 3 * dim + 0.5 * dim * dim) * 4 * n1
+    byts = (nq + 3 * dim + 0.5 * dim * dim) * 4 * n1
     return flops, byts
 
 

@@ -325,7 +325,9 @@ static void alloc_level_geo(tm_hierarchy* h, Level& L, int l) {
         L.kind = TM_LEVEL_GEOMETRIC;
         L.nst = dim == 3 ? 27 : 9;
         L.st64 = halloc<double>(h, (size_t)L.nst * bb * L.n_nodes);
-        L.st32 = halloc<float>(h, (size_t)L.nst * bb * L.n_nodes);
+        L.nq = (L.nst - 1) / 2 * bb + dim * (dim + 1) / 2;
+        L.stc64 = halloc<double>(h, (size_t)L.nq * L.n_nodes);
+        L.stc32 = halloc<float>(h, (size_t)L.nq * L.n_nodes);
     }
 }
 
@@ -360,6 +362,7 @@ static void numeric_setup(tm_hierarchy* h, const double* rho, hipStream_t s) {
         double* cur = bufs[(l - 1) & 1];
         launch_galerkin_elems(h, l - 1, prev, cur, s);
         launch_stencil_assemble(h->lv[l], cur, s);
+        launch_stencil_compact(h->lv[l], s);
         launch_stencil_dinv(h->lv[l], point, h->flags, s);
         prev = cur;
     }
@@ -878,7 +881,8 @@ tm_status tm_plan_bytes(const tm_mesh* mesh, const tm_options* opts, int32_t n_r
             for (int d = 0; d < dim; ++d) nel[d] /= 2;
             const int64_t nn = nodes_of(nel, dim);
             const int64_t ne = (int64_t)nel[0] * nel[1] * (dim == 3 ? nel[2] : 1);
-            b += (size_t)nn * bb * 12 * ((dim == 3 ? 27 : 9) + 1);
+            const int nst = dim == 3 ? 27 : 9, nq = (nst - 1) / 2 * bb + dim * (dim + 1) / 2;
+            b += (size_t)nn * (bb * 8 * nst + 12 * nq + 12 * bb);
             vec += (size_t)nn * dim * (mixed ? 4 : 8) * 3;
             if (l == 1) el1 = (size_t)ne * nd * nd * 8;
             if (l == 2) el2 = (size_t)ne * nd * nd * 8;

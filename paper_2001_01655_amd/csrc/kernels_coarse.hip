@@ -99,7 +99,7 @@ void launch_galerkin_elems(const tm_hierarchy* h, int fine_level, const double* 
 // holding both nodes, in a fixed order.
 template <int DIM>
 __global__ void k_stencil_assemble(const double* __restrict__ elem, int nx, int ny, int nz,
-                                   int64_t N, double* __restrict__ st64, float* __restrict__ st32) {
+                                   int64_t N, double* __restrict__ st64) {
     constexpr int NPE = 1 << DIM, ND = DIM * NPE, NST = DIM == 3 ? 27 : 9;
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (tid >= N * NST) return;
@@ -142,7 +142,6 @@ __global__ void k_stencil_assemble(const double* __restrict__ elem, int nx, int 
 #pragma unroll
     for (int q = 0; q < DIM * DIM; ++q) {
         st64[((int64_t)o * DIM * DIM + q) * N + node] = blk[q];
-        st32[((int64_t)o * DIM * DIM + q) * N + node] = (float)blk[q];
     }
 }
 
@@ -150,10 +149,49 @@ void launch_stencil_assemble(const Level& L, const double* elem, hipStream_t s) 
     const int64_t nt = L.n_nodes * L.nst;
     if (L.dim == 3)
         hipLaunchKernelGGL(k_stencil_assemble<3>, dim3(grid_for(nt)), dim3(WG), 0, s, elem, L.nel[0],
-                           L.nel[1], L.nel[2], L.n_nodes, L.st64, L.st32);
+                           L.nel[1], L.nel[2], L.n_nodes, L.st64);
     else
         hipLaunchKernelGGL(k_stencil_assemble<2>, dim3(grid_for(nt)), dim3(WG), 0, s, elem, L.nel[0],
-                           L.nel[1], 1, L.n_nodes, L.st64, L.st32);
+                           L.nel[1], 1, L.n_nodes, L.st64);
+}
+
+// --------------------------------------------------------------- symmetric form
+// Compact V-cycle copy: q < NU*BB holds entry e of the block towards upper
+// neighbour u (grid offset index (NST+1)/2 + u); the last DIM(DIM+1)/2 hold the
+// diagonal block's upper triangle, row by row.
+template <int DIM>
+__global__ void k_stencil_compact(const double* __restrict__ st64, int64_t N, double* __restrict__ c64,
+                                  float* __restrict__ c32) {
+    constexpr int NST = DIM == 3 ? 27 : 9, BB = DIM * DIM, NU = (NST - 1) / 2;
+    constexpr int NQ = NU * BB + DIM * (DIM + 1) / 2;
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (tid >= N * NQ) return;
+    const int q = (int)(tid / N);
+    const int64_t node = tid % N;
+    int src;
+    if (q < NU * BB) {
+        src = (NU + 1 + q / BB) * BB + q % BB;
+    } else {
+        int t = q - NU * BB, r = 0;
+        while (t >= DIM - r) {
+            t -= DIM - r;
+            ++r;
+        }
+        src = NU * BB + r * DIM + r + t;  // centre block, row r, column r + t
+    }
+    const double v = st64[(int64_t)src * N + node];
+    c64[(int64_t)q * N + node] = v;
+    c32[(int64_t)q * N + node] = (float)v;
+}
+
+void launch_stencil_compact(const Level& L, hipStream_t s) {
+    const int64_t nt = L.n_nodes * L.nq;
+    if (L.dim == 3)
+        hipLaunchKernelGGL(k_stencil_compact<3>, dim3(grid_for(nt)), dim3(WG), 0, s, L.st64, L.n_nodes, L.stc64,
+                           L.stc32);
+    else
+        hipLaunchKernelGGL(k_stencil_compact<2>, dim3(grid_for(nt)), dim3(WG), 0, s, L.st64, L.n_nodes, L.stc64,
+                           L.stc32);
 }
 
 // --------------------------------------------------------------- stencil diagonal
@@ -185,6 +223,11 @@ void launch_stencil_dinv(const Level& L, int point_jacobi, int* flags, hipStream
 }
 
 // --------------------------------------------------------------- stencil operator
+// y = A x from the symmetric form: the diagonal block, the stored blocks towards
+// the upper neighbours, and for each lower neighbour m the transpose of m's
+// stored block towards this node (A is symmetric).  Neighbours outside the grid
+// have zero stored blocks (upper) or have their x masked to zero (lower); all
+// loads use clamped, in-bounds indices, with no branches.
 template <typename T, int DIM, int OP>
 __global__ __launch_bounds__(WG) void k_stencil_op(const T* __restrict__ st, int nx, int ny, int nz,
                                                    int64_t N, const T* __restrict__ x,
@@ -194,45 +237,87 @@ __global__ __launch_bounds__(WG) void k_stencil_op(const T* __restrict__ st, int
     if (done && *done) return;
     const int64_t node = xcd_block() * WG + threadIdx.x;
     if (node >= N) return;
-    constexpr int BB = DIM * DIM;
+    constexpr int BB = DIM * DIM, NST = DIM == 3 ? 27 : 9, NU = (NST - 1) / 2;
+    constexpr int NQ = NU * BB + DIM * (DIM + 1) / 2;
     const int NX = nx + 1, NY = ny + 1, NZ = nz + 1;
     const int i = (int)(node % NX);
     const int j = (int)((node / NX) % NY);
     const int k = DIM == 3 ? (int)(node / ((int64_t)NX * NY)) : 0;
-    // Neighbours outside the grid carry zero blocks, so their (clamped, in-bounds)
-    // x loads contribute nothing; no branches keep all loads in flight at once.
-    // 32-bit byte offsets through buffer descriptors (level sizes < 2 GB).
-    const auto sr = buf_rsrc(st, (int64_t)N * (DIM == 3 ? 27 : 9) * BB * sizeof(T));
+    // 32-bit byte offsets through buffer descriptors (level sizes < 2 GB)
+    const auto sr = buf_rsrc(st, (int64_t)N * NQ * sizeof(T));
     const auto xr = buf_rsrc(x, (int64_t)N * DIM * sizeof(T));
     const uint32_t un = (uint32_t)node, uN = (uint32_t)N;
-    T acc[DIM] = {};
     uint32_t ci[3], cj[3], ck[3];
+    bool ii[3], ij[3], ik[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         ci[d] = (uint32_t)min(max(i + d - 1, 0), NX - 1);
         cj[d] = (uint32_t)min(max(j + d - 1, 0), NY - 1);
         ck[d] = DIM == 3 ? (uint32_t)min(max(k + d - 1, 0), NZ - 1) : 0u;
+        ii[d] = i + d - 1 >= 0 && i + d - 1 < NX;
+        ij[d] = j + d - 1 >= 0 && j + d - 1 < NY;
+        ik[d] = DIM == 2 || (k + d - 1 >= 0 && k + d - 1 < NZ);
     }
+    T acc[DIM] = {};
+    T xo[DIM];
 #pragma unroll
-    for (int dz = 0; dz < (DIM == 3 ? 3 : 1); ++dz)
+    for (int c = 0; c < DIM; ++c) xo[c] = bld<T>(xr, (DIM * un + c) * (uint32_t)sizeof(T));
+    // diagonal block (upper triangle stored)
+    {
+        int q = NU * BB;
 #pragma unroll
-        for (int dy = 0; dy < 3; ++dy)
+        for (int r = 0; r < DIM; ++r)
 #pragma unroll
-            for (int dx = 0; dx < 3; ++dx) {
-                const int o = DIM == 3 ? dz * 9 + dy * 3 + dx : dy * 3 + dx;
-                const uint32_t J = (ck[dz] * (uint32_t)NY + cj[dy]) * (uint32_t)NX + ci[dx];
-                T xv[DIM];
+            for (int c = r; c < DIM; ++c, ++q) {
+                const T a = bld<T>(sr, ((uint32_t)q * uN + un) * (uint32_t)sizeof(T));
+                acc[r] += a * xo[c];
+                if (c != r) acc[c] += a * xo[r];
+            }
+    }
+    // neighbours in groups of G: all loads of a group are issued before its
+    // arithmetic (the scheduling barrier keeps them batched), so G * (BB + DIM)
+    // loads are in flight per wave
+    constexpr int G = DIM == 3 ? 3 : 4;
 #pragma unroll
-                for (int c = 0; c < DIM; ++c) xv[c] = bld<T>(xr, (DIM * J + c) * (uint32_t)sizeof(T));
+    for (int g0 = 0; g0 < NST; g0 += G) {
+        T xv[G][DIM], blk[G][BB];
+#pragma unroll
+        for (int gg = 0; gg < G; ++gg) {
+            const int o = g0 + gg;
+            if (o >= NST || o == NU) continue;
+            const int dx = o % 3, dy = (o / 3) % 3, dz = DIM == 3 ? o / 9 : 1;
+            const uint32_t J = (ck[dz] * (uint32_t)NY + cj[dy]) * (uint32_t)NX + ci[dx];
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) xv[gg][c] = bld<T>(xr, (DIM * J + c) * (uint32_t)sizeof(T));
+            if (o > NU) {
+                // own block towards upper neighbour o - NU - 1 (zero if outside)
+                const uint32_t q0 = (uint32_t)(o - NU - 1) * BB;
+#pragma unroll
+                for (int e = 0; e < BB; ++e) blk[gg][e] = bld<T>(sr, ((q0 + e) * uN + un) * (uint32_t)sizeof(T));
+            } else {
+                // neighbour J's block towards this node (its upper neighbour NST-1-o), transposed
+                const uint32_t q0 = (uint32_t)(NST - 1 - o - NU - 1) * BB;
 #pragma unroll
                 for (int r = 0; r < DIM; ++r)
 #pragma unroll
                     for (int c = 0; c < DIM; ++c)
-                        acc[r] += bld<T>(sr, ((uint32_t)(o * BB + r * DIM + c) * uN + un) * (uint32_t)sizeof(T)) * xv[c];
-            }
-    T xo[DIM];
+                        blk[gg][r * DIM + c] = bld<T>(sr, ((q0 + c * DIM + r) * uN + J) * (uint32_t)sizeof(T));
+                const bool in = ii[dx] && ij[dy] && ik[dz];
 #pragma unroll
-    for (int c = 0; c < DIM; ++c) xo[c] = x[DIM * node + c];
+                for (int c = 0; c < DIM; ++c) xv[gg][c] = in ? xv[gg][c] : T(0);
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int gg = 0; gg < G; ++gg) {
+            const int o = g0 + gg;
+            if (o >= NST || o == NU) continue;
+#pragma unroll
+            for (int r = 0; r < DIM; ++r)
+#pragma unroll
+                for (int c = 0; c < DIM; ++c) acc[r] += blk[gg][r * DIM + c] * xv[gg][c];
+        }
+    }
     double dots[2];
     finish_node<T, DIM, OP>(node, N, acc, xo, 0, b, y, dinv, omega, dots);
 }
@@ -240,9 +325,9 @@ __global__ __launch_bounds__(WG) void k_stencil_op(const T* __restrict__ st, int
 template <typename T>
 static const T* st_of(const Level& L);
 template <>
-const double* st_of<double>(const Level& L) { return L.st64; }
+const double* st_of<double>(const Level& L) { return L.stc64; }
 template <>
-const float* st_of<float>(const Level& L) { return L.st32; }
+const float* st_of<float>(const Level& L) { return L.stc32; }
 template <typename T>
 static const T* dinv_of(const Level& L);
 template <>

@@ -157,10 +157,16 @@ struct Level {
     double* E64 = nullptr;
     float* E32 = nullptr;
     uint8_t* nmask = nullptr;     // per node: bit c set <=> dof c supported
-    // geometric coarse level: stencil [nst][bs*bs][n_nodes]
+    // geometric coarse level: stencil [nst][bs*bs][n_nodes] (FP64, setup and exports)
     int nst = 0;
     double* st64 = nullptr;
-    float* st32 = nullptr;
+    // V-cycle copy in symmetric form [nq][n_nodes]: the blocks towards the
+    // (nst-1)/2 neighbours after the node in grid order, then the upper
+    // triangle of the diagonal block; the other blocks are transposes of the
+    // neighbours' stored ones
+    int nq = 0;
+    double* stc64 = nullptr;
+    float* stc32 = nullptr;
     // aggregation level operator
     BSR A;
     // point-block Jacobi inverse [bs*bs][n_nodes]
@@ -259,6 +265,7 @@ int fine_op_blocks(const tm_hierarchy* h);
 void launch_galerkin_elems(const tm_hierarchy* h, int fine_level, const double* child,
                            double* parent, hipStream_t s);
 void launch_stencil_assemble(const Level& L, const double* elem, hipStream_t s);
+void launch_stencil_compact(const Level& L, hipStream_t s);
 void launch_stencil_dinv(const Level& L, int point_jacobi, int* flags, hipStream_t s);
 template <typename T>
 void launch_stencil_op(const Level& L, int op, const T* x, const T* b, T* y, T omega,
