@@ -228,7 +228,7 @@ void launch_stencil_dinv(const Level& L, int point_jacobi, int* flags, hipStream
 // stored block towards this node (A is symmetric).  Neighbours outside the grid
 // have zero stored blocks (upper) or have their x masked to zero (lower); all
 // loads use clamped, in-bounds indices, with no branches.
-template <typename T, int DIM, int OP>
+template <typename T, int DIM, int OP, int G>
 __global__ __launch_bounds__(WG) void k_stencil_op(const T* __restrict__ st, int nx, int ny, int nz,
                                                    int64_t N, const T* __restrict__ x,
                                                    const T* __restrict__ b, T* __restrict__ y,
@@ -276,8 +276,8 @@ __global__ __launch_bounds__(WG) void k_stencil_op(const T* __restrict__ st, int
     }
     // neighbours in groups of G: all loads of a group are issued before its
     // arithmetic (the scheduling barrier keeps them batched), so G * (BB + DIM)
-    // loads are in flight per wave
-    constexpr int G = DIM == 3 ? 3 : 4;
+    // loads are in flight per wave (small levels: larger groups, fewer round
+    // trips, since occupancy no longer hides the latency)
 #pragma unroll
     for (int g0 = 0; g0 < NST; g0 += G) {
         T xv[G][DIM], blk[G][BB];
@@ -335,27 +335,37 @@ const double* dinv_of<double>(const Level& L) { return L.dinv64; }
 template <>
 const float* dinv_of<float>(const Level& L) { return L.dinv32; }
 
-template <typename T, int DIM>
-static void stencil_dispatch(const Level& L, int op, const T* x, const T* b, T* y, T omega,
-                             const int* done, hipStream_t s) {
+template <typename T, int DIM, int G>
+static void stencil_launch(const Level& L, int op, const T* x, const T* b, T* y, T omega, const int* done,
+                           hipStream_t s) {
     const dim3 g(grid_for(L.n_nodes)), blk(WG);
     const T* st = st_of<T>(L);
     const T* dv = dinv_of<T>(L);
     const int nz = DIM == 3 ? L.nel[2] : 0;
     switch (op) {
         case OP_APPLY:
-            hipLaunchKernelGGL((k_stencil_op<T, DIM, OP_APPLY>), g, blk, 0, s, st, L.nel[0], L.nel[1], nz,
+            hipLaunchKernelGGL((k_stencil_op<T, DIM, OP_APPLY, G>), g, blk, 0, s, st, L.nel[0], L.nel[1], nz,
                                L.n_nodes, x, b, y, dv, omega, done);
             break;
         case OP_RESID:
-            hipLaunchKernelGGL((k_stencil_op<T, DIM, OP_RESID>), g, blk, 0, s, st, L.nel[0], L.nel[1], nz,
+            hipLaunchKernelGGL((k_stencil_op<T, DIM, OP_RESID, G>), g, blk, 0, s, st, L.nel[0], L.nel[1], nz,
                                L.n_nodes, x, b, y, dv, omega, done);
             break;
         default:
-            hipLaunchKernelGGL((k_stencil_op<T, DIM, OP_SMOOTH>), g, blk, 0, s, st, L.nel[0], L.nel[1], nz,
+            hipLaunchKernelGGL((k_stencil_op<T, DIM, OP_SMOOTH, G>), g, blk, 0, s, st, L.nel[0], L.nel[1], nz,
                                L.n_nodes, x, b, y, dv, omega, done);
             break;
     }
+}
+
+template <typename T, int DIM>
+static void stencil_dispatch(const Level& L, int op, const T* x, const T* b, T* y, T omega,
+                             const int* done, hipStream_t s) {
+    // fewer workgroups than compute units: latency-bound, batch more loads
+    if (grid_for(L.n_nodes) < 256)
+        stencil_launch<T, DIM, DIM == 3 ? 9 : 9>(L, op, x, b, y, omega, done, s);
+    else
+        stencil_launch<T, DIM, DIM == 3 ? 3 : 4>(L, op, x, b, y, omega, done, s);
 }
 
 template <typename T>
@@ -375,7 +385,7 @@ template void launch_stencil_op<float>(const Level&, int, const float*, const fl
 // restriction b_c = P~^T r_f: coarse node I gathers fine nodes 2I + d, d in {-1,0,1}^dim,
 // with weight prod w(d_a), w(0) = 1, w(+-1) = 1/2; supported fine dofs contribute 0.
 // Optionally also x_c = omega D_c^-1 b_c (the first sweep of the coarse level from zero).
-template <typename T, int DIM, bool FIRST>
+template <typename T, int DIM, bool FIRST, bool MASK>
 __global__ __launch_bounds__(WG) void k_restrict(const T* __restrict__ rf, const uint8_t* __restrict__ nm,
                                                  int fnx, int fny, int fnz, int cnx, int cny, int cnz,
                                                  T* __restrict__ bc, T* __restrict__ xc,
@@ -390,23 +400,31 @@ __global__ __launch_bounds__(WG) void k_restrict(const T* __restrict__ rf, const
     const int I = (int)(node % CX);
     const int J = (int)((node / CX) % CY);
     const int K = DIM == 3 ? (int)(node / ((int64_t)CX * CY)) : 0;
+    const int64_t Nf = (int64_t)FX * FY * (DIM == 3 ? FZ : 1);
+    const auto rr = buf_rsrc(rf, Nf * DIM * sizeof(T));
+    // every load is unconditional (clamped, in-bounds index) and issued before
+    // the arithmetic; weights and masks zero what lies outside or is supported
+    constexpr int NS = DIM == 3 ? 27 : 9;
+    T v[NS][DIM], w[NS];
+    uint8_t m[NS];
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {
+        const int dx = q % 3 - 1, dy = (q / 3) % 3 - 1, dz = DIM == 3 ? q / 9 - 1 : 0;
+        const int fi = 2 * I + dx, fj = 2 * J + dy, fk = 2 * K + dz;
+        const bool in = fi >= 0 && fi < FX && fj >= 0 && fj < FY && (DIM == 2 || (fk >= 0 && fk < FZ));
+        const int gi = min(max(fi, 0), FX - 1), gj = min(max(fj, 0), FY - 1);
+        const int gk = DIM == 3 ? min(max(fk, 0), FZ - 1) : 0;
+        const uint32_t f = (uint32_t)(DIM == 3 ? (gk * FY + gj) * FX + gi : gj * FX + gi);
+        w[q] = in ? (dx ? T(0.5) : T(1)) * (dy ? T(0.5) : T(1)) * (dz ? T(0.5) : T(1)) : T(0);
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) v[q][c] = bld<T>(rr, (DIM * f + c) * (uint32_t)sizeof(T));
+        m[q] = MASK ? nm[f] : (uint8_t)0;
+    }
     T acc[DIM] = {};
 #pragma unroll
-    for (int dz = (DIM == 3 ? -1 : 0); dz <= (DIM == 3 ? 1 : 0); ++dz)
+    for (int q = 0; q < NS; ++q)
 #pragma unroll
-        for (int dy = -1; dy <= 1; ++dy)
-#pragma unroll
-            for (int dx = -1; dx <= 1; ++dx) {
-                const int fi = 2 * I + dx, fj = 2 * J + dy, fk = 2 * K + dz;
-                const bool in = fi >= 0 && fi < FX && fj >= 0 && fj < FY && (DIM == 2 || (fk >= 0 && fk < FZ));
-                const int gi = min(max(fi, 0), FX - 1), gj = min(max(fj, 0), FY - 1);
-                const int gk = DIM == 3 ? min(max(fk, 0), FZ - 1) : 0;
-                const int64_t f = DIM == 3 ? ((int64_t)gk * FY + gj) * FX + gi : (int64_t)gj * FX + gi;
-                const T w = in ? (dx ? T(0.5) : T(1)) * (dy ? T(0.5) : T(1)) * (dz ? T(0.5) : T(1)) : T(0);
-                const uint8_t m = nm ? nm[f] : 0;
-#pragma unroll
-                for (int c = 0; c < DIM; ++c) acc[c] += ((m >> c) & 1u) ? T(0) : w * rf[DIM * f + c];
-            }
+        for (int c = 0; c < DIM; ++c) acc[c] += ((m[q] >> c) & 1u) ? T(0) : w[q] * v[q][c];
 #pragma unroll
     for (int c = 0; c < DIM; ++c) bc[DIM * node + c] = acc[c];
     if (FIRST) {
@@ -420,28 +438,30 @@ __global__ __launch_bounds__(WG) void k_restrict(const T* __restrict__ rf, const
     }
 }
 
+template <typename T, int DIM, bool FIRST>
+static void restrict_dispatch(const Level& fine, const Level& coarse, const T* rf, T* bc, T* xc, T omega,
+                              const int* done, hipStream_t s) {
+    const dim3 g(grid_for(coarse.n_nodes)), blk(WG);
+    const T* dv = dinv_of<T>(coarse);
+    const int fz = DIM == 3 ? fine.nel[2] : 0, cz = DIM == 3 ? coarse.nel[2] : 0;
+    if (fine.kind == TM_LEVEL_FINE)
+        hipLaunchKernelGGL((k_restrict<T, DIM, FIRST, true>), g, blk, 0, s, rf, fine.nmask, fine.nel[0],
+                           fine.nel[1], fz, coarse.nel[0], coarse.nel[1], cz, bc, xc, dv, omega, done);
+    else
+        hipLaunchKernelGGL((k_restrict<T, DIM, FIRST, false>), g, blk, 0, s, rf, (const uint8_t*)nullptr,
+                           fine.nel[0], fine.nel[1], fz, coarse.nel[0], coarse.nel[1], cz, bc, xc, dv, omega,
+                           done);
+}
+
 template <typename T>
 void launch_restrict(const Level& fine, const Level& coarse, const T* rf, T* bc, T* xc_first,
                      T omega, const int* done, hipStream_t s) {
-    const dim3 g(grid_for(coarse.n_nodes)), blk(WG);
-    const uint8_t* nm = fine.kind == TM_LEVEL_FINE ? fine.nmask : nullptr;
-    const T* dv = dinv_of<T>(coarse);
     if (fine.dim == 3) {
-        if (xc_first)
-            hipLaunchKernelGGL((k_restrict<T, 3, true>), g, blk, 0, s, rf, nm, fine.nel[0], fine.nel[1],
-                               fine.nel[2], coarse.nel[0], coarse.nel[1], coarse.nel[2], bc, xc_first, dv,
-                               omega, done);
-        else
-            hipLaunchKernelGGL((k_restrict<T, 3, false>), g, blk, 0, s, rf, nm, fine.nel[0], fine.nel[1],
-                               fine.nel[2], coarse.nel[0], coarse.nel[1], coarse.nel[2], bc, xc_first, dv,
-                               omega, done);
+        if (xc_first) restrict_dispatch<T, 3, true>(fine, coarse, rf, bc, xc_first, omega, done, s);
+        else restrict_dispatch<T, 3, false>(fine, coarse, rf, bc, xc_first, omega, done, s);
     } else {
-        if (xc_first)
-            hipLaunchKernelGGL((k_restrict<T, 2, true>), g, blk, 0, s, rf, nm, fine.nel[0], fine.nel[1], 0,
-                               coarse.nel[0], coarse.nel[1], 0, bc, xc_first, dv, omega, done);
-        else
-            hipLaunchKernelGGL((k_restrict<T, 2, false>), g, blk, 0, s, rf, nm, fine.nel[0], fine.nel[1], 0,
-                               coarse.nel[0], coarse.nel[1], 0, bc, xc_first, dv, omega, done);
+        if (xc_first) restrict_dispatch<T, 2, true>(fine, coarse, rf, bc, xc_first, omega, done, s);
+        else restrict_dispatch<T, 2, false>(fine, coarse, rf, bc, xc_first, omega, done, s);
     }
 }
 template void launch_restrict<double>(const Level&, const Level&, const double*, double*, double*,
