@@ -52,6 +52,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip the event-timed solve")
+    ap.add_argument("--served", type=int, default=24, help="requests in the served-stream leg (0: skip)")
+    ap.add_argument("--served-designs", type=int, default=20)
     ap.add_argument("--fine-mfma", type=int, default=0, choices=[0, 1],
                     help="FP32 fine operator on the matrix cores (1) or vector FMAs (0)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -162,6 +164,43 @@ def cpu_baseline(cfg_name):
             "host": platform.processor() or platform.machine(), "host_cpus": os.cpu_count()}
 
 
+def served_leg(n_req: int, n_designs: int, seed: int = 5):
+    """The served stream (mixed 2D/3D sizes, 1-4 load cases, design updates
+    with warm starts, rtol 1e-6): first every request at t = 0 to find the
+    saturation throughput, then Poisson arrivals at 70% of that request rate;
+    latency = arrival to the request's last solve.  Densities are generated
+    before the timed runs."""
+    import dataclasses
+
+    import numpy as np
+
+    import synth
+    from paper_2001_01655_amd.serving import GpuEngine, Server, served_requests
+    reqs = served_requests(n_req, rate_per_s=1.0, n_designs=n_designs, seed=seed, rtol=1e-6)
+    for r in reqs:
+        for t in range(n_designs):
+            r.densities(t)
+    eng = GpuEngine()
+    budget = 64 << 30
+    Server(eng, budget, max_slots=8, chunk=4, rtol=1e-6).run(
+        [dataclasses.replace(r, arrival=0.0, n_designs=2) for r in reqs[:4]])          # warm-up
+    sat = Server(eng, budget, max_slots=8, chunk=4, rtol=1e-6).run(
+        [dataclasses.replace(r, arrival=0.0) for r in reqs])
+    rate = 0.7 * n_req / sat["makespan_s"]
+    arr = synth.poisson_arrivals(n_req, rate, seed)
+    res = Server(eng, budget, max_slots=8, chunk=4, rtol=1e-6).run(
+        [dataclasses.replace(r, arrival=float(a)) for r, a in zip(reqs, arr)])
+    iters = [i for o in res["outcomes"] for d in o.iters for i in d]
+    ok = all(st == 0 for o in res["outcomes"] for st in o.status)
+    return {"p50_ms": round(res["p50_ms"], 2), "p99_ms": round(res["p99_ms"], 2),
+            "solves_per_s": round(res["solves_per_s"], 1), "arrival_rate_per_s": round(rate, 3),
+            "saturation_solves_per_s": round(sat["solves_per_s"], 1), "requests": n_req,
+            "designs_per_request": n_designs, "solves": res["solves"], "all_converged": ok,
+            "mean_iters": round(float(np.mean(iters)), 2) if iters else None,
+            "max_slots": 8, "chunk": 4, "latency": "request arrival to its last solve",
+            "sizes": "2D 128x64, 2D 512x256, 3D 48^3, 3D 96x48x48; 1-4 load cases; rtol 1e-6"}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -243,6 +282,8 @@ def main():
         line["speedup_vs_fp64_pcg"] = round(value / v64, 3)
         H64.close()
     line["detail"] = detail
+    if args.served > 0:
+        line["served"] = served_leg(args.served, args.served_designs)
     if not args.no_cpu_baseline:
         cb = cpu_baseline(wl["cfg"])
         if cb:

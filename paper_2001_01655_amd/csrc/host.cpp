@@ -374,6 +374,7 @@ static void numeric_setup(tm_hierarchy* h, const double* rho, hipStream_t s) {
     std::vector<void*> tmp;
     size_t tb = 0;
     double* Ad = dalloc<double>(tmp, tb, (size_t)nc * nc);
+    double* Ls = dalloc<double>(tmp, tb, (size_t)chol_block_elems());
     TM_HIP(hipMemsetAsync(Ad, 0, (size_t)nc * nc * sizeof(double), s));
     if (C.kind == TM_LEVEL_AGGREGATION)
         launch_dense_from_bsr(C, Ad, s);
@@ -386,7 +387,7 @@ static void numeric_setup(tm_hierarchy* h, const double* rho, hipStream_t s) {
         h->ainv_cap = (size_t)nc * nc;
     }
     try {
-        launch_cholesky_inverse(Ad, h->ainv, nc, h->flags, s);
+        launch_cholesky_inverse(Ad, h->ainv, Ls, nc, h->flags, s);
         read_flags(h, s, "coarsest Cholesky");
     } catch (...) {
         TM_HIP(hipStreamSynchronize(s));

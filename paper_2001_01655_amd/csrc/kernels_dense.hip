@@ -64,36 +64,126 @@ void launch_dense_from_bsr(const Level& L, double* Ad, hipStream_t s) {
                        L.A.v64, L.A.nbr, L.bs, Ad);
 }
 
-// In-place right-looking Cholesky of a row-major SPD matrix by one workgroup;
-// a non-positive pivot raises FLAG_NOT_SPD.
-__global__ __launch_bounds__(1024) void k_cholesky(double* __restrict__ A, int64_t n, int* flags) {
+// Blocked right-looking Cholesky (blocks of CB x CB) of a row-major SPD
+// matrix, lower triangle, in place.  Step kb takes two launches:
+//  * panel: every workgroup factors the diagonal block kb in LDS (the
+//    redundant copies are identical); workgroup 0 stores the factor to a
+//    scratch block, workgroup q > 0 solves X L_kk^T = A_(kb+q),kb for its
+//    block row;
+//  * update: one workgroup per tile (i, j), kb < j <= i, of the trailing
+//    matrix, A_ij -= L_ik L_jk^T, and one more that copies L_kk into place.
+// A non-positive pivot raises FLAG_NOT_SPD (the factorisation then continues
+// with a unit pivot, so every launch still terminates normally).
+constexpr int CB = 64;
+
+__global__ __launch_bounds__(256) void k_chol_panel(double* __restrict__ A, int64_t n, int kb,
+                                                    double* __restrict__ Ls, int* flags) {
+    __shared__ double L[CB][CB];
     __shared__ int bad;
-    const int t = threadIdx.x, nt = blockDim.x;
+    const int t = threadIdx.x;
+    const int64_t k0 = (int64_t)kb * CB;
+    const int m = (int)min<int64_t>(CB, n - k0);
+    for (int q = t; q < CB * CB; q += 256) {
+        const int r = q / CB, c = q % CB;
+        L[r][c] = (r < m && c <= r) ? A[(k0 + r) * n + k0 + c] : (r == c ? 1.0 : 0.0);
+    }
     if (t == 0) bad = 0;
-    for (int64_t k = 0; k < n; ++k) {
-        __syncthreads();
+    __syncthreads();
+    for (int k = 0; k < m; ++k) {
         if (t == 0) {
-            double d = A[k * n + k];
+            double d = L[k][k];
             if (!(d > 0.0)) {
                 bad = 1;
                 d = 1.0;
             }
-            A[k * n + k] = sqrt(d);
+            L[k][k] = sqrt(d);
         }
         __syncthreads();
-        if (bad) break;
-        const double dk = A[k * n + k];
-        for (int64_t i = k + 1 + t; i < n; i += nt) A[i * n + k] /= dk;
+        const double dk = L[k][k];
+        for (int i = k + 1 + t; i < m; i += 256) L[i][k] /= dk;
         __syncthreads();
-        // trailing update of the lower triangle, all threads over (i, j) pairs
-        const int64_t m = n - k - 1;
-        for (int64_t q = t; q < m * m; q += nt) {
-            const int64_t i = k + 1 + q / m, j = k + 1 + q % m;
-            if (j <= i) A[i * n + j] -= A[i * n + k] * A[j * n + k];
+        const int mm = m - k - 1;
+        for (int q = t; q < mm * mm; q += 256) {
+            const int i = k + 1 + q / mm, j = k + 1 + q % mm;
+            if (j <= i) L[i][j] -= L[i][k] * L[j][k];
         }
+        __syncthreads();
+    }
+    if (blockIdx.x == 0) {
+        for (int q = t; q < CB * CB; q += 256) Ls[q] = L[q / CB][q % CB];
+        if (t == 0 && bad) atomicOr(flags, FLAG_NOT_SPD);
+        return;
+    }
+    // block row below: only exists when the diagonal block is full (m == CB)
+    const int64_t r0 = k0 + (int64_t)blockIdx.x * CB;
+    const int rows = (int)min<int64_t>(CB, n - r0);
+    if (t < rows) {
+        double* row = A + (r0 + t) * n + k0;
+        double x[CB];
+#pragma unroll
+        for (int c = 0; c < CB; ++c) x[c] = row[c];
+#pragma unroll
+        for (int c = 0; c < CB; ++c) {
+            double sacc = x[c];
+#pragma unroll
+            for (int j = 0; j < c; ++j) sacc -= x[j] * L[c][j];
+            x[c] = sacc / L[c][c];
+        }
+#pragma unroll
+        for (int c = 0; c < CB; ++c) row[c] = x[c];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_chol_update(double* __restrict__ A, int64_t n, int kb, int rem,
+                                                     const double* __restrict__ Ls) {
+    const int t = threadIdx.x;
+    const int64_t k0 = (int64_t)kb * CB;
+    const int ntile = rem * (rem + 1) / 2;
+    if ((int)blockIdx.x == ntile) {        // L_kk into place
+        const int m = (int)min<int64_t>(CB, n - k0);
+        for (int q = t; q < m * m; q += 256) {
+            const int r = q / m, c = q % m;
+            if (c <= r) A[(k0 + r) * n + k0 + c] = Ls[r * CB + c];
+        }
+        return;
+    }
+    int bi = 0, q = (int)blockIdx.x;
+    while (q >= bi + 1) {
+        q -= bi + 1;
+        ++bi;
+    }
+    const int bj = q;
+    const int64_t i0 = k0 + (int64_t)(1 + bi) * CB, j0 = k0 + (int64_t)(1 + bj) * CB;
+    const int ri = (int)min<int64_t>(CB, n - i0), rj = (int)min<int64_t>(CB, n - j0);
+    __shared__ double Li[CB][CB];
+    __shared__ double LjT[CB][CB];
+    for (int e = t; e < CB * CB; e += 256) {
+        const int r = e / CB, k = e % CB;
+        Li[r][k] = r < ri ? A[(i0 + r) * n + k0 + k] : 0.0;
+        LjT[k][r] = r < rj ? A[(j0 + r) * n + k0 + k] : 0.0;
     }
     __syncthreads();
-    if (t == 0 && bad) atomicOr(flags, FLAG_NOT_SPD);
+    const int tx = t % 16, ty = t / 16;
+    double acc[4][4] = {};
+    for (int k = 0; k < CB; ++k) {
+        double a[4], b[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            a[u] = Li[ty * 4 + u][k];
+            b[u] = LjT[k][tx * 4 + u];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * b[v];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int r = ty * 4 + u, c = tx * 4 + v;
+            if (r < ri && c < rj) A[(i0 + r) * n + j0 + c] -= acc[u][v];
+        }
 }
 
 // Column c of A^-1 from the factor L (lower part of Lf): solve L y = e_c, then
@@ -122,9 +212,17 @@ __global__ __launch_bounds__(256) void k_chol_inverse(const double* __restrict__
     for (int64_t i = t; i < n; i += nt) Ainv[c * n + i] = y[i];
 }
 
-void launch_cholesky_inverse(double* A, double* Ainv, int64_t n, int* flags, hipStream_t s) {
+int chol_block_elems() { return CB * CB; }
+
+void launch_cholesky_inverse(double* A, double* Ainv, double* Ls, int64_t n, int* flags, hipStream_t s) {
     if (n > 4096) fail(TM_ERR_ARG, "coarsest level too large for the dense solve (> 4096 dofs)");
-    hipLaunchKernelGGL(k_cholesky, dim3(1), dim3(1024), 0, s, A, n, flags);
+    const int nb = (int)ceil_div(n, (int64_t)CB);
+    for (int kb = 0; kb < nb; ++kb) {
+        const int rem = nb - kb - 1;
+        hipLaunchKernelGGL(k_chol_panel, dim3((unsigned)(rem + 1)), dim3(256), 0, s, A, n, kb, Ls, flags);
+        hipLaunchKernelGGL(k_chol_update, dim3((unsigned)(rem * (rem + 1) / 2 + 1)), dim3(256), 0, s, A, n, kb,
+                           rem, (const double*)Ls);
+    }
     hipLaunchKernelGGL(k_chol_inverse, dim3((unsigned)n), dim3(256), (size_t)n * sizeof(double), s,
                        (const double*)A, n, Ainv);
 }

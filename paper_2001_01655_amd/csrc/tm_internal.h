@@ -281,7 +281,8 @@ void launch_first_smooth(const Level& L, const T* b, T* x, T omega, const int* d
 // dense coarsest level (kernels_dense.hip)
 void launch_dense_from_stencil(const Level& L, double* Ad, hipStream_t s);
 void launch_dense_from_bsr(const Level& L, double* Ad, hipStream_t s);
-void launch_cholesky_inverse(double* A, double* Ainv, int64_t n, int* flags, hipStream_t s);
+int chol_block_elems();  // scratch doubles the blocked factorisation needs
+void launch_cholesky_inverse(double* A, double* Ainv, double* Ls, int64_t n, int* flags, hipStream_t s);
 template <typename T>
 void launch_dense_solve(const double* Ainv, int64_t n, const T* b, T* x, const int* done,
                         hipStream_t s);
