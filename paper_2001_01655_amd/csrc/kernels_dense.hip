@@ -78,8 +78,8 @@ constexpr int CB = 64;
 
 __global__ __launch_bounds__(256) void k_chol_panel(double* __restrict__ A, int64_t n, int kb,
                                                     double* __restrict__ Ls, int* flags) {
-    __shared__ double L[CB][CB];
-    __shared__ int bad;
+    __shared__ double L[CB][CB + 1];
+    __shared__ double piv[CB];
     const int t = threadIdx.x;
     const int64_t k0 = (int64_t)kb * CB;
     const int m = (int)min<int64_t>(CB, n - k0);
@@ -87,34 +87,41 @@ __global__ __launch_bounds__(256) void k_chol_panel(double* __restrict__ A, int6
         const int r = q / CB, c = q % CB;
         L[r][c] = (r < m && c <= r) ? A[(k0 + r) * n + k0 + c] : (r == c ? 1.0 : 0.0);
     }
-    if (t == 0) bad = 0;
     __syncthreads();
+    // unscaled right-looking elimination, one barrier per column:
+    // a_ij -= a_ik a_jk / a_kk for k < j <= i; the pivots are kept and the
+    // columns scaled by 1 / sqrt(a_kk) at the end
+    const int tx = t % 16, ty = t / 16;
     for (int k = 0; k < m; ++k) {
-        if (t == 0) {
-            double d = L[k][k];
-            if (!(d > 0.0)) {
-                bad = 1;
-                d = 1.0;
-            }
-            L[k][k] = sqrt(d);
-        }
-        __syncthreads();
-        const double dk = L[k][k];
-        for (int i = k + 1 + t; i < m; i += 256) L[i][k] /= dk;
-        __syncthreads();
-        const int mm = m - k - 1;
-        for (int q = t; q < mm * mm; q += 256) {
-            const int i = k + 1 + q / mm, j = k + 1 + q % mm;
-            if (j <= i) L[i][j] -= L[i][k] * L[j][k];
+        double akk = L[k][k];
+        if (!(akk > 0.0)) akk = 1.0;
+        if (t == 0) piv[k] = L[k][k];
+        const double inv = 1.0 / akk;
+        for (int i = k + 1 + ty; i < m; i += 16) {
+            const double lik = L[i][k] * inv;
+            for (int j = k + 1 + tx; j <= i; j += 16) L[i][j] -= lik * L[j][k];
         }
         __syncthreads();
     }
+    if (t == 0) {
+        bool bad = false;
+        for (int k = 0; k < m; ++k) bad = bad || !(piv[k] > 0.0);
+        if (bad) atomicOr(flags, FLAG_NOT_SPD);
+    }
+    for (int q = t; q < CB * CB; q += 256) {
+        const int r = q / CB, c = q % CB;
+        if (c < m && c <= r) {
+            const double d = piv[c] > 0.0 ? sqrt(piv[c]) : 1.0;
+            L[r][c] = r == c ? d : L[r][c] / d;
+        }
+    }
+    __syncthreads();
     if (blockIdx.x == 0) {
         for (int q = t; q < CB * CB; q += 256) Ls[q] = L[q / CB][q % CB];
-        if (t == 0 && bad) atomicOr(flags, FLAG_NOT_SPD);
         return;
     }
-    // block row below: only exists when the diagonal block is full (m == CB)
+    // block row below: only exists when the diagonal block is full (m == CB);
+    // solve X L_kk^T = A_(kb+q),kb row by row
     const int64_t r0 = k0 + (int64_t)blockIdx.x * CB;
     const int rows = (int)min<int64_t>(CB, n - r0);
     if (t < rows) {
