@@ -218,3 +218,20 @@ def rigid_body_modes(coords: np.ndarray) -> np.ndarray:
     B[:, 0, 5] = -y
     B[:, 1, 5] = x
     return B.reshape(3 * n, 6)
+
+
+# ------------------------------------------------------------- sensitivities
+def compliance_sensitivity(nel, rho: np.ndarray, p: float, E0: float, Emin: float, KE: np.ndarray,
+                           U: np.ndarray) -> np.ndarray:
+    """d/d rho_e of sum_k c_k, c_k = f_k^T u_k, for the modified SIMP law (Sec. 2):
+    compliance is self-adjoint, so dc_k/d rho_e = -u_k,e^T (dK/d rho_e) u_k,e with
+    dK/d rho_e = p rho_e^(p-1) (E0 - Emin) L_e^T KE L_e.  U holds the solutions
+    (n_rhs, n_dof), zero on supported dofs."""
+    ed = element_dofs(nel)
+    dE = p * np.power(rho, p - 1.0) * (E0 - Emin)
+    U = np.atleast_2d(U)
+    q = np.zeros(ed.shape[0])
+    for u in U:
+        ue = u[ed]
+        q += np.einsum("ei,ij,ej->e", ue, KE, ue)
+    return -dE * q

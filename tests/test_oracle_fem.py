@@ -160,3 +160,43 @@ def test_dirichlet_rows_and_matfree():
     y1 = Kt @ x
     y2 = fem.apply_matfree(p.nel, E, KE, p.fixed, x)
     assert np.max(np.abs(y1 - y2)) <= 1e-14 * np.max(np.abs(y1))
+
+
+def _compliance(nel, rho, fixed, f, p=3.0, E0=1.0, Emin=1e-9, nu=0.3):
+    import scipy.sparse.linalg as spla
+    KE = fem.element_stiffness(len(nel), nu)
+    K = fem.apply_dirichlet(fem.assemble(nel, fem.simp(rho, p, E0, Emin), KE), fixed)
+    fm = f * fem.free_mask(len(f), fixed)
+    u = spla.spsolve(K.tocsc(), fm)
+    return fm @ u, u, KE
+
+
+@pytest.mark.parametrize("nel", [(6, 4), (3, 2, 2)])
+def test_sensitivity_matches_finite_differences(nel):
+    """Central differences of c(rho) = f^T K(rho)^-1 f pin the analytic
+    sensitivity (Sec. 2) element by element."""
+    import synth
+    p = synth.small_case(len(nel), nel, seed=31, n_rhs=1)
+    rho = 0.3 + 0.6 * np.random.default_rng(4).uniform(size=int(np.prod(nel)))
+    c, u, KE = _compliance(nel, rho, p.fixed, p.loads[0])
+    dc = fem.compliance_sensitivity(nel, rho, 3.0, 1.0, 1e-9, KE, u)
+    h = 1e-6
+    for e in range(len(rho)):
+        rp, rm = rho.copy(), rho.copy()
+        rp[e] += h
+        rm[e] -= h
+        fd = (_compliance(nel, rp, p.fixed, p.loads[0])[0] - _compliance(nel, rm, p.fixed, p.loads[0])[0]) / (2 * h)
+        assert abs(fd - dc[e]) <= 1e-6 * np.max(np.abs(dc)), e
+
+
+def test_sensitivity_homogeneity():
+    """With Emin = 0, K(t rho) = t^p K(rho), so c(t rho) = t^-p c and Euler's
+    identity gives sum_e rho_e dc/d rho_e = -p c exactly."""
+    import synth
+    nel = (8, 4)
+    p = synth.small_case(2, nel, seed=32, n_rhs=1)
+    rho = 0.2 + 0.8 * np.random.default_rng(5).uniform(size=32)
+    c, u, KE = _compliance(nel, rho, p.fixed, p.loads[0], p=3.0, Emin=0.0)
+    dc = fem.compliance_sensitivity(nel, rho, 3.0, 1.0, 0.0, KE, u)
+    assert abs(rho @ dc + 3.0 * c) <= 1e-10 * abs(c)
+    assert np.all(dc <= 0.0)
