@@ -125,6 +125,17 @@ tm_status tm_solve(tm_hierarchy* h, int32_t n_rhs, const double* f_dev, double r
                    int32_t use_u0, double* u_dev, int32_t* iters, double* compliance,
                    double* relres, void* stream);
 
+/* Design sensitivity of the summed compliances (Sec. 2; compliance is
+ * self-adjoint, so no second solve is needed):
+ *   dc_e = -p rho_e^(p-1) (E0 - Emin) sum_k u_k,e^T KE u_k,e
+ * for the densities of the current design (tm_setup / tm_update_density).
+ * u_dev holds n_rhs solutions of n_dof FP64 values one after the other (as
+ * returned by tm_solve); dc_dev receives n_el FP64 values in element order.
+ * Both are device buffers owned by the caller.  Enqueued on `stream`; the call
+ * does not wait for it.  TM_ERR_ARG for a NULL handle or buffer or n_rhs < 1. */
+tm_status tm_compliance_sensitivity(tm_hierarchy* h, int32_t n_rhs, const double* u_dev, double* dc_dev,
+                                    void* stream);
+
 /* Iteration-level control for a scheduler (continuous batching).
  * begin:   copies f, sets up the start vector on `stream` and returns a state
  *          bound to (h, stream, u_dev); u_dev must stay valid until end.

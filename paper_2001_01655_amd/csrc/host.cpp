@@ -349,7 +349,7 @@ void numeric_sa_levels(tm_hierarchy* h, hipStream_t s);
 static void numeric_setup(tm_hierarchy* h, const double* rho, hipStream_t s) {
     TM_HIP(hipMemsetAsync(h->flags, 0, sizeof(int), s));
     Level& F = h->lv[0];
-    launch_simp(rho, h->n_el, h->mat.p, h->mat.E0, h->mat.Emin, F.E64, F.E32, h->flags, s);
+    launch_simp(rho, h->n_el, h->mat.p, h->mat.E0, h->mat.Emin, F.E64, F.E32, h->rho64, h->flags, s);
     const int point = h->opt.smoother == TM_SMOOTH_POINT_JACOBI;
     launch_fine_dinv(F, h->KE64, point, h->flags, s);
     read_flags(h, s, "fine diagonal");
@@ -951,6 +951,7 @@ tm_status tm_setup(const tm_mesh* mesh, const tm_material* mat, const double* rh
         else ke_class_values(KE_CLS2, KE, h);
         child_weights(dim, Q);
         h->KE64 = halloc<double>(h, KE.size());
+        h->rho64 = halloc<double>(h, (size_t)h->n_el);
         // A operand of the matrix-core operator: register q, lane L holds row
         // L mod 4 (row 3 = 0) of KE column k = 16 q + L/4, k = 24 a + col for
         // element corner slot a; entries rebuilt from the class values
@@ -1000,6 +1001,17 @@ tm_status tm_update_density(tm_hierarchy* h, const double* rho_dev, void* stream
 void tm_destroy(tm_hierarchy* h) { destroy_impl(h); }
 
 int32_t tm_num_levels(const tm_hierarchy* h) { return h ? (int32_t)h->lv.size() : 0; }
+
+tm_status tm_compliance_sensitivity(tm_hierarchy* h, int32_t n_rhs, const double* u_dev, double* dc_dev,
+                                    void* stream) {
+    return guarded([&] {
+        if (!h) fail(TM_ERR_ARG, "hierarchy is NULL");
+        if (n_rhs < 1) fail(TM_ERR_ARG, "n_rhs must be >= 1");
+        if (!u_dev || !dc_dev) fail(TM_ERR_ARG, "u and dc must be device buffers");
+        launch_sensitivity(h, n_rhs, u_dev, dc_dev, S(stream));
+        TM_HIP(hipGetLastError());
+    });
+}
 
 tm_status tm_hierarchy_bytes(const tm_hierarchy* h, size_t* bytes) {
     return guarded([&] {

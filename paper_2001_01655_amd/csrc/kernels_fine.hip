@@ -7,6 +7,7 @@
 // slice of an element product per element per node, i.e. exactly the flops
 // of the element-by-element product, without redundancy.
 #include <type_traits>
+#include <utility>
 
 #include "tm_device.h"
 
@@ -14,7 +15,8 @@ namespace tmi {
 
 // ------------------------------------------------------------ SIMP
 __global__ void k_simp(const double* __restrict__ rho, int64_t n, double p, double E0, double Emin,
-                       double* __restrict__ E64, float* __restrict__ E32, int* flags) {
+                       double* __restrict__ E64, float* __restrict__ E32, double* __restrict__ rho64,
+                       int* flags) {
     int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= n) return;
     double r = rho[e];
@@ -25,12 +27,81 @@ __global__ void k_simp(const double* __restrict__ rho, int64_t n, double p, doub
     double E = Emin + (E0 - Emin) * pow(r, p);
     E64[e] = E;
     E32[e] = (float)E;
+    rho64[e] = r;
 }
 
 void launch_simp(const double* rho, int64_t n_el, double p, double E0, double Emin, double* E64,
-                 float* E32, int* flags, hipStream_t s) {
+                 float* E32, double* rho64, int* flags, hipStream_t s) {
     hipLaunchKernelGGL(k_simp, dim3(grid_for(n_el)), dim3(WG), 0, s, rho, n_el, p, E0, Emin, E64,
-                       E32, flags);
+                       E32, rho64, flags);
+}
+
+// ------------------------------------------------------------ sensitivities
+// dc_e = -p rho_e^(p-1) (E0 - Emin) sum_k u_k,e^T KE u_k,e: the derivative of
+// the summed compliances for the modified SIMP law (compliance is
+// self-adjoint, Sec. 2).  One thread per element; KE enters as its class
+// values with compile-time signs, u_e is gathered from the element's corners.
+template <int DIM, int R, int S>
+__device__ __forceinline__ double ke_entry(const KeVals<double>& kc) {
+    constexpr int sg = DIM == 3 ? KE_CLS3.sgn[R][S] : KE_CLS2.sgn[R][S];
+    constexpr int cl = DIM == 3 ? KE_CLS3.cls[R][S] : KE_CLS2.cls[R][S];
+    if constexpr (sg > 0) return kc.k[cl];
+    else if constexpr (sg < 0) return -kc.k[cl];
+    else return 0.0;
+}
+template <int DIM, int R, int... S>
+__device__ __forceinline__ double ke_row_dot(const KeVals<double>& kc, const double* ue,
+                                             std::integer_sequence<int, S...>) {
+    double t = 0.0;
+    ((t += ke_entry<DIM, R, S>(kc) * ue[S]), ...);
+    return t;
+}
+template <int DIM, int... R>
+__device__ __forceinline__ double ke_quad(const KeVals<double>& kc, const double* ue,
+                                          std::integer_sequence<int, R...>) {
+    constexpr int ND = DIM << DIM;
+    double q = 0.0;
+    ((q += ue[R] * ke_row_dot<DIM, R>(kc, ue, std::make_integer_sequence<int, ND>{})), ...);
+    return q;
+}
+
+template <int DIM>
+__global__ __launch_bounds__(WG) void k_sensitivity(const double* __restrict__ rho, const KeVals<double> kc,
+                                                    int nx, int ny, int nz, int64_t n_el, int n_rhs,
+                                                    const double* __restrict__ u, int64_t n_dof, double p,
+                                                    double dE, double* __restrict__ dc) {
+    constexpr int NPE = 1 << DIM, ND = DIM * NPE;
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n_el) return;
+    const int ex = (int)(e % nx), ey = (int)((e / nx) % ny), ez = DIM == 3 ? (int)(e / ((int64_t)nx * ny)) : 0;
+    const int64_t NX = nx + 1, NY = ny + 1;
+    int64_t nd[NPE];
+#pragma unroll
+    for (int a = 0; a < NPE; ++a)
+        nd[a] = (ex + corner_coord(a, 0)) + NX * ((ey + corner_coord(a, 1)) + (DIM == 3 ? NY * (ez + corner_coord(a, 2)) : 0));
+    double q = 0.0;
+    for (int k = 0; k < n_rhs; ++k) {
+        const double* uk = u + (int64_t)k * n_dof;
+        double ue[ND];
+#pragma unroll
+        for (int a = 0; a < NPE; ++a)
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) ue[DIM * a + c] = uk[DIM * nd[a] + c];
+        q += ke_quad<DIM>(kc, ue, std::make_integer_sequence<int, ND>{});
+    }
+    const double r = rho[e];
+    dc[e] = -p * (p == 1.0 ? 1.0 : pow(r, p - 1.0)) * dE * q;
+}
+
+void launch_sensitivity(const tm_hierarchy* h, int n_rhs, const double* u, double* dc, hipStream_t s) {
+    const Level& L = h->lv[0];
+    const double dE = h->mat.E0 - h->mat.Emin;
+    if (L.dim == 3)
+        hipLaunchKernelGGL(k_sensitivity<3>, dim3(grid_for(h->n_el)), dim3(WG), 0, s, h->rho64, h->kc64, L.nel[0],
+                           L.nel[1], L.nel[2], h->n_el, n_rhs, u, h->n_dof, h->mat.p, dE, dc);
+    else
+        hipLaunchKernelGGL(k_sensitivity<2>, dim3(grid_for(h->n_el)), dim3(WG), 0, s, h->rho64, h->kc64, L.nel[0],
+                           L.nel[1], 1, h->n_el, n_rhs, u, h->n_dof, h->mat.p, dE, dc);
 }
 
 // ------------------------------------------------------------ fine diagonal

@@ -197,6 +197,7 @@ struct tm_hierarchy {
     std::vector<int64_t> fixed;
     std::vector<tmi::Level> lv;
     double* KE64 = nullptr;        // element stiffness for E = 1 (device)
+    double* rho64 = nullptr;       // densities of the current design (device)
     float* KA32 = nullptr;         // 3D: KE as the broadcast A operand of the matrix-core fine operator
     tmi::KeVals<double> kc64{};       // KE symmetry-class values (fine operator arguments)
     tmi::KeVals<float> kc32{};
@@ -253,7 +254,8 @@ void delete_cached_state(tm_hierarchy* h);
 // fine level (kernels_fine.hip)
 enum { OP_APPLY = 0, OP_RESID = 1, OP_SMOOTH = 2, OP_QDOT = 3 };
 void launch_simp(const double* rho, int64_t n_el, double p, double E0, double Emin, double* E64,
-                 float* E32, int* flags, hipStream_t s);
+                 float* E32, double* rho64, int* flags, hipStream_t s);
+void launch_sensitivity(const tm_hierarchy* h, int n_rhs, const double* u, double* dc, hipStream_t s);
 void launch_fine_dinv(const Level& L, const double* KE64, int point_jacobi, int* flags,
                       hipStream_t s);
 template <typename T>

@@ -167,6 +167,18 @@ class Hierarchy:
         check(LIB.tm_export_dinv(self._h, level, d.ctypes.data), "tm_export_dinv")
         return d
 
+    def compliance_sensitivity(self, u, stream=None) -> torch.Tensor:
+        """d(sum_k f_k^T u_k)/d rho_e for the solutions u (n_dof or (n_rhs, n_dof))."""
+        u_d = _dev(u)
+        n_rhs = u_d.numel() // self.n_dof
+        if n_rhs * self.n_dof != u_d.numel() or n_rhs < 1:
+            raise ValueError("u must hold whole solution vectors")
+        dc = torch.empty(self.n_el, dtype=torch.float64, device=u_d.device)
+        check(LIB.tm_compliance_sensitivity(self.handle, n_rhs, C.c_void_p(u_d.data_ptr()),
+                                            C.c_void_p(dc.data_ptr()), _stream_ptr(stream)),
+              "tm_compliance_sensitivity")
+        return dc
+
     def device_bytes(self) -> int:
         b = C.c_size_t()
         check(LIB.tm_hierarchy_bytes(self._h, C.byref(b)), "tm_hierarchy_bytes")
