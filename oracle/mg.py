@@ -192,6 +192,8 @@ class Hierarchy:
     kinds: List[str] = field(default_factory=list)   # 'geo' or 'sa' per transfer
     aggregates: List[Optional[np.ndarray]] = field(default_factory=list)
     info: dict = field(default_factory=dict)
+    smoother: str = "jacobi"               # 'jacobi' or 'chebyshev'
+    cheb: List[Optional[tuple]] = field(default_factory=list)   # (theta, delta) per level
 
     @property
     def L(self) -> int:
@@ -200,7 +202,8 @@ class Hierarchy:
 
 def build_geometric(nel, E: np.ndarray, KE: np.ndarray, fixed: np.ndarray, L: int,
                     omega: float = 0.5, nu_pre: int = 1, nu_post: int = 1,
-                    point_jacobi: bool = False) -> Hierarchy:
+                    point_jacobi: bool = False, smoother: str = "jacobi",
+                    cheb_lower: float = 0.1) -> Hierarchy:
     """Pure geometric hierarchy with L levels (fine grid included)."""
     dim = len(nel)
     K = fem.assemble(nel, E, KE)
@@ -214,17 +217,81 @@ def build_geometric(nel, E: np.ndarray, KE: np.ndarray, fixed: np.ndarray, L: in
         Ps.append(P)
         As.append(galerkin(P, As[-1]))
         cur = [n // 2 for n in cur]
-    return finish(As, Ps, [dim] * L, omega, nu_pre, nu_post, point_jacobi, ["geo"] * (L - 1))
+    return finish(As, Ps, [dim] * L, omega, nu_pre, nu_post, point_jacobi, ["geo"] * (L - 1),
+                  smoother=smoother, cheb_lower=cheb_lower, fixed=fixed)
 
 
 def finish(As, Ps, bss, omega, nu_pre, nu_post, point_jacobi=False, kinds=None,
-           aggregates=None) -> Hierarchy:
+           aggregates=None, smoother="jacobi", cheb_lower=0.1, fixed=None) -> Hierarchy:
     Dinv = [point_diag_inverse(A) if point_jacobi else block_diag_inverse(A, b)
             for A, b in zip(As, bss)]
     Ac = As[-1].toarray()
     chol = sla.cho_factor(Ac, lower=True)
+    cheb = [None] * len(As)
+    if smoother == "chebyshev":
+        for l in range(len(As) - 1):
+            mask = None
+            if l == 0 and fixed is not None:
+                mask = fem.free_mask(As[0].shape[0], fixed)
+            lam = power_lmax(As[l], Dinv[l], mask)
+            a, b = cheb_lower * lam, 1.1 * lam
+            cheb[l] = ((b + a) / 2.0, (b - a) / 2.0)
     return Hierarchy(As, Ps, Dinv, list(bss), omega, nu_pre, nu_post, chol,
-                     kinds or [], aggregates or [None] * len(As))
+                     kinds or [], aggregates or [None] * len(As), smoother=smoother, cheb=cheb)
+
+
+# ----------------------------------------------------------- Chebyshev smoothing
+def _fmix32(x: np.ndarray) -> np.ndarray:
+    """MurmurHash3's 32-bit finaliser (a published bijection of uint32)."""
+    x = np.asarray(x, dtype=np.uint64) & 0xFFFFFFFF
+    x ^= x >> 16
+    x = (x * 0x85EBCA6B) & 0xFFFFFFFF
+    x ^= x >> 13
+    x = (x * 0xC2B2AE35) & 0xFFFFFFFF
+    x ^= x >> 16
+    return x
+
+
+def power_start(n: int) -> np.ndarray:
+    """Deterministic start vector: v_i = 1 + (fmix32(i) mod 2^16) / 2^16."""
+    return 1.0 + (_fmix32(np.arange(n)) & 0xFFFF).astype(np.float64) / 65536.0
+
+
+def power_lmax(A: sp.csr_matrix, Dinv: sp.csr_matrix, mask: Optional[np.ndarray] = None,
+               iters: int = 12) -> float:
+    """Estimate of the largest eigenvalue of D^-1 A by `iters` power steps from
+    power_start (zero on supported dofs when a mask is given):
+    lambda = ||D^-1 A v|| / ||v||, v <- D^-1 A v / ||D^-1 A v||."""
+    v = power_start(A.shape[0])
+    if mask is not None:
+        v = v * mask
+    lam = 0.0
+    for _ in range(iters):
+        z = Dinv @ (A @ v)
+        nz, nv = np.linalg.norm(z), np.linalg.norm(v)
+        lam = nz / nv
+        v = z / nz
+    return float(lam)
+
+
+def chebyshev_smooth(A, Dinv, b, x, theta: float, delta: float, nu: int) -> np.ndarray:
+    """nu steps of Chebyshev iteration for D^-1 A on the interval
+    [theta - delta, theta + delta] (three-term recurrence):
+    d_0 = D^-1 r_0 / theta, rho_0 = delta / theta;
+    rho_k = 1 / (2 theta / delta - rho_{k-1}),
+    d_k = rho_k rho_{k-1} d_{k-1} + (2 rho_k / delta) D^-1 r_k;  x <- x + d_k.
+    The residual after nu steps is T_nu((theta - D^-1 A) / delta) / T_nu(theta / delta)
+    applied to the initial one."""
+    sigma = theta / delta
+    rho = 1.0 / sigma
+    d = (Dinv @ (b - A @ x)) / theta
+    x = x + d
+    for _ in range(1, nu):
+        rho_new = 1.0 / (2.0 * sigma - rho)
+        d = rho_new * rho * d + (2.0 * rho_new / delta) * (Dinv @ (b - A @ x))
+        x = x + d
+        rho = rho_new
+    return x
 
 
 # ----------------------------------------------------------- V-cycle
@@ -236,12 +303,19 @@ def vcycle(H: Hierarchy, b: np.ndarray, level: int = 0) -> np.ndarray:
         return sla.cho_solve(H.chol, b)
     A, Dinv, w = H.A[level], H.Dinv[level], H.omega
     x = np.zeros_like(b)
-    for _ in range(H.nu_pre):
-        x = x + w * (Dinv @ (b - A @ x))
+    if H.smoother == "chebyshev":
+        th, de = H.cheb[level]
+        x = chebyshev_smooth(A, Dinv, b, x, th, de, H.nu_pre)
+    else:
+        for _ in range(H.nu_pre):
+            x = x + w * (Dinv @ (b - A @ x))
     bc = H.P[level].T @ (b - A @ x)
     x = x + H.P[level] @ vcycle(H, bc, level + 1)
-    for _ in range(H.nu_post):
-        x = x + w * (Dinv @ (b - A @ x))
+    if H.smoother == "chebyshev":
+        x = chebyshev_smooth(A, Dinv, b, x, th, de, H.nu_post)
+    else:
+        for _ in range(H.nu_post):
+            x = x + w * (Dinv @ (b - A @ x))
     return x
 
 

@@ -162,7 +162,7 @@ def smoothed_prolongator(A: sp.csr_matrix, T: sp.csr_matrix, bs: int) -> sp.csr_
 # ------------------------------------------------------------ hybrid
 def build_hybrid(nel, E, KE, fixed, n_geometric: int, max_coarse: int = 1000,
                  beta: float = 0.003, omega: float = 0.5, nu_pre: int = 1, nu_post: int = 1,
-                 h: float = 1.0) -> mg.Hierarchy:
+                 h: float = 1.0, smoother: str = "jacobi", cheb_lower: float = 0.1) -> mg.Hierarchy:
     """n_geometric levels (fine grid included) of geometric coarsening, then
     smoothed aggregation until the level has fewer than max_coarse dofs."""
     dim = len(nel)
@@ -189,4 +189,5 @@ def build_hybrid(nel, E, KE, fixed, n_geometric: int, max_coarse: int = 1000,
         bs = Bcand.shape[1]
         bss.append(bs)
         A, Bcand = Ac, Bc
-    return mg.finish(As, Ps, bss, omega, nu_pre, nu_post, False, kinds, aggs)
+    return mg.finish(As, Ps, bss, omega, nu_pre, nu_post, False, kinds, aggs, smoother=smoother,
+                     cheb_lower=cheb_lower, fixed=fixed)

@@ -139,3 +139,56 @@ def test_rtol_1e8_compliance_close_to_exact():
     assert r.converged and r.relres <= 1e-8
     c_ref = p.loads[0] @ ud
     assert abs(r.compliance - c_ref) <= 1e-9 * abs(c_ref)
+
+
+# ------------------------------------------------------------- Chebyshev smoothing
+def test_chebyshev_residual_polynomial():
+    """On A = diag(lam), D = I, b = 1, x0 = 0 the residual after nu steps is the
+    scaled Chebyshev polynomial T_nu((theta - lam)/delta) / T_nu(theta/delta)."""
+    from numpy.polynomial import chebyshev as C
+    lam = np.linspace(0.05, 2.2, 40)
+    A = sp.diags(lam).tocsr()
+    I = sp.identity(40, format="csr")
+    b = np.ones(40)
+    theta, delta = 1.2, 0.9
+    for nu in (1, 2, 3, 5):
+        x = mg.chebyshev_smooth(A, I, b, np.zeros(40), theta, delta, nu)
+        Tn = np.zeros(nu + 1)
+        Tn[nu] = 1.0
+        expect = C.chebval((theta - lam) / delta, Tn) / C.chebval(theta / delta, Tn)
+        np.testing.assert_allclose(b - A @ x, expect, rtol=1e-12, atol=1e-14)
+
+
+def test_power_estimate_converges_to_lmax():
+    lam = np.array([1, 2, 3, 4, 5, 6, 7, 8, 9, 20.0])
+    A = sp.diags(lam).tocsr()
+    est = mg.power_lmax(A, sp.identity(10, format="csr"))
+    assert est <= 20.0 + 1e-12 and est >= 20.0 * (1 - 1e-6)
+    # start vector values lie in [1, 2) and follow the published hash
+    v = mg.power_start(5)
+    assert np.all((v >= 1.0) & (v < 2.0))
+    assert mg._fmix32(np.array([0]))[0] == 0 and mg._fmix32(np.array([1]))[0] == 0x514E28B7
+
+
+@pytest.mark.parametrize("nu", [2, 3])
+def test_chebyshev_vcycle_spd_and_mbb(nu):
+    """The Chebyshev-smoothed V-cycle is a symmetric positive definite
+    preconditioner and MG-PCG with it reaches the dense solution."""
+    import synth
+    p = synth.mbb_2d(False)
+    KE = fem.element_stiffness(2, p.nu)
+    E = fem.simp(p.rho, p.p, p.E0, p.Emin)
+    H = mg.build_geometric(p.nel, E, KE, p.fixed, 3, nu_pre=nu, nu_post=nu, smoother="chebyshev")
+    assert all(c is not None for c in H.cheb[:-1])
+    n = H.A[0].shape[0]
+    m = fem.free_mask(n, p.fixed)
+    rng = np.random.default_rng(8)
+    X = rng.standard_normal((n, 6)) * m[:, None]
+    V = np.column_stack([mg.vcycle(H, X[:, k]) for k in range(6)])
+    G = X.T @ V
+    assert np.max(np.abs(G - G.T)) <= 1e-10 * np.max(np.abs(G))
+    assert np.all(np.linalg.eigvalsh(0.5 * (G + G.T)) > 0)
+    ud = mg.dense_solve(H.A[0], p.loads[0])
+    r = mg.mg_pcg(H, p.loads[0], 1e-10)
+    assert r.converged
+    assert np.linalg.norm(r.u - ud) <= 1e-8 * np.linalg.norm(ud)
