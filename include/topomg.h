@@ -89,6 +89,8 @@ typedef struct {
                               (v_mfma_f32_4x4x1, KE broadcast from 12 registers); 0 (default):
                               vector FMAs with KE symmetry-class values in scalar registers.
                               Same operator either way; only the rounding order differs      */
+    double  cheb_lower;    /* Chebyshev smoothing interval [cheb_lower, 1.1] x lambda, lambda =
+                              power estimate of the largest eigenvalue of D^-1 A (0.1)        */
 } tm_options;
 
 typedef struct tm_hierarchy tm_hierarchy;       /* opaque */

@@ -233,8 +233,11 @@ static void check_opts(const tm_options* o) {
     if (o->n_geometric < 0 || o->n_geometric > 24) fail(TM_ERR_ARG, "n_geometric out of range");
     if (o->n_geometric == 1) fail(TM_ERR_ARG, "aggregation needs an assembled level: n_geometric >= 2");
     if (o->max_coarse < 1) fail(TM_ERR_ARG, "max_coarse must be >= 1");
-    if (o->smoother != TM_SMOOTH_BLOCK_JACOBI && o->smoother != TM_SMOOTH_POINT_JACOBI)
-        fail(TM_ERR_ARG, "smoother not supported");
+    if (o->smoother != TM_SMOOTH_BLOCK_JACOBI && o->smoother != TM_SMOOTH_POINT_JACOBI &&
+        o->smoother != TM_SMOOTH_CHEBYSHEV)
+        fail(TM_ERR_ARG, "smoother must be TM_SMOOTH_BLOCK_JACOBI, TM_SMOOTH_POINT_JACOBI or TM_SMOOTH_CHEBYSHEV");
+    if (o->smoother == TM_SMOOTH_CHEBYSHEV && !(o->cheb_lower > 0.0 && o->cheb_lower < 1.0))
+        fail(TM_ERR_ARG, "cheb_lower must be in (0, 1)");
     if (o->nu_pre < 1 || o->nu_post < 1 || o->nu_pre > 16 || o->nu_post > 16)
         fail(TM_ERR_ARG, "nu_pre / nu_post must be in 1..16");
     if (!(o->omega > 0.0 && o->omega < 2.0)) fail(TM_ERR_ARG, "omega must be in (0, 2)");
@@ -346,6 +349,8 @@ static void read_flags(tm_hierarchy* h, hipStream_t s, const char* phase) {
 void build_sa_levels(tm_hierarchy* h, hipStream_t s);      // kernels_sa / host_sa
 void numeric_sa_levels(tm_hierarchy* h, hipStream_t s);
 
+static double power_lmax(tm_hierarchy* h, int l, hipStream_t s);
+
 static void numeric_setup(tm_hierarchy* h, const double* rho, hipStream_t s) {
     TM_HIP(hipMemsetAsync(h->flags, 0, sizeof(int), s));
     Level& F = h->lv[0];
@@ -367,6 +372,16 @@ static void numeric_setup(tm_hierarchy* h, const double* rho, hipStream_t s) {
         prev = cur;
     }
     if (h->sa) numeric_sa_levels(h, s);
+    if (h->opt.smoother == TM_SMOOTH_CHEBYSHEV) {
+        // interval of the Chebyshev smoother per level: [lower, 1.1] x lambda,
+        // lambda from 12 power steps on D^-1 A (FP64)
+        for (int l = 0; l + 1 < (int)h->lv.size(); ++l) {
+            const double lam = power_lmax(h, l, s);
+            const double a = h->opt.cheb_lower * lam, b = 1.1 * lam;
+            h->lv[l].cheb_theta = 0.5 * (b + a);
+            h->lv[l].cheb_delta = 0.5 * (b - a);
+        }
+    }
     // coarsest operator: dense FP64, Cholesky, explicit inverse
     Level& C = h->lv.back();
     const int64_t nc = C.n;
@@ -424,22 +439,60 @@ static void timed_end(tm_hierarchy* h, int cls, hipStream_t s, hipEvent_t e0) {
 
 template <typename T>
 static void level_op(tm_hierarchy* h, int l, int op, const T* x, const T* b, T* y, const int* done,
-                     hipStream_t s) {
+                     hipStream_t s, const ChebArgs& ch = ChebArgs{}) {
     Level& L = h->lv[l];
     const T w = (T)h->opt.omega;
     hipEvent_t e0 = nullptr;
     if (L.kind == TM_LEVEL_FINE) {
         timed_begin(h, 1, s, &e0);
-        launch_fine_op<T>(h, op, false, x, b, y, w, done, nullptr, s);
+        launch_fine_op<T>(h, op, false, x, b, y, w, done, nullptr, s, ch);
         timed_end(h, 1, s, e0);
     } else if (L.kind == TM_LEVEL_GEOMETRIC) {
         const int cls = l == 1 ? 2 : -1;
         if (cls >= 0) timed_begin(h, cls, s, &e0);
-        launch_stencil_op<T>(L, op, x, b, y, w, done, s);
+        launch_stencil_op<T>(L, op, x, b, y, w, done, s, ch);
         if (cls >= 0) timed_end(h, cls, s, e0);
     } else {
-        launch_bsr_op<T>(L, op, x, b, y, w, done, s);
+        launch_bsr_op<T>(L, op, x, b, y, w, done, s, ch);
     }
+}
+
+// largest eigenvalue of D^-1 A on level l: 12 power steps from a hashed start
+// vector (zero on supported dofs), lambda = ||D^-1 A v|| / ||v||, v <- D^-1 A v
+// (FP64; block sums added on the host in a fixed order)
+static double power_lmax(tm_hierarchy* h, int l, hipStream_t s) {
+    Level& L = h->lv[l];
+    std::vector<void*> tmp;
+    size_t tb = 0;
+    double* v = dalloc<double>(tmp, tb, (size_t)L.n);
+    double* w = dalloc<double>(tmp, tb, (size_t)L.n);
+    double* z = dalloc<double>(tmp, tb, (size_t)L.n);
+    const int nb = (int)grid_for(L.n_nodes);
+    double* part = dalloc<double>(tmp, tb, (size_t)2 * nb);
+    std::vector<double> hp((size_t)2 * nb);
+    double lam = 0.0;
+    try {
+        launch_power_start(v, L.n, l == 0 ? L.nmask : nullptr, L.bs, s);
+        for (int it = 0; it < 12; ++it) {
+            level_op<double>(h, l, OP_APPLY, v, v, w, nullptr, s);
+            launch_power_step(L, w, v, z, part, s);
+            TM_HIP(hipMemcpyAsync(hp.data(), part, hp.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+            TM_HIP(hipStreamSynchronize(s));
+            double zz = 0.0, vv = 0.0;
+            for (int q = 0; q < nb; ++q) {
+                zz += hp[q];
+                vv += hp[nb + q];
+            }
+            lam = std::sqrt(zz / vv);
+            std::swap(v, z);
+        }
+    } catch (...) {
+        (void)hipStreamSynchronize(s);
+        free_list(tmp);
+        throw;
+    }
+    free_list(tmp);
+    return lam;
 }
 
 template <typename T>
@@ -447,7 +500,7 @@ static void restrict_to(tm_hierarchy* h, int l, const T* r, T* bc, T* xc_first, 
                         hipStream_t s) {
     Level& F = h->lv[l];
     Level& C = h->lv[l + 1];
-    const T w = (T)h->opt.omega;
+    const T w = (T)first_sweep_weight(h, l + 1);
     if (F.xfer_bsr)
         launch_bsr_restrict<T>(F, r, bc, C, xc_first, w, done, s);
     else
@@ -470,15 +523,36 @@ static void vcycle(tm_hierarchy* h, Vcyc& V, const T* b0, T* z, const int* done,
                    bool first_done = false) {
     const int L = (int)h->lv.size();
     const int npre = h->opt.nu_pre, npost = h->opt.nu_post;
-    const T w = (T)h->opt.omega;
+    const bool cheb = h->opt.smoother == TM_SMOOTH_CHEBYSHEV;
     std::vector<T*> xr(L), tr(L);
+    // Chebyshev step k on level l (k = 0: from the current iterate with no
+    // previous direction): coefficients of d_k = c1 d_{k-1} + c2 D^-1 r_k.
+    // After a zero start the direction d_0 is the first iterate itself.
+    auto cheb_args = [&](int l, int k, const T* x, bool zero_start) {
+        const double th = h->lv[l].cheb_theta, de = h->lv[l].cheb_delta, sigma = th / de;
+        double rho = de / th, c1 = 0.0, c2 = 1.0 / th;
+        for (int q = 1; q <= k; ++q) {
+            const double rn = 1.0 / (2.0 * sigma - rho);
+            c1 = rn * rho;
+            c2 = 2.0 * rn / de;
+            rho = rn;
+        }
+        ChebArgs ch;
+        ch.din = (k == 0 || (k == 1 && zero_start)) ? (const void*)x : V.d[l];
+        ch.dout = V.d[l];
+        ch.c1 = k == 0 ? 0.0 : c1;
+        ch.c2 = c2;
+        return ch;
+    };
     for (int l = 0; l < L - 1; ++l) {
         const T* b = l == 0 ? b0 : vb<T>(V, l);
         T* x = vx<T>(V, l);
         T* t = vt<T>(V, l);
-        if (l == 0 && !first_done) launch_first_smooth<T>(h->lv[0], b, x, w, done, s);
+        if (l == 0 && !first_done) launch_first_smooth<T>(h->lv[0], b, x, (T)first_sweep_weight(h, 0), done, s);
         for (int k = 1; k < npre; ++k) {
-            level_op<T>(h, l, OP_SMOOTH, x, b, t, done, s);
+            // from a zero start the first step's direction is the first iterate
+            if (cheb) level_op<T>(h, l, OP_CHEB, x, b, t, done, s, cheb_args(l, k, x, true));
+            else level_op<T>(h, l, OP_SMOOTH, x, b, t, done, s);
             std::swap(x, t);
         }
         level_op<T>(h, l, OP_RESID, x, b, t, done, s);
@@ -496,7 +570,8 @@ static void vcycle(tm_hierarchy* h, Vcyc& V, const T* b0, T* z, const int* done,
         prolong_from<T>(h, l, xr[l + 1], x, done, s);
         for (int k = 0; k < npost; ++k) {
             T* dst = (l == 0 && k == npost - 1) ? z : t;
-            level_op<T>(h, l, OP_SMOOTH, x, b, dst, done, s);
+            if (cheb) level_op<T>(h, l, OP_CHEB, x, b, dst, done, s, cheb_args(l, k, x, false));
+            else level_op<T>(h, l, OP_SMOOTH, x, b, dst, done, s);
             if (!(l == 0 && k == npost - 1)) std::swap(x, t);
         }
         xr[l] = x;
@@ -510,11 +585,14 @@ static void alloc_vcyc(tm_hierarchy* h, Vcyc& V, std::vector<void*>& list, size_
     V.b.assign(L, nullptr);
     V.x.assign(L, nullptr);
     V.t.assign(L, nullptr);
+    V.d.assign(L, nullptr);
+    const bool cheb = h->opt.smoother == TM_SMOOTH_CHEBYSHEV;
     for (int l = 0; l < L; ++l) {
         const size_t n = (size_t)h->lv[l].n;
         if (l > 0) V.b[l] = dalloc<T>(list, bytes, n);
         V.x[l] = dalloc<T>(list, bytes, n);
         if (l < L - 1) V.t[l] = dalloc<T>(list, bytes, n);
+        if (cheb && l < L - 1) V.d[l] = dalloc<T>(list, bytes, n);
     }
 }
 
@@ -845,6 +923,7 @@ void tm_default_options(tm_options* o) {
     o->max_iters = 1000;
     o->check_every = 0;
     o->fine_mfma = 0;
+    o->cheb_lower = 0.1;
 }
 
 const char* tm_status_string(tm_status s) {

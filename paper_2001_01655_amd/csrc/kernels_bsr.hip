@@ -16,7 +16,7 @@ __global__ __launch_bounds__(WG) void k_bsr_op_wave(const int32_t* __restrict__ 
                                                     const T* __restrict__ v, int64_t nbr, const T* __restrict__ x,
                                                     const T* __restrict__ b, T* __restrict__ y,
                                                     const T* __restrict__ dinv, T omega,
-                                                    const int* __restrict__ done) {
+                                                    const int* __restrict__ done, const ChebArgs ch) {
     if (done && *done) return;
     const int64_t row = xcd_block() * (WG / 64) + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
@@ -42,7 +42,7 @@ __global__ __launch_bounds__(WG) void k_bsr_op_wave(const int32_t* __restrict__ 
 #pragma unroll
     for (int c = 0; c < BS; ++c) xo[c] = x[(int64_t)BS * row + c];
     double dots[2];
-    finish_node<T, BS, OP>(row, nbr, acc, xo, 0, b, y, dinv, omega, dots);
+    finish_node<T, BS, OP>(row, nbr, acc, xo, 0, b, y, dinv, omega, dots, ch);
 }
 
 template <typename T>
@@ -60,34 +60,35 @@ const float* dinv_of<float>(const Level& L) { return L.dinv32; }
 
 template <typename T, int BS>
 static void bsr_op_bs(const Level& L, int op, const T* x, const T* b, T* y, T omega, const int* done,
-                      hipStream_t s) {
+                      hipStream_t s, const ChebArgs& ch) {
     const dim3 g(grid_for(L.A.nbr, WG / 64)), blk(WG);
     const T* v = vals_of<T>(L.A);
     const T* dv = dinv_of<T>(L);
-    if (op == OP_APPLY)
-        hipLaunchKernelGGL((k_bsr_op_wave<T, BS, OP_APPLY>), g, blk, 0, s, L.A.rp, L.A.ci, v, L.A.nbr, x, b, y, dv,
-                           omega, done);
-    else if (op == OP_RESID)
-        hipLaunchKernelGGL((k_bsr_op_wave<T, BS, OP_RESID>), g, blk, 0, s, L.A.rp, L.A.ci, v, L.A.nbr, x, b, y, dv,
-                           omega, done);
-    else
-        hipLaunchKernelGGL((k_bsr_op_wave<T, BS, OP_SMOOTH>), g, blk, 0, s, L.A.rp, L.A.ci, v, L.A.nbr, x, b, y, dv,
-                           omega, done);
+#define TM_BO(OPV)                                                                                    \
+    hipLaunchKernelGGL((k_bsr_op_wave<T, BS, OPV>), g, blk, 0, s, L.A.rp, L.A.ci, v, L.A.nbr, x, b, y, dv, omega, \
+                       done, ch)
+    switch (op) {
+        case OP_APPLY: TM_BO(OP_APPLY); break;
+        case OP_RESID: TM_BO(OP_RESID); break;
+        case OP_CHEB: TM_BO(OP_CHEB); break;
+        default: TM_BO(OP_SMOOTH); break;
+    }
+#undef TM_BO
 }
 
 template <typename T>
 void launch_bsr_op(const Level& L, int op, const T* x, const T* b, T* y, T omega, const int* done,
-                   hipStream_t s) {
+                   hipStream_t s, const ChebArgs& ch) {
     switch (L.bs) {
-        case 3: bsr_op_bs<T, 3>(L, op, x, b, y, omega, done, s); break;
-        case 6: bsr_op_bs<T, 6>(L, op, x, b, y, omega, done, s); break;
+        case 3: bsr_op_bs<T, 3>(L, op, x, b, y, omega, done, s, ch); break;
+        case 6: bsr_op_bs<T, 6>(L, op, x, b, y, omega, done, s, ch); break;
         default: fail(TM_ERR_ARG, "aggregation level block size must be 3 or 6");
     }
 }
 template void launch_bsr_op<double>(const Level&, int, const double*, const double*, double*, double,
-                                    const int*, hipStream_t);
+                                    const int*, hipStream_t, const ChebArgs&);
 template void launch_bsr_op<float>(const Level&, int, const float*, const float*, float*, float,
-                                   const int*, hipStream_t);
+                                   const int*, hipStream_t, const ChebArgs&);
 
 // y (+)= B x for a rectangular BSR with BR x BC blocks; optionally x_first = omega D^-1 y
 template <typename T, int BR, int BC, bool ADD, bool FIRST>

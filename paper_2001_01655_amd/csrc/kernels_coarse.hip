@@ -233,7 +233,7 @@ __global__ __launch_bounds__(WG) void k_stencil_op(const T* __restrict__ st, int
                                                    int64_t N, const T* __restrict__ x,
                                                    const T* __restrict__ b, T* __restrict__ y,
                                                    const T* __restrict__ dinv, T omega,
-                                                   const int* __restrict__ done) {
+                                                   const int* __restrict__ done, const ChebArgs ch) {
     if (done && *done) return;
     const int64_t node = xcd_block() * WG + threadIdx.x;
     if (node >= N) return;
@@ -319,7 +319,7 @@ __global__ __launch_bounds__(WG) void k_stencil_op(const T* __restrict__ st, int
         }
     }
     double dots[2];
-    finish_node<T, DIM, OP>(node, N, acc, xo, 0, b, y, dinv, omega, dots);
+    finish_node<T, DIM, OP>(node, N, acc, xo, 0, b, y, dinv, omega, dots, ch);
 }
 
 template <typename T>
@@ -337,49 +337,45 @@ const float* dinv_of<float>(const Level& L) { return L.dinv32; }
 
 template <typename T, int DIM, int G>
 static void stencil_launch(const Level& L, int op, const T* x, const T* b, T* y, T omega, const int* done,
-                           hipStream_t s) {
+                           hipStream_t s, const ChebArgs& ch) {
     const dim3 g(grid_for(L.n_nodes)), blk(WG);
     const T* st = st_of<T>(L);
     const T* dv = dinv_of<T>(L);
     const int nz = DIM == 3 ? L.nel[2] : 0;
+#define TM_SL(OPV)                                                                                   \
+    hipLaunchKernelGGL((k_stencil_op<T, DIM, OPV, G>), g, blk, 0, s, st, L.nel[0], L.nel[1], nz, L.n_nodes, x, \
+                       b, y, dv, omega, done, ch)
     switch (op) {
-        case OP_APPLY:
-            hipLaunchKernelGGL((k_stencil_op<T, DIM, OP_APPLY, G>), g, blk, 0, s, st, L.nel[0], L.nel[1], nz,
-                               L.n_nodes, x, b, y, dv, omega, done);
-            break;
-        case OP_RESID:
-            hipLaunchKernelGGL((k_stencil_op<T, DIM, OP_RESID, G>), g, blk, 0, s, st, L.nel[0], L.nel[1], nz,
-                               L.n_nodes, x, b, y, dv, omega, done);
-            break;
-        default:
-            hipLaunchKernelGGL((k_stencil_op<T, DIM, OP_SMOOTH, G>), g, blk, 0, s, st, L.nel[0], L.nel[1], nz,
-                               L.n_nodes, x, b, y, dv, omega, done);
-            break;
+        case OP_APPLY: TM_SL(OP_APPLY); break;
+        case OP_RESID: TM_SL(OP_RESID); break;
+        case OP_CHEB: TM_SL(OP_CHEB); break;
+        default: TM_SL(OP_SMOOTH); break;
     }
+#undef TM_SL
 }
 
 template <typename T, int DIM>
 static void stencil_dispatch(const Level& L, int op, const T* x, const T* b, T* y, T omega,
-                             const int* done, hipStream_t s) {
+                             const int* done, hipStream_t s, const ChebArgs& ch) {
     // fewer workgroups than compute units: latency-bound, batch more loads
     if (grid_for(L.n_nodes) < 256)
-        stencil_launch<T, DIM, DIM == 3 ? 9 : 9>(L, op, x, b, y, omega, done, s);
+        stencil_launch<T, DIM, 9>(L, op, x, b, y, omega, done, s, ch);
     else
-        stencil_launch<T, DIM, DIM == 3 ? 3 : 4>(L, op, x, b, y, omega, done, s);
+        stencil_launch<T, DIM, DIM == 3 ? 3 : 4>(L, op, x, b, y, omega, done, s, ch);
 }
 
 template <typename T>
 void launch_stencil_op(const Level& L, int op, const T* x, const T* b, T* y, T omega,
-                       const int* done, hipStream_t s) {
+                       const int* done, hipStream_t s, const ChebArgs& ch) {
     if (L.dim == 3)
-        stencil_dispatch<T, 3>(L, op, x, b, y, omega, done, s);
+        stencil_dispatch<T, 3>(L, op, x, b, y, omega, done, s, ch);
     else
-        stencil_dispatch<T, 2>(L, op, x, b, y, omega, done, s);
+        stencil_dispatch<T, 2>(L, op, x, b, y, omega, done, s, ch);
 }
 template void launch_stencil_op<double>(const Level&, int, const double*, const double*, double*,
-                                        double, const int*, hipStream_t);
+                                        double, const int*, hipStream_t, const ChebArgs&);
 template void launch_stencil_op<float>(const Level&, int, const float*, const float*, float*, float,
-                                       const int*, hipStream_t);
+                                       const int*, hipStream_t, const ChebArgs&);
 
 // --------------------------------------------------------------- transfers
 // restriction b_c = P~^T r_f: coarse node I gathers fine nodes 2I + d, d in {-1,0,1}^dim,

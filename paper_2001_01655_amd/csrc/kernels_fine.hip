@@ -230,7 +230,8 @@ __global__ __launch_bounds__(WG) void k_fine3(const T* __restrict__ E, const KeV
                                               int64_t N64, const T* __restrict__ x,
                                               const T* __restrict__ b, T* __restrict__ y,
                                               const T* __restrict__ dinv, T omega,
-                                              const int* __restrict__ done, double* partials) {
+                                              const int* __restrict__ done, double* partials,
+                                              const ChebArgs ch) {
     if (done && *done) return;
     const uint32_t N = (uint32_t)N64;
     const uint32_t node = (uint32_t)xcd_block() * WG + threadIdx.x;
@@ -289,7 +290,7 @@ __global__ __launch_bounds__(WG) void k_fine3(const T* __restrict__ E, const KeV
     double dots[2] = {0.0, 0.0};
     if (live) {
         const T xo[3] = {x[3u * node], x[3u * node + 1], x[3u * node + 2]};
-        finish_node<T, 3, OP>(node, N, acc, xo, nm[node], b, y, dinv, omega, dots);
+        finish_node<T, 3, OP>(node, N, acc, xo, nm[node], b, y, dinv, omega, dots, ch);
     }
     if (OP == OP_QDOT) block_reduce_store<2>(dots, partials);
 }
@@ -338,7 +339,7 @@ __global__ __launch_bounds__(WG) void k_fine3_mfma(const float* __restrict__ E, 
                                                    int64_t N64, const float* __restrict__ x,
                                                    const float* __restrict__ b, float* __restrict__ y,
                                                    const float* __restrict__ dinv, float omega,
-                                                   const int* __restrict__ done) {
+                                                   const int* __restrict__ done, const ChebArgs ch) {
     if (done && *done) return;
     // every lane of the wave takes part in the matrix instructions: lanes past
     // the last node work on node 0 and store nothing
@@ -400,7 +401,7 @@ __global__ __launch_bounds__(WG) void k_fine3_mfma(const float* __restrict__ E, 
     if (live) {
         double dots[2] = {0.0, 0.0};
         const float xo[3] = {x[3u * node], x[3u * node + 1], x[3u * node + 2]};
-        finish_node<float, 3, OP>(node, N, acc, xo, nm[node], b, y, dinv, omega, dots);
+        finish_node<float, 3, OP>(node, N, acc, xo, nm[node], b, y, dinv, omega, dots, ch);
     }
 }
 
@@ -437,7 +438,8 @@ __global__ __launch_bounds__(WG) void k_fine2(const T* __restrict__ E, const KeV
                                               int64_t N, const T* __restrict__ x,
                                               const T* __restrict__ b, T* __restrict__ y,
                                               const T* __restrict__ dinv, T omega,
-                                              const int* __restrict__ done, double* partials) {
+                                              const int* __restrict__ done, double* partials,
+                                              const ChebArgs ch) {
     if (done && *done) return;
     const int64_t node = xcd_block() * WG + threadIdx.x;
     const bool live = node < N;
@@ -488,7 +490,7 @@ __global__ __launch_bounds__(WG) void k_fine2(const T* __restrict__ E, const KeV
     double dots[2] = {0.0, 0.0};
     if (live) {
         const T xo[2] = {x[2 * node], x[2 * node + 1]};
-        finish_node<T, 2, OP>(node, N, acc, xo, nm[node], b, y, dinv, omega, dots);
+        finish_node<T, 2, OP>(node, N, acc, xo, nm[node], b, y, dinv, omega, dots, ch);
     }
     if (OP == OP_QDOT) block_reduce_store<2>(dots, partials);
 }
@@ -516,47 +518,48 @@ const float* pick_dinv<float>(const Level& L) { return L.dinv32; }
 
 template <typename T, int OP, bool MI>
 static void fine_dispatch(const tm_hierarchy* h, const T* x, const T* b, T* y, T omega,
-                          const int* done, double* partials, hipStream_t s) {
+                          const int* done, double* partials, hipStream_t s, const ChebArgs& ch) {
     const Level& L = h->lv[0];
     const dim3 g(grid_for(L.n_nodes)), blk(WG);
     if constexpr (std::is_same<T, float>::value && !MI && OP != OP_QDOT) {
         if (L.dim == 3 && h->opt.fine_mfma) {
             hipLaunchKernelGGL((k_fine3_mfma<OP>), g, blk, 0, s, L.E32, h->KA32, L.nmask, L.nel[0], L.nel[1],
-                               L.nel[2], L.n_nodes, x, b, y, L.dinv32, omega, done);
+                               L.nel[2], L.n_nodes, x, b, y, L.dinv32, omega, done, ch);
             return;
         }
     }
     if (L.dim == 3)
         hipLaunchKernelGGL((k_fine3<T, OP, MI>), g, blk, 0, s, pick_E<T>(L), pick_kc<T>(h), L.nmask,
                            L.nel[0], L.nel[1], L.nel[2], L.n_nodes, x, b, y, pick_dinv<T>(L), omega,
-                           done, partials);
+                           done, partials, ch);
     else
         hipLaunchKernelGGL((k_fine2<T, OP, MI>), g, blk, 0, s, pick_E<T>(L), pick_kc<T>(h), L.nmask,
                            L.nel[0], L.nel[1], L.n_nodes, x, b, y, pick_dinv<T>(L), omega, done,
-                           partials);
+                           partials, ch);
 }
 
 template <typename T>
 void launch_fine_op(const tm_hierarchy* h, int op, bool mask_in, const T* x, const T* b, T* y,
-                    T omega, const int* done, double* partials, hipStream_t s) {
+                    T omega, const int* done, double* partials, hipStream_t s, const ChebArgs& ch) {
     if (mask_in) {
         if (op != OP_APPLY) fail(TM_ERR_ARG, "masked-input fine operator supports apply only");
-        fine_dispatch<T, OP_APPLY, true>(h, x, b, y, omega, done, partials, s);
+        fine_dispatch<T, OP_APPLY, true>(h, x, b, y, omega, done, partials, s, ch);
         return;
     }
     switch (op) {
-        case OP_APPLY: fine_dispatch<T, OP_APPLY, false>(h, x, b, y, omega, done, partials, s); break;
-        case OP_RESID: fine_dispatch<T, OP_RESID, false>(h, x, b, y, omega, done, partials, s); break;
-        case OP_SMOOTH: fine_dispatch<T, OP_SMOOTH, false>(h, x, b, y, omega, done, partials, s); break;
+        case OP_APPLY: fine_dispatch<T, OP_APPLY, false>(h, x, b, y, omega, done, partials, s, ch); break;
+        case OP_RESID: fine_dispatch<T, OP_RESID, false>(h, x, b, y, omega, done, partials, s, ch); break;
+        case OP_SMOOTH: fine_dispatch<T, OP_SMOOTH, false>(h, x, b, y, omega, done, partials, s, ch); break;
+        case OP_CHEB: fine_dispatch<T, OP_CHEB, false>(h, x, b, y, omega, done, partials, s, ch); break;
         default:
             if (!partials) fail(TM_ERR_ARG, "q = K~p needs a partial-sum buffer");
-            fine_dispatch<T, OP_QDOT, false>(h, x, b, y, omega, done, partials, s);
+            fine_dispatch<T, OP_QDOT, false>(h, x, b, y, omega, done, partials, s, ch);
             break;
     }
 }
 template void launch_fine_op<double>(const tm_hierarchy*, int, bool, const double*, const double*,
-                                     double*, double, const int*, double*, hipStream_t);
+                                     double*, double, const int*, double*, hipStream_t, const ChebArgs&);
 template void launch_fine_op<float>(const tm_hierarchy*, int, bool, const float*, const float*,
-                                    float*, float, const int*, double*, hipStream_t);
+                                    float*, float, const int*, double*, hipStream_t, const ChebArgs&);
 
 }  // namespace tmi

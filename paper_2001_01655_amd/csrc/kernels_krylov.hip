@@ -224,7 +224,7 @@ static void update_ur_t(const tm_hierarchy* h, Lane& ln, KScal* sc, double* u, T
                         const TV* dinv, hipStream_t s) {
     const Level& L = h->lv[0];
     const dim3 g(update_ur_blocks(h)), b(WG);
-    const TV w = (TV)h->opt.omega;
+    const TV w = (TV)first_sweep_weight(h, 0);
     if (L.bs == 3)
         hipLaunchKernelGGL((k_update_ur<TV, 3>), g, b, 0, s, u, ln.r, ln.p, ln.q, rv, x0, dinv, w, L.n_nodes,
                            sc, ln.part);
@@ -310,6 +310,53 @@ void launch_final_residual(const tm_hierarchy* h, Lane& ln, KScal* sc, const dou
     const int nb = krylov_blocks(n);
     hipLaunchKernelGGL(k_final_dots, dim3(nb), dim3(WG), 0, s, ln.f, ln.q, u, n, ln.part);
     hipLaunchKernelGGL(k_final_scalars, dim3(1), dim3(FB), 0, s, sc, ln.part, nb);
+}
+
+// ---------------------------------------------------------------- eigenvalue estimate
+// Start vector of the power iteration for D^-1 A: v_i = 1 + (fmix32(i) mod 2^16) / 2^16,
+// zero on supported dofs of the fine level.
+__global__ void k_power_start(double* __restrict__ v, int64_t n, const uint8_t* __restrict__ nm, int bs) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double val = 1.0 + (double)(fmix32((uint32_t)i) & 0xffffu) / 65536.0;
+    if (nm && ((nm[i / bs] >> (i % bs)) & 1u)) val = 0.0;
+    v[i] = val;
+}
+
+void launch_power_start(double* v, int64_t n, const uint8_t* nmask, int bs, hipStream_t s) {
+    hipLaunchKernelGGL(k_power_start, dim3(grid_for(n)), dim3(WG), 0, s, v, n, nmask, bs);
+}
+
+// z = D^-1 w per block row; block partials of z.z and v.v
+template <int BS>
+__global__ __launch_bounds__(WG) void k_power_step(const double* __restrict__ w, const double* __restrict__ dinv,
+                                                   const double* __restrict__ v, int64_t N, double* __restrict__ z,
+                                                   double* part) {
+    const int64_t node = (int64_t)blockIdx.x * WG + threadIdx.x;
+    double d[2] = {0.0, 0.0};
+    if (node < N) {
+#pragma unroll
+        for (int r = 0; r < BS; ++r) {
+            double t = 0.0;
+#pragma unroll
+            for (int c = 0; c < BS; ++c) t += dinv[(int64_t)(r * BS + c) * N + node] * w[BS * node + c];
+            z[BS * node + r] = t;
+            d[0] += t * t;
+            const double vr = v[BS * node + r];
+            d[1] += vr * vr;
+        }
+    }
+    block_reduce_store<2>(d, part);
+}
+
+void launch_power_step(const Level& L, const double* w, const double* v, double* z, double* part, hipStream_t s) {
+    const dim3 g(grid_for(L.n_nodes)), b(WG);
+    switch (L.bs) {
+        case 2: hipLaunchKernelGGL(k_power_step<2>, g, b, 0, s, w, L.dinv64, v, L.n_nodes, z, part); break;
+        case 3: hipLaunchKernelGGL(k_power_step<3>, g, b, 0, s, w, L.dinv64, v, L.n_nodes, z, part); break;
+        case 6: hipLaunchKernelGGL(k_power_step<6>, g, b, 0, s, w, L.dinv64, v, L.n_nodes, z, part); break;
+        default: fail(TM_ERR_ARG, "block size must be 2, 3 or 6");
+    }
 }
 
 }  // namespace tmi

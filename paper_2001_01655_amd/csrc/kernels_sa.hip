@@ -193,14 +193,6 @@ __global__ void k_strength(const int32_t* __restrict__ rp, const int32_t* __rest
 }
 
 // ------------------------------------------------------------------ aggregation
-__device__ __forceinline__ uint32_t fmix32(uint32_t h) {
-    h ^= h >> 16;
-    h *= 0x85ebca6bu;
-    h ^= h >> 13;
-    h *= 0xc2b2ae35u;
-    h ^= h >> 16;
-    return h;
-}
 constexpr uint64_t KEY_NONE = 1ull << 32;
 
 // m1[i] = min key of undecided nodes in {i} u S(i)

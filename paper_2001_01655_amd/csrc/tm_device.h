@@ -28,6 +28,16 @@ __device__ __forceinline__ void block_reduce_store(double (&v)[NV], double* part
     }
 }
 
+// MurmurHash3's 32-bit finaliser: a bijection of uint32 used as a hash
+__device__ __forceinline__ uint32_t fmix32(uint32_t h) {
+    h ^= h >> 16;
+    h *= 0x85ebca6bu;
+    h ^= h >> 13;
+    h *= 0xc2b2ae35u;
+    h ^= h >> 16;
+    return h;
+}
+
 // ------------------------------------------------------------ buffer loads
 // Raw buffer loads take a 32-bit byte offset from a descriptor held in SGPRs,
 // which avoids per-load 64-bit address arithmetic in the gather kernels.
@@ -158,7 +168,8 @@ __device__ void store_dinv(double (&D)[BS][BS], int point, int64_t node, int64_t
 template <typename T, int BS, int OP>
 __device__ __forceinline__ void finish_node(int64_t node, int64_t N, T (&kx)[BS], const T (&xo)[BS],
                                             uint8_t m, const T* __restrict__ b, T* __restrict__ y,
-                                            const T* __restrict__ dinv, T omega, double (&dots)[2]) {
+                                            const T* __restrict__ dinv, T omega, double (&dots)[2],
+                                            const ChebArgs& ch = ChebArgs{}) {
 #pragma unroll
     for (int c = 0; c < BS; ++c)
         if (m & (1u << c)) kx[c] = xo[c];               // unit row of a supported dof
@@ -178,6 +189,22 @@ __device__ __forceinline__ void finish_node(int64_t node, int64_t N, T (&kx)[BS]
 #pragma unroll
             for (int c = 0; c < BS; ++c) t += dinv[(int64_t)(r * BS + c) * N + node] * rr[c];
             y[BS * node + r] = xo[r] + omega * t;
+        }
+    } else if (OP == OP_CHEB) {
+        T rr[BS];
+#pragma unroll
+        for (int c = 0; c < BS; ++c) rr[c] = b[BS * node + c] - kx[c];
+        const T* din = (const T*)ch.din;
+        T* dout = (T*)ch.dout;
+        const T c1 = (T)ch.c1, c2 = (T)ch.c2;
+#pragma unroll
+        for (int r = 0; r < BS; ++r) {
+            T t = 0;
+#pragma unroll
+            for (int c = 0; c < BS; ++c) t += dinv[(int64_t)(r * BS + c) * N + node] * rr[c];
+            const T dn = c1 * din[BS * node + r] + c2 * t;
+            dout[BS * node + r] = dn;
+            y[BS * node + r] = xo[r] + dn;
         }
     } else {  // OP_QDOT: q = K~ p, partial p.q and p.r (b holds r)
 #pragma unroll

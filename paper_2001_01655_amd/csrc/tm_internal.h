@@ -153,6 +153,8 @@ struct Level {
     int64_t n_nodes = 0;          // block rows
     int bs = 0;                   // dofs per block row
     int64_t n = 0;                // dofs
+    // Chebyshev smoothing interval [theta - delta, theta + delta] for D^-1 A
+    double cheb_theta = 0.0, cheb_delta = 0.0;
     // fine level
     double* E64 = nullptr;
     float* E32 = nullptr;
@@ -182,6 +184,7 @@ struct Level {
 
 struct Vcyc {                     // V-cycle work vectors of one precision, per level
     std::vector<void*> b, x, t;   // rhs, iterate, scratch (same length per level)
+    std::vector<void*> d;         // Chebyshev update direction (Chebyshev smoothing only)
 };
 
 struct Lane;                      // one right-hand side of a solve state
@@ -240,6 +243,14 @@ struct tm_solve_state {
 };
 
 namespace tmi {
+// weight of the first smoothing sweep from a zero start on level l: omega for
+// Jacobi, 1 / theta_l for Chebyshev (its first step is a Jacobi step)
+inline double first_sweep_weight(const tm_hierarchy* h, int l) {
+    return h->opt.smoother == TM_SMOOTH_CHEBYSHEV ? 1.0 / h->lv[l].cheb_theta : h->opt.omega;
+}
+void launch_power_start(double* v, int64_t n, const uint8_t* nmask, int bs, hipStream_t s);
+void launch_power_step(const Level& L, const double* w, const double* v, double* z, double* part, hipStream_t s);
+
 
 struct Lane {
     double *f = nullptr, *r = nullptr, *p = nullptr, *q = nullptr, *z64 = nullptr;
@@ -252,7 +263,15 @@ void delete_cached_state(tm_hierarchy* h);
 
 // ----------------------------------------------------------------- launchers
 // fine level (kernels_fine.hip)
-enum { OP_APPLY = 0, OP_RESID = 1, OP_SMOOTH = 2, OP_QDOT = 3 };
+enum { OP_APPLY = 0, OP_RESID = 1, OP_SMOOTH = 2, OP_QDOT = 3, OP_CHEB = 4 };
+
+// OP_CHEB (one Chebyshev step): dout = c1 din + c2 D^-1 (b - A x), y = x + dout.
+// din may be x (first step after a zero start) or equal dout (in place).
+struct ChebArgs {
+    const void* din = nullptr;
+    void* dout = nullptr;
+    double c1 = 0.0, c2 = 0.0;
+};
 void launch_simp(const double* rho, int64_t n_el, double p, double E0, double Emin, double* E64,
                  float* E32, double* rho64, int* flags, hipStream_t s);
 void launch_sensitivity(const tm_hierarchy* h, int n_rhs, const double* u, double* dc, hipStream_t s);
@@ -260,7 +279,8 @@ void launch_fine_dinv(const Level& L, const double* KE64, int point_jacobi, int*
                       hipStream_t s);
 template <typename T>
 void launch_fine_op(const tm_hierarchy* h, int op, bool mask_in, const T* x, const T* b, T* y,
-                    T omega, const int* done, double* partials, hipStream_t s);
+                    T omega, const int* done, double* partials, hipStream_t s,
+                    const ChebArgs& ch = ChebArgs{});
 int update_ur_blocks(const tm_hierarchy* h);
 int fine_op_blocks(const tm_hierarchy* h);
 // coarse geometric levels (kernels_coarse.hip)
@@ -271,7 +291,7 @@ void launch_stencil_compact(const Level& L, hipStream_t s);
 void launch_stencil_dinv(const Level& L, int point_jacobi, int* flags, hipStream_t s);
 template <typename T>
 void launch_stencil_op(const Level& L, int op, const T* x, const T* b, T* y, T omega,
-                       const int* done, hipStream_t s);
+                       const int* done, hipStream_t s, const ChebArgs& ch = ChebArgs{});
 template <typename T>
 void launch_restrict(const Level& fine, const Level& coarse, const T* rf, T* bc, T* xc_first,
                      T omega, const int* done, hipStream_t s);
@@ -291,7 +311,7 @@ void launch_dense_solve(const double* Ainv, int64_t n, const T* b, T* x, const i
 // aggregation levels (kernels_sa.hip)
 template <typename T>
 void launch_bsr_op(const Level& L, int op, const T* x, const T* b, T* y, T omega, const int* done,
-                   hipStream_t s);
+                   hipStream_t s, const ChebArgs& ch = ChebArgs{});
 template <typename T>
 void launch_bsr_restrict(const Level& fine, const T* rf, T* bc, const Level& coarse, T* xc_first,
                          T omega, const int* done, hipStream_t s);

@@ -54,7 +54,8 @@ def _setup_status(nel=(8, 4), nu=0.3, Emin=1e-9, E0=1.0, dofs=(0, 1), **opts):
     (dict(dofs=(0, 10 ** 9)), "out of range"),
     (dict(omega=2.5), "omega"),
     (dict(vcycle_fp=16), "vcycle_fp"),
-    (dict(smoother=2), "smoother"),
+    (dict(smoother=3), "smoother"),
+    (dict(smoother=2, cheb_lower=0.0), "cheb_lower"),
     (dict(n_geometric=1), "n_geometric"),
     (dict(nu_pre=0), "nu_pre"),
     (dict(fine_mfma=2), "fine_mfma"),

@@ -195,3 +195,43 @@ def test_solve_matrix_cores_vs_oracle():
         assert np.linalg.norm(U[k] - ref.u) <= 1e-7 * np.linalg.norm(ref.u)
         assert abs(r.compliance[k] - ref.compliance) <= 1e-9 * abs(ref.compliance)
     G.close()
+
+
+@pytest.mark.parametrize("dim,nel,L", CASES)
+@pytest.mark.parametrize("nu", [2, 3])
+def test_vcycle_chebyshev(dim, nel, L, nu):
+    """Chebyshev smoothing (interval from a 12-step power estimate per level):
+    the V-cycle in FP64 and FP32 against the oracle's."""
+    _say(f"vcycle chebyshev {nel} nu={nu}")
+    p = synth.small_case(dim, nel, seed=28)
+    KE = fem.element_stiffness(p.dim, p.nu)
+    E = fem.simp(p.rho, p.p, p.E0, p.Emin)
+    H = mg.build_geometric(p.nel, E, KE, p.fixed, L, nu_pre=nu, nu_post=nu, smoother="chebyshev")
+    b = H.A[0] @ np.random.default_rng(9).standard_normal(p.n_dof)
+    b[p.fixed] = 0.0
+    ref = mg.vcycle(H, b)
+    G = _gpu(p, L, nu_pre=nu, nu_post=nu, smoother=2, vcycle_fp=64)
+    z = G.vcycle(torch.tensor(b, device="cuda"), fp=64).cpu().numpy()
+    assert _rel(z, ref) <= 1e-9
+    z32 = G.vcycle(torch.tensor(b, device="cuda", dtype=torch.float32), fp=32).cpu().numpy()
+    assert _rel(z32, ref) <= 1e-3
+    G.close()
+
+
+@pytest.mark.parametrize("vfp,outer", [(64, 1), (32, 0)])
+def test_solve_chebyshev_vs_oracle(vfp, outer):
+    _say(f"solve chebyshev vfp={vfp}")
+    p = synth.small_case(3, (16, 8, 8), seed=29, n_rhs=2)
+    KE = fem.element_stiffness(3, p.nu)
+    E = fem.simp(p.rho, p.p, p.E0, p.Emin)
+    H = mg.build_geometric(p.nel, E, KE, p.fixed, 3, nu_pre=2, nu_post=2, smoother="chebyshev")
+    G = _gpu(p, 3, nu_pre=2, nu_post=2, smoother=2, vcycle_fp=vfp, outer=outer)
+    r = G.solve(torch.tensor(p.loads, device="cuda"), rtol=1e-8)
+    U = r.u.cpu().numpy()
+    for k in range(p.loads.shape[0]):
+        ref = mg.mg_pcg(H, p.loads[k], 1e-12)
+        assert r.converged and r.relres[k] <= 1.2e-8
+        assert np.linalg.norm(U[k] - ref.u) <= 1e-7 * np.linalg.norm(ref.u)
+        assert abs(r.compliance[k] - ref.compliance) <= 1e-9 * abs(ref.compliance)
+        _say(f"  rhs {k}: iters={r.iters[k]} (oracle PCG {ref.iters} at rtol 1e-12)")
+    G.close()

@@ -104,3 +104,23 @@ def test_aggregation_update_rebuilds_levels():
     assert r1.converged and r2.converged
     assert np.linalg.norm(r2.u.cpu().numpy() - ref.u) <= 1e-7 * np.linalg.norm(ref.u)
     G.close()
+
+
+@pytest.mark.parametrize("kind,nel,ngeo,maxc", CASES[:2])
+def test_aggregation_vcycle_chebyshev(kind, nel, ngeo, maxc):
+    """Chebyshev smoothing on every level of the hybrid hierarchy (aggregation
+    levels included): the FP64 V-cycle against the oracle's."""
+    print(f"sa chebyshev {kind} {nel}", flush=True)
+    p = _problem(kind, nel)
+    KE = fem.element_stiffness(p.dim, p.nu)
+    E = fem.simp(p.rho, p.p, p.E0, p.Emin)
+    H = sa.build_hybrid(p.nel, E, KE, p.fixed, ngeo, max_coarse=maxc, nu_pre=2, nu_post=2,
+                        smoother="chebyshev")
+    from paper_2001_01655_amd import Hierarchy
+    G = Hierarchy(p.nel, p.rho, p.fixed, p=p.p, E0=p.E0, Emin=p.Emin, nu=p.nu, n_geometric=ngeo,
+                  max_coarse=maxc, vcycle_fp=64, outer=1, nu_pre=2, nu_post=2, smoother=2)
+    b = H.A[0] @ np.random.default_rng(11).standard_normal(p.n_dof)
+    b[p.fixed] = 0.0
+    z = G.vcycle(torch.tensor(b, device="cuda"), fp=64).cpu().numpy()
+    assert _rel(z, mg.vcycle(H, b)) <= 1e-8
+    G.close()
