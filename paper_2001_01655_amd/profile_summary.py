@@ -25,7 +25,7 @@ CLASSES = {
             what="fine operator FP64 (q = K~p, outer loop)"),
     1: dict(match=["k_fine3<float, 1, false>", "k_fine3<float, 2, false>"], source="kernels_fine.hip",
             what="fine operator FP32 (V-cycle residual / smoothing)"),
-    2: dict(match=["k_stencil_op<float, 3, 1>", "k_stencil_op<float, 3, 2>"], source="kernels_coarse.hip",
+    2: dict(match=["k_stencil_op<float, 3, 1, 3>", "k_stencil_op<float, 3, 2, 3>"], source="kernels_coarse.hip",
             what="level-1 stencil operator FP32 (V-cycle)", largest_grid=True),
 }
 
