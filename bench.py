@@ -29,7 +29,7 @@ WORKLOADS = {
     "cantilever3d": dict(cfg="cantilever3d", opts=dict(n_levels=6),
                          label="3D cantilever 192x96x96 Hex8, 5,447,811 dofs, 6-level GMG (coarsest 336 dofs), "
                                "block Jacobi w=0.5 1/1, rtol 1e-8"),
-    "cantilever2d": dict(cfg="cantilever2d", opts=dict(n_levels=7),
+    "cantilever2d": dict(cfg="cantilever2d", opts=dict(n_levels=7, max_iters=20000),
                          label="2D cantilever 1024x512 Q4, 1,051,650 dofs, 7-level GMG (coarsest 306 dofs), "
                                "block Jacobi w=0.5 1/1, rtol 1e-8"),
     "bridge3d": dict(cfg="bridge3d", opts=dict(n_geometric=3, max_coarse=1000),
