@@ -26,21 +26,30 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 WORKLOADS = {
-    "cantilever3d": dict(cfg="cantilever3d", opts=dict(n_levels=6),
-                         label="3D cantilever 192x96x96 Hex8, 5,447,811 dofs, 6-level GMG (coarsest 336 dofs), "
-                               "block Jacobi w=0.5 1/1, rtol 1e-8"),
-    "cantilever2d": dict(cfg="cantilever2d", opts=dict(n_levels=7, max_iters=20000),
-                         label="2D cantilever 1024x512 Q4, 1,051,650 dofs, 7-level GMG (coarsest 306 dofs), "
-                               "block Jacobi w=0.5 1/1, rtol 1e-8"),
-    "bridge3d": dict(cfg="bridge3d", opts=dict(n_geometric=3, max_coarse=1000),
-                     label="3D bridge 256x128x128 Hex8, 12,830,211 dofs, 3 GMG levels + smoothed aggregation "
-                           "to <1000 dofs, block Jacobi w=0.5 1/1, rtol 1e-8"),
+    "cantilever3d": dict(cfg="cantilever3d", levels=6, opts={},
+                         desc="3D cantilever 192x96x96 Hex8, 5,447,811 dofs"),
+    "cantilever2d": dict(cfg="cantilever2d", levels=7, opts=dict(max_iters=20000),
+                         desc="2D cantilever 1024x512 Q4, 1,051,650 dofs"),
+    "bridge3d": dict(cfg="bridge3d", levels=None, opts=dict(n_geometric=3, max_coarse=1000),
+                     desc="3D bridge 256x128x128 Hex8, 12,830,211 dofs, 3 GMG levels + smoothed aggregation "
+                          "to <1000 dofs"),
 }
+SMOOTHERS = {"jacobi": 0, "chebyshev": 2}
+
+
+def workload_label(wl, args, levels, coarsest):
+    s = wl["desc"]
+    if wl["levels"] is not None:
+        s += f", {levels}-level GMG (coarsest {coarsest} dofs)"
+    sm = "block Jacobi w=0.5" if args.smoother == "jacobi" else f"Chebyshev on [{args.cheb_lower:g}, 1.1] x lambda"
+    return s + f", {sm} {args.sweeps}/{args.sweeps}, rtol 1e-8"
+
 
 # MI355X published peaks (dense): HBM3E 8 TB/s; vector FP64 78.6 TFLOP/s; vector
 # FP32 157.3 TFLOP/s (reached only with packed FP32, which this build does not use)
 PEAK = {"hbm_GBs": 8000.0, "fp64_TFs": 78.6, "fp32_TFs": 157.3}
-KERNEL_SOURCES = {0: "kernels_fine.hip", 1: "kernels_fine.hip", 2: "kernels_coarse.hip"}
+KERNEL_SOURCES = {0: ["kernels_fine.hip", "tm_device.h"], 1: ["kernels_fine.hip", "tm_device.h"],
+                  2: ["kernels_coarse.hip", "tm_device.h"]}
 
 
 def parse():
@@ -54,6 +63,11 @@ def parse():
     ap.add_argument("--no-profile", action="store_true", help="skip the event-timed solve")
     ap.add_argument("--served", type=int, default=24, help="requests in the served-stream leg (0: skip)")
     ap.add_argument("--served-designs", type=int, default=20)
+    ap.add_argument("--levels", type=int, default=None, help="multigrid levels (default: the workload's)")
+    ap.add_argument("--smoother", default="chebyshev", choices=sorted(SMOOTHERS))
+    ap.add_argument("--sweeps", type=int, default=2, help="pre- and post-smoothing sweeps")
+    ap.add_argument("--cheb-lower", type=float, default=0.1,
+                    help="Chebyshev interval [cheb_lower, 1.1] x the estimated largest eigenvalue of D^-1 A")
     ap.add_argument("--fine-mfma", type=int, default=0, choices=[0, 1],
                     help="FP32 fine operator on the matrix cores (1) or vector FMAs (0)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -61,9 +75,11 @@ def parse():
     return ap.parse_args()
 
 
-def src_hash(name: str) -> str:
-    p = os.path.join(ROOT, "paper_2001_01655_amd", "csrc", name)
-    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+def src_hash(names) -> str:
+    h = hashlib.sha256()
+    for n in names:
+        h.update(open(os.path.join(ROOT, "paper_2001_01655_amd", "csrc", n), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def timed_solves(H, f, steps, warmup, rtol):
@@ -79,17 +95,35 @@ def timed_solves(H, f, steps, warmup, rtol):
     return time.perf_counter() - t0, res
 
 
-def algorithmic(cls, H, p):
-    """(flops, bytes) one launch of the class must do: the operator's own
-    arithmetic and each operand read or written once."""
+def vcycle_mix(smoother, nu):
+    """Operator launches of one level per V-cycle as (reads D^-1, reads the
+    previous Chebyshev direction, writes the direction).  The first
+    pre-smoothing step is fused into the transfer that makes the level's
+    right-hand side; the last step of each smoothing phase keeps no direction."""
+    if smoother == "jacobi":
+        return [(True, False, False)] * (2 * nu - 1) + [(False, False, False)]
+    pre = [(True, k >= 2, k < nu - 1) for k in range(1, nu)]
+    post = [(True, k >= 1, k < nu - 1) for k in range(nu)]
+    return pre + [(False, False, False)] + post
+
+
+def algorithmic(cls, H, p, args):
+    """(flops, bytes) one launch of the class must do, averaged over the
+    launches of a V-cycle: the operator's own arithmetic and each operand read
+    or written once."""
     dim, n_el, n_nodes = p.dim, p.n_el, p.n_nodes
     nd = dim * 2 ** dim
+    mix = vcycle_mix(args.smoother, args.sweeps)
+
+    def extra(w):  # smoother operands per node, mean over the mix
+        return sum(dv * dim * dim * w + (dr + dw) * dim * w for dv, dr, dw in mix) / len(mix)
+
     if cls in (0, 1):
         flops = 2.0 * nd * (nd + 1) * n_el                   # KE rows x U_e, then E_e scaling
         w = 8 if cls == 0 else 4
-        # x, b (r), y per node, modulus per element, support mask per node;
-        # the smoothing sweep also reads the block inverse (half of class-1 launches)
-        byts = 3 * dim * w * n_nodes + w * n_el + n_nodes + (0 if cls == 0 else 0.5 * dim * dim * w * n_nodes)
+        # x, b (r), y per node, modulus per element, support mask per node,
+        # plus the smoother's operands (V-cycle launches only)
+        byts = 3 * dim * w * n_nodes + w * n_el + n_nodes + (0 if cls == 0 else extra(w) * n_nodes)
         return flops, byts
     # level-1 operator, stored in symmetric form: the blocks towards the upper
     # half of the neighbours plus the diagonal block's upper triangle; the
@@ -99,13 +133,13 @@ def algorithmic(cls, H, p):
     nst = 27 if dim == 3 else 9
     nq = (nst - 1) // 2 * dim * dim + dim * (dim + 1) // 2
     flops = 2.0 * nst * dim * dim * n1
-    byts = (nq + 3 * dim + 0.5 * dim * dim) * 4 * n1
+    byts = ((nq + 3 * dim) * 4 + extra(4)) * n1
     return flops, byts
 
 
-def roofline_entry(cls, launches, total_ms, H, p):
+def roofline_entry(cls, launches, total_ms, H, p, args):
     avg_s = total_ms / 1e3 / max(launches, 1)
-    flops, byts = algorithmic(cls, H, p)
+    flops, byts = algorithmic(cls, H, p, args)
     if cls == 2:
         ach = byts / avg_s / 1e9
         e = {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK["hbm_GBs"], "unit": "GB/s",
@@ -116,7 +150,7 @@ def roofline_entry(cls, launches, total_ms, H, p):
         e = {"bound": "alu", "achieved": round(ach, 2), "peak": peak, "unit": "TFLOP/s",
              "frac": round(ach / peak, 4)}
     e.update({"kernel": {0: "fine operator FP64 (q = K~p, outer loop)",
-                         1: "fine operator FP32 (V-cycle residual / smoothing)",
+                         1: "fine operator FP32 (V-cycle smoothing / residual)",
                          2: "level-1 stencil operator FP32 (V-cycle)"}[cls],
               "launches": launches, "avg_us": round(avg_s * 1e6, 2),
               "algorithmic_flops_per_launch": flops, "algorithmic_bytes_per_launch": byts,
@@ -126,13 +160,13 @@ def roofline_entry(cls, launches, total_ms, H, p):
     tp = os.path.join(ROOT, "profiles", f"traffic_class{cls}.json")
     if os.path.exists(tp):
         t = json.load(open(tp))
-        if t.get("source_sha") == src_hash(KERNEL_SOURCES[cls]):
+        if t.get("source_sha") == src_hash(KERNEL_SOURCES[cls]) and t.get("mix") == [args.smoother, args.sweeps]:
             e["traffic"] = t.get("bytes_per_launch")
             e["traffic_ratio_to_algorithmic"] = round(t["bytes_per_launch"] / byts, 3)
     return e
 
 
-def cpu_baseline(cfg_name):
+def cpu_baseline(cfg_name, args):
     """Oracle (CPU, FP64, single thread) on a bounded sample of the same
     recipe; solve to rtol 1e-8 timed, setup excluded."""
     from threadpoolctl import threadpool_limits
@@ -153,14 +187,16 @@ def cpu_baseline(cfg_name):
     with threadpool_limits(limits=1):
         KE = fem.element_stiffness(p.dim, p.nu)
         E = fem.simp(p.rho, p.p, p.E0, p.Emin)
-        H = mg.build_geometric(p.nel, E, KE, p.fixed, L, omega=0.5, nu_pre=1, nu_post=1)
+        H = mg.build_geometric(p.nel, E, KE, p.fixed, L, omega=0.5, nu_pre=args.sweeps, nu_post=args.sweeps,
+                               smoother=args.smoother, cheb_lower=args.cheb_lower)
         reps = 3
         t0 = time.perf_counter()
         for _ in range(reps):
             r = mg.mg_pcg(H, p.loads[0], 1e-8)
         dt = (time.perf_counter() - t0) / reps
     return {"value": round(p.n_dof / dt / 1e6, 4), "unit": "MDoF/s", "cores": 1, "kind": "oracle",
-            "sample": sample, "seconds": round(dt, 3), "iters": r.iters,
+            "sample": sample + f", {args.smoother} {args.sweeps}/{args.sweeps} smoothing as on the GPU",
+            "seconds": round(dt, 3), "iters": r.iters,
             "host": platform.processor() or platform.machine(), "host_cpus": os.cpu_count()}
 
 
@@ -222,12 +258,17 @@ def main():
         del a, b
     f = torch.tensor(p.loads[0], device="cuda")
     rtol = 1e-8
+    opts = dict(wl["opts"])
+    if wl["levels"] is not None:
+        opts["n_levels"] = args.levels or wl["levels"]
 
     def build(vfp, outer):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        H = Hierarchy(p.nel, p.rho, p.fixed, p=p.p, E0=p.E0, Emin=p.Emin, nu=p.nu, omega=0.5, nu_pre=1,
-                      nu_post=1, vcycle_fp=vfp, outer=outer, fine_mfma=args.fine_mfma, **wl["opts"])
+        H = Hierarchy(p.nel, p.rho, p.fixed, p=p.p, E0=p.E0, Emin=p.Emin, nu=p.nu, omega=0.5,
+                      nu_pre=args.sweeps, nu_post=args.sweeps, smoother=SMOOTHERS[args.smoother],
+                      cheb_lower=args.cheb_lower, vcycle_fp=vfp,
+                      outer=outer, fine_mfma=args.fine_mfma, **opts)
         torch.cuda.synchronize()
         return H, time.perf_counter() - t0
 
@@ -237,6 +278,7 @@ def main():
     value = p.n_dof * args.steps / dt / 1e6
     detail = {"mixed": dict(iters=res.iters[0], relres=res.relres[0], compliance=res.compliance[0],
                             setup_ms=round(t_setup * 1e3, 2), levels=H.num_levels())}
+    coarsest = H.level_info(H.num_levels() - 1)["n_rows"]
     line = {
         "metric": "MDoF/s to rtol 1e-8 (FP32 V-cycle vs FP64 PCG)",
         "value": round(value, 2),
@@ -250,7 +292,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f32 V-cycle + f64 CG",
         "data": "synthetic",
-        "config": {"workload": wl["label"], "n_dof": p.n_dof, "iterations": res.iters[0]},
+        "config": {"workload": workload_label(wl, args, H.num_levels(), coarsest), "n_dof": p.n_dof,
+                   "iterations": res.iters[0]},
     }
     if not args.no_profile:
         classes = [0, 1, 2]
@@ -263,7 +306,7 @@ def main():
             n, tot = H.kernel_timing_read(c)
             H.kernel_timing(c, False)
             if n:
-                ents[c] = roofline_entry(c, n, tot, H, p)
+                ents[c] = roofline_entry(c, n, tot, H, p, args)
                 ents[c]["share_of_step_time"] = round(tot / ms, 4)
         if ents:
             dom = max(ents, key=lambda c: ents[c]["share_of_step_time"])
@@ -285,7 +328,7 @@ def main():
     if args.served > 0:
         line["served"] = served_leg(args.served, args.served_designs)
     if not args.no_cpu_baseline:
-        cb = cpu_baseline(wl["cfg"])
+        cb = cpu_baseline(wl["cfg"], args)
         if cb:
             line["cpu_baseline"] = cb
     print(json.dumps(line), flush=True)

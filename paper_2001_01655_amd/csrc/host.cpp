@@ -528,7 +528,7 @@ static void vcycle(tm_hierarchy* h, Vcyc& V, const T* b0, T* z, const int* done,
     // Chebyshev step k on level l (k = 0: from the current iterate with no
     // previous direction): coefficients of d_k = c1 d_{k-1} + c2 D^-1 r_k.
     // After a zero start the direction d_0 is the first iterate itself.
-    auto cheb_args = [&](int l, int k, const T* x, bool zero_start) {
+    auto cheb_args = [&](int l, int k, const T* x, bool zero_start, bool last) {
         const double th = h->lv[l].cheb_theta, de = h->lv[l].cheb_delta, sigma = th / de;
         double rho = de / th, c1 = 0.0, c2 = 1.0 / th;
         for (int q = 1; q <= k; ++q) {
@@ -539,7 +539,7 @@ static void vcycle(tm_hierarchy* h, Vcyc& V, const T* b0, T* z, const int* done,
         }
         ChebArgs ch;
         ch.din = (k == 0 || (k == 1 && zero_start)) ? (const void*)x : V.d[l];
-        ch.dout = V.d[l];
+        ch.dout = last ? nullptr : V.d[l];   // the last step of a smoothing phase leaves no direction behind
         ch.c1 = k == 0 ? 0.0 : c1;
         ch.c2 = c2;
         return ch;
@@ -551,7 +551,7 @@ static void vcycle(tm_hierarchy* h, Vcyc& V, const T* b0, T* z, const int* done,
         if (l == 0 && !first_done) launch_first_smooth<T>(h->lv[0], b, x, (T)first_sweep_weight(h, 0), done, s);
         for (int k = 1; k < npre; ++k) {
             // from a zero start the first step's direction is the first iterate
-            if (cheb) level_op<T>(h, l, OP_CHEB, x, b, t, done, s, cheb_args(l, k, x, true));
+            if (cheb) level_op<T>(h, l, OP_CHEB, x, b, t, done, s, cheb_args(l, k, x, true, k == npre - 1));
             else level_op<T>(h, l, OP_SMOOTH, x, b, t, done, s);
             std::swap(x, t);
         }
@@ -570,7 +570,7 @@ static void vcycle(tm_hierarchy* h, Vcyc& V, const T* b0, T* z, const int* done,
         prolong_from<T>(h, l, xr[l + 1], x, done, s);
         for (int k = 0; k < npost; ++k) {
             T* dst = (l == 0 && k == npost - 1) ? z : t;
-            if (cheb) level_op<T>(h, l, OP_CHEB, x, b, dst, done, s, cheb_args(l, k, x, false));
+            if (cheb) level_op<T>(h, l, OP_CHEB, x, b, dst, done, s, cheb_args(l, k, x, false, k == npost - 1));
             else level_op<T>(h, l, OP_SMOOTH, x, b, dst, done, s);
             if (!(l == 0 && k == npost - 1)) std::swap(x, t);
         }

@@ -203,7 +203,7 @@ __device__ __forceinline__ void finish_node(int64_t node, int64_t N, T (&kx)[BS]
 #pragma unroll
             for (int c = 0; c < BS; ++c) t += dinv[(int64_t)(r * BS + c) * N + node] * rr[c];
             const T dn = c1 * din[BS * node + r] + c2 * t;
-            dout[BS * node + r] = dn;
+            if (dout) dout[BS * node + r] = dn;           // null: no later step reads it
             y[BS * node + r] = xo[r] + dn;
         }
     } else {  // OP_QDOT: q = K~ p, partial p.q and p.r (b holds r)

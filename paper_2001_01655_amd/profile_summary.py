@@ -2,7 +2,7 @@
 
     python -m paper_2001_01655_amd.profile_summary stats  <kernel_stats.csv> <out.md> "<command>"
     python -m paper_2001_01655_amd.profile_summary traffic <fetch_counter_collection.csv> \
-           <write_counter_collection.csv> <out_dir> "<command>"
+           <write_counter_collection.csv> <out_dir> "<command>" <smoother> <sweeps>
 
 `stats` writes the per-kernel time table.  `traffic` turns FETCH_SIZE and
 WRITE_SIZE (KiB per dispatch) into HBM bytes per launch for the benchmark's
@@ -21,12 +21,13 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 COPY_BYTES = 256 << 20
 CLASSES = {
-    0: dict(match=["k_fine3<double, 3, false>"], source="kernels_fine.hip",
+    0: dict(match=["k_fine3<double, 3, false>"], source=["kernels_fine.hip", "tm_device.h"],
             what="fine operator FP64 (q = K~p, outer loop)"),
-    1: dict(match=["k_fine3<float, 1, false>", "k_fine3<float, 2, false>"], source="kernels_fine.hip",
-            what="fine operator FP32 (V-cycle residual / smoothing)"),
-    2: dict(match=["k_stencil_op<float, 3, 1, 3>", "k_stencil_op<float, 3, 2, 3>"], source="kernels_coarse.hip",
-            what="level-1 stencil operator FP32 (V-cycle)", largest_grid=True),
+    1: dict(match=["k_fine3<float, 1, false>", "k_fine3<float, 2, false>", "k_fine3<float, 4, false>"],
+            source=["kernels_fine.hip", "tm_device.h"], what="fine operator FP32 (V-cycle smoothing / residual)"),
+    2: dict(match=["k_stencil_op<float, 3, 1, 3>", "k_stencil_op<float, 3, 2, 3>", "k_stencil_op<float, 3, 4, 3>"],
+            source=["kernels_coarse.hip", "tm_device.h"], what="level-1 stencil operator FP32 (V-cycle)",
+            largest_grid=True),
 }
 
 
@@ -52,7 +53,7 @@ def _per_dispatch(path: str):
     return [(r["Kernel_Name"], int(r["Grid_Size"]), float(r["Counter_Value"]) * 1024.0) for r in rows]
 
 
-def traffic(fetch_csv: str, write_csv: str, out_dir: str, command: str) -> None:
+def traffic(fetch_csv: str, write_csv: str, out_dir: str, command: str, smoother: str, sweeps: int) -> None:
     fe, wr = _per_dispatch(fetch_csv), _per_dispatch(write_csv)
     cf = max((v for n, g, v in fe if "copyBuffer" in n), default=None)
     cw = max((v for n, g, v in wr if "copyBuffer" in n), default=None)
@@ -76,11 +77,13 @@ def traffic(fetch_csv: str, write_csv: str, out_dir: str, command: str) -> None:
         fb = sum(v for _, _, v in f_rows) / len(f_rows)
         wb = sum(v for _, _, v in w_rows) / len(w_rows)
         per = fb * kf + wb * kw
-        src = open(os.path.join(HERE, "csrc", spec["source"]), "rb").read()
+        h = hashlib.sha256()
+        for n in spec["source"]:
+            h.update(open(os.path.join(HERE, "csrc", n), "rb").read())
         rec = {"class": c, "kernel": spec["what"], "kernels": spec["match"], "launches": len(f_rows),
                "fetch_bytes_raw": fb, "write_bytes_raw": wb, "fetch_factor": kf, "write_factor": kw,
                "bytes_per_launch": per, "source": spec["source"],
-               "source_sha": hashlib.sha256(src).hexdigest()[:16], "command": command}
+               "source_sha": h.hexdigest()[:16], "mix": [smoother, sweeps], "command": command}
         json.dump(rec, open(os.path.join(out_dir, f"traffic_class{c}.json"), "w"), indent=1)
         summary.append(f"| {c} | {spec['what']} | {len(f_rows)} | {fb / 1e6:.1f} | {wb / 1e6:.1f} | {per / 1e6:.1f} |")
     open(os.path.join(out_dir, "traffic_cantilever3d.md"), "w").write("\n".join(summary) + "\n")
@@ -90,6 +93,6 @@ if __name__ == "__main__":
     if sys.argv[1] == "stats":
         stats(sys.argv[2], sys.argv[3], sys.argv[4])
     elif sys.argv[1] == "traffic":
-        traffic(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5])
+        traffic(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5], sys.argv[6], int(sys.argv[7]))
     else:
         raise SystemExit(__doc__)

@@ -11,10 +11,13 @@ from oracle import fem
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
+# (problem, options); the Chebyshev 2/2 cantilever is the benchmark's configuration
+CHEB22 = dict(smoother=2, nu_pre=2, nu_post=2)
 CONFIGS = {
-    "cantilever2d": dict(n_levels=7, max_iters=20000),
-    "cantilever3d": dict(n_levels=6),
-    "bridge3d": dict(n_geometric=3, max_coarse=1000),
+    "cantilever2d": ("cantilever2d", dict(n_levels=7, max_iters=20000)),
+    "cantilever3d": ("cantilever3d", dict(n_levels=6)),
+    "cantilever3d_cheb": ("cantilever3d", dict(n_levels=6, **CHEB22)),
+    "bridge3d": ("bridge3d", dict(n_geometric=3, max_coarse=1000)),
 }
 
 
@@ -40,8 +43,9 @@ def _check(p, res, k=0):
 def test_full_size_solve(name):
     from paper_2001_01655_amd import Hierarchy
     print(f"full size {name}", flush=True)
-    p = synth.get(name)
-    H = Hierarchy(p.nel, p.rho, p.fixed, p=p.p, E0=p.E0, Emin=p.Emin, nu=p.nu, **CONFIGS[name])
+    prob, opts = CONFIGS[name]
+    p = synth.get(prob)
+    H = Hierarchy(p.nel, p.rho, p.fixed, p=p.p, E0=p.E0, Emin=p.Emin, nu=p.nu, **opts)
     res = H.solve(torch.tensor(p.loads[0], device="cuda"), rtol=1e-8)
     assert res.status == 0
     _check(p, res)
@@ -55,13 +59,14 @@ def test_full_size_solve(name):
     H.close()
 
 
-def test_mixed_equals_fp64_at_full_size():
+@pytest.mark.parametrize("opts", [{}, CHEB22], ids=["jacobi", "chebyshev"])
+def test_mixed_equals_fp64_at_full_size(opts):
     from paper_2001_01655_amd import Hierarchy
     p = synth.get("cantilever3d")
     f = torch.tensor(p.loads[0], device="cuda")
     us = []
     for vfp, outer in [(32, 0), (64, 1)]:
-        H = Hierarchy(p.nel, p.rho, p.fixed, n_levels=6, vcycle_fp=vfp, outer=outer)
+        H = Hierarchy(p.nel, p.rho, p.fixed, n_levels=6, vcycle_fp=vfp, outer=outer, **opts)
         r = H.solve(f, rtol=1e-8)
         assert r.status == 0
         us.append(r.u.clone())
