@@ -335,6 +335,113 @@ const double* dinv_of<double>(const Level& L) { return L.dinv64; }
 template <>
 const float* dinv_of<float>(const Level& L) { return L.dinv32; }
 
+// The same operator with P lanes per node (small levels, where a launch is
+// one latency chain): lane p takes the neighbours p, p + P, ... in one batch of
+// loads with uniform control flow (the slot's kind, upper / lower / diagonal,
+// only selects addresses) that also carries the finishing step's operands,
+// then the P partial sums meet in a butterfly and the node's first lane finishes.
+template <typename T, int DIM, int OP, int P>
+__global__ __launch_bounds__(WG) void k_stencil_split(const T* __restrict__ st, int nx, int ny, int nz,
+                                                      int64_t N, const T* __restrict__ x,
+                                                      const T* __restrict__ b, T* __restrict__ y,
+                                                      const T* __restrict__ dinv, T omega,
+                                                      const int* __restrict__ done, const ChebArgs ch) {
+    if (done && *done) return;
+    const int64_t gid = xcd_block() * WG + threadIdx.x;
+    const int64_t node = gid / P;
+    const int p = (int)(gid & (P - 1));
+    if (node >= N) return;      // all P lanes of a node leave together
+    constexpr int BB = DIM * DIM, NST = DIM == 3 ? 27 : 9, NU = (NST - 1) / 2;
+    constexpr int NQ = NU * BB + DIM * (DIM + 1) / 2;
+    constexpr int NS = (NST + P - 1) / P;
+    const int NX = nx + 1, NY = ny + 1, NZ = nz + 1;
+    const int i = (int)(node % NX);
+    const int j = (int)((node / NX) % NY);
+    const int k = DIM == 3 ? (int)(node / ((int64_t)NX * NY)) : 0;
+    const auto sr = buf_rsrc(st, (int64_t)N * NQ * sizeof(T));
+    const auto xr = buf_rsrc(x, (int64_t)N * DIM * sizeof(T));
+    const uint32_t un = (uint32_t)node, uN = (uint32_t)N;
+    uint32_t ci[3], cj[3], ck[3];
+    bool ii[3], ij[3], ik[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        ci[d] = (uint32_t)min(max(i + d - 1, 0), NX - 1);
+        cj[d] = (uint32_t)min(max(j + d - 1, 0), NY - 1);
+        ck[d] = DIM == 3 ? (uint32_t)min(max(k + d - 1, 0), NZ - 1) : 0u;
+        ii[d] = i + d - 1 >= 0 && i + d - 1 < NX;
+        ij[d] = j + d - 1 >= 0 && j + d - 1 < NY;
+        ik[d] = DIM == 2 || (k + d - 1 >= 0 && k + d - 1 < NZ);
+    }
+    T xo[DIM];
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) xo[c] = bld<T>(xr, (DIM * un + c) * (uint32_t)sizeof(T));
+    FinIn<T, DIM> fin;
+    finish_load<T, DIM, OP>(node, N, b, dinv, ch, fin);
+    T xv[NS][DIM], blk[NS][BB];
+#pragma unroll
+    for (int sl = 0; sl < NS; ++sl) {
+        const int o = sl * P + p;
+        const bool valid = o < NST;
+        const int oc = valid ? o : NST - 1;    // spare slot: any in-bounds block, x zeroed below
+        const int dx = oc % 3, dy = (oc / 3) % 3, dz = DIM == 3 ? oc / 9 : 1;
+        const uint32_t J = (ck[dz] * (uint32_t)NY + cj[dy]) * (uint32_t)NX + ci[dx];
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) xv[sl][c] = bld<T>(xr, (DIM * J + c) * (uint32_t)sizeof(T));
+        const bool up = oc > NU, lo = oc < NU;
+        // upper: own block towards neighbour oc; lower: neighbour J's block
+        // towards this node, transposed; diagonal: own upper triangle
+        const uint32_t qU = (uint32_t)(oc - NU - 1) * BB, qL = (uint32_t)(NST - 1 - oc - NU - 1) * BB;
+        const uint32_t at = lo ? J : un;
+#pragma unroll
+        for (int r = 0; r < DIM; ++r)
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) {
+                const int lr = r < c ? r : c, hc = r < c ? c : r;
+                const uint32_t qd = (uint32_t)(NU * BB + lr * DIM - lr * (lr - 1) / 2 + (hc - lr));
+                const uint32_t q = up ? qU + (uint32_t)(r * DIM + c) : (lo ? qL + (uint32_t)(c * DIM + r) : qd);
+                blk[sl][r * DIM + c] = bld<T>(sr, (q * uN + at) * (uint32_t)sizeof(T));
+            }
+        const bool keep = valid && (!lo || (ii[dx] && ij[dy] && ik[dz]));
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) xv[sl][c] = keep ? xv[sl][c] : T(0);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    T acc[DIM] = {};
+#pragma unroll
+    for (int sl = 0; sl < NS; ++sl)
+#pragma unroll
+        for (int r = 0; r < DIM; ++r)
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) acc[r] += blk[sl][r * DIM + c] * xv[sl][c];
+#pragma unroll
+    for (int m = 1; m < P; m <<= 1)
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) acc[c] += __shfl_xor(acc[c], m, 64);
+    if (p == 0) {
+        double dots[2];
+        finish_store<T, DIM, OP>(node, acc, xo, 0, fin, y, omega, dots, ch);
+    }
+}
+
+template <typename T, int DIM, int P>
+static void stencil_split_launch(const Level& L, int op, const T* x, const T* b, T* y, T omega,
+                                 const int* done, hipStream_t s, const ChebArgs& ch) {
+    const dim3 g(grid_for(L.n_nodes * P)), blk(WG);
+    const T* st = st_of<T>(L);
+    const T* dv = dinv_of<T>(L);
+    const int nz = DIM == 3 ? L.nel[2] : 0;
+#define TM_SL(OPV)                                                                                   \
+    hipLaunchKernelGGL((k_stencil_split<T, DIM, OPV, P>), g, blk, 0, s, st, L.nel[0], L.nel[1], nz, L.n_nodes, \
+                       x, b, y, dv, omega, done, ch)
+    switch (op) {
+        case OP_APPLY: TM_SL(OP_APPLY); break;
+        case OP_RESID: TM_SL(OP_RESID); break;
+        case OP_CHEB: TM_SL(OP_CHEB); break;
+        default: TM_SL(OP_SMOOTH); break;
+    }
+#undef TM_SL
+}
+
 template <typename T, int DIM, int G>
 static void stencil_launch(const Level& L, int op, const T* x, const T* b, T* y, T omega, const int* done,
                            hipStream_t s, const ChebArgs& ch) {
@@ -357,9 +464,14 @@ static void stencil_launch(const Level& L, int op, const T* x, const T* b, T* y,
 template <typename T, int DIM>
 static void stencil_dispatch(const Level& L, int op, const T* x, const T* b, T* y, T omega,
                              const int* done, hipStream_t s, const ChebArgs& ch) {
-    // fewer workgroups than compute units: latency-bound, batch more loads
-    if (grid_for(L.n_nodes) < 256)
-        stencil_launch<T, DIM, 9>(L, op, x, b, y, omega, done, s, ch);
+    // fewer workgroups than compute units: latency-bound; 3D splits each
+    // node over 4 lanes, 2D batches all nine neighbours
+    if (grid_for(L.n_nodes) < 256) {
+        if constexpr (DIM == 3)
+            stencil_split_launch<T, DIM, 4>(L, op, x, b, y, omega, done, s, ch);
+        else
+            stencil_launch<T, DIM, 9>(L, op, x, b, y, omega, done, s, ch);
+    }
     else
         stencil_launch<T, DIM, DIM == 3 ? 3 : 4>(L, op, x, b, y, omega, done, s, ch);
 }
@@ -416,6 +528,11 @@ __global__ __launch_bounds__(WG) void k_restrict(const T* __restrict__ rf, const
         for (int c = 0; c < DIM; ++c) v[q][c] = bld<T>(rr, (DIM * f + c) * (uint32_t)sizeof(T));
         m[q] = MASK ? nm[f] : (uint8_t)0;
     }
+    T dv[DIM * DIM];
+    if (FIRST) {
+#pragma unroll
+        for (int e = 0; e < DIM * DIM; ++e) dv[e] = dinv[(int64_t)e * Nc + node];
+    }
     T acc[DIM] = {};
 #pragma unroll
     for (int q = 0; q < NS; ++q)
@@ -428,7 +545,7 @@ __global__ __launch_bounds__(WG) void k_restrict(const T* __restrict__ rf, const
         for (int r = 0; r < DIM; ++r) {
             T t = 0;
 #pragma unroll
-            for (int c = 0; c < DIM; ++c) t += dinv[(int64_t)(r * DIM + c) * Nc + node] * acc[c];
+            for (int c = 0; c < DIM; ++c) t += dv[r * DIM + c] * acc[c];
             xc[DIM * node + r] = omega * t;
         }
     }

@@ -165,11 +165,37 @@ __device__ void store_dinv(double (&D)[BS][BS], int point, int64_t node, int64_t
 }
 
 // ------------------------------------------------------------ operator kernels
+// Operands of a node's finishing step, loaded apart from the arithmetic so
+// that latency-bound kernels can issue them together with their gathers.
+template <typename T, int BS>
+struct FinIn {
+    T b[BS];
+    T dv[BS * BS];
+    T din[BS];
+};
+
 template <typename T, int BS, int OP>
-__device__ __forceinline__ void finish_node(int64_t node, int64_t N, T (&kx)[BS], const T (&xo)[BS],
-                                            uint8_t m, const T* __restrict__ b, T* __restrict__ y,
-                                            const T* __restrict__ dinv, T omega, double (&dots)[2],
-                                            const ChebArgs& ch = ChebArgs{}) {
+__device__ __forceinline__ void finish_load(int64_t node, int64_t N, const T* __restrict__ b,
+                                            const T* __restrict__ dinv, const ChebArgs& ch, FinIn<T, BS>& f) {
+    if (OP != OP_APPLY) {
+#pragma unroll
+        for (int c = 0; c < BS; ++c) f.b[c] = b[BS * node + c];
+    }
+    if (OP == OP_SMOOTH || OP == OP_CHEB) {
+#pragma unroll
+        for (int e = 0; e < BS * BS; ++e) f.dv[e] = dinv[(int64_t)e * N + node];
+    }
+    if (OP == OP_CHEB) {
+        const T* din = (const T*)ch.din;
+#pragma unroll
+        for (int r = 0; r < BS; ++r) f.din[r] = din[BS * node + r];
+    }
+}
+
+template <typename T, int BS, int OP>
+__device__ __forceinline__ void finish_store(int64_t node, T (&kx)[BS], const T (&xo)[BS], uint8_t m,
+                                             const FinIn<T, BS>& f, T* __restrict__ y, T omega,
+                                             double (&dots)[2], const ChebArgs& ch) {
 #pragma unroll
     for (int c = 0; c < BS; ++c)
         if (m & (1u << c)) kx[c] = xo[c];               // unit row of a supported dof
@@ -178,31 +204,30 @@ __device__ __forceinline__ void finish_node(int64_t node, int64_t N, T (&kx)[BS]
         for (int c = 0; c < BS; ++c) y[BS * node + c] = kx[c];
     } else if (OP == OP_RESID) {
 #pragma unroll
-        for (int c = 0; c < BS; ++c) y[BS * node + c] = b[BS * node + c] - kx[c];
+        for (int c = 0; c < BS; ++c) y[BS * node + c] = f.b[c] - kx[c];
     } else if (OP == OP_SMOOTH) {
         T rr[BS];
 #pragma unroll
-        for (int c = 0; c < BS; ++c) rr[c] = b[BS * node + c] - kx[c];
+        for (int c = 0; c < BS; ++c) rr[c] = f.b[c] - kx[c];
 #pragma unroll
         for (int r = 0; r < BS; ++r) {
             T t = 0;
 #pragma unroll
-            for (int c = 0; c < BS; ++c) t += dinv[(int64_t)(r * BS + c) * N + node] * rr[c];
+            for (int c = 0; c < BS; ++c) t += f.dv[r * BS + c] * rr[c];
             y[BS * node + r] = xo[r] + omega * t;
         }
     } else if (OP == OP_CHEB) {
         T rr[BS];
 #pragma unroll
-        for (int c = 0; c < BS; ++c) rr[c] = b[BS * node + c] - kx[c];
-        const T* din = (const T*)ch.din;
+        for (int c = 0; c < BS; ++c) rr[c] = f.b[c] - kx[c];
         T* dout = (T*)ch.dout;
         const T c1 = (T)ch.c1, c2 = (T)ch.c2;
 #pragma unroll
         for (int r = 0; r < BS; ++r) {
             T t = 0;
 #pragma unroll
-            for (int c = 0; c < BS; ++c) t += dinv[(int64_t)(r * BS + c) * N + node] * rr[c];
-            const T dn = c1 * din[BS * node + r] + c2 * t;
+            for (int c = 0; c < BS; ++c) t += f.dv[r * BS + c] * rr[c];
+            const T dn = c1 * f.din[r] + c2 * t;
             if (dout) dout[BS * node + r] = dn;           // null: no later step reads it
             y[BS * node + r] = xo[r] + dn;
         }
@@ -211,9 +236,21 @@ __device__ __forceinline__ void finish_node(int64_t node, int64_t N, T (&kx)[BS]
         for (int c = 0; c < BS; ++c) {
             y[BS * node + c] = kx[c];
             dots[0] += (double)xo[c] * (double)kx[c];
-            dots[1] += (double)xo[c] * (double)b[BS * node + c];
+            dots[1] += (double)xo[c] * (double)f.b[c];
         }
     }
+}
+
+// y from the operator value kx = (A x)_node: apply, residual, damped block
+// Jacobi sweep, Chebyshev step, or q = A p with the partial dots p.q, p.r
+template <typename T, int BS, int OP>
+__device__ __forceinline__ void finish_node(int64_t node, int64_t N, T (&kx)[BS], const T (&xo)[BS],
+                                            uint8_t m, const T* __restrict__ b, T* __restrict__ y,
+                                            const T* __restrict__ dinv, T omega, double (&dots)[2],
+                                            const ChebArgs& ch = ChebArgs{}) {
+    FinIn<T, BS> f;
+    finish_load<T, BS, OP>(node, N, b, dinv, ch, f);
+    finish_store<T, BS, OP>(node, kx, xo, m, f, y, omega, dots, ch);
 }
 
 }  // namespace tmi
