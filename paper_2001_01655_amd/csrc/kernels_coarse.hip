@@ -524,8 +524,12 @@ __global__ __launch_bounds__(WG) void k_restrict(const T* __restrict__ rf, const
         const int gk = DIM == 3 ? min(max(fk, 0), FZ - 1) : 0;
         const uint32_t f = (uint32_t)(DIM == 3 ? (gk * FY + gj) * FX + gi : gj * FX + gi);
         w[q] = in ? (dx ? T(0.5) : T(1)) * (dy ? T(0.5) : T(1)) * (dz ? T(0.5) : T(1)) : T(0);
+        if constexpr (DIM == 3) {
+            bld3(rr, f * (uint32_t)(3 * sizeof(T)), v[q]);
+        } else {
 #pragma unroll
-        for (int c = 0; c < DIM; ++c) v[q][c] = bld<T>(rr, (DIM * f + c) * (uint32_t)sizeof(T));
+            for (int c = 0; c < DIM; ++c) v[q][c] = bld<T>(rr, (DIM * f + c) * (uint32_t)sizeof(T));
+        }
         m[q] = MASK ? nm[f] : (uint8_t)0;
     }
     T dv[DIM * DIM];
@@ -605,23 +609,41 @@ __global__ __launch_bounds__(WG) void k_prolong(const T* __restrict__ xc, const 
     const T wi[2] = {(i & 1) ? T(0.5) : T(1), (i & 1) ? T(0.5) : T(0)};
     const T wj[2] = {(j & 1) ? T(0.5) : T(1), (j & 1) ? T(0.5) : T(0)};
     const T wk[2] = {(k & 1) ? T(0.5) : T(1), (k & 1) ? T(0.5) : T(0)};
+    // all loads (the coarse corners, this node's value and mask) before the
+    // arithmetic; the store is unconditional (supported dofs keep their value)
+    const int64_t Nc = (int64_t)CX * CY * (DIM == 3 ? CZ : 1);
+    const auto cr = buf_rsrc(xc, Nc * DIM * sizeof(T));
+    const auto fr = buf_rsrc(xf, Nf * DIM * sizeof(T));
+    constexpr int NC = DIM == 3 ? 8 : 4;
+    T v[NC][DIM], xo[DIM];
+#pragma unroll
+    for (int q = 0; q < NC; ++q) {
+        const int a2 = q & 1, b2 = (q >> 1) & 1, c2 = q >> 2;
+        const uint32_t C = (uint32_t)(DIM == 3 ? (ka[c2] * CY + ja[b2]) * CX + ia[a2] : ja[b2] * CX + ia[a2]);
+        if constexpr (DIM == 3) {
+            bld3(cr, C * (uint32_t)(3 * sizeof(T)), v[q]);
+        } else {
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) v[q][c] = bld<T>(cr, (DIM * C + c) * (uint32_t)sizeof(T));
+        }
+    }
+    if constexpr (DIM == 3) {
+        bld3(fr, (uint32_t)node * (uint32_t)(3 * sizeof(T)), xo);
+    } else {
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) xo[c] = bld<T>(fr, (DIM * (uint32_t)node + c) * (uint32_t)sizeof(T));
+    }
+    const uint8_t m = nm ? nm[node] : 0;
     T acc[DIM] = {};
 #pragma unroll
-    for (int c2 = 0; c2 < (DIM == 3 ? 2 : 1); ++c2)
+    for (int q = 0; q < NC; ++q) {
+        const int a2 = q & 1, b2 = (q >> 1) & 1, c2 = q >> 2;
+        const T w = wi[a2] * wj[b2] * (DIM == 3 ? wk[c2] : T(1));
 #pragma unroll
-        for (int b2 = 0; b2 < 2; ++b2)
+        for (int c = 0; c < DIM; ++c) acc[c] += w * v[q][c];
+    }
 #pragma unroll
-            for (int a2 = 0; a2 < 2; ++a2) {
-                const int64_t C = DIM == 3 ? ((int64_t)ka[c2] * CY + ja[b2]) * CX + ia[a2]
-                                           : (int64_t)ja[b2] * CX + ia[a2];
-                const T w = wi[a2] * wj[b2] * (DIM == 3 ? wk[c2] : T(1));
-#pragma unroll
-                for (int c = 0; c < DIM; ++c) acc[c] += w * xc[DIM * C + c];
-            }
-    const uint8_t m = nm ? nm[node] : 0;
-#pragma unroll
-    for (int c = 0; c < DIM; ++c)
-        if (!(m & (1u << c))) xf[DIM * node + c] += acc[c];
+    for (int c = 0; c < DIM; ++c) xf[DIM * node + c] = ((m >> c) & 1u) ? xo[c] : xo[c] + acc[c];
 }
 
 template <typename T>

@@ -62,25 +62,50 @@ void launch_fill(void* p, int64_t n_bytes, hipStream_t s) {
 // updates the scalars of its right-hand side.
 constexpr int FB = 1024;
 
-__device__ __forceinline__ double fin_sum(const double* part, int nparts, int q) {
-    __shared__ double red[FB / 64];
-    double a = 0.0;
-    for (int i = threadIdx.x; i < nparts; i += FB) a += part[(int64_t)q * nparts + i];
+// NQ sums of nparts partials each (quantity q at part[q * nparts + i]): every
+// thread issues eight loads per quantity before adding them (one round trip
+// per 8 * FB partials), then a fixed-shape tree over lanes and waves
+template <int NQ>
+__device__ __forceinline__ void fin_sums(const double* part, int nparts, double (&out)[NQ]) {
+    __shared__ double red[NQ][FB / 64];
+    double a[NQ];
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) a += __shfl_down(a, o, 64);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = a;
-    __syncthreads();
-    double t = 0.0;
+    for (int q = 0; q < NQ; ++q) a[q] = 0.0;
+    for (int i0 = 0; i0 < nparts; i0 += 8 * FB) {
+        double v[NQ][8];
 #pragma unroll
-    for (int w = 0; w < FB / 64; ++w) t += red[w];
+        for (int u = 0; u < 8; ++u) {
+            const int i = i0 + u * FB + (int)threadIdx.x;
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) v[q][u] = i < nparts ? part[(int64_t)q * nparts + i] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+            a[q] += ((v[q][0] + v[q][1]) + (v[q][2] + v[q][3])) + ((v[q][4] + v[q][5]) + (v[q][6] + v[q][7]));
+    }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) a[q] += __shfl_down(a[q], o, 64);
+        if ((threadIdx.x & 63) == 0) red[q][threadIdx.x >> 6] = a[q];
+    }
     __syncthreads();
-    return t;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        double t = 0.0;
+#pragma unroll
+        for (int w = 0; w < FB / 64; ++w) t += red[q][w];
+        out[q] = t;
+    }
+    __syncthreads();
 }
 
 __global__ __launch_bounds__(FB) void k_finalize(KScal* sc, const double* part, int nparts, int what) {
     if (sc->done) return;
     if (what == FIN_ALPHA) {
-        const double pq = fin_sum(part, nparts, 0), pr = fin_sum(part, nparts, 1);
+        double t[2];
+        fin_sums<2>(part, nparts, t);
+        const double pq = t[0], pr = t[1];
         if (threadIdx.x == 0) {
             sc->pq = pq;
             sc->pr = pr;
@@ -93,7 +118,9 @@ __global__ __launch_bounds__(FB) void k_finalize(KScal* sc, const double* part, 
             }
         }
     } else if (what == FIN_RR) {
-        const double rr = fin_sum(part, nparts, 0);
+        double t[1];
+        fin_sums<1>(part, nparts, t);
+        const double rr = t[0];
         if (threadIdx.x == 0) {
             sc->rr = rr;
             sc->rr_last = rr;
@@ -111,7 +138,9 @@ __global__ __launch_bounds__(FB) void k_finalize(KScal* sc, const double* part, 
         }
     } else {
         // beta; on the first call (iter == 0, no previous direction) only z^T r is kept
-        const double zq = fin_sum(part, nparts, 0), zr = fin_sum(part, nparts, 1);
+        double t[2];
+        fin_sums<2>(part, nparts, t);
+        const double zq = t[0], zr = t[1];
         if (threadIdx.x == 0) {
             sc->zq = zq;
             sc->zr = zr;
@@ -148,7 +177,9 @@ __global__ void k_init_dots(const double* __restrict__ f, const double* __restri
 
 __global__ __launch_bounds__(FB) void k_init_scalars(KScal* sc, const double* part, int nparts,
                                                     double rtol, int max_iters, int outer) {
-    const double ff = fin_sum(part, nparts, 0), rr = fin_sum(part, nparts, 1);
+    double t[2];
+    fin_sums<2>(part, nparts, t);
+    const double ff = t[0], rr = t[1];
     if (threadIdx.x == 0) {
         sc->ff = ff;
         sc->rr = rr;
@@ -296,7 +327,9 @@ __global__ void k_final_dots(const double* __restrict__ f, const double* __restr
 }
 
 __global__ __launch_bounds__(FB) void k_final_scalars(KScal* sc, const double* part, int nparts) {
-    const double tt = fin_sum(part, nparts, 0), fu = fin_sum(part, nparts, 1);
+    double t2[2];
+    fin_sums<2>(part, nparts, t2);
+    const double tt = t2[0], fu = t2[1];
     if (threadIdx.x == 0) {
         sc->pq = tt;
         sc->zq = fu;
