@@ -239,12 +239,30 @@ __global__ __launch_bounds__(WG) void k_fine3(const T* __restrict__ E, const KeV
     const uint32_t NX = nx + 1, NY = ny + 1, NZ = nz + 1;
     const uint32_t nd = live ? node : 0u;
     const uint32_t i = nd % NX, tq = nd / NX, j = tq % NY, k = tq / NY;
-    const uint32_t cx[3] = {i ? i - 1 : 0u, i, min(i + 1, NX - 1)};
-    const uint32_t cy[3] = {j ? j - 1 : 0u, j, min(j + 1, NY - 1)};
-    const uint32_t cz[3] = {k ? k - 1 : 0u, k, min(k + 1, NZ - 1)};
+    // neighbour node = node + ox[dx] + oy[dy] + oz[dz], clamped to the grid
+    // (the operator zeroes what lies outside): additions only, no per-neighbour
+    // integer multiplies (quarter rate)
+    const uint32_t PL = NX * NY;
+    const uint32_t ox[3] = {i ? 0u - 1u : 0u, 0u, i + 1 < NX ? 1u : 0u};
+    const uint32_t oy[3] = {j ? 0u - NX : 0u, 0u, j + 1 < NY ? NX : 0u};
+    const uint32_t oz[3] = {k ? 0u - PL : 0u, 0u, k + 1 < NZ ? PL : 0u};
+    constexpr uint32_t NB = 3u * sizeof(T);      // bytes per node
+    // byte offsets of the neighbours, as sums; the empty asm keeps the
+    // compiler from folding them back into one multiply per neighbour
+    uint32_t nb0 = nd * NB;
+    asm volatile("" : "+v"(nb0));
+    const uint32_t bx[3] = {i ? 0u - NB : 0u, 0u, i + 1 < NX ? NB : 0u};
+    const uint32_t by[3] = {j ? 0u - NX * NB : 0u, 0u, j + 1 < NY ? NX * NB : 0u};
+    const uint32_t bz[3] = {k ? 0u - PL * NB : 0u, 0u, k + 1 < NZ ? PL * NB : 0u};
     const auto xr = buf_rsrc(x, (int64_t)N * 3 * sizeof(T));
     const auto er = buf_rsrc(E, (int64_t)nx * ny * nz * sizeof(T));
-    // moduli of the 8 elements around the node, [ez][ey][ex]
+    // moduli of the 8 elements around the node, [ez][ey][ex]: element with
+    // lower corner (i-1+ex, j-1+ey, k-1+ez), index clamped, value zero outside
+    const uint32_t EX = (uint32_t)nx, EP = EX * (uint32_t)ny;
+    const uint32_t jE = j * EX, kE = k * EP;
+    const uint32_t gx[2] = {i ? i - 1 : 0u, i < EX ? i : i - 1};
+    const uint32_t gy[2] = {j ? jE - EX : 0u, j < (uint32_t)ny ? jE : jE - EX};
+    const uint32_t gz[2] = {k ? kE - EP : 0u, k < (uint32_t)nz ? kE : kE - EP};
     T Ee[2][2][2];
 #pragma unroll
     for (int ez = 0; ez < 2; ++ez)
@@ -252,26 +270,22 @@ __global__ __launch_bounds__(WG) void k_fine3(const T* __restrict__ E, const KeV
         for (int ey = 0; ey < 2; ++ey)
 #pragma unroll
             for (int ex = 0; ex < 2; ++ex) {
-                // element with lower corner (i-1+ex, j-1+ey, k-1+ez)
                 const bool in = (ex || i) && (ex == 0 || i < (uint32_t)nx) && (ey || j) &&
                                 (ey == 0 || j < (uint32_t)ny) && (ez || k) && (ez == 0 || k < (uint32_t)nz);
-                const uint32_t gx = min(i + ex, (uint32_t)nx) - (i + ex > 0 ? 1u : 0u);
-                const uint32_t gy = min(j + ey, (uint32_t)ny) - (j + ey > 0 ? 1u : 0u);
-                const uint32_t gz = min(k + ez, (uint32_t)nz) - (k + ez > 0 ? 1u : 0u);
-                Ee[ez][ey][ex] =
-                    in ? bld<T>(er, ((gz * (uint32_t)ny + gy) * (uint32_t)nx + gx) * (uint32_t)sizeof(T)) : T(0);
+                Ee[ez][ey][ex] = in ? bld<T>(er, (gz[ez] + gy[ey] + gx[ex]) * (uint32_t)sizeof(T)) : T(0);
             }
     T acc[3] = {0, 0, 0};
     T w[9][3];
     auto load_plane = [&](int dz) {
 #pragma unroll
         for (int dy = 0; dy < 3; ++dy) {
-            const uint32_t row = (cz[dz] * NY + cy[dy]) * NX;
+            const uint32_t row = nd + oz[dz] + oy[dy];
+            const uint32_t rowb = nb0 + bz[dz] + by[dy];
 #pragma unroll
             for (int dx = 0; dx < 3; ++dx) {
-                const uint32_t id = row + cx[dx];
+                const uint32_t id = row + ox[dx];
                 T a[3];
-                bld3(xr, id * (3u * sizeof(T)), a);
+                bld3(xr, rowb + bx[dx], a);
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     if (MASK_IN) a[c] = ((nm[id] >> c) & 1u) ? T(0) : a[c];
@@ -280,18 +294,27 @@ __global__ __launch_bounds__(WG) void k_fine3(const T* __restrict__ E, const KeV
             }
         }
     };
+    // the finishing step's operands (b, block inverse, direction, mask) are
+    // requested first, so that they arrive while the neighbours are gathered
+    FinIn<T, 3> fin;
+    finish_load<T, 3, OP>(nd, N, b, dinv, ch, fin);
+    const uint8_t mo = nm[nd];
     load_plane(0);
     layer_plane3<0, 0>(kc, w, Ee, acc);
     load_plane(1);
+    T xo[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) xo[c] = w[4][c];     // this node's own value
+    if (MASK_IN) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) xo[c] = x[3u * nd + c];
+    }
     layer_plane3<1, 0>(kc, w, Ee, acc);
     layer_plane3<1, 1>(kc, w, Ee, acc);
     load_plane(2);
     layer_plane3<2, 1>(kc, w, Ee, acc);
     double dots[2] = {0.0, 0.0};
-    if (live) {
-        const T xo[3] = {x[3u * node], x[3u * node + 1], x[3u * node + 2]};
-        finish_node<T, 3, OP>(node, N, acc, xo, nm[node], b, y, dinv, omega, dots, ch);
-    }
+    if (live) finish_store<T, 3, OP>(node, acc, xo, mo, fin, y, omega, dots, ch);
     if (OP == OP_QDOT) block_reduce_store<2>(dots, partials);
 }
 
