@@ -63,6 +63,8 @@ def parse():
     ap.add_argument("--no-profile", action="store_true", help="skip the event-timed solve")
     ap.add_argument("--served", type=int, default=24, help="requests in the served-stream leg (0: skip)")
     ap.add_argument("--served-designs", type=int, default=20)
+    ap.add_argument("--served-smoother", default="jacobi", choices=sorted(SMOOTHERS))
+    ap.add_argument("--served-sweeps", type=int, default=1)
     ap.add_argument("--levels", type=int, default=None, help="multigrid levels (default: the workload's)")
     ap.add_argument("--smoother", default="chebyshev", choices=sorted(SMOOTHERS))
     ap.add_argument("--sweeps", type=int, default=2, help="pre- and post-smoothing sweeps")
@@ -200,7 +202,7 @@ def cpu_baseline(cfg_name, args):
             "host": platform.processor() or platform.machine(), "host_cpus": os.cpu_count()}
 
 
-def served_leg(n_req: int, n_designs: int, seed: int = 5):
+def served_leg(n_req: int, n_designs: int, smoother: str = "jacobi", sweeps: int = 1, seed: int = 5):
     """The served stream (mixed 2D/3D sizes, 1-4 load cases, design updates
     with warm starts, rtol 1e-6): first every request at t = 0 to find the
     saturation throughput, then Poisson arrivals at 70% of that request rate;
@@ -216,7 +218,7 @@ def served_leg(n_req: int, n_designs: int, seed: int = 5):
     for r in reqs:
         for t in range(n_designs):
             r.densities(t)
-    eng = GpuEngine()
+    eng = GpuEngine(smoother=SMOOTHERS[smoother], nu_pre=sweeps, nu_post=sweeps)
     budget = 64 << 30
     Server(eng, budget, max_slots=8, chunk=4, rtol=1e-6).run(
         [dataclasses.replace(r, arrival=0.0, n_designs=2) for r in reqs[:4]])          # warm-up
@@ -234,7 +236,8 @@ def served_leg(n_req: int, n_designs: int, seed: int = 5):
             "designs_per_request": n_designs, "solves": res["solves"], "all_converged": ok,
             "mean_iters": round(float(np.mean(iters)), 2) if iters else None,
             "max_slots": 8, "chunk": 4, "latency": "request arrival to its last solve",
-            "sizes": "2D 128x64, 2D 512x256, 3D 48^3, 3D 96x48x48; 1-4 load cases; rtol 1e-6"}
+            "sizes": "2D 128x64, 2D 512x256, 3D 48^3, 3D 96x48x48; 1-4 load cases; rtol 1e-6",
+            "smoothing": f"{smoother} {sweeps}/{sweeps}"}
 
 
 def main():
@@ -326,7 +329,7 @@ def main():
         H64.close()
     line["detail"] = detail
     if args.served > 0:
-        line["served"] = served_leg(args.served, args.served_designs)
+        line["served"] = served_leg(args.served, args.served_designs, args.served_smoother, args.served_sweeps)
     if not args.no_cpu_baseline:
         cb = cpu_baseline(wl["cfg"], args)
         if cb:

@@ -317,8 +317,8 @@ static void alloc_level_geo(tm_hierarchy* h, Level& L, int l) {
     L.n_nodes = nodes_of(L.nel, dim);
     L.n = L.n_nodes * dim;
     const int bb = dim * dim;
-    L.dinv64 = halloc<double>(h, (size_t)bb * L.n_nodes);
-    L.dinv32 = halloc<float>(h, (size_t)bb * L.n_nodes);
+    L.dinv64 = halloc<double>(h, (size_t)sym_n(dim) * L.n_nodes);
+    L.dinv32 = halloc<float>(h, (size_t)sym_n(dim) * L.n_nodes);
     if (l == 0) {
         L.kind = TM_LEVEL_FINE;
         L.E64 = halloc<double>(h, h->n_el);
@@ -952,7 +952,7 @@ tm_status tm_plan_bytes(const tm_mesh* mesh, const tm_options* opts, int32_t n_r
         const int dim = mesh->dim, bb = dim * dim, nd = dim * (1 << dim);
         const int64_t n_el = (int64_t)mesh->nel[0] * mesh->nel[1] * (dim == 3 ? mesh->nel[2] : 1);
         const int64_t nodes0 = nodes_of(mesh->nel, dim);
-        size_t b = (size_t)n_el * 12 + nodes0 * (1 + bb * 12);
+        size_t b = (size_t)n_el * 12 + nodes0 * (1 + sym_n(dim) * 12);
         size_t vec = 0, el1 = 0, el2 = 0;
         int nel[3] = {mesh->nel[0], mesh->nel[1], dim == 3 ? mesh->nel[2] : 1};
         const bool mixed = opts->vcycle_fp == 32;
@@ -962,7 +962,7 @@ tm_status tm_plan_bytes(const tm_mesh* mesh, const tm_options* opts, int32_t n_r
             const int64_t nn = nodes_of(nel, dim);
             const int64_t ne = (int64_t)nel[0] * nel[1] * (dim == 3 ? nel[2] : 1);
             const int nst = dim == 3 ? 27 : 9, nq = (nst - 1) / 2 * bb + dim * (dim + 1) / 2;
-            b += (size_t)nn * (bb * 8 * nst + 12 * nq + 12 * bb);
+            b += (size_t)nn * (bb * 8 * nst + 12 * nq + 12 * sym_n(dim));
             vec += (size_t)nn * dim * (mixed ? 4 : 8) * 3;
             if (l == 1) el1 = (size_t)ne * nd * nd * 8;
             if (l == 2) el2 = (size_t)ne * nd * nd * 8;
@@ -1356,11 +1356,13 @@ tm_status tm_export_dinv(const tm_hierarchy* h, int32_t level, double* dinv) {
     return guarded([&] {
         const Level& L = level_at(h, level);
         if (!dinv) fail(TM_ERR_ARG, "dinv is NULL");
-        const int bb = L.bs * L.bs;
-        std::vector<double> t((size_t)bb * L.n_nodes);
+        const int bs = L.bs, bb = bs * bs;
+        std::vector<double> t((size_t)sym_n(bs) * L.n_nodes);
         TM_HIP(hipMemcpy(t.data(), L.dinv64, t.size() * 8, hipMemcpyDeviceToHost));
         for (int64_t node = 0; node < L.n_nodes; ++node)
-            for (int e = 0; e < bb; ++e) dinv[node * bb + e] = t[(size_t)e * L.n_nodes + node];
+            for (int r = 0; r < bs; ++r)
+                for (int c = 0; c < bs; ++c)
+                    dinv[node * bb + r * bs + c] = t[(size_t)sym_at(r, c, bs) * L.n_nodes + node];
     });
 }
 

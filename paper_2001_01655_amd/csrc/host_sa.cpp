@@ -231,8 +231,8 @@ void numeric_sa_levels(tm_hierarchy* h, hipStream_t s) {
             C.n_nodes = n_agg;
             C.n = n_agg * k;
             C.A = Ac;
-            C.dinv64 = keep.get<double>((size_t)k * k * n_agg);
-            C.dinv32 = keep.get<float>((size_t)k * k * n_agg);
+            C.dinv64 = keep.get<double>((size_t)sym_n(k) * n_agg);
+            C.dinv32 = keep.get<float>((size_t)sym_n(k) * n_agg);
             TM_HIP(hipMemsetAsync(h->flags, 0, sizeof(int), s));
             launch_bsr_dinv(C, h->opt.smoother == TM_SMOOTH_POINT_JACOBI, h->flags, s);
             int fl_host = 0;

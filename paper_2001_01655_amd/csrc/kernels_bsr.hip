@@ -123,7 +123,7 @@ __global__ __launch_bounds__(WG) void k_bsr_mv(const int32_t* __restrict__ rp, c
         for (int r = 0; r < BR; ++r) {
             T t = 0;
 #pragma unroll
-            for (int c = 0; c < BR; ++c) t += dinv[(int64_t)(r * BR + c) * nbr + row] * acc[c];
+            for (int c = 0; c < BR; ++c) t += dinv[(int64_t)sym_at(r, c, BR) * nbr + row] * acc[c];
             xf[(int64_t)BR * row + r] = omega * t;
         }
     }
@@ -162,7 +162,7 @@ __global__ __launch_bounds__(WG) void k_bsr_mv_wave(const int32_t* __restrict__ 
         for (int r = 0; r < BR; ++r) {
             T t = 0;
 #pragma unroll
-            for (int c = 0; c < BR; ++c) t += dinv[(int64_t)(r * BR + c) * nbr + row] * acc[c];
+            for (int c = 0; c < BR; ++c) t += dinv[(int64_t)sym_at(r, c, BR) * nbr + row] * acc[c];
             xf[(int64_t)BR * row + r] = omega * t;
         }
     }

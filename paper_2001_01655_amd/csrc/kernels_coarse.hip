@@ -532,10 +532,10 @@ __global__ __launch_bounds__(WG) void k_restrict(const T* __restrict__ rf, const
         }
         m[q] = MASK ? nm[f] : (uint8_t)0;
     }
-    T dv[DIM * DIM];
+    T dv[sym_n(DIM)];
     if (FIRST) {
 #pragma unroll
-        for (int e = 0; e < DIM * DIM; ++e) dv[e] = dinv[(int64_t)e * Nc + node];
+        for (int e = 0; e < sym_n(DIM); ++e) dv[e] = dinv[(int64_t)e * Nc + node];
     }
     T acc[DIM] = {};
 #pragma unroll
@@ -549,7 +549,7 @@ __global__ __launch_bounds__(WG) void k_restrict(const T* __restrict__ rf, const
         for (int r = 0; r < DIM; ++r) {
             T t = 0;
 #pragma unroll
-            for (int c = 0; c < DIM; ++c) t += dv[r * DIM + c] * acc[c];
+            for (int c = 0; c < DIM; ++c) t += dv[sym_at(r, c, DIM)] * acc[c];
             xc[DIM * node + r] = omega * t;
         }
     }
@@ -678,7 +678,7 @@ __global__ __launch_bounds__(WG) void k_first_smooth(const T* __restrict__ b, co
     for (int r = 0; r < BS; ++r) {
         T t = 0;
 #pragma unroll
-        for (int c = 0; c < BS; ++c) t += dinv[(int64_t)(r * BS + c) * N + node] * bv[c];
+        for (int c = 0; c < BS; ++c) t += dinv[(int64_t)sym_at(r, c, BS) * N + node] * bv[c];
         x[(int64_t)BS * node + r] = omega * t;
     }
 }

@@ -240,7 +240,7 @@ __global__ __launch_bounds__(WG) void k_update_ur(double* __restrict__ u, double
         for (int a = 0; a < BS; ++a) {
             TV t = 0;
 #pragma unroll
-            for (int c = 0; c < BS; ++c) t += dinv[(int64_t)(a * BS + c) * N + node] * rl[c];
+            for (int c = 0; c < BS; ++c) t += dinv[(int64_t)sym_at(a, c, BS) * N + node] * rl[c];
             x0[BS * node + a] = omega * t;
         }
     }
@@ -372,7 +372,7 @@ __global__ __launch_bounds__(WG) void k_power_step(const double* __restrict__ w,
         for (int r = 0; r < BS; ++r) {
             double t = 0.0;
 #pragma unroll
-            for (int c = 0; c < BS; ++c) t += dinv[(int64_t)(r * BS + c) * N + node] * w[BS * node + c];
+            for (int c = 0; c < BS; ++c) t += dinv[(int64_t)sym_at(r, c, BS) * N + node] * w[BS * node + c];
             z[BS * node + r] = t;
             d[0] += t * t;
             const double vr = v[BS * node + r];

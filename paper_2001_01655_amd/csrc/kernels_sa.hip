@@ -407,7 +407,7 @@ __global__ void k_dinv_a_rowmax(const int32_t* __restrict__ rp, const int32_t* _
             for (int c = 0; c < bs; ++c) {
                 double t = 0.0;
                 for (int m = 0; m < bs; ++m)
-                    t += dinv[(int64_t)(r * bs + m) * n + I] * v[((int64_t)q * bs + m) * bs + c];
+                    t += dinv[(int64_t)sym_at(r, m, bs) * n + I] * v[((int64_t)q * bs + m) * bs + c];
                 s += fabs(t);
             }
         best = fmax(best, s);
@@ -520,7 +520,7 @@ __global__ void k_p_numeric(const int32_t* __restrict__ arp, const int32_t* __re
     for (int r = 0; r < bs; ++r)
         for (int c = 0; c < k; ++c) {
             double t = 0.0;
-            for (int m = 0; m < bs; ++m) t += dinv[(int64_t)(r * bs + m) * n + I] * acc[m][c];
+            for (int m = 0; m < bs; ++m) t += dinv[(int64_t)sym_at(r, m, bs) * n + I] * acc[m][c];
             out[r][c] = (g == agg[I] ? TI[r * k + c] : 0.0) - omega * t;
         }
     for (int r = 0; r < bs; ++r)

@@ -158,9 +158,9 @@ __device__ void store_dinv(double (&D)[BS][BS], int point, int64_t node, int64_t
 #pragma unroll
     for (int i = 0; i < BS; ++i)
 #pragma unroll
-        for (int j = 0; j < BS; ++j) {
-            d64[(int64_t)(i * BS + j) * N + node] = X[i][j];
-            d32[(int64_t)(i * BS + j) * N + node] = (float)X[i][j];
+        for (int j = i; j < BS; ++j) {
+            d64[(int64_t)sym_at(i, j, BS) * N + node] = X[i][j];
+            d32[(int64_t)sym_at(i, j, BS) * N + node] = (float)X[i][j];
         }
 }
 
@@ -170,7 +170,7 @@ __device__ void store_dinv(double (&D)[BS][BS], int point, int64_t node, int64_t
 template <typename T, int BS>
 struct FinIn {
     T b[BS];
-    T dv[BS * BS];
+    T dv[sym_n(BS)];      // upper triangle of the block inverse
     T din[BS];
 };
 
@@ -183,7 +183,7 @@ __device__ __forceinline__ void finish_load(int64_t node, int64_t N, const T* __
     }
     if (OP == OP_SMOOTH || OP == OP_CHEB) {
 #pragma unroll
-        for (int e = 0; e < BS * BS; ++e) f.dv[e] = dinv[(int64_t)e * N + node];
+        for (int e = 0; e < sym_n(BS); ++e) f.dv[e] = dinv[(int64_t)e * N + node];
     }
     if (OP == OP_CHEB) {
         const T* din = (const T*)ch.din;
@@ -213,7 +213,7 @@ __device__ __forceinline__ void finish_store(int64_t node, T (&kx)[BS], const T 
         for (int r = 0; r < BS; ++r) {
             T t = 0;
 #pragma unroll
-            for (int c = 0; c < BS; ++c) t += f.dv[r * BS + c] * rr[c];
+            for (int c = 0; c < BS; ++c) t += f.dv[sym_at(r, c, BS)] * rr[c];
             y[BS * node + r] = xo[r] + omega * t;
         }
     } else if (OP == OP_CHEB) {
@@ -226,7 +226,7 @@ __device__ __forceinline__ void finish_store(int64_t node, T (&kx)[BS], const T 
         for (int r = 0; r < BS; ++r) {
             T t = 0;
 #pragma unroll
-            for (int c = 0; c < BS; ++c) t += f.dv[r * BS + c] * rr[c];
+            for (int c = 0; c < BS; ++c) t += f.dv[sym_at(r, c, BS)] * rr[c];
             const T dn = c1 * f.din[r] + c2 * t;
             if (dout) dout[BS * node + r] = dn;           // null: no later step reads it
             y[BS * node + r] = xo[r] + dn;

@@ -35,6 +35,14 @@ __device__ __forceinline__ int64_t xcd_block() {
     return (int64_t)(x * q + (x < r ? x : r) + k);
 }
 
+// Block inverses D^-1 are symmetric: only the upper triangle is stored, entry
+// (r, c) with r <= c at slot sym_at(r, c, bs) of sym_n(bs), row by row; (c, r)
+// reads the same slot.
+__host__ __device__ constexpr int sym_n(int bs) { return bs * (bs + 1) / 2; }
+__host__ __device__ constexpr int sym_at(int r, int c, int bs) {
+    return r <= c ? r * bs - r * (r - 1) / 2 + (c - r) : c * bs - c * (c - 1) / 2 + (r - c);
+}
+
 // local index of the element corner at offsets (lx, ly[, lz]) in {0,1}: 2D
 // counter-clockwise from the lower-left corner, 3D bottom face then top face.
 __host__ __device__ constexpr int loc2(int lx, int ly) { return ly ? (lx ? 2 : 3) : (lx ? 1 : 0); }

@@ -180,7 +180,7 @@ class Server:
 class GpuEngine:
     """Engine over libtopomg: one hierarchy per request, torch streams."""
 
-    def __init__(self):
+    def __init__(self, **options):
         import torch
         from . import _lib as L
         from .solver import Hierarchy, tm_batch_advance
@@ -188,9 +188,11 @@ class GpuEngine:
         self.L = L
         self.Hierarchy = Hierarchy
         self._batch = tm_batch_advance
+        self.options = options          # library options for every request (before the request's own)
 
     def _opts(self, req: Request) -> dict:
         o = dict(n_levels=0, max_coarse=1000, omega=0.5, nu_pre=1, nu_post=1, vcycle_fp=32, outer=0)
+        o.update(self.options)
         o.update(req.options)
         return o
 
