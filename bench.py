@@ -117,8 +117,8 @@ def algorithmic(cls, H, p, args):
     nd = dim * 2 ** dim
     mix = vcycle_mix(args.smoother, args.sweeps)
 
-    def extra(w):  # smoother operands per node, mean over the mix
-        return sum(dv * dim * dim * w + (dr + dw) * dim * w for dv, dr, dw in mix) / len(mix)
+    def extra(w):  # smoother operands per node (upper triangle of D^-1, direction), mean over the mix
+        return sum(dv * dim * (dim + 1) // 2 * w + (dr + dw) * dim * w for dv, dr, dw in mix) / len(mix)
 
     if cls in (0, 1):
         flops = 2.0 * nd * (nd + 1) * n_el                   # KE rows x U_e, then E_e scaling
