@@ -349,7 +349,7 @@ static void read_flags(tm_hierarchy* h, hipStream_t s, const char* phase) {
 void build_sa_levels(tm_hierarchy* h, hipStream_t s);      // kernels_sa / host_sa
 void numeric_sa_levels(tm_hierarchy* h, hipStream_t s);
 
-static double power_lmax(tm_hierarchy* h, int l, hipStream_t s);
+static void cheb_interval(tm_hierarchy* h, int l, hipStream_t s);
 
 static void numeric_setup(tm_hierarchy* h, const double* rho, hipStream_t s) {
     TM_HIP(hipMemsetAsync(h->flags, 0, sizeof(int), s));
@@ -373,14 +373,8 @@ static void numeric_setup(tm_hierarchy* h, const double* rho, hipStream_t s) {
     }
     if (h->sa) numeric_sa_levels(h, s);
     if (h->opt.smoother == TM_SMOOTH_CHEBYSHEV) {
-        // interval of the Chebyshev smoother per level: [lower, 1.1] x lambda,
-        // lambda from 12 power steps on D^-1 A (FP64)
-        for (int l = 0; l + 1 < (int)h->lv.size(); ++l) {
-            const double lam = power_lmax(h, l, s);
-            const double a = h->opt.cheb_lower * lam, b = 1.1 * lam;
-            h->lv[l].cheb_theta = 0.5 * (b + a);
-            h->lv[l].cheb_delta = 0.5 * (b - a);
-        }
+        if ((int)h->lv.size() > CHEB_MAX_LEVELS) fail(TM_ERR_ARG, "too many levels for Chebyshev smoothing");
+        for (int l = 0; l + 1 < (int)h->lv.size(); ++l) cheb_interval(h, l, s);
     }
     // coarsest operator: dense FP64, Cholesky, explicit inverse
     Level& C = h->lv.back();
@@ -460,39 +454,27 @@ static void level_op(tm_hierarchy* h, int l, int op, const T* x, const T* b, T* 
 // largest eigenvalue of D^-1 A on level l: 12 power steps from a hashed start
 // vector (zero on supported dofs), lambda = ||D^-1 A v|| / ||v||, v <- D^-1 A v
 // (FP64; block sums added on the host in a fixed order)
-static double power_lmax(tm_hierarchy* h, int l, hipStream_t s) {
+// Interval of the Chebyshev smoother on level l: [lower, 1.1] x lambda, lambda
+// from 12 power steps on D^-1 A in FP64 (start v_i = 1 + hash(i) / 2^16, zero on
+// supported dofs; lambda = |D^-1 A v| / |v| at the last step).  Everything stays
+// on the device: theta_l = lambda (lower + 1.1) / 2 goes to cheb_theta[l] and the
+// level's D^-1 is divided by it.
+static void cheb_interval(tm_hierarchy* h, int l, hipStream_t s) {
     Level& L = h->lv[l];
-    std::vector<void*> tmp;
-    size_t tb = 0;
-    double* v = dalloc<double>(tmp, tb, (size_t)L.n);
-    double* w = dalloc<double>(tmp, tb, (size_t)L.n);
-    double* z = dalloc<double>(tmp, tb, (size_t)L.n);
+    const int64_t n0 = h->lv[0].n;
+    double* v = h->pw;
+    double* w = h->pw + n0;
+    double* z = h->pw + 2 * n0;
+    double* part = h->pw + 3 * n0;
     const int nb = (int)grid_for(L.n_nodes);
-    double* part = dalloc<double>(tmp, tb, (size_t)2 * nb);
-    std::vector<double> hp((size_t)2 * nb);
-    double lam = 0.0;
-    try {
-        launch_power_start(v, L.n, l == 0 ? L.nmask : nullptr, L.bs, s);
-        for (int it = 0; it < 12; ++it) {
-            level_op<double>(h, l, OP_APPLY, v, v, w, nullptr, s);
-            launch_power_step(L, w, v, z, part, s);
-            TM_HIP(hipMemcpyAsync(hp.data(), part, hp.size() * sizeof(double), hipMemcpyDeviceToHost, s));
-            TM_HIP(hipStreamSynchronize(s));
-            double zz = 0.0, vv = 0.0;
-            for (int q = 0; q < nb; ++q) {
-                zz += hp[q];
-                vv += hp[nb + q];
-            }
-            lam = std::sqrt(zz / vv);
-            std::swap(v, z);
-        }
-    } catch (...) {
-        (void)hipStreamSynchronize(s);
-        free_list(tmp);
-        throw;
+    launch_power_start(v, L.n, l == 0 ? L.nmask : nullptr, L.bs, s);
+    for (int it = 0; it < 12; ++it) {
+        level_op<double>(h, l, OP_APPLY, v, v, w, nullptr, s);
+        launch_power_step(L, w, v, z, part, s);
+        std::swap(v, z);
     }
-    free_list(tmp);
-    return lam;
+    launch_cheb_theta(part, nb, 0.5 * (h->opt.cheb_lower + 1.1), h->cheb_theta + l, s);
+    launch_scale_dinv(L, h->cheb_theta + l, s);
 }
 
 template <typename T>
@@ -528,13 +510,16 @@ static void vcycle(tm_hierarchy* h, Vcyc& V, const T* b0, T* z, const int* done,
     // Chebyshev step k on level l (k = 0: from the current iterate with no
     // previous direction): coefficients of d_k = c1 d_{k-1} + c2 D^-1 r_k.
     // After a zero start the direction d_0 is the first iterate itself.
+    // The stored D^-1 is divided by theta_l, so c2 here is the textbook one
+    // times theta_l; with sigma = theta / delta = (1.1 + lower) / (1.1 - lower)
+    // neither coefficient depends on the eigenvalue estimate.
     auto cheb_args = [&](int l, int k, const T* x, bool zero_start, bool last) {
-        const double th = h->lv[l].cheb_theta, de = h->lv[l].cheb_delta, sigma = th / de;
-        double rho = de / th, c1 = 0.0, c2 = 1.0 / th;
+        const double lo = h->opt.cheb_lower, sigma = (1.1 + lo) / (1.1 - lo);
+        double rho = 1.0 / sigma, c1 = 0.0, c2 = 1.0;
         for (int q = 1; q <= k; ++q) {
             const double rn = 1.0 / (2.0 * sigma - rho);
             c1 = rn * rho;
-            c2 = 2.0 * rn / de;
+            c2 = 2.0 * rn * sigma;
             rho = rn;
         }
         ChebArgs ch;
@@ -970,6 +955,7 @@ tm_status tm_plan_bytes(const tm_mesh* mesh, const tm_options* opts, int32_t n_r
         }
         if (p.sa) last_n = std::min<int64_t>(last_n, opts->max_coarse * 8);
         b += (size_t)last_n * last_n * 8 * 2 + el1 + el2;
+        if (opts->smoother == TM_SMOOTH_CHEBYSHEV) b += (size_t)nodes0 * dim * 8 * 3 + (size_t)nodes0 / 16 + 1024;
         const size_t per_rhs = (size_t)nodes0 * dim * (8 * 4 + (mixed ? 4 * 4 : 8 * 3)) + vec;
         *bytes = b + per_rhs * (size_t)n_rhs;
     });
@@ -1059,6 +1045,10 @@ tm_status tm_setup(const tm_mesh* mesh, const tm_material* mat, const double* rh
         const int nd = dim * (1 << dim);
         if (plan.Lg > 1) h->elem_a = halloc<double>(h, (size_t)level_elems(h->lv[1], dim) * nd * nd);
         if (plan.Lg > 2) h->elem_b = halloc<double>(h, (size_t)level_elems(h->lv[2], dim) * nd * nd);
+        if (opts->smoother == TM_SMOOTH_CHEBYSHEV) {
+            h->cheb_theta = halloc<double>(h, CHEB_MAX_LEVELS);
+            h->pw = halloc<double>(h, (size_t)3 * n_dof + 2 * grid_for(n_nodes));
+        }
         h->sa = plan.sa;
         if (plan.sa) build_sa_levels(h, s);
         numeric_setup(h, rho_dev, s);
@@ -1359,6 +1349,12 @@ tm_status tm_export_dinv(const tm_hierarchy* h, int32_t level, double* dinv) {
         const int bs = L.bs, bb = bs * bs;
         std::vector<double> t((size_t)sym_n(bs) * L.n_nodes);
         TM_HIP(hipMemcpy(t.data(), L.dinv64, t.size() * 8, hipMemcpyDeviceToHost));
+        if (h->opt.smoother == TM_SMOOTH_CHEBYSHEV && level + 1 < (int)h->lv.size()) {
+            // stored divided by the level's interval centre
+            double th = 0.0;
+            TM_HIP(hipMemcpy(&th, h->cheb_theta + level, sizeof(double), hipMemcpyDeviceToHost));
+            for (double& e : t) e *= th;
+        }
         for (int64_t node = 0; node < L.n_nodes; ++node)
             for (int r = 0; r < bs; ++r)
                 for (int c = 0; c < bs; ++c)

@@ -392,4 +392,32 @@ void launch_power_step(const Level& L, const double* w, const double* v, double*
     }
 }
 
+// theta = factor * sqrt(z.z / v.v) from the last power step's partials: the
+// estimate of the largest eigenvalue of D^-1 A times (lower + upper) / 2
+__global__ __launch_bounds__(FB) void k_cheb_theta(const double* part, int nparts, double factor,
+                                                   double* theta) {
+    double t[2];
+    fin_sums<2>(part, nparts, t);
+    if (threadIdx.x == 0) *theta = factor * sqrt(t[0] / t[1]);
+}
+
+void launch_cheb_theta(const double* part, int nparts, double factor, double* theta, hipStream_t s) {
+    hipLaunchKernelGGL(k_cheb_theta, dim3(1), dim3(FB), 0, s, part, nparts, factor, theta);
+}
+
+// D^-1 <- D^-1 / theta (FP64), and its FP32 copy from the result
+__global__ void k_scale_dinv(double* __restrict__ d64, float* __restrict__ d32, int64_t n,
+                             const double* __restrict__ theta) {
+    const int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x;
+    if (i >= n) return;
+    const double v = d64[i] / *theta;
+    d64[i] = v;
+    d32[i] = (float)v;
+}
+
+void launch_scale_dinv(Level& L, const double* theta, hipStream_t s) {
+    const int64_t n = (int64_t)sym_n(L.bs) * L.n_nodes;
+    hipLaunchKernelGGL(k_scale_dinv, dim3(grid_for(n)), dim3(WG), 0, s, L.dinv64, L.dinv32, n, theta);
+}
+
 }  // namespace tmi

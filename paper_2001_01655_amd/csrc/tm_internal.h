@@ -162,7 +162,6 @@ struct Level {
     int bs = 0;                   // dofs per block row
     int64_t n = 0;                // dofs
     // Chebyshev smoothing interval [theta - delta, theta + delta] for D^-1 A
-    double cheb_theta = 0.0, cheb_delta = 0.0;
     // fine level
     double* E64 = nullptr;
     float* E32 = nullptr;
@@ -219,6 +218,10 @@ struct tm_hierarchy {
     size_t ainv_cap = 0;
     bool sa = false;               // smoothed-aggregation levels below the geometric ones
     int* flags = nullptr;          // device status flags
+    // Chebyshev smoothing: centre theta_l of each level's interval (device) and
+    // the setup scratch of the power estimate (three fine-size vectors, partials)
+    double* cheb_theta = nullptr;
+    double* pw = nullptr;
     double* elem_a = nullptr;      // setup workspace: element matrices (ping)
     double* elem_b = nullptr;      // (pong)
     size_t bytes = 0;
@@ -253,11 +256,19 @@ struct tm_solve_state {
 namespace tmi {
 // weight of the first smoothing sweep from a zero start on level l: omega for
 // Jacobi, 1 / theta_l for Chebyshev (its first step is a Jacobi step)
+// Weight of the first smoothing step from zero, x = w D^-1 b.  With Chebyshev
+// smoothing the stored D^-1 of each level is already divided by theta_l, the
+// centre of its interval, so that step has weight 1 (and every later step's
+// coefficients depend only on the interval's ratio, known on the host).
 inline double first_sweep_weight(const tm_hierarchy* h, int l) {
-    return h->opt.smoother == TM_SMOOTH_CHEBYSHEV ? 1.0 / h->lv[l].cheb_theta : h->opt.omega;
+    (void)l;
+    return h->opt.smoother == TM_SMOOTH_CHEBYSHEV ? 1.0 : h->opt.omega;
 }
+constexpr int CHEB_MAX_LEVELS = 64;
 void launch_power_start(double* v, int64_t n, const uint8_t* nmask, int bs, hipStream_t s);
 void launch_power_step(const Level& L, const double* w, const double* v, double* z, double* part, hipStream_t s);
+void launch_cheb_theta(const double* part, int nparts, double factor, double* theta, hipStream_t s);
+void launch_scale_dinv(Level& L, const double* theta, hipStream_t s);
 
 
 struct Lane {

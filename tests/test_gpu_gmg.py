@@ -235,3 +235,19 @@ def test_solve_chebyshev_vs_oracle(vfp, outer):
         assert abs(r.compliance[k] - ref.compliance) <= 1e-9 * abs(ref.compliance)
         _say(f"  rhs {k}: iters={r.iters[k]} (oracle PCG {ref.iters} at rtol 1e-12)")
     G.close()
+
+
+@pytest.mark.parametrize("dim,nel,L", CASES)
+def test_chebyshev_keeps_block_inverses(dim, nel, L):
+    """With Chebyshev smoothing each level's block inverse is stored divided
+    by its interval centre; the export undoes that and gives the same blocks
+    as the Jacobi hierarchy of the same problem."""
+    _say(f"chebyshev dinv {nel}")
+    p = synth.small_case(dim, nel, seed=30)
+    Gj = _gpu(p, L)
+    Gc = _gpu(p, L, smoother=2, nu_pre=2, nu_post=2)
+    for l in range(L):
+        dj, dc = Gj.export_dinv(l), Gc.export_dinv(l)
+        assert _rel(dc, dj) <= 1e-14, f"level {l}"
+    Gj.close()
+    Gc.close()
