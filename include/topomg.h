@@ -91,6 +91,10 @@ typedef struct {
                               Same operator either way; only the rounding order differs      */
     double  cheb_lower;    /* Chebyshev smoothing interval [cheb_lower, 1.1] x lambda, lambda =
                               power estimate of the largest eigenvalue of D^-1 A (0.1)        */
+    int32_t adapt_iters;   /* automated hybrid (Sec. 4.4): when a solve takes more than this
+                              many iterations, the next tm_update_density turns the coarsest
+                              geometric level into smoothed-aggregation levels (down to 2
+                              geometric levels, max_coarse as usual).  0 (default): off      */
 } tm_options;
 
 typedef struct tm_hierarchy tm_hierarchy;       /* opaque */

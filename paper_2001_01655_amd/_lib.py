@@ -42,7 +42,8 @@ class tm_options(C.Structure):
                 ("smoother", C.c_int32), ("nu_pre", C.c_int32), ("nu_post", C.c_int32),
                 ("omega", C.c_double), ("sa_beta", C.c_double), ("vcycle_fp", C.c_int32),
                 ("outer", C.c_int32), ("max_iters", C.c_int32), ("check_every", C.c_int32),
-                ("fine_mfma", C.c_int32), ("cheb_lower", C.c_double)]
+                ("fine_mfma", C.c_int32), ("cheb_lower", C.c_double),
+                ("adapt_iters", C.c_int32)]
 
 
 class TmError(RuntimeError):

@@ -238,6 +238,7 @@ static void check_opts(const tm_options* o) {
         fail(TM_ERR_ARG, "smoother must be TM_SMOOTH_BLOCK_JACOBI, TM_SMOOTH_POINT_JACOBI or TM_SMOOTH_CHEBYSHEV");
     if (o->smoother == TM_SMOOTH_CHEBYSHEV && !(o->cheb_lower > 0.0 && o->cheb_lower < 1.0))
         fail(TM_ERR_ARG, "cheb_lower must be in (0, 1)");
+    if (o->adapt_iters < 0) fail(TM_ERR_ARG, "adapt_iters must be >= 0");
     if (o->nu_pre < 1 || o->nu_post < 1 || o->nu_pre > 16 || o->nu_post > 16)
         fail(TM_ERR_ARG, "nu_pre / nu_post must be in 1..16");
     if (!(o->omega > 0.0 && o->omega < 2.0)) fail(TM_ERR_ARG, "omega must be in (0, 2)");
@@ -772,6 +773,7 @@ static tm_status finish_state(tm_solve_state* st, int32_t* iters, double* compli
     for (int k = 0; k < st->nrhs; ++k) {
         const KScal& c = st->sc_host[k];
         if (iters) iters[k] = c.iter;
+        if (h->opt.adapt_iters > 0 && c.iter > h->opt.adapt_iters) h->demote = true;
         if (compliance) compliance[k] = c.zq;
         if (relres) relres[k] = c.ff > 0.0 ? std::sqrt(c.pq / c.ff) : 0.0;
         const tm_status stt = (tm_status)c.status;
@@ -909,6 +911,7 @@ void tm_default_options(tm_options* o) {
     o->check_every = 0;
     o->fine_mfma = 0;
     o->cheb_lower = 0.1;
+    o->adapt_iters = 0;
 }
 
 const char* tm_status_string(tm_status s) {
@@ -1063,6 +1066,18 @@ tm_status tm_update_density(tm_hierarchy* h, const double* rho_dev, void* stream
     return guarded([&] {
         if (!h) fail(TM_ERR_ARG, "hierarchy is NULL");
         if (!rho_dev) fail(TM_ERR_ARG, "rho_dev is NULL");
+        if (h->demote) {
+            // automated hybrid: one geometric level fewer (at least two stay);
+            // the aggregation levels are rebuilt below the new last one
+            h->demote = false;
+            int Lg = 0;
+            for (auto& L : h->lv)
+                if (L.kind != TM_LEVEL_AGGREGATION) ++Lg;
+            if (Lg > 2) {
+                h->lv.resize(Lg - 1);
+                h->sa = true;
+            }
+        }
         numeric_setup(h, rho_dev, S(stream));
     });
 }

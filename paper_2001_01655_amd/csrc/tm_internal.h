@@ -217,6 +217,7 @@ struct tm_hierarchy {
     int64_t nc = 0;                // coarsest dofs
     size_t ainv_cap = 0;
     bool sa = false;               // smoothed-aggregation levels below the geometric ones
+    bool demote = false;           // a solve exceeded adapt_iters: drop a geometric level at the next update
     int* flags = nullptr;          // device status flags
     // Chebyshev smoothing: centre theta_l of each level's interval (device) and
     // the setup scratch of the power estimate (three fine-size vectors, partials)

@@ -59,6 +59,7 @@ def _setup_status(nel=(8, 4), nu=0.3, Emin=1e-9, E0=1.0, dofs=(0, 1), **opts):
     (dict(n_geometric=1), "n_geometric"),
     (dict(nu_pre=0), "nu_pre"),
     (dict(fine_mfma=2), "fine_mfma"),
+    (dict(adapt_iters=-1), "adapt_iters"),
 ])
 def test_setup_rejects_bad_arguments_before_device_work(kw, msg):
     st, err = _setup_status(**kw)
