@@ -72,6 +72,8 @@ def parse():
                     help="Chebyshev interval [cheb_lower, 1.1] x the estimated largest eigenvalue of D^-1 A")
     ap.add_argument("--fine-mfma", type=int, default=0, choices=[0, 1],
                     help="FP32 fine operator on the matrix cores (1) or vector FMAs (0)")
+    ap.add_argument("--adaptive-stream", type=int, default=0,
+                    help="designs in the automated-hybrid comparison on the bridge recipe (0: skip)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="copy 256 MiB device-to-device first (counter calibration under rocprofv3 --pmc)")
     return ap.parse_args()
@@ -240,6 +242,55 @@ def served_leg(n_req: int, n_designs: int, smoother: str = "jacobi", sweeps: int
             "smoothing": f"{smoother} {sweeps}/{sweeps}"}
 
 
+def adaptive_leg(n_designs: int, nel=(128, 64, 64), seed: int = 4):
+    """Design stream on the thin-strut bridge recipe (warm-started solves to
+    rtol 1e-8, FP32 V-cycle in FCG, block Jacobi 1/1): pure GMG with 6 levels,
+    the fixed hybrid (2 geometric levels, then aggregation below 1000 dofs) and
+    the automated hybrid (start with 6 geometric levels, one fewer after every
+    solve over 200 iterations).  Setup/update and solve are timed per design."""
+    import torch
+
+    import synth
+    from paper_2001_01655_amd import Hierarchy
+    p = synth.bridge_3d(nel=nel, seed=seed)
+    rhos = [p.rho]
+    for t in range(1, n_designs):
+        rhos.append(synth.density_update(rhos[-1], p.nel, seed=seed, step=t))
+    f = torch.tensor(p.loads[0], device="cuda")
+    variants = {"gmg6": dict(n_levels=6), "hybrid2": dict(n_geometric=2, max_coarse=1000),
+                "adaptive": dict(n_levels=6, max_coarse=1000, adapt_iters=200)}
+    out = {}
+    for name, o in variants.items():
+        rec = dict(iters=[], geometric=[], setup_ms=[], solve_ms=[])
+        H, u = None, None
+        for t, rho in enumerate(rhos):
+            rd = torch.tensor(rho, device="cuda")
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if H is None:
+                H = Hierarchy(p.nel, rd, p.fixed, p=p.p, E0=p.E0, Emin=p.Emin, nu=p.nu, omega=0.5, nu_pre=1,
+                              nu_post=1, vcycle_fp=32, outer=0, max_iters=5000, **o)
+            else:
+                H.update_density(rd)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            r = H.solve(f, rtol=1e-8, u0=u)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            u = r.u
+            kinds = [H.level_info(l)["kind"] for l in range(H.num_levels())]
+            rec["iters"].append(int(r.iters[0]))
+            rec["geometric"].append(sum(k != 2 for k in kinds))
+            rec["setup_ms"].append(round((t1 - t0) * 1e3, 2))
+            rec["solve_ms"].append(round((t2 - t1) * 1e3, 2))
+        H.close()
+        rec["total_ms"] = round(sum(rec["setup_ms"]) + sum(rec["solve_ms"]), 1)
+        out[name] = rec
+    out["workload"] = (f"3D bridge recipe {nel[0]}x{nel[1]}x{nel[2]} ({p.n_dof:,} dofs), {n_designs} designs, "
+                       "warm-started, rtol 1e-8")
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -330,6 +381,8 @@ def main():
     line["detail"] = detail
     if args.served > 0:
         line["served"] = served_leg(args.served, args.served_designs, args.served_smoother, args.served_sweeps)
+    if args.adaptive_stream > 0:
+        line["adaptive_stream"] = adaptive_leg(args.adaptive_stream)
     if not args.no_cpu_baseline:
         cb = cpu_baseline(wl["cfg"], args)
         if cb:
