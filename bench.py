@@ -291,6 +291,42 @@ def adaptive_leg(n_designs: int, nel=(128, 64, 64), seed: int = 4):
     return out
 
 
+def filter_leg(nel, reps: int = 50):
+    """tm_density_filter (radius 1.5) on the workload's element grid: mean time
+    per launch from events around reps back-to-back calls of the C function on
+    the current stream (buffers and arguments prepared once); algorithmic
+    bytes = one FP64 read and one write per element."""
+    import ctypes as C
+
+    import torch
+
+    from paper_2001_01655_amd import _lib as L
+    n = 1
+    for v in nel:
+        n *= int(v)
+    x = torch.rand(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    mesh = L.make_mesh(tuple(int(v) for v in nel))
+    stream = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    xp, yp = C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr())
+    out = {}
+    for tr in (0, 1):
+        L.check(L.LIB.tm_density_filter(C.byref(mesh), 1.5, tr, xp, yp, stream))
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            L.LIB.tm_density_filter(C.byref(mesh), 1.5, tr, xp, yp, stream)
+        e1.record()
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) * 1e3 / reps
+        gbs = 16.0 * n / (us * 1e-6) / 1e9
+        out["transpose" if tr else "forward"] = {"avg_us": round(us, 2), "achieved_GBs": round(gbs, 1),
+                                                 "frac_hbm": round(gbs / PEAK["hbm_GBs"], 4)}
+    out["elements"] = n
+    out["radius"] = 1.5
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -368,6 +404,7 @@ def main():
             line["roofline_other_kernels"] = [ents[c] for c in ents if c != dom]
     u_mixed = res.u.clone()
     H.close()
+    line["density_filter"] = filter_leg(p.nel)
     if not args.no_fp64:
         H64, t64s = build(64, 1)
         k64 = max(1, args.steps // 2)

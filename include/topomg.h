@@ -142,6 +142,18 @@ tm_status tm_solve(tm_hierarchy* h, int32_t n_rhs, const double* f_dev, double r
 tm_status tm_compliance_sensitivity(tm_hierarchy* h, int32_t n_rhs, const double* u_dev, double* dc_dev,
                                     void* stream);
 
+/* Linear density filter (Sec. 2: filtered densities rho = S alpha; Sec. 4: radius
+ * 1.5 element sizes).  S[e][i] = H[e][i] / sum_j H[e][j] over the elements i of the
+ * grid, H[e][i] = max(0, radius - |c_e - c_i|), c = element centres in units of
+ * the element size.
+ *   transpose = 0: out = S in    (design variables -> filtered densities)
+ *   transpose = 1: out = S^T in  (sensitivities w.r.t. rho -> w.r.t. alpha)
+ * in_dev, out_dev: n_el FP64 device buffers in element order (x fastest), owned by
+ * the caller; they must not overlap.  radius in (0, 4].  Enqueued on `stream`; the
+ * call does not wait.  TM_ERR_ARG for a bad mesh, radius or NULL buffer. */
+tm_status tm_density_filter(const tm_mesh* mesh, double radius, int32_t transpose, const double* in_dev,
+                            double* out_dev, void* stream);
+
 /* Iteration-level control for a scheduler (continuous batching).
  * begin:   copies f, sets up the start vector on `stream` and returns a state
  *          bound to (h, stream, u_dev); u_dev must stay valid until end.

@@ -80,6 +80,7 @@ def _load():
         "tm_export_connectivity": (I32, [C.POINTER(tm_mesh), P]),
         "tm_hierarchy_bytes": (I32, [P, C.POINTER(SZ)]),
         "tm_compliance_sensitivity": (I32, [P, I32, P, P, P]),
+        "tm_density_filter": (I32, [C.POINTER(tm_mesh), D, I32, P, P, P]),
         "tm_kernel_timing": (I32, [P, I32, I32]),
         "tm_kernel_timing_read": (I32, [P, I32, C.POINTER(I64), C.POINTER(D)]),
         "tm_destroy": (None, [P]),

@@ -26,6 +26,7 @@ SOURCES = [
     "kernels_krylov.hip",
     "kernels_bsr.hip",
     "kernels_sa.hip",
+    "kernels_filter.hip",
     "host.cpp",
     "host_sa.cpp",
 ]

@@ -1097,6 +1097,19 @@ tm_status tm_compliance_sensitivity(tm_hierarchy* h, int32_t n_rhs, const double
     });
 }
 
+tm_status tm_density_filter(const tm_mesh* mesh, double radius, int32_t transpose, const double* in_dev,
+                            double* out_dev, void* stream) {
+    return guarded([&] {
+        check_mesh(mesh);
+        if (!(radius > 0.0 && radius <= 4.0)) fail(TM_ERR_ARG, "radius must be in (0, 4]");
+        if (transpose != 0 && transpose != 1) fail(TM_ERR_ARG, "transpose must be 0 or 1");
+        if (!in_dev || !out_dev) fail(TM_ERR_ARG, "in and out must be device buffers");
+        if (in_dev == out_dev) fail(TM_ERR_ARG, "in and out must not overlap");
+        launch_density_filter(mesh->dim, mesh->nel, radius, transpose == 1, in_dev, out_dev, S(stream));
+        TM_HIP(hipGetLastError());
+    });
+}
+
 tm_status tm_hierarchy_bytes(const tm_hierarchy* h, size_t* bytes) {
     return guarded([&] {
         if (!h || !bytes) fail(TM_ERR_ARG, "NULL argument");

@@ -295,6 +295,8 @@ struct ChebArgs {
 void launch_simp(const double* rho, int64_t n_el, double p, double E0, double Emin, double* E64,
                  float* E32, double* rho64, int* flags, hipStream_t s);
 void launch_sensitivity(const tm_hierarchy* h, int n_rhs, const double* u, double* dc, hipStream_t s);
+void launch_density_filter(int dim, const int* nel, double r, bool tr, const double* in, double* out,
+                           hipStream_t s);
 void launch_fine_dinv(const Level& L, const double* KE64, int point_jacobi, int* flags,
                       hipStream_t s);
 template <typename T>

@@ -238,3 +238,18 @@ class SolveState:
 def tm_batch_advance(states: Sequence[SolveState], k: int):
     arr = (C.c_void_p * len(states))(*[s.handle for s in states])
     check(LIB.tm_batch_advance(len(states), arr, k), "tm_batch_advance")
+
+
+def density_filter(nel: Sequence[int], x, radius: float = 1.5, transpose: bool = False,
+                   stream=None) -> torch.Tensor:
+    """tm_density_filter: S x (or S^T x) for one value per element, S the linear
+    density filter of the given radius in element sizes."""
+    x_d = _dev(x)
+    mesh = L.make_mesh(tuple(int(n) for n in nel))
+    n_el = int(np.prod([int(n) for n in nel]))
+    if x_d.numel() != n_el:
+        raise ValueError("x must hold one value per element")
+    out = torch.empty_like(x_d)
+    check(LIB.tm_density_filter(C.byref(mesh), float(radius), int(bool(transpose)), C.c_void_p(x_d.data_ptr()),
+                                C.c_void_p(out.data_ptr()), _stream_ptr(stream)), "tm_density_filter")
+    return out

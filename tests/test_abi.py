@@ -96,3 +96,15 @@ def test_import_fails_loudly_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(L, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(ImportError):
         L._load()
+
+
+@pytest.mark.parametrize("radius,transpose,same,msg", [
+    (0.0, 0, False, "radius"), (4.5, 0, False, "radius"), (1.5, 2, False, "transpose"), (1.5, 0, True, "overlap"),
+])
+def test_density_filter_rejects_bad_arguments_before_device_work(radius, transpose, same, msg):
+    mesh = L.make_mesh((8, 4))
+    a, b = C.c_void_p(0x1000), C.c_void_p(0x1000 if same else 0x2000)
+    st = L.LIB.tm_density_filter(C.byref(mesh), radius, transpose, a, b, None)
+    assert st == L.TM_ERR_ARG
+    assert msg in L.LIB.tm_last_error().decode()
+    assert L.LIB.tm_density_filter(C.byref(mesh), 1.5, 0, None, b, None) == L.TM_ERR_ARG
