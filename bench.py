@@ -63,8 +63,8 @@ def parse():
     ap.add_argument("--no-profile", action="store_true", help="skip the event-timed solve")
     ap.add_argument("--served", type=int, default=24, help="requests in the served-stream leg (0: skip)")
     ap.add_argument("--served-designs", type=int, default=20)
-    ap.add_argument("--served-smoother", default="jacobi", choices=sorted(SMOOTHERS))
-    ap.add_argument("--served-sweeps", type=int, default=1)
+    ap.add_argument("--served-smoother", default="chebyshev", choices=sorted(SMOOTHERS))
+    ap.add_argument("--served-sweeps", type=int, default=2)
     ap.add_argument("--levels", type=int, default=None, help="multigrid levels (default: the workload's)")
     ap.add_argument("--smoother", default="chebyshev", choices=sorted(SMOOTHERS))
     ap.add_argument("--sweeps", type=int, default=2, help="pre- and post-smoothing sweeps")
@@ -204,7 +204,7 @@ def cpu_baseline(cfg_name, args):
             "host": platform.processor() or platform.machine(), "host_cpus": os.cpu_count()}
 
 
-def served_leg(n_req: int, n_designs: int, smoother: str = "jacobi", sweeps: int = 1, seed: int = 5):
+def served_leg(n_req: int, n_designs: int, smoother: str = "chebyshev", sweeps: int = 2, seed: int = 5):
     """The served stream (mixed 2D/3D sizes, 1-4 load cases, design updates
     with warm starts, rtol 1e-6): first every request at t = 0 to find the
     saturation throughput, then Poisson arrivals at 70% of that request rate;

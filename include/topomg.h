@@ -117,7 +117,13 @@ tm_status tm_setup(const tm_mesh* mesh, const tm_material* mat, const double* rh
                    const tm_bcs* bcs, const tm_options* opts, void* stream, tm_hierarchy** out);
 
 /* Numeric re-setup for new densities on the same mesh, supports and options
- * (a design iteration): the structure and all allocations are reused. */
+ * (a design iteration): the structure and all allocations are reused.  For a
+ * hierarchy without aggregation levels the call only enqueues work on `stream`
+ * and returns; what the device finds (densities outside [0,1], a block or the
+ * coarsest operator not SPD) is then reported by the next solve on this
+ * hierarchy (TM_ERR_ARG / TM_ERR_NOT_SPD), which must be ordered after it.
+ * With aggregation levels (whose sizes depend on the values) it waits and
+ * reports those errors itself. */
 tm_status tm_update_density(tm_hierarchy* h, const double* rho_dev, void* stream);
 
 /* Solve K~ u_k = M f_k for k < n_rhs.  f_dev and u_dev hold n_rhs vectors of

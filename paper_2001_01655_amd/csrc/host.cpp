@@ -352,13 +352,16 @@ void numeric_sa_levels(tm_hierarchy* h, hipStream_t s);
 
 static void cheb_interval(tm_hierarchy* h, int l, hipStream_t s);
 
-static void numeric_setup(tm_hierarchy* h, const double* rho, hipStream_t s) {
+// Numeric setup for densities rho.  With sync the device checks (densities,
+// SPD blocks, coarsest factor) are read before returning; without, nothing
+// waits for the device and the next solve reads them (flags_pending).
+static void numeric_setup(tm_hierarchy* h, const double* rho, hipStream_t s, bool sync = true) {
     TM_HIP(hipMemsetAsync(h->flags, 0, sizeof(int), s));
     Level& F = h->lv[0];
     launch_simp(rho, h->n_el, h->mat.p, h->mat.E0, h->mat.Emin, F.E64, F.E32, h->rho64, h->flags, s);
     const int point = h->opt.smoother == TM_SMOOTH_POINT_JACOBI;
     launch_fine_dinv(F, h->KE64, point, h->flags, s);
-    read_flags(h, s, "fine diagonal");
+    if (sync) read_flags(h, s, "fine diagonal");
     int Lg = 0;
     for (auto& L : h->lv)
         if (L.kind != TM_LEVEL_AGGREGATION) ++Lg;
@@ -381,10 +384,13 @@ static void numeric_setup(tm_hierarchy* h, const double* rho, hipStream_t s) {
     Level& C = h->lv.back();
     const int64_t nc = C.n;
     h->nc = nc;
-    std::vector<void*> tmp;
-    size_t tb = 0;
-    double* Ad = dalloc<double>(tmp, tb, (size_t)nc * nc);
-    double* Ls = dalloc<double>(tmp, tb, (size_t)chol_block_elems());
+    if (h->dense_cap < (size_t)nc * nc) {
+        h->dense_a = halloc<double>(h, (size_t)nc * nc);
+        h->dense_cap = (size_t)nc * nc;
+    }
+    if (!h->chol_ls) h->chol_ls = halloc<double>(h, (size_t)chol_block_elems());
+    double* Ad = h->dense_a;
+    double* Ls = h->chol_ls;
     TM_HIP(hipMemsetAsync(Ad, 0, (size_t)nc * nc * sizeof(double), s));
     if (C.kind == TM_LEVEL_AGGREGATION)
         launch_dense_from_bsr(C, Ad, s);
@@ -396,16 +402,12 @@ static void numeric_setup(tm_hierarchy* h, const double* rho, hipStream_t s) {
         h->ainv = halloc<double>(h, (size_t)nc * nc);
         h->ainv_cap = (size_t)nc * nc;
     }
-    try {
-        launch_cholesky_inverse(Ad, h->ainv, Ls, nc, h->flags, s);
+    launch_cholesky_inverse(Ad, h->ainv, Ls, nc, h->flags, s);
+    if (sync) {
         read_flags(h, s, "coarsest Cholesky");
-    } catch (...) {
         TM_HIP(hipStreamSynchronize(s));
-        free_list(tmp);
-        throw;
     }
-    TM_HIP(hipStreamSynchronize(s));
-    free_list(tmp);
+    h->flags_pending = !sync;
 }
 
 static void destroy_hierarchy(tm_hierarchy* h);
@@ -768,7 +770,16 @@ static tm_status finish_state(tm_solve_state* st, int32_t* iters, double* compli
     for (int k = 0; k < st->nrhs; ++k)
         launch_final_residual(h, *st->lanes[k], st->sc + k, st->u + (size_t)k * n, st->s);
     TM_HIP(hipMemcpyAsync(st->sc_host, st->sc, sizeof(KScal) * st->nrhs, hipMemcpyDeviceToHost, st->s));
+    int fl = 0;
+    if (h->flags_pending) TM_HIP(hipMemcpyAsync(&fl, h->flags, sizeof(int), hipMemcpyDeviceToHost, st->s));
     TM_HIP(hipStreamSynchronize(st->s));
+    if (h->flags_pending) {
+        // device checks of the last density update, which did not wait for them
+        h->flags_pending = false;
+        st->ended = true;
+        if (fl & FLAG_BAD_RHO) fail(TM_ERR_ARG, "densities of the last update must be finite and in [0, 1]");
+        if (fl & FLAG_NOT_SPD) fail(TM_ERR_NOT_SPD, "operator of the last update not positive definite");
+    }
     tm_status worst = TM_OK;
     for (int k = 0; k < st->nrhs; ++k) {
         const KScal& c = st->sc_host[k];
@@ -1078,7 +1089,9 @@ tm_status tm_update_density(tm_hierarchy* h, const double* rho_dev, void* stream
                 h->sa = true;
             }
         }
-        numeric_setup(h, rho_dev, S(stream));
+        // without aggregation levels (whose sizes the host must read) the update
+        // never waits for the device
+        numeric_setup(h, rho_dev, S(stream), h->sa);
     });
 }
 

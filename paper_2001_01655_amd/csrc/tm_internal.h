@@ -218,6 +218,10 @@ struct tm_hierarchy {
     size_t ainv_cap = 0;
     bool sa = false;               // smoothed-aggregation levels below the geometric ones
     bool demote = false;           // a solve exceeded adapt_iters: drop a geometric level at the next update
+    bool flags_pending = false;    // an update ran without waiting: its device checks are read by the next solve
+    double* dense_a = nullptr;     // coarsest operator, dense (setup scratch kept for updates)
+    size_t dense_cap = 0;
+    double* chol_ls = nullptr;     // blocked Cholesky panel scratch
     int* flags = nullptr;          // device status flags
     // Chebyshev smoothing: centre theta_l of each level's interval (device) and
     // the setup scratch of the power estimate (three fine-size vectors, partials)

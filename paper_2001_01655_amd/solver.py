@@ -83,7 +83,11 @@ class Hierarchy:
         return self._h
 
     def update_density(self, rho, stream=None):
+        """tm_update_density; returns without waiting for the device (its checks
+        are reported by the next solve)."""
         rho_d = _dev(rho)
+        if stream is not None:
+            rho_d.record_stream(stream)      # read by the update's first kernel on that stream
         check(LIB.tm_update_density(self._h, C.c_void_p(rho_d.data_ptr()), _stream_ptr(stream)),
               "tm_update_density")
 

@@ -251,3 +251,27 @@ def test_chebyshev_keeps_block_inverses(dim, nel, L):
         assert _rel(dc, dj) <= 1e-14, f"level {l}"
     Gj.close()
     Gc.close()
+
+
+def test_update_without_waiting_reports_device_checks_at_the_next_solve():
+    """A density update of a geometric hierarchy enqueues its work and returns;
+    what the device finds (here a density outside [0, 1]) is reported by the
+    next solve, and a good update afterwards solves normally."""
+    from paper_2001_01655_amd import TmError
+    from paper_2001_01655_amd import _lib as L
+    p = synth.small_case(3, (12, 8, 8), seed=31)
+    G = _gpu(p, 3)
+    f = torch.tensor(p.loads[0], device="cuda")
+    bad = p.rho.copy()
+    bad[5] = 2.0
+    G.update_density(torch.tensor(bad, device="cuda"))
+    with pytest.raises(TmError) as e:
+        G.solve(f, rtol=1e-8)
+    assert e.value.status == L.TM_ERR_ARG
+    G.update_density(torch.tensor(p.rho, device="cuda"))
+    r = G.solve(f, rtol=1e-8)
+    assert r.converged
+    H, E, KE = _oracle(p, 3)
+    ref = mg.mg_pcg(H, p.loads[0], 1e-12)
+    assert np.linalg.norm(r.u.cpu().numpy() - ref.u) <= 1e-7 * np.linalg.norm(ref.u)
+    G.close()
