@@ -458,63 +458,74 @@ __device__ __forceinline__ void elem2(const KeVals<T>& kc, const T (&v)[9][2], T
 template <typename T, int OP, bool MASK_IN>
 __global__ __launch_bounds__(WG) void k_fine2(const T* __restrict__ E, const KeVals<T> kc,
                                               const uint8_t* __restrict__ nm, int nx, int ny,
-                                              int64_t N, const T* __restrict__ x,
+                                              int64_t N64, const T* __restrict__ x,
                                               const T* __restrict__ b, T* __restrict__ y,
                                               const T* __restrict__ dinv, T omega,
                                               const int* __restrict__ done, double* partials,
                                               const ChebArgs ch) {
     if (done && *done) return;
-    const int64_t node = xcd_block() * WG + threadIdx.x;
+    const uint32_t N = (uint32_t)N64;
+    const uint32_t node = (uint32_t)xcd_block() * WG + threadIdx.x;
     const bool live = node < N;
-    const int NX = nx + 1, NY = ny + 1;
-    const int64_t nd = live ? node : 0;
-    const int i = (int)(nd % NX);
-    const int j = (int)(nd / NX);
+    const uint32_t NX = nx + 1, NY = ny + 1;
+    const uint32_t nd = live ? node : 0u;
+    const uint32_t i = nd % NX, j = nd / NX;
+    // clamped neighbours by additions; values outside the grid are zeroed
+    const uint32_t ox[3] = {i ? 0u - 1u : 0u, 0u, i + 1 < NX ? 1u : 0u};
+    const uint32_t oy[3] = {j ? 0u - NX : 0u, 0u, j + 1 < NY ? NX : 0u};
+    const bool inx[3] = {i > 0, true, i + 1 < NX}, iny[3] = {j > 0, true, j + 1 < NY};
+    const auto xr = buf_rsrc(x, (int64_t)N * 2 * sizeof(T));
+    const auto er = buf_rsrc(E, (int64_t)nx * ny * sizeof(T));
+    // the finishing step's operands first, so that they arrive with the gather
+    FinIn<T, 2> fin;
+    finish_load<T, 2, OP>(nd, N, b, dinv, ch, fin);
+    const uint8_t mo = nm[nd];
     T v[9][2];
 #pragma unroll
     for (int dy = 0; dy < 3; ++dy)
 #pragma unroll
         for (int dx = 0; dx < 3; ++dx) {
-            const int ii = i + dx - 1, jj = j + dy - 1;
-            const bool ok = live && ii >= 0 && ii < NX && jj >= 0 && jj < NY;
-            const int64_t id = (int64_t)jj * NX + ii;
-            T a0 = 0, a1 = 0;
-            if (ok) {
-                a0 = x[2 * id];
-                a1 = x[2 * id + 1];
-                if (MASK_IN) {
-                    const uint8_t m = nm[id];
-                    if (m & 1) a0 = 0;
-                    if (m & 2) a1 = 0;
-                }
-            }
-            v[dy * 3 + dx][0] = a0;
-            v[dy * 3 + dx][1] = a1;
+            const uint32_t id = nd + oy[dy] + ox[dx];
+            T a[2];
+            bld2(xr, id * (uint32_t)(2 * sizeof(T)), a);
+            const bool in = inx[dx] & iny[dy];
+            const uint8_t m = MASK_IN ? nm[id] : (uint8_t)0;
+            v[dy * 3 + dx][0] = (in & !(m & 1u)) ? a[0] : T(0);
+            v[dy * 3 + dx][1] = (in & !(m & 2u)) ? a[1] : T(0);
         }
-    auto Eat = [&](int ex, int ey) -> T {
-        const int gx = i - 1 + ex, gy = j - 1 + ey;
-        const bool ok = live && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
-        return ok ? E[(int64_t)gy * nx + gx] : T(0);
-    };
+    // moduli of the 4 elements around the node (lower corner (i-1+ex, j-1+ey))
+    const uint32_t EX = (uint32_t)nx;
+    const uint32_t gx[2] = {i ? i - 1 : 0u, i < EX ? i : i - 1};
+    const uint32_t gy[2] = {(j ? j - 1 : 0u) * EX, (j < (uint32_t)ny ? j : j - 1) * EX};
+    T Ee[2][2];
+#pragma unroll
+    for (int ey = 0; ey < 2; ++ey)
+#pragma unroll
+        for (int ex = 0; ex < 2; ++ex) {
+            const bool in = (ex || i) && (ex == 0 || i < EX) && (ey || j) && (ey == 0 || j < (uint32_t)ny);
+            const T ev = bld<T>(er, (gy[ey] + gx[ex]) * (uint32_t)sizeof(T));
+            Ee[ey][ex] = in ? ev : T(0);
+        }
     T acc[2] = {0, 0};
 #define TM_ELEM(EY, EX)                                                                           \
     {                                                                                              \
-        const T Ee = Eat(EX, EY);                                                                  \
         T t[2] = {0, 0};                                                                           \
         elem2<loc2(1 - EX, 1 - EY), EY, EX>(kc, v, t);                                             \
-        acc[0] += Ee * t[0];                                                                       \
-        acc[1] += Ee * t[1];                                                                       \
+        acc[0] += Ee[EY][EX] * t[0];                                                               \
+        acc[1] += Ee[EY][EX] * t[1];                                                               \
     }
     TM_ELEM(0, 0)
     TM_ELEM(0, 1)
     TM_ELEM(1, 0)
     TM_ELEM(1, 1)
 #undef TM_ELEM
-    double dots[2] = {0.0, 0.0};
-    if (live) {
-        const T xo[2] = {x[2 * node], x[2 * node + 1]};
-        finish_node<T, 2, OP>(node, N, acc, xo, nm[node], b, y, dinv, omega, dots, ch);
+    T xo[2] = {v[4][0], v[4][1]};                   // this node's own value
+    if (MASK_IN) {
+        xo[0] = x[2 * nd];
+        xo[1] = x[2 * nd + 1];
     }
+    double dots[2] = {0.0, 0.0};
+    if (live) finish_store<T, 2, OP>(node, acc, xo, mo, fin, y, omega, dots, ch);
     if (OP == OP_QDOT) block_reduce_store<2>(dots, partials);
 }
 

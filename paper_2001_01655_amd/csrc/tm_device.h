@@ -55,6 +55,20 @@ template <>
 __device__ __forceinline__ double bld<double>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
     return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
 }
+// two consecutive values starting at byte offset off: one 8-byte load for FP32,
+// one 16-byte load for FP64 (bit casts, no value conversion)
+__device__ __forceinline__ void bld2(__amdgpu_buffer_rsrc_t r, uint32_t off, float (&v)[2]) {
+    typedef float f2 __attribute__((ext_vector_type(2)));
+    const f2 t = __builtin_bit_cast(f2, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+    v[0] = t.x;
+    v[1] = t.y;
+}
+__device__ __forceinline__ void bld2(__amdgpu_buffer_rsrc_t r, uint32_t off, double (&v)[2]) {
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    const d2 t = __builtin_bit_cast(d2, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+    v[0] = t.x;
+    v[1] = t.y;
+}
 // three consecutive values starting at byte offset off: one 12-byte load for
 // FP32, a 16-byte and an 8-byte load for FP64 (the vector assignments below
 // reinterpret the loaded bits; they convert no values)
