@@ -291,6 +291,32 @@ def adaptive_leg(n_designs: int, nel=(128, 64, 64), seed: int = 4):
     return out
 
 
+def multi_rhs_leg(H, p, n_rhs: int = 6, reps: int = 3):
+    """Six load cases of the workload's mesh solved together (x0 = 0, rtol 1e-8;
+    each right-hand side on a stream of its own) against the same six solved one
+    after another."""
+    import torch
+
+    import synth
+    F = torch.tensor(synth.served_loads(p.nel, p.dim, n_rhs), device="cuda")
+    H.solve(F, rtol=1e-8)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        r = H.solve(F, rtol=1e-8)
+    torch.cuda.synchronize()
+    together = (time.perf_counter() - t0) / reps
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        for k in range(n_rhs):
+            H.solve(F[k], rtol=1e-8)
+    torch.cuda.synchronize()
+    alone = (time.perf_counter() - t0) / reps
+    return {"n_rhs": n_rhs, "ms_together": round(together * 1e3, 2), "ms_one_by_one": round(alone * 1e3, 2),
+            "speedup": round(alone / together, 3), "iters": [int(i) for i in r.iters],
+            "MDoF_s_together": round(p.n_dof * n_rhs / together / 1e6, 1)}
+
+
 def filter_leg(nel, reps: int = 50):
     """tm_density_filter (radius 1.5) on the workload's element grid: mean time
     per launch from events around reps back-to-back calls of the C function on
@@ -403,6 +429,7 @@ def main():
             line["roofline"] = ents[dom]
             line["roofline_other_kernels"] = [ents[c] for c in ents if c != dom]
     u_mixed = res.u.clone()
+    line["multi_rhs"] = multi_rhs_leg(H, p)
     H.close()
     line["density_filter"] = filter_leg(p.nel)
     if not args.no_fp64:

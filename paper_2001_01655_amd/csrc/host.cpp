@@ -629,10 +629,55 @@ static tm_solve_state* new_state(tm_hierarchy* h, int nrhs) {
         free_list(st->allocs);
         for (Lane* ln : st->lanes) delete ln;
         if (st->sc_host) (void)hipHostFree(st->sc_host);
+        for (hipStream_t q : st->ls) (void)hipStreamDestroy(q);
+        for (hipEvent_t e : st->lev) (void)hipEventDestroy(e);
+        if (st->fork) (void)hipEventDestroy(st->fork);
+        if (st->ev) (void)hipEventDestroy(st->ev);
         delete st;
         throw;
     }
     return st;
+}
+
+// streams of their own for right-hand sides 1.. (tm_solve's cached state)
+static void make_lane_streams(tm_solve_state* st) {
+    if (st->nrhs < 2 || !st->ls.empty()) return;
+    try {
+        TM_HIP(hipEventCreateWithFlags(&st->fork, hipEventDisableTiming));
+        for (int k = 1; k < st->nrhs; ++k) {
+            hipStream_t q = nullptr;
+            TM_HIP(hipStreamCreateWithFlags(&q, hipStreamNonBlocking));     // default priority
+            st->ls.push_back(q);
+            hipEvent_t e = nullptr;
+            TM_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+            st->lev.push_back(e);
+        }
+    } catch (...) {
+        // all lanes on the state's stream, as for scheduler-driven states
+        for (hipStream_t q : st->ls) (void)hipStreamDestroy(q);
+        for (hipEvent_t e : st->lev) (void)hipEventDestroy(e);
+        st->ls.clear();
+        st->lev.clear();
+        throw;
+    }
+}
+
+// stream of right-hand side k, and the fork / join around a batch of work
+static hipStream_t lane_stream(const tm_solve_state* st, int k) {
+    return (k == 0 || st->ls.empty()) ? st->s : st->ls[k - 1];
+}
+
+static void fork_lanes(tm_solve_state* st) {
+    if (st->ls.empty()) return;
+    TM_HIP(hipEventRecord(st->fork, st->s));
+    for (hipStream_t q : st->ls) TM_HIP(hipStreamWaitEvent(q, st->fork, 0));
+}
+
+static void join_lanes(tm_solve_state* st) {
+    for (size_t k = 0; k < st->ls.size(); ++k) {
+        TM_HIP(hipEventRecord(st->lev[k], st->ls[k]));
+        TM_HIP(hipStreamWaitEvent(st->s, st->lev[k], 0));
+    }
 }
 
 static void delete_state(tm_solve_state* st);
@@ -651,10 +696,14 @@ void delete_cached_state(tm_hierarchy* h) {
 
 static void delete_state(tm_solve_state* st) {
     if (!st) return;
+    for (hipStream_t q : st->ls) (void)hipStreamSynchronize(q);
     free_list(st->allocs);
     for (Lane* ln : st->lanes) delete ln;
     if (st->sc_host) (void)hipHostFree(st->sc_host);
     if (st->ev) (void)hipEventDestroy(st->ev);
+    if (st->fork) (void)hipEventDestroy(st->fork);
+    for (hipEvent_t e : st->lev) (void)hipEventDestroy(e);
+    for (hipStream_t q : st->ls) (void)hipStreamDestroy(q);
     delete st;
 }
 
@@ -669,10 +718,11 @@ static void enqueue_vcycle_into_z(tm_hierarchy* h, Lane& ln, const int* done, hi
 
 static void enqueue_begin(tm_solve_state* st, const double* f, int use_u0) {
     tm_hierarchy* h = st->h;
-    hipStream_t s = st->s;
     const int64_t n = h->n_dof;
     const bool mixed = mixed_of(h);
+    fork_lanes(st);
     for (int k = 0; k < st->nrhs; ++k) {
+        hipStream_t s = lane_stream(st, k);
         Lane& ln = *st->lanes[k];
         KScal* sc = st->sc + k;
         double* u = st->u + (size_t)k * n;
@@ -686,11 +736,12 @@ static void enqueue_begin(tm_solve_state* st, const double* f, int use_u0) {
         TM_HIP(hipMemsetAsync(ln.p, 0, n * sizeof(double), s));
         launch_update_p(h, ln, sc, mixed, s);
     }
+    join_lanes(st);
 }
 
 static void enqueue_iteration(tm_solve_state* st, int k) {
     tm_hierarchy* h = st->h;
-    hipStream_t s = st->s;
+    hipStream_t s = lane_stream(st, k);
     const int64_t n = h->n_dof;
     const bool mixed = mixed_of(h);
     Lane& ln = *st->lanes[k];
@@ -711,8 +762,10 @@ static void enqueue_iteration(tm_solve_state* st, int k) {
 }
 
 static void enqueue_advance(tm_solve_state* st, int k_iters) {
+    fork_lanes(st);
     for (int it = 0; it < k_iters; ++it)
         for (int k = 0; k < st->nrhs; ++k) enqueue_iteration(st, k);
+    join_lanes(st);
     TM_HIP(hipMemcpyAsync(st->sc_host, st->sc, sizeof(KScal) * st->nrhs, hipMemcpyDeviceToHost, st->s));
     TM_HIP(hipEventRecord(st->ev, st->s));
     st->pending = true;
@@ -1147,6 +1200,7 @@ static tm_status begin_impl(tm_hierarchy* h, int32_t n_rhs, const double* f_dev,
             if (!h->cached) {
                 h->cached = new_state(h, n_rhs);
                 h->cached->owned_by_h = true;
+                make_lane_streams(h->cached);
             }
             st = h->cached;
         } else {
@@ -1217,11 +1271,13 @@ tm_status tm_batch_advance(int32_t n, tm_solve_state* const* sts, int32_t k_iter
         for (int i = 0; i < n; ++i)
             if (!sts[i] || sts[i]->ended) fail(TM_ERR_STATE, "state is NULL or ended");
         // interleave: one iteration of every state at a time, each on its own stream
+        for (int i = 0; i < n; ++i) fork_lanes(sts[i]);
         for (int it = 0; it < k_iters; ++it)
             for (int i = 0; i < n; ++i)
                 for (int k = 0; k < sts[i]->nrhs; ++k) enqueue_iteration(sts[i], k);
         for (int i = 0; i < n; ++i) {
             tm_solve_state* st = sts[i];
+            join_lanes(st);
             TM_HIP(hipMemcpyAsync(st->sc_host, st->sc, sizeof(KScal) * st->nrhs, hipMemcpyDeviceToHost,
                                   st->s));
             TM_HIP(hipEventRecord(st->ev, st->s));

@@ -252,6 +252,14 @@ struct tm_solve_state {
     tmi::KScal* sc = nullptr;      // device scalars [nrhs]
     tmi::KScal* sc_host = nullptr; // pinned mirror
     hipEvent_t ev = nullptr;
+    // tm_solve: right-hand sides 1.. run on streams of their own (lane 0 on s),
+    // forked from and joined back into s around every batch of enqueued work.
+    // States driven by a scheduler (tm_solve_begin) keep all lanes on s: the
+    // scheduler already overlaps requests, and more streams than hardware
+    // queues only serialise them.
+    std::vector<hipStream_t> ls;
+    std::vector<hipEvent_t> lev;
+    hipEvent_t fork = nullptr;
     bool ended = false, pending = false;
     bool owned_by_h = false;
     size_t bytes = 0;
@@ -259,8 +267,6 @@ struct tm_solve_state {
 };
 
 namespace tmi {
-// weight of the first smoothing sweep from a zero start on level l: omega for
-// Jacobi, 1 / theta_l for Chebyshev (its first step is a Jacobi step)
 // Weight of the first smoothing step from zero, x = w D^-1 b.  With Chebyshev
 // smoothing the stored D^-1 of each level is already divided by theta_l, the
 // centre of its interval, so that step has weight 1 (and every later step's
