@@ -74,6 +74,8 @@ def parse():
                     help="FP32 fine operator on the matrix cores (1) or vector FMAs (0)")
     ap.add_argument("--adaptive-stream", type=int, default=0,
                     help="designs in the automated-hybrid comparison on the bridge recipe (0: skip)")
+    ap.add_argument("--grid-study", action="store_true",
+                    help="the varying-spaced grid comparison (GMG / hybrids) of the 520x520 recipe")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="copy 256 MiB device-to-device first (counter calibration under rocprofv3 --pmc)")
     return ap.parse_args()
@@ -317,6 +319,42 @@ def multi_rhs_leg(H, p, n_rhs: int = 6, reps: int = 3):
             "MDoF_s_together": round(p.n_dof * n_rhs / together / 1e6, 1)}
 
 
+def grid_leg(pairs=((16, 16), (16, 256), (256, 16), (64, 64))):
+    """Varying-spaced grid of Sec. 4.3 (520x520, 8-element beams and columns at
+    spacings sx, sy; rtol 1e-8, FP32 V-cycle in FCG, block Jacobi w = 0.5 1/1):
+    setup and solve per hierarchy, pure GMG with 5 levels (ceil(n/2) coarsening,
+    2312 coarsest dofs), the hybrid with 4 geometric levels and aggregation below
+    1500 dofs, and aggregation from the second level on."""
+    import torch
+
+    import synth
+    from paper_2001_01655_amd import Hierarchy
+    variants = {"gmg5": dict(n_levels=5), "hybrid4": dict(n_geometric=4, max_coarse=1500),
+                "hybrid2": dict(n_geometric=2, max_coarse=1500)}
+    out = {}
+    for sx, sy in pairs:
+        p = synth.grid_2d(sx, sy)
+        f = torch.tensor(p.loads[0], device="cuda")
+        rec = {}
+        for name, o in variants.items():
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            H = Hierarchy(p.nel, p.rho, p.fixed, p=p.p, E0=p.E0, Emin=p.Emin, nu=p.nu, omega=0.5, nu_pre=1,
+                          nu_post=1, vcycle_fp=32, outer=0, max_iters=20000, **o)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            r = H.solve(f, rtol=1e-8)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            rec[name] = {"iters": int(r.iters[0]), "setup_ms": round((t1 - t0) * 1e3, 1),
+                         "solve_ms": round((t2 - t1) * 1e3, 1), "levels": H.num_levels(),
+                         "coarsest_dofs": H.level_info(H.num_levels() - 1)["n_rows"]}
+            H.close()
+        out[f"{sx}x{sy}"] = rec
+    out["workload"] = "2D grid 520x520 Q4 (543,762 dofs), 8-element features, rtol 1e-8"
+    return out
+
+
 def filter_leg(nel, reps: int = 50):
     """tm_density_filter (radius 1.5) on the workload's element grid: mean time
     per launch from events around reps back-to-back calls of the C function on
@@ -445,6 +483,8 @@ def main():
     line["detail"] = detail
     if args.served > 0:
         line["served"] = served_leg(args.served, args.served_designs, args.served_smoother, args.served_sweeps)
+    if args.grid_study:
+        line["grid_study"] = grid_leg()
     if args.adaptive_stream > 0:
         line["adaptive_stream"] = adaptive_leg(args.adaptive_stream)
     if not args.no_cpu_baseline:

@@ -142,6 +142,21 @@ def element_stiffness(dim: int, nu: float, h: float = 1.0) -> np.ndarray:
     return 0.5 * (KE + KE.T)
 
 
+def element_stiffness_box(dim: int, nu: float, sizes) -> np.ndarray:
+    """KE for E = 1 on an axis-aligned box with the given edge lengths (the
+    coarse elements of an odd-count coarsening are such boxes); equal to
+    element_stiffness for a cube."""
+    D = elasticity_matrix(dim, nu)
+    g = 1.0 / np.sqrt(3.0)
+    jac = np.asarray(sizes, dtype=float) / 2.0
+    KE = np.zeros((dim * 2 ** dim, dim * 2 ** dim))
+    for xi in itertools.product([-g, g], repeat=dim):
+        grad = _shape_grad_ref(dim, np.array(xi)) / jac[None, :]
+        B = strain_displacement(dim, grad)
+        KE += B.T @ D @ B * np.prod(jac)
+    return 0.5 * (KE + KE.T)
+
+
 def simp(rho: np.ndarray, p: float, E0: float, Emin: float) -> np.ndarray:
     """Modified SIMP law  E = Emin + (E0 - Emin) rho^p."""
     return Emin + (E0 - Emin) * np.power(rho, p)

@@ -119,38 +119,45 @@ def galerkin(P: sp.spmatrix, A: sp.spmatrix) -> sp.csr_matrix:
 
 
 # ------------------------------------------------------- geometric transfers
+def coarse_count(n: int) -> int:
+    """Elements of the next coarser level along an axis: ceil(n/2) (Sec. 4.3)."""
+    return (n + 1) // 2
+
+
+def axis_prolongator(n: int) -> sp.csr_matrix:
+    """1D interpolation from the coarse nodes (ceil(n/2) elements) to the n + 1
+    fine nodes of one axis.  Coarse node I sits on fine node min(2I, n): a fine
+    node on a coarse node takes it with weight 1, a fine node halfway between two
+    coarse nodes takes each with weight 1/2 (for odd n the last coarse element is
+    one fine element, so its end nodes are both coarse)."""
+    nc = coarse_count(n)
+    pos = np.minimum(2 * np.arange(nc + 1), n)
+    W = np.zeros((n + 1, nc + 1))
+    for I, x in enumerate(pos):
+        W[x, I] = 1.0
+    for i in range(n + 1):
+        if W[i].sum() == 0.0:                      # strictly between two coarse nodes
+            left = np.searchsorted(pos, i) - 1
+            W[i, left] = W[i, left + 1] = 0.5
+    return sp.csr_matrix(W)
+
+
 def geometric_prolongator(nel, fixed: Optional[np.ndarray] = None) -> sp.csr_matrix:
-    """P (fine dofs x coarse dofs) from coarse-grid shape functions: fine node i
-    takes weight prod_axes w(i_a - 2 I_a) from coarse node I, w(0)=1,
-    w(+-1)=1/2, identity over components.  If `fixed` is given, the rows of
-    supported fine dofs are dropped (P~ = M P)."""
+    """P (fine dofs x coarse dofs) from coarse-grid shape functions: the tensor
+    product of the per-axis interpolations (x fastest), identity over the dof
+    components.  If `fixed` is given, the rows of supported fine dofs are
+    dropped (P~ = M P)."""
     dim = len(nel)
-    cel = [n // 2 for n in nel]
-    fcoords = fem.node_coordinates(nel).astype(np.int64)
-    nf = fcoords.shape[0]
-    rows, cols, vals = [], [], []
-    for off in np.array(list(np.ndindex(*([3] * dim)))) - 1:
-        # coarse node 2I = i - off  requires (i - off) even and inside
-        c2 = fcoords - off[None, :]
-        ok = np.all((c2 % 2 == 0) & (c2 >= 0), axis=1)
-        C = c2 // 2
-        ok &= np.all(C <= np.array(cel)[None, :], axis=1)
-        w = np.prod(np.where(off == 0, 1.0, 0.5))
-        fi = np.nonzero(ok)[0]
-        ci = fem.node_index(cel, C[fi])
-        for c in range(dim):
-            rows.append(dim * fi + c)
-            cols.append(dim * ci + c)
-            vals.append(np.full(fi.shape[0], w))
-    r = np.concatenate(rows)
-    c = np.concatenate(cols)
-    v = np.concatenate(vals)
-    nc = dim * int(np.prod([n + 1 for n in cel]))
+    Pn = axis_prolongator(nel[0])
+    for n in nel[1:]:
+        Pn = sp.kron(axis_prolongator(n), Pn, format="csr")     # slower axes to the left
+    P = sp.kron(Pn, sp.identity(dim), format="csr")
+    P.eliminate_zeros()
     if fixed is not None and len(fixed) > 0:
-        m = fem.free_mask(dim * nf, fixed)
-        keep = m[r] > 0
-        r, c, v = r[keep], c[keep], v[keep]
-    P = sp.csr_matrix((v, (r, c)), shape=(dim * nf, nc))
+        m = fem.free_mask(P.shape[0], fixed)
+        P = sp.diags(m) @ P
+        P.eliminate_zeros()
+    P = sp.csr_matrix(P)
     P.sort_indices()
     return P
 
@@ -211,12 +218,12 @@ def build_geometric(nel, E: np.ndarray, KE: np.ndarray, fixed: np.ndarray, L: in
     As, Ps = [A0], []
     cur = list(nel)
     for l in range(L - 1):
-        if any(n % 2 for n in cur):
-            raise ValueError(f"element counts {cur} not divisible by 2 at level {l}")
+        if any(n < 2 for n in cur):
+            raise ValueError(f"element counts {cur} cannot be coarsened at level {l}")
         P = geometric_prolongator(tuple(cur), fixed if l == 0 else None)
         Ps.append(P)
         As.append(galerkin(P, As[-1]))
-        cur = [n // 2 for n in cur]
+        cur = [coarse_count(n) for n in cur]
     return finish(As, Ps, [dim] * L, omega, nu_pre, nu_post, point_jacobi, ["geo"] * (L - 1),
                   smoother=smoother, cheb_lower=cheb_lower, fixed=fixed)
 

@@ -166,6 +166,8 @@ def build_hybrid(nel, E, KE, fixed, n_geometric: int, max_coarse: int = 1000,
     """n_geometric levels (fine grid included) of geometric coarsening, then
     smoothed aggregation until the level has fewer than max_coarse dofs."""
     dim = len(nel)
+    if any(n % 2 ** (n_geometric - 1) for n in nel):
+        raise ValueError("aggregation is built on an even chain of geometric halvings only")
     Hg = mg.build_geometric(nel, E, KE, fixed, n_geometric, omega, nu_pre, nu_post)
     As, Ps, bss, kinds = list(Hg.A), list(Hg.P), list(Hg.bs), list(Hg.kinds)
     aggs = [None] * len(As)

@@ -186,29 +186,6 @@ static void ke_class_values(const KeClasses<DIM>& T, const std::vector<double>& 
 
 // Q[c][a][b]: weight of parent corner b at child c's corner a (coarse shape
 // functions), child c at offsets (c&1, c>>1&1, c>>2&1) inside its parent.
-static void child_weights(int dim, std::vector<double>& Q) {
-    const int npe = 1 << dim;
-    Q.assign((size_t)npe * npe * npe, 0.0);
-    int off[8][3];
-    for (int z = 0; z < (dim == 3 ? 2 : 1); ++z)
-        for (int y = 0; y < 2; ++y)
-            for (int x = 0; x < 2; ++x) {
-                const int a = dim == 3 ? loc3(x, y, z) : loc2(x, y);
-                off[a][0] = x;
-                off[a][1] = y;
-                off[a][2] = z;
-            }
-    auto phi = [](int d) { return d == 0 ? 1.0 : (d == 1 || d == -1) ? 0.5 : 0.0; };
-    for (int c = 0; c < npe; ++c) {
-        const int cp[3] = {c & 1, (c >> 1) & 1, (c >> 2) & 1};
-        for (int a = 0; a < npe; ++a)
-            for (int b = 0; b < npe; ++b) {
-                double w = 1.0;
-                for (int k = 0; k < dim; ++k) w *= phi(cp[k] + off[a][k] - 2 * off[b][k]);
-                Q[((size_t)c * npe + a) * npe + b] = w;
-            }
-    }
-}
 
 // ------------------------------------------------------------------ validation / plan
 static int64_t nodes_of(const int* nel, int dim) {
@@ -263,6 +240,7 @@ static void check_material(const tm_material* m) {
 struct Plan {
     int Lg = 1;
     bool sa = false;
+    bool odd = false;       // some geometric coarsening halves an odd element count
     int L_total = 1;        // known for pure geometric hierarchies
 };
 
@@ -271,9 +249,11 @@ static Plan plan_levels(const tm_mesh* m, const tm_options* o) {
     const int dim = m->dim;
     int cur[3] = {m->nel[0], m->nel[1], dim == 3 ? m->nel[2] : 1};
     auto dofs = [&](const int* c) { return nodes_of(c, dim) * dim; };
-    auto even = [&](const int* c) {
+    // a level coarsens to ceil(n/2) elements per axis (Sec. 4.3); every axis
+    // needs at least two elements for that to shrink it
+    auto coarsenable = [&](const int* c) {
         for (int d = 0; d < dim; ++d)
-            if (c[d] % 2 || c[d] < 2) return false;
+            if (c[d] < 2) return false;
         return true;
     };
     if (o->n_geometric > 0) {
@@ -283,8 +263,8 @@ static Plan plan_levels(const tm_mesh* m, const tm_options* o) {
         p.Lg = o->n_levels;
     } else {
         p.Lg = 1;
-        while (dofs(cur) >= o->max_coarse && even(cur)) {
-            for (int d = 0; d < dim; ++d) cur[d] /= 2;
+        while (dofs(cur) >= o->max_coarse && coarsenable(cur)) {
+            for (int d = 0; d < dim; ++d) cur[d] = (cur[d] + 1) / 2;
             ++p.Lg;
         }
         cur[0] = m->nel[0];
@@ -292,10 +272,15 @@ static Plan plan_levels(const tm_mesh* m, const tm_options* o) {
         cur[2] = dim == 3 ? m->nel[2] : 1;
     }
     for (int l = 0; l + 1 < p.Lg; ++l) {
-        if (!even(cur))
-            fail(TM_ERR_ARG, "element counts must be divisible by 2^(geometric levels - 1)");
-        for (int d = 0; d < dim; ++d) cur[d] /= 2;
+        if (!coarsenable(cur))
+            fail(TM_ERR_ARG, "too many geometric levels: an axis would be coarsened below one element");
+        for (int d = 0; d < dim; ++d) {
+            if (cur[d] & 1) p.odd = true;
+            cur[d] = (cur[d] + 1) / 2;
+        }
     }
+    if (p.sa && p.odd)
+        fail(TM_ERR_ARG, "smoothed aggregation after a coarsening of an odd element count is not supported");
     p.L_total = p.Lg;
     return p;
 }
@@ -312,7 +297,9 @@ static void alloc_level_geo(tm_hierarchy* h, Level& L, int l) {
     L.dim = dim;
     L.bs = dim;
     for (int d = 0; d < 3; ++d) {
-        L.nel[d] = d < dim ? (h->mesh.nel[d] >> l) : 1;
+        int n = d < dim ? h->mesh.nel[d] : 1;
+        for (int q = 0; q < l; ++q) n = (n + 1) / 2;          // ceil(n/2) per coarsening
+        L.nel[d] = n;
         L.nn[d] = d < dim ? L.nel[d] + 1 : 1;
     }
     L.n_nodes = nodes_of(L.nel, dim);
@@ -931,19 +918,40 @@ static void geo_prolongator(const tm_hierarchy* h, int l, std::vector<int64_t>& 
     v.clear();
     const int FX = F.nn[0], FY = F.nn[1];
     const int CX = C.nn[0], CY = C.nn[1];
+    // per axis: fine node i lies on coarse node i/2 (even i), halfway between
+    // (i-1)/2 and (i+1)/2 (odd i), or, for the last node of an odd count, on
+    // the last coarse node
+    auto parents = [](int i, int nf, int* I, double* w) {
+        if ((nf & 1) && i == nf) {
+            I[0] = (nf + 1) / 2;
+            w[0] = 1.0;
+            return 1;
+        }
+        if (!(i & 1)) {
+            I[0] = i / 2;
+            w[0] = 1.0;
+            return 1;
+        }
+        I[0] = (i - 1) / 2;
+        I[1] = (i + 1) / 2;
+        w[0] = w[1] = 0.5;
+        return 2;
+    };
     for (int64_t node = 0; node < F.n_nodes; ++node) {
         const int i = (int)(node % FX), j = (int)((node / FX) % FY), k = (int)(node / ((int64_t)FX * FY));
+        int Ix[2], Iy[2], Iz[2] = {0, 0};
+        double wx[2], wy[2], wz[2] = {1.0, 0.0};
+        const int nx = parents(i, F.nel[0], Ix, wx), ny = parents(j, F.nel[1], Iy, wy);
+        const int nz = dim == 3 ? parents(k, F.nel[2], Iz, wz) : 1;
         for (int r = 0; r < dim; ++r) {
             const bool dropped = l == 0 && (nm[node] & (1u << r));
             if (!dropped) {
                 // coarse nodes in ascending id order: z, then y, then x
-                for (int c2 = 0; c2 < ((dim == 3 && (k & 1)) ? 2 : 1); ++c2)
-                    for (int b2 = 0; b2 < ((j & 1) ? 2 : 1); ++b2)
-                        for (int a2 = 0; a2 < ((i & 1) ? 2 : 1); ++a2) {
-                            const int I = (i >> 1) + a2, J = (j >> 1) + b2, K = (k >> 1) + c2;
-                            const double w = ((i & 1) ? 0.5 : 1.0) * ((j & 1) ? 0.5 : 1.0) *
-                                             ((dim == 3 && (k & 1)) ? 0.5 : 1.0);
-                            const int64_t Cn = ((int64_t)K * CY + J) * CX + I;
+                for (int c2 = 0; c2 < nz; ++c2)
+                    for (int b2 = 0; b2 < ny; ++b2)
+                        for (int a2 = 0; a2 < nx; ++a2) {
+                            const double w = wx[a2] * wy[b2] * wz[c2];
+                            const int64_t Cn = ((int64_t)Iz[c2] * CY + Iy[b2]) * CX + Ix[a2];
                             ci.push_back((int32_t)(dim * Cn + r));
                             v.push_back(w);
                         }
@@ -1010,7 +1018,7 @@ tm_status tm_plan_bytes(const tm_mesh* mesh, const tm_options* opts, int32_t n_r
         const bool mixed = opts->vcycle_fp == 32;
         int64_t last_n = nodes0 * dim;
         for (int l = 1; l < p.Lg; ++l) {
-            for (int d = 0; d < dim; ++d) nel[d] /= 2;
+            for (int d = 0; d < dim; ++d) nel[d] = (nel[d] + 1) / 2;
             const int64_t nn = nodes_of(nel, dim);
             const int64_t ne = (int64_t)nel[0] * nel[1] * (dim == 3 ? nel[2] : 1);
             const int nst = dim == 3 ? 27 : 9, nq = (nst - 1) / 2 * bb + dim * (dim + 1) / 2;
@@ -1077,11 +1085,10 @@ tm_status tm_setup(const tm_mesh* mesh, const tm_material* mat, const double* rh
         h->fixed = fixed;
         h->flags = halloc<int>(h, 4);
         // constants
-        std::vector<double> KE, Q;
+        std::vector<double> KE;
         element_stiffness(dim, mat->nu, mesh->h, KE);
         if (dim == 3) ke_class_values(KE_CLS3, KE, h);
         else ke_class_values(KE_CLS2, KE, h);
-        child_weights(dim, Q);
         h->KE64 = halloc<double>(h, KE.size());
         h->rho64 = halloc<double>(h, (size_t)h->n_el);
         // A operand of the matrix-core operator: register q, lane L holds row
@@ -1099,10 +1106,8 @@ tm_status tm_setup(const tm_mesh* mesh, const tm_material* mat, const double* rh
                 }
             h->KA32 = halloc<float>(h, KA32.size());
         }
-        h->Q64 = halloc<double>(h, Q.size());
         TM_HIP(hipMemcpyAsync(h->KE64, KE.data(), KE.size() * 8, hipMemcpyHostToDevice, s));
         if (dim == 3) TM_HIP(hipMemcpyAsync(h->KA32, KA32.data(), KA32.size() * 4, hipMemcpyHostToDevice, s));
-        TM_HIP(hipMemcpyAsync(h->Q64, Q.data(), Q.size() * 8, hipMemcpyHostToDevice, s));
         // levels
         h->lv.resize(plan.Lg);
         for (int l = 0; l < plan.Lg; ++l) alloc_level_geo(h, h->lv[l], l);
@@ -1137,7 +1142,11 @@ tm_status tm_update_density(tm_hierarchy* h, const double* rho_dev, void* stream
             int Lg = 0;
             for (auto& L : h->lv)
                 if (L.kind != TM_LEVEL_AGGREGATION) ++Lg;
-            if (Lg > 2) {
+            // aggregation needs a geometric chain of even halvings (node coordinates)
+            bool odd = false;
+            for (int q = 0; q + 2 < Lg; ++q)
+                for (int d = 0; d < h->dim; ++d) odd = odd || (h->lv[q].nel[d] & 1);
+            if (Lg > 2 && !odd) {
                 h->lv.resize(Lg - 1);
                 h->sa = true;
             }

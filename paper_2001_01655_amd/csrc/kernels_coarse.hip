@@ -15,10 +15,23 @@
 namespace tmi {
 
 // --------------------------------------------------------------- Galerkin
+// Coarse element E: K_E = sum over its children c of Q_c^T K_c Q_c (masked
+// rows/columns of supported fine dofs dropped).  Per axis a coarse element has
+// two children (fine elements 2X, 2X+1), or one (the last coarse element of an
+// odd count, which is the fine element 2X itself); Q_c is the tensor product of
+// the per-axis weights of the child's two fine nodes on the coarse element's
+// two nodes.
+__device__ __forceinline__ double axis_w(int kind, int a, int b) {
+    // kind 0 / 1: first / second half (fine node 2X + kind + a); kind 2: whole
+    if (kind == 2) return a == b ? 1.0 : 0.0;
+    const int d = kind + a - 2 * b;
+    return d == 0 ? 1.0 : (d == 1 || d == -1) ? 0.5 : 0.0;
+}
+
 template <int DIM>
 __global__ void k_galerkin(const double* __restrict__ child, const double* __restrict__ E,
                            const double* __restrict__ KE, const uint8_t* __restrict__ nm,
-                           const double* __restrict__ Q, int cnx, int cny, int cnz,
+                           int fnx, int fny, int fnz, int cnx, int cny, int cnz,
                            double* __restrict__ parent) {
     constexpr int NPE = 1 << DIM, ND = DIM * NPE;
     __shared__ double Kc[ND * ND];
@@ -29,12 +42,15 @@ __global__ void k_galerkin(const double* __restrict__ child, const double* __res
     const int X = (int)(pe % cnx);
     const int Y = (int)((pe / cnx) % cny);
     const int Z = DIM == 3 ? (int)(pe / ((int64_t)cnx * cny)) : 0;
-    const int fnx = 2 * cnx, fny = 2 * cny;
     const int t = threadIdx.x;
     const int r = t / ND, s = t % ND;
+    // children per axis: 2, or 1 (whole) for the last element of an odd count
+    const bool wx = 2 * X + 1 == fnx, wy = 2 * Y + 1 == fny, wz = DIM == 3 && 2 * Z + 1 == fnz;
     double acc = 0.0;
     for (int c = 0; c < NPE; ++c) {
         const int cx = c & 1, cy = (c >> 1) & 1, cz = (c >> 2) & 1;   // child position bits
+        if ((wx && cx) || (wy && cy) || (wz && cz)) continue;         // block-uniform
+        const int kx = wx ? 2 : cx, ky = wy ? 2 : cy, kz = wz ? 2 : cz;
         const int gx = 2 * X + cx, gy = 2 * Y + cy, gz = 2 * Z + cz;
         const int64_t ce = DIM == 3 ? ((int64_t)gz * fny + gy) * fnx + gx : (int64_t)gy * fnx + gx;
         if (child) {
@@ -42,7 +58,17 @@ __global__ void k_galerkin(const double* __restrict__ child, const double* __res
         } else {
             Kc[t] = E[ce] * KE[t];
         }
-        if (t < NPE * NPE) q[t] = Q[c * NPE * NPE + t];
+        if (t < NPE * NPE) {
+            // q[a][b]: weight of the child's local corner a on the coarse corner b
+            const int a = t / NPE, b = t % NPE;
+            const int ax = (a == 1 || a == 2 || a == 5 || a == 6) ? 1 : 0;
+            const int ay = (a == 2 || a == 3 || a == 6 || a == 7) ? 1 : 0;
+            const int az = a >= 4 ? 1 : 0;
+            const int bx = (b == 1 || b == 2 || b == 5 || b == 6) ? 1 : 0;
+            const int by = (b == 2 || b == 3 || b == 6 || b == 7) ? 1 : 0;
+            const int bz = b >= 4 ? 1 : 0;
+            q[t] = axis_w(kx, ax, bx) * axis_w(ky, ay, by) * (DIM == 3 ? axis_w(kz, az, bz) : 1.0);
+        }
         if (t < NPE * DIM) {
             const int a = t / DIM, comp = t % DIM;
             double m = 1.0;
@@ -88,10 +114,10 @@ void launch_galerkin_elems(const tm_hierarchy* h, int fine_level, const double* 
     const uint8_t* nm = fine_level == 0 ? F.nmask : nullptr;
     if (h->dim == 3)
         hipLaunchKernelGGL(k_galerkin<3>, dim3((unsigned)n_par), dim3(576), 0, s, child, F.E64,
-                           h->KE64, nm, h->Q64, C.nel[0], C.nel[1], C.nel[2], parent);
+                           h->KE64, nm, F.nel[0], F.nel[1], F.nel[2], C.nel[0], C.nel[1], C.nel[2], parent);
     else
         hipLaunchKernelGGL(k_galerkin<2>, dim3((unsigned)n_par), dim3(64), 0, s, child, F.E64,
-                           h->KE64, nm, h->Q64, C.nel[0], C.nel[1], 1, parent);
+                           h->KE64, nm, F.nel[0], F.nel[1], 1, C.nel[0], C.nel[1], 1, parent);
 }
 
 // --------------------------------------------------------------- stencil assembly
@@ -490,8 +516,41 @@ template void launch_stencil_op<float>(const Level&, int, const float*, const fl
                                        const int*, hipStream_t, const ChebArgs&);
 
 // --------------------------------------------------------------- transfers
-// restriction b_c = P~^T r_f: coarse node I gathers fine nodes 2I + d, d in {-1,0,1}^dim,
-// with weight prod w(d_a), w(0) = 1, w(+-1) = 1/2; supported fine dofs contribute 0.
+// Per axis with nf fine elements and ceil(nf/2) coarse ones, coarse node I sits
+// on fine node min(2I, nf): for an odd nf the last coarse node sits on the last
+// fine node, and the last coarse element is a single fine element.
+__device__ __forceinline__ int coarse_pos(int I, int nf) { return min(2 * I, nf); }
+
+// weight of the fine node at offset d in {-1, 0, 1} from coarse node I's position
+template <typename T>
+__device__ __forceinline__ T restrict_w(int I, int d, int nf) {
+    if (2 * I > nf) return d == 0 ? T(1) : T(0);
+    const int j = 2 * I + d;
+    if (j < 0 || j > nf) return T(0);
+    if (d == 0) return T(1);
+    return ((nf & 1) && j == nf) ? T(0) : T(0.5);      // the last fine node of an odd count is coarse
+}
+
+// the (one or two) coarse parents of fine node i and their weights
+template <typename T>
+__device__ __forceinline__ void prolong_parents(int i, int nf, int (&ia)[2], T (&w)[2]) {
+    const int nc1 = (nf + 1) / 2;                       // last coarse node
+    if ((nf & 1) && i == nf) {
+        ia[0] = ia[1] = nc1;
+        w[0] = T(1);
+        w[1] = T(0);
+    } else {
+        ia[0] = i >> 1;
+        ia[1] = min((i >> 1) + 1, nc1);
+        w[0] = (i & 1) ? T(0.5) : T(1);
+        w[1] = (i & 1) ? T(0.5) : T(0);
+    }
+}
+
+
+// restriction b_c = P~^T r_f: coarse node I gathers the fine nodes at offsets d in
+// {-1,0,1}^dim from its position, with weight prod restrict_w (1 on it, 1/2 on a
+// fine midpoint, 0 otherwise); supported fine dofs contribute 0.
 // Optionally also x_c = omega D_c^-1 b_c (the first sweep of the coarse level from zero).
 template <typename T, int DIM, bool FIRST, bool MASK>
 __global__ __launch_bounds__(WG) void k_restrict(const T* __restrict__ rf, const uint8_t* __restrict__ nm,
@@ -518,12 +577,12 @@ __global__ __launch_bounds__(WG) void k_restrict(const T* __restrict__ rf, const
 #pragma unroll
     for (int q = 0; q < NS; ++q) {
         const int dx = q % 3 - 1, dy = (q / 3) % 3 - 1, dz = DIM == 3 ? q / 9 - 1 : 0;
-        const int fi = 2 * I + dx, fj = 2 * J + dy, fk = 2 * K + dz;
-        const bool in = fi >= 0 && fi < FX && fj >= 0 && fj < FY && (DIM == 2 || (fk >= 0 && fk < FZ));
+        const int fi = coarse_pos(I, fnx) + dx, fj = coarse_pos(J, fny) + dy;
+        const int fk = DIM == 3 ? coarse_pos(K, fnz) + dz : 0;
         const int gi = min(max(fi, 0), FX - 1), gj = min(max(fj, 0), FY - 1);
         const int gk = DIM == 3 ? min(max(fk, 0), FZ - 1) : 0;
         const uint32_t f = (uint32_t)(DIM == 3 ? (gk * FY + gj) * FX + gi : gj * FX + gi);
-        w[q] = in ? (dx ? T(0.5) : T(1)) * (dy ? T(0.5) : T(1)) * (dz ? T(0.5) : T(1)) : T(0);
+        w[q] = restrict_w<T>(I, dx, fnx) * restrict_w<T>(J, dy, fny) * (DIM == 3 ? restrict_w<T>(K, dz, fnz) : T(1));
         if constexpr (DIM == 3) {
             bld3(rr, f * (uint32_t)(3 * sizeof(T)), v[q]);
         } else {
@@ -597,18 +656,17 @@ __global__ __launch_bounds__(WG) void k_prolong(const T* __restrict__ xc, const 
     const int64_t Nf = (int64_t)FX * FY * (DIM == 3 ? FZ : 1);
     const int64_t node = xcd_block() * WG + threadIdx.x;
     if (node >= Nf) return;
-    const int CX = fnx / 2 + 1, CY = fny / 2 + 1;
+    const int CX = (fnx + 1) / 2 + 1, CY = (fny + 1) / 2 + 1;     // ceil(n/2) + 1 coarse nodes
     const int i = (int)(node % FX);
     const int j = (int)((node / FX) % FY);
     const int k = DIM == 3 ? (int)(node / ((int64_t)FX * FY)) : 0;
-    const int CZ = fnz / 2 + 1;
-    // per axis: coarse nodes i>>1 and (i>>1)+1 (clamped), weights (1, 0) or (1/2, 1/2)
-    const int ia[2] = {i >> 1, min((i >> 1) + 1, CX - 1)};
-    const int ja[2] = {j >> 1, min((j >> 1) + 1, CY - 1)};
-    const int ka[2] = {k >> 1, DIM == 3 ? min((k >> 1) + 1, CZ - 1) : 0};
-    const T wi[2] = {(i & 1) ? T(0.5) : T(1), (i & 1) ? T(0.5) : T(0)};
-    const T wj[2] = {(j & 1) ? T(0.5) : T(1), (j & 1) ? T(0.5) : T(0)};
-    const T wk[2] = {(k & 1) ? T(0.5) : T(1), (k & 1) ? T(0.5) : T(0)};
+    const int CZ = (fnz + 1) / 2 + 1;
+    // per axis: the coarse parents (one with weight 1, or two with 1/2 each)
+    int ia[2], ja[2], ka[2] = {0, 0};
+    T wi[2], wj[2], wk[2] = {T(1), T(0)};
+    prolong_parents<T>(i, fnx, ia, wi);
+    prolong_parents<T>(j, fny, ja, wj);
+    if (DIM == 3) prolong_parents<T>(k, fnz, ka, wk);
     // all loads (the coarse corners, this node's value and mask) before the
     // arithmetic; the store is unconditional (supported dofs keep their value)
     const int64_t Nc = (int64_t)CX * CY * (DIM == 3 ? CZ : 1);

@@ -211,7 +211,6 @@ struct tm_hierarchy {
     float* KA32 = nullptr;         // 3D: KE as the broadcast A operand of the matrix-core fine operator
     tmi::KeVals<double> kc64{};       // KE symmetry-class values (fine operator arguments)
     tmi::KeVals<float> kc32{};
-    double* Q64 = nullptr;         // coarse-from-fine interpolation weights per child [2^d][2^d][2^d]
     double* ainv = nullptr;        // inverse of the coarsest operator (FP64, dense)
     float* ainv32 = nullptr;
     int64_t nc = 0;                // coarsest dofs

@@ -315,12 +315,35 @@ def small_case(dim: int, nel, seed: int = 11, contrast: bool = True,
     return Problem(f"small{dim}d", dim, tuple(nel), rho, fixed, F)
 
 
+def grid_2d(sx: int = 16, sy: int = 256, nel=(520, 520), width: int = 8) -> Problem:
+    """2D varying-spaced grid (Sec. 4.3): a square of nel elements, all dofs of
+    the bottom nodes fixed, a uniform downward load of total 1 on the top edge
+    (consistent nodal forces, end nodes half), density 1 in beams and columns
+    `width` elements wide and VOID elsewhere.  Columns start at x = 0, sx, 2 sx,
+    ... with one flush with the right edge; beams end at the top edge and repeat
+    every sy elements downwards.  No random numbers are involved."""
+    nx, ny = nel
+    rho = np.full((ny, nx), VOID)
+    for x0 in list(range(0, nx - width + 1, sx)) + [nx - width]:
+        rho[:, x0:x0 + width] = 1.0
+    for y1 in range(ny, width - 1, -sy):
+        rho[y1 - width:y1, :] = 1.0
+    bottom = node_id(nel, np.arange(nx + 1), 0)
+    fixed = _uniq(_dofs(nel, 2, bottom, range(2)))
+    w = np.full(nx + 1, 1.0 / nx)
+    w[[0, -1]] *= 0.5
+    F = np.zeros((1, 2 * (nx + 1) * (ny + 1)))
+    F[0, 2 * node_id(nel, np.arange(nx + 1), ny) + 1] = -w
+    return Problem(f"grid2d_{sx}_{sy}", 2, tuple(nel), rho.ravel(), fixed, F)
+
+
 CONFIGS = {
     "mbb_uniform": lambda: mbb_2d(True),
     "mbb_random": lambda: mbb_2d(False),
     "cantilever2d": cantilever_2d,
     "cantilever3d": cantilever_3d,
     "bridge3d": bridge_3d,
+    "grid2d": grid_2d,
 }
 
 

@@ -48,7 +48,8 @@ def _setup_status(nel=(8, 4), nu=0.3, Emin=1e-9, E0=1.0, dofs=(0, 1), **opts):
 
 
 @pytest.mark.parametrize("kw,msg", [
-    (dict(nel=(7, 4), n_levels=3), "divisible"),
+    (dict(nel=(8, 2), n_levels=3), "too many geometric levels"),
+    (dict(nel=(7, 4), n_geometric=2), "odd element count"),
     (dict(nu=0.5), "nu"),
     (dict(Emin=2.0), "Emin"),
     (dict(dofs=(0, 10 ** 9)), "out of range"),
@@ -81,8 +82,9 @@ def test_plan_bytes():
     b1 = tm.tm_plan_bytes(m, o, 1)
     b4 = tm.tm_plan_bytes(m, o, 4)
     assert 0 < b1 < b4
+    assert tm.tm_plan_bytes(L.make_mesh((63, 32, 32)), o, 1) > 0      # odd counts coarsen to ceil(n/2)
     with pytest.raises(tm.TmError):
-        tm.tm_plan_bytes(L.make_mesh((63, 32, 32)), o, 1)
+        tm.tm_plan_bytes(L.make_mesh((64, 32, 4)), o, 1)               # 4 -> 2 -> 1 -> (none)
 
 
 @pytest.mark.parametrize("nel", [(5, 3), (3, 4, 2)])

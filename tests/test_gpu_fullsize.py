@@ -18,6 +18,8 @@ CONFIGS = {
     "cantilever3d": ("cantilever3d", dict(n_levels=6)),
     "cantilever3d_cheb": ("cantilever3d", dict(n_levels=6, **CHEB22)),
     "bridge3d": ("bridge3d", dict(n_geometric=3, max_coarse=1000)),
+    # Sec. 4.3: 5 geometric levels with ceil(n/2) coarsening, 2312 coarsest dofs
+    "grid2d": ("grid2d", dict(n_levels=5, max_iters=20000)),
 }
 
 
@@ -49,6 +51,9 @@ def test_full_size_solve(name):
     res = H.solve(torch.tensor(p.loads[0], device="cuda"), rtol=1e-8)
     assert res.status == 0
     _check(p, res)
+    if name == "grid2d":
+        sizes = [H.level_info(l)["n_rows"] for l in range(H.num_levels())]
+        assert sizes == [2 * 521 * 521, 2 * 261 * 261, 2 * 131 * 131, 2 * 66 * 66, 2312]
     if name == "bridge3d":
         info = [H.level_info(l) for l in range(H.num_levels())]
         lg = next(l for l, i in enumerate(info) if i["kind"] == 2) - 1

@@ -33,7 +33,8 @@ def _rel(a, b):
     return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
 
 
-CASES = [(2, (28, 12), 3), (3, (10, 6, 4), 2), (3, (12, 8, 8), 3)]
+# the last two coarsen odd element counts to ceil(n/2) (Sec. 4.3)
+CASES = [(2, (28, 12), 3), (3, (10, 6, 4), 2), (3, (12, 8, 8), 3), (2, (13, 7), 3), (3, (9, 5, 7), 3)]
 
 
 @pytest.mark.parametrize("dim,nel,L", CASES)
@@ -121,7 +122,7 @@ def test_mbb_solve_vs_dense(uniform, vfp, outer):
     G.close()
 
 
-@pytest.mark.parametrize("dim,nel,L", [(2, (64, 32), 4), (3, (16, 8, 8), 3)])
+@pytest.mark.parametrize("dim,nel,L", [(2, (64, 32), 4), (3, (16, 8, 8), 3), (2, (45, 23), 4), (3, (11, 6, 5), 3)])
 @pytest.mark.parametrize("vfp", [64, 32])
 def test_solve_vs_oracle(dim, nel, L, vfp):
     """u at rtol 1e-8 against the oracle at rtol 1e-12 (contrast 1e9 in E)."""

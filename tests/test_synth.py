@@ -42,3 +42,16 @@ def test_cantilever_2d_solid_is_anchored():
     assert n == 1 and solid[:, 0].any()
     # the element under the load node is solid and the field is not all solid
     assert solid[ny // 2, nx - 1] and 0.3 < solid.mean() < 0.9
+
+
+def test_grid_recipe():
+    """Varying-spaced grid (Sec. 4.3): 8-element features at the given
+    spacings, bottom nodes fixed, unit total load on the top edge."""
+    import synth
+    p = synth.grid_2d(16, 64, nel=(520, 520))
+    rho = p.rho.reshape(520, 520)
+    assert set(np.unique(rho)) == {synth.problems.VOID, 1.0}
+    assert np.all(rho[:, 0:8] == 1.0) and np.all(rho[:, 512:520] == 1.0)    # first and last column
+    assert np.all(rho[512:520, :] == 1.0)                                     # top beam
+    assert np.all(rho[:, 8:16][100:110] == synth.problems.VOID)               # between two columns, between beams
+    assert len(p.fixed) == 2 * 521 and np.isclose(p.loads[0].sum(), -1.0)
