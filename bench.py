@@ -61,6 +61,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip the event-timed solve")
+    ap.add_argument("--no-side-legs", action="store_true",
+                    help="skip the multi-RHS and density-filter legs (profiled runs: only the headline solves)")
     ap.add_argument("--served", type=int, default=24, help="requests in the served-stream leg (0: skip)")
     ap.add_argument("--served-designs", type=int, default=20)
     ap.add_argument("--served-smoother", default="chebyshev", choices=sorted(SMOOTHERS))
@@ -467,9 +469,11 @@ def main():
             line["roofline"] = ents[dom]
             line["roofline_other_kernels"] = [ents[c] for c in ents if c != dom]
     u_mixed = res.u.clone()
-    line["multi_rhs"] = multi_rhs_leg(H, p)
+    if not args.no_side_legs:
+        line["multi_rhs"] = multi_rhs_leg(H, p)
     H.close()
-    line["density_filter"] = filter_leg(p.nel)
+    if not args.no_side_legs:
+        line["density_filter"] = filter_leg(p.nel)
     if not args.no_fp64:
         H64, t64s = build(64, 1)
         k64 = max(1, args.steps // 2)
