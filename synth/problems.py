@@ -337,6 +337,40 @@ def grid_2d(sx: int = 16, sy: int = 256, nel=(520, 520), width: int = 8) -> Prob
     return Problem(f"grid2d_{sx}_{sy}", 2, tuple(nel), rho.ravel(), fixed, F)
 
 
+def column_2d(nel=(256, 1024), seed: int = 6, flange: float = 0.125, band: float = 0.02,
+              uniform: bool = False) -> Problem:
+    """2D column for the stability problem (Sec. 2, Sec. 4 column example):
+    all dofs of the bottom nodes fixed, a uniform downward (compressive) load
+    of total 1 on the top edge (consistent nodal forces, end nodes half).
+    Density: two solid flanges (`flange` of the width each) and solid bottom
+    and top bands (`band` of the height) joined by a web of smoothed noise
+    thresholded to {1e-3, 1}; web pieces not connected to the bottom are void.
+    `uniform` gives density 1 everywhere (a prismatic column)."""
+    nx, ny = nel
+    if uniform:
+        rho = np.ones((ny, nx))
+    else:
+        solid = smoothed_field(_zyx(nel), seed) >= 0.0
+        f = max(1, int(round(flange * nx)))
+        b = max(1, int(round(band * ny)))
+        solid[:, :f] = True
+        solid[:, nx - f:] = True
+        solid[:b, :] = True
+        solid[ny - b:, :] = True
+        lab, _ = label(solid)
+        anchored = np.unique(lab[0, :])
+        solid = np.isin(lab, anchored[anchored > 0])
+        rho = np.where(solid, 1.0, VOID)
+    bottom = node_id(nel, np.arange(nx + 1), 0)
+    fixed = _uniq(_dofs(nel, 2, bottom, range(2)))
+    w = np.full(nx + 1, 1.0 / nx)
+    w[[0, -1]] *= 0.5
+    F = np.zeros((1, 2 * (nx + 1) * (ny + 1)))
+    F[0, 2 * node_id(nel, np.arange(nx + 1), ny) + 1] = -w
+    return Problem("column2d", 2, tuple(nel), rho.ravel(), fixed, F,
+                   opts=dict(n_levels=5, omega=0.5, nu_pre=1, nu_post=1, rtol=1e-8))
+
+
 CONFIGS = {
     "mbb_uniform": lambda: mbb_2d(True),
     "mbb_random": lambda: mbb_2d(False),
@@ -344,6 +378,7 @@ CONFIGS = {
     "cantilever3d": cantilever_3d,
     "bridge3d": bridge_3d,
     "grid2d": grid_2d,
+    "column2d": column_2d,
 }
 
 
