@@ -163,6 +163,68 @@ tm_status tm_compliance_sensitivity(tm_hierarchy* h, int32_t n_rhs, const double
 tm_status tm_density_filter(const tm_mesh* mesh, double radius, int32_t transpose, const double* in_dev,
                             double* out_dev, void* stream);
 
+/* ---- stability eigenproblem (Sec. 2 stability maximisation; Sec. 3 eigensolvers,
+ * Algorithm 2 generalized Davidson; Sec. 4 column example) ------------------ */
+
+/* Stress-stiffness matrix of the displacements u_dev (n_dof FP64, device, e.g. a
+ * tm_solve result) for the densities of the current design:
+ *   K_sigma = -sum_e E_sigma(rho_e) L_e^T (g_e (x) I_dim) L_e,
+ *   E_sigma(rho) = E0 rho^p for rho >= rho_min (0.1 in Sec. 2), 0 below,
+ *   g_e[a][b] = sum over the 2^dim Gauss points of w |J| grad N_a^T sigma grad N_b,
+ * sigma the unit-modulus stress of u_e (plane stress in 2D).  The paper does not
+ * write K_sigma out: this is the textbook geometric stiffness, with the sign
+ * that gives compressive states positive eigenvalues of K_sigma Phi = lambda K Phi
+ * (lambda = 1 / critical load factor).  Supported rows and columns are removed
+ * (K_sigma~ = M K_sigma M).  The hierarchy keeps the matrix (a scalar nodal
+ * stencil, 3^dim FP64 per node) until the next call; tm_update_density makes it
+ * stale.  Enqueued on `stream`, which must be ordered after the work that wrote
+ * u_dev; the call does not wait.  TM_ERR_ARG for a NULL handle or buffer or
+ * rho_min outside [0, 1]; TM_ERR_OOM. */
+tm_status tm_stress_stiffness(tm_hierarchy* h, const double* u_dev, double rho_min, void* stream);
+
+/* y = K_sigma~ x (device FP64 vectors of n_dof, not overlapping), with the matrix of
+ * the last tm_stress_stiffness.  Waits for completion.  TM_ERR_STATE if there is
+ * no current stress-stiffness matrix. */
+tm_status tm_apply_stress_stiffness(tm_hierarchy* h, const double* x_dev, double* y_dev, void* stream);
+
+typedef struct tm_eig_options {
+    int32_t nev;        /* eigenpairs wanted, the largest eigenvalues (6 in Sec. 4)          */
+    int32_t j_min;      /* search-space size kept at a restart (10 in Sec. 3); nev < j_min   */
+    int32_t j_max;      /* search-space size that triggers a restart (25); j_min < j_max <= 32 */
+    int32_t max_iters;  /* search-space expansions (preconditioner calls) at most            */
+    double tol;         /* a pair converges when ||K_s q - theta K q|| / (|theta| ||K q||)
+                           falls below tol (1e-6, Sec. 4) ...                                */
+    double stag_tol;    /* ... or when theta changes by less than stag_tol |theta| between
+                           consecutive iterations (1e-13, Sec. 4)                           */
+    int32_t precond_fp; /* 32: FP32 V-cycle as the preconditioner M, 64: FP64 V-cycle       */
+} tm_eig_options;
+
+/* Fill `o` with nev 6, j_min 10, j_max 25, max_iters 1000, tol 1e-6, stag_tol
+ * 1e-13, precond_fp 32. */
+void tm_default_eig_options(tm_eig_options* o);
+
+/* The nev largest eigenvalues of K_sigma~ Phi = lambda K~ Phi by generalized
+ * Davidson (Algorithm 2) with one V-cycle of the hierarchy as the preconditioner,
+ * using the matrix of the last tm_stress_stiffness.
+ *   v0_dev   n_init start vectors (1 <= n_init <= j_max), n_dof FP64 each, one after
+ *            the other (device); entries on supported dofs are ignored.  Previous
+ *            eigenvectors make good start vectors (Sec. 4).
+ *   lambda   host, nev values, descending.
+ *   phi_dev  device, nev eigenvectors of n_dof one after the other, normalised
+ *            Phi^T K~ Phi = I (may be NULL).
+ *   iters    host, expansions done (may be NULL); n_conv: converged pairs (may be NULL).
+ * Method as implemented: Gram-Schmidt in the K~ inner product (classical, repeated
+ * once when the norm drops below 1/sqrt(2) of its value), the Ritz pairs of
+ * V^T K_sigma~ V, pairs converge in descending order and stay in the space, a
+ * restart keeps the j_min leading Ritz vectors.  Waits for completion.  The
+ * hierarchy keeps the search space (n_dof x j_max FP64) for later calls.
+ * Returns TM_NOT_CONVERGED if fewer than nev pairs converged within max_iters;
+ * TM_ERR_STATE without a current stress-stiffness matrix; TM_ERR_ARG for bad
+ * options, start vectors that are dependent in the K~ inner product, or NULL
+ * pointers; TM_ERR_BREAKDOWN if a correction lies in the search space. */
+tm_status tm_eigs(tm_hierarchy* h, const tm_eig_options* o, int32_t n_init, const double* v0_dev,
+                  double* lambda, double* phi_dev, int32_t* iters, int32_t* n_conv, void* stream);
+
 /* Iteration-level control for a scheduler (continuous batching).
  * begin:   copies f, sets up the start vector on `stream` and returns a state
  *          bound to (h, stream, u_dev); u_dev must stay valid until end.

@@ -46,6 +46,11 @@ class tm_options(C.Structure):
                 ("adapt_iters", C.c_int32)]
 
 
+class tm_eig_options(C.Structure):
+    _fields_ = [("nev", C.c_int32), ("j_min", C.c_int32), ("j_max", C.c_int32), ("max_iters", C.c_int32),
+                ("tol", C.c_double), ("stag_tol", C.c_double), ("precond_fp", C.c_int32)]
+
+
 class TmError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"{msg} (status {status})")
@@ -81,6 +86,10 @@ def _load():
         "tm_hierarchy_bytes": (I32, [P, C.POINTER(SZ)]),
         "tm_compliance_sensitivity": (I32, [P, I32, P, P, P]),
         "tm_density_filter": (I32, [C.POINTER(tm_mesh), D, I32, P, P, P]),
+        "tm_stress_stiffness": (I32, [P, P, D, P]),
+        "tm_apply_stress_stiffness": (I32, [P, P, P, P]),
+        "tm_default_eig_options": (None, [C.POINTER(tm_eig_options)]),
+        "tm_eigs": (I32, [P, C.POINTER(tm_eig_options), I32, P, P, P, C.POINTER(I32), C.POINTER(I32), P]),
         "tm_kernel_timing": (I32, [P, I32, I32]),
         "tm_kernel_timing_read": (I32, [P, I32, C.POINTER(I64), C.POINTER(D)]),
         "tm_destroy": (None, [P]),
@@ -109,6 +118,16 @@ def check(status: int, what: str = "") -> int:
 def default_options(**kw) -> tm_options:
     o = tm_options()
     LIB.tm_default_options(C.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+def default_eig_options(**kw) -> tm_eig_options:
+    o = tm_eig_options()
+    LIB.tm_default_eig_options(C.byref(o))
     for k, v in kw.items():
         if not hasattr(o, k):
             raise KeyError(k)

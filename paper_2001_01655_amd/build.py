@@ -27,6 +27,7 @@ SOURCES = [
     "kernels_bsr.hip",
     "kernels_sa.hip",
     "kernels_filter.hip",
+    "kernels_eigen.hip",
     "host.cpp",
     "host_sa.cpp",
 ]

@@ -963,6 +963,273 @@ static void geo_prolongator(const tm_hierarchy* h, int l, std::vector<int64_t>& 
 
 }  // namespace tmi
 
+// ============================================================================ stability eigenproblem
+namespace tmi {
+
+void free_eig_work(tm_hierarchy* h) {
+    if (!h->eig) return;
+    (void)hipDeviceSynchronize();
+    if (h->eig->host) (void)hipHostFree(h->eig->host);
+    free_list(h->eig->allocs);
+    delete h->eig;
+    h->eig = nullptr;
+}
+
+// pinned host staging: [0, 33) reduced sums (device to host), then 32
+// coefficients and a 32 x 32 block (host to device)
+constexpr int EIG_PIN_COEF = EIG_MAX_COLS + 1;
+constexpr int EIG_PIN_Y = EIG_PIN_COEF + EIG_MAX_COLS;
+constexpr int EIG_PIN_N = EIG_PIN_Y + EIG_MAX_COLS * EIG_MAX_COLS;
+
+static EigWork* eig_work(tm_hierarchy* h, int jmax, int fp) {
+    if (h->eig && h->eig->jmax >= jmax && h->eig->fp == fp && h->eig->n == h->n_dof) return h->eig;
+    free_eig_work(h);
+    auto* w = new EigWork();
+    h->eig = w;
+    try {
+        const size_t n = (size_t)h->n_dof;
+        w->n = h->n_dof;
+        w->jmax = jmax;
+        w->fp = fp;
+        auto A = [&](size_t k) { return dalloc<double>(w->allocs, w->bytes, k); };
+        w->V = A(n * (size_t)jmax);
+        w->q = A(n);
+        w->Aq = A(n);
+        w->Bq = A(n);
+        w->r = A(n);
+        w->z = A(n);
+        w->w = A(n);
+        w->part = A((size_t)EIG_BLOCKS * (EIG_MAX_COLS + 1));
+        w->red = A(EIG_MAX_COLS + 1);
+        w->coef = A(EIG_MAX_COLS);
+        w->Y = A(EIG_MAX_COLS * EIG_MAX_COLS);
+        if (fp == 64) {
+            alloc_vcyc<double>(h, w->vc, w->allocs, w->bytes);
+        } else {
+            w->r32 = dalloc<float>(w->allocs, w->bytes, n);
+            w->z32 = dalloc<float>(w->allocs, w->bytes, n);
+            alloc_vcyc<float>(h, w->vc, w->allocs, w->bytes);
+        }
+        TM_HIP(hipHostMalloc((void**)&w->host, EIG_PIN_N * sizeof(double), hipHostMallocDefault));
+    } catch (...) {
+        free_eig_work(h);
+        throw;
+    }
+    return w;
+}
+
+// Eigenvalues (descending) and unit eigenvectors (columns of Y, n x n
+// column-major) of a small symmetric matrix H (leading dimension ldh) by the
+// cyclic Jacobi method in Rutishauser's form: each plane rotation zeroes one
+// off-diagonal entry exactly and updates the two diagonal entries by +-t a_pq;
+// after a few sweeps, entries that no longer change the diagonal in floating
+// point are set to zero; the sweeps end when the off-diagonal part is zero.
+static void sym_eig(int n, const std::vector<double>& H, int ldh, std::vector<double>& theta,
+                    std::vector<double>& Y) {
+    std::vector<double> A((size_t)n * n), Q((size_t)n * n, 0.0);
+    auto a = [&](int i, int j) -> double& { return A[i + (size_t)n * j]; };
+    for (int j = 0; j < n; ++j)
+        for (int i = 0; i < n; ++i) a(i, j) = 0.5 * (H[i + (size_t)ldh * j] + H[j + (size_t)ldh * i]);
+    for (int i = 0; i < n; ++i) Q[i + (size_t)n * i] = 1.0;
+    for (int sweep = 0; sweep < 100; ++sweep) {
+        double off = 0.0;
+        for (int p = 0; p < n; ++p)
+            for (int q = p + 1; q < n; ++q) off += std::fabs(a(p, q));
+        if (off == 0.0) break;
+        for (int p = 0; p < n - 1; ++p)
+            for (int q = p + 1; q < n; ++q) {
+                const double apq = a(p, q);
+                const double g = 100.0 * std::fabs(apq);
+                if (sweep > 3 && std::fabs(a(p, p)) + g == std::fabs(a(p, p)) &&
+                    std::fabs(a(q, q)) + g == std::fabs(a(q, q))) {
+                    a(p, q) = a(q, p) = 0.0;
+                    continue;
+                }
+                if (apq == 0.0) continue;
+                const double hd = a(q, q) - a(p, p);
+                double t;
+                if (std::fabs(hd) + g == std::fabs(hd)) {
+                    t = apq / hd;
+                } else {
+                    const double th = 0.5 * hd / apq;
+                    t = 1.0 / (std::fabs(th) + std::sqrt(1.0 + th * th));
+                    if (th < 0.0) t = -t;
+                }
+                const double c = 1.0 / std::sqrt(1.0 + t * t), sn = t * c;
+                a(p, p) -= t * apq;
+                a(q, q) += t * apq;
+                a(p, q) = a(q, p) = 0.0;
+                for (int r = 0; r < n; ++r) {
+                    if (r == p || r == q) continue;
+                    const double arp = a(r, p), arq = a(r, q);
+                    a(r, p) = a(p, r) = c * arp - sn * arq;
+                    a(r, q) = a(q, r) = sn * arp + c * arq;
+                }
+                for (int r = 0; r < n; ++r) {
+                    const double qrp = Q[r + (size_t)n * p], qrq = Q[r + (size_t)n * q];
+                    Q[r + (size_t)n * p] = c * qrp - sn * qrq;
+                    Q[r + (size_t)n * q] = sn * qrp + c * qrq;
+                }
+            }
+    }
+    std::vector<int> ord(n);
+    for (int i = 0; i < n; ++i) ord[i] = i;
+    std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) {
+        return A[x + (size_t)n * x] > A[y + (size_t)n * y];
+    });
+    theta.assign(n, 0.0);
+    Y.assign((size_t)n * n, 0.0);
+    for (int k = 0; k < n; ++k) {
+        theta[k] = A[ord[k] + (size_t)n * ord[k]];
+        for (int i = 0; i < n; ++i) Y[i + (size_t)n * k] = Q[i + (size_t)n * ord[k]];
+    }
+}
+
+// Generalized Davidson for K_sigma~ x = theta K~ x (Algorithm 2).  The search
+// space V lives on the device (column-major, ld = n_dof) and is K~-orthonormal;
+// the projected matrix H = V^T K_sigma~ V (at most 32 x 32) and every decision
+// live on the host, which reads a few reduced sums per step.
+struct Davidson {
+    tm_hierarchy* h;
+    EigWork* w;
+    hipStream_t s;
+    int64_t n;
+    int fp, jmax, j = 0;
+    std::vector<double> H;                       // jmax x jmax, column-major
+
+    double* col(int c) const { return w->V + (int64_t)c * n; }
+    void applyA(const double* x, double* y) { launch_gsig_apply(h, h->gsig, x, y, s); }
+    void applyB(const double* x, double* y) {
+        launch_fine_op<double>(h, OP_APPLY, true, x, nullptr, y, 0.0, nullptr, nullptr, s);
+    }
+    // c[i] = V[:, i]^T v for i < nc, and z^T v when z is given
+    void dots(int nc, const double* v, const double* z, double* c, double* zz) {
+        launch_vtw(w->V, n, nc, v, z, n, w->part, w->red, s);
+        TM_HIP(hipMemcpyAsync(w->host, w->red, (EIG_MAX_COLS + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+        TM_HIP(hipStreamSynchronize(s));
+        for (int i = 0; i < nc; ++i) c[i] = w->host[i];
+        if (zz) *zz = w->host[EIG_MAX_COLS];
+    }
+    void upload(double* dst, const double* src, int cnt, int pin_off) {
+        std::memcpy(w->host + pin_off, src, cnt * sizeof(double));
+        TM_HIP(hipMemcpyAsync(dst, w->host + pin_off, cnt * sizeof(double), hipMemcpyHostToDevice, s));
+    }
+    void precond(const double* r, double* z) {
+        if (fp == 64) {
+            vcycle<double>(h, w->vc, r, z, nullptr, s);
+        } else {
+            launch_cast(r, w->r32, n, s);
+            vcycle<float>(h, w->vc, w->r32, w->z32, nullptr, s);
+            launch_cast_back(w->z32, z, n, s);
+        }
+    }
+    // K~-orthonormalise z against V[:, :j] (classical Gram-Schmidt, repeated
+    // once when the norm drops below 1/sqrt(2); the norm after a projection is
+    // ||z||^2 - ||c||^2), store it as column j and extend H.  z is overwritten.
+    // false: the vector is (numerically) in the span of V.
+    bool append(double* z) {
+        constexpr double ETA2 = 0.5, BREAK2 = 1e-20;
+        double c[EIG_MAX_COLS + 1], coef[EIG_MAX_COLS], zz0 = 0.0, zz = 0.0, beta2 = 0.0;
+        applyB(z, w->w);
+        dots(j, w->w, z, c, &zz0);
+        if (!(zz0 > 0.0)) return false;
+        zz = zz0;
+        for (int pass = 0; pass < 2; ++pass) {
+            if (pass == 1) {
+                applyB(z, w->w);
+                dots(j, w->w, z, c, &zz);
+            }
+            double cc = 0.0;
+            for (int i = 0; i < j; ++i) cc += c[i] * c[i];
+            beta2 = zz - cc;
+            if (beta2 > ETA2 * zz || pass == 1) {
+                if (!(beta2 > BREAK2 * zz0)) return false;
+                const double inv = 1.0 / std::sqrt(beta2);
+                for (int i = 0; i < j; ++i) coef[i] = -c[i] * inv;
+                if (j > 0) upload(w->coef, coef, j, EIG_PIN_COEF);
+                launch_vupdate(w->V, n, j, w->coef, inv, z, col(j), n, s);     // (z - V c) / beta
+                break;
+            }
+            for (int i = 0; i < j; ++i) coef[i] = -c[i];
+            upload(w->coef, coef, j, EIG_PIN_COEF);
+            launch_vupdate(w->V, n, j, w->coef, 1.0, z, z, n, s);               // z - V c
+        }
+        applyA(col(j), w->Aq);
+        double hc[EIG_MAX_COLS + 1];
+        dots(j + 1, w->Aq, nullptr, hc, nullptr);
+        for (int i = 0; i <= j; ++i) {
+            H[i + (size_t)jmax * j] = hc[i];
+            H[j + (size_t)jmax * i] = hc[i];
+        }
+        ++j;
+        return true;
+    }
+};
+
+static tm_status run_davidson(tm_hierarchy* h, const tm_eig_options& o, int32_t n_init, const double* v0,
+                              double* lambda, double* phi, int32_t* iters_out, int32_t* nconv_out, hipStream_t s) {
+    Davidson gd{h, eig_work(h, o.j_max, o.precond_fp), s, h->n_dof, o.precond_fp, o.j_max};
+    EigWork* w = gd.w;
+    const int64_t n = gd.n;
+    gd.H.assign((size_t)o.j_max * o.j_max, 0.0);
+    for (int i = 0; i < n_init; ++i) {
+        launch_mask_copy<double>(h, v0 + (int64_t)i * n, w->z, s);
+        if (!gd.append(w->z)) fail(TM_ERR_ARG, "start vectors are dependent in the K inner product");
+    }
+    std::vector<double> theta, Y;
+    int k = 0, it = 0;
+    bool have_prev = false;
+    double prev = 0.0;
+    for (;;) {
+        sym_eig(gd.j, gd.H, o.j_max, theta, Y);
+        while (k < o.nev) {
+            // Ritz vector q = V y_k, residual r = K_s q - theta K q
+            gd.upload(w->coef, Y.data() + (size_t)gd.j * k, gd.j, EIG_PIN_COEF);
+            launch_vupdate(w->V, n, gd.j, w->coef, 0.0, nullptr, w->q, n, s);
+            gd.applyA(w->q, w->Aq);
+            gd.applyB(w->q, w->Bq);
+            launch_eig_resid(w->Aq, w->Bq, theta[k], w->r, n, w->part, w->red, s);
+            TM_HIP(hipMemcpyAsync(w->host, w->red, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+            TM_HIP(hipStreamSynchronize(s));
+            const double rn = std::sqrt(w->host[0]), den = std::fabs(theta[k]) * std::sqrt(w->host[1]);
+            const double rel = den > 0.0 ? rn / den : (rn == 0.0 ? 0.0 : HUGE_VAL);
+            const bool stag = have_prev && std::fabs(theta[k] - prev) < o.stag_tol * std::fabs(theta[k]);
+            if (rel < o.tol || stag) {
+                ++k;
+                have_prev = false;
+                continue;
+            }
+            break;
+        }
+        if (k == o.nev || it >= o.max_iters) break;
+        prev = theta[k];
+        have_prev = true;
+        if (gd.j == o.j_max) {
+            // restart: keep the j_min leading Ritz vectors
+            gd.upload(w->Y, Y.data(), gd.j * o.j_min, EIG_PIN_Y);
+            launch_vrotate(w->V, n, gd.j, w->Y, o.j_min, w->V, n, n, s);
+            std::fill(gd.H.begin(), gd.H.end(), 0.0);
+            for (int i = 0; i < o.j_min; ++i) gd.H[i + (size_t)o.j_max * i] = theta[i];
+            gd.j = o.j_min;
+        }
+        gd.precond(w->r, w->z);
+        ++it;
+        if (!gd.append(w->z)) fail(TM_ERR_BREAKDOWN, "search space breakdown: the correction lies in the search space");
+    }
+    sym_eig(gd.j, gd.H, o.j_max, theta, Y);
+    for (int i = 0; i < o.nev; ++i) lambda[i] = theta[i];
+    if (phi) {
+        gd.upload(w->Y, Y.data(), gd.j * o.nev, EIG_PIN_Y);
+        launch_vrotate(w->V, n, gd.j, w->Y, o.nev, phi, n, n, s);
+    }
+    TM_HIP(hipStreamSynchronize(s));
+    if (iters_out) *iters_out = it;
+    if (nconv_out) *nconv_out = k;
+    return k == o.nev ? TM_OK : TM_NOT_CONVERGED;
+}
+
+}  // namespace tmi
+
 // ============================================================================ C ABI
 extern "C" {
 
@@ -1039,6 +1306,7 @@ tm_status tm_plan_bytes(const tm_mesh* mesh, const tm_options* opts, int32_t n_r
 static void destroy_impl(tm_hierarchy* h) {
     if (!h) return;
     tmi::delete_cached_state(h);
+    tmi::free_eig_work(h);
     for (int c = 0; c < 3; ++c)
         for (auto& pr : h->tev[c]) {
             (void)hipEventDestroy(pr.first);
@@ -1151,6 +1419,10 @@ tm_status tm_update_density(tm_hierarchy* h, const double* rho_dev, void* stream
                 h->sa = true;
             }
         }
+        // the stress stiffness belongs to the old design; the eigensolver's
+        // V-cycle vectors follow the level list, which aggregation rebuilds
+        h->gsig_valid = false;
+        if (h->sa) free_eig_work(h);
         // without aggregation levels (whose sizes the host must read) the update
         // never waits for the device
         numeric_setup(h, rho_dev, S(stream), h->sa);
@@ -1515,6 +1787,67 @@ tm_status tm_kernel_timing_read(tm_hierarchy* h, int32_t kernel_class, int64_t* 
         if (total_ms) *total_ms = tot;
         v.clear();
     });
+}
+
+tm_status tm_stress_stiffness(tm_hierarchy* h, const double* u_dev, double rho_min, void* stream) {
+    return guarded([&] {
+        if (!h) fail(TM_ERR_ARG, "hierarchy is NULL");
+        if (!u_dev) fail(TM_ERR_ARG, "u must be a device buffer");
+        if (!(rho_min >= 0.0 && rho_min <= 1.0)) fail(TM_ERR_ARG, "rho_min must be in [0, 1]");
+        const size_t nst = h->dim == 3 ? 27 : 9;
+        if (!h->gsig) h->gsig = halloc<double>(h, nst * (size_t)h->n_nodes);
+        h->gsig_valid = false;
+        launch_gsig_assemble(h, u_dev, rho_min, h->gsig, S(stream));
+        TM_HIP(hipGetLastError());
+        h->gsig_valid = true;
+    });
+}
+
+tm_status tm_apply_stress_stiffness(tm_hierarchy* h, const double* x_dev, double* y_dev, void* stream) {
+    return guarded([&] {
+        if (!h) fail(TM_ERR_ARG, "hierarchy is NULL");
+        if (!x_dev || !y_dev) fail(TM_ERR_ARG, "x and y must be device buffers");
+        if (x_dev == y_dev) fail(TM_ERR_ARG, "x and y must not overlap");
+        if (!h->gsig_valid) fail(TM_ERR_STATE, "no current stress-stiffness matrix (call tm_stress_stiffness)");
+        launch_gsig_apply(h, h->gsig, x_dev, y_dev, S(stream));
+        TM_HIP(hipStreamSynchronize(S(stream)));
+    });
+}
+
+void tm_default_eig_options(tm_eig_options* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->nev = 6;
+    o->j_min = 10;
+    o->j_max = 25;
+    o->max_iters = 1000;
+    o->tol = 1e-6;
+    o->stag_tol = 1e-13;
+    o->precond_fp = 32;
+}
+
+tm_status tm_eigs(tm_hierarchy* h, const tm_eig_options* o, int32_t n_init, const double* v0_dev,
+                  double* lambda, double* phi_dev, int32_t* iters, int32_t* n_conv, void* stream) {
+    tm_status st = TM_OK;
+    const tm_status g = guarded([&] {
+        if (!h) fail(TM_ERR_ARG, "hierarchy is NULL");
+        if (!o) fail(TM_ERR_ARG, "options are NULL");
+        if (!(o->nev >= 1 && o->nev < o->j_min && o->j_min < o->j_max && o->j_max <= EIG_MAX_COLS))
+            fail(TM_ERR_ARG, "need 1 <= nev < j_min < j_max <= 32");
+        if (o->max_iters < 0) fail(TM_ERR_ARG, "max_iters must be >= 0");
+        if (!(o->tol >= 0.0) || !(o->stag_tol >= 0.0)) fail(TM_ERR_ARG, "tolerances must be >= 0");
+        if (o->precond_fp != 32 && o->precond_fp != 64) fail(TM_ERR_ARG, "precond_fp must be 32 or 64");
+        if (n_init < 1 || n_init > o->j_max) fail(TM_ERR_ARG, "n_init must be in 1..j_max");
+        if (!v0_dev || !lambda) fail(TM_ERR_ARG, "start vectors and lambda are required");
+        if (!h->gsig_valid) fail(TM_ERR_STATE, "no current stress-stiffness matrix (call tm_stress_stiffness)");
+        hipStream_t s = S(stream);
+        if (h->flags_pending) {
+            h->flags_pending = false;
+            read_flags(h, s, "last update");
+        }
+        st = run_davidson(h, *o, n_init, v0_dev, lambda, phi_dev, iters, n_conv, s);
+    });
+    return g != TM_OK ? g : st;
 }
 
 }  // extern "C"

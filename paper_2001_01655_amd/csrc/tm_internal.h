@@ -196,6 +196,31 @@ struct Vcyc {                     // V-cycle work vectors of one precision, per 
 
 struct Lane;                      // one right-hand side of a solve state
 
+// Generalized Davidson (stability eigenproblem): the search space has at most
+// EIG_MAX_COLS columns; reductions over rows use at most EIG_BLOCKS workgroups.
+constexpr int EIG_MAX_COLS = 32;
+constexpr int EIG_BLOCKS = 1024;
+inline int eig_blocks(int64_t n) {
+    const int64_t b = ceil_div(n > 0 ? n : 1, (int64_t)WG * 4);
+    return (int)(b < EIG_BLOCKS ? b : EIG_BLOCKS);
+}
+struct EigWork {                  // device workspace of tm_eigs, kept by the hierarchy
+    int64_t n = 0;
+    int jmax = 0, fp = 0;
+    double *V = nullptr;          // search space, n x jmax, column-major
+    double *q = nullptr, *Aq = nullptr, *Bq = nullptr, *r = nullptr, *z = nullptr, *w = nullptr;
+    double *part = nullptr;       // EIG_BLOCKS x (EIG_MAX_COLS + 1) partial sums
+    double *red = nullptr;        // EIG_MAX_COLS + 1 reduced sums
+    double *coef = nullptr;       // EIG_MAX_COLS coefficients
+    double *Y = nullptr;          // EIG_MAX_COLS^2 Ritz coefficients
+    double *rb = nullptr;         // masked V-cycle input (FP64)
+    float *r32 = nullptr, *z32 = nullptr;
+    double *host = nullptr;       // pinned mirror of red
+    Vcyc vc;                      // V-cycle work vectors in the preconditioner's precision
+    std::vector<void*> allocs;
+    size_t bytes = 0;
+};
+
 }  // namespace tmi
 
 struct tm_hierarchy {
@@ -235,6 +260,12 @@ struct tm_hierarchy {
     // kernel timing hooks
     bool timing[3] = {false, false, false};
     std::vector<std::pair<hipEvent_t, hipEvent_t>> tev[3];
+    // stability eigenproblem: stress-stiffness stencil [3^dim][n_nodes] of the
+    // last tm_stress_stiffness (stale after a density update) and the
+    // eigensolver's workspace
+    double* gsig = nullptr;
+    bool gsig_valid = false;
+    tmi::EigWork* eig = nullptr;
     // default solve state (tm_solve) and ended states kept for reuse
     tm_solve_state* cached = nullptr;
     std::vector<tm_solve_state*> pool;
@@ -367,5 +398,16 @@ void launch_cast(const double* a, float* b, int64_t n, hipStream_t s);
 void launch_cast_back(const float* a, double* b, int64_t n, hipStream_t s);
 void launch_fill(void* p, int64_t n_bytes, hipStream_t s);
 int krylov_blocks(int64_t n);
+// stability eigenproblem (kernels_eigen.hip)
+void launch_gsig_assemble(const tm_hierarchy* h, const double* u, double rho_min, double* G, hipStream_t s);
+void launch_gsig_apply(const tm_hierarchy* h, const double* G, const double* x, double* y, hipStream_t s);
+void launch_vtw(const double* V, int64_t ld, int nc, const double* w, const double* z, int64_t n, double* part,
+                double* out, hipStream_t s);
+void launch_vupdate(const double* V, int64_t ld, int nc, const double* coef, double a, const double* in, double* out,
+                    int64_t n, hipStream_t s);
+void launch_vrotate(double* V, int64_t ld, int nc, const double* Y, int m, double* dst, int64_t ldd, int64_t n,
+                    hipStream_t s);
+void launch_eig_resid(const double* Aq, const double* Bq, double theta, double* r, int64_t n, double* part,
+                      double* out, hipStream_t s);
 
 }  // namespace tmi

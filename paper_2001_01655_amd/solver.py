@@ -183,6 +183,44 @@ class Hierarchy:
               "tm_compliance_sensitivity")
         return dc
 
+    def stress_stiffness(self, u, rho_min: float = 0.1, stream=None):
+        """tm_stress_stiffness: build K_sigma~ of the displacements u (n_dof)."""
+        u_d = _dev(u)
+        if u_d.numel() != self.n_dof:
+            raise ValueError("u must hold one solution vector")
+        check(LIB.tm_stress_stiffness(self.handle, C.c_void_p(u_d.data_ptr()), float(rho_min), _stream_ptr(stream)),
+              "tm_stress_stiffness")
+
+    def apply_stress_stiffness(self, x, stream=None) -> torch.Tensor:
+        """y = K_sigma~ x with the matrix of the last stress_stiffness call."""
+        x_d = _dev(x)
+        if x_d.numel() != self.n_dof:
+            raise ValueError("x must hold n_dof values")
+        y = torch.empty_like(x_d)
+        check(LIB.tm_apply_stress_stiffness(self.handle, C.c_void_p(x_d.data_ptr()), C.c_void_p(y.data_ptr()),
+                                            _stream_ptr(stream)), "tm_apply_stress_stiffness")
+        return y
+
+    def eigs(self, v0, stream=None, want_vectors: bool = True, **opts):
+        """tm_eigs: the largest eigenvalues of K_sigma~ Phi = lambda K~ Phi by
+        generalized Davidson.  v0: (n_init, n_dof) start vectors.  Options as in
+        tm_eig_options (nev, j_min, j_max, max_iters, tol, stag_tol, precond_fp).
+        Returns (lambda (numpy, descending), Phi (nev, n_dof) or None, iters,
+        n_conv, status)."""
+        o = L.default_eig_options(**opts)
+        v_d = _dev(v0)
+        n_init = v_d.numel() // self.n_dof
+        if n_init * self.n_dof != v_d.numel() or n_init < 1:
+            raise ValueError("v0 must hold whole vectors")
+        lam = np.zeros(max(1, o.nev))
+        phi = torch.empty((o.nev, self.n_dof), dtype=torch.float64, device=v_d.device) if want_vectors else None
+        it, nc = C.c_int32(), C.c_int32()
+        st = check(LIB.tm_eigs(self.handle, C.byref(o), n_init, C.c_void_p(v_d.data_ptr()),
+                               lam.ctypes.data_as(C.c_void_p),
+                               C.c_void_p(phi.data_ptr()) if phi is not None else None,
+                               C.byref(it), C.byref(nc), _stream_ptr(stream)), "tm_eigs")
+        return lam[:o.nev], phi, it.value, nc.value, st
+
     def device_bytes(self) -> int:
         b = C.c_size_t()
         check(LIB.tm_hierarchy_bytes(self._h, C.byref(b)), "tm_hierarchy_bytes")

@@ -74,6 +74,16 @@ def test_null_arguments():
     assert L.LIB.tm_solve(None, 1, None, 1e-8, 0, None, None, None, None, None) == L.TM_ERR_ARG
     assert L.LIB.tm_solve_end(None, None, None, None) == L.TM_ERR_STATE
     assert L.LIB.tm_num_levels(None) == 0
+    assert L.LIB.tm_stress_stiffness(None, None, 0.1, None) == L.TM_ERR_ARG
+    assert L.LIB.tm_apply_stress_stiffness(None, None, None, None) == L.TM_ERR_ARG
+    o = L.default_eig_options()
+    assert L.LIB.tm_eigs(None, C.byref(o), 1, None, None, None, None, None, None) == L.TM_ERR_ARG
+
+
+def test_eig_defaults_follow_the_paper():
+    o = L.default_eig_options()
+    assert (o.nev, o.j_min, o.j_max) == (6, 10, 25)
+    assert o.tol == 1e-6 and o.stag_tol == 1e-13 and o.precond_fp == 32
 
 
 def test_plan_bytes():
