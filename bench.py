@@ -61,6 +61,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip the event-timed solve")
+    ap.add_argument("--eigen-only", action="store_true",
+                    help="run only the stability eigenproblem leg and print its record (profiling)")
     ap.add_argument("--no-side-legs", action="store_true",
                     help="skip the multi-RHS and density-filter legs (profiled runs: only the headline solves)")
     ap.add_argument("--served", type=int, default=24, help="requests in the served-stream leg (0: skip)")
@@ -357,6 +359,59 @@ def grid_leg(pairs=((16, 16), (16, 256), (256, 16), (64, 64))):
     return out
 
 
+def eigen_leg(reps: int = 3):
+    """Stability eigenproblem (Sec. 2) on the 256x1024 column of Sec. 4
+    (prismatic start design, unit compressive load on the top edge, bottom
+    clamped; 526,850 dofs): displacements by the mixed FCG to rtol 1e-8, the
+    stress stiffness, then the six largest eigenvalues of
+    K_sigma Phi = lambda K Phi by generalized Davidson (Algorithm 2; j_min 10,
+    j_max 25, tol 1e-6, stagnation 1e-13) with one FP32 V-cycle (5 geometric
+    levels, 2210 coarsest dofs, block Jacobi 0.5, 1/1) as the preconditioner,
+    from 10 seeded start vectors.  Wall time of tm_eigs (host decisions and
+    transfers included), mean over reps after one warm call.  The web design
+    (voids) is run with a cap of 2000 expansions, for its convergence only."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2001_01655_amd import Hierarchy
+    out = {}
+    for name, uni in (("prismatic", True), ("web_design", False)):
+        p = synth.column_2d(uniform=uni)
+        H = Hierarchy(p.nel, p.rho, p.fixed, p=p.p, E0=p.E0, Emin=p.Emin, nu=p.nu, n_levels=5, omega=0.5,
+                      nu_pre=1, nu_post=1, vcycle_fp=32)
+        r = H.solve(torch.tensor(p.loads[0], device="cuda"), rtol=1e-8)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        H.stress_stiffness(r.u)
+        torch.cuda.synchronize()
+        t_ks = time.perf_counter() - t0
+        V0 = np.random.default_rng(3).standard_normal((10, p.n_dof))
+        V0[:, p.fixed] = 0.0
+        v0 = torch.tensor(V0, device="cuda")
+        cap = 1000 if uni else 2000
+        H.eigs(v0, nev=6, max_iters=cap, want_vectors=False)
+        n_rep = reps if uni else 1
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(n_rep):
+            lam, _, it, nc, st = H.eigs(v0, nev=6, max_iters=cap)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / n_rep
+        rec = {"iters": int(it), "n_conv": int(nc), "ms": round(dt * 1e3, 1),
+               "ms_per_iter": round(dt * 1e3 / max(it, 1), 3), "stress_stiffness_ms": round(t_ks * 1e3, 2),
+               "lambda": [float(f"{v:.8g}") for v in lam], "linear_iters": int(r.iters[0])}
+        if uni:
+            pcr = np.pi ** 2 * (p.nel[0] ** 3 / 12.0) / (4.0 * p.nel[1] ** 2)
+            rec["lambda1_x_euler_load"] = round(float(lam[0] * pcr), 4)
+        else:
+            rec["max_iters"] = cap
+        out[name] = rec
+        H.close()
+    out["workload"] = "2D column 256x1024 Q4 (526,850 dofs), 6 eigenpairs, GMG5 FP32 V-cycle preconditioner"
+    return out
+
+
 def filter_leg(nel, reps: int = 50):
     """tm_density_filter (radius 1.5) on the workload's element grid: mean time
     per launch from events around reps back-to-back calls of the C function on
@@ -404,6 +459,9 @@ def main():
     import synth
     from paper_2001_01655_amd import Hierarchy
 
+    if args.eigen_only:
+        print(json.dumps({"eigen": eigen_leg()}))
+        return
     wl = WORKLOADS[args.workload]
     p = synth.get(wl["cfg"])
     if args.calibrate_copy:
@@ -474,6 +532,7 @@ def main():
     H.close()
     if not args.no_side_legs:
         line["density_filter"] = filter_leg(p.nel)
+        line["eigen"] = eigen_leg()
     if not args.no_fp64:
         H64, t64s = build(64, 1)
         k64 = max(1, args.steps // 2)

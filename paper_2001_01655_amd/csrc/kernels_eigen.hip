@@ -202,74 +202,91 @@ void launch_gsig_apply(const tm_hierarchy* h, const double* G, const double* x, 
 // ------------------------------------------------------------ search-space products
 // V is column-major, n rows, leading dimension ld, at most EIG_MAX_COLS columns.
 // Rows are split over a grid of eig_blocks(n) workgroups; each workgroup
-// writes one partial per column and a single workgroup adds the partials in
-// block order, so every sum has a fixed order (deterministic).
+// writes one partial per column (column-major: part[c * EIG_BLOCKS + block])
+// and one workgroup per column adds that column's partials in block order, so
+// every sum has a fixed order (deterministic).  Every row's loads of V are
+// issued before any of them is used (the column count is a uniform runtime
+// value: a load and its use in one guarded block would wait load by load).
 
-// part[b][c] = sum over the rows of block b of V[c][row] w[row] (c < nc), and
-// column nc: z[row] w[row] when z is given.
+// part[c][b] = sum over the rows of block b of V[c][row] w[row] (c < nc), and
+// slot EIG_MAX_COLS: z[row] w[row] when z is given.  The columns (z counted as
+// column nc) are split into chunks of VTW_CHUNK over blockIdx.y, so a thread
+// holds few accumulators and the grid many waves; w is re-read per chunk
+// (from cache).
+constexpr int VTW_CHUNK = 8;
 __global__ __launch_bounds__(WG) void k_vtw(const double* __restrict__ V, int64_t ld, int nc,
                                             const double* __restrict__ w, const double* __restrict__ z, int64_t n,
                                             double* __restrict__ part) {
-    double acc[EIG_MAX_COLS + 1];
+    const int ntot = nc + (z ? 1 : 0);
+    const int c0 = (int)blockIdx.y * VTW_CHUNK;
+    double acc[VTW_CHUNK];
 #pragma unroll
-    for (int c = 0; c <= EIG_MAX_COLS; ++c) acc[c] = 0.0;
+    for (int k = 0; k < VTW_CHUNK; ++k) acc[k] = 0.0;
     const int64_t stride = (int64_t)gridDim.x * WG;
     for (int64_t row = (int64_t)blockIdx.x * WG + threadIdx.x; row < n; row += stride) {
+        double v[VTW_CHUNK];
+#pragma unroll
+        for (int k = 0; k < VTW_CHUNK; ++k) {
+            const int c = c0 + k;
+            if (c < nc) v[k] = V[c * ld + row];
+            else if (c == nc && z) v[k] = z[row];
+        }
         const double wv = w[row];
 #pragma unroll
-        for (int c = 0; c < EIG_MAX_COLS; ++c)
-            if (c < nc) acc[c] += V[c * ld + row] * wv;
-        if (z) acc[EIG_MAX_COLS] += z[row] * wv;
+        for (int k = 0; k < VTW_CHUNK; ++k)
+            if (c0 + k < ntot) acc[k] += v[k] * wv;
     }
-    __shared__ double red[WG / 64][EIG_MAX_COLS + 1];
+    __shared__ double red[WG / 64][VTW_CHUNK];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-    for (int c = 0; c <= EIG_MAX_COLS; ++c) {
-        if (c < nc || (c == EIG_MAX_COLS && z)) {
-            double v = acc[c];
+    for (int k = 0; k < VTW_CHUNK; ++k) {
+        if (c0 + k < ntot) {
+            double v = acc[k];
 #pragma unroll
             for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-            if (lane == 0) red[wave][c] = v;
+            if (lane == 0) red[wave][k] = v;
         }
     }
     __syncthreads();
-    const int c = threadIdx.x;
-    if (c < nc || (c == EIG_MAX_COLS && z)) {
+    const int k = threadIdx.x;
+    if (k < VTW_CHUNK && c0 + k < ntot) {
         double v = 0.0;
 #pragma unroll
-        for (int q = 0; q < WG / 64; ++q) v += red[q][c];
-        part[(int64_t)blockIdx.x * (EIG_MAX_COLS + 1) + c] = v;
+        for (int q = 0; q < WG / 64; ++q) v += red[q][k];
+        const int slot = c0 + k < nc ? c0 + k : EIG_MAX_COLS;
+        part[(int64_t)slot * EIG_BLOCKS + blockIdx.x] = v;
     }
 }
 
-// out[c] = sum_b part[b][c] for c < ncols (slot EIG_MAX_COLS included when asked)
-__global__ __launch_bounds__(WG) void k_eig_reduce(const double* __restrict__ part, int nparts, int nc, int with_z,
+// out[c] = sum_b part[c][b]; workgroup g reduces column g (g < nc), or column
+// EIG_MAX_COLS for g == nc when with_z
+__global__ __launch_bounds__(WG) void k_eig_reduce(const double* __restrict__ part, int nparts, int nc,
                                                    double* __restrict__ out) {
+    const int c = (int)blockIdx.x < nc ? (int)blockIdx.x : EIG_MAX_COLS;
+    const double* src = part + (int64_t)c * EIG_BLOCKS;
+    double v = 0.0;
+    for (int b = threadIdx.x; b < nparts; b += WG) v += src[b];
     __shared__ double red[WG / 64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int c = 0; c <= EIG_MAX_COLS; ++c) {
-        if (!(c < nc || (c == EIG_MAX_COLS && with_z))) continue;
-        double v = 0.0;
-        for (int b = threadIdx.x; b < nparts; b += WG) v += part[(int64_t)b * (EIG_MAX_COLS + 1) + c];
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-        if (lane == 0) red[wave] = v;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            double t = 0.0;
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
 #pragma unroll
-            for (int q = 0; q < WG / 64; ++q) t += red[q];
-            out[c] = t;
-        }
-        __syncthreads();
+        for (int q = 0; q < WG / 64; ++q) t += red[q];
+        out[c] = t;
     }
 }
 
 void launch_vtw(const double* V, int64_t ld, int nc, const double* w, const double* z, int64_t n, double* part,
                 double* out, hipStream_t s) {
-    const int nb = eig_blocks(n);
-    hipLaunchKernelGGL(k_vtw, dim3(nb), dim3(WG), 0, s, V, ld, nc, w, z, n, part);
-    hipLaunchKernelGGL(k_eig_reduce, dim3(1), dim3(WG), 0, s, part, nb, nc, z ? 1 : 0, out);
+    const int nb = eig_blocks(n), ncols = nc + (z ? 1 : 0);
+    if (ncols == 0) return;
+    hipLaunchKernelGGL(k_vtw, dim3(nb, (unsigned)ceil_div(ncols, VTW_CHUNK)), dim3(WG), 0, s, V, ld, nc, w, z, n,
+                       part);
+    hipLaunchKernelGGL(k_eig_reduce, dim3(ncols), dim3(WG), 0, s, part, nb, nc, out);
 }
 
 // out[row] = a in[row] + sum_c V[c][row] coef[c]   (in may be NULL, may equal out)
@@ -278,11 +295,15 @@ __global__ __launch_bounds__(WG) void k_vupdate(const double* __restrict__ V, in
                                                 double* out, int64_t n) {
     const int64_t row = (int64_t)blockIdx.x * WG + threadIdx.x;
     if (row >= n) return;
-    double v = in ? a * in[row] : 0.0;
+    double v[EIG_MAX_COLS];
 #pragma unroll
     for (int c = 0; c < EIG_MAX_COLS; ++c)
-        if (c < nc) v += V[c * ld + row] * coef[c];
-    out[row] = v;
+        if (c < nc) v[c] = V[c * ld + row];
+    double acc = in ? a * in[row] : 0.0;
+#pragma unroll
+    for (int c = 0; c < EIG_MAX_COLS; ++c)
+        if (c < nc) acc += v[c] * coef[c];
+    out[row] = acc;
 }
 
 void launch_vupdate(const double* V, int64_t ld, int nc, const double* coef, double a, const double* in, double* out,
@@ -343,7 +364,7 @@ __global__ __launch_bounds__(WG) void k_eig_resid(const double* __restrict__ Aq,
         double v = 0.0;
 #pragma unroll
         for (int q = 0; q < WG / 64; ++q) v += red[q][threadIdx.x];
-        part[(int64_t)blockIdx.x * (EIG_MAX_COLS + 1) + threadIdx.x] = v;
+        part[(int64_t)threadIdx.x * EIG_BLOCKS + blockIdx.x] = v;
     }
 }
 
@@ -351,7 +372,7 @@ void launch_eig_resid(const double* Aq, const double* Bq, double theta, double* 
                       double* out, hipStream_t s) {
     const int nb = eig_blocks(n);
     hipLaunchKernelGGL(k_eig_resid, dim3(nb), dim3(WG), 0, s, Aq, Bq, theta, r, n, part);
-    hipLaunchKernelGGL(k_eig_reduce, dim3(1), dim3(WG), 0, s, part, nb, 2, 0, out);
+    hipLaunchKernelGGL(k_eig_reduce, dim3(2), dim3(WG), 0, s, part, nb, 2, out);
 }
 
 }  // namespace tmi

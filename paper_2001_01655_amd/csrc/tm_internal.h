@@ -199,9 +199,9 @@ struct Lane;                      // one right-hand side of a solve state
 // Generalized Davidson (stability eigenproblem): the search space has at most
 // EIG_MAX_COLS columns; reductions over rows use at most EIG_BLOCKS workgroups.
 constexpr int EIG_MAX_COLS = 32;
-constexpr int EIG_BLOCKS = 1024;
+constexpr int EIG_BLOCKS = 2048;
 inline int eig_blocks(int64_t n) {
-    const int64_t b = ceil_div(n > 0 ? n : 1, (int64_t)WG * 4);
+    const int64_t b = ceil_div(n > 0 ? n : 1, (int64_t)WG * 2);
     return (int)(b < EIG_BLOCKS ? b : EIG_BLOCKS);
 }
 struct EigWork {                  // device workspace of tm_eigs, kept by the hierarchy
@@ -209,7 +209,7 @@ struct EigWork {                  // device workspace of tm_eigs, kept by the hi
     int jmax = 0, fp = 0;
     double *V = nullptr;          // search space, n x jmax, column-major
     double *q = nullptr, *Aq = nullptr, *Bq = nullptr, *r = nullptr, *z = nullptr, *w = nullptr;
-    double *part = nullptr;       // EIG_BLOCKS x (EIG_MAX_COLS + 1) partial sums
+    double *part = nullptr;       // (EIG_MAX_COLS + 1) x EIG_BLOCKS partial sums, column-major
     double *red = nullptr;        // EIG_MAX_COLS + 1 reduced sums
     double *coef = nullptr;       // EIG_MAX_COLS coefficients
     double *Y = nullptr;          // EIG_MAX_COLS^2 Ritz coefficients
