@@ -198,3 +198,54 @@ def test_column_full_size_sampled_rows_and_eigenpairs():
         print(f"  pair {i}: relative residual {rel:.2e}", flush=True)
         assert rel <= 1e-3
     H.close()
+
+
+@pytest.mark.parametrize("variant", ["chebyshev", "hybrid", "fp32_3d"])
+def test_eigs_other_preconditioners_vs_oracle(variant):
+    """Davidson with a Chebyshev-smoothed V-cycle (2/2), with the smoothed-
+    aggregation hybrid (2 geometric levels, aggregation below), and with an
+    FP32 V-cycle in 3D: the same eigenvalues as the oracle's Davidson with the
+    matching oracle preconditioner."""
+    from oracle import sa
+    print(f"eigs {variant}", flush=True)
+    if variant == "chebyshev":
+        p, levels = synth.column_2d(nel=(16, 32), seed=4), 3
+        kw = dict(smoother=2, nu_pre=2, nu_post=2)
+    elif variant == "hybrid":
+        p, levels = synth.column_2d(nel=(16, 64), seed=5), None
+        kw = dict(n_geometric=2, max_coarse=200)
+    else:
+        p, levels = synth.small_case(3, (6, 4, 8), seed=9), 2
+        kw = {}
+    KE = fem.element_stiffness(p.dim, p.nu)
+    E = fem.simp(p.rho, p.p, p.E0, p.Emin)
+    if variant == "chebyshev":
+        Ho = mg.build_geometric(p.nel, E, KE, p.fixed, levels, nu_pre=2, nu_post=2, smoother="chebyshev")
+    elif variant == "hybrid":
+        Ho = sa.build_hybrid(p.nel, E, KE, p.fixed, 2, max_coarse=200)
+    else:
+        Ho = mg.build_geometric(p.nel, E, KE, p.fixed, levels)
+    K = Ho.A[0]
+    u = mg.dense_solve(K, p.loads[0])
+    Ks = buckling.stress_stiffness(p.nel, u, p.rho, p.p, p.E0, p.nu, p.fixed)
+    V0 = _start(K.shape[0], 10, p.fixed, 2)
+    ref = davidson.generalized_davidson(lambda v: Ks @ v, lambda v: K @ v, lambda r: mg.vcycle(Ho, r), V0, nev=6)
+    assert ref.converged
+    if levels is not None:
+        kw["n_levels"] = levels
+    from paper_2001_01655_amd import Hierarchy
+    H = Hierarchy(p.nel, p.rho, p.fixed, p=p.p, E0=p.E0, Emin=p.Emin, nu=p.nu, **kw)
+    if variant == "hybrid":
+        assert H.num_levels() == Ho.L
+    r = H.solve(torch.tensor(p.loads[0], device="cuda"), rtol=1e-13)
+    H.stress_stiffness(r.u)
+    fp = 32 if variant == "fp32_3d" else 64
+    lam, Phi, it, nc, st = H.eigs(torch.tensor(V0.T.copy(), device="cuda"), nev=6, precond_fp=fp)
+    print(f"  gpu iters {it} oracle {ref.iters}", flush=True)
+    assert st == 0 and nc == 6
+    assert np.allclose(lam, ref.theta, rtol=1e-8, atol=0)
+    Pg = Phi.cpu().numpy().T
+    assert np.allclose(Pg.T @ (K @ Pg), np.eye(6), atol=1e-9)
+    if fp == 64:
+        assert abs(it - ref.iters) <= max(2, ref.iters // 10)
+    H.close()
