@@ -249,3 +249,25 @@ def test_eigs_other_preconditioners_vs_oracle(variant):
     if fp == 64:
         assert abs(it - ref.iters) <= max(2, ref.iters // 10)
     H.close()
+
+
+def test_eigs_degenerate_and_largest_space():
+    """No stress (u = 0): K_sigma~ = 0, all six eigenvalues 0 without an
+    expansion; the largest search space (j_max 32) gives the same eigenvalues
+    as the default one."""
+    p = synth.column_2d(nel=(8, 32), seed=2)
+    H = _hier(p, 3)
+    V0 = _start(p.n_dof, 10, p.fixed, 0)
+    v0 = torch.tensor(V0.T.copy(), device="cuda")
+    H.stress_stiffness(torch.zeros(p.n_dof, dtype=torch.float64, device="cuda"))
+    y = H.apply_stress_stiffness(torch.ones(p.n_dof, dtype=torch.float64, device="cuda"))
+    assert float(y.abs().max()) == 0.0
+    lam, Phi, it, nc, st = H.eigs(v0, nev=6)
+    assert st == 0 and it == 0 and nc == 6 and np.all(lam == 0.0)
+    r = H.solve(torch.tensor(p.loads[0], device="cuda"), rtol=1e-13)
+    H.stress_stiffness(r.u)
+    a, _, ita, nca, sta = H.eigs(v0, nev=6, precond_fp=64)
+    b, _, itb, ncb, stb = H.eigs(v0, nev=6, j_min=10, j_max=32, precond_fp=64)
+    assert sta == 0 and stb == 0 and np.allclose(a, b, rtol=1e-8)
+    print(f"  j_max 25: {ita} expansions, j_max 32: {itb}", flush=True)
+    H.close()

@@ -96,3 +96,13 @@ def test_standard_problem_with_exact_inverse_preconditioner():
                                         nev=3, j_min=5, j_max=12, max_iters=200)
     assert res.converged
     assert np.allclose(res.theta, [30.0, 20.0, 15.0], rtol=1e-10)
+
+
+def test_zero_pencil_converges_without_expansion():
+    """A = 0 (no stress, e.g. u = 0): every Ritz value is 0 with a zero
+    residual, so all pairs converge before the first expansion."""
+    n = 30
+    B = np.diag(np.linspace(1.0, 2.0, n))
+    res = davidson.generalized_davidson(lambda v: np.zeros_like(v), lambda v: B @ v, lambda r: r.copy(),
+                                        np.random.default_rng(0).standard_normal((n, 10)), nev=6)
+    assert res.converged and res.iters == 0 and np.all(res.theta == 0.0)
