@@ -1296,7 +1296,7 @@ tm_status tm_plan_bytes(const tm_mesh* mesh, const tm_options* opts, int32_t n_r
             last_n = nn * dim;
         }
         if (p.sa) last_n = std::min<int64_t>(last_n, opts->max_coarse * 8);
-        b += (size_t)last_n * last_n * 8 * 2 + el1 + el2;
+        b += (size_t)last_n * last_n * 8 * 2 + el1 + el2 + (size_t)(dim == 3 ? 27 : 9) * nd * nd * 8;
         if (opts->smoother == TM_SMOOTH_CHEBYSHEV) b += (size_t)nodes0 * dim * 8 * 3 + (size_t)nodes0 / 16 + 1024;
         const size_t per_rhs = (size_t)nodes0 * dim * (8 * 4 + (mixed ? 4 * 4 : 8 * 3)) + vec;
         *bytes = b + per_rhs * (size_t)n_rhs;
@@ -1375,6 +1375,8 @@ tm_status tm_setup(const tm_mesh* mesh, const tm_material* mat, const double* rh
             h->KA32 = halloc<float>(h, KA32.size());
         }
         TM_HIP(hipMemcpyAsync(h->KE64, KE.data(), KE.size() * 8, hipMemcpyHostToDevice, s));
+        h->galG = halloc<double>(h, (dim == 3 ? 27 : 9) * KE.size());
+        launch_galerkin_unit(dim, h->KE64, h->galG, s);
         if (dim == 3) TM_HIP(hipMemcpyAsync(h->KA32, KA32.data(), KA32.size() * 4, hipMemcpyHostToDevice, s));
         // levels
         h->lv.resize(plan.Lg);

@@ -28,11 +28,49 @@ __device__ __forceinline__ double axis_w(int kind, int a, int b) {
     return d == 0 ? 1.0 : (d == 1 || d == -1) ? 0.5 : 0.0;
 }
 
+// corner a's coordinate bit on axis ax (local order loc2 / loc3)
+__device__ __forceinline__ int gal_bit(int a, int ax) {
+    return ax == 0 ? (a == 1 || a == 2 || a == 5 || a == 6) : ax == 1 ? (a == 2 || a == 3 || a == 6 || a == 7) : a >= 4;
+}
+
+// Unit Galerkin products G_k = Q_k^T KE Q_k for every child kind triple
+// k = kx + 3 ky (+ 9 kz), kind per axis 0 / 1 (first / second half) or 2
+// (whole): a first coarse level whose children touch no supported dof is
+// sum_c E_c G_k(c), since a fine element's matrix there is E_e KE.
+template <int DIM>
+__global__ void k_galerkin_unit(const double* __restrict__ KE, double* __restrict__ G) {
+    constexpr int NPE = 1 << DIM, ND = DIM * NPE;
+    const int k = blockIdx.x, t = threadIdx.x;
+    const int kx = k % 3, ky = (k / 3) % 3, kz = k / 9;
+    const int rp = t / ND, sp = t % ND;
+    const int b = rp / DIM, i = rp % DIM, bq = sp / DIM, j = sp % DIM;
+    auto w = [&](int a, int c) {
+        return axis_w(kx, gal_bit(a, 0), gal_bit(c, 0)) * axis_w(ky, gal_bit(a, 1), gal_bit(c, 1)) *
+               (DIM == 3 ? axis_w(kz, gal_bit(a, 2), gal_bit(c, 2)) : 1.0);
+    };
+    double v = 0.0;
+    for (int a = 0; a < NPE; ++a) {
+        const double wa = w(a, b);
+        if (wa == 0.0) continue;
+        double u = 0.0;
+        for (int a2 = 0; a2 < NPE; ++a2) u += KE[(DIM * a + i) * ND + DIM * a2 + j] * w(a2, bq);
+        v += wa * u;
+    }
+    G[(int64_t)k * ND * ND + t] = v;
+}
+
+void launch_galerkin_unit(int dim, const double* KE, double* G, hipStream_t s) {
+    if (dim == 3)
+        hipLaunchKernelGGL(k_galerkin_unit<3>, dim3(27), dim3(576), 0, s, KE, G);
+    else
+        hipLaunchKernelGGL(k_galerkin_unit<2>, dim3(9), dim3(64), 0, s, KE, G);
+}
+
 template <int DIM>
 __global__ void k_galerkin(const double* __restrict__ child, const double* __restrict__ E,
-                           const double* __restrict__ KE, const uint8_t* __restrict__ nm,
-                           int fnx, int fny, int fnz, int cnx, int cny, int cnz,
-                           double* __restrict__ parent) {
+                           const double* __restrict__ KE, const double* __restrict__ G,
+                           const uint8_t* __restrict__ nm, int fnx, int fny, int fnz, int cnx, int cny,
+                           int cnz, double* __restrict__ parent) {
     constexpr int NPE = 1 << DIM, ND = DIM * NPE;
     __shared__ double Kc[ND * ND];
     __shared__ double Tm[ND * ND];
@@ -46,6 +84,32 @@ __global__ void k_galerkin(const double* __restrict__ child, const double* __res
     const int r = t / ND, s = t % ND;
     // children per axis: 2, or 1 (whole) for the last element of an odd count
     const bool wx = 2 * X + 1 == fnx, wy = 2 * Y + 1 == fny, wz = DIM == 3 && 2 * Z + 1 == fnz;
+    if (!child) {
+        // first coarse level: children are E_e KE; without supported dofs among
+        // the parent's fine nodes the product is sum_c E_c G_k(c)
+        int touched = 0;
+        if (nm && t < (DIM == 3 ? 27 : 9)) {
+            const int nx_ = 2 * X + t % 3, ny_ = 2 * Y + (t / 3) % 3, nz_ = 2 * Z + t / 9;
+            if (nx_ <= fnx && ny_ <= fny && (DIM == 2 || nz_ <= fnz)) {
+                const int64_t fnode = DIM == 3 ? ((int64_t)nz_ * (fny + 1) + ny_) * (fnx + 1) + nx_
+                                               : (int64_t)ny_ * (fnx + 1) + nx_;
+                touched = nm[fnode] != 0;
+            }
+        }
+        if (!__syncthreads_or(touched)) {
+            double acc = 0.0;
+            for (int c = 0; c < NPE; ++c) {
+                const int cx = c & 1, cy = (c >> 1) & 1, cz = (c >> 2) & 1;
+                if ((wx && cx) || (wy && cy) || (wz && cz)) continue;
+                const int kx = wx ? 2 : cx, ky = wy ? 2 : cy, kz = wz ? 2 : cz;
+                const int gx = 2 * X + cx, gy = 2 * Y + cy, gz = 2 * Z + cz;
+                const int64_t ce = DIM == 3 ? ((int64_t)gz * fny + gy) * fnx + gx : (int64_t)gy * fnx + gx;
+                acc += E[ce] * G[(int64_t)(kx + 3 * ky + 9 * kz) * ND * ND + t];
+            }
+            parent[pe * ND * ND + t] = acc;
+            return;
+        }
+    }
     double acc = 0.0;
     for (int c = 0; c < NPE; ++c) {
         const int cx = c & 1, cy = (c >> 1) & 1, cz = (c >> 2) & 1;   // child position bits
@@ -114,10 +178,11 @@ void launch_galerkin_elems(const tm_hierarchy* h, int fine_level, const double* 
     const uint8_t* nm = fine_level == 0 ? F.nmask : nullptr;
     if (h->dim == 3)
         hipLaunchKernelGGL(k_galerkin<3>, dim3((unsigned)n_par), dim3(576), 0, s, child, F.E64,
-                           h->KE64, nm, F.nel[0], F.nel[1], F.nel[2], C.nel[0], C.nel[1], C.nel[2], parent);
+                           h->KE64, h->galG, nm, F.nel[0], F.nel[1], F.nel[2], C.nel[0], C.nel[1], C.nel[2],
+                           parent);
     else
         hipLaunchKernelGGL(k_galerkin<2>, dim3((unsigned)n_par), dim3(64), 0, s, child, F.E64,
-                           h->KE64, nm, F.nel[0], F.nel[1], 1, C.nel[0], C.nel[1], 1, parent);
+                           h->KE64, h->galG, nm, F.nel[0], F.nel[1], 1, C.nel[0], C.nel[1], 1, parent);
 }
 
 // --------------------------------------------------------------- stencil assembly

@@ -232,6 +232,7 @@ struct tm_hierarchy {
     std::vector<int64_t> fixed;
     std::vector<tmi::Level> lv;
     double* KE64 = nullptr;        // element stiffness for E = 1 (device)
+    double* galG = nullptr;        // unit Galerkin products Q_k^T KE Q_k per child kind (27 or 9)
     double* rho64 = nullptr;       // densities of the current design (device)
     float* KA32 = nullptr;         // 3D: KE as the broadcast A operand of the matrix-core fine operator
     tmi::KeVals<double> kc64{};       // KE symmetry-class values (fine operator arguments)
@@ -348,6 +349,7 @@ int fine_op_blocks(const tm_hierarchy* h);
 // coarse geometric levels (kernels_coarse.hip)
 void launch_galerkin_elems(const tm_hierarchy* h, int fine_level, const double* child,
                            double* parent, hipStream_t s);
+void launch_galerkin_unit(int dim, const double* KE, double* G, hipStream_t s);
 void launch_stencil_assemble(const Level& L, const double* elem, hipStream_t s);
 void launch_stencil_compact(const Level& L, hipStream_t s);
 void launch_stencil_dinv(const Level& L, int point_jacobi, int* flags, hipStream_t s);
