@@ -318,6 +318,111 @@ __global__ __launch_bounds__(WG) void k_fine3(const T* __restrict__ E, const KeV
     if (OP == OP_QDOT) block_reduce_store<2>(dots, partials);
 }
 
+// The same operator for two nodes stacked in z per thread (k even, k + 1):
+// their neighbourhoods share two of the four planes k-1 .. k+2, so a thread
+// gathers 36 neighbour values and 12 moduli for two nodes instead of 54 and 16.
+// Each node's terms are summed in the order of k_fine3 (layer 0 of plane 0,
+// layers 0 and 1 of plane 1, layer 1 of plane 2), so the results are bitwise
+// those of k_fine3.  Used for the V-cycle's operators (no partial sums).
+template <typename T, int OP>
+__global__ __launch_bounds__(WG) void k_fine3z2(const T* __restrict__ E, const KeVals<T> kc,
+                                                const uint8_t* __restrict__ nm, int nx, int ny, int nz,
+                                                int64_t N64, const T* __restrict__ x, const T* __restrict__ b,
+                                                T* __restrict__ y, const T* __restrict__ dinv, T omega,
+                                                const int* __restrict__ done, const ChebArgs ch) {
+    static_assert(OP != OP_QDOT, "no partial sums in the two-node operator");
+    if (done && *done) return;
+    const uint32_t N = (uint32_t)N64;
+    const uint32_t NX = nx + 1, NY = ny + 1, NZ = nz + 1, PL = NX * NY;
+    const uint32_t NT = PL * ((NZ + 1) / 2);           // threads: z pairs
+    const uint32_t p = (uint32_t)xcd_block() * WG + threadIdx.x;
+    const bool live = p < NT;
+    const uint32_t pp = live ? p : 0u;
+    const uint32_t i = pp % NX, tq = pp / NX, j = tq % NY, k = 2u * (tq / NY);
+    const bool two = k + 1 < NZ;                        // the upper node exists
+    const uint32_t nd0 = k * PL + j * NX + i;
+    const uint32_t nd1 = two ? nd0 + PL : nd0;
+    const uint32_t ox[3] = {i ? 0u - 1u : 0u, 0u, i + 1 < NX ? 1u : 0u};
+    const uint32_t oy[3] = {j ? 0u - NX : 0u, 0u, j + 1 < NY ? NX : 0u};
+    (void)ox;
+    (void)oy;
+    constexpr uint32_t NB = 3u * sizeof(T);
+    uint32_t nb0 = nd0 * NB;
+    asm volatile("" : "+v"(nb0));
+    const uint32_t bx[3] = {i ? 0u - NB : 0u, 0u, i + 1 < NX ? NB : 0u};
+    const uint32_t by[3] = {j ? 0u - NX * NB : 0u, 0u, j + 1 < NY ? NX * NB : 0u};
+    // planes k-1 .. k+2 relative to node k, clamped into the grid (what lies
+    // outside only meets elements of modulus zero)
+    const uint32_t bz[4] = {k ? 0u - PL * NB : 0u, 0u, k + 1 < NZ ? PL * NB : 0u,
+                            k + 2 < NZ ? 2u * PL * NB : (k + 1 < NZ ? PL * NB : 0u)};
+    const auto xr = buf_rsrc(x, (int64_t)N * 3 * sizeof(T));
+    const auto er = buf_rsrc(E, (int64_t)nx * ny * nz * sizeof(T));
+    // moduli of element layers k-1, k, k+1 (index clamped, zero outside)
+    const uint32_t EX = (uint32_t)nx, EP = EX * (uint32_t)ny;
+    const uint32_t jE = j * EX;
+    const uint32_t gx[2] = {i ? i - 1 : 0u, i < EX ? i : i - 1};
+    const uint32_t gy[2] = {j ? jE - EX : 0u, j < (uint32_t)ny ? jE : jE - EX};
+    T El[3][2][2];
+#pragma unroll
+    for (int lz = 0; lz < 3; ++lz) {
+        const int layer = (int)k - 1 + lz;
+        const bool zin = layer >= 0 && layer < nz;
+        const uint32_t gz = zin ? (uint32_t)layer * EP : 0u;
+#pragma unroll
+        for (int ey = 0; ey < 2; ++ey)
+#pragma unroll
+            for (int ex = 0; ex < 2; ++ex) {
+                const bool in = zin && (ex || i) && (ex == 0 || i < (uint32_t)nx) && (ey || j) &&
+                                (ey == 0 || j < (uint32_t)ny);
+                El[lz][ey][ex] = in ? bld<T>(er, (gz + gy[ey] + gx[ex]) * (uint32_t)sizeof(T)) : T(0);
+            }
+    }
+    T E0[2][2][2], E1[2][2][2];
+#pragma unroll
+    for (int ez = 0; ez < 2; ++ez)
+#pragma unroll
+        for (int ey = 0; ey < 2; ++ey)
+#pragma unroll
+            for (int ex = 0; ex < 2; ++ex) {
+                E0[ez][ey][ex] = El[ez][ey][ex];
+                E1[ez][ey][ex] = El[ez + 1][ey][ex];
+            }
+    T acc0[3] = {0, 0, 0}, acc1[3] = {0, 0, 0};
+    T w[9][3];
+    auto load_plane = [&](int P) {
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy) {
+            const uint32_t rowb = nb0 + bz[P] + by[dy];
+#pragma unroll
+            for (int dx = 0; dx < 3; ++dx) bld3(xr, rowb + bx[dx], w[dy * 3 + dx]);
+        }
+    };
+    FinIn<T, 3> fin0, fin1;
+    finish_load<T, 3, OP>(nd0, N, b, dinv, ch, fin0);
+    finish_load<T, 3, OP>(nd1, N, b, dinv, ch, fin1);
+    const uint8_t m0 = nm[nd0], m1 = nm[nd1];
+    load_plane(0);
+    layer_plane3<0, 0>(kc, w, E0, acc0);
+    load_plane(1);
+    T xo0[3], xo1[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) xo0[c] = w[4][c];
+    layer_plane3<1, 0>(kc, w, E0, acc0);
+    layer_plane3<1, 1>(kc, w, E0, acc0);
+    layer_plane3<0, 0>(kc, w, E1, acc1);
+    load_plane(2);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) xo1[c] = w[4][c];
+    layer_plane3<2, 1>(kc, w, E0, acc0);
+    layer_plane3<1, 0>(kc, w, E1, acc1);
+    layer_plane3<1, 1>(kc, w, E1, acc1);
+    load_plane(3);
+    layer_plane3<2, 1>(kc, w, E1, acc1);
+    double dots[2] = {0.0, 0.0};
+    if (live) finish_store<T, 3, OP>(nd0, acc0, xo0, m0, fin0, y, omega, dots, ch);
+    if (live && two) finish_store<T, 3, OP>(nd1, acc1, xo1, m1, fin1, y, omega, dots, ch);
+}
+
 // 3D FP32 on the matrix cores: the same node-per-lane operator, with the
 // 24x24 KE contraction on v_mfma_f32_4x4x1 (16 blocks of 4 lanes).  In each
 // block, lane 4b+j supplies B = one neighbour value of its own node and gets
@@ -559,6 +664,15 @@ static void fine_dispatch(const tm_hierarchy* h, const T* x, const T* b, T* y, T
         if (L.dim == 3 && h->opt.fine_mfma) {
             hipLaunchKernelGGL((k_fine3_mfma<OP>), g, blk, 0, s, L.E32, h->KA32, L.nmask, L.nel[0], L.nel[1],
                                L.nel[2], L.n_nodes, x, b, y, L.dinv32, omega, done, ch);
+            return;
+        }
+    }
+    if constexpr (std::is_same<T, float>::value && !MI && OP != OP_QDOT) {
+        if (L.dim == 3) {
+            const int64_t nt = (int64_t)L.nn[0] * L.nn[1] * ((L.nn[2] + 1) / 2);
+            hipLaunchKernelGGL((k_fine3z2<T, OP>), dim3(grid_for(nt)), blk, 0, s, pick_E<T>(L), pick_kc<T>(h),
+                               L.nmask, L.nel[0], L.nel[1], L.nel[2], L.n_nodes, x, b, y, pick_dinv<T>(L), omega,
+                               done, ch);
             return;
         }
     }
