@@ -234,7 +234,9 @@ void launch_cholesky_inverse(double* A, double* Ainv, double* Ls, int64_t n, int
                        (const double*)A, n, Ainv);
 }
 
-// x = A^-1 b in FP64 (one wave per row, fixed shuffle tree)
+// x = A^-1 b in FP64 (one wave per row, fixed shuffle tree).  Each lane keeps
+// four partial sums over columns lane + 64 (4 q + r), so four independent
+// loads are in flight per lane; the partials are added in a fixed order.
 template <typename T>
 __global__ __launch_bounds__(256) void k_dense_solve(const double* __restrict__ Ainv, int64_t n,
                                                      const T* __restrict__ b, T* __restrict__ x,
@@ -243,8 +245,19 @@ __global__ __launch_bounds__(256) void k_dense_solve(const double* __restrict__ 
     const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (row >= n) return;
-    double a = 0.0;
-    for (int64_t c = lane; c < n; c += 64) a += Ainv[row * n + c] * (double)b[c];
+    const double* Ar = Ainv + row * n;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int64_t c = lane;
+    for (; c + 192 < n; c += 256) {
+        a0 += Ar[c] * (double)b[c];
+        a1 += Ar[c + 64] * (double)b[c + 64];
+        a2 += Ar[c + 128] * (double)b[c + 128];
+        a3 += Ar[c + 192] * (double)b[c + 192];
+    }
+    if (c < n) a0 += Ar[c] * (double)b[c];
+    if (c + 64 < n) a1 += Ar[c + 64] * (double)b[c + 64];
+    if (c + 128 < n) a2 += Ar[c + 128] * (double)b[c + 128];
+    double a = (a0 + a1) + (a2 + a3);
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) a += __shfl_down(a, o, 64);
     if (lane == 0) x[row] = (T)a;
