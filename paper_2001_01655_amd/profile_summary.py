@@ -23,7 +23,7 @@ COPY_BYTES = 256 << 20
 CLASSES = {
     0: dict(match=["k_fine3<double, 3, false>"], source=["kernels_fine.hip", "tm_device.h"],
             what="fine operator FP64 (q = K~p, outer loop)"),
-    1: dict(match=["k_fine3<float, 1, false>", "k_fine3<float, 2, false>", "k_fine3<float, 4, false>"],
+    1: dict(match=["k_fine3z2<float, 1>", "k_fine3z2<float, 2>", "k_fine3z2<float, 4>"],
             source=["kernels_fine.hip", "tm_device.h"], what="fine operator FP32 (V-cycle smoothing / residual)"),
     2: dict(match=["k_stencil_op<float, 3, 1, 3>", "k_stencil_op<float, 3, 2, 3>", "k_stencil_op<float, 3, 4, 3>"],
             source=["kernels_coarse.hip", "tm_device.h"], what="level-1 stencil operator FP32 (V-cycle)",
