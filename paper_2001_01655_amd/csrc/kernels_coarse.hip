@@ -319,6 +319,15 @@ void launch_stencil_dinv(const Level& L, int point_jacobi, int* flags, hipStream
 // stored block towards this node (A is symmetric).  Neighbours outside the grid
 // have zero stored blocks (upper) or have their x masked to zero (lower); all
 // loads use clamped, in-bounds indices, with no branches.
+// Offset visited at step t of the neighbour loop: the mirror pair
+// (NU-1-q, NU+1+q) for t = 2q, 2q+1 (both read stored row group q of the
+// symmetric form: the upper offset as the node's own block, the lower one as
+// the neighbour's block, transposed), the centre NU last.
+template <int NU>
+__host__ __device__ constexpr int pair_order(int t) {
+    return t >= 2 * NU ? NU : ((t & 1) ? NU + 1 + t / 2 : NU - 1 - t / 2);
+}
+
 template <typename T, int DIM, int OP, int G>
 __global__ __launch_bounds__(WG) void k_stencil_op(const T* __restrict__ st, int nx, int ny, int nz,
                                                    int64_t N, const T* __restrict__ x,
@@ -368,14 +377,17 @@ __global__ __launch_bounds__(WG) void k_stencil_op(const T* __restrict__ st, int
     // neighbours in groups of G: all loads of a group are issued before its
     // arithmetic (the scheduling barrier keeps them batched), so G * (BB + DIM)
     // loads are in flight per wave (small levels: larger groups, fewer round
-    // trips, since occupancy no longer hides the latency)
+    // trips, since occupancy no longer hides the latency).  Offsets are visited
+    // in mirror pairs (pair_order), so a stored row is read as an own block and
+    // as a neighbour's transposed block at about the same time.
 #pragma unroll
     for (int g0 = 0; g0 < NST; g0 += G) {
         T xv[G][DIM], blk[G][BB];
 #pragma unroll
         for (int gg = 0; gg < G; ++gg) {
-            const int o = g0 + gg;
-            if (o >= NST || o == NU) continue;
+            if (g0 + gg >= NST) continue;
+            const int o = pair_order<NU>(g0 + gg);
+            if (o == NU) continue;
             const int dx = o % 3, dy = (o / 3) % 3, dz = DIM == 3 ? o / 9 : 1;
             const uint32_t J = (ck[dz] * (uint32_t)NY + cj[dy]) * (uint32_t)NX + ci[dx];
 #pragma unroll
@@ -401,8 +413,9 @@ __global__ __launch_bounds__(WG) void k_stencil_op(const T* __restrict__ st, int
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int gg = 0; gg < G; ++gg) {
-            const int o = g0 + gg;
-            if (o >= NST || o == NU) continue;
+            if (g0 + gg >= NST) continue;
+            const int o = pair_order<NU>(g0 + gg);
+            if (o == NU) continue;
 #pragma unroll
             for (int r = 0; r < DIM; ++r)
 #pragma unroll
