@@ -577,7 +577,7 @@ static void stencil_dispatch(const Level& L, int op, const T* x, const T* b, T* 
             stencil_launch<T, DIM, 9>(L, op, x, b, y, omega, done, s, ch);
     }
     else
-        stencil_launch<T, DIM, DIM == 3 ? 3 : 4>(L, op, x, b, y, omega, done, s, ch);
+        stencil_launch<T, DIM, 4>(L, op, x, b, y, omega, done, s, ch);
 }
 
 template <typename T>

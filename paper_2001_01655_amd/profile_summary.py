@@ -25,7 +25,7 @@ CLASSES = {
             what="fine operator FP64 (q = K~p, outer loop)"),
     1: dict(match=["k_fine3z2<float, 1>", "k_fine3z2<float, 2>", "k_fine3z2<float, 4>"],
             source=["kernels_fine.hip", "tm_device.h"], what="fine operator FP32 (V-cycle smoothing / residual)"),
-    2: dict(match=["k_stencil_op<float, 3, 1, 3>", "k_stencil_op<float, 3, 2, 3>", "k_stencil_op<float, 3, 4, 3>"],
+    2: dict(match=["k_stencil_op<float, 3, 1, 4>", "k_stencil_op<float, 3, 2, 4>", "k_stencil_op<float, 3, 4, 4>"],
             source=["kernels_coarse.hip", "tm_device.h"], what="level-1 stencil operator FP32 (V-cycle)",
             largest_grid=True),
 }
