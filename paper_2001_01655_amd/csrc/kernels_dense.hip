@@ -193,29 +193,53 @@ __global__ __launch_bounds__(256) void k_chol_update(double* __restrict__ A, int
         }
 }
 
-// Column c of A^-1 from the factor L (lower part of Lf): solve L y = e_c, then
-// L^T x = y; by symmetry x is also row c, which is stored.
+// Mirror the factor into the strict upper triangle (Lf[i][k] = L[k][i], k > i),
+// so that the forward solve below reads column i of L as a contiguous row.
+__global__ __launch_bounds__(256) void k_chol_mirror(double* __restrict__ Lf, int64_t n) {
+    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= n * n) return;
+    const int64_t i = idx / n, k = idx % n;
+    if (k > i) Lf[i * n + k] = Lf[k * n + i];
+}
+
+// Column c of A^-1 from the factor L (lower part of Lf, mirrored above): solve
+// L y = e_c, then L^T x = y; by symmetry x is also row c, which is stored.
+// The reciprocal diagonal sits in LDS; every step reads one row of Lf
+// (contiguous) and ends in one barrier: the entry a step finishes is written
+// back by thread 0 one step later, when no thread reads it any more.
 __global__ __launch_bounds__(256) void k_chol_inverse(const double* __restrict__ Lf, int64_t n,
                                                       double* __restrict__ Ainv) {
-    extern __shared__ double y[];
+    extern __shared__ double sh[];
+    double* y = sh;
+    double* dinv = sh + n;
     const int64_t c = blockIdx.x;
     const int t = threadIdx.x, nt = blockDim.x;
-    for (int64_t i = t; i < n; i += nt) y[i] = (i == c) ? 1.0 : 0.0;
+    for (int64_t i = t; i < n; i += nt) {
+        y[i] = (i == c) ? 1.0 : 0.0;
+        dinv[i] = 1.0 / Lf[i * n + i];
+    }
     __syncthreads();
+    double prev = 0.0;
     for (int64_t i = c; i < n; ++i) {            // forward: y_i /= L_ii; y_k -= L_ki y_i (k > i)
-        const double yi = y[i] / Lf[i * n + i];
-        __syncthreads();
-        if (t == 0) y[i] = yi;
-        for (int64_t k = i + 1 + t; k < n; k += nt) y[k] -= Lf[k * n + i] * yi;
+        const double yi = y[i] * dinv[i];
+        if (t == 0 && i > c) y[i - 1] = prev;
+        const double* Lt = Lf + i * n;           // row i of the mirror: L_ki for k > i
+        for (int64_t k = i + 1 + t; k < n; k += nt) y[k] -= Lt[k] * yi;
+        prev = yi;
         __syncthreads();
     }
+    if (t == 0) y[n - 1] = prev;
+    __syncthreads();
     for (int64_t i = n - 1; i >= 0; --i) {       // backward: x_i = y_i / L_ii; y_k -= L_ik x_i (k < i)
-        const double xi = y[i] / Lf[i * n + i];
-        __syncthreads();
-        if (t == 0) y[i] = xi;
-        for (int64_t k = t; k < i; k += nt) y[k] -= Lf[i * n + k] * xi;
+        const double xi = y[i] * dinv[i];
+        if (t == 0 && i < n - 1) y[i + 1] = prev;
+        const double* Li = Lf + i * n;
+        for (int64_t k = t; k < i; k += nt) y[k] -= Li[k] * xi;
+        prev = xi;
         __syncthreads();
     }
+    if (t == 0) y[0] = prev;
+    __syncthreads();
     for (int64_t i = t; i < n; i += nt) Ainv[c * n + i] = y[i];
 }
 
@@ -230,7 +254,8 @@ void launch_cholesky_inverse(double* A, double* Ainv, double* Ls, int64_t n, int
         hipLaunchKernelGGL(k_chol_update, dim3((unsigned)(rem * (rem + 1) / 2 + 1)), dim3(256), 0, s, A, n, kb,
                            rem, (const double*)Ls);
     }
-    hipLaunchKernelGGL(k_chol_inverse, dim3((unsigned)n), dim3(256), (size_t)n * sizeof(double), s,
+    hipLaunchKernelGGL(k_chol_mirror, dim3((unsigned)ceil_div(n * n, (int64_t)256)), dim3(256), 0, s, A, n);
+    hipLaunchKernelGGL(k_chol_inverse, dim3((unsigned)n), dim3(256), (size_t)2 * n * sizeof(double), s,
                        (const double*)A, n, Ainv);
 }
 
