@@ -69,6 +69,8 @@ def parse():
     ap.add_argument("--served-designs", type=int, default=20)
     ap.add_argument("--served-smoother", default="chebyshev", choices=sorted(SMOOTHERS))
     ap.add_argument("--served-sweeps", type=int, default=2)
+    ap.add_argument("--served-warm-steps", type=int, default=4,
+                    help="power steps of a design update's Chebyshev estimate, from the previous vector (0: 12 cold)")
     ap.add_argument("--levels", type=int, default=None, help="multigrid levels (default: the workload's)")
     ap.add_argument("--smoother", default="chebyshev", choices=sorted(SMOOTHERS))
     ap.add_argument("--sweeps", type=int, default=2, help="pre- and post-smoothing sweeps")
@@ -210,7 +212,8 @@ def cpu_baseline(cfg_name, args):
             "host": platform.processor() or platform.machine(), "host_cpus": os.cpu_count()}
 
 
-def served_leg(n_req: int, n_designs: int, smoother: str = "chebyshev", sweeps: int = 2, seed: int = 5):
+def served_leg(n_req: int, n_designs: int, smoother: str = "chebyshev", sweeps: int = 2, seed: int = 5,
+               warm_steps: int = 4):
     """The served stream (mixed 2D/3D sizes, 1-4 load cases, design updates
     with warm starts, rtol 1e-6): first every request at t = 0 to find the
     saturation throughput, then Poisson arrivals at 70% of that request rate;
@@ -226,7 +229,8 @@ def served_leg(n_req: int, n_designs: int, smoother: str = "chebyshev", sweeps: 
     for r in reqs:
         for t in range(n_designs):
             r.densities(t)
-    eng = GpuEngine(smoother=SMOOTHERS[smoother], nu_pre=sweeps, nu_post=sweeps)
+    warm = warm_steps if smoother == "chebyshev" else 0
+    eng = GpuEngine(smoother=SMOOTHERS[smoother], nu_pre=sweeps, nu_post=sweeps, cheb_warm_steps=warm)
     budget = 64 << 30
     Server(eng, budget, max_slots=8, chunk=4, rtol=1e-6).run(
         [dataclasses.replace(r, arrival=0.0, n_designs=2) for r in reqs[:4]])          # warm-up
@@ -245,7 +249,7 @@ def served_leg(n_req: int, n_designs: int, smoother: str = "chebyshev", sweeps: 
             "mean_iters": round(float(np.mean(iters)), 2) if iters else None,
             "max_slots": 8, "chunk": 4, "latency": "request arrival to its last solve",
             "sizes": "2D 128x64, 2D 512x256, 3D 48^3, 3D 96x48x48; 1-4 load cases; rtol 1e-6",
-            "smoothing": f"{smoother} {sweeps}/{sweeps}"}
+            "smoothing": f"{smoother} {sweeps}/{sweeps}", "cheb_warm_steps": warm}
 
 
 def adaptive_leg(n_designs: int, nel=(128, 64, 64), seed: int = 4):
@@ -545,7 +549,8 @@ def main():
         H64.close()
     line["detail"] = detail
     if args.served > 0:
-        line["served"] = served_leg(args.served, args.served_designs, args.served_smoother, args.served_sweeps)
+        line["served"] = served_leg(args.served, args.served_designs, args.served_smoother, args.served_sweeps,
+                                    warm_steps=args.served_warm_steps)
     if args.grid_study:
         line["grid_study"] = grid_leg()
     if args.adaptive_stream > 0:

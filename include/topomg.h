@@ -95,6 +95,11 @@ typedef struct {
                               many iterations, the next tm_update_density turns the coarsest
                               geometric level into smoothed-aggregation levels (down to 2
                               geometric levels, max_coarse as usual).  0 (default): off      */
+    int32_t cheb_warm_steps; /* Chebyshev smoothing: a tm_update_density starts each geometric
+                              level's power estimate from that level's last estimate vector and
+                              runs this many steps (1..12) instead of 12 from the fixed start;
+                              aggregation levels and the first setup always start cold.
+                              0 (default): every setup runs 12 steps from the fixed start     */
 } tm_options;
 
 typedef struct tm_hierarchy tm_hierarchy;       /* opaque */

@@ -216,6 +216,7 @@ static void check_opts(const tm_options* o) {
     if (o->smoother == TM_SMOOTH_CHEBYSHEV && !(o->cheb_lower > 0.0 && o->cheb_lower < 1.0))
         fail(TM_ERR_ARG, "cheb_lower must be in (0, 1)");
     if (o->adapt_iters < 0) fail(TM_ERR_ARG, "adapt_iters must be >= 0");
+    if (o->cheb_warm_steps < 0 || o->cheb_warm_steps > 12) fail(TM_ERR_ARG, "cheb_warm_steps must be in 0..12");
     if (o->nu_pre < 1 || o->nu_post < 1 || o->nu_pre > 16 || o->nu_post > 16)
         fail(TM_ERR_ARG, "nu_pre / nu_post must be in 1..16");
     if (!(o->omega > 0.0 && o->omega < 2.0)) fail(TM_ERR_ARG, "omega must be in (0, 2)");
@@ -337,7 +338,7 @@ static void read_flags(tm_hierarchy* h, hipStream_t s, const char* phase) {
 void build_sa_levels(tm_hierarchy* h, hipStream_t s);      // kernels_sa / host_sa
 void numeric_sa_levels(tm_hierarchy* h, hipStream_t s);
 
-static void cheb_interval(tm_hierarchy* h, int l, hipStream_t s);
+static void cheb_interval(tm_hierarchy* h, int l, hipStream_t s, bool warm);
 
 // Numeric setup for densities rho.  With sync the device checks (densities,
 // SPD blocks, coarsest factor) are read before returning; without, nothing
@@ -365,7 +366,21 @@ static void numeric_setup(tm_hierarchy* h, const double* rho, hipStream_t s, boo
     if (h->sa) numeric_sa_levels(h, s);
     if (h->opt.smoother == TM_SMOOTH_CHEBYSHEV) {
         if ((int)h->lv.size() > CHEB_MAX_LEVELS) fail(TM_ERR_ARG, "too many levels for Chebyshev smoothing");
-        for (int l = 0; l + 1 < (int)h->lv.size(); ++l) cheb_interval(h, l, s);
+        if (h->opt.cheb_warm_steps > 0 && !h->cheb_v) {
+            // one vector per geometric level (their sizes never change)
+            int64_t tot = 0;
+            h->cheb_off.assign(Lg, 0);
+            for (int l = 0; l < Lg; ++l) {
+                h->cheb_off[l] = tot;
+                tot += h->lv[l].n;
+            }
+            h->cheb_v = halloc<double>(h, (size_t)tot);
+            h->cheb_ninv = halloc<double>(h, CHEB_MAX_LEVELS);
+            h->cheb_warm = false;
+        }
+        const bool warm = h->cheb_v && h->cheb_warm;
+        for (int l = 0; l + 1 < (int)h->lv.size(); ++l) cheb_interval(h, l, s, warm && l < Lg);
+        if (h->cheb_v) h->cheb_warm = true;
     }
     // coarsest operator: dense FP64, Cholesky, explicit inverse
     Level& C = h->lv.back();
@@ -449,7 +464,11 @@ static void level_op(tm_hierarchy* h, int l, int op, const T* x, const T* b, T* 
 // supported dofs; lambda = |D^-1 A v| / |v| at the last step).  Everything stays
 // on the device: theta_l = lambda (lower + 1.1) / 2 goes to cheb_theta[l] and the
 // level's D^-1 is divided by it.
-static void cheb_interval(tm_hierarchy* h, int l, hipStream_t s) {
+// Chebyshev interval centre of level l from power steps on D^-1 A: 12 steps
+// from the fixed start vector, or (warm) cheb_warm_steps steps from the level's
+// last estimate vector.  A level with a kept vector saves its last iterate at
+// unit length for the next design.
+static void cheb_interval(tm_hierarchy* h, int l, hipStream_t s, bool warm) {
     Level& L = h->lv[l];
     const int64_t n0 = h->lv[0].n;
     double* v = h->pw;
@@ -457,13 +476,23 @@ static void cheb_interval(tm_hierarchy* h, int l, hipStream_t s) {
     double* z = h->pw + 2 * n0;
     double* part = h->pw + 3 * n0;
     const int nb = (int)grid_for(L.n_nodes);
-    launch_power_start(v, L.n, l == 0 ? L.nmask : nullptr, L.bs, s);
-    for (int it = 0; it < 12; ++it) {
+    // geometric levels keep their sizes for the hierarchy's life (a demotion
+    // turns the last one into aggregation levels, which never keep a vector)
+    const bool keep = h->cheb_v && l < (int)h->cheb_off.size() && L.kind != TM_LEVEL_AGGREGATION;
+    double* kept = keep ? h->cheb_v + h->cheb_off[l] : nullptr;
+    if (warm && keep)
+        TM_HIP(hipMemcpyAsync(v, kept, (size_t)L.n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    else
+        launch_power_start(v, L.n, l == 0 ? L.nmask : nullptr, L.bs, s);
+    const int steps = warm && keep ? h->opt.cheb_warm_steps : 12;
+    for (int it = 0; it < steps; ++it) {
         level_op<double>(h, l, OP_APPLY, v, v, w, nullptr, s);
         launch_power_step(L, w, v, z, part, s);
         std::swap(v, z);
     }
-    launch_cheb_theta(part, nb, 0.5 * (h->opt.cheb_lower + 1.1), h->cheb_theta + l, s);
+    launch_cheb_theta(part, nb, 0.5 * (h->opt.cheb_lower + 1.1), h->cheb_theta + l,
+                      keep ? h->cheb_ninv + l : nullptr, s);
+    if (keep) launch_scale_copy(v, kept, L.n, h->cheb_ninv + l, s);
     launch_scale_dinv(L, h->cheb_theta + l, s);
 }
 
@@ -1251,6 +1280,7 @@ void tm_default_options(tm_options* o) {
     o->fine_mfma = 0;
     o->cheb_lower = 0.1;
     o->adapt_iters = 0;
+    o->cheb_warm_steps = 0;
 }
 
 const char* tm_status_string(tm_status s) {
@@ -1298,6 +1328,7 @@ tm_status tm_plan_bytes(const tm_mesh* mesh, const tm_options* opts, int32_t n_r
         if (p.sa) last_n = std::min<int64_t>(last_n, opts->max_coarse * 8);
         b += (size_t)last_n * last_n * 8 * 2 + el1 + el2 + (size_t)(dim == 3 ? 27 : 9) * nd * nd * 8;
         if (opts->smoother == TM_SMOOTH_CHEBYSHEV) b += (size_t)nodes0 * dim * 8 * 3 + (size_t)nodes0 / 16 + 1024;
+        if (opts->smoother == TM_SMOOTH_CHEBYSHEV && opts->cheb_warm_steps > 0) b += (size_t)nodes0 * dim * 8 * 2;
         const size_t per_rhs = (size_t)nodes0 * dim * (8 * 4 + (mixed ? 4 * 4 : 8 * 3)) + vec;
         *bytes = b + per_rhs * (size_t)n_rhs;
     });

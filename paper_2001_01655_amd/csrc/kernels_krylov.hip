@@ -394,15 +394,30 @@ void launch_power_step(const Level& L, const double* w, const double* v, double*
 
 // theta = factor * sqrt(z.z / v.v) from the last power step's partials: the
 // estimate of the largest eigenvalue of D^-1 A times (lower + upper) / 2
+// (and, when ninv is given, 1 / ||z|| for keeping the last vector at unit length)
 __global__ __launch_bounds__(FB) void k_cheb_theta(const double* part, int nparts, double factor,
-                                                   double* theta) {
+                                                   double* theta, double* ninv) {
     double t[2];
     fin_sums<2>(part, nparts, t);
-    if (threadIdx.x == 0) *theta = factor * sqrt(t[0] / t[1]);
+    if (threadIdx.x == 0) {
+        *theta = factor * sqrt(t[0] / t[1]);
+        if (ninv) *ninv = t[0] > 0.0 ? 1.0 / sqrt(t[0]) : 0.0;
+    }
 }
 
-void launch_cheb_theta(const double* part, int nparts, double factor, double* theta, hipStream_t s) {
-    hipLaunchKernelGGL(k_cheb_theta, dim3(1), dim3(FB), 0, s, part, nparts, factor, theta);
+void launch_cheb_theta(const double* part, int nparts, double factor, double* theta, double* ninv, hipStream_t s) {
+    hipLaunchKernelGGL(k_cheb_theta, dim3(1), dim3(FB), 0, s, part, nparts, factor, theta, ninv);
+}
+
+// dst = src * (*scale)
+__global__ void k_scale_copy(const double* __restrict__ src, double* __restrict__ dst, int64_t n,
+                             const double* __restrict__ scale) {
+    const int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x;
+    if (i < n) dst[i] = src[i] * *scale;
+}
+
+void launch_scale_copy(const double* src, double* dst, int64_t n, const double* scale, hipStream_t s) {
+    hipLaunchKernelGGL(k_scale_copy, dim3(grid_for(n)), dim3(WG), 0, s, src, dst, n, scale);
 }
 
 // D^-1 <- D^-1 / theta (FP64), and its FP32 copy from the result

@@ -252,6 +252,12 @@ struct tm_hierarchy {
     // the setup scratch of the power estimate (three fine-size vectors, partials)
     double* cheb_theta = nullptr;
     double* pw = nullptr;
+    // warm-started estimates (option cheb_warm_steps): each geometric level's
+    // last estimate vector, scaled to unit length, and the scale factors
+    double* cheb_v = nullptr;
+    std::vector<int64_t> cheb_off;
+    double* cheb_ninv = nullptr;
+    bool cheb_warm = false;        // cheb_v holds the previous design's vectors
     double* elem_a = nullptr;      // setup workspace: element matrices (ping)
     double* elem_b = nullptr;      // (pong)
     size_t bytes = 0;
@@ -309,7 +315,8 @@ inline double first_sweep_weight(const tm_hierarchy* h, int l) {
 constexpr int CHEB_MAX_LEVELS = 64;
 void launch_power_start(double* v, int64_t n, const uint8_t* nmask, int bs, hipStream_t s);
 void launch_power_step(const Level& L, const double* w, const double* v, double* z, double* part, hipStream_t s);
-void launch_cheb_theta(const double* part, int nparts, double factor, double* theta, hipStream_t s);
+void launch_cheb_theta(const double* part, int nparts, double factor, double* theta, double* ninv, hipStream_t s);
+void launch_scale_copy(const double* src, double* dst, int64_t n, const double* scale, hipStream_t s);
 void launch_scale_dinv(Level& L, const double* theta, hipStream_t s);
 
 

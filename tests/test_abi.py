@@ -61,6 +61,8 @@ def _setup_status(nel=(8, 4), nu=0.3, Emin=1e-9, E0=1.0, dofs=(0, 1), **opts):
     (dict(nu_pre=0), "nu_pre"),
     (dict(fine_mfma=2), "fine_mfma"),
     (dict(adapt_iters=-1), "adapt_iters"),
+    (dict(cheb_warm_steps=-1), "cheb_warm_steps"),
+    (dict(cheb_warm_steps=13), "cheb_warm_steps"),
 ])
 def test_setup_rejects_bad_arguments_before_device_work(kw, msg):
     st, err = _setup_status(**kw)
