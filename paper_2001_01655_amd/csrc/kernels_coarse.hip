@@ -327,6 +327,21 @@ template <int NU>
 __host__ __device__ constexpr int pair_order(int t) {
     return t >= 2 * NU ? NU : ((t & 1) ? NU + 1 + t / 2 : NU - 1 - t / 2);
 }
+// every offset once, and the two offsets of a pair read the same row group:
+// the lower one reads row NU-1-o, the upper one row o-NU-1
+template <int NU>
+constexpr bool pair_order_ok() {
+    bool seen[2 * NU + 1] = {};
+    for (int t = 0; t <= 2 * NU; ++t) {
+        const int o = pair_order<NU>(t);
+        if (o < 0 || o > 2 * NU || seen[o]) return false;
+        seen[o] = true;
+    }
+    for (int q = 0; q < NU; ++q)
+        if (NU - 1 - pair_order<NU>(2 * q) != q || pair_order<NU>(2 * q + 1) - NU - 1 != q) return false;
+    return true;
+}
+static_assert(pair_order_ok<13>() && pair_order_ok<4>(), "stencil visiting order");
 
 template <typename T, int DIM, int OP, int G>
 __global__ __launch_bounds__(WG) void k_stencil_op(const T* __restrict__ st, int nx, int ny, int nz,
