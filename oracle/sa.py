@@ -160,19 +160,32 @@ def smoothed_prolongator(A: sp.csr_matrix, T: sp.csr_matrix, bs: int) -> sp.csr_
 
 
 # ------------------------------------------------------------ hybrid
+def level_node_positions(nel, levels: int, h: float = 1.0):
+    """Element counts and per-axis physical node positions of geometric level
+    levels - 1 (the fine grid is level 0): each coarsening takes n elements to
+    ceil(n/2) and puts coarse node I on fine node min(2I, n) of the level
+    above, so an odd count leaves a last coarse element of one fine element."""
+    pos = [h * np.arange(n + 1, dtype=np.float64) for n in nel]
+    cur = list(nel)
+    for _ in range(levels - 1):
+        nxt = [mg.coarse_count(n) for n in cur]
+        pos = [p[np.minimum(2 * np.arange(m + 1), n)] for p, m, n in zip(pos, nxt, cur)]
+        cur = nxt
+    return cur, pos
+
+
 def build_hybrid(nel, E, KE, fixed, n_geometric: int, max_coarse: int = 1000,
                  beta: float = 0.003, omega: float = 0.5, nu_pre: int = 1, nu_post: int = 1,
                  h: float = 1.0, smoother: str = "jacobi", cheb_lower: float = 0.1) -> mg.Hierarchy:
     """n_geometric levels (fine grid included) of geometric coarsening, then
     smoothed aggregation until the level has fewer than max_coarse dofs."""
     dim = len(nel)
-    if any(n % 2 ** (n_geometric - 1) for n in nel):
-        raise ValueError("aggregation is built on an even chain of geometric halvings only")
     Hg = mg.build_geometric(nel, E, KE, fixed, n_geometric, omega, nu_pre, nu_post)
     As, Ps, bss, kinds = list(Hg.A), list(Hg.P), list(Hg.bs), list(Hg.kinds)
     aggs = [None] * len(As)
-    lev_nel = [n // 2 ** (n_geometric - 1) for n in nel]
-    coords = fem.node_coordinates(lev_nel, h * 2 ** (n_geometric - 1))
+    _, pos = level_node_positions(nel, n_geometric, h)
+    grids = np.meshgrid(*[pos[d] for d in reversed(range(dim))], indexing="ij")
+    coords = np.stack([g.ravel() for g in reversed(grids)], axis=1)
     Bcand = fem.rigid_body_modes(coords)
     A, bs = As[-1], dim
     while A.shape[0] >= max_coarse:

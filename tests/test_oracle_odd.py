@@ -76,3 +76,43 @@ def test_odd_hierarchy_solves(dim, nel, L):
     ud = mg.dense_solve(A0, f)
     r = mg.mg_pcg(H, p.loads[0], 1e-10)
     assert np.linalg.norm(r.u - ud) <= 1e-8 * np.linalg.norm(ud)
+
+
+@pytest.mark.parametrize("nel,levels,h", [((13, 7), 3, 1.0), ((9, 5, 7), 3, 0.5), ((33, 17), 4, 2.0)])
+def test_level_node_positions_closed_form(nel, levels, h):
+    """Composing 'coarse node I sits on fine node min(2I, n)' over l levels
+    places node I of level l at h * min(2^l I, n_0)."""
+    from oracle import sa
+    cur, pos = sa.level_node_positions(nel, levels, h)
+    sc = 2 ** (levels - 1)
+    for n0, m, p in zip(nel, cur, pos):
+        assert len(p) == m + 1
+        assert np.array_equal(p, h * np.minimum(sc * np.arange(m + 1), n0).astype(float))
+        assert p[-1] == h * n0                     # the last node stays on the boundary
+
+
+@pytest.mark.parametrize("dim,nel,ngeo,maxc", [(2, (45, 23), 2, 300), (2, (45, 27), 3, 100), (3, (13, 9, 7), 2, 300)])
+def test_hybrid_below_odd_coarsening(dim, nel, ngeo, maxc):
+    """Aggregation on a level reached through odd counts: the tentative
+    prolongator reproduces the rigid-body modes at the level's true node
+    positions, every level is SPD, and PCG matches a dense solve."""
+    from oracle import sa
+    p = synth.small_case(dim, nel, seed=62)
+    KE = fem.element_stiffness(dim, p.nu)
+    E = fem.simp(p.rho, p.p, p.E0, p.Emin)
+    H = sa.build_hybrid(p.nel, E, KE, p.fixed, ngeo, max_coarse=maxc)
+    assert H.kinds[ngeo - 1:] and all(k == "sa" for k in H.kinds[ngeo - 1:])
+    for A in H.A:
+        assert np.linalg.eigvalsh(A.toarray()).min() > 0
+    cur, pos = sa.level_node_positions(p.nel, ngeo, p.h)
+    grids = np.meshgrid(*[pos[d] for d in reversed(range(dim))], indexing="ij")
+    coords = np.stack([g.ravel() for g in reversed(grids)], axis=1)
+    B = fem.rigid_body_modes(coords)
+    T, Bc = sa.tentative(H.aggregates[ngeo - 1], H.P[ngeo - 1].shape[1] // B.shape[1], B, dim)
+    assert np.allclose(T @ Bc, B, atol=1e-12 * np.abs(B).max())
+    A0 = fem.apply_dirichlet(fem.assemble(p.nel, E, KE), p.fixed)
+    f = p.loads[0].copy()
+    f[p.fixed] = 0.0
+    ud = mg.dense_solve(A0, f)
+    r = mg.mg_pcg(H, p.loads[0], 1e-10)
+    assert np.linalg.norm(r.u - ud) <= 1e-8 * np.linalg.norm(ud)
