@@ -116,10 +116,10 @@ tm_status tm_plan_bytes(const tm_mesh* mesh, const tm_options* opts, int32_t n_r
  * SIMP moduli, fine point-block diagonal, geometric Galerkin levels, optional
  * smoothed-aggregation levels, coarsest Cholesky factor (Secs. 2, 3.2, 4).
  * Each geometric coarsening takes an axis of n elements to ceil(n/2) (Sec. 4.3);
- * for odd n the last coarse element is a single fine element.
+ * for odd n the last coarse element is a single fine element (aggregation
+ * levels below such a chain take the rigid-body modes at the true node positions).
  * Errors: TM_ERR_ARG (bad mesh/material/options, an axis that would be coarsened
- * below one element, aggregation levels below an odd-count coarsening, dof id
- * out of range), TM_ERR_NOT_SPD, TM_ERR_OOM.
+ * below one element, dof id out of range), TM_ERR_NOT_SPD, TM_ERR_OOM.
  * rho values are checked on the device (finite and in [0,1]). */
 tm_status tm_setup(const tm_mesh* mesh, const tm_material* mat, const double* rho_dev,
                    const tm_bcs* bcs, const tm_options* opts, void* stream, tm_hierarchy** out);

@@ -241,7 +241,6 @@ static void check_material(const tm_material* m) {
 struct Plan {
     int Lg = 1;
     bool sa = false;
-    bool odd = false;       // some geometric coarsening halves an odd element count
     int L_total = 1;        // known for pure geometric hierarchies
 };
 
@@ -276,12 +275,9 @@ static Plan plan_levels(const tm_mesh* m, const tm_options* o) {
         if (!coarsenable(cur))
             fail(TM_ERR_ARG, "too many geometric levels: an axis would be coarsened below one element");
         for (int d = 0; d < dim; ++d) {
-            if (cur[d] & 1) p.odd = true;
             cur[d] = (cur[d] + 1) / 2;
         }
     }
-    if (p.sa && p.odd)
-        fail(TM_ERR_ARG, "smoothed aggregation after a coarsening of an odd element count is not supported");
     p.L_total = p.Lg;
     return p;
 }
@@ -1443,11 +1439,7 @@ tm_status tm_update_density(tm_hierarchy* h, const double* rho_dev, void* stream
             int Lg = 0;
             for (auto& L : h->lv)
                 if (L.kind != TM_LEVEL_AGGREGATION) ++Lg;
-            // aggregation needs a geometric chain of even halvings (node coordinates)
-            bool odd = false;
-            for (int q = 0; q + 2 < Lg; ++q)
-                for (int d = 0; d < h->dim; ++d) odd = odd || (h->lv[q].nel[d] & 1);
-            if (Lg > 2 && !odd) {
+            if (Lg > 2) {
                 h->lv.resize(Lg - 1);
                 h->sa = true;
             }

@@ -25,7 +25,7 @@ void sa_agg_passes(const int32_t* srp, const int32_t* sci, int64_t n, const uint
 void sa_members(int64_t n, int64_t ng, const int32_t* agg, int32_t* cnt_off, int32_t* cursor, int32_t* mem,
                 int64_t* work, hipStream_t s);
 void sa_tentative(int64_t ng, const int32_t* off, const int32_t* mem, const double* Bprev, int dim, int nx1,
-                  int ny1, double hl, int bs, int k, double* T, double* Bc, hipStream_t s);
+                  int ny1, double h, int level, const int* nel0, int bs, int k, double* T, double* Bc, hipStream_t s);
 double sa_jacobi_bound(const BSR& A, int bs, const double* dinv, unsigned long long* work, hipStream_t s);
 void sa_symbolic(const int32_t* rp1, const int32_t* ci1, const int32_t* agg, const int32_t* rp2,
                  const int32_t* ci2, int32_t ncols, int kind, int64_t nrows, int32_t* cnt, const int32_t* orp,
@@ -135,7 +135,6 @@ void numeric_sa_levels(tm_hierarchy* h, hipStream_t s) {
         }
         const double* Bprev = nullptr;
         int cur = Lg - 1;
-        const double hl = h->mesh.h * (double)(1 << (Lg - 1));
         while (h->lv[cur].n >= h->opt.max_coarse) {
             Pool tmp{tmp_list, tmp_bytes};
             Level& F = h->lv[cur];
@@ -181,7 +180,8 @@ void numeric_sa_levels(tm_hierarchy* h, hipStream_t s) {
             size_t next_bytes = 0;
             Pool nextp{next_list, next_bytes};
             double* Bc = nextp.get<double>((size_t)n_agg * k * k);
-            sa_tentative(n_agg, off, mem, Bprev, dim, F.nn[0], F.nn[1], hl, bs, k, T, Bc, s);
+            sa_tentative(n_agg, off, mem, Bprev, dim, F.nn[0], F.nn[1], h->mesh.h, Lg - 1, h->mesh.nel, bs, k, T, Bc,
+                         s);
             // smoothed prolongator P = T - omega D^-1 A T
             unsigned long long* mx = tmp.get<unsigned long long>(1);
             const double lam = sa_jacobi_bound(F.A, bs, F.dinv64, mx, s);

@@ -323,13 +323,24 @@ __global__ void k_sort_segments(int64_t ng, const int32_t* __restrict__ off, int
     }
 }
 
+// Node positions of geometric level l: each coarsening puts coarse node I on
+// fine node min(2I, n) of the level above, so node I of level l sits on fine
+// node min(2^l I, n0) of its axis (n0 fine elements), at h times that.
+struct LevelPos {
+    double h;
+    int sc;                 // 2^l
+    int n0[3];              // fine elements per axis
+};
+
 // candidate block of node i: first aggregation step = rigid-body modes at the
 // node coordinates of a geometric level, later steps = R factors of the step before
-__device__ __forceinline__ double cand(const double* __restrict__ Bprev, int dim, int nx1, int ny1, double hl,
-                                       int bs, int k, int64_t i, int r, int c) {
+__device__ __forceinline__ double cand(const double* __restrict__ Bprev, int dim, int nx1, int ny1,
+                                       const LevelPos& lp, int bs, int k, int64_t i, int r, int c) {
     if (Bprev) return Bprev[((int64_t)i * bs + r) * k + c];
-    const double x = hl * (double)(i % nx1), y = hl * (double)((i / nx1) % ny1);
-    const double z = dim == 3 ? hl * (double)(i / ((int64_t)nx1 * ny1)) : 0.0;
+    const int64_t ix = i % nx1, iy = (i / nx1) % ny1, iz = dim == 3 ? i / ((int64_t)nx1 * ny1) : 0;
+    const double x = lp.h * (double)min<int64_t>((int64_t)lp.sc * ix, lp.n0[0]);
+    const double y = lp.h * (double)min<int64_t>((int64_t)lp.sc * iy, lp.n0[1]);
+    const double z = dim == 3 ? lp.h * (double)min<int64_t>((int64_t)lp.sc * iz, lp.n0[2]) : 0.0;
     if (c < dim) return r == c ? 1.0 : 0.0;
     if (dim == 2) return r == 0 ? -y : x;                 // (-y, x)
     if (c == 3) return r == 0 ? 0.0 : (r == 1 ? -z : y);   // (0, -z, y)
@@ -339,8 +350,8 @@ __device__ __forceinline__ double cand(const double* __restrict__ Bprev, int dim
 
 // thread per aggregate: modified Gram-Schmidt on its member rows (in place in T)
 __global__ void k_tentative(int64_t ng, const int32_t* __restrict__ off, const int32_t* __restrict__ mem,
-                            const double* __restrict__ Bprev, int dim, int nx1, int ny1, double hl, int bs, int k,
-                            double* __restrict__ T, double* __restrict__ Bc) {
+                            const double* __restrict__ Bprev, int dim, int nx1, int ny1, const LevelPos lp, int bs,
+                            int k, double* __restrict__ T, double* __restrict__ Bc) {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= ng) return;
     const int32_t p0 = off[g], p1 = off[g + 1];
@@ -348,7 +359,7 @@ __global__ void k_tentative(int64_t ng, const int32_t* __restrict__ off, const i
     for (int32_t p = p0; p < p1; ++p) {
         const int64_t i = mem[p];
         for (int r = 0; r < bs; ++r)
-            for (int c = 0; c < k; ++c) T[((int64_t)i * bs + r) * k + c] = cand(Bprev, dim, nx1, ny1, hl, bs, k, i, r, c);
+            for (int c = 0; c < k; ++c) T[((int64_t)i * bs + r) * k + c] = cand(Bprev, dim, nx1, ny1, lp, bs, k, i, r, c);
     }
     double R[6][6];
     for (int a = 0; a < 6; ++a)
@@ -671,9 +682,10 @@ void sa_members(int64_t n, int64_t ng, const int32_t* agg, int32_t* cnt_off, int
     hipLaunchKernelGGL(k_sort_segments, dim3(grid_for(ng)), dim3(WG), 0, s, ng, (const int32_t*)cnt_off, mem);
 }
 void sa_tentative(int64_t ng, const int32_t* off, const int32_t* mem, const double* Bprev, int dim, int nx1,
-                  int ny1, double hl, int bs, int k, double* T, double* Bc, hipStream_t s) {
+                  int ny1, double h, int level, const int* nel0, int bs, int k, double* T, double* Bc, hipStream_t s) {
+    LevelPos lp{h, 1 << level, {nel0[0], nel0[1], dim == 3 ? nel0[2] : 0}};
     hipLaunchKernelGGL(k_tentative, dim3(grid_for(ng, 64)), dim3(64), 0, s, ng, off, mem, Bprev, dim, nx1, ny1,
-                       hl, bs, k, T, Bc);
+                       lp, bs, k, T, Bc);
 }
 double sa_jacobi_bound(const BSR& A, int bs, const double* dinv, unsigned long long* work, hipStream_t s) {
     TM_HIP(hipMemsetAsync(work, 0, sizeof(unsigned long long), s));

@@ -15,13 +15,17 @@ CASES = [
     ("bridge", (32, 16, 16), 2, 1000),
     ("bridge", (32, 16, 16), 3, 300),
     ("small2d", (64, 32), 2, 300),
+    # aggregation below odd-count coarsenings (rigid-body modes at the true node positions)
+    ("small2d", (45, 23), 2, 300),
+    ("small2d", (45, 27), 3, 100),
+    ("small3d", (13, 9, 7), 2, 300),
 ]
 
 
 def _problem(kind, nel):
     if kind == "bridge":
         return synth.bridge_3d(nel=nel)
-    return synth.small_case(2, nel, seed=31)
+    return synth.small_case(len(nel), nel, seed=31)
 
 
 def _pair(kind, nel, ngeo, maxc, vfp=64):
