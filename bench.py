@@ -416,6 +416,49 @@ def eigen_leg(reps: int = 3):
     return out
 
 
+def stability_stream_leg(n_designs: int = 4):
+    """The stability workflow over a stream of designs (Sec. 2 / Sec. 4 column
+    example): the 256x1024 column starting from the prismatic design, each next
+    design a seeded smooth perturbation (rho + 0.05 G(N(0,1)), clipped to
+    [1e-3, 1]); per design: density update, displacement solve warm-started
+    from the previous u (rtol 1e-8), stress stiffness, six eigenpairs by
+    generalized Davidson started from the previous design's eigenvectors plus
+    four seeded vectors (Sec. 4: previous eigenvectors as the initial search
+    space), and, for comparison, from ten seeded vectors."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2001_01655_amd import Hierarchy
+    p = synth.column_2d(uniform=True)
+    seq = synth.design_sequence(p.rho, p.nel, seed=7)
+    H = Hierarchy(p.nel, p.rho, p.fixed, p=p.p, E0=p.E0, Emin=p.Emin, nu=p.nu, n_levels=5, omega=0.5,
+                  nu_pre=1, nu_post=1, vcycle_fp=32)
+    f = torch.tensor(p.loads[0], device="cuda")
+    rng = np.random.default_rng(11)
+    cold = rng.standard_normal((10, p.n_dof))
+    cold[:, p.fixed] = 0.0
+    cold = torch.tensor(cold, device="cuda")
+    u, phi, out = None, None, []
+    for t in range(n_designs):
+        if t > 0:
+            H.update_density(torch.tensor(seq(t), device="cuda"))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = H.solve(f, rtol=1e-8, u0=u)
+        u = r.u
+        H.stress_stiffness(u)
+        v0 = cold if phi is None else torch.cat([phi, cold[:4]])
+        lam, phi, it, nc, st = H.eigs(v0, nev=6)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        lam_c, _, it_c, nc_c, _ = H.eigs(cold, nev=6, want_vectors=False)
+        out.append({"design": t, "solve_iters": int(r.iters[0]), "eig_iters": int(it), "eig_iters_cold_start": int(it_c),
+                    "n_conv": int(nc), "lambda1": float(f"{lam[0]:.8g}"), "ms_solve_and_eigs": round(dt * 1e3, 1)})
+    H.close()
+    return {"designs": out, "workload": "2D column 256x1024, prismatic start then seeded perturbations, GMG5"}
+
+
 def filter_leg(nel, reps: int = 50):
     """tm_density_filter (radius 1.5) on the workload's element grid: mean time
     per launch from events around reps back-to-back calls of the C function on
@@ -537,6 +580,7 @@ def main():
     if not args.no_side_legs:
         line["density_filter"] = filter_leg(p.nel)
         line["eigen"] = eigen_leg()
+        line["stability_stream"] = stability_stream_leg()
     if not args.no_fp64:
         H64, t64s = build(64, 1)
         k64 = max(1, args.steps // 2)
