@@ -271,3 +271,23 @@ def test_eigs_degenerate_and_largest_space():
     assert sta == 0 and stb == 0 and np.allclose(a, b, rtol=1e-8)
     print(f"  j_max 25: {ita} expansions, j_max 32: {itb}", flush=True)
     H.close()
+
+
+def test_eigs_restart_from_previous_eigenvectors():
+    """Start vectors = converged eigenvectors (plus seeded ones): the same six
+    eigenvalues after far fewer expansions; start vectors given in any scale
+    and with entries on supported dofs (ignored) work the same."""
+    p = synth.column_2d(nel=(8, 32), seed=2)
+    H = _hier(p, 3)
+    r = H.solve(torch.tensor(p.loads[0], device="cuda"), rtol=1e-13)
+    H.stress_stiffness(r.u)
+    V0 = torch.tensor(_start(p.n_dof, 10, p.fixed, 0).T.copy(), device="cuda")
+    lam, Phi, it, nc, st = H.eigs(V0, nev=6, precond_fp=64)
+    assert st == 0
+    warm = torch.cat([Phi * 3.0, V0[:4]])
+    warm[:, torch.tensor(p.fixed, device="cuda")] = 1.0          # ignored by the solver
+    lam2, _, it2, nc2, st2 = H.eigs(warm, nev=6, precond_fp=64)
+    print(f"  cold {it} expansions, from the eigenvectors {it2}", flush=True)
+    assert st2 == 0 and nc2 == 6 and np.allclose(lam2, lam, rtol=1e-8)
+    assert it2 <= it // 4
+    H.close()
