@@ -41,7 +41,7 @@ __global__ __launch_bounds__(WG) void k_gsig_assemble(const double* __restrict__
                                                       double p, double E0, double rho_min, double lam, double mu,
                                                       double h, int nx, int ny, int nz, int cx, int cy, int cz,
                                                       double* __restrict__ G, int64_t n_nodes) {
-    constexpr int NPE = 1 << DIM, NST = DIM == 3 ? 27 : 9;
+    constexpr int NPE = 1 << DIM;
     // elements of colour (cx, cy, cz): ex = 2 i + cx, ...
     const int hx = (nx - cx + 1) / 2, hy = (ny - cy + 1) / 2, hz = DIM == 3 ? (nz - cz + 1) / 2 : 1;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -126,7 +126,6 @@ __global__ __launch_bounds__(WG) void k_gsig_assemble(const double* __restrict__
             double* dst = G + (int64_t)o * n_nodes + nd[a];
             *dst = *dst - v;
         }
-    (void)NST;
 }
 
 void launch_gsig_assemble(const tm_hierarchy* h, const double* u, double rho_min, double* G, hipStream_t s) {

@@ -342,10 +342,6 @@ __global__ __launch_bounds__(WG) void k_fine3z2(const T* __restrict__ E, const K
     const bool two = k + 1 < NZ;                        // the upper node exists
     const uint32_t nd0 = k * PL + j * NX + i;
     const uint32_t nd1 = two ? nd0 + PL : nd0;
-    const uint32_t ox[3] = {i ? 0u - 1u : 0u, 0u, i + 1 < NX ? 1u : 0u};
-    const uint32_t oy[3] = {j ? 0u - NX : 0u, 0u, j + 1 < NY ? NX : 0u};
-    (void)ox;
-    (void)oy;
     constexpr uint32_t NB = 3u * sizeof(T);
     uint32_t nb0 = nd0 * NB;
     asm volatile("" : "+v"(nb0));
