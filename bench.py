@@ -46,7 +46,8 @@ def workload_label(wl, args, levels, coarsest):
 
 
 # MI355X published peaks (dense): HBM3E 8 TB/s; vector FP64 78.6 TFLOP/s; vector
-# FP32 157.3 TFLOP/s (reached only with packed FP32, which this build does not use)
+# FP32 157.3 TFLOP/s (reached only with packed FP32 instructions, which these
+# kernels are compiled without)
 PEAK = {"hbm_GBs": 8000.0, "fp64_TFs": 78.6, "fp32_TFs": 157.3}
 KERNEL_SOURCES = {0: ["kernels_fine.hip", "tm_device.h"], 1: ["kernels_fine.hip", "tm_device.h"],
                   2: ["kernels_coarse.hip", "tm_device.h"]}

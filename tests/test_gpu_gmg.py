@@ -139,9 +139,6 @@ def test_solve_vs_oracle(dim, nel, L, vfp):
         e = np.linalg.norm(U[k] - ref.u) / np.linalg.norm(ref.u)
         ce = abs(r.compliance[k] - ref.compliance) / abs(ref.compliance)
         _say(f"  rhs {k}: iters={r.iters[k]} (oracle {ref.iters}) err_u={e:.2e} err_c={ce:.2e}")
-        with open("gpurun_out/solve_parity.txt", "a") as fh:
-            fh.write(f"{nel} vfp={vfp} rhs={k} iters={r.iters[k]} oracle_iters={ref.iters} "
-                     f"err_u={e:.3e} err_c={ce:.3e}\n")
         assert e <= 1e-7 and ce <= 1e-9
     G.close()
 
