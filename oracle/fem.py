@@ -196,6 +196,50 @@ def apply_dirichlet(K: sp.csr_matrix, fixed: np.ndarray) -> sp.csr_matrix:
     return Kt
 
 
+def assemble_dirichlet_blocked(nel, E: np.ndarray, KE: np.ndarray, fixed: np.ndarray,
+                               planes_per_block: int = 8) -> sp.csr_matrix:
+    """K~ = M K M + (I - M) built in slabs of node planes along the slowest axis,
+    so that only one slab's element contributions are held at a time (the
+    one-shot assembly of a 5.4M-dof grid needs more host memory than a
+    workstation has).  Each slab takes the element layers that touch its
+    node planes, keeps the contributions whose row lies in the slab, drops the
+    off-diagonal entries of supported rows and columns and puts a single unit
+    diagonal on supported rows; the slabs are stacked in row order.  Every
+    stored entry is the sum of the same element terms as in assemble() +
+    apply_dirichlet()."""
+    dim = len(nel)
+    ed = element_dofs(nel)
+    nd = ed.shape[1]
+    n = dim * int(np.prod(n_nodes_axis(nel)))
+    m = free_mask(n, fixed)
+    plane_dofs = dim * int(np.prod([k + 1 for k in nel[:-1]]))
+    el_layer = int(np.prod(nel[:-1]))
+    n_planes = nel[-1] + 1
+    blocks = []
+    for p0 in range(0, n_planes, planes_per_block):
+        p1 = min(p0 + planes_per_block, n_planes)
+        e0, e1 = max(p0 - 1, 0) * el_layer, min(p1, nel[-1]) * el_layer
+        sub = ed[e0:e1]
+        rows = np.repeat(sub, nd, axis=1).ravel()
+        cols = np.tile(sub, (1, nd)).ravel()
+        vals = (E[e0:e1, None, None] * KE[None, :, :]).ravel()
+        r0, r1 = p0 * plane_dofs, p1 * plane_dofs
+        keep = (rows >= r0) & (rows < r1) & (m[rows] > 0) & (m[cols] > 0)
+        rows, cols, vals = rows[keep], cols[keep], vals[keep]
+        fx = np.nonzero(m[r0:r1] == 0)[0] + r0
+        rows = np.concatenate([rows, fx])
+        cols = np.concatenate([cols, fx])
+        vals = np.concatenate([vals, np.ones(fx.shape[0])])
+        B = sp.coo_matrix((vals, (rows - r0, cols)), shape=(r1 - r0, n)).tocsr()
+        B.sum_duplicates()
+        B.sort_indices()
+        blocks.append(B)
+        del rows, cols, vals, keep
+    K = sp.vstack(blocks, format="csr")
+    K.sort_indices()
+    return K
+
+
 def apply_matfree(nel, E: np.ndarray, KE: np.ndarray, fixed: np.ndarray,
                   x: np.ndarray, chunk: int = 1 << 18) -> np.ndarray:
     """y = K~ x = M (sum_e E_e L_e^T KE L_e) M x + (I - M) x, element by element."""

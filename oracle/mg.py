@@ -105,9 +105,21 @@ def structural_add(A: sp.spmatrix, B: sp.spmatrix) -> sp.csr_matrix:
     return out
 
 
-def galerkin(P: sp.spmatrix, A: sp.spmatrix) -> sp.csr_matrix:
-    """A_c = P^T (A P), structural pattern; exactly-zero diagonals set to 1."""
-    Ac = structural_matmul(sp.csr_matrix(P.T), structural_matmul(A, P))
+def galerkin(P: sp.spmatrix, A: sp.spmatrix, block_rows: Optional[int] = None) -> sp.csr_matrix:
+    """A_c = P^T (A P), structural pattern; exactly-zero diagonals set to 1.
+    With `block_rows`, the product is summed over row blocks b of A and P,
+    A_c = sum_b P_b^T (A_b P), so that only one block's A P is held at a time
+    (same pattern; the sums are associated by block)."""
+    if block_rows is None or block_rows >= A.shape[0]:
+        Ac = structural_matmul(sp.csr_matrix(P.T), structural_matmul(A, P))
+    else:
+        A = sp.csr_matrix(A)
+        P = sp.csr_matrix(P)
+        Ac = None
+        for r0 in range(0, A.shape[0], block_rows):
+            r1 = min(r0 + block_rows, A.shape[0])
+            part = structural_matmul(sp.csr_matrix(P[r0:r1].T), structural_matmul(A[r0:r1], P))
+            Ac = part if Ac is None else structural_add(Ac, part)
     d = Ac.diagonal()
     if np.any(d == 0.0):
         Ac = Ac.tolil()
@@ -210,11 +222,15 @@ class Hierarchy:
 def build_geometric(nel, E: np.ndarray, KE: np.ndarray, fixed: np.ndarray, L: int,
                     omega: float = 0.5, nu_pre: int = 1, nu_post: int = 1,
                     point_jacobi: bool = False, smoother: str = "jacobi",
-                    cheb_lower: float = 0.1) -> Hierarchy:
-    """Pure geometric hierarchy with L levels (fine grid included)."""
+                    cheb_lower: float = 0.1, lean: bool = False) -> Hierarchy:
+    """Pure geometric hierarchy with L levels (fine grid included).  `lean`
+    assembles K~ in slabs and forms the Galerkin products in row blocks (same
+    operators, for grids whose one-shot products do not fit in host memory)."""
     dim = len(nel)
-    K = fem.assemble(nel, E, KE)
-    A0 = fem.apply_dirichlet(K, fixed)
+    if lean:
+        A0 = fem.assemble_dirichlet_blocked(nel, E, KE, fixed)
+    else:
+        A0 = fem.apply_dirichlet(fem.assemble(nel, E, KE), fixed)
     As, Ps = [A0], []
     cur = list(nel)
     for l in range(L - 1):
@@ -222,7 +238,7 @@ def build_geometric(nel, E: np.ndarray, KE: np.ndarray, fixed: np.ndarray, L: in
             raise ValueError(f"element counts {cur} cannot be coarsened at level {l}")
         P = geometric_prolongator(tuple(cur), fixed if l == 0 else None)
         Ps.append(P)
-        As.append(galerkin(P, As[-1]))
+        As.append(galerkin(P, As[-1], block_rows=(1 << 20) if lean else None))
         cur = [coarse_count(n) for n in cur]
     return finish(As, Ps, [dim] * L, omega, nu_pre, nu_post, point_jacobi, ["geo"] * (L - 1),
                   smoother=smoother, cheb_lower=cheb_lower, fixed=fixed)

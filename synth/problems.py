@@ -292,6 +292,16 @@ def poisson_arrivals(n: int, rate_per_s: float, seed: int = 5) -> np.ndarray:
     return np.cumsum(rng.exponential(1.0 / rate_per_s, size=n))
 
 
+# ------------------------------------------------------------- test vectors
+def seeded_vector(n: int, seed: int, fixed=None) -> np.ndarray:
+    """n standard-normal values from default_rng(seed), zero on the `fixed`
+    dofs if given: the input vectors of the sampled parity cases."""
+    v = np.random.default_rng(seed).standard_normal(n)
+    if fixed is not None:
+        v[np.asarray(fixed, dtype=np.int64)] = 0.0
+    return v
+
+
 # ------------------------------------------------------------- small cases
 def small_case(dim: int, nel, seed: int = 11, contrast: bool = True,
                support: str = "clamp", n_rhs: int = 1) -> Problem:

@@ -200,3 +200,19 @@ def test_sensitivity_homogeneity():
     dc = fem.compliance_sensitivity(nel, rho, 3.0, 1.0, 0.0, KE, u)
     assert abs(rho @ dc + 3.0 * c) <= 1e-10 * abs(c)
     assert np.all(dc <= 0.0)
+
+
+@pytest.mark.parametrize("nel,ppb", [((13, 7), 3), ((5, 4, 6), 2), ((6, 3, 4), 8)])
+def test_blocked_assembly_equals_one_shot(nel, ppb):
+    """The slab-by-slab K~ is the one-shot assemble + apply_dirichlet: the same
+    pattern, and each entry the sum of the same (at most 2^dim) element terms,
+    up to the order in which the sparse conversion adds them."""
+    p = synth.small_case(len(nel), nel, seed=41)
+    KE = fem.element_stiffness(p.dim, p.nu)
+    E = fem.simp(p.rho, p.p, p.E0, p.Emin)
+    A = fem.apply_dirichlet(fem.assemble(p.nel, E, KE), p.fixed)
+    B = fem.assemble_dirichlet_blocked(p.nel, E, KE, p.fixed, planes_per_block=ppb)
+    assert np.array_equal(A.indptr, B.indptr) and np.array_equal(A.indices, B.indices)
+    absK = fem.assemble(p.nel, E, np.abs(KE))          # bound on each entry's terms
+    bound = 8 * np.finfo(float).eps * np.abs(fem.apply_dirichlet(absK, p.fixed).data)
+    assert np.all(np.abs(A.data - B.data) <= bound)

@@ -192,3 +192,50 @@ def test_chebyshev_vcycle_spd_and_mbb(nu):
     r = mg.mg_pcg(H, p.loads[0], 1e-10)
     assert r.converged
     assert np.linalg.norm(r.u - ud) <= 1e-8 * np.linalg.norm(ud)
+
+
+def test_block_diag_inverse_hand_built():
+    """Point-block inverse on a matrix whose blocks are inverted by hand: the
+    off-diagonal blocks are ignored, a non-symmetric block catches a transposed
+    fill, and each stored block times A's diagonal block is the identity."""
+    A = np.zeros((8, 8))
+    A[0:3, 0:3] = [[4, 1, 0], [1, 3, 1], [0, 1, 2]]        # det 18 (cofactor expansion)
+    A[3:6, 3:6] = np.diag([2.0, 5.0, 0.5])
+    A[0, 3] = A[3, 0] = 7.0                                 # coupling between blocks 0 and 1
+    A[2, 5] = A[5, 2] = -3.0
+    A = sp.csr_matrix(A[:6, :6])
+    D = mg.block_diag_inverse(A, 3).toarray()
+    inv0 = np.array([[5, -2, 1], [-2, 8, -4], [1, -4, 11]]) / 18.0   # adjugate / det
+    np.testing.assert_allclose(D[0:3, 0:3], inv0, rtol=0, atol=1e-15)
+    np.testing.assert_allclose(D[3:6, 3:6], np.diag([0.5, 0.2, 2.0]), rtol=0, atol=1e-15)
+    assert np.all(D[0:3, 3:6] == 0) and np.all(D[3:6, 0:3] == 0)
+    for b in range(2):
+        s = slice(3 * b, 3 * b + 3)
+        np.testing.assert_allclose(D[s, s] @ A.toarray()[s, s], np.eye(3), atol=1e-14)
+    # a non-symmetric 2x2 block: [[1, 2], [0, 1]]^-1 = [[1, -2], [0, 1]]
+    B = sp.csr_matrix(np.array([[1.0, 2.0, 9.0, 0.0], [0.0, 1.0, 0.0, 0.0],
+                                [9.0, 0.0, 4.0, 0.0], [0.0, 0.0, 0.0, 8.0]]))
+    DB = mg.block_diag_inverse(B, 2).toarray()
+    np.testing.assert_array_equal(DB[0:2, 0:2], [[1.0, -2.0], [0.0, 1.0]])
+    np.testing.assert_array_equal(DB[2:4, 2:4], [[0.25, 0.0], [0.0, 0.125]])
+    assert np.all(DB[0:2, 2:4] == 0)
+
+
+@pytest.mark.parametrize("nel,rows", [((14, 10), 37), ((6, 4, 6), 100)])
+def test_blocked_galerkin_equals_one_shot(nel, rows):
+    """P^T A P summed over row blocks has the one-shot pattern and values (to the
+    rounding of the re-associated sums)."""
+    p = synth.small_case(len(nel), nel, seed=42)
+    KE = fem.element_stiffness(p.dim, p.nu)
+    E = fem.simp(p.rho, p.p, p.E0, p.Emin)
+    A = fem.apply_dirichlet(fem.assemble(p.nel, E, KE), p.fixed)
+    P = mg.geometric_prolongator(p.nel, p.fixed)
+    G1 = mg.galerkin(P, A)
+    G2 = mg.galerkin(P, A, block_rows=rows)
+    assert np.array_equal(G1.indptr, G2.indptr) and np.array_equal(G1.indices, G2.indices)
+    assert np.max(np.abs(G1.data - G2.data)) <= 1e-14 * np.max(np.abs(G1.data))
+    H1 = mg.build_geometric(p.nel, E, KE, p.fixed, 3)
+    H2 = mg.build_geometric(p.nel, E, KE, p.fixed, 3, lean=True)
+    for a, b in zip(H1.A, H2.A):
+        assert np.array_equal(a.indices, b.indices)
+        assert np.max(np.abs(a.data - b.data)) <= 1e-14 * np.max(np.abs(a.data))

@@ -220,3 +220,28 @@ def test_hybrid_solve_matches_direct():
     ud = mg.dense_solve(H.A[0], p.loads[0])
     assert np.linalg.norm(r.u - ud) <= 1e-6 * np.linalg.norm(ud)
     assert abs(r.compliance - p.loads[0] @ ud) <= 1e-10 * abs(p.loads[0] @ ud)
+
+
+def test_jacobi_weight_hand_computed():
+    """omega = (4/3) / ||D^-1 A||_inf on a 4x4 matrix with 2x2 point blocks,
+    D^-1 A and its row sums worked out by hand:
+      block 0 = [[4, 1], [1, 2]], inverse [[2, -1], [-1, 4]] / 7;
+      block 1 = diag(3, 4), inverse diag(1/3, 1/4);
+      D^-1 A rows: [7, 0, 4, 2]/7, [0, 7, -2, -8]/7, [2/3, 0, 1, 0], [0, -1/2, 0, 1];
+      absolute row sums 13/7, 17/7, 5/3, 3/2, so omega = (4/3)(7/17) = 28/51.
+    Point Jacobi (diag A) would give rows summing to 7/4, 5/2, 5/3, 3/2 and
+    omega 8/15; a halved weight 14/51."""
+    A = sp.csr_matrix(np.array([[4.0, 1.0, 2.0, 0.0],
+                                [1.0, 2.0, 0.0, -2.0],
+                                [2.0, 0.0, 3.0, 0.0],
+                                [0.0, -2.0, 0.0, 4.0]]))
+    Dinv = mg.block_diag_inverse(A, 2)
+    DA = np.array([[1.0, 0.0, 4 / 7, 2 / 7],
+                   [0.0, 1.0, -2 / 7, -8 / 7],
+                   [2 / 3, 0.0, 1.0, 0.0],
+                   [0.0, -0.5, 0.0, 1.0]])
+    np.testing.assert_allclose((Dinv @ A).toarray(), DA, rtol=0, atol=1e-15)
+    w = sa.jacobi_weight(A, Dinv)
+    assert abs(w - 28.0 / 51.0) <= 1e-15
+    # the weight is fixed by the block inverse: point Jacobi gives another value
+    assert abs(sa.jacobi_weight(A, mg.point_diag_inverse(A)) - 8.0 / 15.0) <= 1e-15
