@@ -100,6 +100,11 @@ typedef struct {
                               runs this many steps (1..12) instead of 12 from the fixed start;
                               aggregation levels and the first setup always start cold.
                               0 (default): every setup runs 12 steps from the fixed start     */
+    int32_t stencil_kernel; /* operator kernel of the geometric coarse levels: 0 (default) by
+                              level size (levels of at least 256 workgroups of nodes take the
+                              large-level kernel, smaller ones the latency-bound form); 1: the
+                              large-level kernel on every level; 2: the small-level form on
+                              every level.  Same operator either way                        */
 } tm_options;
 
 typedef struct tm_hierarchy tm_hierarchy;       /* opaque */

@@ -43,7 +43,8 @@ class tm_options(C.Structure):
                 ("omega", C.c_double), ("sa_beta", C.c_double), ("vcycle_fp", C.c_int32),
                 ("outer", C.c_int32), ("max_iters", C.c_int32), ("check_every", C.c_int32),
                 ("fine_mfma", C.c_int32), ("cheb_lower", C.c_double),
-                ("adapt_iters", C.c_int32), ("cheb_warm_steps", C.c_int32)]
+                ("adapt_iters", C.c_int32), ("cheb_warm_steps", C.c_int32),
+                ("stencil_kernel", C.c_int32)]
 
 
 class tm_eig_options(C.Structure):

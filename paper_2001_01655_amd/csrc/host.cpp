@@ -226,6 +226,7 @@ static void check_opts(const tm_options* o) {
     if (o->max_iters < 1) fail(TM_ERR_ARG, "max_iters must be >= 1");
     if (o->check_every < 0) fail(TM_ERR_ARG, "check_every must be >= 0");
     if (o->fine_mfma != 0 && o->fine_mfma != 1) fail(TM_ERR_ARG, "fine_mfma must be 0 or 1");
+    if (o->stencil_kernel < 0 || o->stencil_kernel > 2) fail(TM_ERR_ARG, "stencil_kernel must be 0, 1 or 2");
     if (o->n_levels > 0 && o->n_geometric > o->n_levels) fail(TM_ERR_ARG, "n_geometric > n_levels");
 }
 
@@ -279,6 +280,22 @@ static Plan plan_levels(const tm_mesh* m, const tm_options* o) {
         }
     }
     p.L_total = p.Lg;
+    // The operator kernels address the fine vectors and moduli and the first
+    // coarse level's stored stencil through buffer descriptors, whose range is
+    // below 2 GiB, with 32-bit byte offsets: refuse a mesh whose FP64 copies
+    // of those arrays would reach 2 GiB (deeper levels are 8x smaller each).
+    const int64_t lim = (int64_t)1 << 31;
+    const int64_t nodes0 = nodes_of(m->nel, dim);
+    const int64_t n_el = (int64_t)m->nel[0] * m->nel[1] * (dim == 3 ? m->nel[2] : 1);
+    if (nodes0 * dim * 8 >= lim || n_el * 8 >= lim)
+        fail(TM_ERR_ARG, "mesh too large: an FP64 fine-level vector must stay below 2 GiB (buffer range)");
+    if (p.Lg > 1) {
+        int c1[3] = {(m->nel[0] + 1) / 2, (m->nel[1] + 1) / 2, dim == 3 ? (m->nel[2] + 1) / 2 : 1};
+        const int bb = dim * dim, nst = dim == 3 ? 27 : 9, nq = (nst - 1) / 2 * bb + dim * (dim + 1) / 2;
+        if (nodes_of(c1, dim) * nq * 8 >= lim)
+            fail(TM_ERR_ARG, "mesh too large: the first coarse level's FP64 stencil must stay below 2 GiB "
+                             "(buffer range)");
+    }
     return p;
 }
 
@@ -314,6 +331,7 @@ static void alloc_level_geo(tm_hierarchy* h, Level& L, int l) {
         L.nst = dim == 3 ? 27 : 9;
         L.st64 = halloc<double>(h, (size_t)L.nst * bb * L.n_nodes);
         L.nq = (L.nst - 1) / 2 * bb + dim * (dim + 1) / 2;
+        L.op_kernel = h->opt.stencil_kernel;
         L.stc64 = halloc<double>(h, (size_t)L.nq * L.n_nodes);
         L.stc32 = halloc<float>(h, (size_t)L.nq * L.n_nodes);
     }
@@ -1277,6 +1295,7 @@ void tm_default_options(tm_options* o) {
     o->cheb_lower = 0.1;
     o->adapt_iters = 0;
     o->cheb_warm_steps = 0;
+    o->stencil_kernel = 0;
 }
 
 const char* tm_status_string(tm_status s) {

@@ -584,8 +584,10 @@ template <typename T, int DIM>
 static void stencil_dispatch(const Level& L, int op, const T* x, const T* b, T* y, T omega,
                              const int* done, hipStream_t s, const ChebArgs& ch) {
     // fewer workgroups than compute units: latency-bound; 3D splits each
-    // node over 4 lanes, 2D batches all nine neighbours
-    if (grid_for(L.n_nodes) < 256) {
+    // node over 4 lanes, 2D batches all nine neighbours (the level's
+    // op_kernel can pin either form, whatever the size)
+    const bool small = L.op_kernel == 0 ? grid_for(L.n_nodes) < 256 : L.op_kernel == 2;
+    if (small) {
         if constexpr (DIM == 3)
             stencil_split_launch<T, DIM, 4>(L, op, x, b, y, omega, done, s, ch);
         else

@@ -174,6 +174,7 @@ struct Level {
     // triangle of the diagonal block; the other blocks are transposes of the
     // neighbours' stored ones
     int nq = 0;
+    int op_kernel = 0;            // stencil operator kernel: 0 by size, 1 large-level, 2 small-level
     double* stc64 = nullptr;
     float* stc32 = nullptr;
     // aggregation level operator

@@ -62,6 +62,7 @@ def _setup_status(nel=(8, 4), nu=0.3, Emin=1e-9, E0=1.0, dofs=(0, 1), **opts):
     (dict(adapt_iters=-1), "adapt_iters"),
     (dict(cheb_warm_steps=-1), "cheb_warm_steps"),
     (dict(cheb_warm_steps=13), "cheb_warm_steps"),
+    (dict(stencil_kernel=3), "stencil_kernel"),
 ])
 def test_setup_rejects_bad_arguments_before_device_work(kw, msg):
     st, err = _setup_status(**kw)
@@ -121,3 +122,22 @@ def test_density_filter_rejects_bad_arguments_before_device_work(radius, transpo
     assert st == L.TM_ERR_ARG
     assert msg in L.LIB.tm_last_error().decode()
     assert L.LIB.tm_density_filter(C.byref(mesh), 1.5, 0, None, b, None) == L.TM_ERR_ARG
+
+
+def test_plan_refuses_meshes_past_the_buffer_range():
+    """Operator kernels address the fine vectors and the first coarse level's
+    stencil through buffer descriptors (range below 2 GiB): a 3D mesh whose
+    level-1 FP64 stencil (123 values per node) reaches 2 GiB is refused by both
+    admission and setup; the largest that fits is accepted."""
+    o = L.default_options(n_levels=6)
+    ok = L.make_mesh((256, 256, 256))          # level 1: 129^3 nodes * 984 B = 2.11e9 B
+    assert tm.tm_plan_bytes(ok, o, 1) > 0
+    big = L.make_mesh((264, 264, 264))         # level 1: 133^3 nodes * 984 B = 2.31e9 B
+    with pytest.raises(tm.TmError) as e:
+        tm.tm_plan_bytes(big, o, 1)
+    assert e.value.status == L.TM_ERR_ARG and "2 GiB" in str(e.value)
+    st, err = _setup_status(nel=(264, 264, 264), n_levels=6)
+    assert st == L.TM_ERR_ARG and "2 GiB" in err
+    # a 2D fine grid whose FP64 vector reaches 2 GiB (dofs of 8 B >= 2^31 B)
+    with pytest.raises(tm.TmError):
+        tm.tm_plan_bytes(L.make_mesh((11600, 11600)), L.default_options(n_levels=2), 1)
