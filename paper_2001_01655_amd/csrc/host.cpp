@@ -871,8 +871,14 @@ static tm_status finish_state(tm_solve_state* st, int32_t* iters, double* compli
         if (compliance) compliance[k] = c.zq;
         if (relres) relres[k] = c.ff > 0.0 ? std::sqrt(c.pq / c.ff) : 0.0;
         const tm_status stt = (tm_status)c.status;
-        if (stt < 0) worst = stt;
-        else if (stt == TM_NOT_CONVERGED && worst == TM_OK) worst = TM_NOT_CONVERGED;
+        if (stt < 0) {
+            worst = stt;
+            set_error("right-hand side " + std::to_string(k) + " at iteration " + std::to_string(c.iter) + ": " +
+                      (stt == TM_ERR_ARG ? "load or start vector not finite"
+                                         : "breakdown (p^T K p <= 0, z^T r <= 0 or a non-finite value)"));
+        } else if (stt == TM_NOT_CONVERGED && worst == TM_OK) {
+            worst = TM_NOT_CONVERGED;
+        }
     }
     st->ended = true;
     return worst;

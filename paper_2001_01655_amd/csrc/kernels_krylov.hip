@@ -190,6 +190,11 @@ __global__ __launch_bounds__(FB) void k_init_scalars(KScal* sc, const double* pa
         sc->outer = outer;
         sc->status = TM_OK;
         sc->done = (rr <= sc->rr_stop) ? 1 : 0;
+        if (!(ff - ff == 0.0) || !(rr - rr == 0.0)) {
+            // a load or start vector with an infinity or a NaN: nothing to iterate on
+            sc->status = TM_ERR_ARG;
+            sc->done = 1;
+        }
         sc->alpha = sc->beta = 0.0;
         sc->zr_old = 1.0;
     }

@@ -1,0 +1,112 @@
+"""Write the oracle's reference solutions of the full-size configurations.
+
+    python tests/golden/make_golden.py <case> [<case> ...]      # or: all
+
+Calls only the oracle (oracle/) and the seeded input generator (synth/).  For
+each case it builds the oracle's FP64 hierarchy on assembled CSR, solves
+K~ u = M f by multigrid-preconditioned CG to a relative residual of 1e-12,
+and writes solve_<case>.json beside this script with:
+  * compliance f^T u, ||u||_2, max |u|, the oracle's iterations and its true
+    relative residual ||M f - K~ u|| / ||M f||;
+  * u at 4096 seeded free dofs (the dof ids are stored with the values);
+  * a fingerprint of the inputs (sums of densities and loads, dof count), so a
+    change of the generator is caught before values are compared;
+  * the command line that produced the file.
+u is unique (K~ is SPD), so the preconditioner the oracle uses here only
+changes how fast it gets there; it is chosen per case for speed.
+"""
+from __future__ import annotations
+
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import synth  # noqa: E402
+from oracle import fem, mg, sa  # noqa: E402
+
+RTOL = 1e-12
+N_SAMPLES = 4096
+
+# case -> (problem factory, hierarchy recipe for the oracle)
+CASES = {
+    "mbb_random": (lambda: synth.mbb_2d(False), dict(kind="geo", L=3, omega=0.6, nu=2)),
+    "grid2d": (synth.grid_2d, dict(kind="geo", L=5, nu=2, smoother="chebyshev")),
+    "cantilever2d": (synth.cantilever_2d, dict(kind="geo", L=7, nu=2, smoother="chebyshev")),
+    "cantilever3d": (synth.cantilever_3d, dict(kind="geo", L=6, nu=2, smoother="chebyshev", lean=True)),
+    # the bridge recipe (strut lattice, corner supports, top pressure) at an
+    # eighth of its volume: the oracle's aggregation levels at full size need
+    # more host memory than a workstation holds
+    "bridge3d_128x64x64": (lambda: synth.bridge_3d(nel=(128, 64, 64)),
+                           dict(kind="hybrid", n_geometric=3, max_coarse=1000)),
+}
+
+
+def fingerprint(p) -> dict:
+    return {"n_dof": int(p.n_dof), "nel": list(p.nel), "rho_sum": float(np.sum(p.rho)),
+            "load_sum": float(np.sum(p.loads[0])), "n_fixed": int(len(p.fixed))}
+
+
+def sample_dofs(p, seed: int = 4242) -> np.ndarray:
+    free = np.setdiff1d(np.arange(p.n_dof), p.fixed)
+    rng = np.random.default_rng(seed)
+    return np.sort(rng.choice(free, size=min(N_SAMPLES, free.size), replace=False))
+
+
+def build(p, rec):
+    KE = fem.element_stiffness(p.dim, p.nu)
+    E = fem.simp(p.rho, p.p, p.E0, p.Emin)
+    if rec["kind"] == "geo":
+        nu = rec.get("nu", 1)
+        return mg.build_geometric(p.nel, E, KE, p.fixed, rec["L"], omega=rec.get("omega", 0.5), nu_pre=nu,
+                                  nu_post=nu, smoother=rec.get("smoother", "jacobi"), lean=rec.get("lean", False))
+    return sa.build_hybrid(p.nel, E, KE, p.fixed, rec["n_geometric"], max_coarse=rec["max_coarse"])
+
+
+def run(case: str) -> dict:
+    make, rec = CASES[case]
+    p = make()
+    t0 = time.time()
+    H = build(p, rec)
+    t_build = time.time() - t0
+    f = p.loads[0].copy()
+    f[p.fixed] = 0.0
+    t0 = time.time()
+    res = mg.mg_pcg(H, f, RTOL, max_iters=20000)
+    t_solve = time.time() - t0
+    if not res.converged:
+        raise RuntimeError(f"{case}: the oracle did not reach rtol {RTOL}")
+    idx = sample_dofs(p)
+    out = {
+        "case": case,
+        "command": "python tests/golden/make_golden.py " + case,
+        "inputs": fingerprint(p),
+        "oracle": {"rtol": RTOL, "iters": res.iters, "true_relres": res.true_relres,
+                   "levels": [int(A.shape[0]) for A in H.A], "recipe": rec,
+                   "build_s": round(t_build, 1), "solve_s": round(t_solve, 1)},
+        "compliance": float(f @ res.u),
+        "norm_u": float(np.linalg.norm(res.u)),
+        "max_abs_u": float(np.max(np.abs(res.u))),
+        "sample_dofs": [int(i) for i in idx],
+        "sample_u": [float(res.u[i]) for i in idx],
+    }
+    with open(os.path.join(HERE, f"solve_{case}.json"), "w") as fh:
+        json.dump(out, fh, indent=0)
+    print(f"{case}: {res.iters} iterations, true relres {res.true_relres:.2e}, c = {out['compliance']!r} "
+          f"(build {t_build:.0f} s, solve {t_solve:.0f} s)", flush=True)
+    return out
+
+
+if __name__ == "__main__":
+    names = sys.argv[1:]
+    if names == ["all"]:
+        names = list(CASES)
+    for n in names:
+        run(n)

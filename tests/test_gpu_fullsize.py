@@ -79,3 +79,53 @@ def test_mixed_equals_fp64_at_full_size(opts):
     d = float((us[0] - us[1]).norm() / us[1].norm())
     print(f"  mixed vs fp64: {d:.2e}", flush=True)
     assert d <= 1e-7
+
+
+# ---------------------------------------------------------------- against the oracle's solutions
+# golden case -> (problem, GPU options); the oracle's u at rtol 1e-12 comes
+# from tests/golden/make_golden.py (oracle only)
+import json  # noqa: E402
+import os  # noqa: E402
+
+GOLDEN_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+GOLDEN = {
+    "mbb_random": (lambda: synth.mbb_2d(False), dict(n_levels=3, omega=0.6, nu_pre=2, nu_post=2)),
+    "grid2d": (lambda: synth.get("grid2d"), dict(n_levels=5, max_iters=20000)),
+}
+
+
+def golden_errors(g, u, c):
+    """Relative errors of a solution against an oracle reference: u over the
+    sampled dofs, ||u||_2, and the compliance."""
+    idx = np.asarray(g["sample_dofs"], dtype=np.int64)
+    ref = np.asarray(g["sample_u"])
+    e_u = float(np.linalg.norm(u[idx] - ref) / np.linalg.norm(ref))
+    e_n = abs(float(np.linalg.norm(u)) - g["norm_u"]) / g["norm_u"]
+    e_c = abs(c - g["compliance"]) / abs(g["compliance"])
+    return e_u, e_n, e_c
+
+
+@pytest.mark.parametrize("name", list(GOLDEN))
+def test_full_size_vs_oracle(name):
+    """FP32-V-cycle / FP64-FCG solve at rtol 1e-8 against the oracle's u at
+    rtol 1e-12: relative error <= 1e-7 over 4096 seeded dofs and in ||u||,
+    and <= 1e-9 in the compliance."""
+    from paper_2001_01655_amd import Hierarchy
+    path = os.path.join(GOLDEN_DIR, f"solve_{name.replace('_cheb', '')}.json")
+    with open(path) as fh:
+        g = json.load(fh)
+    make, opts = GOLDEN[name]
+    p = make()
+    fp = g["inputs"]
+    assert fp["n_dof"] == p.n_dof and fp["n_fixed"] == len(p.fixed)
+    assert abs(fp["rho_sum"] - float(np.sum(p.rho))) <= 1e-12 * abs(fp["rho_sum"]), "density generator changed"
+    assert fp["load_sum"] == float(np.sum(p.loads[0])), "load generator changed"
+    print(f"vs oracle {name} ({p.n_dof} dofs)", flush=True)
+    H = Hierarchy(p.nel, p.rho, p.fixed, p=p.p, E0=p.E0, Emin=p.Emin, nu=p.nu, **opts)
+    res = H.solve(torch.tensor(p.loads[0], device="cuda"), rtol=1e-8)
+    H.close()
+    assert res.status == 0
+    u = res.u.cpu().numpy().reshape(-1)
+    e_u, e_n, e_c = golden_errors(g, u, res.compliance[0])
+    print(f"  iters={res.iters[0]} err_u(sampled)={e_u:.2e} err_norm={e_n:.2e} err_c={e_c:.2e}", flush=True)
+    assert e_u <= 1e-7 and e_n <= 1e-7 and e_c <= 1e-9

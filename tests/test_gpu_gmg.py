@@ -53,12 +53,18 @@ def test_fine_apply(dim, nel, L):
     G.close()
 
 
+# stencil_kernel 1 runs the large-level coarse operator kernel on these small
+# levels too (0 picks by size, which here is always the small-level form)
+KERNELS = pytest.mark.parametrize("kern", [0, 1], ids=["by_size", "large_kernel"])
+
+
 @pytest.mark.parametrize("dim,nel,L", CASES)
-def test_levels_prolongators_dinv(dim, nel, L):
-    _say(f"levels {nel}")
+@KERNELS
+def test_levels_prolongators_dinv(dim, nel, L, kern):
+    _say(f"levels {nel} stencil_kernel={kern}")
     p = synth.small_case(dim, nel, seed=22)
     H, E, KE = _oracle(p, L)
-    G = _gpu(p, L)
+    G = _gpu(p, L, stencil_kernel=kern)
     assert G.num_levels() == L
     for l in range(1, L):
         rp, ci, v = G.export_csr(l)
@@ -83,11 +89,12 @@ def test_levels_prolongators_dinv(dim, nel, L):
 
 
 @pytest.mark.parametrize("dim,nel,L", CASES)
-def test_vcycle_fp64(dim, nel, L):
-    _say(f"vcycle {nel}")
+@KERNELS
+def test_vcycle_fp64(dim, nel, L, kern):
+    _say(f"vcycle {nel} stencil_kernel={kern}")
     p = synth.small_case(dim, nel, seed=23)
     H, E, KE = _oracle(p, L)
-    G = _gpu(p, L, vcycle_fp=64)
+    G = _gpu(p, L, vcycle_fp=64, stencil_kernel=kern)
     b = H.A[0] @ np.random.default_rng(5).standard_normal(p.n_dof)
     b[p.fixed] = 0.0                      # the V-cycle acts on masked vectors
     ref = mg.vcycle(H, b)
@@ -197,10 +204,11 @@ def test_solve_matrix_cores_vs_oracle():
 
 @pytest.mark.parametrize("dim,nel,L", CASES)
 @pytest.mark.parametrize("nu", [2, 3])
-def test_vcycle_chebyshev(dim, nel, L, nu):
+@KERNELS
+def test_vcycle_chebyshev(dim, nel, L, nu, kern):
     """Chebyshev smoothing (interval from a 12-step power estimate per level):
     the V-cycle in FP64 and FP32 against the oracle's."""
-    _say(f"vcycle chebyshev {nel} nu={nu}")
+    _say(f"vcycle chebyshev {nel} nu={nu} stencil_kernel={kern}")
     p = synth.small_case(dim, nel, seed=28)
     KE = fem.element_stiffness(p.dim, p.nu)
     E = fem.simp(p.rho, p.p, p.E0, p.Emin)
@@ -208,7 +216,7 @@ def test_vcycle_chebyshev(dim, nel, L, nu):
     b = H.A[0] @ np.random.default_rng(9).standard_normal(p.n_dof)
     b[p.fixed] = 0.0
     ref = mg.vcycle(H, b)
-    G = _gpu(p, L, nu_pre=nu, nu_post=nu, smoother=2, vcycle_fp=64)
+    G = _gpu(p, L, nu_pre=nu, nu_post=nu, smoother=2, vcycle_fp=64, stencil_kernel=kern)
     z = G.vcycle(torch.tensor(b, device="cuda"), fp=64).cpu().numpy()
     assert _rel(z, ref) <= 1e-9
     z32 = G.vcycle(torch.tensor(b, device="cuda", dtype=torch.float32), fp=32).cpu().numpy()
