@@ -419,16 +419,18 @@ __global__ __launch_bounds__(WG) void k_fine3z2(const T* __restrict__ E, const K
     if (live && two) finish_store<T, 3, OP>(nd1, acc1, xo1, m1, fin1, y, omega, dots, ch);
 }
 
-// 3D FP32 on the matrix cores: the same node-per-lane operator, with the
-// 24x24 KE contraction on v_mfma_f32_4x4x1 (16 blocks of 4 lanes).  In each
-// block, lane 4b+j supplies B = one neighbour value of its own node and gets
-// back D[i][j] = sum_k A[i][k] B[k][j] for rows i = 0..3, i.e. the three
-// KE-row products of its own node (row 3 is padding).  A is broadcast from one
-// block to all 16 (CBSZ = 4, ABID = k mod 16), so the 192 KE columns
-// (24 per element corner slot) x 4 rows sit in 12 registers per lane:
-// register q, block m holds column k = 16 q + m.  One accumulator per element
-// slot collects its 24 columns; the slots are then scaled by their moduli and
-// summed in a fixed order (deterministic, FP32 accumulation).
+// 3D FP32 on the matrix cores, two nodes stacked in z per lane as in
+// k_fine3z2 (shared neighbour planes).  Each node's 24x24 KE contraction runs
+// on v_mfma_f32_4x4x1 (16 blocks of 4 lanes): in each block, lane 4b+j supplies
+// B = one neighbour value of its own node and gets back D[i][j] = sum_k
+// A[i][k] B[k][j] for rows i = 0..3, i.e. the three KE-row products of its own
+// node (row 3 is padding).  A is broadcast from one block to all 16 (CBSZ = 4,
+// ABID = k mod 16), so the 192 KE columns (24 per element corner slot) x 4
+// rows sit in 12 registers per lane: register q, block m holds column
+// k = 16 q + m.  One accumulator per element slot collects its 24 columns; a
+// layer's four slots are scaled by their moduli and added as soon as its two
+// planes are done (fixed order: layer below, then layer above; FP32
+// accumulation), so at most 12 accumulators are live.
 typedef float v4f __attribute__((ext_vector_type(4)));
 
 template <int K>
@@ -437,96 +439,137 @@ __device__ __forceinline__ v4f mfma_col(const float (&ka)[12], float bv, v4f c) 
     return __builtin_amdgcn_mfma_f32_4x4x1f32(ka[K >> 4], bv, c, 4, K & 15, 0);
 }
 
+// plane DZ (relative to the node) of the elements of layer EZ: accumulators
+// C[EY * 2 + EX] of that layer
 template <int DZ, int EZ>
-__device__ __forceinline__ void layer_plane3_mfma(const float (&ka)[12], const float (&w)[9][3], v4f (&C)[8]) {
+__device__ __forceinline__ void layer_plane3_mfma(const float (&ka)[12], const float (&w)[9][3], v4f (&C)[4]) {
     constexpr int BZ = DZ - EZ;
-    if constexpr (BZ >= 0 && BZ <= 1) {
-        // consecutive instructions go to the 4 different accumulators of the layer
+    static_assert(BZ >= 0 && BZ <= 1, "plane outside the layer");
+    // consecutive instructions go to the 4 different accumulators of the layer
 #define TM_MF(EY, EX, BX, BY, D)                                                                  \
-    C[EZ * 4 + EY * 2 + EX] = mfma_col<24 * loc3(1 - EX, 1 - EY, 1 - EZ) + 3 * loc3(BX, BY, BZ) + D>( \
-        ka, w[(EY + BY) * 3 + EX + BX][D], C[EZ * 4 + EY * 2 + EX]);
+    C[EY * 2 + EX] = mfma_col<24 * loc3(1 - EX, 1 - EY, 1 - EZ) + 3 * loc3(BX, BY, BZ) + D>(       \
+        ka, w[(EY + BY) * 3 + EX + BX][D], C[EY * 2 + EX]);
 #define TM_MF4(BX, BY, D) TM_MF(0, 0, BX, BY, D) TM_MF(0, 1, BX, BY, D) TM_MF(1, 0, BX, BY, D) TM_MF(1, 1, BX, BY, D)
 #define TM_MF12(BX, BY) TM_MF4(BX, BY, 0) TM_MF4(BX, BY, 1) TM_MF4(BX, BY, 2)
-        TM_MF12(0, 0)
-        TM_MF12(1, 0)
-        TM_MF12(0, 1)
-        TM_MF12(1, 1)
+    TM_MF12(0, 0)
+    TM_MF12(1, 0)
+    TM_MF12(0, 1)
+    TM_MF12(1, 1)
 #undef TM_MF12
 #undef TM_MF4
 #undef TM_MF
+}
+
+// acc += sum over the layer's slots (EY, EX) of E[EY][EX] * C[EY * 2 + EX]
+__device__ __forceinline__ void layer_reduce(const v4f (&C)[4], const float (&E)[2][2], float (&acc)[3]) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const float e = E[q >> 1][q & 1];
+        acc[0] += e * C[q][0];
+        acc[1] += e * C[q][1];
+        acc[2] += e * C[q][2];
     }
 }
 
 template <int OP>
-__global__ __launch_bounds__(WG) void k_fine3_mfma(const float* __restrict__ E, const float* __restrict__ KA,
-                                                   const uint8_t* __restrict__ nm, int nx, int ny, int nz,
-                                                   int64_t N64, const float* __restrict__ x,
-                                                   const float* __restrict__ b, float* __restrict__ y,
-                                                   const float* __restrict__ dinv, float omega,
-                                                   const int* __restrict__ done, const ChebArgs ch) {
+__global__ __launch_bounds__(WG) void k_fine3z2_mfma(const float* __restrict__ E, const float* __restrict__ KA,
+                                                     const uint8_t* __restrict__ nm, int nx, int ny, int nz,
+                                                     int64_t N64, const float* __restrict__ x,
+                                                     const float* __restrict__ b, float* __restrict__ y,
+                                                     const float* __restrict__ dinv, float omega,
+                                                     const int* __restrict__ done, const ChebArgs ch) {
+    static_assert(OP != OP_QDOT, "no partial sums in the two-node operator");
     if (done && *done) return;
     // every lane of the wave takes part in the matrix instructions: lanes past
-    // the last node work on node 0 and store nothing
+    // the last pair work on pair 0 and store nothing
     const uint32_t lane = threadIdx.x & 63u;
     float ka[12];
 #pragma unroll
     for (int q = 0; q < 12; ++q) ka[q] = KA[q * 64 + lane];
     const uint32_t N = (uint32_t)N64;
-    const uint32_t node = (uint32_t)xcd_block() * WG + threadIdx.x;
-    const bool live = node < N;
-    const uint32_t NX = nx + 1, NY = ny + 1, NZ = nz + 1;
-    const uint32_t nd = live ? node : 0u;
-    const uint32_t i = nd % NX, tq = nd / NX, j = tq % NY, k = tq / NY;
-    const uint32_t cx[3] = {i ? i - 1 : 0u, i, min(i + 1, NX - 1)};
-    const uint32_t cy[3] = {j ? j - 1 : 0u, j, min(j + 1, NY - 1)};
-    const uint32_t cz[3] = {k ? k - 1 : 0u, k, min(k + 1, NZ - 1)};
-    const auto xr = buf_rsrc(x, (int64_t)N * 12);
+    const uint32_t NX = nx + 1, NY = ny + 1, NZ = nz + 1, PL = NX * NY;
+    const uint32_t NT = PL * ((NZ + 1) / 2);           // threads: z pairs
+    const uint32_t p = (uint32_t)xcd_block() * WG + threadIdx.x;
+    const bool live = p < NT;
+    const uint32_t pp = live ? p : 0u;
+    const uint32_t i = pp % NX, tq = pp / NX, j = tq % NY, k = 2u * (tq / NY);
+    const bool two = k + 1 < NZ;                        // the upper node exists
+    const uint32_t nd0 = k * PL + j * NX + i;
+    const uint32_t nd1 = two ? nd0 + PL : nd0;
+    constexpr uint32_t NB = 12u;                        // bytes per node
+    uint32_t nb0 = nd0 * NB;
+    asm volatile("" : "+v"(nb0));
+    const uint32_t bx[3] = {i ? 0u - NB : 0u, 0u, i + 1 < NX ? NB : 0u};
+    const uint32_t by[3] = {j ? 0u - NX * NB : 0u, 0u, j + 1 < NY ? NX * NB : 0u};
+    // planes k-1 .. k+2 relative to node k, clamped into the grid (what lies
+    // outside only meets elements of modulus zero)
+    const uint32_t bz[4] = {k ? 0u - PL * NB : 0u, 0u, k + 1 < NZ ? PL * NB : 0u,
+                            k + 2 < NZ ? 2u * PL * NB : (k + 1 < NZ ? PL * NB : 0u)};
+    const auto xr = buf_rsrc(x, (int64_t)N * NB);
     const auto er = buf_rsrc(E, (int64_t)nx * ny * nz * 4);
-    float Ee[8];
+    // moduli of element layers k-1, k, k+1 (index clamped, zero outside)
+    const uint32_t EX = (uint32_t)nx, EP = EX * (uint32_t)ny;
+    const uint32_t jE = j * EX;
+    const uint32_t gx[2] = {i ? i - 1 : 0u, i < EX ? i : i - 1};
+    const uint32_t gy[2] = {j ? jE - EX : 0u, j < (uint32_t)ny ? jE : jE - EX};
+    float El[3][2][2];
 #pragma unroll
-    for (int ez = 0; ez < 2; ++ez)
+    for (int lz = 0; lz < 3; ++lz) {
+        const int layer = (int)k - 1 + lz;
+        const bool zin = layer >= 0 && layer < nz;
+        const uint32_t gz = zin ? (uint32_t)layer * EP : 0u;
 #pragma unroll
         for (int ey = 0; ey < 2; ++ey)
 #pragma unroll
             for (int ex = 0; ex < 2; ++ex) {
-                const bool in = (ex || i) && (ex == 0 || i < (uint32_t)nx) && (ey || j) &&
-                                (ey == 0 || j < (uint32_t)ny) && (ez || k) && (ez == 0 || k < (uint32_t)nz);
-                const uint32_t gx = min(i + ex, (uint32_t)nx) - (i + ex > 0 ? 1u : 0u);
-                const uint32_t gy = min(j + ey, (uint32_t)ny) - (j + ey > 0 ? 1u : 0u);
-                const uint32_t gz = min(k + ez, (uint32_t)nz) - (k + ez > 0 ? 1u : 0u);
-                Ee[ez * 4 + ey * 2 + ex] = in ? bld<float>(er, ((gz * (uint32_t)ny + gy) * (uint32_t)nx + gx) * 4u) : 0.f;
+                const bool in = zin && (ex || i) && (ex == 0 || i < (uint32_t)nx) && (ey || j) &&
+                                (ey == 0 || j < (uint32_t)ny);
+                El[lz][ey][ex] = in ? bld<float>(er, (gz + gy[ey] + gx[ex]) * 4u) : 0.f;
             }
-    v4f C[8];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) C[q] = v4f{0.f, 0.f, 0.f, 0.f};
+    }
     float w[9][3];
-    auto load_plane = [&](int dz) {
+    auto load_plane = [&](int P) {
 #pragma unroll
         for (int dy = 0; dy < 3; ++dy) {
-            const uint32_t row = (cz[dz] * NY + cy[dy]) * NX;
+            const uint32_t rowb = nb0 + bz[P] + by[dy];
 #pragma unroll
-            for (int dx = 0; dx < 3; ++dx) bld3(xr, (row + cx[dx]) * 12u, w[dy * 3 + dx]);
+            for (int dx = 0; dx < 3; ++dx) bld3(xr, rowb + bx[dx], w[dy * 3 + dx]);
         }
     };
+    FinIn<float, 3> fin0, fin1;
+    finish_load<float, 3, OP>(nd0, N, b, dinv, ch, fin0);
+    finish_load<float, 3, OP>(nd1, N, b, dinv, ch, fin1);
+    const uint8_t m0 = nm[nd0], m1 = nm[nd1];
+    const v4f zero4 = {0.f, 0.f, 0.f, 0.f};
+    v4f A0[4] = {zero4, zero4, zero4, zero4};      // node k,   layer k-1
+    v4f B0[4] = {zero4, zero4, zero4, zero4};      // node k,   layer k
+    v4f A1[4] = {zero4, zero4, zero4, zero4};      // node k+1, layer k
+    v4f B1[4] = {zero4, zero4, zero4, zero4};      // node k+1, layer k+1
+    float acc0[3] = {0.f, 0.f, 0.f}, acc1[3] = {0.f, 0.f, 0.f};
+    float xo0[3], xo1[3];
     load_plane(0);
-    layer_plane3_mfma<0, 0>(ka, w, C);
+    layer_plane3_mfma<0, 0>(ka, w, A0);
     load_plane(1);
-    layer_plane3_mfma<1, 0>(ka, w, C);
-    layer_plane3_mfma<1, 1>(ka, w, C);
-    load_plane(2);
-    layer_plane3_mfma<2, 1>(ka, w, C);
-    float acc[3] = {0.f, 0.f, 0.f};
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        acc[0] += Ee[q] * C[q][0];
-        acc[1] += Ee[q] * C[q][1];
-        acc[2] += Ee[q] * C[q][2];
-    }
-    if (live) {
-        double dots[2] = {0.0, 0.0};
-        const float xo[3] = {x[3u * node], x[3u * node + 1], x[3u * node + 2]};
-        finish_node<float, 3, OP>(node, N, acc, xo, nm[node], b, y, dinv, omega, dots, ch);
-    }
+    for (int c = 0; c < 3; ++c) xo0[c] = w[4][c];
+    layer_plane3_mfma<1, 0>(ka, w, A0);
+    layer_plane3_mfma<1, 1>(ka, w, B0);
+    layer_plane3_mfma<0, 0>(ka, w, A1);
+    layer_reduce(A0, El[0], acc0);
+    load_plane(2);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) xo1[c] = w[4][c];
+    layer_plane3_mfma<2, 1>(ka, w, B0);
+    layer_plane3_mfma<1, 0>(ka, w, A1);
+    layer_plane3_mfma<1, 1>(ka, w, B1);
+    layer_reduce(B0, El[1], acc0);
+    layer_reduce(A1, El[1], acc1);
+    load_plane(3);
+    layer_plane3_mfma<2, 1>(ka, w, B1);
+    layer_reduce(B1, El[2], acc1);
+    double dots[2] = {0.0, 0.0};
+    if (live) finish_store<float, 3, OP>(nd0, acc0, xo0, m0, fin0, y, omega, dots, ch);
+    if (live && two) finish_store<float, 3, OP>(nd1, acc1, xo1, m1, fin1, y, omega, dots, ch);
 }
 
 // 2D: 9 neighbour nodes, 4 elements, 8x8 KE.
@@ -658,8 +701,9 @@ static void fine_dispatch(const tm_hierarchy* h, const T* x, const T* b, T* y, T
     const dim3 g(grid_for(L.n_nodes)), blk(WG);
     if constexpr (std::is_same<T, float>::value && !MI && OP != OP_QDOT) {
         if (L.dim == 3 && h->opt.fine_mfma) {
-            hipLaunchKernelGGL((k_fine3_mfma<OP>), g, blk, 0, s, L.E32, h->KA32, L.nmask, L.nel[0], L.nel[1],
-                               L.nel[2], L.n_nodes, x, b, y, L.dinv32, omega, done, ch);
+            const int64_t nt = (int64_t)L.nn[0] * L.nn[1] * ((L.nn[2] + 1) / 2);
+            hipLaunchKernelGGL((k_fine3z2_mfma<OP>), dim3(grid_for(nt)), blk, 0, s, L.E32, h->KA32, L.nmask,
+                               L.nel[0], L.nel[1], L.nel[2], L.n_nodes, x, b, y, L.dinv32, omega, done, ch);
             return;
         }
     }
