@@ -27,7 +27,8 @@
  *   memory   "_dev" pointers are device memory, everything else host memory.
  *            The caller owns every buffer it passes; the library keeps no
  *            caller pointer past the call that received it.  A hierarchy owns
- *            the device memory it allocates (hipMalloc) until tm_destroy.
+ *            the device memory it allocates until tm_destroy: from the
+ *            tm_allocator given to tm_setup, else from hipMalloc.
  *   streams  `stream` is a hipStream_t (NULL = default stream).  All device
  *            work of a call is ordered on that stream.  Calls that return
  *            host-visible results synchronise that stream before returning.
@@ -86,9 +87,10 @@ typedef struct {
     int32_t max_iters;     /* outer iteration limit (1000)                                        */
     int32_t check_every;   /* host convergence check period in iterations; 0 = adaptive          */
     int32_t fine_mfma;     /* 1: FP32 3D fine operator contracts KE on the matrix cores
-                              (v_mfma_f32_4x4x1, KE broadcast from 12 registers); 0 (default):
-                              vector FMAs with KE symmetry-class values in scalar registers.
-                              Same operator either way; only the rounding order differs      */
+                              (v_mfma_f32_4x4x1, KE broadcast from 12 registers, two nodes
+                              stacked in z per lane); 0 (default): vector FMAs with KE
+                              symmetry-class values in scalar registers.  Same operator either
+                              way; only the rounding order differs                           */
     double  cheb_lower;    /* Chebyshev smoothing interval [cheb_lower, 1.1] x lambda, lambda =
                               power estimate of the largest eigenvalue of D^-1 A (0.1)        */
     int32_t adapt_iters;   /* automated hybrid (Sec. 4.4): when a solve takes more than this
@@ -106,6 +108,25 @@ typedef struct {
                               large-level kernel on every level; 2: the small-level form on
                               every level.  Same operator either way                        */
 } tm_options;
+
+/* Source of a hierarchy's device memory (levels, solve states, work vectors,
+ * aggregation levels, eigensolver workspace), e.g. a framework's caching
+ * allocator.
+ *   alloc(bytes, stream, ctx) returns `bytes` of device memory on the current
+ *     device, aligned to 256 bytes, for use on `stream` (the stream of the call
+ *     that needs it), or NULL (the call then fails with TM_ERR_OOM);
+ *   free(ptr, stream, ctx) takes back a block from alloc.  The library calls it
+ *     only after synchronising the device, so no queued work uses the block.
+ *   ctx is passed through and must stay valid until tm_destroy.
+ * The callbacks are called from the thread that calls into the library, during
+ * tm_setup, tm_update_density (aggregation levels), the first solve of a new
+ * right-hand-side count, tm_vcycle, tm_stress_stiffness, tm_eigs and
+ * tm_destroy. */
+typedef struct {
+    void* (*alloc)(size_t bytes, void* stream, void* ctx);
+    void (*free)(void* ptr, void* stream, void* ctx);
+    void* ctx;
+} tm_allocator;
 
 typedef struct tm_hierarchy tm_hierarchy;       /* opaque */
 typedef struct tm_solve_state tm_solve_state;   /* opaque */
@@ -125,9 +146,12 @@ tm_status tm_plan_bytes(const tm_mesh* mesh, const tm_options* opts, int32_t n_r
  * levels below such a chain take the rigid-body modes at the true node positions).
  * Errors: TM_ERR_ARG (bad mesh/material/options, an axis that would be coarsened
  * below one element, dof id out of range), TM_ERR_NOT_SPD, TM_ERR_OOM.
- * rho values are checked on the device (finite and in [0,1]). */
+ * rho values are checked on the device (finite and in [0,1]).
+ * alloc: the hierarchy's device memory source for its whole life (NULL:
+ * hipMalloc / hipFree); TM_ERR_ARG if it is given without both callbacks. */
 tm_status tm_setup(const tm_mesh* mesh, const tm_material* mat, const double* rho_dev,
-                   const tm_bcs* bcs, const tm_options* opts, void* stream, tm_hierarchy** out);
+                   const tm_bcs* bcs, const tm_options* opts, const tm_allocator* alloc, void* stream,
+                   tm_hierarchy** out);
 
 /* Numeric re-setup for new densities on the same mesh, supports and options
  * (a design iteration): the structure and all allocations are reused.  For a

@@ -52,6 +52,31 @@ class tm_eig_options(C.Structure):
                 ("tol", C.c_double), ("stag_tol", C.c_double), ("precond_fp", C.c_int32)]
 
 
+# tm_allocator: device memory callbacks (alloc(bytes, stream, ctx), free(ptr, stream, ctx))
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+
+
+class tm_allocator(C.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("ctx", C.c_void_p)]
+
+
+def _torch_alloc(nbytes, stream, ctx):
+    try:
+        return torch.cuda.caching_allocator_alloc(int(nbytes), stream=int(stream or 0))
+    except Exception:           # out of memory: NULL, the library reports TM_ERR_OOM
+        return None
+
+
+def _torch_free(ptr, stream, ctx):
+    torch.cuda.caching_allocator_delete(int(ptr))
+
+
+# torch's caching allocator as the hierarchies' device memory (the callback
+# objects live as long as the module)
+TORCH_ALLOCATOR = tm_allocator(ALLOC_FN(_torch_alloc), FREE_FN(_torch_free), None)
+
+
 class TmError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"{msg} (status {status})")
@@ -67,7 +92,7 @@ def _load():
         "tm_default_options": (None, [C.POINTER(tm_options)]),
         "tm_plan_bytes": (I32, [C.POINTER(tm_mesh), C.POINTER(tm_options), I32, C.POINTER(SZ)]),
         "tm_setup": (I32, [C.POINTER(tm_mesh), C.POINTER(tm_material), P, C.POINTER(tm_bcs),
-                           C.POINTER(tm_options), P, C.POINTER(P)]),
+                           C.POINTER(tm_options), C.POINTER(tm_allocator), P, C.POINTER(P)]),
         "tm_update_density": (I32, [P, P, P]),
         "tm_solve": (I32, [P, I32, P, D, I32, P, P, P, P, P]),
         "tm_solve_begin": (I32, [P, I32, P, D, I32, P, P, C.POINTER(P)]),

@@ -50,26 +50,49 @@ static tm_status guarded(F&& f) {
 }
 
 // ------------------------------------------------------------------ memory
-template <typename T>
-static T* dalloc(std::vector<void*>& list, size_t& bytes, size_t n) {
+// Device memory of a hierarchy comes from the caller's allocator when one was
+// given to tm_setup (on the stream of the call that needs it), else hipMalloc.
+void* dev_alloc(const tm_hierarchy* h, size_t b) {
     void* p = nullptr;
-    const size_t b = std::max<size_t>(n, 1) * sizeof(T);
+    if (h->has_alloc) {
+        p = h->alloc.alloc(b, (void*)h->cur_stream, h->alloc.ctx);
+        if (!p) fail(TM_ERR_OOM, "the caller's allocator returned no memory for " + std::to_string(b) + " bytes");
+        return p;
+    }
     const hipError_t e = hipMalloc(&p, b);
     if (e != hipSuccess) {
         (void)hipGetLastError();
         fail(TM_ERR_OOM, "hipMalloc of " + std::to_string(b) + " bytes failed");
     }
+    return p;
+}
+
+// Every block goes back only after the device has finished the work that
+// used it: hipFree waits by itself; a caller's free is preceded by a device
+// synchronisation (its allocator may hand the block out again at once).
+void dev_free_list(const tm_hierarchy* h, std::vector<void*>& list) {
+    if (list.empty()) return;
+    if (h->has_alloc) {
+        (void)hipDeviceSynchronize();
+        for (void* p : list) h->alloc.free(p, (void*)h->cur_stream, h->alloc.ctx);
+    } else {
+        for (void* p : list) (void)hipFree(p);
+    }
+    list.clear();
+}
+
+template <typename T>
+static T* dalloc(const tm_hierarchy* h, std::vector<void*>& list, size_t& bytes, size_t n) {
+    const size_t b = std::max<size_t>(n, 1) * sizeof(T);
+    void* p = dev_alloc(h, b);
     list.push_back(p);
     bytes += b;
     return (T*)p;
 }
 template <typename T>
-static T* halloc(tm_hierarchy* h, size_t n) { return dalloc<T>(h->allocs, h->bytes, n); }
+static T* halloc(tm_hierarchy* h, size_t n) { return dalloc<T>(h, h->allocs, h->bytes, n); }
 
-static void free_list(std::vector<void*>& list) {
-    for (void* p : list) (void)hipFree(p);
-    list.clear();
-}
+static void free_list(const tm_hierarchy* h, std::vector<void*>& list) { dev_free_list(h, list); }
 
 static hipStream_t S(void* s) { return (hipStream_t)s; }
 
@@ -607,10 +630,10 @@ static void alloc_vcyc(tm_hierarchy* h, Vcyc& V, std::vector<void*>& list, size_
     const bool cheb = h->opt.smoother == TM_SMOOTH_CHEBYSHEV;
     for (int l = 0; l < L; ++l) {
         const size_t n = (size_t)h->lv[l].n;
-        if (l > 0) V.b[l] = dalloc<T>(list, bytes, n);
-        V.x[l] = dalloc<T>(list, bytes, n);
-        if (l < L - 1) V.t[l] = dalloc<T>(list, bytes, n);
-        if (cheb && l < L - 1) V.d[l] = dalloc<T>(list, bytes, n);
+        if (l > 0) V.b[l] = dalloc<T>(h, list, bytes, n);
+        V.x[l] = dalloc<T>(h, list, bytes, n);
+        if (l < L - 1) V.t[l] = dalloc<T>(h, list, bytes, n);
+        if (cheb && l < L - 1) V.d[l] = dalloc<T>(h, list, bytes, n);
     }
 }
 
@@ -637,26 +660,26 @@ static tm_solve_state* new_state(tm_hierarchy* h, int nrhs) {
         for (int k = 0; k < nrhs; ++k) {
             Lane* ln = new Lane();
             st->lanes.push_back(ln);
-            ln->f = dalloc<double>(st->allocs, st->bytes, n);
-            ln->r = dalloc<double>(st->allocs, st->bytes, n);
-            ln->p = dalloc<double>(st->allocs, st->bytes, n);
-            ln->q = dalloc<double>(st->allocs, st->bytes, n);
-            ln->part = dalloc<double>(st->allocs, st->bytes, (size_t)2 * nparts_cap(h));
+            ln->f = dalloc<double>(h, st->allocs, st->bytes, n);
+            ln->r = dalloc<double>(h, st->allocs, st->bytes, n);
+            ln->p = dalloc<double>(h, st->allocs, st->bytes, n);
+            ln->q = dalloc<double>(h, st->allocs, st->bytes, n);
+            ln->part = dalloc<double>(h, st->allocs, st->bytes, (size_t)2 * nparts_cap(h));
             if (mixed) {
-                ln->r32 = dalloc<float>(st->allocs, st->bytes, n);
-                ln->z32 = dalloc<float>(st->allocs, st->bytes, n);
+                ln->r32 = dalloc<float>(h, st->allocs, st->bytes, n);
+                ln->z32 = dalloc<float>(h, st->allocs, st->bytes, n);
                 alloc_vcyc<float>(h, ln->v32, st->allocs, st->bytes);
             } else {
-                ln->z64 = dalloc<double>(st->allocs, st->bytes, n);
+                ln->z64 = dalloc<double>(h, st->allocs, st->bytes, n);
                 alloc_vcyc<double>(h, ln->v64, st->allocs, st->bytes);
             }
         }
-        st->sc = dalloc<KScal>(st->allocs, st->bytes, nrhs);
+        st->sc = dalloc<KScal>(h, st->allocs, st->bytes, nrhs);
         TM_HIP(hipMemset(st->sc, 0, sizeof(KScal) * nrhs));
         TM_HIP(hipHostMalloc((void**)&st->sc_host, sizeof(KScal) * nrhs, hipHostMallocDefault));
         TM_HIP(hipEventCreateWithFlags(&st->ev, hipEventDisableTiming));
     } catch (...) {
-        free_list(st->allocs);
+        free_list(st->h, st->allocs);
         for (Lane* ln : st->lanes) delete ln;
         if (st->sc_host) (void)hipHostFree(st->sc_host);
         for (hipStream_t q : st->ls) (void)hipStreamDestroy(q);
@@ -727,7 +750,7 @@ void delete_cached_state(tm_hierarchy* h) {
 static void delete_state(tm_solve_state* st) {
     if (!st) return;
     for (hipStream_t q : st->ls) (void)hipStreamSynchronize(q);
-    free_list(st->allocs);
+    free_list(st->h, st->allocs);
     for (Lane* ln : st->lanes) delete ln;
     if (st->sc_host) (void)hipHostFree(st->sc_host);
     if (st->ev) (void)hipEventDestroy(st->ev);
@@ -1019,7 +1042,7 @@ void free_eig_work(tm_hierarchy* h) {
     if (!h->eig) return;
     (void)hipDeviceSynchronize();
     if (h->eig->host) (void)hipHostFree(h->eig->host);
-    free_list(h->eig->allocs);
+    free_list(h, h->eig->allocs);
     delete h->eig;
     h->eig = nullptr;
 }
@@ -1040,7 +1063,7 @@ static EigWork* eig_work(tm_hierarchy* h, int jmax, int fp) {
         w->n = h->n_dof;
         w->jmax = jmax;
         w->fp = fp;
-        auto A = [&](size_t k) { return dalloc<double>(w->allocs, w->bytes, k); };
+        auto A = [&](size_t k) { return dalloc<double>(h, w->allocs, w->bytes, k); };
         w->V = A(n * (size_t)jmax);
         w->q = A(n);
         w->Aq = A(n);
@@ -1055,8 +1078,8 @@ static EigWork* eig_work(tm_hierarchy* h, int jmax, int fp) {
         if (fp == 64) {
             alloc_vcyc<double>(h, w->vc, w->allocs, w->bytes);
         } else {
-            w->r32 = dalloc<float>(w->allocs, w->bytes, n);
-            w->z32 = dalloc<float>(w->allocs, w->bytes, n);
+            w->r32 = dalloc<float>(h, w->allocs, w->bytes, n);
+            w->z32 = dalloc<float>(h, w->allocs, w->bytes, n);
             alloc_vcyc<float>(h, w->vc, w->allocs, w->bytes);
         }
         TM_HIP(hipHostMalloc((void**)&w->host, EIG_PIN_N * sizeof(double), hipHostMallocDefault));
@@ -1330,8 +1353,12 @@ tm_status tm_plan_bytes(const tm_mesh* mesh, const tm_options* opts, int32_t n_r
         const int dim = mesh->dim, bb = dim * dim, nd = dim * (1 << dim);
         const int64_t n_el = (int64_t)mesh->nel[0] * mesh->nel[1] * (dim == 3 ? mesh->nel[2] : 1);
         const int64_t nodes0 = nodes_of(mesh->nel, dim);
-        size_t b = (size_t)n_el * 12 + nodes0 * (1 + sym_n(dim) * 12);
+        // moduli FP64 + FP32, densities FP64, support mask, block inverses FP64 + FP32
+        size_t b = (size_t)n_el * 20 + nodes0 * (1 + sym_n(dim) * 12);
         size_t vec = 0, el1 = 0, el2 = 0;
+        const bool cheb = opts->smoother == TM_SMOOTH_CHEBYSHEV;
+        const size_t vw = opts->vcycle_fp == 32 ? 4 : 8;
+        size_t cheb_dir = cheb ? (size_t)nodes0 * dim * vw : 0;    // Chebyshev directions, per RHS
         int nel[3] = {mesh->nel[0], mesh->nel[1], dim == 3 ? mesh->nel[2] : 1};
         const bool mixed = opts->vcycle_fp == 32;
         int64_t last_n = nodes0 * dim;
@@ -1342,6 +1369,7 @@ tm_status tm_plan_bytes(const tm_mesh* mesh, const tm_options* opts, int32_t n_r
             const int nst = dim == 3 ? 27 : 9, nq = (nst - 1) / 2 * bb + dim * (dim + 1) / 2;
             b += (size_t)nn * (bb * 8 * nst + 12 * nq + 12 * sym_n(dim));
             vec += (size_t)nn * dim * (mixed ? 4 : 8) * 3;
+            if (cheb && l + 1 < p.Lg) cheb_dir += (size_t)nn * dim * vw;
             if (l == 1) el1 = (size_t)ne * nd * nd * 8;
             if (l == 2) el2 = (size_t)ne * nd * nd * 8;
             last_n = nn * dim;
@@ -1350,13 +1378,19 @@ tm_status tm_plan_bytes(const tm_mesh* mesh, const tm_options* opts, int32_t n_r
         b += (size_t)last_n * last_n * 8 * 2 + el1 + el2 + (size_t)(dim == 3 ? 27 : 9) * nd * nd * 8;
         if (opts->smoother == TM_SMOOTH_CHEBYSHEV) b += (size_t)nodes0 * dim * 8 * 3 + (size_t)nodes0 / 16 + 1024;
         if (opts->smoother == TM_SMOOTH_CHEBYSHEV && opts->cheb_warm_steps > 0) b += (size_t)nodes0 * dim * 8 * 2;
-        const size_t per_rhs = (size_t)nodes0 * dim * (8 * 4 + (mixed ? 4 * 4 : 8 * 3)) + vec;
-        *bytes = b + per_rhs * (size_t)n_rhs;
+        const size_t per_rhs = (size_t)nodes0 * dim * (8 * 4 + (mixed ? 4 * 4 : 8 * 3)) + vec + cheb_dir;
+        // every allocation may be rounded up (allocator granularity, partial
+        // sums, scalars): one 4 KiB page per allocation of the hierarchy
+        // (about 8 per level) and of each right-hand side (about 5 per level)
+        const int L_est = p.Lg + (p.sa ? 4 : 0);
+        const size_t n_alloc = 32 + 8 * (size_t)L_est + (size_t)n_rhs * (8 + 5 * (size_t)L_est);
+        *bytes = b + per_rhs * (size_t)n_rhs + n_alloc * 4096;
     });
 }
 
 static void destroy_impl(tm_hierarchy* h) {
     if (!h) return;
+    h->cur_stream = nullptr;       // the caller's streams may be gone by now
     tmi::delete_cached_state(h);
     tmi::free_eig_work(h);
     for (int c = 0; c < 3; ++c)
@@ -1364,13 +1398,14 @@ static void destroy_impl(tm_hierarchy* h) {
             (void)hipEventDestroy(pr.first);
             (void)hipEventDestroy(pr.second);
         }
-    tmi::free_list(h->allocs);
-    tmi::free_list(h->sa_allocs);
+    tmi::free_list(h, h->allocs);
+    tmi::free_list(h, h->sa_allocs);
     delete h;
 }
 
 tm_status tm_setup(const tm_mesh* mesh, const tm_material* mat, const double* rho_dev,
-                   const tm_bcs* bcs, const tm_options* opts, void* stream, tm_hierarchy** out) {
+                   const tm_bcs* bcs, const tm_options* opts, const tm_allocator* alloc, void* stream,
+                   tm_hierarchy** out) {
     tm_hierarchy* h = nullptr;
     tm_status st = guarded([&] {
         if (!out) fail(TM_ERR_ARG, "out is NULL");
@@ -1379,6 +1414,7 @@ tm_status tm_setup(const tm_mesh* mesh, const tm_material* mat, const double* rh
         check_material(mat);
         check_opts(opts);
         if (!rho_dev) fail(TM_ERR_ARG, "rho_dev is NULL");
+        if (alloc && (!alloc->alloc || !alloc->free)) fail(TM_ERR_ARG, "allocator needs both alloc and free");
         const Plan plan = plan_levels(mesh, opts);
         const int dim = mesh->dim;
         const int64_t n_nodes = nodes_of(mesh->nel, dim), n_dof = n_nodes * dim;
@@ -1394,6 +1430,11 @@ tm_status tm_setup(const tm_mesh* mesh, const tm_material* mat, const double* rh
         if (plan.Lg < 2 && !plan.sa) fail(TM_ERR_ARG, "a hierarchy needs at least two levels");
         hipStream_t s = S(stream);
         h = new tm_hierarchy();
+        if (alloc) {
+            h->alloc = *alloc;
+            h->has_alloc = true;
+        }
+        h->cur_stream = s;
         h->mesh = *mesh;
         if (dim == 2) h->mesh.nel[2] = 1;
         h->mat = *mat;
@@ -1475,6 +1516,7 @@ tm_status tm_update_density(tm_hierarchy* h, const double* rho_dev, void* stream
         if (h->sa) free_eig_work(h);
         // without aggregation levels (whose sizes the host must read) the update
         // never waits for the device
+        h->cur_stream = S(stream);
         numeric_setup(h, rho_dev, S(stream), h->sa);
     });
 }
@@ -1523,6 +1565,7 @@ static tm_status begin_impl(tm_hierarchy* h, int32_t n_rhs, const double* f_dev,
         if (!f_dev || !u_dev) fail(TM_ERR_ARG, "f_dev / u_dev is NULL");
         if (!(rtol > 0.0 && rtol < 1.0)) fail(TM_ERR_ARG, "rtol must be in (0, 1)");
         tm_solve_state* st = nullptr;
+        h->cur_stream = S(stream);
         if (cached) {
             if (h->cached && h->cached->nrhs != n_rhs) {
                 delete_state(h->cached);
@@ -1678,28 +1721,29 @@ tm_status tm_vcycle(tm_hierarchy* h, int32_t fp, const void* b_dev, void* x_dev,
         if (fp != 32 && fp != 64) fail(TM_ERR_ARG, "fp must be 32 or 64");
         if (!b_dev || !x_dev) fail(TM_ERR_ARG, "NULL vector");
         hipStream_t s = S(stream);
+        h->cur_stream = s;
         std::vector<void*> list;
         size_t bytes = 0;
         Vcyc V;
         try {
             if (fp == 64) {
                 alloc_vcyc<double>(h, V, list, bytes);
-                double* bm = dalloc<double>(list, bytes, h->n_dof);
+                double* bm = dalloc<double>(h, list, bytes, h->n_dof);
                 launch_mask_copy<double>(h, (const double*)b_dev, bm, s);
                 vcycle<double>(h, V, bm, (double*)x_dev, nullptr, s);
             } else {
                 alloc_vcyc<float>(h, V, list, bytes);
-                float* bm = dalloc<float>(list, bytes, h->n_dof);
+                float* bm = dalloc<float>(h, list, bytes, h->n_dof);
                 launch_mask_copy<float>(h, (const float*)b_dev, bm, s);
                 vcycle<float>(h, V, bm, (float*)x_dev, nullptr, s);
             }
             TM_HIP(hipStreamSynchronize(s));
         } catch (...) {
             (void)hipStreamSynchronize(s);
-            free_list(list);
+            free_list(h, list);
             throw;
         }
-        free_list(list);
+        free_list(h, list);
     });
 }
 
@@ -1845,6 +1889,7 @@ tm_status tm_stress_stiffness(tm_hierarchy* h, const double* u_dev, double rho_m
         if (!u_dev) fail(TM_ERR_ARG, "u must be a device buffer");
         if (!(rho_min >= 0.0 && rho_min <= 1.0)) fail(TM_ERR_ARG, "rho_min must be in [0, 1]");
         const size_t nst = h->dim == 3 ? 27 : 9;
+        h->cur_stream = S(stream);
         if (!h->gsig) h->gsig = halloc<double>(h, nst * (size_t)h->n_nodes);
         h->gsig_valid = false;
         launch_gsig_assemble(h, u_dev, rho_min, h->gsig, S(stream));
@@ -1891,6 +1936,7 @@ tm_status tm_eigs(tm_hierarchy* h, const tm_eig_options* o, int32_t n_init, cons
         if (!v0_dev || !lambda) fail(TM_ERR_ARG, "start vectors and lambda are required");
         if (!h->gsig_valid) fail(TM_ERR_STATE, "no current stress-stiffness matrix (call tm_stress_stiffness)");
         hipStream_t s = S(stream);
+        h->cur_stream = s;
         if (h->flags_pending) {
             h->flags_pending = false;
             read_flags(h, s, "last update");

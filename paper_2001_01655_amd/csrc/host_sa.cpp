@@ -42,26 +42,18 @@ void sa_to_f32(const double* a, float* b, int64_t n, hipStream_t s);
 namespace {
 
 struct Pool {                       // device allocations with one owner
+    const tm_hierarchy* h;
     std::vector<void*>& list;
     size_t& bytes;
     template <typename T>
     T* get(size_t n) {
-        void* p = nullptr;
         const size_t b = std::max<size_t>(n, 1) * sizeof(T);
-        if (hipMalloc(&p, b) != hipSuccess) {
-            (void)hipGetLastError();
-            fail(TM_ERR_OOM, "hipMalloc of " + std::to_string(b) + " bytes failed (aggregation setup)");
-        }
+        void* p = dev_alloc(h, b);
         list.push_back(p);
         bytes += b;
         return (T*)p;
     }
 };
-
-void free_all(std::vector<void*>& v) {
-    for (void* p : v) (void)hipFree(p);
-    v.clear();
-}
 
 // symbolic + allocation of a BSR product/pattern with nrows block rows
 void make_pattern(Pool& keep, Pool& tmp, BSR& C, int64_t nrows, int64_t ncols, int br, int bc,
@@ -89,7 +81,7 @@ void build_sa_levels(tm_hierarchy* h, hipStream_t s) {
 
 void numeric_sa_levels(tm_hierarchy* h, hipStream_t s) {
     // drop the levels of a previous setup
-    free_all(h->sa_allocs);
+    dev_free_list(h, h->sa_allocs);
     h->bytes -= std::min(h->bytes, h->sa_bytes);
     h->sa_bytes = 0;
     int Lg = 0;
@@ -106,7 +98,7 @@ void numeric_sa_levels(tm_hierarchy* h, hipStream_t s) {
     delete_cached_state(h);      // V-cycle work vectors follow the level list
     if (G0.n < h->opt.max_coarse) return;
 
-    Pool keep{h->sa_allocs, h->sa_bytes};
+    Pool keep{h, h->sa_allocs, h->sa_bytes};
     std::vector<void*> tmp_list, prev_list;
     size_t tmp_bytes = 0, prev_bytes = 0;
     try {
@@ -136,7 +128,7 @@ void numeric_sa_levels(tm_hierarchy* h, hipStream_t s) {
         const double* Bprev = nullptr;
         int cur = Lg - 1;
         while (h->lv[cur].n >= h->opt.max_coarse) {
-            Pool tmp{tmp_list, tmp_bytes};
+            Pool tmp{h, tmp_list, tmp_bytes};
             Level& F = h->lv[cur];
             const int bs = F.bs;
             const int64_t n = F.n_nodes;
@@ -175,10 +167,10 @@ void numeric_sa_levels(tm_hierarchy* h, hipStream_t s) {
             int32_t* mem = tmp.get<int32_t>(n);
             sa_members(n, n_agg, agg, off, cursor, mem, work, s);
             double* T = tmp.get<double>((size_t)n * bs * k);
-            Pool prevp{prev_list, prev_bytes};
+            Pool prevp{h, prev_list, prev_bytes};
             std::vector<void*> next_list;
             size_t next_bytes = 0;
-            Pool nextp{next_list, next_bytes};
+            Pool nextp{h, next_list, next_bytes};
             double* Bc = nextp.get<double>((size_t)n_agg * k * k);
             sa_tentative(n_agg, off, mem, Bprev, dim, F.nn[0], F.nn[1], h->mesh.h, Lg - 1, h->mesh.nel, bs, k, T, Bc,
                          s);
@@ -248,21 +240,21 @@ void numeric_sa_levels(tm_hierarchy* h, hipStream_t s) {
             ++cur;
             // candidates of the next step: the R factors
             TM_HIP(hipStreamSynchronize(s));
-            free_all(tmp_list);
+            dev_free_list(h, tmp_list);
             tmp_bytes = 0;
-            free_all(prev_list);
+            dev_free_list(h, prev_list);
             prev_list = next_list;
             prev_bytes = next_bytes;
             Bprev = Bc;
         }
         TM_HIP(hipStreamSynchronize(s));
-        free_all(tmp_list);
-        free_all(prev_list);
+        dev_free_list(h, tmp_list);
+        dev_free_list(h, prev_list);
         h->bytes += h->sa_bytes;
     } catch (...) {
         (void)hipStreamSynchronize(s);
-        free_all(tmp_list);
-        free_all(prev_list);
+        dev_free_list(h, tmp_list);
+        dev_free_list(h, prev_list);
         throw;
     }
 }

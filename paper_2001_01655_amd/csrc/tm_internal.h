@@ -277,6 +277,11 @@ struct tm_hierarchy {
     // default solve state (tm_solve) and ended states kept for reuse
     tm_solve_state* cached = nullptr;
     std::vector<tm_solve_state*> pool;
+    // device memory source (tm_setup's allocator, else hipMalloc) and the
+    // stream of the call in progress, handed to the allocator
+    tm_allocator alloc{};
+    bool has_alloc = false;
+    hipStream_t cur_stream = nullptr;
 };
 
 struct tm_solve_state {
@@ -329,6 +334,10 @@ struct Lane {
 };
 
 void delete_cached_state(tm_hierarchy* h);
+// device memory of a hierarchy (host.cpp): from its allocator or hipMalloc;
+// a list is returned after the device has finished with it
+void* dev_alloc(const tm_hierarchy* h, size_t bytes);
+void dev_free_list(const tm_hierarchy* h, std::vector<void*>& list);
 
 // ----------------------------------------------------------------- launchers
 // fine level (kernels_fine.hip)

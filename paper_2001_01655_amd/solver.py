@@ -45,7 +45,9 @@ class Hierarchy:
 
     def __init__(self, nel: Sequence[int], rho, fixed, *, h: float = 1.0, p: float = 3.0,
                  E0: float = 1.0, Emin: float = 1e-9, nu: float = 0.3,
-                 stream: Optional[torch.cuda.Stream] = None, **options):
+                 stream: Optional[torch.cuda.Stream] = None, allocator: Optional[str] = "torch", **options):
+        """allocator: "torch" takes the hierarchy's device memory from torch's
+        caching allocator; None lets the library use hipMalloc."""
         self.nel = tuple(int(n) for n in nel)
         self.dim = len(self.nel)
         self.mesh = L.make_mesh(self.nel, h)
@@ -61,8 +63,11 @@ class Hierarchy:
         bcs = L.tm_bcs(len(self._fixed), self._fixed.ctypes.data_as(C.POINTER(C.c_int64)))
         hp = C.c_void_p()
         self._h = None
+        if allocator not in ("torch", None):
+            raise ValueError("allocator must be 'torch' or None")
+        alloc = C.byref(L.TORCH_ALLOCATOR) if allocator == "torch" else None
         check(LIB.tm_setup(C.byref(self.mesh), C.byref(self.mat), C.c_void_p(rho_d.data_ptr()),
-                           C.byref(bcs), C.byref(self.opts), _stream_ptr(stream), C.byref(hp)),
+                           C.byref(bcs), C.byref(self.opts), alloc, _stream_ptr(stream), C.byref(hp)),
               "tm_setup")
         self._h = hp
 

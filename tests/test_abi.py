@@ -42,7 +42,7 @@ def _setup_status(nel=(8, 4), nu=0.3, Emin=1e-9, E0=1.0, dofs=(0, 1), **opts):
     bcs = L.tm_bcs(len(arr), arr.ctypes.data_as(C.POINTER(C.c_int64)))
     h = C.c_void_p()
     # a non-null stand-in for the density buffer: argument checks fail before it is read
-    st = L.LIB.tm_setup(C.byref(mesh), C.byref(mat), C.c_void_p(16), C.byref(bcs), C.byref(o), None,
+    st = L.LIB.tm_setup(C.byref(mesh), C.byref(mat), C.c_void_p(16), C.byref(bcs), C.byref(o), None, None,
                         C.byref(h))
     return st, L.LIB.tm_last_error().decode()
 
@@ -70,9 +70,35 @@ def test_setup_rejects_bad_arguments_before_device_work(kw, msg):
     assert msg in err
 
 
+def test_setup_rejects_an_allocator_without_both_callbacks():
+    mesh = L.make_mesh((8, 4))
+    mat = L.make_material()
+    o = L.default_options()
+    arr = np.asarray((0, 1), dtype=np.int64)
+    bcs = L.tm_bcs(2, arr.ctypes.data_as(C.POINTER(C.c_int64)))
+    h = C.c_void_p()
+    half = L.tm_allocator(L.TORCH_ALLOCATOR.alloc, L.FREE_FN(), None)
+    st = L.LIB.tm_setup(C.byref(mesh), C.byref(mat), C.c_void_p(16), C.byref(bcs), C.byref(o), C.byref(half),
+                        None, C.byref(h))
+    assert st == L.TM_ERR_ARG and "allocator" in L.LIB.tm_last_error().decode()
+    assert not h.value
+
+
+def test_plan_bytes_counts_chebyshev_directions():
+    """Chebyshev smoothing keeps a direction vector per level and right-hand
+    side: the per-RHS increment of the plan grows by at least the fine level's
+    FP32 direction."""
+    mesh = L.make_mesh((32, 16, 16))
+    plan = {(sm, k): L.tm_plan_bytes(mesh, L.default_options(n_levels=3, smoother=sm), k)
+            for sm in (0, 2) for k in (1, 4)}
+    per_rhs_jac = (plan[0, 4] - plan[0, 1]) / 3
+    per_rhs_cheb = (plan[2, 4] - plan[2, 1]) / 3
+    assert per_rhs_cheb - per_rhs_jac >= 4 * 3 * 33 * 17 * 17
+
+
 def test_null_arguments():
     h = C.c_void_p()
-    assert L.LIB.tm_setup(None, None, None, None, None, None, C.byref(h)) == L.TM_ERR_ARG
+    assert L.LIB.tm_setup(None, None, None, None, None, None, None, C.byref(h)) == L.TM_ERR_ARG
     assert L.LIB.tm_solve(None, 1, None, 1e-8, 0, None, None, None, None, None) == L.TM_ERR_ARG
     assert L.LIB.tm_solve_end(None, None, None, None) == L.TM_ERR_STATE
     assert L.LIB.tm_num_levels(None) == 0
