@@ -66,6 +66,8 @@ def parse():
                     help="run only the stability eigenproblem leg and print its record (profiling)")
     ap.add_argument("--no-side-legs", action="store_true",
                     help="skip the multi-RHS and density-filter legs (profiled runs: only the headline solves)")
+    ap.add_argument("--stability", action="store_true",
+                    help="add the stability eigenproblem legs (generalized Davidson on the 2D column)")
     ap.add_argument("--served", type=int, default=24, help="requests in the served-stream leg (0: skip)")
     ap.add_argument("--served-designs", type=int, default=20)
     ap.add_argument("--served-smoother", default="chebyshev", choices=sorted(SMOOTHERS))
@@ -179,6 +181,25 @@ def roofline_entry(cls, launches, total_ms, H, p, args):
     return e
 
 
+def oracle_error(cfg_name, u, c):
+    """Relative error of the headline solution against the oracle's solution at
+    rtol 1e-12 (stored by tests/golden/make_golden.py, which calls only the
+    oracle): u over 4096 seeded free dofs, ||u||_2, and the compliance."""
+    path = os.path.join(ROOT, "tests", "golden", f"solve_{cfg_name}.json")
+    if not os.path.exists(path):
+        return None
+    g = json.load(open(path))
+    import numpy as np
+    idx = np.asarray(g["sample_dofs"], dtype=np.int64)
+    ref = np.asarray(g["sample_u"])
+    uu = u.detach().cpu().numpy().reshape(-1)
+    return {"err_u_sampled": float(np.linalg.norm(uu[idx] - ref) / np.linalg.norm(ref)),
+            "err_norm_u": abs(float(np.linalg.norm(uu)) - g["norm_u"]) / g["norm_u"],
+            "err_c": abs(c - g["compliance"]) / abs(g["compliance"]),
+            "reference": f"oracle FP64 MG-PCG at rtol 1e-12 (true relres {g['oracle']['true_relres']:.1e}), "
+                         f"{len(idx)} sampled dofs"}
+
+
 def cpu_baseline(cfg_name, args):
     """Oracle (CPU, FP64, single thread) on a bounded sample of the same
     recipe; solve to rtol 1e-8 timed, setup excluded."""
@@ -197,19 +218,30 @@ def cpu_baseline(cfg_name, args):
         sample = "2D cantilever recipe at 512x256 (263,682 dofs), 6 levels, three solves to rtol 1e-8, mean"
     else:
         return None
-    with threadpool_limits(limits=1):
-        KE = fem.element_stiffness(p.dim, p.nu)
-        E = fem.simp(p.rho, p.p, p.E0, p.Emin)
-        H = mg.build_geometric(p.nel, E, KE, p.fixed, L, omega=0.5, nu_pre=args.sweeps, nu_post=args.sweeps,
-                               smoother=args.smoother, cheb_lower=args.cheb_lower)
-        reps = 3
+    KE = fem.element_stiffness(p.dim, p.nu)
+    E = fem.simp(p.rho, p.p, p.E0, p.Emin)
+    H = mg.build_geometric(p.nel, E, KE, p.fixed, L, omega=0.5, nu_pre=args.sweeps, nu_post=args.sweeps,
+                           smoother=args.smoother, cheb_lower=args.cheb_lower)
+    reps = 3
+
+    def timed():
         t0 = time.perf_counter()
         for _ in range(reps):
             r = mg.mg_pcg(H, p.loads[0], 1e-8)
-        dt = (time.perf_counter() - t0) / reps
+        return (time.perf_counter() - t0) / reps, r
+
+    with threadpool_limits(limits=1):
+        dt, r = timed()
+    # the same solves with the BLAS thread pool at its default size: SciPy's
+    # sparse products (every operator and transfer) run on one thread either
+    # way; only the dense coarsest solve can use more
+    dt_all, _ = timed()
     return {"value": round(p.n_dof / dt / 1e6, 4), "unit": "MDoF/s", "cores": 1, "kind": "oracle",
             "sample": sample + f", {args.smoother} {args.sweeps}/{args.sweeps} smoothing as on the GPU",
             "seconds": round(dt, 3), "iters": r.iters,
+            "all_cores": {"value": round(p.n_dof / dt_all / 1e6, 4), "seconds": round(dt_all, 3),
+                          "threads_available": os.cpu_count(),
+                          "parallel_parts": "dense coarsest Cholesky solve (BLAS); sparse products single-threaded"},
             "host": platform.processor() or platform.machine(), "host_cpus": os.cpu_count()}
 
 
@@ -575,11 +607,15 @@ def main():
             line["roofline"] = ents[dom]
             line["roofline_other_kernels"] = [ents[c] for c in ents if c != dom]
     u_mixed = res.u.clone()
+    ref = oracle_error(wl["cfg"], u_mixed, res.compliance[0])
+    if ref:
+        line["oracle_error"] = ref
     if not args.no_side_legs:
         line["multi_rhs"] = multi_rhs_leg(H, p)
     H.close()
     if not args.no_side_legs:
         line["density_filter"] = filter_leg(p.nel)
+    if args.stability:
         line["eigen"] = eigen_leg()
         line["stability_stream"] = stability_stream_leg()
     if not args.no_fp64:

@@ -4,8 +4,8 @@
 
 Calls only the oracle (oracle/) and the seeded input generator (synth/).  For
 each case it builds the oracle's FP64 hierarchy on assembled CSR, solves
-K~ u = M f by multigrid-preconditioned CG to a relative residual of 1e-12,
-and writes solve_<case>.json beside this script with:
+K~ u = M f by multigrid-preconditioned CG to a relative residual of 1e-12
+(restarted from its iterate while the true residual is above 1e-11), and writes solve_<case>.json beside this script with:
   * compliance f^T u, ||u||_2, max |u|, the oracle's iterations and its true
     relative residual ||M f - K~ u|| / ||M f||;
   * u at 4096 seeded free dofs (the dof ids are stored with the values);
@@ -33,6 +33,7 @@ import synth  # noqa: E402
 from oracle import fem, mg, sa  # noqa: E402
 
 RTOL = 1e-12
+TRUE_RTOL = 1e-11
 N_SAMPLES = 4096
 
 # case -> (problem factory, hierarchy recipe for the oracle)
@@ -79,16 +80,25 @@ def run(case: str) -> dict:
     f = p.loads[0].copy()
     f[p.fixed] = 0.0
     t0 = time.time()
+    # at high contrast the recursive residual drifts from the true one: restart
+    # from the iterate (a fresh true residual) until the true residual meets
+    # TRUE_RTOL as well
     res = mg.mg_pcg(H, f, RTOL, max_iters=20000)
+    iters, restarts = res.iters, 0
+    while res.true_relres > TRUE_RTOL and restarts < 8:
+        res = mg.mg_pcg(H, f, RTOL, u0=res.u, max_iters=20000)
+        iters += res.iters
+        restarts += 1
+    res.iters = iters
     t_solve = time.time() - t0
-    if not res.converged:
-        raise RuntimeError(f"{case}: the oracle did not reach rtol {RTOL}")
+    if not res.converged or res.true_relres > TRUE_RTOL:
+        raise RuntimeError(f"{case}: the oracle did not reach rtol {RTOL} (true {res.true_relres:.2e})")
     idx = sample_dofs(p)
     out = {
         "case": case,
         "command": "python tests/golden/make_golden.py " + case,
         "inputs": fingerprint(p),
-        "oracle": {"rtol": RTOL, "iters": res.iters, "true_relres": res.true_relres,
+        "oracle": {"rtol": RTOL, "iters": res.iters, "restarts": restarts, "true_relres": res.true_relres,
                    "levels": [int(A.shape[0]) for A in H.A], "recipe": rec,
                    "build_s": round(t_build, 1), "solve_s": round(t_solve, 1)},
         "compliance": float(f @ res.u),
