@@ -201,6 +201,25 @@ tm_status tm_compliance_sensitivity(tm_hierarchy* h, int32_t n_rhs, const double
 tm_status tm_density_filter(const tm_mesh* mesh, double radius, int32_t transpose, const double* in_dev,
                             double* out_dev, void* stream);
 
+/* tm_density_filter for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same filter, same arguments and same results, but the transpose keeps its
+ * intermediate W^-1 in (one FP64 value per element) in a fixed device array of
+ * the library instead of stream-ordered scratch.  The call allocates nothing
+ * (no hipMalloc, hipFree or allocating library routine).
+ *   Limit: at most 8,388,608 elements (the array is 64 MiB; each GPU the library
+ *   runs on holds its own copy until the process ends); larger meshes get
+ *   TM_ERR_ARG before any device work.
+ *   Sharing: every call on one GPU uses that GPU's array, so calls whose device
+ *   work overlaps on one GPU (different streams, or different threads, without
+ *   ordering) race and give wrong results; order them on one stream.  Every
+ *   entry the transpose reads is written earlier in the same call, so no state
+ *   carries over between calls.
+ *   The first call on a device looks up the array's address on that device
+ *   (the device must be current).  Errors as tm_density_filter. */
+tm_status tm_density_filter_noalloc(const tm_mesh* mesh, double radius, int32_t transpose, const double* in_dev,
+                                    double* out_dev, void* stream);
+
 /* ---- stability eigenproblem (Sec. 2 stability maximisation; Sec. 3 eigensolvers,
  * Algorithm 2 generalized Davidson; Sec. 4 column example) ------------------ */
 

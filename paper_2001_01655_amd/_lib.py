@@ -112,6 +112,7 @@ def _load():
         "tm_hierarchy_bytes": (I32, [P, C.POINTER(SZ)]),
         "tm_compliance_sensitivity": (I32, [P, I32, P, P, P]),
         "tm_density_filter": (I32, [C.POINTER(tm_mesh), D, I32, P, P, P]),
+        "tm_density_filter_noalloc": (I32, [C.POINTER(tm_mesh), D, I32, P, P, P]),
         "tm_stress_stiffness": (I32, [P, P, D, P]),
         "tm_apply_stress_stiffness": (I32, [P, P, P, P]),
         "tm_default_eig_options": (None, [C.POINTER(tm_eig_options)]),

@@ -1544,7 +1544,25 @@ tm_status tm_density_filter(const tm_mesh* mesh, double radius, int32_t transpos
         if (transpose != 0 && transpose != 1) fail(TM_ERR_ARG, "transpose must be 0 or 1");
         if (!in_dev || !out_dev) fail(TM_ERR_ARG, "in and out must be device buffers");
         if (in_dev == out_dev) fail(TM_ERR_ARG, "in and out must not overlap");
-        launch_density_filter(mesh->dim, mesh->nel, radius, transpose == 1, in_dev, out_dev, S(stream));
+        launch_density_filter(mesh->dim, mesh->nel, radius, transpose == 1, in_dev, out_dev, nullptr, S(stream));
+        TM_HIP(hipGetLastError());
+    });
+}
+
+tm_status tm_density_filter_noalloc(const tm_mesh* mesh, double radius, int32_t transpose, const double* in_dev,
+                                    double* out_dev, void* stream) {
+    return guarded([&] {
+        check_mesh(mesh);
+        if (!(radius > 0.0 && radius <= 4.0)) fail(TM_ERR_ARG, "radius must be in (0, 4]");
+        if (transpose != 0 && transpose != 1) fail(TM_ERR_ARG, "transpose must be 0 or 1");
+        if (!in_dev || !out_dev) fail(TM_ERR_ARG, "in and out must be device buffers");
+        if (in_dev == out_dev) fail(TM_ERR_ARG, "in and out must not overlap");
+        const int64_t n_el = (int64_t)mesh->nel[0] * mesh->nel[1] * (mesh->dim == 3 ? mesh->nel[2] : 1);
+        if (n_el > FILTER_SCRATCH_MAX)
+            fail(TM_ERR_ARG, "mesh has " + std::to_string(n_el) + " elements; tm_density_filter_noalloc takes at most " +
+                                 std::to_string(FILTER_SCRATCH_MAX));
+        double* scr = transpose == 1 ? filter_scratch() : nullptr;
+        launch_density_filter(mesh->dim, mesh->nel, radius, transpose == 1, in_dev, out_dev, scr, S(stream));
         TM_HIP(hipGetLastError());
     });
 }

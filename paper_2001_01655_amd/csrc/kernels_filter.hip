@@ -2,10 +2,38 @@
 // matrix S; Sec. 4, radius 1.5 element sizes): element-parallel stencil over
 // the elements whose centres lie closer than the radius.
 #include <cmath>
+#include <mutex>
 
 #include "tm_device.h"
 
 namespace tmi {
+
+// Fixed scratch of tm_density_filter_noalloc: the scaled input W^-1 x of the
+// transpose, one FP64 value per element.  Each GPU holds its own copy of this
+// array for the life of the process; host code uses only the device address
+// that hipGetSymbolAddress returns for it (taken once per device, with that
+// device current), never the array's name.
+static __device__ __align__(256) double scratch[FILTER_SCRATCH_MAX];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_dev[MAX_DEVICES] = {};
+}  // namespace
+
+double* filter_scratch() {
+    int dev = 0;
+    TM_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= MAX_DEVICES) fail(TM_ERR_DEVICE, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        TM_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) fail(TM_ERR_DEVICE, "no device address for the filter scratch");
+        g_scratch_dev[dev] = (double*)p;
+    }
+    return g_scratch_dev[dev];
+}
 
 // cone weights max(0, r - |d|) of the (2R+1)^DIM offsets d, x fastest
 template <int DIM, int R>
@@ -165,7 +193,7 @@ __global__ __launch_bounds__(WG) void k_filter_scale(const double* __restrict__ 
 
 template <int DIM, int R>
 static void filter_run(int nx, int ny, int nz, double r, bool tr, const double* in, double* out,
-                       hipStream_t s) {
+                       double* fixed_scratch, hipStream_t s) {
     constexpr int W = 2 * R + 1;
     ConeW<DIM, R> cw;
     for (int o = 0; o < ConeW<DIM, R>::N; ++o) {
@@ -190,21 +218,23 @@ static void filter_run(int nx, int ny, int nz, double r, bool tr, const double* 
         apply(in, out, true);
         return;
     }
-    double* t = nullptr;            // stream-ordered scratch for W^-1 in
-    TM_HIP(hipMallocAsync((void**)&t, (size_t)n * sizeof(double), s));
+    // W^-1 in: the caller's fixed scratch, else stream-ordered scratch; every
+    // entry is written by the scaling kernel before it is read
+    double* t = fixed_scratch;
+    if (!t) TM_HIP(hipMallocAsync((void**)&t, (size_t)n * sizeof(double), s));
     hipLaunchKernelGGL((k_filter_scale<DIM, R>), g, b, 0, s, in, t, nx, ny, nz, cw);
     apply(t, out, false);
-    TM_HIP(hipFreeAsync(t, s));
+    if (!fixed_scratch) TM_HIP(hipFreeAsync(t, s));
 }
 
 void launch_density_filter(int dim, const int* nel, double r, bool tr, const double* in, double* out,
-                           hipStream_t s) {
+                           double* fixed_scratch, hipStream_t s) {
     // stencil half-width: offsets up to ceil(r) - 1 can lie closer than r
     const int R = (int)std::ceil(r) - 1;
     const int nz = dim == 3 ? nel[2] : 1;
 #define TM_FL(RR)                                                             \
-    if (dim == 3) filter_run<3, RR>(nel[0], nel[1], nz, r, tr, in, out, s);   \
-    else filter_run<2, RR>(nel[0], nel[1], 1, r, tr, in, out, s);
+    if (dim == 3) filter_run<3, RR>(nel[0], nel[1], nz, r, tr, in, out, fixed_scratch, s);   \
+    else filter_run<2, RR>(nel[0], nel[1], 1, r, tr, in, out, fixed_scratch, s);
     switch (R) {
         case 0: TM_FL(0) break;
         case 1: TM_FL(1) break;

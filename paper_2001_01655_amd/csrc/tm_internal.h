@@ -353,8 +353,14 @@ struct ChebArgs {
 void launch_simp(const double* rho, int64_t n_el, double p, double E0, double Emin, double* E64,
                  float* E32, double* rho64, int* flags, hipStream_t s);
 void launch_sensitivity(const tm_hierarchy* h, int n_rhs, const double* u, double* dc, hipStream_t s);
+// fixed_scratch: n_el FP64 device values for the transpose (NULL: stream-ordered
+// scratch allocated by the call)
 void launch_density_filter(int dim, const int* nel, double r, bool tr, const double* in, double* out,
-                           hipStream_t s);
+                           double* fixed_scratch, hipStream_t s);
+// largest element count of tm_density_filter_noalloc, and the device address of
+// its fixed scratch on the current device
+constexpr int64_t FILTER_SCRATCH_MAX = (int64_t)1 << 23;
+double* filter_scratch();
 void launch_fine_dinv(const Level& L, const double* KE64, int point_jacobi, int* flags,
                       hipStream_t s);
 template <typename T>
