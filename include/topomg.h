@@ -285,19 +285,32 @@ tm_status tm_eigs(tm_hierarchy* h, const tm_eig_options* o, int32_t n_init, cons
 /* Iteration-level control for a scheduler (continuous batching).
  * begin:   copies f, sets up the start vector on `stream` and returns a state
  *          bound to (h, stream, u_dev); u_dev must stay valid until end.
- * advance: enqueues up to k further iterations without waiting.
+ * advance: enqueues up to k further iterations on the state's stream without
+ *          waiting.
  * poll:    non-blocking; *done = 1 once every right-hand side has stopped, 0 when
  *          the enqueued iterations have finished without that, -1 while they
  *          are still running.
- * batch_advance: advance for n states at once (each on its own stream, so the
- *          work of different requests overlaps on the device).
+ * batch_iterate: k further iterations of n states (of one or several
+ *          hierarchies), enqueued on `stream` as grouped launches: the
+ *          right-hand sides of all states whose hierarchies have the same level
+ *          structure and options (level kinds and sizes, smoother, sweeps,
+ *          precision, outer method, element stiffness) advance together, each
+ *          operation of an iteration (operators and transfers per level,
+ *          coarsest solve, Krylov updates and reductions) one launch for up to
+ *          8 right-hand sides; aggregation levels, whose operators differ per
+ *          hierarchy, are applied per right-hand side in the same sequence.
+ *          `stream` first waits for the work queued on each state's own stream,
+ *          and each state's stream waits for the batch, so later calls on a
+ *          state stay ordered.  Every right-hand side computes exactly what it
+ *          computes alone.  A state may appear only once in the list.
  * end:     waits, writes the outputs of tm_solve and releases the state (its
- *          device buffers stay with the hierarchy for the next begin). */
+ *          device buffers stay with the hierarchy for the next begin).
+ * The right-hand sides of one state always share launches (also in tm_solve). */
 tm_status tm_solve_begin(tm_hierarchy* h, int32_t n_rhs, const double* f_dev, double rtol,
                          int32_t use_u0, double* u_dev, void* stream, tm_solve_state** st);
 tm_status tm_solve_advance(tm_solve_state* st, int32_t k_iters);
 tm_status tm_solve_poll(tm_solve_state* st, int32_t* done);
-tm_status tm_batch_advance(int32_t n, tm_solve_state* const* st, int32_t k_iters);
+tm_status tm_batch_iterate(int32_t n, tm_solve_state* const* st, int32_t k_iters, void* stream);
 tm_status tm_solve_end(tm_solve_state* st, int32_t* iters, double* compliance, double* relres);
 
 /* ---- parity and inspection (tests) --------------------------------------- */

@@ -10,7 +10,7 @@ from ._lib import (LIB, TmError, check, default_options, make_material, make_mes
 def __getattr__(name):
     # torch-facing classes are imported lazily so that the C ABI can be
     # inspected without initialising torch
-    if name in ("Hierarchy", "SolveState", "SolveResult", "tm_batch_advance", "density_filter"):
+    if name in ("Hierarchy", "SolveState", "SolveResult", "tm_batch_iterate", "density_filter"):
         from . import solver
         return getattr(solver, name)
     raise AttributeError(name)

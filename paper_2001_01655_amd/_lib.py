@@ -98,7 +98,7 @@ def _load():
         "tm_solve_begin": (I32, [P, I32, P, D, I32, P, P, C.POINTER(P)]),
         "tm_solve_advance": (I32, [P, I32]),
         "tm_solve_poll": (I32, [P, C.POINTER(I32)]),
-        "tm_batch_advance": (I32, [I32, C.POINTER(P), I32]),
+        "tm_batch_iterate": (I32, [I32, C.POINTER(P), I32, P]),
         "tm_solve_end": (I32, [P, P, P, P]),
         "tm_apply": (I32, [P, I32, I32, P, P, P]),
         "tm_vcycle": (I32, [P, I32, P, P, P]),

@@ -473,24 +473,50 @@ static void timed_end(tm_hierarchy* h, int cls, hipStream_t s, hipEvent_t e0) {
     h->tev[cls].push_back({e0, e1});
 }
 
+// one operator application on level l for lanes io[0..n) (hierarchies with
+// the same level structure as io[0].h; Chebyshev coefficients c1, c2 are the
+// same for all lanes, the directions are the lanes' own)
 template <typename T>
-static void level_op(tm_hierarchy* h, int l, int op, const T* x, const T* b, T* y, const int* done,
-                     hipStream_t s, const ChebArgs& ch = ChebArgs{}) {
+static void level_op_b(int l, int op, const LaneIO* io, int n, hipStream_t s, double c1 = 0.0, double c2 = 0.0) {
+    tm_hierarchy* h = const_cast<tm_hierarchy*>(io[0].h);
     Level& L = h->lv[l];
     const T w = (T)h->opt.omega;
     hipEvent_t e0 = nullptr;
     if (L.kind == TM_LEVEL_FINE) {
         timed_begin(h, 1, s, &e0);
-        launch_fine_op<T>(h, op, false, x, b, y, w, done, nullptr, s, ch);
+        launch_fine_op_b<T>(op, false, io, n, w, c1, c2, s);
         timed_end(h, 1, s, e0);
     } else if (L.kind == TM_LEVEL_GEOMETRIC) {
         const int cls = l == 1 ? 2 : -1;
         if (cls >= 0) timed_begin(h, cls, s, &e0);
-        launch_stencil_op<T>(L, op, x, b, y, w, done, s, ch);
+        launch_stencil_op_b<T>(l, op, io, n, w, c1, c2, s);
         if (cls >= 0) timed_end(h, cls, s, e0);
     } else {
-        launch_bsr_op<T>(L, op, x, b, y, w, done, s, ch);
+        // aggregation levels: each lane's own operator (sizes depend on its data)
+        for (int q = 0; q < n; ++q) {
+            ChebArgs ch;
+            ch.din = io[q].din;
+            ch.dout = io[q].dout;
+            ch.c1 = c1;
+            ch.c2 = c2;
+            launch_bsr_op<T>(io[q].h->lv[l], op, (const T*)io[q].x, (const T*)io[q].b, (T*)io[q].y, w, io[q].done,
+                             s, ch);
+        }
     }
+}
+
+template <typename T>
+static void level_op(tm_hierarchy* h, int l, int op, const T* x, const T* b, T* y, const int* done,
+                     hipStream_t s, const ChebArgs& ch = ChebArgs{}) {
+    LaneIO io{};
+    io.h = h;
+    io.x = x;
+    io.b = b;
+    io.y = y;
+    io.done = done;
+    io.din = ch.din;
+    io.dout = ch.dout;
+    level_op_b<T>(l, op, &io, 1, s, ch.c1, ch.c2);
 }
 
 // largest eigenvalue of D^-1 A on level l: 12 power steps from a hashed start
@@ -533,91 +559,165 @@ static void cheb_interval(tm_hierarchy* h, int l, hipStream_t s, bool warm) {
     launch_scale_dinv(L, h->cheb_theta + l, s);
 }
 
+// restriction from level l for lanes io (x: fine residual, y: coarse right-hand
+// side, y2: the coarse level's first sweep, or NULL at the coarsest level)
 template <typename T>
-static void restrict_to(tm_hierarchy* h, int l, const T* r, T* bc, T* xc_first, const int* done,
-                        hipStream_t s) {
-    Level& F = h->lv[l];
-    Level& C = h->lv[l + 1];
+static void restrict_b(int l, const LaneIO* io, int n, hipStream_t s) {
+    const tm_hierarchy* h = io[0].h;
     const T w = (T)first_sweep_weight(h, l + 1);
-    if (F.xfer_bsr)
-        launch_bsr_restrict<T>(F, r, bc, C, xc_first, w, done, s);
-    else
-        launch_restrict<T>(F, C, r, bc, xc_first, w, done, s);
+    if (h->lv[l].xfer_bsr) {
+        for (int q = 0; q < n; ++q)
+            launch_bsr_restrict<T>(io[q].h->lv[l], (const T*)io[q].x, (T*)io[q].y, io[q].h->lv[l + 1], (T*)io[q].y2, w,
+                                   io[q].done, s);
+    } else {
+        launch_restrict_b<T>(l, io, n, w, s);
+    }
 }
 
+// prolongation to level l for lanes io (x: coarse correction, y: fine iterate)
 template <typename T>
-static void prolong_from(tm_hierarchy* h, int l, const T* xc, T* xf, const int* done, hipStream_t s) {
-    Level& F = h->lv[l];
-    if (F.xfer_bsr)
-        launch_bsr_prolong<T>(F, xc, xf, done, s);
-    else
-        launch_prolong<T>(F, h->lv[l + 1], xc, xf, done, s);
+static void prolong_b(int l, const LaneIO* io, int n, hipStream_t s) {
+    const tm_hierarchy* h = io[0].h;
+    if (h->lv[l].xfer_bsr) {
+        for (int q = 0; q < n; ++q)
+            launch_bsr_prolong<T>(io[q].h->lv[l], (const T*)io[q].x, (T*)io[q].y, io[q].done, s);
+    } else {
+        launch_prolong_b<T>(l, io, n, s);
+    }
 }
 
-// z = V(b0) on level 0 (Algorithm 1 from x = 0).  Work vectors of level l:
-// V.b[l] (l > 0), V.x[l], V.t[l].  The last post-smoothing sweep writes z.
+// One lane of a batched V-cycle: its hierarchy, work vectors, input (level 0)
+// and output.  The lanes of one call share their level structure.
 template <typename T>
-static void vcycle(tm_hierarchy* h, Vcyc& V, const T* b0, T* z, const int* done, hipStream_t s,
-                   bool first_done = false) {
-    const int L = (int)h->lv.size();
-    const int npre = h->opt.nu_pre, npost = h->opt.nu_post;
-    const bool cheb = h->opt.smoother == TM_SMOOTH_CHEBYSHEV;
-    std::vector<T*> xr(L), tr(L);
+struct VLane {
+    tm_hierarchy* h;
+    Vcyc* V;
+    const T* b0;
+    T* z;
+    const int* done;
+};
+
+// z = V(b0) on level 0 (Algorithm 1 from x = 0) for every lane, each operation
+// one launch for all lanes.  Work vectors of level l: V.b[l] (l > 0), V.x[l],
+// V.t[l].  The last post-smoothing sweep writes z.  With first_done the fine
+// level's first sweep was produced by the u, r update.
+template <typename T>
+static void vcycle_b(const VLane<T>* lanes, int n, hipStream_t s, bool first_done = false) {
+    tm_hierarchy* h0 = lanes[0].h;
+    const int L = (int)h0->lv.size();
+    const int npre = h0->opt.nu_pre, npost = h0->opt.nu_post;
+    const bool cheb = h0->opt.smoother == TM_SMOOTH_CHEBYSHEV;
+    // per level and lane: the iterate and the scratch vector (swapped after each sweep)
+    std::vector<std::vector<T*>> xr(L, std::vector<T*>(n)), tr(L, std::vector<T*>(n));
+    std::vector<LaneIO> io(n);
+    for (int q = 0; q < n; ++q) {
+        io[q] = LaneIO{};
+        io[q].h = lanes[q].h;
+        io[q].done = lanes[q].done;
+    }
+    auto bvec = [&](int l, int q) -> T* { return l == 0 ? const_cast<T*>(lanes[q].b0) : vb<T>(*lanes[q].V, l); };
     // Chebyshev step k on level l (k = 0: from the current iterate with no
     // previous direction): coefficients of d_k = c1 d_{k-1} + c2 D^-1 r_k.
     // After a zero start the direction d_0 is the first iterate itself.
     // The stored D^-1 is divided by theta_l, so c2 here is the textbook one
     // times theta_l; with sigma = theta / delta = (1.1 + lower) / (1.1 - lower)
     // neither coefficient depends on the eigenvalue estimate.
-    auto cheb_args = [&](int l, int k, const T* x, bool zero_start, bool last) {
-        const double lo = h->opt.cheb_lower, sigma = (1.1 + lo) / (1.1 - lo);
-        double rho = 1.0 / sigma, c1 = 0.0, c2 = 1.0;
+    auto cheb_coef = [&](int k, double& c1, double& c2) {
+        const double lo = h0->opt.cheb_lower, sigma = (1.1 + lo) / (1.1 - lo);
+        double rho = 1.0 / sigma;
+        c1 = 0.0;
+        c2 = 1.0;
         for (int q = 1; q <= k; ++q) {
             const double rn = 1.0 / (2.0 * sigma - rho);
             c1 = rn * rho;
             c2 = 2.0 * rn * sigma;
             rho = rn;
         }
-        ChebArgs ch;
-        ch.din = (k == 0 || (k == 1 && zero_start)) ? (const void*)x : V.d[l];
-        ch.dout = last ? nullptr : V.d[l];   // the last step of a smoothing phase leaves no direction behind
-        ch.c1 = k == 0 ? 0.0 : c1;
-        ch.c2 = c2;
-        return ch;
+        if (k == 0) c1 = 0.0;
+    };
+    // one smoothing step on level l from the lanes' x into dst (dst(q))
+    auto smooth = [&](int l, int k, bool zero_start, bool last, const std::vector<T*>& x,
+                      const std::vector<T*>& dst) {
+        double c1 = 0.0, c2 = 0.0;
+        if (cheb) cheb_coef(k, c1, c2);
+        for (int q = 0; q < n; ++q) {
+            io[q].x = x[q];
+            io[q].b = bvec(l, q);
+            io[q].y = dst[q];
+            io[q].din = nullptr;
+            io[q].dout = nullptr;
+            if (cheb) {
+                void* d = lanes[q].V->d[l];
+                io[q].din = (k == 0 || (k == 1 && zero_start)) ? (const void*)x[q] : d;
+                io[q].dout = last ? nullptr : d;     // the last step of a phase leaves no direction behind
+            }
+        }
+        level_op_b<T>(l, cheb ? OP_CHEB : OP_SMOOTH, io.data(), n, s, c1, c2);
     };
     for (int l = 0; l < L - 1; ++l) {
-        const T* b = l == 0 ? b0 : vb<T>(V, l);
-        T* x = vx<T>(V, l);
-        T* t = vt<T>(V, l);
-        if (l == 0 && !first_done) launch_first_smooth<T>(h->lv[0], b, x, (T)first_sweep_weight(h, 0), done, s);
+        std::vector<T*>& x = xr[l];
+        std::vector<T*>& t = tr[l];
+        for (int q = 0; q < n; ++q) {
+            x[q] = vx<T>(*lanes[q].V, l);
+            t[q] = vt<T>(*lanes[q].V, l);
+        }
+        if (l == 0 && !first_done) {
+            for (int q = 0; q < n; ++q) {
+                io[q].b = bvec(0, q);
+                io[q].y = x[q];
+            }
+            launch_first_smooth_b<T>(0, io.data(), n, (T)first_sweep_weight(h0, 0), s);
+        }
         for (int k = 1; k < npre; ++k) {
             // from a zero start the first step's direction is the first iterate
-            if (cheb) level_op<T>(h, l, OP_CHEB, x, b, t, done, s, cheb_args(l, k, x, true, k == npre - 1));
-            else level_op<T>(h, l, OP_SMOOTH, x, b, t, done, s);
+            smooth(l, k, true, k == npre - 1, x, t);
             std::swap(x, t);
         }
-        level_op<T>(h, l, OP_RESID, x, b, t, done, s);
-        T* xc_first = (l + 1 < L - 1) ? vx<T>(V, l + 1) : nullptr;
-        restrict_to<T>(h, l, t, vb<T>(V, l + 1), xc_first, done, s);
-        xr[l] = x;
-        tr[l] = t;
-    }
-    launch_dense_solve<T>(h->ainv, h->nc, vb<T>(V, L - 1), vx<T>(V, L - 1), done, s);
-    xr[L - 1] = vx<T>(V, L - 1);
-    for (int l = L - 2; l >= 0; --l) {
-        const T* b = l == 0 ? b0 : vb<T>(V, l);
-        T* x = xr[l];
-        T* t = tr[l];
-        prolong_from<T>(h, l, xr[l + 1], x, done, s);
-        for (int k = 0; k < npost; ++k) {
-            T* dst = (l == 0 && k == npost - 1) ? z : t;
-            if (cheb) level_op<T>(h, l, OP_CHEB, x, b, dst, done, s, cheb_args(l, k, x, false, k == npost - 1));
-            else level_op<T>(h, l, OP_SMOOTH, x, b, dst, done, s);
-            if (!(l == 0 && k == npost - 1)) std::swap(x, t);
+        for (int q = 0; q < n; ++q) {
+            io[q].x = x[q];
+            io[q].b = bvec(l, q);
+            io[q].y = t[q];
+            io[q].din = nullptr;
+            io[q].dout = nullptr;
         }
-        xr[l] = x;
-        tr[l] = t;
+        level_op_b<T>(l, OP_RESID, io.data(), n, s);
+        for (int q = 0; q < n; ++q) {
+            io[q].x = t[q];
+            io[q].y = vb<T>(*lanes[q].V, l + 1);
+            io[q].y2 = (l + 1 < L - 1) ? vx<T>(*lanes[q].V, l + 1) : nullptr;
+        }
+        restrict_b<T>(l, io.data(), n, s);
+        for (int q = 0; q < n; ++q) io[q].y2 = nullptr;
     }
+    for (int q = 0; q < n; ++q) {
+        io[q].x = vb<T>(*lanes[q].V, L - 1);
+        io[q].y = vx<T>(*lanes[q].V, L - 1);
+        xr[L - 1][q] = vx<T>(*lanes[q].V, L - 1);
+    }
+    launch_dense_solve_b<T>(io.data(), n, s);
+    for (int l = L - 2; l >= 0; --l) {
+        std::vector<T*>& x = xr[l];
+        std::vector<T*>& t = tr[l];
+        for (int q = 0; q < n; ++q) {
+            io[q].x = xr[l + 1][q];
+            io[q].y = x[q];
+        }
+        prolong_b<T>(l, io.data(), n, s);
+        for (int k = 0; k < npost; ++k) {
+            const bool to_z = l == 0 && k == npost - 1;
+            std::vector<T*> dst(n);
+            for (int q = 0; q < n; ++q) dst[q] = to_z ? lanes[q].z : t[q];
+            smooth(l, k, false, k == npost - 1, x, dst);
+            if (!to_z) std::swap(x, t);
+        }
+    }
+}
+
+template <typename T>
+static void vcycle(tm_hierarchy* h, Vcyc& V, const T* b0, T* z, const int* done, hipStream_t s,
+                   bool first_done = false) {
+    const VLane<T> ln{h, &V, b0, z, done};
+    vcycle_b<T>(&ln, 1, s, first_done);
 }
 
 template <typename T>
@@ -678,59 +778,17 @@ static tm_solve_state* new_state(tm_hierarchy* h, int nrhs) {
         TM_HIP(hipMemset(st->sc, 0, sizeof(KScal) * nrhs));
         TM_HIP(hipHostMalloc((void**)&st->sc_host, sizeof(KScal) * nrhs, hipHostMallocDefault));
         TM_HIP(hipEventCreateWithFlags(&st->ev, hipEventDisableTiming));
+        TM_HIP(hipEventCreateWithFlags(&st->order, hipEventDisableTiming));
     } catch (...) {
         free_list(st->h, st->allocs);
         for (Lane* ln : st->lanes) delete ln;
         if (st->sc_host) (void)hipHostFree(st->sc_host);
-        for (hipStream_t q : st->ls) (void)hipStreamDestroy(q);
-        for (hipEvent_t e : st->lev) (void)hipEventDestroy(e);
-        if (st->fork) (void)hipEventDestroy(st->fork);
+        if (st->order) (void)hipEventDestroy(st->order);
         if (st->ev) (void)hipEventDestroy(st->ev);
         delete st;
         throw;
     }
     return st;
-}
-
-// streams of their own for right-hand sides 1.. (tm_solve's cached state)
-static void make_lane_streams(tm_solve_state* st) {
-    if (st->nrhs < 2 || !st->ls.empty()) return;
-    try {
-        TM_HIP(hipEventCreateWithFlags(&st->fork, hipEventDisableTiming));
-        for (int k = 1; k < st->nrhs; ++k) {
-            hipStream_t q = nullptr;
-            TM_HIP(hipStreamCreateWithFlags(&q, hipStreamNonBlocking));     // default priority
-            st->ls.push_back(q);
-            hipEvent_t e = nullptr;
-            TM_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-            st->lev.push_back(e);
-        }
-    } catch (...) {
-        // all lanes on the state's stream, as for scheduler-driven states
-        for (hipStream_t q : st->ls) (void)hipStreamDestroy(q);
-        for (hipEvent_t e : st->lev) (void)hipEventDestroy(e);
-        st->ls.clear();
-        st->lev.clear();
-        throw;
-    }
-}
-
-// stream of right-hand side k, and the fork / join around a batch of work
-static hipStream_t lane_stream(const tm_solve_state* st, int k) {
-    return (k == 0 || st->ls.empty()) ? st->s : st->ls[k - 1];
-}
-
-static void fork_lanes(tm_solve_state* st) {
-    if (st->ls.empty()) return;
-    TM_HIP(hipEventRecord(st->fork, st->s));
-    for (hipStream_t q : st->ls) TM_HIP(hipStreamWaitEvent(q, st->fork, 0));
-}
-
-static void join_lanes(tm_solve_state* st) {
-    for (size_t k = 0; k < st->ls.size(); ++k) {
-        TM_HIP(hipEventRecord(st->lev[k], st->ls[k]));
-        TM_HIP(hipStreamWaitEvent(st->s, st->lev[k], 0));
-    }
 }
 
 static void delete_state(tm_solve_state* st);
@@ -749,79 +807,131 @@ void delete_cached_state(tm_hierarchy* h) {
 
 static void delete_state(tm_solve_state* st) {
     if (!st) return;
-    for (hipStream_t q : st->ls) (void)hipStreamSynchronize(q);
     free_list(st->h, st->allocs);
     for (Lane* ln : st->lanes) delete ln;
     if (st->sc_host) (void)hipHostFree(st->sc_host);
     if (st->ev) (void)hipEventDestroy(st->ev);
-    if (st->fork) (void)hipEventDestroy(st->fork);
-    for (hipEvent_t e : st->lev) (void)hipEventDestroy(e);
-    for (hipStream_t q : st->ls) (void)hipStreamDestroy(q);
+    if (st->order) (void)hipEventDestroy(st->order);
     delete st;
 }
 
-// z = V(r); with first_done the fine level's first sweep was produced by the u, r update
-static void enqueue_vcycle_into_z(tm_hierarchy* h, Lane& ln, const int* done, hipStream_t s,
-                                  bool first_done) {
-    if (mixed_of(h))
-        vcycle<float>(h, ln.v32, ln.r32, ln.z32, done, s, first_done);
-    else
-        vcycle<double>(h, ln.v64, ln.r, ln.z64, done, s, first_done);
+// the lanes of a state (one per right-hand side) as batched-launch lanes
+static void state_lanes(tm_solve_state* st, std::vector<LaneIO>& out) {
+    for (int k = 0; k < st->nrhs; ++k) {
+        LaneIO l{};
+        l.h = st->h;
+        l.ln = st->lanes[k];
+        l.sc = st->sc + k;
+        l.done = &st->sc[k].done;
+        l.part = st->lanes[k]->part;
+        l.u = st->u + (size_t)k * st->h->n_dof;
+        out.push_back(l);
+    }
+}
+
+// z = V(r) for lanes io; with first_done the fine level's first sweep was
+// produced by the u, r update
+static void vcycle_lanes(const std::vector<LaneIO>& io, hipStream_t s, bool first_done) {
+    const int n = (int)io.size();
+    tm_hierarchy* h = const_cast<tm_hierarchy*>(io[0].h);
+    if (mixed_of(h)) {
+        std::vector<VLane<float>> v(n);
+        for (int q = 0; q < n; ++q)
+            v[q] = VLane<float>{const_cast<tm_hierarchy*>(io[q].h), &io[q].ln->v32, io[q].ln->r32, io[q].ln->z32,
+                                io[q].done};
+        vcycle_b<float>(v.data(), n, s, first_done);
+    } else {
+        std::vector<VLane<double>> v(n);
+        for (int q = 0; q < n; ++q)
+            v[q] = VLane<double>{const_cast<tm_hierarchy*>(io[q].h), &io[q].ln->v64, io[q].ln->r, io[q].ln->z64,
+                                 io[q].done};
+        vcycle_b<double>(v.data(), n, s, first_done);
+    }
 }
 
 static void enqueue_begin(tm_solve_state* st, const double* f, int use_u0) {
     tm_hierarchy* h = st->h;
     const int64_t n = h->n_dof;
     const bool mixed = mixed_of(h);
-    fork_lanes(st);
+    hipStream_t s = st->s;
+    std::vector<LaneIO> io;
+    state_lanes(st, io);
     for (int k = 0; k < st->nrhs; ++k) {
-        hipStream_t s = lane_stream(st, k);
         Lane& ln = *st->lanes[k];
-        KScal* sc = st->sc + k;
-        double* u = st->u + (size_t)k * n;
         launch_mask_copy<double>(h, f + (size_t)k * n, ln.f, s);
-        launch_fcg_init(h, ln, sc, use_u0, u, st->rtol, h->opt.max_iters, h->opt.outer, s);
+        launch_fcg_init(h, ln, st->sc + k, use_u0, io[k].u, st->rtol, h->opt.max_iters, h->opt.outer, s);
         if (mixed) launch_cast(ln.r, ln.r32, n, s);
-        const int* done = &sc->done;
-        enqueue_vcycle_into_z(h, ln, done, s, false);
-        launch_zdots(h, ln, sc, mixed, s);
-        launch_finalize(sc, ln.part, krylov_blocks(n), FIN_BETA, s);
-        TM_HIP(hipMemsetAsync(ln.p, 0, n * sizeof(double), s));
-        launch_update_p(h, ln, sc, mixed, s);
     }
-    join_lanes(st);
+    vcycle_lanes(io, s, false);
+    launch_zdots_b(io.data(), st->nrhs, mixed, s);
+    launch_finalize_b(io.data(), st->nrhs, krylov_blocks(n), FIN_BETA, s);
+    for (int k = 0; k < st->nrhs; ++k) TM_HIP(hipMemsetAsync(st->lanes[k]->p, 0, n * sizeof(double), s));
+    launch_update_p_b(io.data(), st->nrhs, mixed, s);
 }
 
-static void enqueue_iteration(tm_solve_state* st, int k) {
-    tm_hierarchy* h = st->h;
-    hipStream_t s = lane_stream(st, k);
-    const int64_t n = h->n_dof;
+// one outer iteration for lanes io (hierarchies with the same level structure
+// and options), every operation one launch for all lanes
+static void enqueue_iteration_b(const std::vector<LaneIO>& lanes, hipStream_t s) {
+    tm_hierarchy* h = const_cast<tm_hierarchy*>(lanes[0].h);
+    const int n = (int)lanes.size();
+    const int64_t nd = h->n_dof;
     const bool mixed = mixed_of(h);
-    Lane& ln = *st->lanes[k];
-    KScal* sc = st->sc + k;
-    const int* done = &sc->done;
-    double* u = st->u + (size_t)k * n;
+    std::vector<LaneIO> io(lanes);
+    for (int q = 0; q < n; ++q) {
+        io[q].x = io[q].ln->p;
+        io[q].b = io[q].ln->r;
+        io[q].y = io[q].ln->q;
+    }
     hipEvent_t e0 = nullptr;
     timed_begin(h, 0, s, &e0);
-    launch_fine_op<double>(h, OP_QDOT, false, ln.p, ln.r, ln.q, 0.0, done, ln.part, s);
+    launch_fine_op_b<double>(OP_QDOT, false, io.data(), n, 0.0, 0.0, 0.0, s);
     timed_end(h, 0, s, e0);
-    launch_finalize(sc, ln.part, fine_op_blocks(h), FIN_ALPHA, s);
-    launch_update_ur(h, ln, sc, u, mixed, s);
-    launch_finalize(sc, ln.part, update_ur_blocks(h), FIN_RR, s);
-    enqueue_vcycle_into_z(h, ln, done, s, true);
-    launch_zdots(h, ln, sc, mixed, s);
-    launch_finalize(sc, ln.part, krylov_blocks(n), FIN_BETA, s);
-    launch_update_p(h, ln, sc, mixed, s);
+    launch_finalize_b(io.data(), n, fine_op_blocks(h), FIN_ALPHA, s);
+    launch_update_ur_b(io.data(), n, mixed, s);
+    launch_finalize_b(io.data(), n, update_ur_blocks(h), FIN_RR, s);
+    vcycle_lanes(lanes, s, true);
+    launch_zdots_b(io.data(), n, mixed, s);
+    launch_finalize_b(io.data(), n, krylov_blocks(nd), FIN_BETA, s);
+    launch_update_p_b(io.data(), n, mixed, s);
+}
+
+// the pinned mirror of the scalars and the completion event of a state, after
+// its work enqueued on stream s
+static void state_sync_point(tm_solve_state* st, hipStream_t s) {
+    TM_HIP(hipMemcpyAsync(st->sc_host, st->sc, sizeof(KScal) * st->nrhs, hipMemcpyDeviceToHost, s));
+    TM_HIP(hipEventRecord(st->ev, s));
+    if (s != st->s) TM_HIP(hipStreamWaitEvent(st->s, st->ev, 0));
+    st->pending = true;
 }
 
 static void enqueue_advance(tm_solve_state* st, int k_iters) {
-    fork_lanes(st);
-    for (int it = 0; it < k_iters; ++it)
-        for (int k = 0; k < st->nrhs; ++k) enqueue_iteration(st, k);
-    join_lanes(st);
-    TM_HIP(hipMemcpyAsync(st->sc_host, st->sc, sizeof(KScal) * st->nrhs, hipMemcpyDeviceToHost, st->s));
-    TM_HIP(hipEventRecord(st->ev, st->s));
-    st->pending = true;
+    std::vector<LaneIO> io;
+    state_lanes(st, io);
+    for (int it = 0; it < k_iters; ++it) enqueue_iteration_b(io, st->s);
+    state_sync_point(st, st->s);
+}
+
+// Lanes whose hierarchies can share launches: the same level list (kinds,
+// sizes, block sizes, transfers, operator kernels, coarsest size) and the same
+// solver options and element stiffness.
+static std::string shape_key(const tm_hierarchy* h) {
+    std::string k;
+    auto put = [&](const void* p, size_t n) { k.append((const char*)p, n); };
+    const tm_options& o = h->opt;
+    const int ints[] = {h->dim, o.smoother, o.nu_pre, o.nu_post, o.vcycle_fp, o.outer, o.fine_mfma,
+                        (int)h->lv.size()};
+    put(ints, sizeof(ints));
+    const double dbl[] = {o.omega, o.cheb_lower};
+    put(dbl, sizeof(dbl));
+    put(&h->n_dof, sizeof(h->n_dof));
+    put(&h->nc, sizeof(h->nc));
+    put(h->kc64.k, sizeof(h->kc64.k));
+    for (const Level& L : h->lv) {
+        const int li[] = {L.kind, L.bs, L.nel[0], L.nel[1], L.nel[2], (int)L.xfer_bsr, L.op_kernel};
+        put(li, sizeof(li));
+        put(&L.n, sizeof(L.n));
+    }
+    return k;
 }
 
 static bool state_done(tm_solve_state* st) {
@@ -1592,7 +1702,6 @@ static tm_status begin_impl(tm_hierarchy* h, int32_t n_rhs, const double* f_dev,
             if (!h->cached) {
                 h->cached = new_state(h, n_rhs);
                 h->cached->owned_by_h = true;
-                make_lane_streams(h->cached);
             }
             st = h->cached;
         } else {
@@ -1656,25 +1765,39 @@ tm_status tm_solve_advance(tm_solve_state* st, int32_t k_iters) {
     });
 }
 
-tm_status tm_batch_advance(int32_t n, tm_solve_state* const* sts, int32_t k_iters) {
+tm_status tm_batch_iterate(int32_t n, tm_solve_state* const* sts, int32_t k_iters, void* stream) {
     return guarded([&] {
         if (n < 0 || (n > 0 && !sts)) fail(TM_ERR_ARG, "bad state list");
         if (k_iters < 1) fail(TM_ERR_ARG, "k_iters must be >= 1");
         for (int i = 0; i < n; ++i)
             if (!sts[i] || sts[i]->ended) fail(TM_ERR_STATE, "state is NULL or ended");
-        // interleave: one iteration of every state at a time, each on its own stream
-        for (int i = 0; i < n; ++i) fork_lanes(sts[i]);
-        for (int it = 0; it < k_iters; ++it)
-            for (int i = 0; i < n; ++i)
-                for (int k = 0; k < sts[i]->nrhs; ++k) enqueue_iteration(sts[i], k);
+        for (int i = 0; i < n; ++i)
+            for (int j = i + 1; j < n; ++j)
+                if (sts[i] == sts[j]) fail(TM_ERR_ARG, "a state appears twice in the list");
+        hipStream_t bs = S(stream);
+        // the batch stream continues after the work queued on each state's stream
+        for (int i = 0; i < n; ++i)
+            if (sts[i]->s != bs) {
+                TM_HIP(hipEventRecord(sts[i]->order, sts[i]->s));
+                TM_HIP(hipStreamWaitEvent(bs, sts[i]->order, 0));
+            }
+        // group the lanes of all states by level structure: each group runs an
+        // iteration as one launch per operation (MAXB lanes per launch)
+        std::vector<std::string> keys;
+        std::vector<std::vector<LaneIO>> groups;
         for (int i = 0; i < n; ++i) {
-            tm_solve_state* st = sts[i];
-            join_lanes(st);
-            TM_HIP(hipMemcpyAsync(st->sc_host, st->sc, sizeof(KScal) * st->nrhs, hipMemcpyDeviceToHost,
-                                  st->s));
-            TM_HIP(hipEventRecord(st->ev, st->s));
-            st->pending = true;
+            const std::string key = shape_key(sts[i]->h);
+            size_t g = 0;
+            while (g < keys.size() && keys[g] != key) ++g;
+            if (g == keys.size()) {
+                keys.push_back(key);
+                groups.emplace_back();
+            }
+            state_lanes(sts[i], groups[g]);
         }
+        for (int it = 0; it < k_iters; ++it)
+            for (auto& g : groups) enqueue_iteration_b(g, bs);
+        for (int i = 0; i < n; ++i) state_sync_point(sts[i], bs);
     });
 }
 

@@ -343,12 +343,21 @@ constexpr bool pair_order_ok() {
 }
 static_assert(pair_order_ok<13>() && pair_order_ok<4>(), "stencil visiting order");
 
-template <typename T, int DIM, int OP, int G>
-__global__ __launch_bounds__(WG) void k_stencil_op(const T* __restrict__ st, int nx, int ny, int nz,
-                                                   int64_t N, const T* __restrict__ x,
-                                                   const T* __restrict__ b, T* __restrict__ y,
-                                                   const T* __restrict__ dinv, T omega,
-                                                   const int* __restrict__ done, const ChebArgs ch) {
+template <typename T, int DIM, int OP, int G, int NB>
+__global__ __launch_bounds__(WG) void k_stencil_op(const Pack<OpA<T>, NB> pk, int nx, int ny, int nz, int64_t N,
+                                                   T omega, double c1, double c2) {
+    const OpA<T>& A_ = lane_of(pk);
+    const T* __restrict__ st = A_.E;
+    const T* __restrict__ x = A_.x;
+    const T* __restrict__ b = A_.b;
+    T* __restrict__ y = A_.y;
+    const T* __restrict__ dinv = A_.dinv;
+    const int* __restrict__ done = A_.done;
+    ChebArgs ch;
+    ch.din = A_.din;
+    ch.dout = A_.dout;
+    ch.c1 = c1;
+    ch.c2 = c2;
     if (done && *done) return;
     const int64_t node = xcd_block() * WG + threadIdx.x;
     if (node >= N) return;
@@ -459,12 +468,21 @@ const float* dinv_of<float>(const Level& L) { return L.dinv32; }
 // loads with uniform control flow (the slot's kind, upper / lower / diagonal,
 // only selects addresses) that also carries the finishing step's operands,
 // then the P partial sums meet in a butterfly and the node's first lane finishes.
-template <typename T, int DIM, int OP, int P>
-__global__ __launch_bounds__(WG) void k_stencil_split(const T* __restrict__ st, int nx, int ny, int nz,
-                                                      int64_t N, const T* __restrict__ x,
-                                                      const T* __restrict__ b, T* __restrict__ y,
-                                                      const T* __restrict__ dinv, T omega,
-                                                      const int* __restrict__ done, const ChebArgs ch) {
+template <typename T, int DIM, int OP, int P, int NB>
+__global__ __launch_bounds__(WG) void k_stencil_split(const Pack<OpA<T>, NB> pk, int nx, int ny, int nz,
+                                                      int64_t N, T omega, double c1, double c2) {
+    const OpA<T>& A_ = lane_of(pk);
+    const T* __restrict__ st = A_.E;
+    const T* __restrict__ x = A_.x;
+    const T* __restrict__ b = A_.b;
+    T* __restrict__ y = A_.y;
+    const T* __restrict__ dinv = A_.dinv;
+    const int* __restrict__ done = A_.done;
+    ChebArgs ch;
+    ch.din = A_.din;
+    ch.dout = A_.dout;
+    ch.c1 = c1;
+    ch.c2 = c2;
     if (done && *done) return;
     const int64_t gid = xcd_block() * WG + threadIdx.x;
     const int64_t node = gid / P;
@@ -542,73 +560,90 @@ __global__ __launch_bounds__(WG) void k_stencil_split(const T* __restrict__ st, 
     }
 }
 
-template <typename T, int DIM, int P>
-static void stencil_split_launch(const Level& L, int op, const T* x, const T* b, T* y, T omega,
-                                 const int* done, hipStream_t s, const ChebArgs& ch) {
-    const dim3 g(grid_for(L.n_nodes * P)), blk(WG);
-    const T* st = st_of<T>(L);
-    const T* dv = dinv_of<T>(L);
-    const int nz = DIM == 3 ? L.nel[2] : 0;
-#define TM_SL(OPV)                                                                                   \
-    hipLaunchKernelGGL((k_stencil_split<T, DIM, OPV, P>), g, blk, 0, s, st, L.nel[0], L.nel[1], nz, L.n_nodes, \
-                       x, b, y, dv, omega, done, ch)
-    switch (op) {
-        case OP_APPLY: TM_SL(OP_APPLY); break;
-        case OP_RESID: TM_SL(OP_RESID); break;
-        case OP_CHEB: TM_SL(OP_CHEB); break;
-        default: TM_SL(OP_SMOOTH); break;
+template <typename T, int NB>
+static Pack<OpA<T>, NB> stencil_pack(int level, const LaneIO* L, int n) {
+    Pack<OpA<T>, NB> pk{};
+    for (int q = 0; q < n; ++q) {
+        const Level& Lq = L[q].h->lv[level];
+        OpA<T>& a = pk.a[q];
+        a.E = st_of<T>(Lq);
+        a.x = (const T*)L[q].x;
+        a.b = (const T*)L[q].b;
+        a.y = (T*)L[q].y;
+        a.dinv = dinv_of<T>(Lq);
+        a.done = L[q].done;
+        a.din = (const T*)L[q].din;
+        a.dout = (T*)L[q].dout;
     }
-#undef TM_SL
+    return pk;
 }
 
-template <typename T, int DIM, int G>
-static void stencil_launch(const Level& L, int op, const T* x, const T* b, T* y, T omega, const int* done,
-                           hipStream_t s, const ChebArgs& ch) {
-    const dim3 g(grid_for(L.n_nodes)), blk(WG);
-    const T* st = st_of<T>(L);
-    const T* dv = dinv_of<T>(L);
-    const int nz = DIM == 3 ? L.nel[2] : 0;
-#define TM_SL(OPV)                                                                                   \
-    hipLaunchKernelGGL((k_stencil_op<T, DIM, OPV, G>), g, blk, 0, s, st, L.nel[0], L.nel[1], nz, L.n_nodes, x, \
-                       b, y, dv, omega, done, ch)
-    switch (op) {
-        case OP_APPLY: TM_SL(OP_APPLY); break;
-        case OP_RESID: TM_SL(OP_RESID); break;
-        case OP_CHEB: TM_SL(OP_CHEB); break;
-        default: TM_SL(OP_SMOOTH); break;
-    }
-#undef TM_SL
-}
-
-template <typename T, int DIM>
-static void stencil_dispatch(const Level& L, int op, const T* x, const T* b, T* y, T omega,
-                             const int* done, hipStream_t s, const ChebArgs& ch) {
+// one launch for lanes L[0..n), n <= NB: the small-level form (P lanes per
+// node) or the large-level form (groups of G neighbours)
+template <typename T, int DIM, int NB>
+static void stencil_launch(int level, const LaneIO* L, int n, int op, T omega, double c1, double c2,
+                           hipStream_t s) {
+    const Level& V = L[0].h->lv[level];
+    const auto pk = stencil_pack<T, NB>(level, L, n);
+    const int nz = DIM == 3 ? V.nel[2] : 0;
     // fewer workgroups than compute units: latency-bound; 3D splits each
     // node over 4 lanes, 2D batches all nine neighbours (the level's
     // op_kernel can pin either form, whatever the size)
-    const bool small = L.op_kernel == 0 ? grid_for(L.n_nodes) < 256 : L.op_kernel == 2;
-    if (small) {
-        if constexpr (DIM == 3)
-            stencil_split_launch<T, DIM, 4>(L, op, x, b, y, omega, done, s, ch);
-        else
-            stencil_launch<T, DIM, 9>(L, op, x, b, y, omega, done, s, ch);
+    const bool small = V.op_kernel == 0 ? grid_for(V.n_nodes) < 256 : V.op_kernel == 2;
+    const dim3 blk(WG);
+    if (small && DIM == 3) {
+        constexpr int P = 4;
+        const dim3 g(grid_for(V.n_nodes * P), n);
+#define TM_SL(OPV)                                                                                   \
+    hipLaunchKernelGGL((k_stencil_split<T, DIM, OPV, P, NB>), g, blk, 0, s, pk, V.nel[0], V.nel[1], nz, V.n_nodes, \
+                       omega, c1, c2)
+        switch (op) {
+            case OP_APPLY: TM_SL(OP_APPLY); break;
+            case OP_RESID: TM_SL(OP_RESID); break;
+            case OP_CHEB: TM_SL(OP_CHEB); break;
+            default: TM_SL(OP_SMOOTH); break;
+        }
+#undef TM_SL
+        return;
     }
-    else
-        stencil_launch<T, DIM, 4>(L, op, x, b, y, omega, done, s, ch);
+    const dim3 g(grid_for(V.n_nodes), n);
+#define TM_SO(OPV, G)                                                                                \
+    hipLaunchKernelGGL((k_stencil_op<T, DIM, OPV, G, NB>), g, blk, 0, s, pk, V.nel[0], V.nel[1], nz, V.n_nodes, \
+                       omega, c1, c2)
+#define TM_SOG(G)                                                                                    \
+    switch (op) {                                                                                    \
+        case OP_APPLY: TM_SO(OP_APPLY, G); break;                                                    \
+        case OP_RESID: TM_SO(OP_RESID, G); break;                                                    \
+        case OP_CHEB: TM_SO(OP_CHEB, G); break;                                                      \
+        default: TM_SO(OP_SMOOTH, G); break;                                                         \
+    }
+    if (small) {
+        TM_SOG(9)
+    } else {
+        TM_SOG(4)
+    }
+#undef TM_SOG
+#undef TM_SO
 }
 
 template <typename T>
-void launch_stencil_op(const Level& L, int op, const T* x, const T* b, T* y, T omega,
-                       const int* done, hipStream_t s, const ChebArgs& ch) {
-    if (L.dim == 3)
-        stencil_dispatch<T, 3>(L, op, x, b, y, omega, done, s, ch);
-    else
-        stencil_dispatch<T, 2>(L, op, x, b, y, omega, done, s, ch);
+void launch_stencil_op_b(int level, int op, const LaneIO* L, int n, T omega, double c1, double c2,
+                         hipStream_t s) {
+    if (n < 1) return;
+    const int dim = L[0].h->lv[level].dim;
+    for (int q0 = 0; q0 < n; q0 += MAXB) {
+        const int m = std::min(MAXB, n - q0);
+        if (dim == 3) {
+            if (m == 1) stencil_launch<T, 3, 1>(level, L + q0, 1, op, omega, c1, c2, s);
+            else stencil_launch<T, 3, MAXB>(level, L + q0, m, op, omega, c1, c2, s);
+        } else {
+            if (m == 1) stencil_launch<T, 2, 1>(level, L + q0, 1, op, omega, c1, c2, s);
+            else stencil_launch<T, 2, MAXB>(level, L + q0, m, op, omega, c1, c2, s);
+        }
+    }
 }
-template void launch_stencil_op<double>(const Level&, int, const double*, const double*, double*,
-                                        double, const int*, hipStream_t, const ChebArgs&);
-template void launch_stencil_op<float>(const Level&, int, const float*, const float*, float*, float,
-                                       const int*, hipStream_t, const ChebArgs&);
+template void launch_stencil_op_b<double>(int, int, const LaneIO*, int, double, double, double, hipStream_t);
+template void launch_stencil_op_b<float>(int, int, const LaneIO*, int, float, double, double, hipStream_t);
 
 // --------------------------------------------------------------- transfers
 // Per axis with nf fine elements and ceil(nf/2) coarse ones, coarse node I sits
@@ -647,12 +682,16 @@ __device__ __forceinline__ void prolong_parents(int i, int nf, int (&ia)[2], T (
 // {-1,0,1}^dim from its position, with weight prod restrict_w (1 on it, 1/2 on a
 // fine midpoint, 0 otherwise); supported fine dofs contribute 0.
 // Optionally also x_c = omega D_c^-1 b_c (the first sweep of the coarse level from zero).
-template <typename T, int DIM, bool FIRST, bool MASK>
-__global__ __launch_bounds__(WG) void k_restrict(const T* __restrict__ rf, const uint8_t* __restrict__ nm,
-                                                 int fnx, int fny, int fnz, int cnx, int cny, int cnz,
-                                                 T* __restrict__ bc, T* __restrict__ xc,
-                                                 const T* __restrict__ dinv, T omega,
-                                                 const int* __restrict__ done) {
+template <typename T, int DIM, bool FIRST, bool MASK, int NB>
+__global__ __launch_bounds__(WG) void k_restrict(const Pack<RestrictA<T>, NB> pk, int fnx, int fny, int fnz,
+                                                 int cnx, int cny, int cnz, T omega) {
+    const RestrictA<T>& A_ = lane_of(pk);
+    const T* __restrict__ rf = A_.rf;
+    const uint8_t* __restrict__ nm = A_.nm;
+    T* __restrict__ bc = A_.bc;
+    T* __restrict__ xc = A_.xc;
+    const T* __restrict__ dinv = A_.dinv;
+    const int* __restrict__ done = A_.done;
     if (done && *done) return;
     const int CX = cnx + 1, CY = cny + 1, CZ = cnz + 1;
     const int64_t Nc = (int64_t)CX * CY * (DIM == 3 ? CZ : 1);
@@ -709,43 +748,62 @@ __global__ __launch_bounds__(WG) void k_restrict(const T* __restrict__ rf, const
     }
 }
 
-template <typename T, int DIM, bool FIRST>
-static void restrict_dispatch(const Level& fine, const Level& coarse, const T* rf, T* bc, T* xc, T omega,
-                              const int* done, hipStream_t s) {
-    const dim3 g(grid_for(coarse.n_nodes)), blk(WG);
-    const T* dv = dinv_of<T>(coarse);
+template <typename T, int DIM, bool FIRST, int NB>
+static void restrict_launch(int fl, const LaneIO* L, int n, T omega, hipStream_t s) {
+    const Level& fine = L[0].h->lv[fl];
+    const Level& coarse = L[0].h->lv[fl + 1];
+    Pack<RestrictA<T>, NB> pk{};
+    for (int q = 0; q < n; ++q) {
+        RestrictA<T>& a = pk.a[q];
+        a.rf = (const T*)L[q].x;
+        a.nm = fine.kind == TM_LEVEL_FINE ? L[q].h->lv[fl].nmask : nullptr;
+        a.bc = (T*)L[q].y;
+        a.xc = (T*)L[q].y2;
+        a.dinv = dinv_of<T>(L[q].h->lv[fl + 1]);
+        a.done = L[q].done;
+    }
+    const dim3 g(grid_for(coarse.n_nodes), n), blk(WG);
     const int fz = DIM == 3 ? fine.nel[2] : 0, cz = DIM == 3 ? coarse.nel[2] : 0;
     if (fine.kind == TM_LEVEL_FINE)
-        hipLaunchKernelGGL((k_restrict<T, DIM, FIRST, true>), g, blk, 0, s, rf, fine.nmask, fine.nel[0],
-                           fine.nel[1], fz, coarse.nel[0], coarse.nel[1], cz, bc, xc, dv, omega, done);
+        hipLaunchKernelGGL((k_restrict<T, DIM, FIRST, true, NB>), g, blk, 0, s, pk, fine.nel[0], fine.nel[1], fz,
+                           coarse.nel[0], coarse.nel[1], cz, omega);
     else
-        hipLaunchKernelGGL((k_restrict<T, DIM, FIRST, false>), g, blk, 0, s, rf, (const uint8_t*)nullptr,
-                           fine.nel[0], fine.nel[1], fz, coarse.nel[0], coarse.nel[1], cz, bc, xc, dv, omega,
-                           done);
+        hipLaunchKernelGGL((k_restrict<T, DIM, FIRST, false, NB>), g, blk, 0, s, pk, fine.nel[0], fine.nel[1], fz,
+                           coarse.nel[0], coarse.nel[1], cz, omega);
 }
 
+// b_c = P~^T r_f (lane x -> y) and, if the lanes give y2, the coarse level's
+// first sweep into y2 (all lanes alike)
 template <typename T>
-void launch_restrict(const Level& fine, const Level& coarse, const T* rf, T* bc, T* xc_first,
-                     T omega, const int* done, hipStream_t s) {
-    if (fine.dim == 3) {
-        if (xc_first) restrict_dispatch<T, 3, true>(fine, coarse, rf, bc, xc_first, omega, done, s);
-        else restrict_dispatch<T, 3, false>(fine, coarse, rf, bc, xc_first, omega, done, s);
-    } else {
-        if (xc_first) restrict_dispatch<T, 2, true>(fine, coarse, rf, bc, xc_first, omega, done, s);
-        else restrict_dispatch<T, 2, false>(fine, coarse, rf, bc, xc_first, omega, done, s);
+void launch_restrict_b(int fl, const LaneIO* L, int n, T omega, hipStream_t s) {
+    if (n < 1) return;
+    const int dim = L[0].h->lv[fl].dim;
+    const bool first = L[0].y2 != nullptr;
+    for (int q0 = 0; q0 < n; q0 += MAXB) {
+        const int m = std::min(MAXB, n - q0);
+#define TM_RL(D, F)                                                        \
+    if (m == 1) restrict_launch<T, D, F, 1>(fl, L + q0, 1, omega, s);      \
+    else restrict_launch<T, D, F, MAXB>(fl, L + q0, m, omega, s);
+        if (dim == 3) {
+            if (first) { TM_RL(3, true) } else { TM_RL(3, false) }
+        } else {
+            if (first) { TM_RL(2, true) } else { TM_RL(2, false) }
+        }
+#undef TM_RL
     }
 }
-template void launch_restrict<double>(const Level&, const Level&, const double*, double*, double*,
-                                      double, const int*, hipStream_t);
-template void launch_restrict<float>(const Level&, const Level&, const float*, float*, float*, float,
-                                     const int*, hipStream_t);
+template void launch_restrict_b<double>(int, const LaneIO*, int, double, hipStream_t);
+template void launch_restrict_b<float>(int, const LaneIO*, int, float, hipStream_t);
 
 // prolongation x_f += M P x_c: fine node i interpolates from the coarse nodes
 // around it (1, 2, 4 or 8 of them), weights 1 or 1/2 per axis.
-template <typename T, int DIM>
-__global__ __launch_bounds__(WG) void k_prolong(const T* __restrict__ xc, const uint8_t* __restrict__ nm,
-                                                int fnx, int fny, int fnz, T* __restrict__ xf,
-                                                const int* __restrict__ done) {
+template <typename T, int DIM, int NB>
+__global__ __launch_bounds__(WG) void k_prolong(const Pack<ProlongA<T>, NB> pk, int fnx, int fny, int fnz) {
+    const ProlongA<T>& A_ = lane_of(pk);
+    const T* __restrict__ xc = A_.xc;
+    const uint8_t* __restrict__ nm = A_.nm;
+    T* __restrict__ xf = A_.xf;
+    const int* __restrict__ done = A_.done;
     if (done && *done) return;
     const int FX = fnx + 1, FY = fny + 1, FZ = fnz + 1;
     const int64_t Nf = (int64_t)FX * FY * (DIM == 3 ? FZ : 1);
@@ -799,28 +857,49 @@ __global__ __launch_bounds__(WG) void k_prolong(const T* __restrict__ xc, const 
     for (int c = 0; c < DIM; ++c) xf[DIM * node + c] = ((m >> c) & 1u) ? xo[c] : xo[c] + acc[c];
 }
 
-template <typename T>
-void launch_prolong(const Level& fine, const Level& coarse, const T* xc, T* xf, const int* done,
-                    hipStream_t s) {
-    (void)coarse;
-    const dim3 g(grid_for(fine.n_nodes)), blk(WG);
-    const uint8_t* nm = fine.kind == TM_LEVEL_FINE ? fine.nmask : nullptr;
-    if (fine.dim == 3)
-        hipLaunchKernelGGL((k_prolong<T, 3>), g, blk, 0, s, xc, nm, fine.nel[0], fine.nel[1], fine.nel[2],
-                           xf, done);
-    else
-        hipLaunchKernelGGL((k_prolong<T, 2>), g, blk, 0, s, xc, nm, fine.nel[0], fine.nel[1], 0, xf, done);
+template <typename T, int DIM, int NB>
+static void prolong_launch(int fl, const LaneIO* L, int n, hipStream_t s) {
+    const Level& fine = L[0].h->lv[fl];
+    Pack<ProlongA<T>, NB> pk{};
+    for (int q = 0; q < n; ++q) {
+        ProlongA<T>& a = pk.a[q];
+        a.xc = (const T*)L[q].x;
+        a.nm = fine.kind == TM_LEVEL_FINE ? L[q].h->lv[fl].nmask : nullptr;
+        a.xf = (T*)L[q].y;
+        a.done = L[q].done;
+    }
+    const dim3 g(grid_for(fine.n_nodes), n), blk(WG);
+    hipLaunchKernelGGL((k_prolong<T, DIM, NB>), g, blk, 0, s, pk, fine.nel[0], fine.nel[1],
+                       DIM == 3 ? fine.nel[2] : 0);
 }
-template void launch_prolong<double>(const Level&, const Level&, const double*, double*, const int*,
-                                     hipStream_t);
-template void launch_prolong<float>(const Level&, const Level&, const float*, float*, const int*,
-                                    hipStream_t);
+
+// x_f += M P x_c (lane x = coarse, y = fine)
+template <typename T>
+void launch_prolong_b(int fl, const LaneIO* L, int n, hipStream_t s) {
+    if (n < 1) return;
+    const int dim = L[0].h->lv[fl].dim;
+    for (int q0 = 0; q0 < n; q0 += MAXB) {
+        const int m = std::min(MAXB, n - q0);
+        if (dim == 3) {
+            if (m == 1) prolong_launch<T, 3, 1>(fl, L + q0, 1, s);
+            else prolong_launch<T, 3, MAXB>(fl, L + q0, m, s);
+        } else {
+            if (m == 1) prolong_launch<T, 2, 1>(fl, L + q0, 1, s);
+            else prolong_launch<T, 2, MAXB>(fl, L + q0, m, s);
+        }
+    }
+}
+template void launch_prolong_b<double>(int, const LaneIO*, int, hipStream_t);
+template void launch_prolong_b<float>(int, const LaneIO*, int, hipStream_t);
 
 // first smoothing sweep from x = 0:  x = omega D^-1 b  (block per node)
-template <typename T, int BS>
-__global__ __launch_bounds__(WG) void k_first_smooth(const T* __restrict__ b, const T* __restrict__ dinv,
-                                                     int64_t N, T omega, T* __restrict__ x,
-                                                     const int* __restrict__ done) {
+template <typename T, int BS, int NB>
+__global__ __launch_bounds__(WG) void k_first_smooth(const Pack<FirstA<T>, NB> pk, int64_t N, T omega) {
+    const FirstA<T>& A_ = lane_of(pk);
+    const T* __restrict__ b = A_.b;
+    const T* __restrict__ dinv = A_.dinv;
+    T* __restrict__ x = A_.x;
+    const int* __restrict__ done = A_.done;
     if (done && *done) return;
     const int64_t node = xcd_block() * WG + threadIdx.x;
     if (node >= N) return;
@@ -836,20 +915,41 @@ __global__ __launch_bounds__(WG) void k_first_smooth(const T* __restrict__ b, co
     }
 }
 
+template <typename T, int BS, int NB>
+static void first_launch(int l, const LaneIO* L, int n, T omega, hipStream_t s) {
+    const Level& V = L[0].h->lv[l];
+    Pack<FirstA<T>, NB> pk{};
+    for (int q = 0; q < n; ++q) {
+        FirstA<T>& a = pk.a[q];
+        a.b = (const T*)L[q].b;
+        a.dinv = dinv_of<T>(L[q].h->lv[l]);
+        a.x = (T*)L[q].y;
+        a.done = L[q].done;
+    }
+    hipLaunchKernelGGL((k_first_smooth<T, BS, NB>), dim3(grid_for(V.n_nodes), n), dim3(WG), 0, s, pk, V.n_nodes,
+                       omega);
+}
+
+// first sweep from zero on level l: y = omega D^-1 b
 template <typename T>
-void launch_first_smooth(const Level& L, const T* b, T* x, T omega, const int* done, hipStream_t s) {
-    const dim3 g(grid_for(L.n_nodes)), blk(WG);
-    const T* dv = dinv_of<T>(L);
-    switch (L.bs) {
-        case 2: hipLaunchKernelGGL((k_first_smooth<T, 2>), g, blk, 0, s, b, dv, L.n_nodes, omega, x, done); break;
-        case 3: hipLaunchKernelGGL((k_first_smooth<T, 3>), g, blk, 0, s, b, dv, L.n_nodes, omega, x, done); break;
-        case 6: hipLaunchKernelGGL((k_first_smooth<T, 6>), g, blk, 0, s, b, dv, L.n_nodes, omega, x, done); break;
-        default: fail(TM_ERR_ARG, "unsupported block size");
+void launch_first_smooth_b(int l, const LaneIO* L, int n, T omega, hipStream_t s) {
+    if (n < 1) return;
+    const int bs = L[0].h->lv[l].bs;
+    for (int q0 = 0; q0 < n; q0 += MAXB) {
+        const int m = std::min(MAXB, n - q0);
+#define TM_FS(BS)                                                         \
+    if (m == 1) first_launch<T, BS, 1>(l, L + q0, 1, omega, s);           \
+    else first_launch<T, BS, MAXB>(l, L + q0, m, omega, s);
+        switch (bs) {
+            case 2: TM_FS(2) break;
+            case 3: TM_FS(3) break;
+            case 6: TM_FS(6) break;
+            default: fail(TM_ERR_ARG, "unsupported block size");
+        }
+#undef TM_FS
     }
 }
-template void launch_first_smooth<double>(const Level&, const double*, double*, double, const int*,
-                                          hipStream_t);
-template void launch_first_smooth<float>(const Level&, const float*, float*, float, const int*,
-                                         hipStream_t);
+template void launch_first_smooth_b<double>(int, const LaneIO*, int, double, hipStream_t);
+template void launch_first_smooth_b<float>(int, const LaneIO*, int, float, hipStream_t);
 
 }  // namespace tmi

@@ -262,10 +262,13 @@ void launch_cholesky_inverse(double* A, double* Ainv, double* Ls, int64_t n, int
 // x = A^-1 b in FP64 (one wave per row, fixed shuffle tree).  Each lane keeps
 // four partial sums over columns lane + 64 (4 q + r), so four independent
 // loads are in flight per lane; the partials are added in a fixed order.
-template <typename T>
-__global__ __launch_bounds__(256) void k_dense_solve(const double* __restrict__ Ainv, int64_t n,
-                                                     const T* __restrict__ b, T* __restrict__ x,
-                                                     const int* __restrict__ done) {
+template <typename T, int NB>
+__global__ __launch_bounds__(256) void k_dense_solve(const Pack<DenseA<T>, NB> pk, int64_t n) {
+    const DenseA<T>& A_ = lane_of(pk);
+    const double* __restrict__ Ainv = A_.Ainv;
+    const T* __restrict__ b = A_.b;
+    T* __restrict__ x = A_.x;
+    const int* __restrict__ done = A_.done;
     if (done && *done) return;
     const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
@@ -288,15 +291,30 @@ __global__ __launch_bounds__(256) void k_dense_solve(const double* __restrict__ 
     if (lane == 0) x[row] = (T)a;
 }
 
-template <typename T>
-void launch_dense_solve(const double* Ainv, int64_t n, const T* b, T* x, const int* done,
-                        hipStream_t s) {
-    hipLaunchKernelGGL((k_dense_solve<T>), dim3((unsigned)ceil_div(n, 4)), dim3(256), 0, s, Ainv, n,
-                       b, x, done);
+template <typename T, int NB>
+static void dense_launch(const LaneIO* L, int n, hipStream_t s) {
+    Pack<DenseA<T>, NB> pk{};
+    for (int q = 0; q < n; ++q) {
+        DenseA<T>& a = pk.a[q];
+        a.Ainv = L[q].h->ainv;
+        a.b = (const T*)L[q].x;
+        a.x = (T*)L[q].y;
+        a.done = L[q].done;
+    }
+    const int64_t nc = L[0].h->nc;
+    hipLaunchKernelGGL((k_dense_solve<T, NB>), dim3((unsigned)ceil_div(nc, 4), n), dim3(256), 0, s, pk, nc);
 }
-template void launch_dense_solve<double>(const double*, int64_t, const double*, double*, const int*,
-                                         hipStream_t);
-template void launch_dense_solve<float>(const double*, int64_t, const float*, float*, const int*,
-                                        hipStream_t);
+
+// y = A_c^-1 x on the coarsest level of each lane's hierarchy
+template <typename T>
+void launch_dense_solve_b(const LaneIO* L, int n, hipStream_t s) {
+    for (int q0 = 0; q0 < n; q0 += MAXB) {
+        const int m = std::min(MAXB, n - q0);
+        if (m == 1) dense_launch<T, 1>(L + q0, 1, s);
+        else dense_launch<T, MAXB>(L + q0, m, s);
+    }
+}
+template void launch_dense_solve_b<double>(const LaneIO*, int, hipStream_t);
+template void launch_dense_solve_b<float>(const LaneIO*, int, hipStream_t);
 
 }  // namespace tmi

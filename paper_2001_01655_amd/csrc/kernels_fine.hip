@@ -224,14 +224,23 @@ __device__ __forceinline__ void layer_plane3(const KeVals<T>& kc, const T (&w)[9
     }
 }
 
-template <typename T, int OP, bool MASK_IN>
-__global__ __launch_bounds__(WG) void k_fine3(const T* __restrict__ E, const KeVals<T> kc,
-                                              const uint8_t* __restrict__ nm, int nx, int ny, int nz,
-                                              int64_t N64, const T* __restrict__ x,
-                                              const T* __restrict__ b, T* __restrict__ y,
-                                              const T* __restrict__ dinv, T omega,
-                                              const int* __restrict__ done, double* partials,
-                                              const ChebArgs ch) {
+template <typename T, int OP, bool MASK_IN, int NB>
+__global__ __launch_bounds__(WG) void k_fine3(const Pack<OpA<T>, NB> pk, const KeVals<T> kc, int nx, int ny,
+                                              int nz, int64_t N64, T omega, double c1, double c2) {
+    const OpA<T>& A_ = lane_of(pk);
+    const T* __restrict__ E = A_.E;
+    const uint8_t* __restrict__ nm = A_.nm;
+    const T* __restrict__ x = A_.x;
+    const T* __restrict__ b = A_.b;
+    T* __restrict__ y = A_.y;
+    const T* __restrict__ dinv = A_.dinv;
+    const int* __restrict__ done = A_.done;
+    ChebArgs ch;
+    ch.din = A_.din;
+    ch.dout = A_.dout;
+    ch.c1 = c1;
+    ch.c2 = c2;
+    double* partials = A_.partials;
     if (done && *done) return;
     const uint32_t N = (uint32_t)N64;
     const uint32_t node = (uint32_t)xcd_block() * WG + threadIdx.x;
@@ -246,14 +255,14 @@ __global__ __launch_bounds__(WG) void k_fine3(const T* __restrict__ E, const KeV
     const uint32_t ox[3] = {i ? 0u - 1u : 0u, 0u, i + 1 < NX ? 1u : 0u};
     const uint32_t oy[3] = {j ? 0u - NX : 0u, 0u, j + 1 < NY ? NX : 0u};
     const uint32_t oz[3] = {k ? 0u - PL : 0u, 0u, k + 1 < NZ ? PL : 0u};
-    constexpr uint32_t NB = 3u * sizeof(T);      // bytes per node
+    constexpr uint32_t NBY = 3u * sizeof(T);     // bytes per node
     // byte offsets of the neighbours, as sums; the empty asm keeps the
     // compiler from folding them back into one multiply per neighbour
-    uint32_t nb0 = nd * NB;
+    uint32_t nb0 = nd * NBY;
     asm volatile("" : "+v"(nb0));
-    const uint32_t bx[3] = {i ? 0u - NB : 0u, 0u, i + 1 < NX ? NB : 0u};
-    const uint32_t by[3] = {j ? 0u - NX * NB : 0u, 0u, j + 1 < NY ? NX * NB : 0u};
-    const uint32_t bz[3] = {k ? 0u - PL * NB : 0u, 0u, k + 1 < NZ ? PL * NB : 0u};
+    const uint32_t bx[3] = {i ? 0u - NBY : 0u, 0u, i + 1 < NX ? NBY : 0u};
+    const uint32_t by[3] = {j ? 0u - NX * NBY : 0u, 0u, j + 1 < NY ? NX * NBY : 0u};
+    const uint32_t bz[3] = {k ? 0u - PL * NBY : 0u, 0u, k + 1 < NZ ? PL * NBY : 0u};
     const auto xr = buf_rsrc(x, (int64_t)N * 3 * sizeof(T));
     const auto er = buf_rsrc(E, (int64_t)nx * ny * nz * sizeof(T));
     // moduli of the 8 elements around the node, [ez][ey][ex]: element with
@@ -324,13 +333,23 @@ __global__ __launch_bounds__(WG) void k_fine3(const T* __restrict__ E, const KeV
 // Each node's terms are summed in the order of k_fine3 (layer 0 of plane 0,
 // layers 0 and 1 of plane 1, layer 1 of plane 2), so the results are bitwise
 // those of k_fine3.  Used for the V-cycle's operators (no partial sums).
-template <typename T, int OP>
-__global__ __launch_bounds__(WG) void k_fine3z2(const T* __restrict__ E, const KeVals<T> kc,
-                                                const uint8_t* __restrict__ nm, int nx, int ny, int nz,
-                                                int64_t N64, const T* __restrict__ x, const T* __restrict__ b,
-                                                T* __restrict__ y, const T* __restrict__ dinv, T omega,
-                                                const int* __restrict__ done, const ChebArgs ch) {
+template <typename T, int OP, int NB>
+__global__ __launch_bounds__(WG) void k_fine3z2(const Pack<OpA<T>, NB> pk, const KeVals<T> kc, int nx, int ny,
+                                                int nz, int64_t N64, T omega, double c1, double c2) {
     static_assert(OP != OP_QDOT, "no partial sums in the two-node operator");
+    const OpA<T>& A_ = lane_of(pk);
+    const T* __restrict__ E = A_.E;
+    const uint8_t* __restrict__ nm = A_.nm;
+    const T* __restrict__ x = A_.x;
+    const T* __restrict__ b = A_.b;
+    T* __restrict__ y = A_.y;
+    const T* __restrict__ dinv = A_.dinv;
+    const int* __restrict__ done = A_.done;
+    ChebArgs ch;
+    ch.din = A_.din;
+    ch.dout = A_.dout;
+    ch.c1 = c1;
+    ch.c2 = c2;
     if (done && *done) return;
     const uint32_t N = (uint32_t)N64;
     const uint32_t NX = nx + 1, NY = ny + 1, NZ = nz + 1, PL = NX * NY;
@@ -342,15 +361,15 @@ __global__ __launch_bounds__(WG) void k_fine3z2(const T* __restrict__ E, const K
     const bool two = k + 1 < NZ;                        // the upper node exists
     const uint32_t nd0 = k * PL + j * NX + i;
     const uint32_t nd1 = two ? nd0 + PL : nd0;
-    constexpr uint32_t NB = 3u * sizeof(T);
-    uint32_t nb0 = nd0 * NB;
+    constexpr uint32_t NBY = 3u * sizeof(T);
+    uint32_t nb0 = nd0 * NBY;
     asm volatile("" : "+v"(nb0));
-    const uint32_t bx[3] = {i ? 0u - NB : 0u, 0u, i + 1 < NX ? NB : 0u};
-    const uint32_t by[3] = {j ? 0u - NX * NB : 0u, 0u, j + 1 < NY ? NX * NB : 0u};
+    const uint32_t bx[3] = {i ? 0u - NBY : 0u, 0u, i + 1 < NX ? NBY : 0u};
+    const uint32_t by[3] = {j ? 0u - NX * NBY : 0u, 0u, j + 1 < NY ? NX * NBY : 0u};
     // planes k-1 .. k+2 relative to node k, clamped into the grid (what lies
     // outside only meets elements of modulus zero)
-    const uint32_t bz[4] = {k ? 0u - PL * NB : 0u, 0u, k + 1 < NZ ? PL * NB : 0u,
-                            k + 2 < NZ ? 2u * PL * NB : (k + 1 < NZ ? PL * NB : 0u)};
+    const uint32_t bz[4] = {k ? 0u - PL * NBY : 0u, 0u, k + 1 < NZ ? PL * NBY : 0u,
+                            k + 2 < NZ ? 2u * PL * NBY : (k + 1 < NZ ? PL * NBY : 0u)};
     const auto xr = buf_rsrc(x, (int64_t)N * 3 * sizeof(T));
     const auto er = buf_rsrc(E, (int64_t)nx * ny * nz * sizeof(T));
     // moduli of element layers k-1, k, k+1 (index clamped, zero outside)
@@ -430,7 +449,7 @@ __global__ __launch_bounds__(WG) void k_fine3z2(const T* __restrict__ E, const K
 // k = 16 q + m.  One accumulator per element slot collects its 24 columns; a
 // layer's four slots are scaled by their moduli and added as soon as its two
 // planes are done (fixed order: layer below, then layer above; FP32
-// accumulation), so at most 12 accumulators are live.
+// accumulation).
 typedef float v4f __attribute__((ext_vector_type(4)));
 
 template <int K>
@@ -471,14 +490,25 @@ __device__ __forceinline__ void layer_reduce(const v4f (&C)[4], const float (&E)
     }
 }
 
-template <int OP>
-__global__ __launch_bounds__(WG) void k_fine3z2_mfma(const float* __restrict__ E, const float* __restrict__ KA,
-                                                     const uint8_t* __restrict__ nm, int nx, int ny, int nz,
-                                                     int64_t N64, const float* __restrict__ x,
-                                                     const float* __restrict__ b, float* __restrict__ y,
-                                                     const float* __restrict__ dinv, float omega,
-                                                     const int* __restrict__ done, const ChebArgs ch) {
+template <int OP, int NB>
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4))) void k_fine3z2_mfma(
+    const Pack<OpA<float>, NB> pk, int nx, int ny, int nz, int64_t N64, float omega, double c1, double c2) {
     static_assert(OP != OP_QDOT, "no partial sums in the two-node operator");
+    using T = float;
+    const OpA<T>& A_ = lane_of(pk);
+    const T* __restrict__ E = A_.E;
+    const uint8_t* __restrict__ nm = A_.nm;
+    const T* __restrict__ x = A_.x;
+    const T* __restrict__ b = A_.b;
+    T* __restrict__ y = A_.y;
+    const T* __restrict__ dinv = A_.dinv;
+    const int* __restrict__ done = A_.done;
+    ChebArgs ch;
+    ch.din = A_.din;
+    ch.dout = A_.dout;
+    ch.c1 = c1;
+    ch.c2 = c2;
+    const float* __restrict__ KA = A_.KA;
     if (done && *done) return;
     // every lane of the wave takes part in the matrix instructions: lanes past
     // the last pair work on pair 0 and store nothing
@@ -496,16 +526,16 @@ __global__ __launch_bounds__(WG) void k_fine3z2_mfma(const float* __restrict__ E
     const bool two = k + 1 < NZ;                        // the upper node exists
     const uint32_t nd0 = k * PL + j * NX + i;
     const uint32_t nd1 = two ? nd0 + PL : nd0;
-    constexpr uint32_t NB = 12u;                        // bytes per node
-    uint32_t nb0 = nd0 * NB;
+    constexpr uint32_t NBY = 12u;                       // bytes per node
+    uint32_t nb0 = nd0 * NBY;
     asm volatile("" : "+v"(nb0));
-    const uint32_t bx[3] = {i ? 0u - NB : 0u, 0u, i + 1 < NX ? NB : 0u};
-    const uint32_t by[3] = {j ? 0u - NX * NB : 0u, 0u, j + 1 < NY ? NX * NB : 0u};
+    const uint32_t bx[3] = {i ? 0u - NBY : 0u, 0u, i + 1 < NX ? NBY : 0u};
+    const uint32_t by[3] = {j ? 0u - NX * NBY : 0u, 0u, j + 1 < NY ? NX * NBY : 0u};
     // planes k-1 .. k+2 relative to node k, clamped into the grid (what lies
     // outside only meets elements of modulus zero)
-    const uint32_t bz[4] = {k ? 0u - PL * NB : 0u, 0u, k + 1 < NZ ? PL * NB : 0u,
-                            k + 2 < NZ ? 2u * PL * NB : (k + 1 < NZ ? PL * NB : 0u)};
-    const auto xr = buf_rsrc(x, (int64_t)N * NB);
+    const uint32_t bz[4] = {k ? 0u - PL * NBY : 0u, 0u, k + 1 < NZ ? PL * NBY : 0u,
+                            k + 2 < NZ ? 2u * PL * NBY : (k + 1 < NZ ? PL * NBY : 0u)};
+    const auto xr = buf_rsrc(x, (int64_t)N * NBY);
     const auto er = buf_rsrc(E, (int64_t)nx * ny * nz * 4);
     // moduli of element layers k-1, k, k+1 (index clamped, zero outside)
     const uint32_t EX = (uint32_t)nx, EP = EX * (uint32_t)ny;
@@ -536,37 +566,45 @@ __global__ __launch_bounds__(WG) void k_fine3z2_mfma(const float* __restrict__ E
             for (int dx = 0; dx < 3; ++dx) bld3(xr, rowb + bx[dx], w[dy * 3 + dx]);
         }
     };
+    // two sets of four accumulators, reused layer after layer: a layer's
+    // slots are scaled and added before its registers take the next layer (the
+    // scheduling barriers keep the compiler from starting the next layer's
+    // chain early, which would keep three sets live and lower the occupancy)
+    const v4f z4 = {0.f, 0.f, 0.f, 0.f};
+    float acc0[3] = {0.f, 0.f, 0.f}, acc1[3] = {0.f, 0.f, 0.f};
+    float xo0[3], xo1[3];
+    v4f A[4] = {z4, z4, z4, z4}, B[4] = {z4, z4, z4, z4};
+    load_plane(0);
+    layer_plane3_mfma<0, 0>(ka, w, A);                 // node k, layer k-1
+    load_plane(1);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) xo0[c] = w[4][c];
+    layer_plane3_mfma<1, 0>(ka, w, A);
+    layer_plane3_mfma<1, 1>(ka, w, B);                 // node k, layer k
+    layer_reduce(A, El[0], acc0);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) A[q] = z4;
+    layer_plane3_mfma<0, 0>(ka, w, A);                 // node k+1, layer k
+    load_plane(2);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) xo1[c] = w[4][c];
+    layer_plane3_mfma<2, 1>(ka, w, B);
+    layer_plane3_mfma<1, 0>(ka, w, A);
+    layer_reduce(B, El[1], acc0);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) B[q] = z4;
+    layer_plane3_mfma<1, 1>(ka, w, B);                 // node k+1, layer k+1
+    layer_reduce(A, El[1], acc1);
+    // the finishing step's operands, requested while the last plane is used
     FinIn<float, 3> fin0, fin1;
     finish_load<float, 3, OP>(nd0, N, b, dinv, ch, fin0);
     finish_load<float, 3, OP>(nd1, N, b, dinv, ch, fin1);
     const uint8_t m0 = nm[nd0], m1 = nm[nd1];
-    const v4f zero4 = {0.f, 0.f, 0.f, 0.f};
-    v4f A0[4] = {zero4, zero4, zero4, zero4};      // node k,   layer k-1
-    v4f B0[4] = {zero4, zero4, zero4, zero4};      // node k,   layer k
-    v4f A1[4] = {zero4, zero4, zero4, zero4};      // node k+1, layer k
-    v4f B1[4] = {zero4, zero4, zero4, zero4};      // node k+1, layer k+1
-    float acc0[3] = {0.f, 0.f, 0.f}, acc1[3] = {0.f, 0.f, 0.f};
-    float xo0[3], xo1[3];
-    load_plane(0);
-    layer_plane3_mfma<0, 0>(ka, w, A0);
-    load_plane(1);
-#pragma unroll
-    for (int c = 0; c < 3; ++c) xo0[c] = w[4][c];
-    layer_plane3_mfma<1, 0>(ka, w, A0);
-    layer_plane3_mfma<1, 1>(ka, w, B0);
-    layer_plane3_mfma<0, 0>(ka, w, A1);
-    layer_reduce(A0, El[0], acc0);
-    load_plane(2);
-#pragma unroll
-    for (int c = 0; c < 3; ++c) xo1[c] = w[4][c];
-    layer_plane3_mfma<2, 1>(ka, w, B0);
-    layer_plane3_mfma<1, 0>(ka, w, A1);
-    layer_plane3_mfma<1, 1>(ka, w, B1);
-    layer_reduce(B0, El[1], acc0);
-    layer_reduce(A1, El[1], acc1);
     load_plane(3);
-    layer_plane3_mfma<2, 1>(ka, w, B1);
-    layer_reduce(B1, El[2], acc1);
+    layer_plane3_mfma<2, 1>(ka, w, B);
+    layer_reduce(B, El[2], acc1);
     double dots[2] = {0.0, 0.0};
     if (live) finish_store<float, 3, OP>(nd0, acc0, xo0, m0, fin0, y, omega, dots, ch);
     if (live && two) finish_store<float, 3, OP>(nd1, acc1, xo1, m1, fin1, y, omega, dots, ch);
@@ -599,14 +637,23 @@ __device__ __forceinline__ void elem2(const KeVals<T>& kc, const T (&v)[9][2], T
 #undef TM_CORNER
 }
 
-template <typename T, int OP, bool MASK_IN>
-__global__ __launch_bounds__(WG) void k_fine2(const T* __restrict__ E, const KeVals<T> kc,
-                                              const uint8_t* __restrict__ nm, int nx, int ny,
-                                              int64_t N64, const T* __restrict__ x,
-                                              const T* __restrict__ b, T* __restrict__ y,
-                                              const T* __restrict__ dinv, T omega,
-                                              const int* __restrict__ done, double* partials,
-                                              const ChebArgs ch) {
+template <typename T, int OP, bool MASK_IN, int NB>
+__global__ __launch_bounds__(WG) void k_fine2(const Pack<OpA<T>, NB> pk, const KeVals<T> kc, int nx, int ny,
+                                              int64_t N64, T omega, double c1, double c2) {
+    const OpA<T>& A_ = lane_of(pk);
+    const T* __restrict__ E = A_.E;
+    const uint8_t* __restrict__ nm = A_.nm;
+    const T* __restrict__ x = A_.x;
+    const T* __restrict__ b = A_.b;
+    T* __restrict__ y = A_.y;
+    const T* __restrict__ dinv = A_.dinv;
+    const int* __restrict__ done = A_.done;
+    ChebArgs ch;
+    ch.din = A_.din;
+    ch.dout = A_.dout;
+    ch.c1 = c1;
+    ch.c2 = c2;
+    double* partials = A_.partials;
     if (done && *done) return;
     const uint32_t N = (uint32_t)N64;
     const uint32_t node = (uint32_t)xcd_block() * WG + threadIdx.x;
@@ -694,56 +741,97 @@ const double* pick_dinv<double>(const Level& L) { return L.dinv64; }
 template <>
 const float* pick_dinv<float>(const Level& L) { return L.dinv32; }
 
-template <typename T, int OP, bool MI>
-static void fine_dispatch(const tm_hierarchy* h, const T* x, const T* b, T* y, T omega,
-                          const int* done, double* partials, hipStream_t s, const ChebArgs& ch) {
-    const Level& L = h->lv[0];
-    const dim3 g(grid_for(L.n_nodes)), blk(WG);
+// one launch of the fine operator for lanes L[0..n) (n <= MAXB), all of
+// hierarchies with the same fine grid and options
+template <typename T, int OP, bool MI, int NB>
+static void fine_launch(const LaneIO* L, int n, T omega, double c1, double c2, hipStream_t s) {
+    const tm_hierarchy* h = L[0].h;
+    const Level& F = h->lv[0];
+    Pack<OpA<T>, NB> pk{};
+    for (int q = 0; q < n; ++q) {
+        const Level& Lq = L[q].h->lv[0];
+        OpA<T>& a = pk.a[q];
+        a.E = pick_E<T>(Lq);
+        a.KA = L[q].h->KA32;
+        a.nm = Lq.nmask;
+        a.x = (const T*)L[q].x;
+        a.b = (const T*)L[q].b;
+        a.y = (T*)L[q].y;
+        a.dinv = pick_dinv<T>(Lq);
+        a.done = L[q].done;
+        a.partials = L[q].part;
+        a.din = (const T*)L[q].din;
+        a.dout = (T*)L[q].dout;
+    }
+    const dim3 blk(WG);
     if constexpr (std::is_same<T, float>::value && !MI && OP != OP_QDOT) {
-        if (L.dim == 3 && h->opt.fine_mfma) {
-            const int64_t nt = (int64_t)L.nn[0] * L.nn[1] * ((L.nn[2] + 1) / 2);
-            hipLaunchKernelGGL((k_fine3z2_mfma<OP>), dim3(grid_for(nt)), blk, 0, s, L.E32, h->KA32, L.nmask,
-                               L.nel[0], L.nel[1], L.nel[2], L.n_nodes, x, b, y, L.dinv32, omega, done, ch);
+        if (F.dim == 3) {
+            const int64_t nt = (int64_t)F.nn[0] * F.nn[1] * ((F.nn[2] + 1) / 2);
+            const dim3 g(grid_for(nt), n);
+            if (h->opt.fine_mfma)
+                hipLaunchKernelGGL((k_fine3z2_mfma<OP, NB>), g, blk, 0, s, pk, F.nel[0], F.nel[1], F.nel[2], F.n_nodes,
+                                   omega, c1, c2);
+            else
+                hipLaunchKernelGGL((k_fine3z2<T, OP, NB>), g, blk, 0, s, pk, pick_kc<T>(h), F.nel[0], F.nel[1],
+                                   F.nel[2], F.n_nodes, omega, c1, c2);
             return;
         }
     }
-    if constexpr (std::is_same<T, float>::value && !MI && OP != OP_QDOT) {
-        if (L.dim == 3) {
-            const int64_t nt = (int64_t)L.nn[0] * L.nn[1] * ((L.nn[2] + 1) / 2);
-            hipLaunchKernelGGL((k_fine3z2<T, OP>), dim3(grid_for(nt)), blk, 0, s, pick_E<T>(L), pick_kc<T>(h),
-                               L.nmask, L.nel[0], L.nel[1], L.nel[2], L.n_nodes, x, b, y, pick_dinv<T>(L), omega,
-                               done, ch);
-            return;
-        }
-    }
-    if (L.dim == 3)
-        hipLaunchKernelGGL((k_fine3<T, OP, MI>), g, blk, 0, s, pick_E<T>(L), pick_kc<T>(h), L.nmask,
-                           L.nel[0], L.nel[1], L.nel[2], L.n_nodes, x, b, y, pick_dinv<T>(L), omega,
-                           done, partials, ch);
+    const dim3 g(grid_for(F.n_nodes), n);
+    if (F.dim == 3)
+        hipLaunchKernelGGL((k_fine3<T, OP, MI, NB>), g, blk, 0, s, pk, pick_kc<T>(h), F.nel[0], F.nel[1], F.nel[2],
+                           F.n_nodes, omega, c1, c2);
     else
-        hipLaunchKernelGGL((k_fine2<T, OP, MI>), g, blk, 0, s, pick_E<T>(L), pick_kc<T>(h), L.nmask,
-                           L.nel[0], L.nel[1], L.n_nodes, x, b, y, pick_dinv<T>(L), omega, done,
-                           partials, ch);
+        hipLaunchKernelGGL((k_fine2<T, OP, MI, NB>), g, blk, 0, s, pk, pick_kc<T>(h), F.nel[0], F.nel[1], F.n_nodes,
+                           omega, c1, c2);
 }
+
+template <typename T, int OP, bool MI>
+static void fine_dispatch(const LaneIO* L, int n, T omega, double c1, double c2, hipStream_t s) {
+    for (int q0 = 0; q0 < n; q0 += MAXB) {
+        const int m = std::min(MAXB, n - q0);
+        if (m == 1) fine_launch<T, OP, MI, 1>(L + q0, 1, omega, c1, c2, s);
+        else fine_launch<T, OP, MI, MAXB>(L + q0, m, omega, c1, c2, s);
+    }
+}
+
+template <typename T>
+void launch_fine_op_b(int op, bool mask_in, const LaneIO* L, int n, T omega, double c1, double c2,
+                      hipStream_t s) {
+    if (n < 1) return;
+    if (mask_in) {
+        if (op != OP_APPLY) fail(TM_ERR_ARG, "masked-input fine operator supports apply only");
+        fine_dispatch<T, OP_APPLY, true>(L, n, omega, c1, c2, s);
+        return;
+    }
+    switch (op) {
+        case OP_APPLY: fine_dispatch<T, OP_APPLY, false>(L, n, omega, c1, c2, s); break;
+        case OP_RESID: fine_dispatch<T, OP_RESID, false>(L, n, omega, c1, c2, s); break;
+        case OP_SMOOTH: fine_dispatch<T, OP_SMOOTH, false>(L, n, omega, c1, c2, s); break;
+        case OP_CHEB: fine_dispatch<T, OP_CHEB, false>(L, n, omega, c1, c2, s); break;
+        default:
+            for (int q = 0; q < n; ++q)
+                if (!L[q].part) fail(TM_ERR_ARG, "q = K~p needs a partial-sum buffer");
+            fine_dispatch<T, OP_QDOT, false>(L, n, omega, c1, c2, s);
+            break;
+    }
+}
+template void launch_fine_op_b<double>(int, bool, const LaneIO*, int, double, double, double, hipStream_t);
+template void launch_fine_op_b<float>(int, bool, const LaneIO*, int, float, double, double, hipStream_t);
 
 template <typename T>
 void launch_fine_op(const tm_hierarchy* h, int op, bool mask_in, const T* x, const T* b, T* y,
                     T omega, const int* done, double* partials, hipStream_t s, const ChebArgs& ch) {
-    if (mask_in) {
-        if (op != OP_APPLY) fail(TM_ERR_ARG, "masked-input fine operator supports apply only");
-        fine_dispatch<T, OP_APPLY, true>(h, x, b, y, omega, done, partials, s, ch);
-        return;
-    }
-    switch (op) {
-        case OP_APPLY: fine_dispatch<T, OP_APPLY, false>(h, x, b, y, omega, done, partials, s, ch); break;
-        case OP_RESID: fine_dispatch<T, OP_RESID, false>(h, x, b, y, omega, done, partials, s, ch); break;
-        case OP_SMOOTH: fine_dispatch<T, OP_SMOOTH, false>(h, x, b, y, omega, done, partials, s, ch); break;
-        case OP_CHEB: fine_dispatch<T, OP_CHEB, false>(h, x, b, y, omega, done, partials, s, ch); break;
-        default:
-            if (!partials) fail(TM_ERR_ARG, "q = K~p needs a partial-sum buffer");
-            fine_dispatch<T, OP_QDOT, false>(h, x, b, y, omega, done, partials, s, ch);
-            break;
-    }
+    LaneIO l{};
+    l.h = h;
+    l.x = x;
+    l.b = b;
+    l.y = y;
+    l.done = done;
+    l.part = partials;
+    l.din = ch.din;
+    l.dout = ch.dout;
+    launch_fine_op_b<T>(op, mask_in, &l, 1, omega, ch.c1, ch.c2, s);
 }
 template void launch_fine_op<double>(const tm_hierarchy*, int, bool, const double*, const double*,
                                      double*, double, const int*, double*, hipStream_t, const ChebArgs&);

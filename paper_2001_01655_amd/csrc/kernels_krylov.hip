@@ -100,7 +100,15 @@ __device__ __forceinline__ void fin_sums(const double* part, int nparts, double 
     __syncthreads();
 }
 
-__global__ __launch_bounds__(FB) void k_finalize(KScal* sc, const double* part, int nparts, int what) {
+struct FinA {
+    KScal* sc;
+    const double* part;
+};
+
+template <int NB>
+__global__ __launch_bounds__(FB) void k_finalize(const Pack<FinA, NB> pk, int nparts, int what) {
+    KScal* sc = lane_of(pk).sc;
+    const double* part = lane_of(pk).part;
     if (sc->done) return;
     if (what == FIN_ALPHA) {
         double t[2];
@@ -160,8 +168,25 @@ __global__ __launch_bounds__(FB) void k_finalize(KScal* sc, const double* part, 
     }
 }
 
+void launch_finalize_b(const LaneIO* L, int n, int nparts, int what, hipStream_t s) {
+    for (int q0 = 0; q0 < n; q0 += MAXB) {
+        const int m = std::min(MAXB, n - q0);
+        if (m == 1) {
+            Pack<FinA, 1> pk{{{L[q0].sc, L[q0].part}}};
+            hipLaunchKernelGGL((k_finalize<1>), dim3(1, 1), dim3(FB), 0, s, pk, nparts, what);
+        } else {
+            Pack<FinA, MAXB> pk{};
+            for (int q = 0; q < m; ++q) pk.a[q] = FinA{L[q0 + q].sc, L[q0 + q].part};
+            hipLaunchKernelGGL((k_finalize<MAXB>), dim3(1, m), dim3(FB), 0, s, pk, nparts, what);
+        }
+    }
+}
+
 void launch_finalize(KScal* sc, const double* part, int nparts, int what, hipStream_t s) {
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(FB), 0, s, sc, part, nparts, what);
+    LaneIO l{};
+    l.sc = sc;
+    l.part = const_cast<double*>(part);
+    launch_finalize_b(&l, 1, nparts, what, s);
 }
 
 // init: ||f||^2 and ||r||^2, then the scalars of a fresh solve
@@ -219,12 +244,27 @@ void launch_fcg_init(const tm_hierarchy* h, Lane& ln, KScal* sc, int use_u0, dou
 // Node-parallel: u += alpha p, r -= alpha q, ||r||^2; the r copy handed to the
 // V-cycle (FP32 in the mixed path) and the V-cycle's first fine-level sweep
 // from zero, x0 = omega D^-1 r, are produced in the same pass.
+template <typename TV>
+struct UrA {
+    double* u;
+    double* r;
+    const double* p;
+    const double* q;
+    TV* rv;
+    TV* x0;
+    const TV* dinv;
+    const KScal* sc;
+    double* part;
+};
+
+// (a function of its own so that the lane's pointers keep their no-alias
+// qualifiers: the updates of u and r are in place)
 template <typename TV, int BS>
-__global__ __launch_bounds__(WG) void k_update_ur(double* __restrict__ u, double* __restrict__ r,
-                                                  const double* __restrict__ p, const double* __restrict__ q,
-                                                  TV* __restrict__ rv, TV* __restrict__ x0,
-                                                  const TV* __restrict__ dinv, TV omega, int64_t N,
-                                                  const KScal* __restrict__ sc, double* part) {
+__device__ __forceinline__ void update_ur_body(double* __restrict__ u, double* __restrict__ r,
+                                               const double* __restrict__ p, const double* __restrict__ q,
+                                               TV* __restrict__ rv, TV* __restrict__ x0,
+                                               const TV* __restrict__ dinv, TV omega, int64_t N,
+                                               const KScal* __restrict__ sc, double* part) {
     if (sc->done) return;
     const double alpha = sc->alpha;
     const int64_t node = xcd_block() * WG + threadIdx.x;
@@ -252,36 +292,86 @@ __global__ __launch_bounds__(WG) void k_update_ur(double* __restrict__ u, double
     block_reduce_store<1>(v, part);
 }
 
+template <typename TV, int BS, int NB>
+__global__ __launch_bounds__(WG) void k_update_ur(const Pack<UrA<TV>, NB> pk, TV omega, int64_t N) {
+    const UrA<TV>& A_ = lane_of(pk);
+    update_ur_body<TV, BS>(A_.u, A_.r, A_.p, A_.q, A_.rv, A_.x0, A_.dinv, omega, N, A_.sc, A_.part);
+}
+
 // one block per WG nodes; its partial sums of |r|^2 are finalised with this count
 int update_ur_blocks(const tm_hierarchy* h) { return (int)grid_for(h->lv[0].n_nodes); }
 
-template <typename TV>
-static void update_ur_t(const tm_hierarchy* h, Lane& ln, KScal* sc, double* u, TV* rv, TV* x0,
-                        const TV* dinv, hipStream_t s) {
-    const Level& L = h->lv[0];
-    const dim3 g(update_ur_blocks(h)), b(WG);
+template <typename TV, int BS, int NB>
+static void update_ur_launch(const LaneIO* L, int n, bool mixed, hipStream_t s) {
+    const tm_hierarchy* h = L[0].h;
+    Pack<UrA<TV>, NB> pk{};
+    for (int q = 0; q < n; ++q) {
+        Lane& ln = *L[q].ln;
+        const Level& F = L[q].h->lv[0];
+        UrA<TV>& a = pk.a[q];
+        a.u = L[q].u;
+        a.r = ln.r;
+        a.p = ln.p;
+        a.q = ln.q;
+        a.rv = mixed ? (TV*)ln.r32 : nullptr;
+        a.x0 = mixed ? (TV*)ln.v32.x[0] : (TV*)ln.v64.x[0];
+        a.dinv = mixed ? (const TV*)F.dinv32 : (const TV*)F.dinv64;
+        a.sc = L[q].sc;
+        a.part = ln.part;
+    }
     const TV w = (TV)first_sweep_weight(h, 0);
-    if (L.bs == 3)
-        hipLaunchKernelGGL((k_update_ur<TV, 3>), g, b, 0, s, u, ln.r, ln.p, ln.q, rv, x0, dinv, w, L.n_nodes,
-                           sc, ln.part);
-    else
-        hipLaunchKernelGGL((k_update_ur<TV, 2>), g, b, 0, s, u, ln.r, ln.p, ln.q, rv, x0, dinv, w, L.n_nodes,
-                           sc, ln.part);
+    hipLaunchKernelGGL((k_update_ur<TV, BS, NB>), dim3(update_ur_blocks(h), n), dim3(WG), 0, s, pk, w,
+                       h->lv[0].n_nodes);
 }
 
-void launch_update_ur(const tm_hierarchy* h, Lane& ln, KScal* sc, double* u, bool mixed,
-                      hipStream_t s) {
-    if (mixed)
-        update_ur_t<float>(h, ln, sc, u, ln.r32, (float*)ln.v32.x[0], h->lv[0].dinv32, s);
-    else
-        update_ur_t<double>(h, ln, sc, u, nullptr, (double*)ln.v64.x[0], h->lv[0].dinv64, s);
+template <typename TV>
+static void update_ur_t(const LaneIO* L, int n, bool mixed, hipStream_t s) {
+    const int bs = L[0].h->lv[0].bs;
+    for (int q0 = 0; q0 < n; q0 += MAXB) {
+        const int m = std::min(MAXB, n - q0);
+        if (bs == 3) {
+            if (m == 1) update_ur_launch<TV, 3, 1>(L + q0, 1, mixed, s);
+            else update_ur_launch<TV, 3, MAXB>(L + q0, m, mixed, s);
+        } else {
+            if (m == 1) update_ur_launch<TV, 2, 1>(L + q0, 1, mixed, s);
+            else update_ur_launch<TV, 2, MAXB>(L + q0, m, mixed, s);
+        }
+    }
+}
+
+void launch_update_ur_b(const LaneIO* L, int n, bool mixed, hipStream_t s) {
+    if (n < 1) return;
+    if (mixed) update_ur_t<float>(L, n, true, s);
+    else update_ur_t<double>(L, n, false, s);
+}
+
+void launch_update_ur(const tm_hierarchy* h, Lane& ln, KScal* sc, double* u, bool mixed, hipStream_t s) {
+    LaneIO l{};
+    l.h = h;
+    l.ln = &ln;
+    l.sc = sc;
+    l.u = u;
+    launch_update_ur_b(&l, 1, mixed, s);
 }
 
 // ---------------------------------------------------------------- z dots, beta, p
 template <typename TZ>
-__global__ void k_zdots(const TZ* __restrict__ z, const double* __restrict__ q,
-                        const double* __restrict__ r, int64_t n, const KScal* __restrict__ sc,
-                        double* part) {
+struct ZdA {
+    const TZ* z;
+    const double* q;
+    const double* r;
+    const KScal* sc;
+    double* part;
+};
+
+template <typename TZ, int NB>
+__global__ void k_zdots(const Pack<ZdA<TZ>, NB> pk, int64_t n) {
+    const ZdA<TZ>& A_ = lane_of(pk);
+    const TZ* __restrict__ z = A_.z;
+    const double* __restrict__ q = A_.q;
+    const double* __restrict__ r = A_.r;
+    const KScal* __restrict__ sc = A_.sc;
+    double* part = A_.part;
     if (sc->done) return;
     double v[2] = {0.0, 0.0};
     for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += (int64_t)gridDim.x * WG) {
@@ -292,31 +382,86 @@ __global__ void k_zdots(const TZ* __restrict__ z, const double* __restrict__ q,
     block_reduce_store<2>(v, part);
 }
 
+template <typename TZ, int NB>
+static void zdots_launch(const LaneIO* L, int n, hipStream_t s) {
+    Pack<ZdA<TZ>, NB> pk{};
+    for (int q = 0; q < n; ++q) {
+        Lane& ln = *L[q].ln;
+        pk.a[q] = ZdA<TZ>{sizeof(TZ) == 4 ? (const TZ*)ln.z32 : (const TZ*)ln.z64, ln.q, ln.r, L[q].sc, ln.part};
+    }
+    const int64_t nd = L[0].h->n_dof;
+    hipLaunchKernelGGL((k_zdots<TZ, NB>), dim3(krylov_blocks(nd), n), dim3(WG), 0, s, pk, nd);
+}
+
+void launch_zdots_b(const LaneIO* L, int n, bool mixed, hipStream_t s) {
+    for (int q0 = 0; q0 < n; q0 += MAXB) {
+        const int m = std::min(MAXB, n - q0);
+        if (mixed) {
+            if (m == 1) zdots_launch<float, 1>(L + q0, 1, s);
+            else zdots_launch<float, MAXB>(L + q0, m, s);
+        } else {
+            if (m == 1) zdots_launch<double, 1>(L + q0, 1, s);
+            else zdots_launch<double, MAXB>(L + q0, m, s);
+        }
+    }
+}
+
 void launch_zdots(const tm_hierarchy* h, Lane& ln, KScal* sc, bool mixed, hipStream_t s) {
-    const int64_t n = h->n_dof;
-    const int nb = krylov_blocks(n);
-    if (mixed)
-        hipLaunchKernelGGL(k_zdots<float>, dim3(nb), dim3(WG), 0, s, ln.z32, ln.q, ln.r, n, sc, ln.part);
-    else
-        hipLaunchKernelGGL(k_zdots<double>, dim3(nb), dim3(WG), 0, s, ln.z64, ln.q, ln.r, n, sc, ln.part);
+    LaneIO l{};
+    l.h = h;
+    l.ln = &ln;
+    l.sc = sc;
+    launch_zdots_b(&l, 1, mixed, s);
 }
 
 template <typename TZ>
-__global__ void k_update_p(double* __restrict__ p, const TZ* __restrict__ z, int64_t n,
-                           const KScal* __restrict__ sc) {
+struct UpA {
+    double* p;
+    const TZ* z;
+    const KScal* sc;
+};
+
+template <typename TZ, int NB>
+__global__ void k_update_p(const Pack<UpA<TZ>, NB> pk, int64_t n) {
+    double* __restrict__ p = lane_of(pk).p;
+    const TZ* __restrict__ z = lane_of(pk).z;
+    const KScal* __restrict__ sc = lane_of(pk).sc;
     if (sc->done) return;
     const double beta = sc->beta;
     for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += (int64_t)gridDim.x * WG)
         p[i] = (double)z[i] + beta * p[i];
 }
 
+template <typename TZ, int NB>
+static void update_p_launch(const LaneIO* L, int n, hipStream_t s) {
+    Pack<UpA<TZ>, NB> pk{};
+    for (int q = 0; q < n; ++q) {
+        Lane& ln = *L[q].ln;
+        pk.a[q] = UpA<TZ>{ln.p, sizeof(TZ) == 4 ? (const TZ*)ln.z32 : (const TZ*)ln.z64, L[q].sc};
+    }
+    const int64_t nd = L[0].h->n_dof;
+    hipLaunchKernelGGL((k_update_p<TZ, NB>), dim3(krylov_blocks(nd), n), dim3(WG), 0, s, pk, nd);
+}
+
+void launch_update_p_b(const LaneIO* L, int n, bool mixed, hipStream_t s) {
+    for (int q0 = 0; q0 < n; q0 += MAXB) {
+        const int m = std::min(MAXB, n - q0);
+        if (mixed) {
+            if (m == 1) update_p_launch<float, 1>(L + q0, 1, s);
+            else update_p_launch<float, MAXB>(L + q0, m, s);
+        } else {
+            if (m == 1) update_p_launch<double, 1>(L + q0, 1, s);
+            else update_p_launch<double, MAXB>(L + q0, m, s);
+        }
+    }
+}
+
 void launch_update_p(const tm_hierarchy* h, Lane& ln, KScal* sc, bool mixed, hipStream_t s) {
-    const int64_t n = h->n_dof;
-    const int nb = krylov_blocks(n);
-    if (mixed)
-        hipLaunchKernelGGL(k_update_p<float>, dim3(nb), dim3(WG), 0, s, ln.p, ln.z32, n, sc);
-    else
-        hipLaunchKernelGGL(k_update_p<double>, dim3(nb), dim3(WG), 0, s, ln.p, ln.z64, n, sc);
+    LaneIO l{};
+    l.h = h;
+    l.ln = &ln;
+    l.sc = sc;
+    launch_update_p_b(&l, 1, mixed, s);
 }
 
 // ---------------------------------------------------------------- outputs

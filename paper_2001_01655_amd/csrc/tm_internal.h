@@ -128,6 +128,66 @@ struct KeVals {
     T k[KE_MAX_CLASSES];
 };
 
+// Lane batching: a kernel of the solve path runs the same operation for up to
+// MAXB lanes (right-hand sides of one or several hierarchies with the same
+// level structure) in one launch; blockIdx.y selects the lane, whose pointers
+// travel by value in the kernel arguments.  NB = 1 for single launches.
+constexpr int MAXB = 8;
+template <typename A, int NB>
+struct Pack {
+    A a[NB];
+};
+template <typename A, int NB>
+__device__ __forceinline__ const A& lane_of(const Pack<A, NB>& pk) {
+    return pk.a[NB == 1 ? 0 : blockIdx.y];
+}
+
+// per-lane operands of the level operators (fine matrix-free and stored stencil)
+template <typename T>
+struct OpA {
+    const T* E;          // fine: moduli; stencil: the stored operator
+    const float* KA;     // fine FP32 on the matrix cores: KE columns
+    const uint8_t* nm;   // fine: support mask
+    const T* x;
+    const T* b;
+    T* y;
+    const T* dinv;
+    const int* done;
+    double* partials;
+    const T* din;        // Chebyshev step: previous direction (or the iterate) ...
+    T* dout;             // ... and the new direction (NULL: not kept)
+};
+template <typename T>
+struct RestrictA {
+    const T* rf;
+    const uint8_t* nm;
+    T* bc;
+    T* xc;
+    const T* dinv;
+    const int* done;
+};
+template <typename T>
+struct ProlongA {
+    const T* xc;
+    const uint8_t* nm;
+    T* xf;
+    const int* done;
+};
+template <typename T>
+struct DenseA {
+    const double* Ainv;
+    const T* b;
+    T* x;
+    const int* done;
+};
+template <typename T>
+struct FirstA {
+    const T* b;
+    const T* dinv;
+    T* x;
+    const int* done;
+};
+
 // Status flags written by kernels (checked by the host after setup phases).
 enum : int { FLAG_BAD_RHO = 1, FLAG_NOT_SPD = 2, FLAG_OVERFLOW = 4 };
 
@@ -294,15 +354,8 @@ struct tm_solve_state {
     std::vector<tmi::Lane*> lanes;
     tmi::KScal* sc = nullptr;      // device scalars [nrhs]
     tmi::KScal* sc_host = nullptr; // pinned mirror
-    hipEvent_t ev = nullptr;
-    // tm_solve: right-hand sides 1.. run on streams of their own (lane 0 on s),
-    // forked from and joined back into s around every batch of enqueued work.
-    // States driven by a scheduler (tm_solve_begin) keep all lanes on s: the
-    // scheduler already overlaps requests, and more streams than hardware
-    // queues only serialise them.
-    std::vector<hipStream_t> ls;
-    std::vector<hipEvent_t> lev;
-    hipEvent_t fork = nullptr;
+    hipEvent_t ev = nullptr;       // the scalars' host copy has arrived
+    hipEvent_t order = nullptr;    // marks the work queued on s (start of a batch on another stream)
     bool ended = false, pending = false;
     bool owned_by_h = false;
     size_t bytes = 0;
@@ -334,6 +387,44 @@ struct Lane {
 };
 
 void delete_cached_state(tm_hierarchy* h);
+
+// One lane of a batched launch (host side): its hierarchy and the vectors the
+// operation reads and writes.  Operators: x in, b right-hand side, y out,
+// din / dout the Chebyshev directions, part the partial sums; transfers: x in,
+// y out, y2 the coarse level's first sweep; dense solve: x = b in, y out;
+// Krylov updates: the lane's scalars, vectors and solution.
+struct LaneIO {
+    const tm_hierarchy* h = nullptr;
+    const void* x = nullptr;
+    const void* b = nullptr;
+    void* y = nullptr;
+    void* y2 = nullptr;
+    const int* done = nullptr;
+    double* part = nullptr;
+    const void* din = nullptr;
+    void* dout = nullptr;
+    KScal* sc = nullptr;
+    Lane* ln = nullptr;
+    double* u = nullptr;
+};
+// batched launchers: n lanes (any number; MAXB per launch) of hierarchies with
+// the same level structure and options; the lanes' own pointers differ
+template <typename T>
+void launch_fine_op_b(int op, bool mask_in, const LaneIO* L, int n, T omega, double c1, double c2, hipStream_t s);
+template <typename T>
+void launch_stencil_op_b(int level, int op, const LaneIO* L, int n, T omega, double c1, double c2, hipStream_t s);
+template <typename T>
+void launch_restrict_b(int fine_level, const LaneIO* L, int n, T omega, hipStream_t s);
+template <typename T>
+void launch_prolong_b(int fine_level, const LaneIO* L, int n, hipStream_t s);
+template <typename T>
+void launch_first_smooth_b(int level, const LaneIO* L, int n, T omega, hipStream_t s);
+template <typename T>
+void launch_dense_solve_b(const LaneIO* L, int n, hipStream_t s);
+void launch_finalize_b(const LaneIO* L, int n, int nparts, int what, hipStream_t s);
+void launch_update_ur_b(const LaneIO* L, int n, bool mixed, hipStream_t s);
+void launch_zdots_b(const LaneIO* L, int n, bool mixed, hipStream_t s);
+void launch_update_p_b(const LaneIO* L, int n, bool mixed, hipStream_t s);
 // device memory of a hierarchy (host.cpp): from its allocator or hipMalloc;
 // a list is returned after the device has finished with it
 void* dev_alloc(const tm_hierarchy* h, size_t bytes);
@@ -376,25 +467,11 @@ void launch_galerkin_unit(int dim, const double* KE, double* G, hipStream_t s);
 void launch_stencil_assemble(const Level& L, const double* elem, hipStream_t s);
 void launch_stencil_compact(const Level& L, hipStream_t s);
 void launch_stencil_dinv(const Level& L, int point_jacobi, int* flags, hipStream_t s);
-template <typename T>
-void launch_stencil_op(const Level& L, int op, const T* x, const T* b, T* y, T omega,
-                       const int* done, hipStream_t s, const ChebArgs& ch = ChebArgs{});
-template <typename T>
-void launch_restrict(const Level& fine, const Level& coarse, const T* rf, T* bc, T* xc_first,
-                     T omega, const int* done, hipStream_t s);
-template <typename T>
-void launch_prolong(const Level& fine, const Level& coarse, const T* xc, T* xf, const int* done,
-                    hipStream_t s);
-template <typename T>
-void launch_first_smooth(const Level& L, const T* b, T* x, T omega, const int* done, hipStream_t s);
 // dense coarsest level (kernels_dense.hip)
 void launch_dense_from_stencil(const Level& L, double* Ad, hipStream_t s);
 void launch_dense_from_bsr(const Level& L, double* Ad, hipStream_t s);
 int chol_block_elems();  // scratch doubles the blocked factorisation needs
 void launch_cholesky_inverse(double* A, double* Ainv, double* Ls, int64_t n, int* flags, hipStream_t s);
-template <typename T>
-void launch_dense_solve(const double* Ainv, int64_t n, const T* b, T* x, const int* done,
-                        hipStream_t s);
 // aggregation levels (kernels_sa.hip)
 template <typename T>
 void launch_bsr_op(const Level& L, int op, const T* x, const T* b, T* y, T omega, const int* done,

@@ -10,10 +10,12 @@ The loop:
   * admits queued requests whose arrival time has passed while a slot and
     enough HBM (tm_plan_bytes) are free; the hierarchy stays resident for all
     of the request's design iterations (tm_update_density between them);
-  * keeps every admitted request's solve on its own HIP stream and advances
-    all running solves together with one batched call (tm_batch_advance), a
-    few iterations at a time, so work of different requests overlaps on the
-    device; results never mix across requests;
+  * keeps every admitted request on its own HIP stream (setup, design
+    updates) and advances all running solves together with one batched call
+    (tm_batch_iterate) on the server's stream, a few iterations at a time:
+    the load cases of requests with the same level structure share every
+    launch of an iteration, so small requests stop paying a launch each;
+    results never mix across requests;
   * polls without blocking, retires finished solves, frees slot and memory
     when a request completes, and records latency from arrival to completion.
 
@@ -183,11 +185,12 @@ class GpuEngine:
     def __init__(self, **options):
         import torch
         from . import _lib as L
-        from .solver import Hierarchy, tm_batch_advance
+        from .solver import Hierarchy, tm_batch_iterate
         self.torch = torch
         self.L = L
         self.Hierarchy = Hierarchy
-        self._batch = tm_batch_advance
+        self._batch = tm_batch_iterate
+        self._stream = torch.cuda.Stream()     # grouped iterations of all requests
         self.options = options          # library options for every request (before the request's own)
 
     def _opts(self, req: Request) -> dict:
@@ -221,7 +224,7 @@ class GpuEngine:
         return st.poll()
 
     def batch_advance(self, states, k: int):
-        self._batch(states, k)
+        self._batch(states, k, self._stream)
 
     def end(self, st):
         return st.end()

@@ -282,9 +282,11 @@ class SolveState:
         return self.result
 
 
-def tm_batch_advance(states: Sequence[SolveState], k: int):
+def tm_batch_iterate(states: Sequence[SolveState], k: int, stream: Optional[torch.cuda.Stream] = None):
+    """k iterations of every state as grouped launches on `stream` (default:
+    the current stream)."""
     arr = (C.c_void_p * len(states))(*[s.handle for s in states])
-    check(LIB.tm_batch_advance(len(states), arr, k), "tm_batch_advance")
+    check(LIB.tm_batch_iterate(len(states), arr, k, _stream_ptr(stream)), "tm_batch_iterate")
 
 
 def density_filter(nel: Sequence[int], x, radius: float = 1.5, transpose: bool = False,
