@@ -68,7 +68,9 @@ def parse():
                     help="skip the multi-RHS and density-filter legs (profiled runs: only the headline solves)")
     ap.add_argument("--stability", action="store_true",
                     help="add the stability eigenproblem legs (generalized Davidson on the 2D column)")
-    ap.add_argument("--served", type=int, default=24, help="requests in the served-stream leg (0: skip)")
+    ap.add_argument("--served", type=int, default=200, help="requests in the served-stream leg (0: skip)")
+    ap.add_argument("--served-hybrid-every", type=int, default=8,
+                    help="every n-th served request is a hybrid (aggregation) hierarchy (0: none)")
     ap.add_argument("--served-designs", type=int, default=20)
     ap.add_argument("--served-smoother", default="chebyshev", choices=sorted(SMOOTHERS))
     ap.add_argument("--served-sweeps", type=int, default=2)
@@ -88,6 +90,11 @@ def parse():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="copy 256 MiB device-to-device first (counter calibration under rocprofv3 --pmc)")
     return ap.parse_args()
+
+
+def progress(msg: str) -> None:
+    """A progress line on stderr (the JSON record alone goes to stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def src_hash(names) -> str:
@@ -246,12 +253,14 @@ def cpu_baseline(cfg_name, args):
 
 
 def served_leg(n_req: int, n_designs: int, smoother: str = "chebyshev", sweeps: int = 2, seed: int = 5,
-               warm_steps: int = 4):
+               warm_steps: int = 4, hybrid_every: int = 8, fractions=(0.5, 0.7, 0.9)):
     """The served stream (mixed 2D/3D sizes, 1-4 load cases, design updates
-    with warm starts, rtol 1e-6): first every request at t = 0 to find the
-    saturation throughput, then Poisson arrivals at 70% of that request rate;
-    latency = arrival to the request's last solve.  Densities are generated
-    before the timed runs."""
+    with warm starts, rtol 1e-6; every hybrid_every-th request a hybrid
+    hierarchy, smoothed aggregation below two geometric levels): first every
+    request at t = 0 to find the saturation throughput, then Poisson arrivals
+    at fractions of that request rate; latency = arrival to the request's last
+    solve.  The record's p50 / p99 / solves_per_s are those at 70%.  Densities
+    are generated before the timed runs."""
     import dataclasses
 
     import numpy as np
@@ -259,28 +268,58 @@ def served_leg(n_req: int, n_designs: int, smoother: str = "chebyshev", sweeps: 
     import synth
     from paper_2001_01655_amd.serving import GpuEngine, Server, served_requests
     reqs = served_requests(n_req, rate_per_s=1.0, n_designs=n_designs, seed=seed, rtol=1e-6)
-    for r in reqs:
+    if hybrid_every > 0:
+        for r in reqs:
+            if r.rid % hybrid_every == hybrid_every - 1:
+                r.options = dict(r.options, n_geometric=2, max_coarse=1000)
+    hybrid_ids = {r.rid for r in reqs if "n_geometric" in r.options}
+    for i, r in enumerate(reqs):
         for t in range(n_designs):
             r.densities(t)
+        if (i + 1) % 25 == 0:
+            progress(f"served: densities of {i + 1}/{n_req} requests")
     warm = warm_steps if smoother == "chebyshev" else 0
     eng = GpuEngine(smoother=SMOOTHERS[smoother], nu_pre=sweeps, nu_post=sweeps, cheb_warm_steps=warm)
     budget = 64 << 30
-    Server(eng, budget, max_slots=8, chunk=4, rtol=1e-6).run(
-        [dataclasses.replace(r, arrival=0.0, n_designs=2) for r in reqs[:4]])          # warm-up
-    sat = Server(eng, budget, max_slots=8, chunk=4, rtol=1e-6).run(
+    Server(eng, budget, max_slots=8, chunk=4, rtol=1e-6, workers=4).run(
+        [dataclasses.replace(r, arrival=0.0, n_designs=2) for r in reqs[:8]])          # warm-up
+    sat = Server(eng, budget, max_slots=8, chunk=4, rtol=1e-6, workers=4).run(
         [dataclasses.replace(r, arrival=0.0) for r in reqs])
-    rate = 0.7 * n_req / sat["makespan_s"]
-    arr = synth.poisson_arrivals(n_req, rate, seed)
-    res = Server(eng, budget, max_slots=8, chunk=4, rtol=1e-6).run(
-        [dataclasses.replace(r, arrival=float(a)) for r, a in zip(reqs, arr)])
+    progress(f"served: saturation {sat['solves_per_s']:.0f} solves/s")
+    sweep = []
+    main = None
+    for fr in fractions:
+        rate = fr * n_req / sat["makespan_s"]
+        arr = synth.poisson_arrivals(n_req, rate, seed)
+        res = Server(eng, budget, max_slots=8, chunk=4, rtol=1e-6, workers=4).run(
+            [dataclasses.replace(r, arrival=float(a)) for r, a in zip(reqs, arr)])
+        ok = all(st == 0 for o in res["outcomes"] for st in o.status)
+        by_kind = {}
+        for kind, sel in (("geometric", False), ("hybrid", True)):
+            lat = [o.latency * 1e3 for o in res["outcomes"] if hybrid_ids.__contains__(o.rid) == sel]
+            if lat:
+                by_kind[kind] = {"requests": len(lat), "p50_ms": round(float(np.percentile(lat, 50)), 2),
+                                 "p99_ms": round(float(np.percentile(lat, 99)), 2)}
+        sweep.append({"fraction_of_saturation": fr, "arrival_rate_per_s": round(rate, 3),
+                      "p50_ms": round(res["p50_ms"], 2), "p99_ms": round(res["p99_ms"], 2),
+                      "solves_per_s": round(res["solves_per_s"], 1), "all_converged": ok,
+                      "latency_by_kind": by_kind})
+        progress(f"served: {fr:.0%} of saturation, p50 {res['p50_ms']:.1f} ms, p99 {res['p99_ms']:.1f} ms")
+        if abs(fr - 0.7) < 1e-9:
+            main = res
+    res = main
     iters = [i for o in res["outcomes"] for d in o.iters for i in d]
     ok = all(st == 0 for o in res["outcomes"] for st in o.status)
     return {"p50_ms": round(res["p50_ms"], 2), "p99_ms": round(res["p99_ms"], 2),
-            "solves_per_s": round(res["solves_per_s"], 1), "arrival_rate_per_s": round(rate, 3),
-            "saturation_solves_per_s": round(sat["solves_per_s"], 1), "requests": n_req,
+            "solves_per_s": round(res["solves_per_s"], 1),
+            "arrival_rate_per_s": next(x["arrival_rate_per_s"] for x in sweep if x["fraction_of_saturation"] == 0.7),
+            "latency_by_kind": next(x["latency_by_kind"] for x in sweep if x["fraction_of_saturation"] == 0.7),
+            "saturation_solves_per_s": round(sat["solves_per_s"], 1), "rate_sweep": sweep, "requests": n_req,
+            "hybrid_requests": sum(1 for r in reqs if "n_geometric" in r.options),
             "designs_per_request": n_designs, "solves": res["solves"], "all_converged": ok,
             "mean_iters": round(float(np.mean(iters)), 2) if iters else None,
-            "max_slots": 8, "chunk": 4, "latency": "request arrival to its last solve",
+            "max_slots": 8, "chunk": 4, "workers": 4, "latency": "request arrival to its last solve",
+            "launches": "right-hand sides of requests with the same level structure share each launch",
             "sizes": "2D 128x64, 2D 512x256, 3D 48^3, 3D 96x48x48; 1-4 load cases; rtol 1e-6",
             "smoothing": f"{smoother} {sweeps}/{sweeps}", "cheb_warm_steps": warm}
 
@@ -567,6 +606,7 @@ def main():
         return H, time.perf_counter() - t0
 
     H, t_setup = build(32, 0)
+    progress("headline solves")
     dt, res = timed_solves(H, f, args.steps, args.warmup, rtol)
     ms = dt / args.steps * 1e3
     value = p.n_dof * args.steps / dt / 1e6
@@ -611,6 +651,7 @@ def main():
     if ref:
         line["oracle_error"] = ref
     if not args.no_side_legs:
+        progress("multi-RHS leg")
         line["multi_rhs"] = multi_rhs_leg(H, p)
     H.close()
     if not args.no_side_legs:
@@ -619,6 +660,7 @@ def main():
         line["eigen"] = eigen_leg()
         line["stability_stream"] = stability_stream_leg()
     if not args.no_fp64:
+        progress("FP64 PCG comparison")
         H64, t64s = build(64, 1)
         k64 = max(1, args.steps // 2)
         dt64, r64 = timed_solves(H64, f, k64, 1, rtol)
@@ -630,13 +672,16 @@ def main():
         H64.close()
     line["detail"] = detail
     if args.served > 0:
+        progress("served stream")
         line["served"] = served_leg(args.served, args.served_designs, args.served_smoother, args.served_sweeps,
+                                    hybrid_every=args.served_hybrid_every,
                                     warm_steps=args.served_warm_steps)
     if args.grid_study:
         line["grid_study"] = grid_leg()
     if args.adaptive_stream > 0:
         line["adaptive_stream"] = adaptive_leg(args.adaptive_stream)
     if not args.no_cpu_baseline:
+        progress("oracle baseline on the host")
         cb = cpu_baseline(wl["cfg"], args)
         if cb:
             line["cpu_baseline"] = cb

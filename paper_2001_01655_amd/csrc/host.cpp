@@ -81,6 +81,58 @@ void dev_free_list(const tm_hierarchy* h, std::vector<void*>& list) {
     list.clear();
 }
 
+void* arena_get(const tm_hierarchy* h, Arena& a, size_t bytes) {
+    const size_t b = (std::max<size_t>(bytes, 1) + 255) & ~(size_t)255;
+    a.need += b;
+    if (a.used + b <= a.cap) {
+        void* p = a.base + a.used;
+        a.used += b;
+        return p;
+    }
+    void* p = dev_alloc(h, b);
+    a.overflow.push_back(p);
+    a.overflow_bytes += b;
+    return p;
+}
+
+void arena_reset(Arena& a) {
+    a.peak = std::max(a.peak, a.need);
+    a.need = 0;
+    a.used = 0;
+}
+
+void arena_prepare(const tm_hierarchy* h, Arena& a) {
+    arena_reset(a);
+    if (a.overflow.empty()) {
+        a.peak = 0;
+        return;
+    }
+    // the last rebuild outgrew the buffer: one buffer for its largest cycle
+    // (with headroom), once the device is done with the old blocks
+    const size_t want = a.peak + a.peak / 4;
+    std::vector<void*> old = a.overflow;
+    if (a.base) old.push_back(a.base);
+    dev_free_list(h, old);
+    a.overflow.clear();
+    a.overflow_bytes = 0;
+    a.base = nullptr;
+    a.cap = 0;
+    a.base = (char*)dev_alloc(h, want);
+    a.cap = want;
+    a.used = 0;
+    a.need = 0;
+    a.peak = 0;
+}
+
+void arena_release(const tm_hierarchy* h, Arena& a) {
+    std::vector<void*> all = a.overflow;
+    if (a.base) all.push_back(a.base);
+    dev_free_list(h, all);
+    a = Arena();
+}
+
+size_t arena_bytes(const Arena& a) { return a.cap + a.overflow_bytes; }
+
 template <typename T>
 static T* dalloc(const tm_hierarchy* h, std::vector<void*>& list, size_t& bytes, size_t n) {
     const size_t b = std::max<size_t>(n, 1) * sizeof(T);
@@ -727,9 +779,11 @@ static void alloc_vcyc(tm_hierarchy* h, Vcyc& V, std::vector<void*>& list, size_
     V.x.assign(L, nullptr);
     V.t.assign(L, nullptr);
     V.d.assign(L, nullptr);
+    V.cap.assign(L, 0);
     const bool cheb = h->opt.smoother == TM_SMOOTH_CHEBYSHEV;
     for (int l = 0; l < L; ++l) {
         const size_t n = (size_t)h->lv[l].n;
+        V.cap[l] = (int64_t)n;
         if (l > 0) V.b[l] = dalloc<T>(h, list, bytes, n);
         V.x[l] = dalloc<T>(h, list, bytes, n);
         if (l < L - 1) V.t[l] = dalloc<T>(h, list, bytes, n);
@@ -792,6 +846,19 @@ static tm_solve_state* new_state(tm_hierarchy* h, int nrhs) {
 }
 
 static void delete_state(tm_solve_state* st);
+
+// a state's V-cycle vectors still serve the hierarchy's current levels (an
+// update of aggregation levels may change their number or sizes)
+static bool state_fits(const tm_hierarchy* h, const tm_solve_state* st) {
+    const size_t L = h->lv.size();
+    for (const Lane* ln : st->lanes) {
+        const Vcyc& V = mixed_of(h) ? ln->v32 : ln->v64;
+        if (V.cap.size() != L) return false;
+        for (size_t l = 0; l < L; ++l)
+            if (V.cap[l] < h->lv[l].n) return false;
+    }
+    return true;
+}
 
 // drop the states whose V-cycle work vectors follow the current level list
 void delete_cached_state(tm_hierarchy* h) {
@@ -1509,7 +1576,10 @@ static void destroy_impl(tm_hierarchy* h) {
             (void)hipEventDestroy(pr.second);
         }
     tmi::free_list(h, h->allocs);
-    tmi::free_list(h, h->sa_allocs);
+    tmi::arena_release(h, h->sa_keep);
+    tmi::arena_release(h, h->sa_tmp);
+    tmi::arena_release(h, h->sa_cand[0]);
+    tmi::arena_release(h, h->sa_cand[1]);
     delete h;
 }
 
@@ -1695,7 +1765,7 @@ static tm_status begin_impl(tm_hierarchy* h, int32_t n_rhs, const double* f_dev,
         tm_solve_state* st = nullptr;
         h->cur_stream = S(stream);
         if (cached) {
-            if (h->cached && h->cached->nrhs != n_rhs) {
+            if (h->cached && (h->cached->nrhs != n_rhs || !state_fits(h, h->cached))) {
                 delete_state(h->cached);
                 h->cached = nullptr;
             }
@@ -1705,12 +1775,19 @@ static tm_status begin_impl(tm_hierarchy* h, int32_t n_rhs, const double* f_dev,
             }
             st = h->cached;
         } else {
-            for (size_t i = 0; i < h->pool.size(); ++i)
-                if (h->pool[i]->nrhs == n_rhs) {
+            for (size_t i = 0; i < h->pool.size();) {
+                if (!state_fits(h, h->pool[i])) {          // levels outgrew it
+                    delete_state(h->pool[i]);
+                    h->pool.erase(h->pool.begin() + i);
+                    continue;
+                }
+                if (!st && h->pool[i]->nrhs == n_rhs) {
                     st = h->pool[i];
                     h->pool.erase(h->pool.begin() + i);
-                    break;
+                    continue;
                 }
+                ++i;
+            }
             if (!st) st = new_state(h, n_rhs);
         }
         st->s = S(stream);

@@ -41,17 +41,12 @@ void sa_to_f32(const double* a, float* b, int64_t n, hipStream_t s);
 
 namespace {
 
-struct Pool {                       // device allocations with one owner
+struct Pool {                       // typed blocks from one arena
     const tm_hierarchy* h;
-    std::vector<void*>& list;
-    size_t& bytes;
+    Arena& a;
     template <typename T>
     T* get(size_t n) {
-        const size_t b = std::max<size_t>(n, 1) * sizeof(T);
-        void* p = dev_alloc(h, b);
-        list.push_back(p);
-        bytes += b;
-        return (T*)p;
+        return (T*)arena_get(h, a, std::max<size_t>(n, 1) * sizeof(T));
     }
 };
 
@@ -80,10 +75,16 @@ void build_sa_levels(tm_hierarchy* h, hipStream_t s) {
 }
 
 void numeric_sa_levels(tm_hierarchy* h, hipStream_t s) {
-    // drop the levels of a previous setup
-    dev_free_list(h, h->sa_allocs);
-    h->bytes -= std::min(h->bytes, h->sa_bytes);
-    h->sa_bytes = 0;
+    // The new levels overwrite the arenas of the previous ones in stream
+    // order: the rebuild waits for the solves of this hierarchy still queued
+    // on their own streams (no device-wide wait), and only an arena that the
+    // last rebuild outgrew is replaced.
+    if (h->cached) TM_HIP(hipStreamWaitEvent(s, h->cached->ev, 0));
+    for (tm_solve_state* st : h->pool) TM_HIP(hipStreamWaitEvent(s, st->ev, 0));
+    arena_prepare(h, h->sa_keep);
+    arena_prepare(h, h->sa_tmp);
+    arena_prepare(h, h->sa_cand[0]);
+    arena_prepare(h, h->sa_cand[1]);
     int Lg = 0;
     for (auto& L : h->lv)
         if (L.kind != TM_LEVEL_AGGREGATION) ++Lg;
@@ -95,12 +96,21 @@ void numeric_sa_levels(tm_hierarchy* h, hipStream_t s) {
     G0.PT = BSR();
     G0.agg = nullptr;
     G0.n_agg = 0;
-    delete_cached_state(h);      // V-cycle work vectors follow the level list
-    if (G0.n < h->opt.max_coarse) return;
+    // (solve states keep their V-cycle vectors while the new level sizes fit:
+    // checked when the next solve begins)
+    auto account = [&] {
+        h->bytes -= std::min(h->bytes, h->sa_bytes);
+        h->sa_bytes = arena_bytes(h->sa_keep) + arena_bytes(h->sa_tmp) + arena_bytes(h->sa_cand[0]) +
+                      arena_bytes(h->sa_cand[1]);
+        h->bytes += h->sa_bytes;
+    };
+    if (G0.n < h->opt.max_coarse) {
+        account();
+        return;
+    }
 
-    Pool keep{h, h->sa_allocs, h->sa_bytes};
-    std::vector<void*> tmp_list, prev_list;
-    size_t tmp_bytes = 0, prev_bytes = 0;
+    Pool keep{h, h->sa_keep};
+    int step = 0;
     try {
         const int dim = h->dim;
         const int k = dim == 3 ? 6 : 3;
@@ -128,7 +138,8 @@ void numeric_sa_levels(tm_hierarchy* h, hipStream_t s) {
         const double* Bprev = nullptr;
         int cur = Lg - 1;
         while (h->lv[cur].n >= h->opt.max_coarse) {
-            Pool tmp{h, tmp_list, tmp_bytes};
+            arena_reset(h->sa_tmp);
+            Pool tmp{h, h->sa_tmp};
             Level& F = h->lv[cur];
             const int bs = F.bs;
             const int64_t n = F.n_nodes;
@@ -167,10 +178,9 @@ void numeric_sa_levels(tm_hierarchy* h, hipStream_t s) {
             int32_t* mem = tmp.get<int32_t>(n);
             sa_members(n, n_agg, agg, off, cursor, mem, work, s);
             double* T = tmp.get<double>((size_t)n * bs * k);
-            Pool prevp{h, prev_list, prev_bytes};
-            std::vector<void*> next_list;
-            size_t next_bytes = 0;
-            Pool nextp{h, next_list, next_bytes};
+            // this step's candidates (the previous step's stay in the other arena)
+            arena_reset(h->sa_cand[step & 1]);
+            Pool nextp{h, h->sa_cand[step & 1]};
             double* Bc = nextp.get<double>((size_t)n_agg * k * k);
             sa_tentative(n_agg, off, mem, Bprev, dim, F.nn[0], F.nn[1], h->mesh.h, Lg - 1, h->mesh.nel, bs, k, T, Bc,
                          s);
@@ -239,22 +249,14 @@ void numeric_sa_levels(tm_hierarchy* h, hipStream_t s) {
             h->lv.push_back(C);
             ++cur;
             // candidates of the next step: the R factors
-            TM_HIP(hipStreamSynchronize(s));
-            dev_free_list(h, tmp_list);
-            tmp_bytes = 0;
-            dev_free_list(h, prev_list);
-            prev_list = next_list;
-            prev_bytes = next_bytes;
             Bprev = Bc;
+            ++step;
         }
-        TM_HIP(hipStreamSynchronize(s));
-        dev_free_list(h, tmp_list);
-        dev_free_list(h, prev_list);
-        h->bytes += h->sa_bytes;
+        arena_reset(h->sa_tmp);
+        account();
     } catch (...) {
         (void)hipStreamSynchronize(s);
-        dev_free_list(h, tmp_list);
-        dev_free_list(h, prev_list);
+        account();
         throw;
     }
 }

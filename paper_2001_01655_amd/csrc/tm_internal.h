@@ -253,6 +253,23 @@ struct Level {
 struct Vcyc {                     // V-cycle work vectors of one precision, per level
     std::vector<void*> b, x, t;   // rhs, iterate, scratch (same length per level)
     std::vector<void*> d;         // Chebyshev update direction (Chebyshev smoothing only)
+    std::vector<int64_t> cap;     // entries each vector of a level holds
+};
+
+// Grow-only device arena for the aggregation levels, which a density update
+// rebuilds with data-dependent sizes: blocks are cut from one buffer in order
+// and the arena is emptied (reset) when its contents are no longer needed, in
+// stream order.  A request that does not fit gets a block of its own
+// (overflow); the next rebuild replaces buffer and overflow blocks by one
+// buffer large enough for everything, so rebuilds of steady size allocate and
+// free nothing.
+struct Arena {
+    char* base = nullptr;
+    size_t cap = 0, used = 0;
+    size_t need = 0;              // bytes asked for since the last reset
+    size_t peak = 0;              // largest need of a reset cycle since the last rebuild began
+    std::vector<void*> overflow;
+    size_t overflow_bytes = 0;
 };
 
 struct Lane;                      // one right-hand side of a solve state
@@ -323,8 +340,11 @@ struct tm_hierarchy {
     double* elem_b = nullptr;      // (pong)
     size_t bytes = 0;
     std::vector<void*> allocs;
-    std::vector<void*> sa_allocs;  // aggregation levels (rebuilt by every numeric setup)
-    size_t sa_bytes = 0;
+    // aggregation levels (rebuilt by every numeric setup): level data, the
+    // temporaries of one coarsening step, the candidate vectors of two
+    // consecutive steps
+    tmi::Arena sa_keep, sa_tmp, sa_cand[2];
+    size_t sa_bytes = 0;           // the arenas' share of `bytes`
     // kernel timing hooks
     bool timing[3] = {false, false, false};
     std::vector<std::pair<hipEvent_t, hipEvent_t>> tev[3];
@@ -429,6 +449,14 @@ void launch_update_p_b(const LaneIO* L, int n, bool mixed, hipStream_t s);
 // a list is returned after the device has finished with it
 void* dev_alloc(const tm_hierarchy* h, size_t bytes);
 void dev_free_list(const tm_hierarchy* h, std::vector<void*>& list);
+// arenas (host.cpp): a block of at least `bytes` (256-byte aligned); reset for
+// reuse; prepare for a rebuild (one buffer for the last rebuild's total, only
+// if it grew); release everything
+void* arena_get(const tm_hierarchy* h, Arena& a, size_t bytes);
+void arena_reset(Arena& a);
+void arena_prepare(const tm_hierarchy* h, Arena& a);
+void arena_release(const tm_hierarchy* h, Arena& a);
+size_t arena_bytes(const Arena& a);
 
 // ----------------------------------------------------------------- launchers
 // fine level (kernels_fine.hip)

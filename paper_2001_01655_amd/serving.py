@@ -73,6 +73,7 @@ class _Slot:
         self.bytes = bytes_
         self.design = 0
         self.state = None
+        self.prep = None          # pending setup / update + begin (a future)
         self.u = None
         self.admitted = admitted
         self.iters: List[List[int]] = []
@@ -80,11 +81,31 @@ class _Slot:
         self.status: List[int] = []
 
 
+class _Now:
+    """A finished 'future' for work done at once (no worker threads)."""
+
+    def __init__(self, fn):
+        self._v = fn()
+
+    def done(self) -> bool:
+        return True
+
+    def result(self):
+        return self._v
+
+
 class Server:
-    """Admission by HBM footprint, one stream per slot, batched iteration."""
+    """Admission by HBM footprint, one stream per slot, batched iteration.
+
+    workers > 0: a request's setup, each design update with the begin of its
+    next solve, and the release of its hierarchy run on a pool of that many
+    threads, so that a slow update (aggregation levels are rebuilt with
+    host-side waits) never holds up the iterations of the other requests; the
+    loop only collects what has finished.  workers = 0 does everything inline."""
 
     def __init__(self, engine, hbm_budget: int, max_slots: int = 8, chunk: int = 4,
-                 rtol: float = 1e-6, keep_solutions: bool = False):
+                 rtol: float = 1e-6, keep_solutions: bool = False, workers: int = 0):
+        self.workers = int(workers)
         self.engine = engine
         self.budget = int(hbm_budget)
         self.max_slots = int(max_slots)
@@ -96,6 +117,9 @@ class Server:
         self.queue_depth: List[int] = []
 
     # ------------------------------------------------------------------ slots
+    def _later(self, fn):
+        return self._pool.submit(fn) if self._pool is not None else _Now(fn)
+
     def _admit(self, req: Request, now: float) -> Optional[_Slot]:
         need = self.engine.plan_bytes(req)
         if need > self.budget:
@@ -103,13 +127,23 @@ class Server:
         if self.in_use + need > self.budget:
             return None
         stream = self.engine.new_stream()
-        h = self.engine.setup(req, req.densities(0), stream)
         self.in_use += need
         self.peak_in_use = max(self.peak_in_use, self.in_use)
-        return _Slot(req, h, stream, need, now)
+        s = _Slot(req, None, stream, need, now)
 
-    def _start_solve(self, s: _Slot):
-        s.state = self.engine.begin(s.h, s.req, self.rtol, s.u, s.stream)
+        def prepare():
+            s.h = self.engine.setup(req, req.densities(0), stream)
+            return self.engine.begin(s.h, s.req, self.rtol, s.u, s.stream)
+        s.prep = self._later(prepare)
+        return s
+
+    def _next_design(self, s: _Slot):
+        rho = s.req.densities(s.design)
+
+        def prepare():
+            self.engine.update(s.h, rho, s.stream)
+            return self.engine.begin(s.h, s.req, self.rtol, s.u, s.stream)
+        s.prep = self._later(prepare)
 
     def _finish_solve(self, s: _Slot):
         res = self.engine.end(s.state)
@@ -127,44 +161,66 @@ class Server:
         done: List[Outcome] = []
         t0 = clock()
         n_solves = 0
-        while pending or active:
-            now = clock() - t0
-            # admission: arrived requests, in arrival order, while a slot and memory are free
-            while pending and pending[0].arrival <= now and len(active) < self.max_slots:
-                s = self._admit(pending[0], now)
-                if s is None:
-                    break
-                pending.pop(0)
-                self._start_solve(s)
-                active.append(s)
-            self.queue_depth.append(sum(1 for r in pending if r.arrival <= now))
-            # poll all running solves without blocking
-            idle = []
-            for s in list(active):
-                st = self.engine.poll(s.state)
-                if st == 1:                                   # every load case stopped
-                    self._finish_solve(s)
-                    n_solves += s.req.n_rhs
-                    s.design += 1
-                    if s.design < s.req.n_designs:
-                        self.engine.update(s.h, s.req.densities(s.design), s.stream)
-                        self._start_solve(s)
+        releasing = []                                        # (future, bytes)
+        self._pool = None
+        if self.workers > 0:
+            from concurrent.futures import ThreadPoolExecutor
+            self._pool = ThreadPoolExecutor(self.workers)
+        try:
+            while pending or active or releasing:
+                now = clock() - t0
+                # memory of released hierarchies returns to the budget once freed
+                for fr in [x for x in releasing if x[0].done()]:
+                    fr[0].result()
+                    self.in_use -= fr[1]
+                    releasing.remove(fr)
+                # admission: arrived requests, in arrival order, while a slot and memory are free
+                while pending and pending[0].arrival <= now and len(active) < self.max_slots:
+                    s = self._admit(pending[0], now)
+                    if s is None:
+                        break
+                    pending.pop(0)
+                    active.append(s)
+                self.queue_depth.append(sum(1 for r in pending if r.arrival <= now))
+                # collect prepared solves, poll running ones without blocking
+                idle = []
+                for s in list(active):
+                    if s.prep is not None:
+                        if not s.prep.done():
+                            continue
+                        s.state = s.prep.result()
+                        s.prep = None
                         idle.append(s)
-                    else:
-                        fin = clock() - t0
-                        done.append(Outcome(s.req.rid, s.req.arrival, s.admitted, fin, s.iters, s.comp,
-                                            s.status, s.u if self.keep else None))
-                        self.engine.release(s.h)
-                        self.in_use -= s.bytes
-                        active.remove(s)
-                elif st == 0:                                 # chunk finished, keep going
-                    idle.append(s)
-            if idle:
-                self.engine.batch_advance([s.state for s in idle], self.chunk)
-            elif active:
-                time.sleep(5e-5)
-            elif pending:
-                time.sleep(max(0.0, min(1e-3, pending[0].arrival - (clock() - t0))))
+                        continue
+                    st = self.engine.poll(s.state)
+                    if st == 1:                                   # every load case stopped
+                        self._finish_solve(s)
+                        n_solves += s.req.n_rhs
+                        s.design += 1
+                        if s.design < s.req.n_designs:
+                            self._next_design(s)
+                            if s.prep.done():                     # done inline: advance it now
+                                s.state = s.prep.result()
+                                s.prep = None
+                                idle.append(s)
+                        else:
+                            fin = clock() - t0
+                            done.append(Outcome(s.req.rid, s.req.arrival, s.admitted, fin, s.iters, s.comp,
+                                                s.status, s.u if self.keep else None))
+                            h = s.h
+                            releasing.append((self._later(lambda h=h: self.engine.release(h)), s.bytes))
+                            active.remove(s)
+                    elif st == 0:                                 # chunk finished, keep going
+                        idle.append(s)
+                if idle:
+                    self.engine.batch_advance([s.state for s in idle], self.chunk)
+                elif active or releasing:
+                    time.sleep(5e-5)
+                elif pending:
+                    time.sleep(max(0.0, min(1e-3, pending[0].arrival - (clock() - t0))))
+        finally:
+            if self._pool is not None:
+                self._pool.shutdown(wait=True)
         makespan = clock() - t0
         lat = np.array([o.latency for o in done]) if done else np.zeros(1)
         return {

@@ -128,3 +128,34 @@ def test_aggregation_vcycle_chebyshev(kind, nel, ngeo, maxc):
     z = G.vcycle(torch.tensor(b, device="cuda"), fp=64).cpu().numpy()
     assert _rel(z, mg.vcycle(H, b)) <= 1e-8
     G.close()
+
+
+def test_hybrid_updates_reuse_memory_and_match_fresh_setup():
+    """Density updates of a hybrid hierarchy rebuild its aggregation levels in
+    grow-only arenas: once the sizes have been seen, further updates take no
+    device memory, and each solve equals, bit for bit, the solve of a
+    hierarchy set up from scratch for the same densities."""
+    from paper_2001_01655_amd import Hierarchy
+    print("hybrid updates", flush=True)
+    p = synth.small_case(3, (16, 12, 8), seed=81)
+    opts = dict(p=p.p, E0=p.E0, Emin=p.Emin, nu=p.nu, n_geometric=2, max_coarse=300)
+    f = torch.tensor(p.loads[0], device="cuda")
+    G = Hierarchy(p.nel, p.rho, p.fixed, **opts)
+    rhos = [synth.density_update(p.rho, p.nel, seed=81, step=t) for t in range(1, 5)]
+    held = []
+    for t, rho in enumerate(rhos):
+        G.update_density(torch.tensor(rho, device="cuda"))
+        r = G.solve(f, rtol=1e-8)
+        torch.cuda.synchronize()
+        held.append(torch.cuda.memory_allocated())
+        F = Hierarchy(p.nel, rho, p.fixed, **opts)
+        rf = F.solve(f, rtol=1e-8)
+        assert r.converged and r.iters == rf.iters, f"update {t}"
+        assert torch.equal(r.u, rf.u), f"update {t}"
+        F.close()
+        del rf
+        torch.cuda.synchronize()
+        held[-1] = torch.cuda.memory_allocated()
+    print(f"  bytes held after each update: {held}", flush=True)
+    assert held[2] == held[1] and held[3] == held[2]
+    G.close()

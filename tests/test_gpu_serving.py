@@ -42,7 +42,8 @@ def test_mix_equals_alone(engine_opts, hybrid):
     print(f"mix equals alone {engine_opts} hybrid={hybrid}", flush=True)
     eng = GpuEngine(**engine_opts)
     reqs = _mix(hybrid=hybrid)
-    mix = Server(eng, hbm_budget=8 << 30, max_slots=4, chunk=3, rtol=1e-6, keep_solutions=True).run(reqs)
+    mix = Server(eng, hbm_budget=8 << 30, max_slots=4, chunk=3, rtol=1e-6, keep_solutions=True,
+                 workers=2).run(reqs)
     print("mix:", {k: v for k, v in mix.items() if k != "outcomes"}, flush=True)
     assert len(mix["outcomes"]) == len(reqs)
     for r in reqs:
