@@ -252,6 +252,22 @@ def cpu_baseline(cfg_name, args):
             "host": platform.processor() or platform.machine(), "host_cpus": os.cpu_count()}
 
 
+def served_requests(n: int, rate_per_s: float, n_designs: int = 20, seed: int = 5) -> list:
+    """The served stream: sizes drawn from {2D 128x64, 2D 512x256, 3D 48^3,
+    3D 96x48x48}, 1-4 load cases, smoothed seeded densities and a sequence of
+    seeded design updates, Poisson arrivals."""
+    import synth
+    from paper_2001_01655_amd.serving import Request
+    arrivals = synth.poisson_arrivals(n, rate_per_s, seed)
+    out = []
+    for rid in range(n):
+        p = synth.served_request(rid, seed)
+        dens = synth.design_sequence(p.rho, p.nel, seed + rid)
+        out.append(Request(rid, float(arrivals[rid]), p.nel, p.fixed, p.loads, dens, n_designs,
+                           material=dict(p=p.p, E0=p.E0, Emin=p.Emin, nu=p.nu)))
+    return out
+
+
 def served_leg(n_req: int, n_designs: int, smoother: str = "chebyshev", sweeps: int = 2, seed: int = 5,
                warm_steps: int = 4, hybrid_every: int = 8, fractions=(0.5, 0.7, 0.9)):
     """The served stream (mixed 2D/3D sizes, 1-4 load cases, design updates
@@ -266,8 +282,8 @@ def served_leg(n_req: int, n_designs: int, smoother: str = "chebyshev", sweeps: 
     import numpy as np
 
     import synth
-    from paper_2001_01655_amd.serving import GpuEngine, Server, served_requests
-    reqs = served_requests(n_req, rate_per_s=1.0, n_designs=n_designs, seed=seed, rtol=1e-6)
+    from paper_2001_01655_amd.serving import GpuEngine, Server
+    reqs = served_requests(n_req, rate_per_s=1.0, n_designs=n_designs, seed=seed)
     if hybrid_every > 0:
         for r in reqs:
             if r.rid % hybrid_every == hybrid_every - 1:

@@ -3,11 +3,14 @@
     python -m paper_2001_01655_amd.profile_summary stats  <kernel_stats.csv> <out.md> "<command>"
     python -m paper_2001_01655_amd.profile_summary traffic <fetch_counter_collection.csv> \
            <write_counter_collection.csv> <out_dir> "<command>" <smoother> <sweeps>
+    python -m paper_2001_01655_amd.profile_summary units <counter_collection.csv> <out.md> "<command>" "<title>"
 
 `stats` writes the per-kernel time table.  `traffic` turns FETCH_SIZE and
 WRITE_SIZE (KiB per dispatch) into HBM bytes per launch for the benchmark's
 kernel classes, scaling each counter by what it reads for the benchmark's
-256 MiB device-to-device copy (known bytes read and written).
+256 MiB device-to-device copy (known bytes read and written).  `units`
+tabulates any other counters (VALU and matrix-core activity, occupancy) as
+the mean per launch of each kernel class.
 """
 from __future__ import annotations
 
@@ -21,13 +24,17 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 COPY_BYTES = 256 << 20
 CLASSES = {
-    0: dict(match=["k_fine3<double, 3, false>"], source=["kernels_fine.hip", "tm_device.h"],
+    0: dict(match=["k_fine3<double, 3, false, 1>"], source=["kernels_fine.hip", "tm_device.h"],
             what="fine operator FP64 (q = K~p, outer loop)"),
-    1: dict(match=["k_fine3z2<float, 1>", "k_fine3z2<float, 2>", "k_fine3z2<float, 4>"],
+    1: dict(match=["k_fine3z2<float, 1, 1>", "k_fine3z2<float, 2, 1>", "k_fine3z2<float, 4, 1>"],
             source=["kernels_fine.hip", "tm_device.h"], what="fine operator FP32 (V-cycle smoothing / residual)"),
-    2: dict(match=["k_stencil_op<float, 3, 1, 4>", "k_stencil_op<float, 3, 2, 4>", "k_stencil_op<float, 3, 4, 4>"],
+    2: dict(match=["k_stencil_op<float, 3, 1, 4, 1>", "k_stencil_op<float, 3, 2, 4, 1>",
+                   "k_stencil_op<float, 3, 4, 4, 1>"],
             source=["kernels_coarse.hip", "tm_device.h"], what="level-1 stencil operator FP32 (V-cycle)",
             largest_grid=True),
+    3: dict(match=["k_fine3z2_mfma<1, 1>", "k_fine3z2_mfma<2, 1>", "k_fine3z2_mfma<4, 1>"],
+            source=["kernels_fine.hip", "tm_device.h"],
+            what="fine operator FP32 on the matrix cores (option fine_mfma)"),
 }
 
 
@@ -89,10 +96,34 @@ def traffic(fetch_csv: str, write_csv: str, out_dir: str, command: str, smoother
     open(os.path.join(out_dir, "traffic_cantilever3d.md"), "w").write("\n".join(summary) + "\n")
 
 
+def units(path: str, out: str, command: str, title: str) -> None:
+    rows = list(csv.DictReader(open(path)))
+    names = sorted({r["Counter_Name"] for r in rows})
+    lines = [f"# {title}", "", f"Command: `{command}`", "", "Mean per launch of each counter (rocprofv3 `--pmc`).",
+             "", "| class | kernel | launches | " + " | ".join(names) + " |",
+             "|---|---|---:|" + "---:|" * len(names)]
+    for c, spec in CLASSES.items():
+        sel = [r for r in rows if any(m in r["Kernel_Name"] for m in spec["match"])]
+        if spec.get("largest_grid") and sel:
+            g = max(int(r["Grid_Size"]) for r in sel)
+            sel = [r for r in sel if int(r["Grid_Size"]) == g]
+        if not sel:
+            continue
+        vals = collections.defaultdict(list)
+        for r in sel:
+            vals[r["Counter_Name"]].append(float(r["Counter_Value"]))
+        launches = max(len(v) for v in vals.values())
+        cells = [f"{sum(vals[n]) / len(vals[n]):.4g}" if vals[n] else "" for n in names]
+        lines.append(f"| {c} | {spec['what']} | {launches} | " + " | ".join(cells) + " |")
+    open(out, "w").write("\n".join(lines) + "\n")
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "stats":
         stats(sys.argv[2], sys.argv[3], sys.argv[4])
     elif sys.argv[1] == "traffic":
         traffic(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5], sys.argv[6], int(sys.argv[7]))
+    elif sys.argv[1] == "units":
+        units(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5])
     else:
         raise SystemExit(__doc__)

@@ -287,19 +287,3 @@ class GpuEngine:
 
     def release(self, H):
         H.close()
-
-
-def served_requests(n: int, rate_per_s: float, n_designs: int = 20, seed: int = 5,
-                    rtol: float = 1e-6) -> List[Request]:
-    """The served stream: sizes drawn from {2D 128x64, 2D 512x256, 3D 48^3,
-    3D 96x48x48}, 1-4 load cases, smoothed seeded densities and a sequence of
-    seeded design updates, Poisson arrivals."""
-    import synth
-    arrivals = synth.poisson_arrivals(n, rate_per_s, seed)
-    out = []
-    for rid in range(n):
-        p = synth.served_request(rid, seed)
-        dens = synth.design_sequence(p.rho, p.nel, seed + rid)
-        out.append(Request(rid, float(arrivals[rid]), p.nel, p.fixed, p.loads, dens, n_designs,
-                           material=dict(p=p.p, E0=p.E0, Emin=p.Emin, nu=p.nu)))
-    return out

@@ -91,6 +91,8 @@ GOLDEN_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 GOLDEN = {
     "mbb_random": (lambda: synth.mbb_2d(False), dict(n_levels=3, omega=0.6, nu_pre=2, nu_post=2)),
     "grid2d": (lambda: synth.get("grid2d"), dict(n_levels=5, max_iters=20000)),
+    "cantilever3d": (lambda: synth.get("cantilever3d"), dict(n_levels=6)),
+    "cantilever3d_cheb": (lambda: synth.get("cantilever3d"), dict(n_levels=6, **CHEB22)),
 }
 
 

@@ -58,8 +58,14 @@ def test_mix_equals_alone(engine_opts, hybrid):
 
 
 def test_served_stream_runs():
-    from paper_2001_01655_amd.serving import GpuEngine, Server, served_requests
-    reqs = served_requests(4, rate_per_s=50.0, n_designs=2)
+    from paper_2001_01655_amd.serving import GpuEngine, Request, Server
+    arrivals = synth.poisson_arrivals(4, 50.0, 5)
+    reqs = []
+    for rid in range(4):
+        p = synth.served_request(rid, 5)
+        reqs.append(Request(rid, float(arrivals[rid]), p.nel, p.fixed, p.loads,
+                            synth.design_sequence(p.rho, p.nel, 5 + rid), 2,
+                            material=dict(p=p.p, E0=p.E0, Emin=p.Emin, nu=p.nu)))
     out = Server(GpuEngine(), hbm_budget=16 << 30, max_slots=4, chunk=4, rtol=1e-6).run(reqs)
     assert len(out["outcomes"]) == 4
     for o in out["outcomes"]:
