@@ -391,7 +391,7 @@ def adaptive_leg(n_designs: int, nel=(128, 64, 64), seed: int = 4):
 
 def multi_rhs_leg(H, p, n_rhs: int = 6, reps: int = 3):
     """Six load cases of the workload's mesh solved together (x0 = 0, rtol 1e-8;
-    each right-hand side on a stream of its own) against the same six solved one
+    one launch per operation serves all six) against the same six solved one
     after another."""
     import torch
 

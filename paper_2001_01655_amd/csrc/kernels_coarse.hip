@@ -450,6 +450,149 @@ __global__ __launch_bounds__(WG) void k_stencil_op(const Pack<OpA<T>, NB> pk, in
     finish_node<T, DIM, OP>(node, N, acc, xo, 0, b, y, dinv, omega, dots, ch);
 }
 
+// The same operator for R right-hand sides of ONE hierarchy per thread (the
+// load cases of one solve): the stored stencil and the block inverse are read
+// once for all of them, the vectors per right-hand side.  Lanes R*blockIdx.y ..
+// +R-1 of the pack; a lane index at or past n_lanes repeats the last lane's
+// reads and stores nothing, a lane whose solve has stopped stores nothing.
+// Each lane's sums run in the order of k_stencil_op, so every right-hand side
+// gets bitwise the result of its own launch.
+template <typename T, int DIM, int OP, int G, int R>
+__global__ __launch_bounds__(WG) void k_stencil_opm(const Pack<OpA<T>, MAXB> pk, int n_lanes, int nx, int ny,
+                                                    int nz, int64_t N, T omega, double c1, double c2) {
+    const int l0 = (int)blockIdx.y * R;
+    const T* __restrict__ st = pk.a[l0].E;
+    const T* __restrict__ dinv = pk.a[l0].dinv;
+    // the lanes' pointers, copied out of the argument block once
+    const T* xs[R];
+    const T* bs[R];
+    T* ys[R];
+    const T* dis[R];
+    T* dos[R];
+    bool act[R];
+    bool any = false;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int lr = min(l0 + r, n_lanes - 1);
+        xs[r] = pk.a[lr].x;
+        bs[r] = pk.a[lr].b;
+        ys[r] = pk.a[lr].y;
+        dis[r] = pk.a[lr].din;
+        dos[r] = pk.a[lr].dout;
+        const int* dn = pk.a[lr].done;
+        act[r] = l0 + r < n_lanes && !(dn && *dn);
+        any = any || act[r];
+    }
+    if (!any) return;
+    const int64_t node = xcd_block() * WG + threadIdx.x;
+    if (node >= N) return;
+    constexpr int BB = DIM * DIM, NST = DIM == 3 ? 27 : 9, NU = (NST - 1) / 2;
+    constexpr int NQ = NU * BB + DIM * (DIM + 1) / 2;
+    const int NX = nx + 1, NY = ny + 1, NZ = nz + 1;
+    const int i = (int)(node % NX);
+    const int j = (int)((node / NX) % NY);
+    const int k = DIM == 3 ? (int)(node / ((int64_t)NX * NY)) : 0;
+    const auto sr = buf_rsrc(st, (int64_t)N * NQ * sizeof(T));
+    decltype(buf_rsrc(st, 0)) xr[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) xr[r] = buf_rsrc(xs[r], (int64_t)N * DIM * sizeof(T));
+    const uint32_t un = (uint32_t)node, uN = (uint32_t)N;
+    uint32_t ci[3], cj[3], ck[3];
+    bool ii[3], ij[3], ik[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        ci[d] = (uint32_t)min(max(i + d - 1, 0), NX - 1);
+        cj[d] = (uint32_t)min(max(j + d - 1, 0), NY - 1);
+        ck[d] = DIM == 3 ? (uint32_t)min(max(k + d - 1, 0), NZ - 1) : 0u;
+        ii[d] = i + d - 1 >= 0 && i + d - 1 < NX;
+        ij[d] = j + d - 1 >= 0 && j + d - 1 < NY;
+        ik[d] = DIM == 2 || (k + d - 1 >= 0 && k + d - 1 < NZ);
+    }
+    T acc[R][DIM] = {};
+    T xo[R][DIM];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) xo[r][c] = bld<T>(xr[r], (DIM * un + c) * (uint32_t)sizeof(T));
+    {
+        int q = NU * BB;
+#pragma unroll
+        for (int rr = 0; rr < DIM; ++rr)
+#pragma unroll
+            for (int c = rr; c < DIM; ++c, ++q) {
+                const T a = bld<T>(sr, ((uint32_t)q * uN + un) * (uint32_t)sizeof(T));
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    acc[r][rr] += a * xo[r][c];
+                    if (c != rr) acc[r][c] += a * xo[r][rr];
+                }
+            }
+    }
+#pragma unroll
+    for (int g0 = 0; g0 < NST; g0 += G) {
+        T xv[G][R][DIM], blk[G][BB];
+#pragma unroll
+        for (int gg = 0; gg < G; ++gg) {
+            if (g0 + gg >= NST) continue;
+            const int o = pair_order<NU>(g0 + gg);
+            if (o == NU) continue;
+            const int dx = o % 3, dy = (o / 3) % 3, dz = DIM == 3 ? o / 9 : 1;
+            const uint32_t J = (ck[dz] * (uint32_t)NY + cj[dy]) * (uint32_t)NX + ci[dx];
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int c = 0; c < DIM; ++c) xv[gg][r][c] = bld<T>(xr[r], (DIM * J + c) * (uint32_t)sizeof(T));
+            if (o > NU) {
+                const uint32_t q0 = (uint32_t)(o - NU - 1) * BB;
+#pragma unroll
+                for (int e = 0; e < BB; ++e) blk[gg][e] = bld<T>(sr, ((q0 + e) * uN + un) * (uint32_t)sizeof(T));
+            } else {
+                const uint32_t q0 = (uint32_t)(NST - 1 - o - NU - 1) * BB;
+#pragma unroll
+                for (int rr = 0; rr < DIM; ++rr)
+#pragma unroll
+                    for (int c = 0; c < DIM; ++c)
+                        blk[gg][rr * DIM + c] = bld<T>(sr, ((q0 + c * DIM + rr) * uN + J) * (uint32_t)sizeof(T));
+                const bool in = ii[dx] && ij[dy] && ik[dz];
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+#pragma unroll
+                    for (int c = 0; c < DIM; ++c) xv[gg][r][c] = in ? xv[gg][r][c] : T(0);
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int gg = 0; gg < G; ++gg) {
+            if (g0 + gg >= NST) continue;
+            const int o = pair_order<NU>(g0 + gg);
+            if (o == NU) continue;
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int rr = 0; rr < DIM; ++rr)
+#pragma unroll
+                    for (int c = 0; c < DIM; ++c) acc[r][rr] += blk[gg][rr * DIM + c] * xv[gg][r][c];
+        }
+    }
+    // pin the sums here: used only under the per-lane condition below, they
+    // would otherwise be sunk into it, past every group's scheduling barrier
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) asm volatile("" : "+v"(acc[r][c]));
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if (!act[r]) continue;
+        ChebArgs ch;
+        ch.din = dis[r];
+        ch.dout = dos[r];
+        ch.c1 = c1;
+        ch.c2 = c2;
+        double dots[2];
+        finish_node<T, DIM, OP>(node, N, acc[r], xo[r], 0, bs[r], ys[r], dinv, omega, dots, ch);
+    }
+}
+
 template <typename T>
 static const T* st_of(const Level& L);
 template <>
@@ -626,6 +769,43 @@ static void stencil_launch(int level, const LaneIO* L, int n, int op, T omega, d
 #undef TM_SO
 }
 
+// Several right-hand sides of one hierarchy on a large level: R per thread
+// (the operator read once for R of them), ceil(n / 4) groups of lanes.
+template <typename T, int DIM, int R>
+static void stencil_launch_shared(int level, const LaneIO* L, int n, int op, T omega, double c1, double c2,
+                                  hipStream_t s) {
+    const Level& V = L[0].h->lv[level];
+    const auto pk = stencil_pack<T, MAXB>(level, L, n);
+    const int nz = DIM == 3 ? V.nel[2] : 0;
+    const dim3 g(grid_for(V.n_nodes), (unsigned)ceil_div(n, R)), blk(WG);
+#define TM_SM(OPV)                                                                                   \
+    hipLaunchKernelGGL((k_stencil_opm<T, DIM, OPV, 4, R>), g, blk, 0, s, pk, n, V.nel[0], V.nel[1], nz,   \
+                       V.n_nodes, omega, c1, c2)
+    switch (op) {
+        case OP_APPLY: TM_SM(OP_APPLY); break;
+        case OP_RESID: TM_SM(OP_RESID); break;
+        case OP_CHEB: TM_SM(OP_CHEB); break;
+        default: TM_SM(OP_SMOOTH); break;
+    }
+#undef TM_SM
+}
+
+template <typename T, int DIM>
+static bool try_shared(int level, const LaneIO* L, int n, int op, T omega, double c1, double c2, hipStream_t s) {
+    const Level& V = L[0].h->lv[level];
+    const bool small = V.op_kernel == 0 ? grid_for(V.n_nodes) < 256 : V.op_kernel == 2;
+    if (n < 2 || small) return false;
+    for (int q = 1; q < n; ++q)
+        if (L[q].h != L[0].h) return false;
+    const int groups = (int)ceil_div(n, 4), R = (int)ceil_div(n, groups);
+    switch (R) {
+        case 2: stencil_launch_shared<T, DIM, 2>(level, L, n, op, omega, c1, c2, s); break;
+        case 3: stencil_launch_shared<T, DIM, 3>(level, L, n, op, omega, c1, c2, s); break;
+        default: stencil_launch_shared<T, DIM, 4>(level, L, n, op, omega, c1, c2, s); break;
+    }
+    return true;
+}
+
 template <typename T>
 void launch_stencil_op_b(int level, int op, const LaneIO* L, int n, T omega, double c1, double c2,
                          hipStream_t s) {
@@ -633,6 +813,9 @@ void launch_stencil_op_b(int level, int op, const LaneIO* L, int n, T omega, dou
     const int dim = L[0].h->lv[level].dim;
     for (int q0 = 0; q0 < n; q0 += MAXB) {
         const int m = std::min(MAXB, n - q0);
+        if (dim == 3 ? try_shared<T, 3>(level, L + q0, m, op, omega, c1, c2, s)
+                     : try_shared<T, 2>(level, L + q0, m, op, omega, c1, c2, s))
+            continue;
         if (dim == 3) {
             if (m == 1) stencil_launch<T, 3, 1>(level, L + q0, 1, op, omega, c1, c2, s);
             else stencil_launch<T, 3, MAXB>(level, L + q0, m, op, omega, c1, c2, s);

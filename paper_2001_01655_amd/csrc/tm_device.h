@@ -178,6 +178,9 @@ __device__ void store_dinv(double (&D)[BS][BS], int point, int64_t node, int64_t
         }
 }
 
+__device__ __forceinline__ float fma_of(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_of(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 // ------------------------------------------------------------ operator kernels
 // Operands of a node's finishing step, loaded apart from the arithmetic so
 // that latency-bound kernels can issue them together with their gathers.
@@ -241,7 +244,10 @@ __device__ __forceinline__ void finish_store(int64_t node, T (&kx)[BS], const T 
             T t = 0;
 #pragma unroll
             for (int c = 0; c < BS; ++c) t += f.dv[sym_at(r, c, BS)] * rr[c];
-            const T dn = c1 * f.din[r] + c2 * t;
+            // the fused multiply-add is written out: c1 din + c2 t has two
+            // contractions, and the compiler's pick differs between kernels,
+            // while every kernel that runs this step must round alike
+            const T dn = fma_of(t, c2, c1 * f.din[r]);
             if (dout) dout[BS * node + r] = dn;           // null: no later step reads it
             y[BS * node + r] = xo[r] + dn;
         }
