@@ -91,8 +91,12 @@ GOLDEN_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 GOLDEN = {
     "mbb_random": (lambda: synth.mbb_2d(False), dict(n_levels=3, omega=0.6, nu_pre=2, nu_post=2)),
     "grid2d": (lambda: synth.get("grid2d"), dict(n_levels=5, max_iters=20000)),
+    "cantilever2d": (lambda: synth.get("cantilever2d"), dict(n_levels=7, max_iters=20000)),
     "cantilever3d": (lambda: synth.get("cantilever3d"), dict(n_levels=6)),
     "cantilever3d_cheb": (lambda: synth.get("cantilever3d"), dict(n_levels=6, **CHEB22)),
+    # the bridge recipe at an eighth of its volume (the oracle's aggregation
+    # levels at full size do not fit in a workstation's memory)
+    "bridge3d_128x64x64": (lambda: synth.bridge_3d(nel=(128, 64, 64)), dict(n_geometric=3, max_coarse=1000)),
 }
 
 
@@ -111,7 +115,11 @@ def golden_errors(g, u, c):
 def test_full_size_vs_oracle(name):
     """FP32-V-cycle / FP64-FCG solve at rtol 1e-8 against the oracle's u at
     rtol 1e-12: relative error <= 1e-7 over 4096 seeded dofs and in ||u||,
-    and <= 1e-9 in the compliance."""
+    and <= 1e-9 in the compliance.  Where the oracle's true residual stays
+    above 1e-11 (the FP64 floor eps ||K|| ||u|| / ||f|| of a 1e9 stiffness
+    contrast: restarts no longer lower it), its compliance is itself only
+    known to about that residual, and the compliance bound is ten times the
+    reference's true relative residual."""
     from paper_2001_01655_amd import Hierarchy
     path = os.path.join(GOLDEN_DIR, f"solve_{name.replace('_cheb', '')}.json")
     with open(path) as fh:
@@ -130,4 +138,5 @@ def test_full_size_vs_oracle(name):
     u = res.u.cpu().numpy().reshape(-1)
     e_u, e_n, e_c = golden_errors(g, u, res.compliance[0])
     print(f"  iters={res.iters[0]} err_u(sampled)={e_u:.2e} err_norm={e_n:.2e} err_c={e_c:.2e}", flush=True)
-    assert e_u <= 1e-7 and e_n <= 1e-7 and e_c <= 1e-9
+    tol_c = max(1e-9, 10.0 * g["oracle"]["true_relres"])
+    assert e_u <= 1e-7 and e_n <= 1e-7 and e_c <= tol_c
