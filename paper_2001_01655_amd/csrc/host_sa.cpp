@@ -23,7 +23,7 @@ void sa_root_flags(int64_t n, const uint8_t* state, int32_t* flag, hipStream_t s
 void sa_agg_passes(const int32_t* srp, const int32_t* sci, int64_t n, const uint8_t* state, const int32_t* rid,
                    int32_t* agg1, int32_t* root1, int32_t* agg, int32_t* missing, hipStream_t s);
 void sa_members(int64_t n, int64_t ng, const int32_t* agg, int32_t* cnt_off, int32_t* cursor, int32_t* mem,
-                int64_t* work, hipStream_t s);
+                int32_t* umem, int64_t* work, hipStream_t s);
 void sa_tentative(int64_t ng, const int32_t* off, const int32_t* mem, const double* Bprev, int dim, int nx1,
                   int ny1, double h, int level, const int* nel0, int bs, int k, double* T, double* Bc, hipStream_t s);
 double sa_jacobi_bound(const BSR& A, int bs, const double* dinv, unsigned long long* work, hipStream_t s);
@@ -33,9 +33,9 @@ void sa_symbolic(const int32_t* rp1, const int32_t* ci1, const int32_t* agg, con
 void sa_row_of(const int32_t* rp, int64_t nrows, int32_t* rowof, hipStream_t s);
 void sa_p_numeric(const BSR& A, const int32_t* agg, const double* T, const double* dinv, int bs, int k,
                   double omega, const int32_t* prow, const BSR& P, hipStream_t s);
-void sa_transpose(const BSR& P, const int32_t* prow, BSR& PT, int32_t* cursor, int32_t* tsrc, int64_t* work,
-                  hipStream_t s);
-void sa_prod_numeric(const BSR& X, const BSR& Y, const int32_t* crow, BSR& C, hipStream_t s);
+void sa_transpose(const BSR& P, const int32_t* prow, BSR& PT, int32_t* cursor, int32_t* tsrc, int32_t* uci,
+                  int32_t* usrc, int64_t* work, hipStream_t s);
+void sa_prod_numeric(const BSR& X, const BSR& Y, const int32_t* crow, BSR& C, int32_t* dtmp, hipStream_t s);
 void sa_fix_diag(BSR& A, int bs, hipStream_t s);
 void sa_to_f32(const double* a, float* b, int64_t n, hipStream_t s);
 
@@ -176,7 +176,8 @@ void numeric_sa_levels(tm_hierarchy* h, hipStream_t s) {
             int32_t* off = tmp.get<int32_t>(n_agg + 1);
             int32_t* cursor = tmp.get<int32_t>(std::max<int64_t>(n_agg, n) + 1);
             int32_t* mem = tmp.get<int32_t>(n);
-            sa_members(n, n_agg, agg, off, cursor, mem, work, s);
+            int32_t* umem = tmp.get<int32_t>(n);
+            sa_members(n, n_agg, agg, off, cursor, mem, umem, work, s);
             double* T = tmp.get<double>((size_t)n * bs * k);
             // this step's candidates (the previous step's stay in the other arena)
             arena_reset(h->sa_cand[step & 1]);
@@ -205,18 +206,20 @@ void numeric_sa_levels(tm_hierarchy* h, hipStream_t s) {
             PT.ci = keep.get<int32_t>(P.nnzb);
             PT.v64 = keep.get<double>((size_t)P.nnzb * bs * k);
             int32_t* tsrc = tmp.get<int32_t>(P.nnzb);
-            sa_transpose(P, prow, PT, cursor, tsrc, work, s);
+            int32_t* uci = tmp.get<int32_t>(P.nnzb);
+            int32_t* usrc = tmp.get<int32_t>(P.nnzb);
+            sa_transpose(P, prow, PT, cursor, tsrc, uci, usrc, work, s);
             // A P, then A_c = P^T (A P)
             BSR AP;
             make_pattern(tmp, tmp, AP, n, n_agg, bs, k, F.A.rp, F.A.ci, nullptr, P.rp, P.ci, 1, work, s);
             int32_t* aprow = tmp.get<int32_t>(AP.nnzb);
             sa_row_of(AP.rp, n, aprow, s);
-            sa_prod_numeric(F.A, P, aprow, AP, s);
+            sa_prod_numeric(F.A, P, aprow, AP, counter, s);
             BSR Ac;
             make_pattern(keep, tmp, Ac, n_agg, n_agg, k, k, PT.rp, PT.ci, nullptr, AP.rp, AP.ci, 2, work, s);
             int32_t* acrow = tmp.get<int32_t>(Ac.nnzb);
             sa_row_of(Ac.rp, n_agg, acrow, s);
-            sa_prod_numeric(PT, AP, acrow, Ac, s);
+            sa_prod_numeric(PT, AP, acrow, Ac, counter, s);
             sa_fix_diag(Ac, k, s);
             // FP32 copies for the V-cycle
             P.v32 = keep.get<float>((size_t)P.nnzb * bs * k);

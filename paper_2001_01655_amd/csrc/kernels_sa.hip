@@ -3,7 +3,10 @@
 // tentative prolongator smoothed by one weighted-Jacobi step, rigid-body
 // modes as candidates).  Every result is independent of thread scheduling:
 // integer decisions are order-free (min / max / set), and every floating-point
-// sum runs over its terms in ascending index order.
+// sum runs over its terms in ascending index order.  Rows, aggregates and
+// product blocks with long loops take one wave each (64-thread workgroups):
+// the lanes compute the terms side by side, and the sums still run in
+// ascending order (one lane per output entry, or every lane redundantly).
 //
 //  strength      I != J strong iff f_IJ^2 > beta^2 f_II f_JJ, f = squared
 //                Frobenius norm of the block; symmetrised (either direction).
@@ -174,22 +177,26 @@ __device__ __forceinline__ bool strong_pair(const int32_t* rp, const int32_t* ci
     return false;
 }
 
+// one wave per row: lane l tests entry q0 + l; the strong entries keep their
+// order (ballot prefix counts)
 template <bool FILL>
-__global__ void k_strength(const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
-                           const double* __restrict__ v, const double* __restrict__ dn, int64_t n, int bs,
-                           double beta2, int32_t* __restrict__ cnt, const int32_t* __restrict__ srp,
-                           int32_t* __restrict__ sci) {
-    const int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(64) void k_strength(const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                                                 const double* __restrict__ v, const double* __restrict__ dn,
+                                                 int64_t n, int bs, double beta2, int32_t* __restrict__ cnt,
+                                                 const int32_t* __restrict__ srp, int32_t* __restrict__ sci) {
+    const int64_t I = blockIdx.x;
+    const int lane = threadIdx.x;
     if (I >= n) return;
+    const int32_t q0 = rp[I], q1 = rp[I + 1];
     int32_t c = 0;
-    for (int32_t q = rp[I]; q < rp[I + 1]; ++q) {
-        if (ci[q] == (int32_t)I) continue;
-        if (strong_pair(rp, ci, v, dn, bs, beta2, I, q)) {
-            if (FILL) sci[srp[I] + c] = ci[q];
-            ++c;
-        }
+    for (int32_t qb = q0; qb < q1; qb += 64) {
+        const int32_t q = qb + lane;
+        const bool st = q < q1 && ci[q] != (int32_t)I && strong_pair(rp, ci, v, dn, bs, beta2, I, q);
+        const uint64_t m = __ballot(st);
+        if (FILL && st) sci[srp[I] + c + __popcll(m & ((1ull << lane) - 1ull))] = ci[q];
+        c += __popcll(m);
     }
-    if (!FILL) cnt[I] = c;
+    if (!FILL && lane == 0) cnt[I] = c;
 }
 
 // ------------------------------------------------------------------ aggregation
@@ -308,18 +315,22 @@ __global__ void k_place_members(int64_t n, const int32_t* __restrict__ agg, cons
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) mem[off[agg[i]] + atomicAdd(&cursor[agg[i]], 1)] = (int32_t)i;
 }
-// insertion sort of each segment [off[g], off[g+1])
-__global__ void k_sort_segments(int64_t ng, const int32_t* __restrict__ off, int32_t* __restrict__ a) {
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// segment [off[g], off[g+1]) of `in` (distinct keys) into `out` in ascending
+// order, one wave per segment: each key goes to its rank (the number of
+// smaller keys in the segment); optional payload moves with its key
+__global__ __launch_bounds__(64) void k_rank_segments(int64_t ng, const int32_t* __restrict__ off,
+                                                      const int32_t* __restrict__ in,
+                                                      const int32_t* __restrict__ pin, int32_t* __restrict__ out,
+                                                      int32_t* __restrict__ pout) {
+    const int64_t g = blockIdx.x;
     if (g >= ng) return;
-    for (int32_t p = off[g] + 1; p < off[g + 1]; ++p) {
-        const int32_t v = a[p];
-        int32_t q = p - 1;
-        while (q >= off[g] && a[q] > v) {
-            a[q + 1] = a[q];
-            --q;
-        }
-        a[q + 1] = v;
+    const int32_t p0 = off[g], p1 = off[g + 1];
+    for (int32_t p = p0 + (int32_t)threadIdx.x; p < p1; p += 64) {
+        const int32_t key = in[p];
+        int32_t rank = 0;
+        for (int32_t q = p0; q < p1; ++q) rank += in[q] < key;
+        out[p0 + rank] = key;
+        if (pin) pout[p0 + rank] = pin[p];
     }
 }
 
@@ -348,82 +359,126 @@ __device__ __forceinline__ double cand(const double* __restrict__ Bprev, int dim
     return r == 0 ? -y : (r == 1 ? x : 0.0);               // (-y, x, 0)
 }
 
-// thread per aggregate: modified Gram-Schmidt on its member rows (in place in T)
-__global__ void k_tentative(int64_t ng, const int32_t* __restrict__ off, const int32_t* __restrict__ mem,
-                            const double* __restrict__ Bprev, int dim, int nx1, int ny1, const LevelPos lp, int bs,
-                            int k, double* __restrict__ T, double* __restrict__ Bc) {
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= ng) return;
-    const int32_t p0 = off[g], p1 = off[g + 1];
-    // T rows of member m: T[(mem * bs + r) * k + c]
-    for (int32_t p = p0; p < p1; ++p) {
-        const int64_t i = mem[p];
-        for (int r = 0; r < bs; ++r)
-            for (int c = 0; c < k; ++c) T[((int64_t)i * bs + r) * k + c] = cand(Bprev, dim, nx1, ny1, lp, bs, k, i, r, c);
-    }
-    double R[6][6];
-    for (int a = 0; a < 6; ++a)
-        for (int b = 0; b < 6; ++b) R[a][b] = 0.0;
+// one wave per aggregate: modified Gram-Schmidt on its member rows.  The rows
+// (members ascending, then the block's rows) sit in LDS when they fit, else
+// they are worked on in T itself; element-wise steps run across the lanes,
+// every norm and dot product is summed over the rows in ascending order (by
+// every lane alike, so all lanes hold the same value).
+constexpr int TENT_LDS = 4096;    // doubles: rows x k of one aggregate
+
+template <bool SH>
+__device__ __forceinline__ void mgs_rows(double* __restrict__ W, const int32_t* __restrict__ mem, int32_t p0,
+                                         int nrow, int bs, int k, double (&R)[6][6]) {
+    // row t of the aggregate: member p0 + t / bs, block row t % bs
+    auto at = [&](int t, int c) -> double& {
+        if (SH) return W[t * k + c];
+        return W[((int64_t)mem[p0 + t / bs] * bs + t % bs) * k + c];
+    };
     for (int j = 0; j < k; ++j) {
         double n0 = 0.0;
-        for (int32_t p = p0; p < p1; ++p)
-            for (int r = 0; r < bs; ++r) {
-                const double v = T[((int64_t)mem[p] * bs + r) * k + j];
-                n0 += v * v;
-            }
+        for (int t = 0; t < nrow; ++t) {
+            const double v = at(t, j);
+            n0 += v * v;
+        }
         n0 = sqrt(n0);
         for (int i = 0; i < j; ++i) {
             double d = 0.0;
-            for (int32_t p = p0; p < p1; ++p)
-                for (int r = 0; r < bs; ++r) {
-                    const int64_t row = (int64_t)mem[p] * bs + r;
-                    d += T[row * k + i] * T[row * k + j];
-                }
+            for (int t = 0; t < nrow; ++t) d += at(t, i) * at(t, j);
             R[i][j] = d;
-            for (int32_t p = p0; p < p1; ++p)
-                for (int r = 0; r < bs; ++r) {
-                    const int64_t row = (int64_t)mem[p] * bs + r;
-                    T[row * k + j] -= d * T[row * k + i];
-                }
+            __syncthreads();
+            for (int t = (int)threadIdx.x; t < nrow; t += 64) at(t, j) -= d * at(t, i);
+            __syncthreads();
         }
         double nr = 0.0;
-        for (int32_t p = p0; p < p1; ++p)
-            for (int r = 0; r < bs; ++r) {
-                const double v = T[((int64_t)mem[p] * bs + r) * k + j];
-                nr += v * v;
-            }
+        for (int t = 0; t < nrow; ++t) {
+            const double v = at(t, j);
+            nr += v * v;
+        }
         nr = sqrt(nr);
         const bool dead = n0 == 0.0 || nr <= 1e-10 * n0;
         R[j][j] = dead ? 0.0 : nr;
-        for (int32_t p = p0; p < p1; ++p)
-            for (int r = 0; r < bs; ++r) {
-                double& t = T[((int64_t)mem[p] * bs + r) * k + j];
-                t = dead ? 0.0 : t / nr;
-            }
+        __syncthreads();
+        for (int t = (int)threadIdx.x; t < nrow; t += 64) {
+            double& x = at(t, j);
+            x = dead ? 0.0 : x / nr;
+        }
+        __syncthreads();
     }
-    for (int a = 0; a < k; ++a)
-        for (int b = 0; b < k; ++b) Bc[((int64_t)g * k + a) * k + b] = R[a][b];
+}
+
+__global__ __launch_bounds__(64) void k_tentative(int64_t ng, const int32_t* __restrict__ off,
+                                                  const int32_t* __restrict__ mem, const double* __restrict__ Bprev,
+                                                  int dim, int nx1, int ny1, const LevelPos lp, int bs, int k,
+                                                  double* __restrict__ T, double* __restrict__ Bc) {
+    __shared__ double W[TENT_LDS];
+    const int64_t g = blockIdx.x;
+    if (g >= ng) return;
+    const int32_t p0 = off[g], p1 = off[g + 1];
+    const int nrow = (p1 - p0) * bs;
+    const bool sh = nrow * k <= TENT_LDS;
+    for (int t = (int)threadIdx.x; t < nrow; t += 64) {
+        const int64_t i = mem[p0 + t / bs];
+        const int r = t % bs;
+        for (int c = 0; c < k; ++c) {
+            const double v = cand(Bprev, dim, nx1, ny1, lp, bs, k, i, r, c);
+            if (sh) W[t * k + c] = v;
+            else T[((int64_t)i * bs + r) * k + c] = v;
+        }
+    }
+    __syncthreads();
+    double R[6][6];
+    for (int a = 0; a < 6; ++a)
+        for (int b = 0; b < 6; ++b) R[a][b] = 0.0;
+    if (sh)
+        mgs_rows<true>(W, mem, p0, nrow, bs, k, R);
+    else
+        mgs_rows<false>(T, mem, p0, nrow, bs, k, R);
+    if (sh)
+        for (int t = (int)threadIdx.x; t < nrow; t += 64) {
+            const int64_t i = mem[p0 + t / bs];
+            const int r = t % bs;
+            for (int c = 0; c < k; ++c) T[((int64_t)i * bs + r) * k + c] = W[t * k + c];
+        }
+    if (threadIdx.x == 0)
+        for (int a = 0; a < k; ++a)
+            for (int b = 0; b < k; ++b) Bc[((int64_t)g * k + a) * k + b] = R[a][b];
 }
 
 // ------------------------------------------------------------------ ||D^-1 A||_inf
-__global__ void k_dinv_a_rowmax(const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
-                                const double* __restrict__ v, const double* __restrict__ dinv, int64_t n, int bs,
-                                unsigned long long* __restrict__ out) {
-    const int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// one wave per row: lane l forms |(D^-1 A)_{rc}| for block q0 + l, then lane r
+// adds its row's terms block by block, column by column (ascending order)
+__global__ __launch_bounds__(64) void k_dinv_a_rowmax(const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                                                      const double* __restrict__ v, const double* __restrict__ dinv,
+                                                      int64_t n, int bs, unsigned long long* __restrict__ out) {
+    __shared__ double u[64][36];
+    const int64_t I = blockIdx.x;
     if (I >= n) return;
-    double best = 0.0;
-    for (int r = 0; r < bs; ++r) {
-        double s = 0.0;
-        for (int32_t q = rp[I]; q < rp[I + 1]; ++q)
-            for (int c = 0; c < bs; ++c) {
-                double t = 0.0;
-                for (int m = 0; m < bs; ++m)
-                    t += dinv[(int64_t)sym_at(r, m, bs) * n + I] * v[((int64_t)q * bs + m) * bs + c];
-                s += fabs(t);
-            }
-        best = fmax(best, s);
+    const int lane = threadIdx.x;
+    const int32_t q0 = rp[I], q1 = rp[I + 1];
+    double s = 0.0;
+    for (int32_t qb = q0; qb < q1; qb += 64) {
+        const int32_t q = qb + lane;
+        if (q < q1)
+            for (int r = 0; r < bs; ++r)
+                for (int c = 0; c < bs; ++c) {
+                    double t = 0.0;
+                    for (int m = 0; m < bs; ++m)
+                        t += dinv[(int64_t)sym_at(r, m, bs) * n + I] * v[((int64_t)q * bs + m) * bs + c];
+                    u[lane][r * bs + c] = fabs(t);
+                }
+        __syncthreads();
+        if (lane < bs) {
+            const int cnt = min(64, q1 - qb);
+            for (int l = 0; l < cnt; ++l)
+                for (int c = 0; c < bs; ++c) s += u[l][lane * bs + c];
+        }
+        __syncthreads();
     }
-    atomicMax(out, (unsigned long long)__double_as_longlong(best));   // non-negative: bit order = value order
+    // the largest row sum of this block row
+    double best = lane < bs ? s : 0.0;
+    for (int o = 32; o > 0; o >>= 1) best = fmax(best, __shfl_xor(best, o));
+    if (lane == 0)
+        atomicMax(out, (unsigned long long)__double_as_longlong(best));   // non-negative: bit order = value order
 }
 
 // ------------------------------------------------------------------ sparse products
@@ -502,43 +557,90 @@ __global__ void k_row_of(const int32_t* __restrict__ rp, int64_t nrows, int32_t*
     for (int32_t q = rp[r]; q < rp[r + 1]; ++q) rowof[q] = (int32_t)r;
 }
 
-// numeric P: block (I, g) = [g == agg[I]] T_I - omega Dinv_I sum_{J in row I, agg[J] = g} A_IJ T_J
-__global__ void k_p_numeric(const int32_t* __restrict__ arp, const int32_t* __restrict__ aci,
-                            const double* __restrict__ av, const int32_t* __restrict__ agg,
-                            const double* __restrict__ T, const double* __restrict__ dinv, int64_t n, int bs, int k,
-                            double omega, const int32_t* __restrict__ prow, const int32_t* __restrict__ pci,
-                            int64_t nnzb, double* __restrict__ pv) {
-    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= nnzb) return;
-    const int64_t I = prow[b];
-    const int32_t g = pci[b];
-    double acc[6][6], out[6][6];
-    for (int r = 0; r < bs; ++r)
-        for (int c = 0; c < k; ++c) acc[r][c] = 0.0;
-    for (int32_t q = arp[I]; q < arp[I + 1]; ++q) {
-        const int32_t J = aci[q];
-        if (agg[J] != g) continue;
-        const double* A = av + (int64_t)q * bs * bs;
-        const double* TJ = T + (int64_t)J * bs * k;
-        for (int r = 0; r < bs; ++r)
-            for (int c = 0; c < k; ++c) {
-                double t = 0.0;
-                for (int m = 0; m < bs; ++m) t += A[r * bs + m] * TJ[m * k + c];
-                acc[r][c] += t;
-            }
-    }
-    const double* TI = T + I * bs * k;
-    for (int r = 0; r < bs; ++r)
-        for (int c = 0; c < k; ++c) {
-            double t = 0.0;
-            for (int m = 0; m < bs; ++m) t += dinv[(int64_t)sym_at(r, m, bs) * n + I] * acc[m][c];
-            out[r][c] = (g == agg[I] ? TI[r * k + c] : 0.0) - omega * t;
+// t = X Y for an XR x XC block X and an XC x YC block Y (row-major), each
+// entry summed over m in ascending order
+template <int XR, int XC, int YC>
+__device__ __forceinline__ void block_mul(const double* __restrict__ X, const double* __restrict__ Y,
+                                          double (&t)[XR * YC]) {
+    double x[XR * XC], y[XC * YC];
+#pragma unroll
+    for (int e = 0; e < XR * XC; ++e) x[e] = X[e];
+#pragma unroll
+    for (int e = 0; e < XC * YC; ++e) y[e] = Y[e];
+#pragma unroll
+    for (int r = 0; r < XR; ++r)
+#pragma unroll
+        for (int c = 0; c < YC; ++c) {
+            double a = 0.0;
+#pragma unroll
+            for (int m = 0; m < XC; ++m) a += x[r * XC + m] * y[m * YC + c];
+            t[r * YC + c] = a;
         }
-    for (int r = 0; r < bs; ++r)
-        for (int c = 0; c < k; ++c) pv[(b * bs + r) * k + c] = out[r][c];
 }
 
-// transpose of a BSR (br x bc blocks): counts, then placement, then per-row sort
+// numeric P: block (I, g) = [g == agg[I]] T_I - omega Dinv_I sum_{J in row I, agg[J] = g} A_IJ T_J
+// One wave per row I: lane l forms A_IJ T_J for entry q0 + l of A's row, lane
+// (block, r, c) adds the terms of its aggregate in ascending entry order and
+// then finishes its entry.  BS x BS blocks of A, BS x K of T.
+constexpr int PN_SLOTS = 64;     // blocks of one P row held in LDS
+
+template <int BS, int K>
+__global__ __launch_bounds__(64) void k_p_numeric(const int32_t* __restrict__ arp, const int32_t* __restrict__ aci,
+                                                  const double* __restrict__ av, const int32_t* __restrict__ agg,
+                                                  const double* __restrict__ T, const double* __restrict__ dinv,
+                                                  int64_t n, double omega, const int32_t* __restrict__ prp,
+                                                  const int32_t* __restrict__ pci, double* __restrict__ pv) {
+    constexpr int NE = BS * K;
+    __shared__ double u[64][NE];
+    __shared__ int32_t gq[64];
+    __shared__ double sums[PN_SLOTS][NE];
+    const int64_t I = blockIdx.x;
+    if (I >= n) return;
+    const int lane = threadIdx.x;
+    const int32_t b0 = prp[I], nb = prp[I + 1] - b0;
+    const int32_t q0 = arp[I], q1 = arp[I + 1];
+    const double* TI = T + I * NE;
+    const int32_t gI = agg[I];
+    // blocks of the row in groups of PN_SLOTS (a row has a handful)
+    for (int32_t s0 = 0; s0 < nb; s0 += PN_SLOTS) {
+        const int ns = min(PN_SLOTS, nb - s0);
+        for (int t = lane; t < ns * NE; t += 64) sums[t / NE][t % NE] = 0.0;
+        for (int32_t qb = q0; qb < q1; qb += 64) {
+            const int32_t q = qb + lane;
+            if (q < q1) {
+                const int32_t J = aci[q];
+                gq[lane] = agg[J];
+                double t[NE];
+                block_mul<BS, BS, K>(av + (int64_t)q * BS * BS, T + (int64_t)J * NE, t);
+#pragma unroll
+                for (int e = 0; e < NE; ++e) u[lane][e] = t[e];
+            }
+            __syncthreads();
+            const int cnt = min(64, q1 - qb);
+            for (int t = lane; t < ns * NE; t += 64) {
+                const int sl = t / NE, e = t % NE;
+                const int32_t g = pci[b0 + s0 + sl];
+                double a = sums[sl][e];
+                for (int l = 0; l < cnt; ++l)
+                    if (gq[l] == g) a += u[l][e];
+                sums[sl][e] = a;
+            }
+            __syncthreads();
+        }
+        for (int t = lane; t < ns * NE; t += 64) {
+            const int sl = t / NE, e = t % NE, r = e / K, c = e % K;
+            const int32_t g = pci[b0 + s0 + sl];
+            double a = 0.0;
+#pragma unroll
+            for (int mm = 0; mm < BS; ++mm) a += dinv[(int64_t)sym_at(r, mm, BS) * n + I] * sums[sl][mm * K + c];
+            pv[(int64_t)(b0 + s0 + sl) * NE + e] = (g == gI ? TI[e] : 0.0) - omega * a;
+        }
+        __syncthreads();
+    }
+}
+
+// transpose of a BSR (br x bc blocks): counts, then placement, then each row
+// in ascending column order (rank of each key)
 __global__ void k_tr_count(int64_t nnzb, const int32_t* __restrict__ ci, int32_t* __restrict__ cnt) {
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q < nnzb) atomicAdd(&cnt[ci[q]], 1);
@@ -553,23 +655,6 @@ __global__ void k_tr_place(int64_t nnzb, const int32_t* __restrict__ rowof, cons
     tci[p] = rowof[q];
     tsrc[p] = (int32_t)q;
 }
-// sort each transposed row by column (source row index); keys are unique per row
-__global__ void k_tr_sort(int64_t nr, const int32_t* __restrict__ trp, int32_t* __restrict__ tci,
-                          int32_t* __restrict__ tsrc) {
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= nr) return;
-    for (int32_t p = trp[r] + 1; p < trp[r + 1]; ++p) {
-        const int32_t kc = tci[p], ks = tsrc[p];
-        int32_t q = p - 1;
-        while (q >= trp[r] && tci[q] > kc) {
-            tci[q + 1] = tci[q];
-            tsrc[q + 1] = tsrc[q];
-            --q;
-        }
-        tci[q + 1] = kc;
-        tsrc[q + 1] = ks;
-    }
-}
 __global__ void k_tr_values(int64_t nnzb, const int32_t* __restrict__ tsrc, const double* __restrict__ v, int br,
                             int bc, double* __restrict__ tv) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -581,33 +666,91 @@ __global__ void k_tr_values(int64_t nnzb, const int32_t* __restrict__ tsrc, cons
 
 // numeric C = X Y for one output block (row R, col H):
 //   sum_{q in row R of X (ascending)} X_q Y_{ci_x[q], H}  (Y row searched for H)
-// X blocks are xr x xc, Y blocks xc x yc.
-__global__ void k_prod_numeric(const int32_t* __restrict__ xrp, const int32_t* __restrict__ xci,
-                               const double* __restrict__ xv, int xr, int xc, const int32_t* __restrict__ yrp,
-                               const int32_t* __restrict__ yci, const double* __restrict__ yv, int yc,
-                               const int32_t* __restrict__ crow, const int32_t* __restrict__ cci, int64_t nnzb,
-                               double* __restrict__ cv) {
-    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= nnzb) return;
-    const int32_t R = crow[b], H = cci[b];
-    double acc[6][6];
-    for (int r = 0; r < xr; ++r)
-        for (int c = 0; c < yc; ++c) acc[r][c] = 0.0;
-    for (int32_t q = xrp[R]; q < xrp[R + 1]; ++q) {
-        const int32_t J = xci[q];
-        const int32_t p = find_col(yci, yrp[J], yrp[J + 1], H);
-        if (p >= yrp[J + 1] || yci[p] != H) continue;
-        const double* X = xv + (int64_t)q * xr * xc;
-        const double* Y = yv + (int64_t)p * xc * yc;
-        for (int r = 0; r < xr; ++r)
-            for (int c = 0; c < yc; ++c) {
-                double t = 0.0;
-                for (int m = 0; m < xc; ++m) t += X[r * xc + m] * Y[m * yc + c];
-                acc[r][c] += t;
+// X blocks are XR x XC, Y blocks XC x YC (compile-time shapes, so a lane holds
+// its two blocks in registers).  One output row per wave (row-by-row
+// product): the row's sums sit in LDS (stride NE + 1 against bank
+// conflicts); the entries q of X's row are taken in ascending order, and for
+// each the lanes take the blocks p of Y's row ci_x[q] (distinct columns, so
+// distinct sums): every block adds its terms in ascending q.  A row longer
+// than the LDS the launch sized is done block by block, with the same order.
+template <int XR, int XC, int YC>
+__global__ __launch_bounds__(64) void k_prod_rows(const int32_t* __restrict__ xrp, const int32_t* __restrict__ xci,
+                                                  const double* __restrict__ xv, const int32_t* __restrict__ yrp,
+                                                  const int32_t* __restrict__ yci, const double* __restrict__ yv,
+                                                  const int32_t* __restrict__ crp, const int32_t* __restrict__ cci,
+                                                  int64_t nrows, int mcap, double* __restrict__ cv) {
+    constexpr int NE = XR * YC, NS = NE + 1;
+    extern __shared__ double lds[];
+    const int64_t R = blockIdx.x;
+    if (R >= nrows) return;
+    const int lane = threadIdx.x;
+    const int32_t c0 = crp[R], c1 = crp[R + 1];
+    const int m = c1 - c0;
+    const int32_t q0 = xrp[R], q1 = xrp[R + 1];
+    if (m > mcap) {
+        // block by block: lane l forms the term of entry q0 + l, lane e adds
+        double* u = lds;                                   // [64][NE]
+        int* hit = reinterpret_cast<int*>(lds + 64 * NE);  // [64]
+        for (int32_t b = c0; b < c1; ++b) {
+            const int32_t H = cci[b];
+            double acc = 0.0;
+            for (int32_t qb = q0; qb < q1; qb += 64) {
+                const int32_t q = qb + lane;
+                bool h = false;
+                if (q < q1) {
+                    const int32_t J = xci[q];
+                    const int32_t p = find_col(yci, yrp[J], yrp[J + 1], H);
+                    h = p < yrp[J + 1] && yci[p] == H;
+                    if (h) {
+                        double t[NE];
+                        block_mul<XR, XC, YC>(xv + (int64_t)q * XR * XC, yv + (int64_t)p * XC * YC, t);
+#pragma unroll
+                        for (int e = 0; e < NE; ++e) u[lane * NE + e] = t[e];
+                    }
+                }
+                hit[lane] = h;
+                __syncthreads();
+                if (lane < NE) {
+                    const int cnt = min(64, q1 - qb);
+                    for (int l = 0; l < cnt; ++l)
+                        if (hit[l]) acc += u[l * NE + lane];
+                }
+                __syncthreads();
             }
+            if (lane < NE) cv[(int64_t)b * NE + lane] = acc;
+        }
+        return;
     }
-    for (int r = 0; r < xr; ++r)
-        for (int c = 0; c < yc; ++c) cv[(b * xr + r) * yc + c] = acc[r][c];
+    double* acc = lds;                                         // [m][NS]
+    int32_t* cols = reinterpret_cast<int32_t*>(lds + (size_t)mcap * NS);
+    for (int t = lane; t < m * NS; t += 64) acc[t] = 0.0;
+    for (int t = lane; t < m; t += 64) cols[t] = cci[c0 + t];
+    __syncthreads();
+    for (int32_t qb = q0; qb < q1; qb += 64) {
+        int32_t pa = 0, pb = 0;
+        if (qb + lane < q1) {
+            const int32_t J = xci[qb + lane];
+            pa = yrp[J];
+            pb = yrp[J + 1];
+        }
+        const int cnt = min(64, q1 - qb);
+        for (int l = 0; l < cnt; ++l) {
+            const int32_t a0 = __shfl(pa, l), a1 = __shfl(pb, l);
+            const double* X = xv + (int64_t)(qb + l) * XR * XC;
+            for (int32_t p = a0 + lane; p < a1; p += 64) {
+                const int32_t H = yci[p];
+                double t[NE];
+                block_mul<XR, XC, YC>(X, yv + (int64_t)p * XC * YC, t);
+                const int sl = find_col(cols, 0, m, H);
+                if (sl < m && cols[sl] == H) {
+#pragma unroll
+                    for (int e = 0; e < NE; ++e) acc[sl * NS + e] += t[e];
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int t = lane; t < m * NE; t += 64) cv[(int64_t)c0 * NE + t] = acc[(t / NE) * NS + t % NE];
 }
 
 // exactly-zero diagonal entries of a square BSR become 1
@@ -636,10 +779,10 @@ void sa_launch_strength(const BSR& A, int bs, const double* dn, double beta, int
                         const int32_t* srp, int32_t* sci, bool fill, hipStream_t s) {
     const double b2 = beta * beta;
     if (fill)
-        hipLaunchKernelGGL(k_strength<true>, dim3(grid_for(A.nbr)), dim3(WG), 0, s, A.rp, A.ci, A.v64, dn,
+        hipLaunchKernelGGL(k_strength<true>, dim3((unsigned)A.nbr), dim3(64), 0, s, A.rp, A.ci, A.v64, dn,
                            A.nbr, bs, b2, cnt, srp, sci);
     else
-        hipLaunchKernelGGL(k_strength<false>, dim3(grid_for(A.nbr)), dim3(WG), 0, s, A.rp, A.ci, A.v64, dn,
+        hipLaunchKernelGGL(k_strength<false>, dim3((unsigned)A.nbr), dim3(64), 0, s, A.rp, A.ci, A.v64, dn,
                            A.nbr, bs, b2, cnt, srp, sci);
 }
 int sa_mis2(const int32_t* srp, const int32_t* sci, int64_t n, uint8_t* state, uint64_t* m1, uint64_t* m2,
@@ -672,24 +815,25 @@ void sa_agg_passes(const int32_t* srp, const int32_t* sci, int64_t n, const uint
                        missing);
 }
 void sa_members(int64_t n, int64_t ng, const int32_t* agg, int32_t* cnt_off, int32_t* cursor, int32_t* mem,
-                int64_t* work, hipStream_t s) {
+                int32_t* umem, int64_t* work, hipStream_t s) {
     TM_HIP(hipMemsetAsync(cnt_off, 0, sizeof(int32_t) * (ng + 1), s));
     TM_HIP(hipMemsetAsync(cursor, 0, sizeof(int32_t) * ng, s));
     hipLaunchKernelGGL(k_count_members, dim3(grid_for(n)), dim3(WG), 0, s, n, agg, cnt_off);
     scan_exclusive(cnt_off, cnt_off, ng, work, s);
     hipLaunchKernelGGL(k_place_members, dim3(grid_for(n)), dim3(WG), 0, s, n, agg, (const int32_t*)cnt_off,
-                       cursor, mem);
-    hipLaunchKernelGGL(k_sort_segments, dim3(grid_for(ng)), dim3(WG), 0, s, ng, (const int32_t*)cnt_off, mem);
+                       cursor, umem);
+    hipLaunchKernelGGL(k_rank_segments, dim3((unsigned)ng), dim3(64), 0, s, ng, (const int32_t*)cnt_off,
+                       (const int32_t*)umem, (const int32_t*)nullptr, mem, (int32_t*)nullptr);
 }
 void sa_tentative(int64_t ng, const int32_t* off, const int32_t* mem, const double* Bprev, int dim, int nx1,
                   int ny1, double h, int level, const int* nel0, int bs, int k, double* T, double* Bc, hipStream_t s) {
     LevelPos lp{h, 1 << level, {nel0[0], nel0[1], dim == 3 ? nel0[2] : 0}};
-    hipLaunchKernelGGL(k_tentative, dim3(grid_for(ng, 64)), dim3(64), 0, s, ng, off, mem, Bprev, dim, nx1, ny1,
+    hipLaunchKernelGGL(k_tentative, dim3((unsigned)ng), dim3(64), 0, s, ng, off, mem, Bprev, dim, nx1, ny1,
                        lp, bs, k, T, Bc);
 }
 double sa_jacobi_bound(const BSR& A, int bs, const double* dinv, unsigned long long* work, hipStream_t s) {
     TM_HIP(hipMemsetAsync(work, 0, sizeof(unsigned long long), s));
-    hipLaunchKernelGGL(k_dinv_a_rowmax, dim3(grid_for(A.nbr)), dim3(WG), 0, s, A.rp, A.ci, A.v64, dinv, A.nbr,
+    hipLaunchKernelGGL(k_dinv_a_rowmax, dim3((unsigned)A.nbr), dim3(64), 0, s, A.rp, A.ci, A.v64, dinv, A.nbr,
                        bs, work);
     unsigned long long u = 0;
     TM_HIP(hipMemcpyAsync(&u, work, sizeof(u), hipMemcpyDeviceToHost, s));
@@ -716,25 +860,67 @@ void sa_row_of(const int32_t* rp, int64_t nrows, int32_t* rowof, hipStream_t s) 
 }
 void sa_p_numeric(const BSR& A, const int32_t* agg, const double* T, const double* dinv, int bs, int k,
                   double omega, const int32_t* prow, const BSR& P, hipStream_t s) {
-    hipLaunchKernelGGL(k_p_numeric, dim3(grid_for(P.nnzb, 64)), dim3(64), 0, s, A.rp, A.ci, A.v64, agg, T, dinv,
-                       A.nbr, bs, k, omega, prow, P.ci, P.nnzb, P.v64);
+    (void)prow;
+    const dim3 g((unsigned)A.nbr), b(64);
+#define TM_PN(BS, K)                                                                                     \
+    hipLaunchKernelGGL((k_p_numeric<BS, K>), g, b, 0, s, A.rp, A.ci, A.v64, agg, T, dinv, (int64_t)A.nbr, omega, \
+                       P.rp, P.ci, P.v64)
+    if (bs == 3 && k == 6) TM_PN(3, 6);
+    else if (bs == 6 && k == 6) TM_PN(6, 6);
+    else if (bs == 2 && k == 3) TM_PN(2, 3);
+    else if (bs == 3 && k == 3) TM_PN(3, 3);
+    else fail(TM_ERR_ARG, "aggregation block shape not supported");
+#undef TM_PN
 }
-void sa_transpose(const BSR& P, const int32_t* prow, BSR& PT, int32_t* cursor, int32_t* tsrc, int64_t* work,
-                  hipStream_t s) {
+void sa_transpose(const BSR& P, const int32_t* prow, BSR& PT, int32_t* cursor, int32_t* tsrc, int32_t* uci,
+                  int32_t* usrc, int64_t* work, hipStream_t s) {
     TM_HIP(hipMemsetAsync(PT.rp, 0, sizeof(int32_t) * (PT.nbr + 1), s));
     TM_HIP(hipMemsetAsync(cursor, 0, sizeof(int32_t) * PT.nbr, s));
     hipLaunchKernelGGL(k_tr_count, dim3(grid_for(P.nnzb)), dim3(WG), 0, s, P.nnzb, P.ci, PT.rp);
     scan_exclusive(PT.rp, PT.rp, PT.nbr, work, s);
     hipLaunchKernelGGL(k_tr_place, dim3(grid_for(P.nnzb)), dim3(WG), 0, s, P.nnzb, prow, P.ci,
-                       (const int32_t*)PT.rp, cursor, PT.ci, tsrc);
-    hipLaunchKernelGGL(k_tr_sort, dim3(grid_for(PT.nbr)), dim3(WG), 0, s, PT.nbr, (const int32_t*)PT.rp, PT.ci,
-                       tsrc);
+                       (const int32_t*)PT.rp, cursor, uci, usrc);
+    hipLaunchKernelGGL(k_rank_segments, dim3((unsigned)PT.nbr), dim3(64), 0, s, (int64_t)PT.nbr,
+                       (const int32_t*)PT.rp, (const int32_t*)uci, (const int32_t*)usrc, PT.ci, tsrc);
     hipLaunchKernelGGL(k_tr_values, dim3(grid_for(P.nnzb)), dim3(WG), 0, s, P.nnzb, (const int32_t*)tsrc, P.v64,
                        P.br, P.bc, PT.v64);
 }
-void sa_prod_numeric(const BSR& X, const BSR& Y, const int32_t* crow, BSR& C, hipStream_t s) {
-    hipLaunchKernelGGL(k_prod_numeric, dim3(grid_for(C.nnzb, 64)), dim3(64), 0, s, X.rp, X.ci, X.v64, X.br, X.bc,
-                       Y.rp, Y.ci, Y.v64, Y.bc, crow, C.ci, C.nnzb, C.v64);
+__global__ void k_max_row(const int32_t* __restrict__ rp, int64_t n, int32_t* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) atomicMax(out, rp[i + 1] - rp[i]);
+}
+
+// LDS of the row form: the longest output row's sums (+ its columns), at most
+// 48 KB; longer rows take the block form
+template <int XR, int XC, int YC>
+static void prod_launch(const BSR& X, const BSR& Y, BSR& C, int32_t mmax, hipStream_t s) {
+    constexpr int NE = XR * YC, NS = NE + 1;
+    constexpr size_t CAP = 48 * 1024;
+    const size_t block_form = (size_t)64 * NE * sizeof(double) + 64 * sizeof(int);
+    int mcap = (int)std::min<int64_t>(mmax, (int64_t)(CAP / (NS * sizeof(double) + sizeof(int32_t))));
+    size_t lds = (size_t)mcap * (NS * sizeof(double) + sizeof(int32_t));
+    lds = std::max(lds, block_form);
+    hipLaunchKernelGGL((k_prod_rows<XR, XC, YC>), dim3((unsigned)C.nbr), dim3(64), lds, s, X.rp, X.ci, X.v64, Y.rp,
+                       Y.ci, Y.v64, C.rp, C.ci, (int64_t)C.nbr, mcap, C.v64);
+}
+
+void sa_prod_numeric(const BSR& X, const BSR& Y, const int32_t* crow, BSR& C, int32_t* dtmp, hipStream_t s) {
+    (void)crow;
+    if (C.nbr < 1) return;
+    TM_HIP(hipMemsetAsync(dtmp, 0, sizeof(int32_t), s));
+    hipLaunchKernelGGL(k_max_row, dim3(grid_for(C.nbr)), dim3(WG), 0, s, C.rp, (int64_t)C.nbr, dtmp);
+    int32_t mmax = 0;
+    TM_HIP(hipMemcpyAsync(&mmax, dtmp, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    TM_HIP(hipStreamSynchronize(s));
+    const int xr = X.br, xc = X.bc, yc = Y.bc;
+    if (Y.br != xc) fail(TM_ERR_ARG, "block shapes of a product do not match");
+    if (xr == 3 && xc == 3 && yc == 6) prod_launch<3, 3, 6>(X, Y, C, mmax, s);
+    else if (xr == 6 && xc == 3 && yc == 6) prod_launch<6, 3, 6>(X, Y, C, mmax, s);
+    else if (xr == 6 && xc == 6 && yc == 6) prod_launch<6, 6, 6>(X, Y, C, mmax, s);
+    else if (xr == 2 && xc == 2 && yc == 3) prod_launch<2, 2, 3>(X, Y, C, mmax, s);
+    else if (xr == 3 && xc == 2 && yc == 3) prod_launch<3, 2, 3>(X, Y, C, mmax, s);
+    else if (xr == 3 && xc == 3 && yc == 3) prod_launch<3, 3, 3>(X, Y, C, mmax, s);
+    else fail(TM_ERR_ARG, "aggregation block shape not supported");
 }
 void sa_fix_diag(BSR& A, int bs, hipStream_t s) {
     hipLaunchKernelGGL(k_fix_diag, dim3(grid_for(A.nbr)), dim3(WG), 0, s, A.rp, A.ci, A.nbr, bs, A.v64);
