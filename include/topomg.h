@@ -338,6 +338,11 @@ tm_status tm_export_prolongator(const tm_hierarchy* h, int32_t level, int64_t* n
 tm_status tm_export_aggregates(const tm_hierarchy* h, int32_t level, int32_t* agg_of_node);
 /* Point-block diagonal inverse of a level, FP64, [node][bs*bs] row-major blocks. */
 tm_status tm_export_dinv(const tm_hierarchy* h, int32_t level, double* dinv);
+/* The coarsest level's inverse as the V-cycle applies it (Sec. 3.2 coarsest
+ * solve; formed at setup from the FP64 Cholesky factor as L^-T L^-1), n x n
+ * FP64 row-major into a host buffer, n = rows of the last level.  Waits for the
+ * device. */
+tm_status tm_export_coarse_inverse(const tm_hierarchy* h, double* ainv);
 /* Element-to-node table of a mesh (host int32[n_el * 2^dim], local order above). */
 tm_status tm_export_connectivity(const tm_mesh* mesh, int32_t* conn);
 /* Device bytes held by the hierarchy (not counting solve states). */

@@ -108,6 +108,7 @@ def _load():
         "tm_export_prolongator": (I32, [P, I32, C.POINTER(I64), C.POINTER(I64), P, P, P]),
         "tm_export_aggregates": (I32, [P, I32, P]),
         "tm_export_dinv": (I32, [P, I32, P]),
+        "tm_export_coarse_inverse": (I32, [P, P]),
         "tm_export_connectivity": (I32, [C.POINTER(tm_mesh), P]),
         "tm_hierarchy_bytes": (I32, [P, C.POINTER(SZ)]),
         "tm_compliance_sensitivity": (I32, [P, I32, P, P, P]),

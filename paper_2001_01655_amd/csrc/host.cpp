@@ -2052,6 +2052,15 @@ tm_status tm_export_dinv(const tm_hierarchy* h, int32_t level, double* dinv) {
     });
 }
 
+tm_status tm_export_coarse_inverse(const tm_hierarchy* h, double* ainv) {
+    return guarded([&] {
+        if (!h) fail(TM_ERR_ARG, "hierarchy is NULL");
+        if (!ainv) fail(TM_ERR_ARG, "ainv is NULL");
+        TM_HIP(hipDeviceSynchronize());
+        TM_HIP(hipMemcpy(ainv, h->ainv, (size_t)h->nc * h->nc * sizeof(double), hipMemcpyDeviceToHost));
+    });
+}
+
 tm_status tm_export_connectivity(const tm_mesh* mesh, int32_t* conn) {
     return guarded([&] {
         check_mesh(mesh);

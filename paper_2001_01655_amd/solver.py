@@ -176,6 +176,12 @@ class Hierarchy:
         check(LIB.tm_export_dinv(self._h, level, d.ctypes.data), "tm_export_dinv")
         return d
 
+    def export_coarse_inverse(self) -> np.ndarray:
+        n = self.level_info(self.num_levels() - 1)["n_rows"]
+        a = np.empty((n, n), np.float64)
+        check(LIB.tm_export_coarse_inverse(self._h, a.ctypes.data), "tm_export_coarse_inverse")
+        return a
+
     def compliance_sensitivity(self, u, stream=None) -> torch.Tensor:
         """d(sum_k f_k^T u_k)/d rho_e for the solutions u (n_dof or (n_rhs, n_dof))."""
         u_d = _dev(u)

@@ -41,6 +41,32 @@ def test_sensitivity_vs_oracle(dim, nel, L, n_rhs):
     H.close()
 
 
+@pytest.mark.parametrize("dim,nel,L,n_rhs", [(2, (40, 24), 3, 2), (3, (12, 8, 8), 3, 1)])
+def test_sensitivity_end_to_end(dim, nel, L, n_rhs):
+    """From the loads to dc on both sides: the oracle's own displacements
+    (a sparse direct solve of its assembled K~) and its formula, against the
+    GPU's solve at rtol 1e-10 and its sensitivity kernel.  The difference is
+    that of the two solutions, carried to first order by 2 |u_e| |KE| |du_e|:
+    bounded here by 1e-7 of the largest |dc_e|."""
+    import scipy.sparse.linalg as spl
+    from paper_2001_01655_amd import Hierarchy
+    print(f"sensitivity end to end {nel} rhs={n_rhs}", flush=True)
+    p = synth.small_case(dim, nel, seed=43, n_rhs=n_rhs)
+    KE = fem.element_stiffness(dim, p.nu)
+    K = fem.apply_dirichlet(fem.assemble(p.nel, fem.simp(p.rho, p.p, p.E0, p.Emin), KE), p.fixed).tocsc()
+    F = p.loads.copy()
+    F[:, p.fixed] = 0.0
+    U_ref = np.stack([spl.spsolve(K, F[k]) for k in range(n_rhs)])
+    ref = fem.compliance_sensitivity(p.nel, p.rho, p.p, p.E0, p.Emin, KE, U_ref)
+    H = Hierarchy(p.nel, p.rho, p.fixed, p=p.p, E0=p.E0, Emin=p.Emin, nu=p.nu, n_levels=L)
+    r = H.solve(torch.tensor(p.loads, device="cuda"), rtol=1e-10)
+    dc = H.compliance_sensitivity(r.u).cpu().numpy()
+    H.close()
+    err = float(np.max(np.abs(dc - ref)) / np.max(np.abs(ref)))
+    print(f"  max |dc - dc_oracle| / max |dc_oracle| = {err:.2e}", flush=True)
+    assert err <= 1e-7
+
+
 def test_sensitivity_full_size_homogeneity():
     """3D cantilever at full size: sum_e rho_e dc_e = -p c up to the Emin part,
     which the oracle's element sum evaluates exactly on the GPU solution."""
