@@ -129,7 +129,7 @@ __global__ __launch_bounds__(WG) void k_bsr_mv(const int32_t* __restrict__ rp, c
     }
 }
 
-template <typename T, int BR, int BC, bool FIRST>
+template <typename T, int BR, int BC, bool ADD, bool FIRST>
 __global__ __launch_bounds__(WG) void k_bsr_mv_wave(const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
                                                     const T* __restrict__ v, int64_t nbr, const T* __restrict__ x,
                                                     T* __restrict__ y, T* __restrict__ xf,
@@ -156,7 +156,12 @@ __global__ __launch_bounds__(WG) void k_bsr_mv_wave(const int32_t* __restrict__ 
         for (int o = 32; o > 0; o >>= 1) acc[r] += __shfl_down(acc[r], o, 64);
     if (lane != 0) return;
 #pragma unroll
-    for (int r = 0; r < BR; ++r) y[(int64_t)BR * row + r] = acc[r];
+    for (int r = 0; r < BR; ++r) {
+        if (ADD)
+            y[(int64_t)BR * row + r] += acc[r];
+        else
+            y[(int64_t)BR * row + r] = acc[r];
+    }
     if (FIRST) {
 #pragma unroll
         for (int r = 0; r < BR; ++r) {
@@ -173,14 +178,17 @@ static void bsr_mv_shape(const BSR& B, const T* x, T* y, bool add, T* xfirst, co
                          const int* done, hipStream_t s) {
     const dim3 g(grid_for(B.nbr)), blk(WG);
     const T* v = vals_of<T>(B);
-    if (!add && B.nnzb >= 8 * B.nbr) {      // long rows (restriction): one wave per row
+    if (B.nnzb >= 8 * B.nbr) {      // long rows (restriction, smoothed prolongators): one wave per row
         const dim3 gw(grid_for(B.nbr, WG / 64));
-        if (xfirst)
-            hipLaunchKernelGGL((k_bsr_mv_wave<T, BR, BC, true>), gw, blk, 0, s, B.rp, B.ci, v, B.nbr, x, y, xfirst,
-                               dinv, omega, done);
+        if (add)
+            hipLaunchKernelGGL((k_bsr_mv_wave<T, BR, BC, true, false>), gw, blk, 0, s, B.rp, B.ci, v, B.nbr, x, y,
+                               xfirst, dinv, omega, done);
+        else if (xfirst)
+            hipLaunchKernelGGL((k_bsr_mv_wave<T, BR, BC, false, true>), gw, blk, 0, s, B.rp, B.ci, v, B.nbr, x, y,
+                               xfirst, dinv, omega, done);
         else
-            hipLaunchKernelGGL((k_bsr_mv_wave<T, BR, BC, false>), gw, blk, 0, s, B.rp, B.ci, v, B.nbr, x, y, xfirst,
-                               dinv, omega, done);
+            hipLaunchKernelGGL((k_bsr_mv_wave<T, BR, BC, false, false>), gw, blk, 0, s, B.rp, B.ci, v, B.nbr, x, y,
+                               xfirst, dinv, omega, done);
         return;
     }
     if (add)
