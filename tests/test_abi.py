@@ -49,6 +49,7 @@ def _setup_status(nel=(8, 4), nu=0.3, Emin=1e-9, E0=1.0, dofs=(0, 1), **opts):
 
 @pytest.mark.parametrize("kw,msg", [
     (dict(nel=(8, 2), n_levels=3), "too many geometric levels"),
+    (dict(n_levels=1), "at least two levels"),
     (dict(nu=0.5), "nu"),
     (dict(Emin=2.0), "Emin"),
     (dict(dofs=(0, 10 ** 9)), "out of range"),
