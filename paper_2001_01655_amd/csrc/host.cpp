@@ -750,16 +750,36 @@ static void vcycle_b(const VLane<T>* lanes, int n, hipStream_t s, bool first_don
     for (int l = L - 2; l >= 0; --l) {
         std::vector<T*>& x = xr[l];
         std::vector<T*>& t = tr[l];
-        for (int q = 0; q < n; ++q) {
-            io[q].x = xr[l + 1][q];
-            io[q].y = x[q];
+        // small geometric levels below a geometric level take the prolongation
+        // inside their first post-smoothing step
+        const bool fused = stencil_pro_ok(h0, l);
+        if (!fused) {
+            for (int q = 0; q < n; ++q) {
+                io[q].x = xr[l + 1][q];
+                io[q].y = x[q];
+            }
+            prolong_b<T>(l, io.data(), n, s);
         }
-        prolong_b<T>(l, io.data(), n, s);
         for (int k = 0; k < npost; ++k) {
             const bool to_z = l == 0 && k == npost - 1;
             std::vector<T*> dst(n);
             for (int q = 0; q < n; ++q) dst[q] = to_z ? lanes[q].z : t[q];
-            smooth(l, k, false, k == npost - 1, x, dst);
+            if (fused && k == 0) {
+                double c1 = 0.0, c2 = 0.0;
+                if (cheb) cheb_coef(0, c1, c2);
+                for (int q = 0; q < n; ++q) {
+                    io[q].x = x[q];
+                    io[q].xc = xr[l + 1][q];
+                    io[q].b = bvec(l, q);
+                    io[q].y = dst[q];
+                    io[q].din = nullptr;
+                    io[q].dout = cheb && npost > 1 ? lanes[q].V->d[l] : nullptr;
+                }
+                launch_stencil_pro_b<T>(l, cheb ? OP_CHEB : OP_SMOOTH, io.data(), n, (T)h0->opt.omega, c1, c2, s);
+                for (int q = 0; q < n; ++q) io[q].xc = nullptr;
+            } else {
+                smooth(l, k, false, k == npost - 1, x, dst);
+            }
             if (!to_z) std::swap(x, t);
         }
     }

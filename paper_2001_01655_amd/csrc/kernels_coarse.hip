@@ -1040,6 +1040,163 @@ __global__ __launch_bounds__(WG) void k_prolong(const Pack<ProlongA<T>, NB> pk, 
     for (int c = 0; c < DIM; ++c) xf[DIM * node + c] = ((m >> c) & 1u) ? xo[c] : xo[c] + acc[c];
 }
 
+// The prolongation x_l + P x_{l+1} fused into the first post-smoothing step of
+// a small geometric level (coarse level geometric too): the step reads the
+// prolonged iterate of the node and of its neighbours, formed on the fly
+// exactly as k_prolong forms it (same parents, weights and order), so the
+// prolongation launch and its store are saved.  The coarse values a node needs
+// lie in a 3^DIM block of coarse nodes (per axis: the parents of fine nodes
+// i-1 .. i+1); the P lanes of a node load that block into LDS together, then
+// (after the barrier) each lane loads its neighbour slots as k_stencil_split
+// does and forms their prolonged values.  Neighbour slots, blocks and sums are
+// those of k_stencil_split with P lanes per node (used in 2D with P = 1).
+// Nodes past the end compute on a clamped node and store nothing (every
+// thread reaches the barrier).
+template <typename T, int DIM, int OP, int P, int NB>
+__global__ __launch_bounds__(WG) void k_stencil_pro(const Pack<OpA<T>, NB> pk, int nx, int ny, int nz,
+                                                    int64_t N, T omega, double c1, double c2) {
+    constexpr int NCB = DIM == 3 ? 27 : 9;          // coarse block
+    __shared__ T cblk[WG / P][NCB][DIM];
+    const OpA<T>& A_ = lane_of(pk);
+    const T* __restrict__ st = A_.E;
+    const T* __restrict__ x = A_.x;
+    const T* __restrict__ xc = A_.xc;
+    const T* __restrict__ b = A_.b;
+    T* __restrict__ y = A_.y;
+    const T* __restrict__ dinv = A_.dinv;
+    const int* __restrict__ done = A_.done;
+    if (done && *done) return;                       // uniform over the workgroup (one lane per grid row)
+    const int64_t gid = xcd_block() * WG + threadIdx.x;
+    const bool live = gid / P < N;
+    const int64_t node = live ? gid / P : N - 1;
+    const int p = (int)(gid & (P - 1));
+    const int nl = (int)threadIdx.x / P;
+    constexpr int BB = DIM * DIM, NST = DIM == 3 ? 27 : 9, NU = (NST - 1) / 2;
+    constexpr int NQ = NU * BB + DIM * (DIM + 1) / 2;
+    constexpr int NS = (NST + P - 1) / P;
+    const int NX = nx + 1, NY = ny + 1, NZ = nz + 1;
+    const int i = (int)(node % NX);
+    const int j = (int)((node / NX) % NY);
+    const int k = DIM == 3 ? (int)(node / ((int64_t)NX * NY)) : 0;
+    const int CX = (nx + 1) / 2 + 1, CY = (ny + 1) / 2 + 1, CZ = DIM == 3 ? (nz + 1) / 2 + 1 : 1;
+    const int64_t Nc = (int64_t)CX * CY * CZ;
+    const auto sr = buf_rsrc(st, (int64_t)N * NQ * sizeof(T));
+    const auto xr = buf_rsrc(x, (int64_t)N * DIM * sizeof(T));
+    const auto cr = buf_rsrc(xc, Nc * DIM * sizeof(T));
+    const uint32_t un = (uint32_t)node, uN = (uint32_t)N;
+    uint32_t ci[3], cj[3], ck[3];
+    bool ii[3], ij[3], ik[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        ci[d] = (uint32_t)min(max(i + d - 1, 0), NX - 1);
+        cj[d] = (uint32_t)min(max(j + d - 1, 0), NY - 1);
+        ck[d] = DIM == 3 ? (uint32_t)min(max(k + d - 1, 0), NZ - 1) : 0u;
+        ii[d] = i + d - 1 >= 0 && i + d - 1 < NX;
+        ij[d] = j + d - 1 >= 0 && j + d - 1 < NY;
+        ik[d] = DIM == 2 || (k + d - 1 >= 0 && k + d - 1 < NZ);
+    }
+    // the block starts at the first parent of fine node i - 1 (clamped) per axis
+    const int lx = (int)ci[0] >> 1, ly = (int)cj[0] >> 1, lz = DIM == 3 ? (int)ck[0] >> 1 : 0;
+    // the coarse block [lx, lx+2] x [ly, ly+2] (x [lz, lz+2]), indices clamped
+#pragma unroll
+    for (int sb = p; sb < NCB; sb += P) {
+        const int sx = sb % 3, sy = (sb / 3) % 3, sz = sb / 9;
+        const uint32_t C = (uint32_t)((DIM == 3 ? min(lz + sz, CZ - 1) * CY : 0) + min(ly + sy, CY - 1)) *
+                               (uint32_t)CX + (uint32_t)min(lx + sx, CX - 1);
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) cblk[nl][sb][c] = bld<T>(cr, (DIM * C + c) * (uint32_t)sizeof(T));
+    }
+    __syncthreads();
+    // this node's value and the finishing operands, then the slots' loads
+    // (after the barrier, so that it waits for the coarse block only)
+    T xraw[DIM];
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) xraw[c] = bld<T>(xr, (DIM * un + c) * (uint32_t)sizeof(T));
+    ChebArgs ch;
+    ch.din = nullptr;
+    ch.dout = A_.dout;
+    ch.c1 = c1;
+    ch.c2 = c2;
+    FinIn<T, DIM> fin;
+    finish_load<T, DIM, OP == OP_CHEB ? OP_SMOOTH : OP>(node, N, b, dinv, ch, fin);
+    T xv[NS][DIM], blk[NS][BB];
+#pragma unroll
+    for (int sl = 0; sl < NS; ++sl) {
+        const int o = sl * P + p;
+        const bool valid = o < NST;
+        const int oc = valid ? o : NST - 1;
+        const int dx = oc % 3, dy = (oc / 3) % 3, dz = DIM == 3 ? oc / 9 : 1;
+        const uint32_t J = (ck[dz] * (uint32_t)NY + cj[dy]) * (uint32_t)NX + ci[dx];
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) xv[sl][c] = bld<T>(xr, (DIM * J + c) * (uint32_t)sizeof(T));
+        const bool up = oc > NU, lo = oc < NU;
+        const uint32_t qU = (uint32_t)(oc - NU - 1) * BB, qL = (uint32_t)(NST - 1 - oc - NU - 1) * BB;
+        const uint32_t at = lo ? J : un;
+#pragma unroll
+        for (int r = 0; r < DIM; ++r)
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) {
+                const int lr = r < c ? r : c, hc = r < c ? c : r;
+                const uint32_t qd = (uint32_t)(NU * BB + lr * DIM - lr * (lr - 1) / 2 + (hc - lr));
+                const uint32_t q = up ? qU + (uint32_t)(r * DIM + c) : (lo ? qL + (uint32_t)(c * DIM + r) : qd);
+                blk[sl][r * DIM + c] = bld<T>(sr, (q * uN + at) * (uint32_t)sizeof(T));
+            }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    // prolonged value of fine node (fi, fj, fk): x + sum of the corners, as in k_prolong
+    auto pro = [&](int fi, int fj, int fk, const T (&xin)[DIM], T (&out)[DIM]) {
+        int pa[2], pb[2], pc[2] = {lz, lz};
+        T wa[2], wb[2], wc[2] = {T(1), T(0)};
+        prolong_parents<T>(fi, nx, pa, wa);
+        prolong_parents<T>(fj, ny, pb, wb);
+        if (DIM == 3) prolong_parents<T>(fk, nz, pc, wc);
+        T acc[DIM] = {};
+#pragma unroll
+        for (int q = 0; q < (DIM == 3 ? 8 : 4); ++q) {
+            const int a2 = q & 1, b2 = (q >> 1) & 1, c2 = q >> 2;
+            const T w = wa[a2] * wb[b2] * (DIM == 3 ? wc[c2] : T(1));
+            const int sb = (pa[a2] - lx) + 3 * ((pb[b2] - ly) + (DIM == 3 ? 3 * (pc[c2] - lz) : 0));
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) acc[c] += w * cblk[nl][sb][c];
+        }
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) out[c] = xin[c] + acc[c];
+    };
+    T xo[DIM];
+    pro((int)ci[1], (int)cj[1], (int)ck[1], xraw, xo);
+    // slot by slot (the sums in the order of k_stencil_split), so that only one
+    // slot's prolonged values are live
+    T acc[DIM] = {};
+#pragma unroll
+    for (int sl = 0; sl < NS; ++sl) {
+        const int oc = min(sl * P + p, NST - 1);
+        const int dx = oc % 3, dy = (oc / 3) % 3, dz = DIM == 3 ? oc / 9 : 1;
+        T xp[DIM];
+        pro((int)ci[dx], (int)cj[dy], (int)ck[dz], xv[sl], xp);
+        const bool lo = oc < NU;
+        const bool keep = sl * P + p < NST && (!lo || (ii[dx] && ij[dy] && ik[dz]));
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) xp[c] = keep ? xp[c] : T(0);
+#pragma unroll
+        for (int r = 0; r < DIM; ++r)
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) acc[r] += blk[sl][r * DIM + c] * xp[c];
+        __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int m = 1; m < P; m <<= 1)
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) acc[c] += __shfl_xor(acc[c], m, 64);
+    if (p == 0 && live) {
+        // the step starts from the prolonged iterate, which is also the first
+        // Chebyshev step's direction input (its coefficient is zero)
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) fin.din[c] = xo[c];
+        double dots[2];
+        finish_store<T, DIM, OP>(node, acc, xo, 0, fin, y, omega, dots, ch);
+    }
+}
+
 template <typename T, int DIM, int NB>
 static void prolong_launch(int fl, const LaneIO* L, int n, hipStream_t s) {
     const Level& fine = L[0].h->lv[fl];
@@ -1057,6 +1214,51 @@ static void prolong_launch(int fl, const LaneIO* L, int n, hipStream_t s) {
 }
 
 // x_f += M P x_c (lane x = coarse, y = fine)
+// a small 2D geometric level (the small-level operator form) below a geometric
+// level.  In 3D the fused step needs every register of a lane for its seven
+// neighbour slots' prolonged values and was slower than the two launches, so
+// 3D levels keep the separate prolongation.
+bool stencil_pro_ok(const tm_hierarchy* h, int level) {
+    if (level < 1 || level + 1 >= (int)h->lv.size() || h->dim != 2) return false;
+    const Level& V = h->lv[level];
+    if (V.kind != TM_LEVEL_GEOMETRIC || h->lv[level + 1].kind != TM_LEVEL_GEOMETRIC || V.xfer_bsr) return false;
+    return V.op_kernel == 0 ? grid_for(V.n_nodes) < 256 : V.op_kernel == 2;
+}
+
+template <typename T, int DIM, int NB>
+static void stencil_pro_launch(int level, const LaneIO* L, int n, int op, T omega, double c1, double c2,
+                               hipStream_t s) {
+    const Level& V = L[0].h->lv[level];
+    auto pk = stencil_pack<T, NB>(level, L, n);
+    for (int q = 0; q < n; ++q) pk.a[q].xc = (const T*)L[q].xc;
+    const int nz = DIM == 3 ? V.nel[2] : 0;
+    constexpr int P = DIM == 3 ? 4 : 1;
+    const dim3 g(grid_for(V.n_nodes * P), n), blk(WG);
+#define TM_SP(OPV)                                                                                   \
+    hipLaunchKernelGGL((k_stencil_pro<T, DIM, OPV, P, NB>), g, blk, 0, s, pk, V.nel[0], V.nel[1], nz, V.n_nodes, \
+                       omega, c1, c2)
+    if (op == OP_CHEB)
+        TM_SP(OP_CHEB);
+    else
+        TM_SP(OP_SMOOTH);
+#undef TM_SP
+}
+
+template <typename T>
+void launch_stencil_pro_b(int level, int op, const LaneIO* L, int n, T omega, double c1, double c2,
+                          hipStream_t s) {
+    if (n < 1) return;
+    if (op != OP_CHEB && op != OP_SMOOTH) fail(TM_ERR_ARG, "fused prolongation takes a smoothing step");
+    if (L[0].h->lv[level].dim != 2) fail(TM_ERR_ARG, "fused prolongation is for 2D levels");
+    for (int q0 = 0; q0 < n; q0 += MAXB) {
+        const int m = std::min(MAXB, n - q0);
+        if (m == 1) stencil_pro_launch<T, 2, 1>(level, L + q0, 1, op, omega, c1, c2, s);
+        else stencil_pro_launch<T, 2, MAXB>(level, L + q0, m, op, omega, c1, c2, s);
+    }
+}
+template void launch_stencil_pro_b<double>(int, int, const LaneIO*, int, double, double, double, hipStream_t);
+template void launch_stencil_pro_b<float>(int, int, const LaneIO*, int, float, double, double, hipStream_t);
+
 template <typename T>
 void launch_prolong_b(int fl, const LaneIO* L, int n, hipStream_t s) {
     if (n < 1) return;

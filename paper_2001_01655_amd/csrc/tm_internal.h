@@ -156,6 +156,7 @@ struct OpA {
     double* partials;
     const T* din;        // Chebyshev step: previous direction (or the iterate) ...
     T* dout;             // ... and the new direction (NULL: not kept)
+    const T* xc;         // fused prolongation: the coarse level's correction
 };
 template <typename T>
 struct RestrictA {
@@ -423,6 +424,7 @@ struct LaneIO {
     double* part = nullptr;
     const void* din = nullptr;
     void* dout = nullptr;
+    const void* xc = nullptr;
     KScal* sc = nullptr;
     Lane* ln = nullptr;
     double* u = nullptr;
@@ -437,6 +439,12 @@ template <typename T>
 void launch_restrict_b(int fine_level, const LaneIO* L, int n, T omega, hipStream_t s);
 template <typename T>
 void launch_prolong_b(int fine_level, const LaneIO* L, int n, hipStream_t s);
+// prolongation fused into the first post-smoothing step (op OP_SMOOTH or
+// OP_CHEB from the prolonged iterate) of a small geometric level whose coarse
+// level is geometric too; stencil_pro_ok says whether level l qualifies
+bool stencil_pro_ok(const tm_hierarchy* h, int level);
+template <typename T>
+void launch_stencil_pro_b(int level, int op, const LaneIO* L, int n, T omega, double c1, double c2, hipStream_t s);
 template <typename T>
 void launch_first_smooth_b(int level, const LaneIO* L, int n, T omega, hipStream_t s);
 template <typename T>
