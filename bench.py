@@ -117,6 +117,33 @@ def timed_solves(H, f, steps, warmup, rtol):
     return time.perf_counter() - t0, res
 
 
+def event_solves(H, f, n, rtol):
+    """Device time of n single solves, each from f resident to u resident,
+    between HIP events on the stream the solve runs on (median and range)."""
+    import torch
+    ts = []
+    for _ in range(n):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        H.solve(f, rtol=rtol)
+        e1.record()
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    ts.sort()
+    return {"median_ms": round(ts[len(ts) // 2], 3), "min_ms": round(ts[0], 3), "max_ms": round(ts[-1], 3),
+            "solves": n}
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
 def vcycle_mix(smoother, nu):
     """Operator launches of one level per V-cycle as (reads D^-1, reads the
     previous Chebyshev direction, writes the direction).  The first
@@ -249,7 +276,7 @@ def cpu_baseline(cfg_name, args):
             "all_cores": {"value": round(p.n_dof / dt_all / 1e6, 4), "seconds": round(dt_all, 3),
                           "threads_available": os.cpu_count(),
                           "parallel_parts": "dense coarsest Cholesky solve (BLAS); sparse products single-threaded"},
-            "host": platform.processor() or platform.machine(), "host_cpus": os.cpu_count()}
+            "host": cpu_model(), "host_cpus": os.cpu_count()}
 
 
 def served_requests(n: int, rate_per_s: float, n_designs: int = 20, seed: int = 5) -> list:
@@ -627,7 +654,8 @@ def main():
     ms = dt / args.steps * 1e3
     value = p.n_dof * args.steps / dt / 1e6
     detail = {"mixed": dict(iters=res.iters[0], relres=res.relres[0], compliance=res.compliance[0],
-                            setup_ms=round(t_setup * 1e3, 2), levels=H.num_levels())}
+                            setup_ms=round(t_setup * 1e3, 2), levels=H.num_levels(),
+                            device_time_per_solve=event_solves(H, f, 5, rtol))}
     coarsest = H.level_info(H.num_levels() - 1)["n_rows"]
     line = {
         "metric": "MDoF/s to rtol 1e-8 (FP32 V-cycle vs FP64 PCG)",
