@@ -107,6 +107,10 @@ typedef struct {
                               large-level kernel, smaller ones the latency-bound form); 1: the
                               large-level kernel on every level; 2: the small-level form on
                               every level.  Same operator either way                        */
+    int32_t sa_lds;         /* aggregation setup: 0 (default) keeps a Galerkin product row's sums,
+                              an aggregate's Gram-Schmidt rows and a prolongator row's blocks in
+                              LDS when they fit; 1: never (block by block, in device memory).
+                              The levels are bitwise the same either way                     */
 } tm_options;
 
 /* Source of a hierarchy's device memory (levels, solve states, work vectors,

@@ -302,6 +302,7 @@ static void check_opts(const tm_options* o) {
     if (o->check_every < 0) fail(TM_ERR_ARG, "check_every must be >= 0");
     if (o->fine_mfma != 0 && o->fine_mfma != 1) fail(TM_ERR_ARG, "fine_mfma must be 0 or 1");
     if (o->stencil_kernel < 0 || o->stencil_kernel > 2) fail(TM_ERR_ARG, "stencil_kernel must be 0, 1 or 2");
+    if (o->sa_lds < 0 || o->sa_lds > 1) fail(TM_ERR_ARG, "sa_lds must be 0 or 1");
     if (o->n_levels > 0 && o->n_geometric > o->n_levels) fail(TM_ERR_ARG, "n_geometric > n_levels");
 }
 
@@ -1522,6 +1523,7 @@ void tm_default_options(tm_options* o) {
     o->adapt_iters = 0;
     o->cheb_warm_steps = 0;
     o->stencil_kernel = 0;
+    o->sa_lds = 0;
 }
 
 const char* tm_status_string(tm_status s) {

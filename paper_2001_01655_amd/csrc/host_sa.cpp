@@ -25,17 +25,19 @@ void sa_agg_passes(const int32_t* srp, const int32_t* sci, int64_t n, const uint
 void sa_members(int64_t n, int64_t ng, const int32_t* agg, int32_t* cnt_off, int32_t* cursor, int32_t* mem,
                 int32_t* umem, int64_t* work, hipStream_t s);
 void sa_tentative(int64_t ng, const int32_t* off, const int32_t* mem, const double* Bprev, int dim, int nx1,
-                  int ny1, double h, int level, const int* nel0, int bs, int k, double* T, double* Bc, hipStream_t s);
+                  int ny1, double h, int level, const int* nel0, int bs, int k, double* T, double* Bc, bool use_lds,
+                  hipStream_t s);
 double sa_jacobi_bound(const BSR& A, int bs, const double* dinv, unsigned long long* work, hipStream_t s);
 void sa_symbolic(const int32_t* rp1, const int32_t* ci1, const int32_t* agg, const int32_t* rp2,
                  const int32_t* ci2, int32_t ncols, int kind, int64_t nrows, int32_t* cnt, const int32_t* orp,
                  int32_t* oci, bool fill, hipStream_t s);
 void sa_row_of(const int32_t* rp, int64_t nrows, int32_t* rowof, hipStream_t s);
 void sa_p_numeric(const BSR& A, const int32_t* agg, const double* T, const double* dinv, int bs, int k,
-                  double omega, const int32_t* prow, const BSR& P, hipStream_t s);
+                  double omega, const int32_t* prow, const BSR& P, bool use_lds, hipStream_t s);
 void sa_transpose(const BSR& P, const int32_t* prow, BSR& PT, int32_t* cursor, int32_t* tsrc, int32_t* uci,
                   int32_t* usrc, int64_t* work, hipStream_t s);
-void sa_prod_numeric(const BSR& X, const BSR& Y, const int32_t* crow, BSR& C, int32_t* dtmp, hipStream_t s);
+void sa_prod_numeric(const BSR& X, const BSR& Y, const int32_t* crow, BSR& C, int32_t* dtmp, bool use_lds,
+                     hipStream_t s);
 void sa_fix_diag(BSR& A, int bs, hipStream_t s);
 void sa_to_f32(const double* a, float* b, int64_t n, hipStream_t s);
 
@@ -184,7 +186,7 @@ void numeric_sa_levels(tm_hierarchy* h, hipStream_t s) {
             Pool nextp{h, h->sa_cand[step & 1]};
             double* Bc = nextp.get<double>((size_t)n_agg * k * k);
             sa_tentative(n_agg, off, mem, Bprev, dim, F.nn[0], F.nn[1], h->mesh.h, Lg - 1, h->mesh.nel, bs, k, T, Bc,
-                         s);
+                         h->opt.sa_lds == 0, s);
             // smoothed prolongator P = T - omega D^-1 A T
             unsigned long long* mx = tmp.get<unsigned long long>(1);
             const double lam = sa_jacobi_bound(F.A, bs, F.dinv64, mx, s);
@@ -194,7 +196,7 @@ void numeric_sa_levels(tm_hierarchy* h, hipStream_t s) {
             make_pattern(keep, tmp, P, n, n_agg, bs, k, F.A.rp, F.A.ci, agg, nullptr, nullptr, 0, work, s);
             int32_t* prow = tmp.get<int32_t>(P.nnzb);
             sa_row_of(P.rp, n, prow, s);
-            sa_p_numeric(F.A, agg, T, F.dinv64, bs, k, omega, prow, P, s);
+            sa_p_numeric(F.A, agg, T, F.dinv64, bs, k, omega, prow, P, h->opt.sa_lds == 0, s);
             // P^T
             BSR PT;
             PT.nbr = n_agg;
@@ -214,12 +216,12 @@ void numeric_sa_levels(tm_hierarchy* h, hipStream_t s) {
             make_pattern(tmp, tmp, AP, n, n_agg, bs, k, F.A.rp, F.A.ci, nullptr, P.rp, P.ci, 1, work, s);
             int32_t* aprow = tmp.get<int32_t>(AP.nnzb);
             sa_row_of(AP.rp, n, aprow, s);
-            sa_prod_numeric(F.A, P, aprow, AP, counter, s);
+            sa_prod_numeric(F.A, P, aprow, AP, counter, h->opt.sa_lds == 0, s);
             BSR Ac;
             make_pattern(keep, tmp, Ac, n_agg, n_agg, k, k, PT.rp, PT.ci, nullptr, AP.rp, AP.ci, 2, work, s);
             int32_t* acrow = tmp.get<int32_t>(Ac.nnzb);
             sa_row_of(Ac.rp, n_agg, acrow, s);
-            sa_prod_numeric(PT, AP, acrow, Ac, counter, s);
+            sa_prod_numeric(PT, AP, acrow, Ac, counter, h->opt.sa_lds == 0, s);
             sa_fix_diag(Ac, k, s);
             // FP32 copies for the V-cycle
             P.v32 = keep.get<float>((size_t)P.nnzb * bs * k);

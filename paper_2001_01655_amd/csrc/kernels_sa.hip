@@ -409,13 +409,13 @@ __device__ __forceinline__ void mgs_rows(double* __restrict__ W, const int32_t* 
 __global__ __launch_bounds__(64) void k_tentative(int64_t ng, const int32_t* __restrict__ off,
                                                   const int32_t* __restrict__ mem, const double* __restrict__ Bprev,
                                                   int dim, int nx1, int ny1, const LevelPos lp, int bs, int k,
-                                                  double* __restrict__ T, double* __restrict__ Bc) {
+                                                  double* __restrict__ T, double* __restrict__ Bc, int use_lds) {
     __shared__ double W[TENT_LDS];
     const int64_t g = blockIdx.x;
     if (g >= ng) return;
     const int32_t p0 = off[g], p1 = off[g + 1];
     const int nrow = (p1 - p0) * bs;
-    const bool sh = nrow * k <= TENT_LDS;
+    const bool sh = use_lds && nrow * k <= TENT_LDS;
     for (int t = (int)threadIdx.x; t < nrow; t += 64) {
         const int64_t i = mem[p0 + t / bs];
         const int r = t % bs;
@@ -589,7 +589,7 @@ __global__ __launch_bounds__(64) void k_p_numeric(const int32_t* __restrict__ ar
                                                   const double* __restrict__ av, const int32_t* __restrict__ agg,
                                                   const double* __restrict__ T, const double* __restrict__ dinv,
                                                   int64_t n, double omega, const int32_t* __restrict__ prp,
-                                                  const int32_t* __restrict__ pci, double* __restrict__ pv) {
+                                                  const int32_t* __restrict__ pci, double* __restrict__ pv, int slots) {
     constexpr int NE = BS * K;
     __shared__ double u[64][NE];
     __shared__ int32_t gq[64];
@@ -602,8 +602,8 @@ __global__ __launch_bounds__(64) void k_p_numeric(const int32_t* __restrict__ ar
     const double* TI = T + I * NE;
     const int32_t gI = agg[I];
     // blocks of the row in groups of PN_SLOTS (a row has a handful)
-    for (int32_t s0 = 0; s0 < nb; s0 += PN_SLOTS) {
-        const int ns = min(PN_SLOTS, nb - s0);
+    for (int32_t s0 = 0; s0 < nb; s0 += slots) {
+        const int ns = min(slots, nb - s0);
         for (int t = lane; t < ns * NE; t += 64) sums[t / NE][t % NE] = 0.0;
         for (int32_t qb = q0; qb < q1; qb += 64) {
             const int32_t q = qb + lane;
@@ -826,10 +826,11 @@ void sa_members(int64_t n, int64_t ng, const int32_t* agg, int32_t* cnt_off, int
                        (const int32_t*)umem, (const int32_t*)nullptr, mem, (int32_t*)nullptr);
 }
 void sa_tentative(int64_t ng, const int32_t* off, const int32_t* mem, const double* Bprev, int dim, int nx1,
-                  int ny1, double h, int level, const int* nel0, int bs, int k, double* T, double* Bc, hipStream_t s) {
+                  int ny1, double h, int level, const int* nel0, int bs, int k, double* T, double* Bc, bool use_lds,
+                  hipStream_t s) {
     LevelPos lp{h, 1 << level, {nel0[0], nel0[1], dim == 3 ? nel0[2] : 0}};
     hipLaunchKernelGGL(k_tentative, dim3((unsigned)ng), dim3(64), 0, s, ng, off, mem, Bprev, dim, nx1, ny1,
-                       lp, bs, k, T, Bc);
+                       lp, bs, k, T, Bc, (int)use_lds);
 }
 double sa_jacobi_bound(const BSR& A, int bs, const double* dinv, unsigned long long* work, hipStream_t s) {
     TM_HIP(hipMemsetAsync(work, 0, sizeof(unsigned long long), s));
@@ -859,12 +860,12 @@ void sa_row_of(const int32_t* rp, int64_t nrows, int32_t* rowof, hipStream_t s) 
     hipLaunchKernelGGL(k_row_of, dim3(grid_for(nrows)), dim3(WG), 0, s, rp, nrows, rowof);
 }
 void sa_p_numeric(const BSR& A, const int32_t* agg, const double* T, const double* dinv, int bs, int k,
-                  double omega, const int32_t* prow, const BSR& P, hipStream_t s) {
+                  double omega, const int32_t* prow, const BSR& P, bool use_lds, hipStream_t s) {
     (void)prow;
     const dim3 g((unsigned)A.nbr), b(64);
 #define TM_PN(BS, K)                                                                                     \
     hipLaunchKernelGGL((k_p_numeric<BS, K>), g, b, 0, s, A.rp, A.ci, A.v64, agg, T, dinv, (int64_t)A.nbr, omega, \
-                       P.rp, P.ci, P.v64)
+                       P.rp, P.ci, P.v64, use_lds ? PN_SLOTS : 1)
     if (bs == 3 && k == 6) TM_PN(3, 6);
     else if (bs == 6 && k == 6) TM_PN(6, 6);
     else if (bs == 2 && k == 3) TM_PN(2, 3);
@@ -893,18 +894,19 @@ __global__ void k_max_row(const int32_t* __restrict__ rp, int64_t n, int32_t* __
 // LDS of the row form: the longest output row's sums (+ its columns), at most
 // 48 KB; longer rows take the block form
 template <int XR, int XC, int YC>
-static void prod_launch(const BSR& X, const BSR& Y, BSR& C, int32_t mmax, hipStream_t s) {
+static void prod_launch(const BSR& X, const BSR& Y, BSR& C, int32_t mmax, bool use_lds, hipStream_t s) {
     constexpr int NE = XR * YC, NS = NE + 1;
     constexpr size_t CAP = 48 * 1024;
     const size_t block_form = (size_t)64 * NE * sizeof(double) + 64 * sizeof(int);
-    int mcap = (int)std::min<int64_t>(mmax, (int64_t)(CAP / (NS * sizeof(double) + sizeof(int32_t))));
+    int mcap = use_lds ? (int)std::min<int64_t>(mmax, (int64_t)(CAP / (NS * sizeof(double) + sizeof(int32_t)))) : 0;
     size_t lds = (size_t)mcap * (NS * sizeof(double) + sizeof(int32_t));
     lds = std::max(lds, block_form);
     hipLaunchKernelGGL((k_prod_rows<XR, XC, YC>), dim3((unsigned)C.nbr), dim3(64), lds, s, X.rp, X.ci, X.v64, Y.rp,
                        Y.ci, Y.v64, C.rp, C.ci, (int64_t)C.nbr, mcap, C.v64);
 }
 
-void sa_prod_numeric(const BSR& X, const BSR& Y, const int32_t* crow, BSR& C, int32_t* dtmp, hipStream_t s) {
+void sa_prod_numeric(const BSR& X, const BSR& Y, const int32_t* crow, BSR& C, int32_t* dtmp, bool use_lds,
+                     hipStream_t s) {
     (void)crow;
     if (C.nbr < 1) return;
     TM_HIP(hipMemsetAsync(dtmp, 0, sizeof(int32_t), s));
@@ -914,12 +916,12 @@ void sa_prod_numeric(const BSR& X, const BSR& Y, const int32_t* crow, BSR& C, in
     TM_HIP(hipStreamSynchronize(s));
     const int xr = X.br, xc = X.bc, yc = Y.bc;
     if (Y.br != xc) fail(TM_ERR_ARG, "block shapes of a product do not match");
-    if (xr == 3 && xc == 3 && yc == 6) prod_launch<3, 3, 6>(X, Y, C, mmax, s);
-    else if (xr == 6 && xc == 3 && yc == 6) prod_launch<6, 3, 6>(X, Y, C, mmax, s);
-    else if (xr == 6 && xc == 6 && yc == 6) prod_launch<6, 6, 6>(X, Y, C, mmax, s);
-    else if (xr == 2 && xc == 2 && yc == 3) prod_launch<2, 2, 3>(X, Y, C, mmax, s);
-    else if (xr == 3 && xc == 2 && yc == 3) prod_launch<3, 2, 3>(X, Y, C, mmax, s);
-    else if (xr == 3 && xc == 3 && yc == 3) prod_launch<3, 3, 3>(X, Y, C, mmax, s);
+    if (xr == 3 && xc == 3 && yc == 6) prod_launch<3, 3, 6>(X, Y, C, mmax, use_lds, s);
+    else if (xr == 6 && xc == 3 && yc == 6) prod_launch<6, 3, 6>(X, Y, C, mmax, use_lds, s);
+    else if (xr == 6 && xc == 6 && yc == 6) prod_launch<6, 6, 6>(X, Y, C, mmax, use_lds, s);
+    else if (xr == 2 && xc == 2 && yc == 3) prod_launch<2, 2, 3>(X, Y, C, mmax, use_lds, s);
+    else if (xr == 3 && xc == 2 && yc == 3) prod_launch<3, 2, 3>(X, Y, C, mmax, use_lds, s);
+    else if (xr == 3 && xc == 3 && yc == 3) prod_launch<3, 3, 3>(X, Y, C, mmax, use_lds, s);
     else fail(TM_ERR_ARG, "aggregation block shape not supported");
 }
 void sa_fix_diag(BSR& A, int bs, hipStream_t s) {

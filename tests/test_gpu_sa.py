@@ -159,3 +159,29 @@ def test_hybrid_updates_reuse_memory_and_match_fresh_setup():
     print(f"  bytes held after each update: {held}", flush=True)
     assert held[2] == held[1] and held[3] == held[2]
     G.close()
+
+
+@pytest.mark.parametrize("kind,nel,ngeo,maxc", [CASES[1], CASES[2], CASES[5]])
+def test_setup_without_lds_staging_is_bitwise_equal(kind, nel, ngeo, maxc):
+    """Option sa_lds = 1 takes the paths that long rows and large aggregates
+    take (every Galerkin product block by block, Gram-Schmidt in device
+    memory, one prolongator block per group): every aggregation level's
+    prolongator and operator, and the solve, are bitwise those of the default."""
+    from paper_2001_01655_amd import Hierarchy
+    print(f"sa without lds {kind} {nel}", flush=True)
+    p = _problem(kind, nel)
+    Gs = [Hierarchy(p.nel, p.rho, p.fixed, p=p.p, E0=p.E0, Emin=p.Emin, nu=p.nu, n_geometric=ngeo,
+                    max_coarse=maxc, sa_lds=m) for m in (0, 1)]
+    L = Gs[0].num_levels()
+    assert Gs[1].num_levels() == L
+    for l in range(ngeo - 1, L - 1):
+        for a, b in zip(Gs[0].export_prolongator(l), Gs[1].export_prolongator(l)):
+            assert np.array_equal(a, b), f"prolongator level {l}"
+    for l in range(ngeo, L):
+        for a, b in zip(Gs[0].export_csr(l), Gs[1].export_csr(l)):
+            assert np.array_equal(a, b), f"operator level {l}"
+    f = torch.tensor(p.loads[0], device="cuda")
+    r0, r1 = (G.solve(f, rtol=1e-8) for G in Gs)
+    assert r0.iters == r1.iters and torch.equal(r0.u, r1.u)
+    for G in Gs:
+        G.close()
