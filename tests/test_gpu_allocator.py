@@ -63,3 +63,27 @@ def test_plan_bytes_cover_hierarchy_and_solve_state(smoother, n_rhs):
     print(f"  plan {plan} used {used} (hierarchy {G.device_bytes()})", flush=True)
     assert plan >= used
     G.close()
+
+
+@pytest.mark.parametrize("kind,nel,ngeo", [("bridge", (32, 16, 16), 2), ("bridge", (32, 16, 16), 3),
+                                           ("small", (64, 32), 2), ("small", (24, 16, 16), 2)])
+def test_plan_bytes_cover_hybrid_hierarchies(kind, nel, ngeo):
+    """Aggregation levels have data-dependent sizes: the plan's allowance for
+    them (a dense coarsest level of up to 8 max_coarse dofs) covers what the
+    hierarchy, its aggregation arenas and a two-load-case solve take."""
+    from paper_2001_01655_amd import Hierarchy, _lib as L
+    print(f"plan bytes hybrid {kind} {nel} ngeo={ngeo}", flush=True)
+    p = synth.bridge_3d(nel=nel) if kind == "bridge" else synth.small_case(len(nel), nel, seed=62, n_rhs=2)
+    F = torch.tensor(np.vstack([p.loads[0], p.loads[0]]), device="cuda")
+    U = torch.empty_like(F)
+    torch.cuda.synchronize()
+    base = torch.cuda.memory_allocated()
+    G = Hierarchy(p.nel, p.rho, p.fixed, p=p.p, E0=p.E0, Emin=p.Emin, nu=p.nu, n_geometric=ngeo, max_coarse=300,
+                  smoother=2, nu_pre=2, nu_post=2, cheb_warm_steps=4, allocator="torch")
+    G.solve(F, rtol=1e-6, out=U)
+    torch.cuda.synchronize()
+    used = torch.cuda.memory_allocated() - base
+    plan = L.tm_plan_bytes(G.mesh, G.opts, 2)
+    print(f"  plan {plan} used {used}", flush=True)
+    assert plan >= used
+    G.close()
