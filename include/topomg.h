@@ -177,7 +177,9 @@ tm_status tm_update_density(tm_hierarchy* h, const double* rho_dev, void* stream
  * the last iterate); TM_ERR_ARG if a load or start vector holds an infinity or
  * a NaN (found on the device at the first step); TM_ERR_BREAKDOWN if p^T K~ p
  * <= 0 or, for PCG, z^T r <= 0 (a V-cycle that is not positive definite, e.g.
- * an over-relaxed smoother).  tm_last_error() names the right-hand side. */
+ * an over-relaxed smoother).  tm_last_error() names the right-hand side.
+ * The right-hand sides share every launch (several load cases, Sec. 2 and
+ * Sec. 4.2); each one's result is bitwise that of its own solve. */
 tm_status tm_solve(tm_hierarchy* h, int32_t n_rhs, const double* f_dev, double rtol,
                    int32_t use_u0, double* u_dev, int32_t* iters, double* compliance,
                    double* relres, void* stream);
