@@ -26,6 +26,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 WORKLOADS = {
+    # the MBB half-beam of the classic setting: block Jacobi w = 0.6, 2/2 sweeps
+    "mbb2d": dict(cfg="mbb_random", levels=3, opts=dict(omega=0.6), smoother="jacobi", sweeps=2,
+                  desc="2D MBB half-beam 60x20 Q4, 2,562 dofs, U(0,1) densities"),
     "cantilever3d": dict(cfg="cantilever3d", levels=6, opts={},
                          desc="3D cantilever 192x96x96 Hex8, 5,447,811 dofs"),
     "cantilever2d": dict(cfg="cantilever2d", levels=7, opts=dict(max_iters=20000),
@@ -41,13 +44,14 @@ def workload_label(wl, args, levels, coarsest):
     s = wl["desc"]
     if wl["levels"] is not None:
         s += f", {levels}-level GMG (coarsest {coarsest} dofs)"
-    sm = "block Jacobi w=0.5" if args.smoother == "jacobi" else f"Chebyshev on [{args.cheb_lower:g}, 1.1] x lambda"
+    w = wl["opts"].get("omega", 0.5)
+    sm = f"block Jacobi w={w:g}" if args.smoother == "jacobi" else f"Chebyshev on [{args.cheb_lower:g}, 1.1] x lambda"
     return s + f", {sm} {args.sweeps}/{args.sweeps}, rtol 1e-8"
 
 
 # MI355X published peaks (dense): HBM3E 8 TB/s; vector FP64 78.6 TFLOP/s; vector
-# FP32 157.3 TFLOP/s (reached only with packed FP32 instructions, which these
-# kernels are compiled without)
+# FP32 157.3 TFLOP/s (the kernels are compiled without packed FP32 instructions;
+# plain FP32 FMAs issue at up to about 85% of that rate)
 PEAK = {"hbm_GBs": 8000.0, "fp64_TFs": 78.6, "fp32_TFs": 157.3}
 KERNEL_SOURCES = {0: ["kernels_fine.hip", "tm_device.h"], 1: ["kernels_fine.hip", "tm_device.h"],
                   2: ["kernels_coarse.hip", "tm_device.h"]}
@@ -77,8 +81,9 @@ def parse():
     ap.add_argument("--served-warm-steps", type=int, default=4,
                     help="power steps of a design update's Chebyshev estimate, from the previous vector (0: 12 cold)")
     ap.add_argument("--levels", type=int, default=None, help="multigrid levels (default: the workload's)")
-    ap.add_argument("--smoother", default="chebyshev", choices=sorted(SMOOTHERS))
-    ap.add_argument("--sweeps", type=int, default=2, help="pre- and post-smoothing sweeps")
+    ap.add_argument("--smoother", default=None, choices=sorted(SMOOTHERS),
+                    help="default: the workload's (chebyshev, block Jacobi for the MBB half-beam)")
+    ap.add_argument("--sweeps", type=int, default=None, help="pre- and post-smoothing sweeps (default: the workload's, 2)")
     ap.add_argument("--cheb-lower", type=float, default=0.1,
                     help="Chebyshev interval [cheb_lower, 1.1] x the estimated largest eigenvalue of D^-1 A")
     ap.add_argument("--fine-mfma", type=int, default=0, choices=[0, 1],
@@ -89,7 +94,13 @@ def parse():
                     help="the varying-spaced grid comparison (GMG / hybrids) of the 520x520 recipe")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="copy 256 MiB device-to-device first (counter calibration under rocprofv3 --pmc)")
-    return ap.parse_args()
+    args = ap.parse_args()
+    wl = WORKLOADS[args.workload]
+    if args.smoother is None:
+        args.smoother = wl.get("smoother", "chebyshev")
+    if args.sweeps is None:
+        args.sweeps = wl.get("sweeps", 2)
+    return args
 
 
 def progress(msg: str) -> None:
@@ -641,10 +652,12 @@ def main():
     def build(vfp, outer):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        H = Hierarchy(p.nel, p.rho, p.fixed, p=p.p, E0=p.E0, Emin=p.Emin, nu=p.nu, omega=0.5,
+        kw = dict(omega=0.5)
+        kw.update(opts)
+        H = Hierarchy(p.nel, p.rho, p.fixed, p=p.p, E0=p.E0, Emin=p.Emin, nu=p.nu,
                       nu_pre=args.sweeps, nu_post=args.sweeps, smoother=SMOOTHERS[args.smoother],
                       cheb_lower=args.cheb_lower, vcycle_fp=vfp,
-                      outer=outer, fine_mfma=args.fine_mfma, **opts)
+                      outer=outer, fine_mfma=args.fine_mfma, **kw)
         torch.cuda.synchronize()
         return H, time.perf_counter() - t0
 

@@ -384,6 +384,7 @@ def column_2d(nel=(256, 1024), seed: int = 6, flange: float = 0.125, band: float
 CONFIGS = {
     "mbb_uniform": lambda: mbb_2d(True),
     "mbb_random": lambda: mbb_2d(False),
+    "mbb_random": lambda: mbb_2d(False),
     "cantilever2d": cantilever_2d,
     "cantilever3d": cantilever_3d,
     "bridge3d": bridge_3d,
