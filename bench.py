@@ -373,6 +373,7 @@ def served_leg(n_req: int, n_designs: int, smoother: str = "chebyshev", sweeps: 
             "designs_per_request": n_designs, "solves": res["solves"], "all_converged": ok,
             "mean_iters": round(float(np.mean(iters)), 2) if iters else None,
             "max_slots": 8, "chunk": 4, "workers": 4, "latency": "request arrival to its last solve",
+            "grouping": "idle solves advance together once no chunk of another solve is running",
             "launches": "right-hand sides of requests with the same level structure share each launch",
             "sizes": "2D 128x64, 2D 512x256, 3D 48^3, 3D 96x48x48; 1-4 load cases; rtol 1e-6",
             "smoothing": f"{smoother} {sweeps}/{sweeps}", "cheb_warm_steps": warm}

@@ -310,7 +310,11 @@ tm_status tm_eigs(tm_hierarchy* h, const tm_eig_options* o, int32_t n_init, cons
  *          state stay ordered.  Every right-hand side computes exactly what it
  *          computes alone.  A state may appear only once in the list.
  * end:     waits, writes the outputs of tm_solve and releases the state (its
- *          device buffers stay with the hierarchy for the next begin).
+ *          device buffers stay with the hierarchy for the next begin).  Each
+ *          begin, advance and batch_iterate also computes the outputs (true
+ *          residual, compliance) of the right-hand sides that stopped in it, as
+ *          the same kernels as end's; after a poll that reported done = 1, end
+ *          therefore launches and waits for nothing.
  * The right-hand sides of one state always share launches (also in tm_solve). */
 tm_status tm_solve_begin(tm_hierarchy* h, int32_t n_rhs, const double* f_dev, double rtol,
                          int32_t use_u0, double* u_dev, void* stream, tm_solve_state** st);

@@ -434,6 +434,7 @@ static void cheb_interval(tm_hierarchy* h, int l, hipStream_t s, bool warm);
 // SPD blocks, coarsest factor) are read before returning; without, nothing
 // waits for the device and the next solve reads them (flags_pending).
 static void numeric_setup(tm_hierarchy* h, const double* rho, hipStream_t s, bool sync = true) {
+    ++h->update_seq;
     TM_HIP(hipMemsetAsync(h->flags, 0, sizeof(int), s));
     Level& F = h->lv[0];
     launch_simp(rho, h->n_el, h->mat.p, h->mat.E0, h->mat.Emin, F.E64, F.E32, h->rho64, h->flags, s);
@@ -852,12 +853,14 @@ static tm_solve_state* new_state(tm_hierarchy* h, int nrhs) {
         st->sc = dalloc<KScal>(h, st->allocs, st->bytes, nrhs);
         TM_HIP(hipMemset(st->sc, 0, sizeof(KScal) * nrhs));
         TM_HIP(hipHostMalloc((void**)&st->sc_host, sizeof(KScal) * nrhs, hipHostMallocDefault));
+        TM_HIP(hipHostMalloc((void**)&st->flags_host, sizeof(int), hipHostMallocDefault));
         TM_HIP(hipEventCreateWithFlags(&st->ev, hipEventDisableTiming));
         TM_HIP(hipEventCreateWithFlags(&st->order, hipEventDisableTiming));
     } catch (...) {
         free_list(st->h, st->allocs);
         for (Lane* ln : st->lanes) delete ln;
         if (st->sc_host) (void)hipHostFree(st->sc_host);
+        if (st->flags_host) (void)hipHostFree(st->flags_host);
         if (st->order) (void)hipEventDestroy(st->order);
         if (st->ev) (void)hipEventDestroy(st->ev);
         delete st;
@@ -898,6 +901,7 @@ static void delete_state(tm_solve_state* st) {
     free_list(st->h, st->allocs);
     for (Lane* ln : st->lanes) delete ln;
     if (st->sc_host) (void)hipHostFree(st->sc_host);
+    if (st->flags_host) (void)hipHostFree(st->flags_host);
     if (st->ev) (void)hipEventDestroy(st->ev);
     if (st->order) (void)hipEventDestroy(st->order);
     delete st;
@@ -983,10 +987,16 @@ static void enqueue_iteration_b(const std::vector<LaneIO>& lanes, hipStream_t s)
     launch_update_p_b(io.data(), n, mixed, s);
 }
 
-// the pinned mirror of the scalars and the completion event of a state, after
-// its work enqueued on stream s
+// the pinned mirror of the scalars (and of the device checks of an update
+// that did not wait for them) and the completion event of a state, after its
+// work enqueued on stream s
 static void state_sync_point(tm_solve_state* st, hipStream_t s) {
     TM_HIP(hipMemcpyAsync(st->sc_host, st->sc, sizeof(KScal) * st->nrhs, hipMemcpyDeviceToHost, s));
+    st->flags_copied = st->h->flags_pending;
+    if (st->flags_copied) {
+        TM_HIP(hipMemcpyAsync(st->flags_host, st->h->flags, sizeof(int), hipMemcpyDeviceToHost, s));
+        st->flags_seq = st->h->update_seq;
+    }
     TM_HIP(hipEventRecord(st->ev, s));
     if (s != st->s) TM_HIP(hipStreamWaitEvent(st->s, st->ev, 0));
     st->pending = true;
@@ -996,6 +1006,7 @@ static void enqueue_advance(tm_solve_state* st, int k_iters) {
     std::vector<LaneIO> io;
     state_lanes(st, io);
     for (int it = 0; it < k_iters; ++it) enqueue_iteration_b(io, st->s);
+    launch_final_residual_b(io.data(), (int)io.size(), true, st->s);
     state_sync_point(st, st->s);
 }
 
@@ -1070,13 +1081,24 @@ static void run_to_completion(tm_solve_state* st) {
 static tm_status finish_state(tm_solve_state* st, int32_t* iters, double* compliance, double* relres) {
     tm_hierarchy* h = st->h;
     wait_state(st);
-    const int64_t n = h->n_dof;
+    // the last batch of iterations left the outputs of every right-hand side
+    // (and the device checks of the last update, if pending) in the host
+    // mirror: nothing to launch or wait for
+    bool have = true;
     for (int k = 0; k < st->nrhs; ++k)
-        launch_final_residual(h, *st->lanes[k], st->sc + k, st->u + (size_t)k * n, st->s);
-    TM_HIP(hipMemcpyAsync(st->sc_host, st->sc, sizeof(KScal) * st->nrhs, hipMemcpyDeviceToHost, st->s));
+        if (!st->sc_host[k].fin) have = false;
+    if (h->flags_pending && !(st->flags_copied && st->flags_seq == h->update_seq)) have = false;
     int fl = 0;
-    if (h->flags_pending) TM_HIP(hipMemcpyAsync(&fl, h->flags, sizeof(int), hipMemcpyDeviceToHost, st->s));
-    TM_HIP(hipStreamSynchronize(st->s));
+    if (have) {
+        if (h->flags_pending) fl = *st->flags_host;
+    } else {
+        std::vector<LaneIO> io;
+        state_lanes(st, io);
+        launch_final_residual_b(io.data(), (int)io.size(), false, st->s);
+        TM_HIP(hipMemcpyAsync(st->sc_host, st->sc, sizeof(KScal) * st->nrhs, hipMemcpyDeviceToHost, st->s));
+        if (h->flags_pending) TM_HIP(hipMemcpyAsync(&fl, h->flags, sizeof(int), hipMemcpyDeviceToHost, st->s));
+        TM_HIP(hipStreamSynchronize(st->s));
+    }
     if (h->flags_pending) {
         // device checks of the last density update, which did not wait for them
         h->flags_pending = false;
@@ -1821,11 +1843,14 @@ static tm_status begin_impl(tm_hierarchy* h, int32_t n_rhs, const double* f_dev,
         try {
             if (st->ev) TM_HIP(hipEventSynchronize(st->ev));   // a reused state may still be draining
             enqueue_begin(st, f_dev, use_u0);
-            // the host mirror must describe this solve before the first poll
+            // outputs of right-hand sides that need no iteration (start already
+            // within the tolerance); the host mirror must describe this solve
+            // before the first poll
+            std::vector<LaneIO> io;
+            state_lanes(st, io);
+            launch_final_residual_b(io.data(), (int)io.size(), true, st->s);
             std::memset(st->sc_host, 0, sizeof(KScal) * st->nrhs);
-            TM_HIP(hipMemcpyAsync(st->sc_host, st->sc, sizeof(KScal) * st->nrhs, hipMemcpyDeviceToHost, st->s));
-            TM_HIP(hipEventRecord(st->ev, st->s));
-            st->pending = true;
+            state_sync_point(st, st->s);
         } catch (...) {
             if (!cached) delete_state(st);
             throw;
@@ -1896,6 +1921,8 @@ tm_status tm_batch_iterate(int32_t n, tm_solve_state* const* sts, int32_t k_iter
         }
         for (int it = 0; it < k_iters; ++it)
             for (auto& g : groups) enqueue_iteration_b(g, bs);
+        // outputs of the lanes that stopped in this batch
+        for (auto& g : groups) launch_final_residual_b(g.data(), (int)g.size(), true, bs);
         for (int i = 0; i < n; ++i) state_sync_point(sts[i], bs);
     });
 }

@@ -213,6 +213,8 @@ __global__ __launch_bounds__(FB) void k_init_scalars(KScal* sc, const double* pa
         sc->iter = 0;
         sc->max_iters = max_iters;
         sc->outer = outer;
+        sc->fin = 0;
+        sc->skipfin = 0;
         sc->status = TM_OK;
         sc->done = (rr <= sc->rr_stop) ? 1 : 0;
         if (!(ff - ff == 0.0) || !(rr - rr == 0.0)) {
@@ -465,34 +467,96 @@ void launch_update_p(const tm_hierarchy* h, Lane& ln, KScal* sc, bool mixed, hip
 }
 
 // ---------------------------------------------------------------- outputs
-// true residual ||f - K~u||^2 and compliance f^T u (slots pq / zq once the loop is over)
-__global__ void k_final_dots(const double* __restrict__ f, const double* __restrict__ t,
-                             const double* __restrict__ u, int64_t n, double* part) {
+// true residual ||f - K~u||^2 and compliance f^T u (slots pq / zq once the loop
+// is over; fin = 1 marks them).  Gated launches (the end of every batch of
+// iterations) compute them only for the lanes that stopped in that batch and
+// leave the others as empty launches, so that ending a solve needs no more
+// device work.  The gate reads done / fin into skipfin; ungated launches clear
+// skipfin themselves.
+template <int NB>
+__global__ void k_final_gate(const Pack<FinA, NB> pk, int gated) {
+    KScal* sc = lane_of(pk).sc;
+    sc->skipfin = gated ? (sc->done && !sc->fin ? 0 : 1) : 0;
+}
+
+struct FdA {
+    const double* f;
+    const double* t;
+    const double* u;
+    double* part;
+    const int* skip;
+};
+
+template <int NB>
+__global__ void k_final_dots(const Pack<FdA, NB> pk, int64_t n) {
+    const FdA& a = lane_of(pk);
+    if (*a.skip) return;
+    const double* __restrict__ f = a.f;
+    const double* __restrict__ t = a.t;
+    const double* __restrict__ u = a.u;
     double v[2] = {0.0, 0.0};
     for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += (int64_t)gridDim.x * WG) {
         v[0] += t[i] * t[i];
         v[1] += f[i] * u[i];
     }
-    block_reduce_store<2>(v, part);
+    block_reduce_store<2>(v, a.part);
 }
 
-__global__ __launch_bounds__(FB) void k_final_scalars(KScal* sc, const double* part, int nparts) {
+template <int NB>
+__global__ __launch_bounds__(FB) void k_final_scalars(const Pack<FinA, NB> pk, int nparts) {
+    KScal* sc = lane_of(pk).sc;
+    if (sc->skipfin) return;
     double t2[2];
-    fin_sums<2>(part, nparts, t2);
+    fin_sums<2>(lane_of(pk).part, nparts, t2);
     const double tt = t2[0], fu = t2[1];
     if (threadIdx.x == 0) {
         sc->pq = tt;
         sc->zq = fu;
+        sc->fin = 1;
+    }
+}
+
+template <int NB>
+static void final_launch(const LaneIO* L, int m, bool gated, hipStream_t s) {
+    const tm_hierarchy* h = L[0].h;
+    const int64_t n = h->n_dof;
+    const int nb = krylov_blocks(n);
+    Pack<FinA, NB> pf{};
+    Pack<FdA, NB> pd{};
+    LaneIO io[NB];
+    for (int q = 0; q < m; ++q) {
+        Lane& ln = *L[q].ln;
+        pf.a[q] = FinA{L[q].sc, ln.part};
+        pd.a[q] = FdA{ln.f, ln.q, L[q].u, ln.part, &L[q].sc->skipfin};
+        io[q] = LaneIO{};
+        io[q].h = L[q].h;
+        io[q].x = L[q].u;
+        io[q].b = ln.f;
+        io[q].y = ln.q;
+        io[q].done = &L[q].sc->skipfin;
+    }
+    hipLaunchKernelGGL((k_final_gate<NB>), dim3(1, m), dim3(1), 0, s, pf, gated ? 1 : 0);
+    launch_fine_op_b<double>(OP_RESID, false, io, m, 0.0, 0.0, 0.0, s);
+    hipLaunchKernelGGL((k_final_dots<NB>), dim3(nb, m), dim3(WG), 0, s, pd, n);
+    hipLaunchKernelGGL((k_final_scalars<NB>), dim3(1, m), dim3(FB), 0, s, pf, nb);
+}
+
+void launch_final_residual_b(const LaneIO* L, int n, bool gated, hipStream_t s) {
+    for (int q0 = 0; q0 < n; q0 += MAXB) {
+        const int m = std::min(MAXB, n - q0);
+        if (m == 1) final_launch<1>(L + q0, 1, gated, s);
+        else final_launch<MAXB>(L + q0, m, gated, s);
     }
 }
 
 void launch_final_residual(const tm_hierarchy* h, Lane& ln, KScal* sc, const double* u,
                            hipStream_t s) {
-    const int64_t n = h->n_dof;
-    launch_fine_op<double>(h, OP_RESID, false, u, ln.f, ln.q, 0.0, nullptr, nullptr, s);
-    const int nb = krylov_blocks(n);
-    hipLaunchKernelGGL(k_final_dots, dim3(nb), dim3(WG), 0, s, ln.f, ln.q, u, n, ln.part);
-    hipLaunchKernelGGL(k_final_scalars, dim3(1), dim3(FB), 0, s, sc, ln.part, nb);
+    LaneIO l{};
+    l.h = h;
+    l.ln = &ln;
+    l.sc = sc;
+    l.u = const_cast<double*>(u);
+    launch_final_residual_b(&l, 1, false, s);
 }
 
 // ---------------------------------------------------------------- eigenvalue estimate

@@ -201,7 +201,9 @@ struct KScal {
     double rr_last;         // ||r||^2 after the last completed iteration
     int32_t iter, done, status, max_iters;
     int32_t outer;          // TM_OUTER_*
-    int32_t pad[3];
+    int32_t fin;            // pq / zq hold the true residual and compliance of the stopped iterate
+    int32_t skipfin;        // gate of the in-batch output kernels (0: compute them for this lane)
+    int32_t pad;
 };
 
 // ----------------------------------------------------------------- structures
@@ -323,6 +325,7 @@ struct tm_hierarchy {
     bool sa = false;               // smoothed-aggregation levels below the geometric ones
     bool demote = false;           // a solve exceeded adapt_iters: drop a geometric level at the next update
     bool flags_pending = false;    // an update ran without waiting: its device checks are read by the next solve
+    uint64_t update_seq = 0;       // numeric setups so far (which update a copy of the checks belongs to)
     double* dense_a = nullptr;     // coarsest operator, dense (setup scratch kept for updates)
     size_t dense_cap = 0;
     double* chol_ls = nullptr;     // blocked Cholesky panel scratch
@@ -376,6 +379,9 @@ struct tm_solve_state {
     tmi::KScal* sc = nullptr;      // device scalars [nrhs]
     tmi::KScal* sc_host = nullptr; // pinned mirror
     hipEvent_t ev = nullptr;       // the scalars' host copy has arrived
+    int* flags_host = nullptr;     // pinned copy of the hierarchy's device checks, taken with the scalars
+    uint64_t flags_seq = 0;        // update_seq of that copy
+    bool flags_copied = false;
     hipEvent_t order = nullptr;    // marks the work queued on s (start of a batch on another stream)
     bool ended = false, pending = false;
     bool owned_by_h = false;
@@ -532,6 +538,9 @@ void launch_finalize(KScal* sc, const double* part, int nparts, int what, hipStr
 void launch_update_p(const tm_hierarchy* h, Lane& ln, KScal* sc, bool mixed, hipStream_t s);
 void launch_final_residual(const tm_hierarchy* h, Lane& ln, KScal* sc, const double* u,
                            hipStream_t s);
+// the same for lanes L[0..n) (h, ln, sc, u set); gated: only the lanes that
+// have stopped and have no outputs yet (sc->fin == 0), the others stay as they are
+void launch_final_residual_b(const LaneIO* L, int n, bool gated, hipStream_t s);
 void launch_cast(const double* a, float* b, int64_t n, hipStream_t s);
 void launch_cast_back(const float* a, double* b, int64_t n, hipStream_t s);
 void launch_fill(void* p, int64_t n_bytes, hipStream_t s);

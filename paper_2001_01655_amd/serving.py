@@ -101,11 +101,21 @@ class Server:
     next solve, and the release of its hierarchy run on a pool of that many
     threads, so that a slow update (aggregation levels are rebuilt with
     host-side waits) never holds up the iterations of the other requests; the
-    loop only collects what has finished.  workers = 0 does everything inline."""
+    loop only collects what has finished.  workers = 0 does everything inline.
+
+    gather: while chunks of other solves are still running, idle solves wait
+    until they number at least gather times the running ones, so that they
+    advance in fewer, larger grouped calls (the host cost of a call hardly
+    depends on its size); with nothing running they advance at once.  0
+    advances every idle solve at once; the default (infinite) advances all
+    idle solves together once no chunk is running: the calls share one stream,
+    so a solve's next chunk could not start before the running ones anyway."""
 
     def __init__(self, engine, hbm_budget: int, max_slots: int = 8, chunk: int = 4,
-                 rtol: float = 1e-6, keep_solutions: bool = False, workers: int = 0):
+                 rtol: float = 1e-6, keep_solutions: bool = False, workers: int = 0,
+                 gather: float = float("inf")):
         self.workers = int(workers)
+        self.gather = float(gather)
         self.engine = engine
         self.budget = int(hbm_budget)
         self.max_slots = int(max_slots)
@@ -184,6 +194,7 @@ class Server:
                 self.queue_depth.append(sum(1 for r in pending if r.arrival <= now))
                 # collect prepared solves, poll running ones without blocking
                 idle = []
+                running = 0
                 for s in list(active):
                     if s.prep is not None:
                         if not s.prep.done():
@@ -212,7 +223,9 @@ class Server:
                             active.remove(s)
                     elif st == 0:                                 # chunk finished, keep going
                         idle.append(s)
-                if idle:
+                    else:
+                        running += 1
+                if idle and (running == 0 or len(idle) >= self.gather * running):
                     self.engine.batch_advance([s.state for s in idle], self.chunk)
                 elif active or releasing:
                     time.sleep(5e-5)

@@ -104,3 +104,55 @@ def test_batch_iterate_groups_equal_alone():
         assert torch.equal(r.u, a.u)
     for H in Hs:
         H.close()
+
+
+def _outputs_match_definition(H, F, r):
+    """compliance f^T u and relres ||f - K~u|| / ||f|| of every load case, K~u
+    from tm_apply (FP64, a different summation order than the solve's own)."""
+    for k in range(F.shape[0]):
+        f, u = F[k].double(), r.u[k].double()
+        c = float(torch.dot(f, u))
+        rel = float(torch.linalg.norm(f - H.apply(0, u)) / torch.linalg.norm(f))
+        assert abs(r.compliance[k] - c) <= 1e-12 * abs(c)
+        assert abs(r.relres[k] - rel) <= 1e-3 * rel + 1e-13
+
+
+def test_end_outputs_left_by_the_last_batch():
+    """The outputs that a batch leaves for the load cases that stopped in it
+    (and that begin leaves for a start already within the tolerance) are the
+    true residual and compliance of the returned displacements; a state ended
+    before it stopped computes them at end with the same kernels."""
+    from paper_2001_01655_amd import Hierarchy
+    from paper_2001_01655_amd.solver import tm_batch_iterate
+    print("end outputs", flush=True)
+    p = synth.small_case(3, (12, 8, 8), seed=75, n_rhs=2)
+    H = Hierarchy(p.nel, p.rho, p.fixed, n_levels=3)
+    F = torch.tensor(p.loads, device="cuda")
+    stream = torch.cuda.Stream()
+    st = H.begin(F, 1e-8)
+    for _ in range(200):
+        if st.poll() == 1:
+            break
+        tm_batch_iterate([st], 2, stream)
+        torch.cuda.synchronize()
+    r = st.end()
+    assert r.converged
+    _outputs_match_definition(H, F, r)
+    a = H.solve(F, rtol=1e-8)
+    assert r.iters == a.iters and r.compliance == a.compliance and r.relres == a.relres
+    # start within the tolerance: no iteration, outputs from begin
+    st = H.begin(F, 1e-6, u0=r.u)
+    torch.cuda.synchronize()
+    assert st.poll() == 1
+    w = st.end()
+    assert w.converged and w.iters == [0, 0]
+    _outputs_match_definition(H, F, w)
+    # ended after one iteration, before stopping: outputs computed by end
+    st = H.begin(F, 1e-12)
+    tm_batch_iterate([st], 1, stream)
+    torch.cuda.synchronize()
+    assert st.poll() == 0
+    e = st.end()
+    assert e.iters == [1, 1]
+    _outputs_match_definition(H, F, e)
+    H.close()

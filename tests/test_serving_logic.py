@@ -136,3 +136,47 @@ def test_oversized_request_rejected():
     eng = FakeEngine()
     with pytest.raises(ValueError):
         Server(eng, hbm_budget=10, max_slots=2).run(_reqs(1))
+
+
+class LaggingEngine(FakeEngine):
+    """A chunk stays in flight for a few polls (poll returns -1 meanwhile);
+    records how many chunks were still running at every grouped call."""
+
+    def __init__(self, lag):
+        super().__init__()
+        self.lag = lag
+        self.running = set()
+        self.calls = []
+
+    def poll(self, st):
+        if st.inflight:
+            st.inflight -= 1
+            if st.inflight:
+                return -1
+            self.running.discard(id(st))
+        return 1 if st.left <= 0 else 0
+
+    def batch_advance(self, states, k):
+        self.calls.append((len(states), len(self.running)))
+        for st in states:
+            st.left -= k
+            st.inflight = 1 + self.lag
+            st.advanced += k
+            self.running.add(id(st))
+
+
+@pytest.mark.parametrize("gather", [0.0, 1.0, float("inf")])
+def test_gathering_idle_solves(gather):
+    """With gather g, idle solves advance while others run only when they are
+    at least g times as many; the default (infinite) advances only when nothing
+    runs.  Results never depend on it."""
+    reqs = _reqs(6, designs=3)
+    eng = LaggingEngine(lag=3)
+    out = Server(eng, hbm_budget=10 ** 9, max_slots=6, chunk=2, gather=gather).run(reqs)
+    ref = Server(FakeEngine(), hbm_budget=10 ** 9, max_slots=6, chunk=2).run(reqs)
+    for a, b in zip(out["outcomes"], ref["outcomes"]):
+        assert a.compliance == b.compliance and a.iters == b.iters
+    for n_idle, n_running in eng.calls:
+        assert n_running == 0 or n_idle >= gather * n_running
+    if gather == float("inf"):
+        assert all(r == 0 for _, r in eng.calls)
