@@ -88,6 +88,9 @@ def parse():
                     help="Chebyshev interval [cheb_lower, 1.1] x the estimated largest eigenvalue of D^-1 A")
     ap.add_argument("--fine-mfma", type=int, default=0, choices=[0, 1],
                     help="FP32 fine operator on the matrix cores (1) or vector FMAs (0)")
+    ap.add_argument("--fine-tensor", type=int, default=None,
+                    help="FP32 3D fine operator: 1 tensor-product form, n >= 2 the same with n node "
+                         "planes per workgroup, 0 node gather (default: the library's)")
     ap.add_argument("--adaptive-stream", type=int, default=0,
                     help="designs in the automated-hybrid comparison on the bridge recipe (0: skip)")
     ap.add_argument("--grid-study", action="store_true",
@@ -200,7 +203,10 @@ def algorithmic(cls, H, p, args):
 def roofline_entry(cls, launches, total_ms, H, p, args):
     avg_s = total_ms / 1e3 / max(launches, 1)
     flops, byts = algorithmic(cls, H, p, args)
-    if cls == 2:
+    # the FP32 fine operator in the tensor-product form does about a fifth of
+    # the dense KE arithmetic, far below its HBM time: HBM is its roof
+    tensor = cls == 1 and p.dim == 3 and args.fine_mfma == 0 and args.fine_tensor != 0
+    if cls == 2 or tensor:
         ach = byts / avg_s / 1e9
         e = {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK["hbm_GBs"], "unit": "GB/s",
              "frac": round(ach / PEAK["hbm_GBs"], 4)}
@@ -210,7 +216,8 @@ def roofline_entry(cls, launches, total_ms, H, p, args):
         e = {"bound": "alu", "achieved": round(ach, 2), "peak": peak, "unit": "TFLOP/s",
              "frac": round(ach / peak, 4)}
     e.update({"kernel": {0: "fine operator FP64 (q = K~p, outer loop)",
-                         1: "fine operator FP32 (V-cycle smoothing / residual)",
+                         1: "fine operator FP32 (V-cycle smoothing / residual)" +
+                            (", tensor-product form" if tensor else ""),
                          2: "level-1 stencil operator FP32 (V-cycle)"}[cls],
               "launches": launches, "avg_us": round(avg_s * 1e6, 2),
               "algorithmic_flops_per_launch": flops, "algorithmic_bytes_per_launch": byts,
@@ -655,6 +662,8 @@ def main():
         t0 = time.perf_counter()
         kw = dict(omega=0.5)
         kw.update(opts)
+        if args.fine_tensor is not None:
+            kw["fine_tensor"] = args.fine_tensor
         H = Hierarchy(p.nel, p.rho, p.fixed, p=p.p, E0=p.E0, Emin=p.Emin, nu=p.nu,
                       nu_pre=args.sweeps, nu_post=args.sweeps, smoother=SMOOTHERS[args.smoother],
                       cheb_lower=args.cheb_lower, vcycle_fp=vfp,

@@ -45,7 +45,7 @@ class tm_options(C.Structure):
                 ("fine_mfma", C.c_int32), ("cheb_lower", C.c_double),
                 ("adapt_iters", C.c_int32), ("cheb_warm_steps", C.c_int32),
                 ("stencil_kernel", C.c_int32),
-                ("sa_lds", C.c_int32)]
+                ("sa_lds", C.c_int32), ("fine_tensor", C.c_int32)]
 
 
 class tm_eig_options(C.Structure):

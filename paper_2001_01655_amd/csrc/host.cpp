@@ -259,6 +259,42 @@ static void ke_class_values(const KeClasses<DIM>& T, const std::vector<double>& 
     }
 }
 
+// The 3D KE in the tensor form: C = F KE F^T / 64 per pair of components (F
+// the +-1 sum / difference transform of the eight corner values), kept where
+// the form has a coupling; every other entry of C must vanish, or the fine
+// operator keeps the node gather (sf_ok false).
+static void ke_tensor_coefs(const std::vector<double>& KE, tm_hierarchy* h) {
+    double F[8][8];
+    for (int m = 0; m < 8; ++m)
+        for (int lz = 0; lz < 2; ++lz)
+            for (int ly = 0; ly < 2; ++ly)
+                for (int lx = 0; lx < 2; ++lx) {
+                    const int l[3] = {lx, ly, lz};
+                    double w = 1.0;
+                    for (int k = 0; k < 3; ++k)
+                        if ((m >> k) & 1) w *= l[k] ? 1.0 : -1.0;
+                    F[m][loc3(lx, ly, lz)] = w;
+                }
+    double amax = 0.0;
+    for (double v : KE) amax = std::max(amax, std::fabs(v));
+    bool ok = true;
+    for (int c = 0; c < 3; ++c)
+        for (int d = 0; d < 3; ++d)
+            for (int mo = 0; mo < 8; ++mo)
+                for (int mi = 0; mi < 8; ++mi) {
+                    double v = 0.0;
+                    for (int a = 0; a < 8; ++a)
+                        for (int b2 = 0; b2 < 8; ++b2) v += F[mo][a] * KE[(3 * a + c) * 24 + 3 * b2 + d] * F[mi][b2];
+                    v /= 64.0;
+                    const int sl = SF_SLOTS.s[c][d][mi];
+                    if (sl >= 0 && sf_out_mode(c, d, mi) == mo)
+                        h->sf32.k[sl] = (float)v;
+                    else if (std::fabs(v) > 1e-12 * amax)
+                        ok = false;
+                }
+    h->sf_ok = ok;
+}
+
 // Q[c][a][b]: weight of parent corner b at child c's corner a (coarse shape
 // functions), child c at offsets (c&1, c>>1&1, c>>2&1) inside its parent.
 
@@ -303,6 +339,7 @@ static void check_opts(const tm_options* o) {
     if (o->fine_mfma != 0 && o->fine_mfma != 1) fail(TM_ERR_ARG, "fine_mfma must be 0 or 1");
     if (o->stencil_kernel < 0 || o->stencil_kernel > 2) fail(TM_ERR_ARG, "stencil_kernel must be 0, 1 or 2");
     if (o->sa_lds < 0 || o->sa_lds > 1) fail(TM_ERR_ARG, "sa_lds must be 0 or 1");
+    if (o->fine_tensor < 0 || o->fine_tensor > 4096) fail(TM_ERR_ARG, "fine_tensor must be in 0..4096");
     if (o->n_levels > 0 && o->n_geometric > o->n_levels) fail(TM_ERR_ARG, "n_geometric > n_levels");
 }
 
@@ -1017,7 +1054,7 @@ static std::string shape_key(const tm_hierarchy* h) {
     std::string k;
     auto put = [&](const void* p, size_t n) { k.append((const char*)p, n); };
     const tm_options& o = h->opt;
-    const int ints[] = {h->dim, o.smoother, o.nu_pre, o.nu_post, o.vcycle_fp, o.outer, o.fine_mfma,
+    const int ints[] = {h->dim, o.smoother, o.nu_pre, o.nu_post, o.vcycle_fp, o.outer, o.fine_mfma, o.fine_tensor,
                         (int)h->lv.size()};
     put(ints, sizeof(ints));
     const double dbl[] = {o.omega, o.cheb_lower};
@@ -1546,6 +1583,7 @@ void tm_default_options(tm_options* o) {
     o->cheb_warm_steps = 0;
     o->stencil_kernel = 0;
     o->sa_lds = 0;
+    o->fine_tensor = 1;
 }
 
 const char* tm_status_string(tm_status s) {
@@ -1672,8 +1710,12 @@ tm_status tm_setup(const tm_mesh* mesh, const tm_material* mat, const double* rh
         // constants
         std::vector<double> KE;
         element_stiffness(dim, mat->nu, mesh->h, KE);
-        if (dim == 3) ke_class_values(KE_CLS3, KE, h);
-        else ke_class_values(KE_CLS2, KE, h);
+        if (dim == 3) {
+            ke_class_values(KE_CLS3, KE, h);
+            ke_tensor_coefs(KE, h);
+        } else {
+            ke_class_values(KE_CLS2, KE, h);
+        }
         h->KE64 = halloc<double>(h, KE.size());
         h->rho64 = halloc<double>(h, (size_t)h->n_el);
         // A operand of the matrix-core operator: register q, lane L holds row

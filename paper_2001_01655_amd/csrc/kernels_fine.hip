@@ -438,6 +438,271 @@ __global__ __launch_bounds__(WG) void k_fine3z2(const Pack<OpA<T>, NB> pk, const
     if (live && two) finish_store<T, 3, OP>(nd1, acc1, xo1, m1, fin1, y, omega, dots, ch);
 }
 
+// 3D FP32 in the tensor-product form (SfSlots).  A workgroup owns a tile of
+// SF_NX x SF_NY node columns and a range of node planes; its SF_TX x SF_TY threads
+// are the element columns around the tile (one ring beyond it, so every owned
+// node has all of its elements), each marching up its column one element
+// layer at a time.  Per layer, a thread:
+//   loads the four corner values of the layer's top face and forms their face
+//   modes (sums and differences in x and y; the bottom face's modes are the
+//   previous layer's top),
+//   forms the element's eight modes per component (z sum and difference),
+//   scales them by the element's modulus and applies the 45 couplings,
+//   splits the result back into bottom- and top-face modes, adds the bottom
+//   ones to the previous layer's top ones (both belong to the bottom face's
+//   node plane) and turns them into the face's four corner values,
+//   which go to LDS; after one barrier each owned node adds the corner values
+//   of its four element columns (own column first, then +x, +y, +x+y) and
+//   finishes as the node-gather form does.
+// An element outside the grid has modulus zero; the corner loads of such
+// columns read clamped in-grid nodes, so every value stays finite.
+constexpr int SF_TX = 32, SF_TY = 8;                // element columns per tile
+constexpr int SF_NX = SF_TX - 1, SF_NY = SF_TY - 1;  // owned node columns per tile
+
+template <int I>
+__device__ __forceinline__ void sf_couple(const SfCoef<float>& cf, const float (&md)[8][3], float (&o)[8][3]) {
+    if constexpr (I < 72) {
+        constexpr int c = I / 24, d = (I / 8) % 3, m = I % 8;
+        constexpr int sl = SF_SLOTS.s[c][d][m];
+        if constexpr (sl >= 0) {
+            constexpr int mo = sf_out_mode(c, d, m);
+            o[mo][c] = fma_of(cf.k[sl], md[m][d], o[mo][c]);
+        }
+        sf_couple<I + 1>(cf, md, o);
+    }
+}
+
+// face modes of corner values v[2 ly + lx][c]: [0] sum, [1] x difference,
+// [2] y difference, [3] both
+__device__ __forceinline__ void sf_face_modes(const float (&v)[4][3], float (&m)[4][3]) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const float s0 = v[0][c] + v[1][c], d0 = v[1][c] - v[0][c];
+        const float s1 = v[2][c] + v[3][c], d1 = v[3][c] - v[2][c];
+        m[0][c] = s0 + s1;
+        m[1][c] = d0 + d1;
+        m[2][c] = s1 - s0;
+        m[3][c] = d1 - d0;
+    }
+}
+
+template <int OP, int NB>
+__global__ __launch_bounds__(SF_TX * SF_TY) __attribute__((amdgpu_waves_per_eu(4))) void k_fine3sf(
+    const Pack<OpA<float>, NB> pk, const SfCoef<float> cf, int nx, int ny, int nz, int tiles_x, int tiles_y,
+    int zlen, float omega, double c1, double c2) {
+    static_assert(OP != OP_QDOT, "no partial sums in the tensor form");
+    __shared__ float cv[2][4][3][SF_TX * SF_TY];    // corner values of the plane per element column
+    const OpA<float>& A_ = lane_of(pk);
+    const int* __restrict__ done = A_.done;
+    if (done && *done) return;
+    const uint32_t NX = nx + 1, NY = ny + 1, NZ = nz + 1, PL = NX * NY, N = PL * NZ;
+    const uint32_t blk = (uint32_t)xcd_block();
+    const uint32_t bx = blk % (uint32_t)tiles_x, br = blk / (uint32_t)tiles_x;
+    const uint32_t by = br % (uint32_t)tiles_y, bz = br / (uint32_t)tiles_y;
+    const int t = threadIdx.x;
+    const int tx = t % SF_TX, ty = t / SF_TX;
+    const int ex = (int)bx * SF_NX - 1 + tx, ey = (int)by * SF_NY - 1 + ty;
+    const bool ecol = ex >= 0 && ex < nx && ey >= 0 && ey < ny;
+    const uint32_t ix0 = (uint32_t)min(max(ex, 0), (int)NX - 1), ix1 = (uint32_t)min(max(ex + 1, 0), (int)NX - 1);
+    const uint32_t iy0 = (uint32_t)min(max(ey, 0), (int)NY - 1), iy1 = (uint32_t)min(max(ey + 1, 0), (int)NY - 1);
+    constexpr uint32_t NBY = 3u * sizeof(float);
+    const uint32_t fo[4] = {(iy0 * NX + ix0) * NBY, (iy0 * NX + ix1) * NBY, (iy1 * NX + ix0) * NBY,
+                            (iy1 * NX + ix1) * NBY};
+    // owned node: the column's upper corner in x and y
+    const uint32_t own_col = iy1 * NX + ix1;
+    const bool own = tx < SF_NX && ty < SF_NY && ex + 1 < (int)NX && ey + 1 < (int)NY;
+    const uint32_t EP = (uint32_t)nx * (uint32_t)ny;
+    const uint32_t ecix = ecol ? (uint32_t)ey * (uint32_t)nx + (uint32_t)ex : 0u;
+    const int k0 = (int)bz * zlen;
+    const int k1 = min(k0 + zlen, (int)NZ);
+    // Every access goes through a buffer descriptor with a clamped offset, and
+    // the loop body has no branch besides its barrier, so the compiler can
+    // wait for exactly the loads a step reads while later ones stay in
+    // flight.  A store of a node the thread does not own (or of a plane past
+    // the range) gets an offset past the descriptor's end, which the hardware
+    // drops; with no direction output the direction descriptor is empty.
+    const auto xr = buf_rsrc(A_.x, (int64_t)N * NBY);
+    const auto er = buf_rsrc(A_.E, (int64_t)EP * nz * sizeof(float));
+    const auto mr = buf_rsrc(A_.nm, (int64_t)N);
+    const auto brs = buf_rsrc(A_.b, OP == OP_APPLY ? 0 : (int64_t)N * NBY);
+    const auto dr = buf_rsrc(A_.dinv, OP == OP_SMOOTH || OP == OP_CHEB ? (int64_t)6 * N * sizeof(float) : 0);
+    const auto inr = buf_rsrc(A_.din, OP == OP_CHEB ? (int64_t)N * NBY : 0);
+    const auto yr = buf_rsrc(A_.y, (int64_t)N * NBY);
+    const auto dor = buf_rsrc(A_.dout, OP == OP_CHEB && A_.dout ? (int64_t)N * NBY : 0);
+    const float fc1 = (float)c1, fc2 = (float)c2;
+    auto load_face = [&](int p, float (&v)[4][3]) {
+        const uint32_t pb = (uint32_t)min(max(p, 0), (int)NZ - 1) * PL * NBY;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) bld3(xr, pb + fo[q], v[q]);
+    };
+    // operands of element layer l: its top face's corners and its modulus
+    // (with weight 0 for an element outside the grid, applied where the
+    // layer is used, so that nothing waits for the load when it is issued)
+    struct Face {
+        float v[4][3];
+        float E, w;
+    };
+    auto fetch_face = [&](int l, Face& F) {
+        load_face(l + 1, F.v);
+        const uint32_t lz = (uint32_t)min(max(l, 0), nz - 1);
+        F.E = bld<float>(er, (lz * EP + ecix) * (uint32_t)sizeof(float));
+        F.w = (ecol && l >= 0 && l < nz) ? 1.f : 0.f;
+    };
+    // finishing operands of the owned node in plane l
+    struct Fin {
+        float b[3], dv[6], din[3];
+        uint32_t m;
+    };
+    auto node_of = [&](int l) { return (uint32_t)min(max(l, 0), (int)NZ - 1) * PL + own_col; };
+    auto fetch_fin = [&](int l, Fin& f) {
+        const uint32_t nd = node_of(l);
+        if (OP != OP_APPLY) bld3(brs, nd * NBY, f.b);
+        if (OP == OP_SMOOTH || OP == OP_CHEB) {
+#pragma unroll
+            for (int e = 0; e < 6; ++e) f.dv[e] = bld<float>(dr, ((uint32_t)e * N + nd) * (uint32_t)sizeof(float));
+        }
+        if (OP == OP_CHEB) bld3(inr, nd * NBY, f.din);
+        f.m = __builtin_amdgcn_raw_buffer_load_b8(mr, nd, 0, 0);
+    };
+    // element layer l from its top face S and the bottom face's modes fb:
+    // the plane-l face modes pm (this layer's bottom plus the layer below's
+    // top, st), and st, fb for the next layer
+    float fb[4][3], st[4][3];
+    auto layer = [&](const float (&v)[4][3], float Ee, float (&pm)[4][3]) {
+        float ft[4][3];
+        sf_face_modes(v, ft);
+        float md[8][3], o[8][3];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                md[q][c] = Ee * (ft[q][c] + fb[q][c]);
+                md[q + 4][c] = Ee * (ft[q][c] - fb[q][c]);
+                o[q][c] = 0.f;
+                o[q + 4][c] = 0.f;
+            }
+        sf_couple<0>(cf, md, o);
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                pm[q][c] = st[q][c] + (o[q][c] - o[q + 4][c]);
+                st[q][c] = o[q][c] + o[q + 4][c];
+                fb[q][c] = ft[q][c];
+            }
+    };
+    float xo[3];        // the owned node's value in the plane being finished
+    Face FA, FB;
+    {
+        // layer k0 - 1: only its top-face outputs (plane k0) are kept
+        float v0[4][3];
+        load_face(k0 - 1, v0);
+        fetch_face(k0 - 1, FA);
+        fetch_face(k0, FB);
+        sf_face_modes(v0, fb);
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) st[q][c] = 0.f;
+        float v[4][3];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) v[q][c] = FA.v[q][c];
+        const float Ee = FA.E * FA.w;
+        fetch_face(k0 + 1, FA);
+        float pm[4][3];
+        layer(v, Ee, pm);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) xo[c] = v[3][c];
+    }
+    // plane l from layer l (operand set S, refilled with layer l + 2: two
+    // sets alternate, the march being unrolled by two, so a set is refilled
+    // as soon as it is read, without copies of loads in flight); the
+    // finishing operands are issued before that refill, so that waiting for
+    // them after the layer's arithmetic leaves the refill in flight
+    auto step = [&](int l, Face& S) {
+        float v[4][3];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) v[q][c] = S.v[q][c];
+        const float Ee = S.E * S.w;
+        Fin fin;
+        fetch_fin(l, fin);
+        __builtin_amdgcn_sched_barrier(0);          // keep the issue order
+        fetch_face(l + 2, S);
+        float pm[4][3];
+        layer(v, Ee, pm);
+        __builtin_amdgcn_sched_barrier(0);          // the finishing operands are read below
+        const int buf = (l - k0) & 1;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const float P = pm[0][c] + pm[2][c], Q = pm[0][c] - pm[2][c];
+            const float R = pm[1][c] + pm[3][c], U = pm[1][c] - pm[3][c];
+            cv[buf][0][c][t] = Q - U;
+            cv[buf][1][c][t] = Q + U;
+            cv[buf][2][c][t] = P - R;
+            cv[buf][3][c][t] = P + R;
+        }
+        __syncthreads();
+        // the four columns' corner values at the owned node (threads that own
+        // none read their own slots instead, and store nothing)
+        const int t1 = own ? t + 1 : t, t16 = own ? t + SF_TX : t, t17 = own ? t + SF_TX + 1 : t;
+        float kx[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            kx[c] = ((cv[buf][3][c][t] + cv[buf][2][c][t1]) + cv[buf][1][c][t16]) + cv[buf][0][c][t17];
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            if (fin.m & (1u << c)) kx[c] = xo[c];           // unit row of a supported dof
+        float yv[3], dn[3] = {0.f, 0.f, 0.f};
+        if (OP == OP_APPLY) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) yv[c] = kx[c];
+        } else if (OP == OP_RESID) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) yv[c] = fin.b[c] - kx[c];
+        } else {
+            float rr[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) rr[c] = fin.b[c] - kx[c];
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+                float s = 0.f;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) s += fin.dv[sym_at(r, c, 3)] * rr[c];
+                if (OP == OP_SMOOTH) {
+                    yv[r] = xo[r] + omega * s;
+                } else {
+                    dn[r] = fma_of(s, fc2, fc1 * fin.din[r]);
+                    yv[r] = xo[r] + dn[r];
+                }
+            }
+        }
+        const uint32_t so = own && l < k1 ? node_of(l) * NBY : 0xfffffff0u;
+        typedef float f3 __attribute__((ext_vector_type(3)));
+        __builtin_amdgcn_raw_buffer_store_b96(f3{yv[0], yv[1], yv[2]}, yr, so, 0, 0);
+        if (OP == OP_CHEB) __builtin_amdgcn_raw_buffer_store_b96(f3{dn[0], dn[1], dn[2]}, dor, so, 0, 0);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) xo[c] = v[3][c];
+    };
+    // an even number of steps (a last one past the range stores nothing)
+    for (int l = k0; l < k1; l += 2) {
+        step(l, FB);
+        step(l + 1, FA);
+    }
+}
+
+static int sf_tiles(int nn, int per) { return (nn + per - 1) / per; }
+
+// node planes per workgroup: enough workgroups for about four per compute
+// unit (each is four waves), one extra element layer per workgroup
+static int sf_zlen(int tiles, int nz_nodes) {
+    const int chunks = std::max(1, std::min(nz_nodes, 1024 / std::max(1, tiles)));
+    return (int)ceil_div(nz_nodes, chunks);
+}
+
 // 3D FP32 on the matrix cores, two nodes stacked in z per lane as in
 // k_fine3z2 (shared neighbour planes).  Each node's 24x24 KE contraction runs
 // on v_mfma_f32_4x4x1 (16 blocks of 4 lanes): in each block, lane 4b+j supplies
@@ -765,6 +1030,14 @@ static void fine_launch(const LaneIO* L, int n, T omega, double c1, double c2, h
     }
     const dim3 blk(WG);
     if constexpr (std::is_same<T, float>::value && !MI && OP != OP_QDOT) {
+        if (F.dim == 3 && h->opt.fine_tensor && h->sf_ok && !h->opt.fine_mfma) {
+            const int tx = sf_tiles(F.nn[0], SF_NX), ty = sf_tiles(F.nn[1], SF_NY);
+            const int zl = h->opt.fine_tensor >= 2 ? h->opt.fine_tensor : sf_zlen(tx * ty, F.nn[2]);
+            const dim3 g((unsigned)(tx * ty * ceil_div(F.nn[2], zl)), n);
+            hipLaunchKernelGGL((k_fine3sf<OP, NB>), g, dim3(SF_TX * SF_TY), 0, s, pk, h->sf32, F.nel[0], F.nel[1],
+                               F.nel[2], tx, ty, zl, omega, c1, c2);
+            return;
+        }
         if (F.dim == 3) {
             const int64_t nt = (int64_t)F.nn[0] * F.nn[1] * ((F.nn[2] + 1) / 2);
             const dim3 g(grid_for(nt), n);

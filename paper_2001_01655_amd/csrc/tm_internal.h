@@ -128,6 +128,42 @@ struct KeVals {
     T k[KE_MAX_CLASSES];
 };
 
+// Tensor form of the 3D element stiffness.  Transform the corner values of one
+// component to modes, one per choice of sum or difference along each axis
+// (bit k of the mode index m set: difference along axis k; for a face of four
+// corners, bits 0 and 1; for the element, bit 2 adds z).  The trilinear cube's
+// 1D mass matrix is diagonal in these modes and its 1D stiffness and mixed
+// matrices map a sum to a difference or back, so KE = F^T C F (F the +-1
+// transform per component) with C nonzero only where component d's input mode
+// m feeds component c's output mode m (c = d, m != 0) or m with bits c and d
+// flipped (c != d, bits c and d of m differ): 21 + 24 = 45 coefficients,
+// slot s[c][d][m] (-1: none).
+struct SfSlots {
+    int8_t s[3][3][8];
+    int n;
+};
+constexpr SfSlots make_sf_slots() {
+    SfSlots t{};
+    int n = 0;
+    for (int c = 0; c < 3; ++c)
+        for (int d = 0; d < 3; ++d)
+            for (int m = 0; m < 8; ++m) {
+                const bool on = c == d ? m != 0 : ((m >> c) & 1) != ((m >> d) & 1);
+                t.s[c][d][m] = on ? (int8_t)n++ : (int8_t)-1;
+            }
+    t.n = n;
+    return t;
+}
+inline constexpr SfSlots SF_SLOTS = make_sf_slots();
+constexpr int SF_COEFS = 45;
+static_assert(SF_SLOTS.n == SF_COEFS, "tensor-form coefficient count");
+// output mode of component c fed by input mode m of component d
+__host__ __device__ constexpr int sf_out_mode(int c, int d, int m) { return c == d ? m : m ^ (1 << c) ^ (1 << d); }
+template <typename T>
+struct SfCoef {
+    T k[SF_COEFS];
+};
+
 // Lane batching: a kernel of the solve path runs the same operation for up to
 // MAXB lanes (right-hand sides of one or several hierarchies with the same
 // level structure) in one launch; blockIdx.y selects the lane, whose pointers
@@ -318,6 +354,8 @@ struct tm_hierarchy {
     float* KA32 = nullptr;         // 3D: KE as the broadcast A operand of the matrix-core fine operator
     tmi::KeVals<double> kc64{};       // KE symmetry-class values (fine operator arguments)
     tmi::KeVals<float> kc32{};
+    tmi::SfCoef<float> sf32{};        // 3D KE in the tensor form (fine operator arguments)
+    bool sf_ok = false;               // KE has the tensor form's structure
     double* ainv = nullptr;        // inverse of the coarsest operator (FP64, dense)
     float* ainv32 = nullptr;
     int64_t nc = 0;                // coarsest dofs

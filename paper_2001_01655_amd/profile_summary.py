@@ -26,8 +26,9 @@ COPY_BYTES = 256 << 20
 CLASSES = {
     0: dict(match=["k_fine3<double, 3, false, 1>"], source=["kernels_fine.hip", "tm_device.h"],
             what="fine operator FP64 (q = K~p, outer loop)"),
-    1: dict(match=["k_fine3z2<float, 1, 1>", "k_fine3z2<float, 2, 1>", "k_fine3z2<float, 4, 1>"],
-            source=["kernels_fine.hip", "tm_device.h"], what="fine operator FP32 (V-cycle smoothing / residual)"),
+    1: dict(match=["k_fine3sf<1, 1>", "k_fine3sf<2, 1>", "k_fine3sf<4, 1>"],
+            source=["kernels_fine.hip", "tm_device.h"],
+            what="fine operator FP32, tensor-product form (V-cycle smoothing / residual)"),
     2: dict(match=["k_stencil_op<float, 3, 1, 4, 1>", "k_stencil_op<float, 3, 2, 4, 1>",
                    "k_stencil_op<float, 3, 4, 4, 1>"],
             source=["kernels_coarse.hip", "tm_device.h"], what="level-1 stencil operator FP32 (V-cycle)",
@@ -35,6 +36,9 @@ CLASSES = {
     3: dict(match=["k_fine3z2_mfma<1, 1>", "k_fine3z2_mfma<2, 1>", "k_fine3z2_mfma<4, 1>"],
             source=["kernels_fine.hip", "tm_device.h"],
             what="fine operator FP32 on the matrix cores (option fine_mfma)"),
+    4: dict(match=["k_fine3z2<float, 1, 1>", "k_fine3z2<float, 2, 1>", "k_fine3z2<float, 4, 1>"],
+            source=["kernels_fine.hip", "tm_device.h"],
+            what="fine operator FP32, node gather (option fine_tensor = 0)"),
 }
 
 
