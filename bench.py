@@ -203,9 +203,9 @@ def algorithmic(cls, H, p, args):
 def roofline_entry(cls, launches, total_ms, H, p, args):
     avg_s = total_ms / 1e3 / max(launches, 1)
     flops, byts = algorithmic(cls, H, p, args)
-    # the FP32 fine operator in the tensor-product form does about a fifth of
-    # the dense KE arithmetic, far below its HBM time: HBM is its roof
-    tensor = cls == 1 and p.dim == 3 and args.fine_mfma == 0 and args.fine_tensor != 0
+    # the fine operators in the tensor-product form (3D) do about a fifth of
+    # the dense KE arithmetic, far below their HBM time: HBM is their roof
+    tensor = cls in (0, 1) and p.dim == 3 and args.fine_tensor != 0 and not (cls == 1 and args.fine_mfma)
     if cls == 2 or tensor:
         ach = byts / avg_s / 1e9
         e = {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK["hbm_GBs"], "unit": "GB/s",
@@ -216,9 +216,9 @@ def roofline_entry(cls, launches, total_ms, H, p, args):
         e = {"bound": "alu", "achieved": round(ach, 2), "peak": peak, "unit": "TFLOP/s",
              "frac": round(ach / peak, 4)}
     e.update({"kernel": {0: "fine operator FP64 (q = K~p, outer loop)",
-                         1: "fine operator FP32 (V-cycle smoothing / residual)" +
-                            (", tensor-product form" if tensor else ""),
-                         2: "level-1 stencil operator FP32 (V-cycle)"}[cls],
+                         1: "fine operator FP32 (V-cycle smoothing / residual)",
+                         2: "level-1 stencil operator FP32 (V-cycle)"}[cls] +
+                        (", tensor-product form" if tensor else ""),
               "launches": launches, "avg_us": round(avg_s * 1e6, 2),
               "algorithmic_flops_per_launch": flops, "algorithmic_bytes_per_launch": byts,
               "traffic": None})

@@ -287,8 +287,10 @@ static void ke_tensor_coefs(const std::vector<double>& KE, tm_hierarchy* h) {
                         for (int b2 = 0; b2 < 8; ++b2) v += F[mo][a] * KE[(3 * a + c) * 24 + 3 * b2 + d] * F[mi][b2];
                     v /= 64.0;
                     const int sl = SF_SLOTS.s[c][d][mi];
-                    if (sl >= 0 && sf_out_mode(c, d, mi) == mo)
+                    if (sl >= 0 && sf_out_mode(c, d, mi) == mo) {
+                        h->sf64.k[sl] = v;
                         h->sf32.k[sl] = (float)v;
+                    }
                     else if (std::fabs(v) > 1e-12 * amax)
                         ok = false;
                 }

@@ -459,8 +459,8 @@ __global__ __launch_bounds__(WG) void k_fine3z2(const Pack<OpA<T>, NB> pk, const
 constexpr int SF_TX = 32, SF_TY = 8;                // element columns per tile
 constexpr int SF_NX = SF_TX - 1, SF_NY = SF_TY - 1;  // owned node columns per tile
 
-template <int I>
-__device__ __forceinline__ void sf_couple(const SfCoef<float>& cf, const float (&md)[8][3], float (&o)[8][3]) {
+template <int I, typename T>
+__device__ __forceinline__ void sf_couple(const SfCoef<T>& cf, const T (&md)[8][3], T (&o)[8][3]) {
     if constexpr (I < 72) {
         constexpr int c = I / 24, d = (I / 8) % 3, m = I % 8;
         constexpr int sl = SF_SLOTS.s[c][d][m];
@@ -468,17 +468,18 @@ __device__ __forceinline__ void sf_couple(const SfCoef<float>& cf, const float (
             constexpr int mo = sf_out_mode(c, d, m);
             o[mo][c] = fma_of(cf.k[sl], md[m][d], o[mo][c]);
         }
-        sf_couple<I + 1>(cf, md, o);
+        sf_couple<I + 1, T>(cf, md, o);
     }
 }
 
 // face modes of corner values v[2 ly + lx][c]: [0] sum, [1] x difference,
 // [2] y difference, [3] both
-__device__ __forceinline__ void sf_face_modes(const float (&v)[4][3], float (&m)[4][3]) {
+template <typename T>
+__device__ __forceinline__ void sf_face_modes(const T (&v)[4][3], T (&m)[4][3]) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        const float s0 = v[0][c] + v[1][c], d0 = v[1][c] - v[0][c];
-        const float s1 = v[2][c] + v[3][c], d1 = v[3][c] - v[2][c];
+        const T s0 = v[0][c] + v[1][c], d0 = v[1][c] - v[0][c];
+        const T s1 = v[2][c] + v[3][c], d1 = v[3][c] - v[2][c];
         m[0][c] = s0 + s1;
         m[1][c] = d0 + d1;
         m[2][c] = s1 - s0;
@@ -486,13 +487,28 @@ __device__ __forceinline__ void sf_face_modes(const float (&v)[4][3], float (&m)
     }
 }
 
-template <int OP, int NB>
-__global__ __launch_bounds__(SF_TX * SF_TY) __attribute__((amdgpu_waves_per_eu(4))) void k_fine3sf(
-    const Pack<OpA<float>, NB> pk, const SfCoef<float> cf, int nx, int ny, int nz, int tiles_x, int tiles_y,
-    int zlen, float omega, double c1, double c2) {
-    static_assert(OP != OP_QDOT, "no partial sums in the tensor form");
-    __shared__ float cv[2][4][3][SF_TX * SF_TY];    // corner values of the plane per element column
-    const OpA<float>& A_ = lane_of(pk);
+// three consecutive values stored at byte offset off (one 12-byte store in
+// FP32, a 16- and an 8-byte store in FP64); an offset past the descriptor's
+// end drops the store
+__device__ __forceinline__ void bst3(__amdgpu_buffer_rsrc_t r, uint32_t off, const float (&v)[3]) {
+    typedef float f3 __attribute__((ext_vector_type(3)));
+    __builtin_amdgcn_raw_buffer_store_b96(f3{v[0], v[1], v[2]}, r, off, 0, 0);
+}
+__device__ __forceinline__ void bst3(__amdgpu_buffer_rsrc_t r, uint32_t off, const double (&v)[3]) {
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    typedef unsigned u2 __attribute__((ext_vector_type(2)));
+    typedef unsigned u4 __attribute__((ext_vector_type(4)));
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, d2{v[0], v[1]}), r, off, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v[2]), r, off + 16, 0, 0);
+}
+
+// cv: the plane's corner values per element column, two buffers (LDS)
+template <typename T, int OP, int NB>
+__device__ __forceinline__ void fine3sf_body(const Pack<OpA<T>, NB>& pk, const SfCoef<T>& cf, int nx, int ny,
+                                             int nz, int tiles_x, int tiles_y, int zlen, T omega, double c1,
+                                             double c2, T (&cv)[2][4][3][SF_TX * SF_TY]) {
+    static_assert(OP != OP_QDOT || std::is_same<T, double>::value, "partial sums in the FP64 form only");
+    const OpA<T>& A_ = lane_of(pk);
     const int* __restrict__ done = A_.done;
     if (done && *done) return;
     const uint32_t NX = nx + 1, NY = ny + 1, NZ = nz + 1, PL = NX * NY, N = PL * NZ;
@@ -505,7 +521,7 @@ __global__ __launch_bounds__(SF_TX * SF_TY) __attribute__((amdgpu_waves_per_eu(4
     const bool ecol = ex >= 0 && ex < nx && ey >= 0 && ey < ny;
     const uint32_t ix0 = (uint32_t)min(max(ex, 0), (int)NX - 1), ix1 = (uint32_t)min(max(ex + 1, 0), (int)NX - 1);
     const uint32_t iy0 = (uint32_t)min(max(ey, 0), (int)NY - 1), iy1 = (uint32_t)min(max(ey + 1, 0), (int)NY - 1);
-    constexpr uint32_t NBY = 3u * sizeof(float);
+    constexpr uint32_t NBY = 3u * sizeof(T);
     const uint32_t fo[4] = {(iy0 * NX + ix0) * NBY, (iy0 * NX + ix1) * NBY, (iy1 * NX + ix0) * NBY,
                             (iy1 * NX + ix1) * NBY};
     // owned node: the column's upper corner in x and y
@@ -522,15 +538,15 @@ __global__ __launch_bounds__(SF_TX * SF_TY) __attribute__((amdgpu_waves_per_eu(4
     // the range) gets an offset past the descriptor's end, which the hardware
     // drops; with no direction output the direction descriptor is empty.
     const auto xr = buf_rsrc(A_.x, (int64_t)N * NBY);
-    const auto er = buf_rsrc(A_.E, (int64_t)EP * nz * sizeof(float));
+    const auto er = buf_rsrc(A_.E, (int64_t)EP * nz * sizeof(T));
     const auto mr = buf_rsrc(A_.nm, (int64_t)N);
     const auto brs = buf_rsrc(A_.b, OP == OP_APPLY ? 0 : (int64_t)N * NBY);
-    const auto dr = buf_rsrc(A_.dinv, OP == OP_SMOOTH || OP == OP_CHEB ? (int64_t)6 * N * sizeof(float) : 0);
+    const auto dr = buf_rsrc(A_.dinv, OP == OP_SMOOTH || OP == OP_CHEB ? (int64_t)6 * N * sizeof(T) : 0);
     const auto inr = buf_rsrc(A_.din, OP == OP_CHEB ? (int64_t)N * NBY : 0);
     const auto yr = buf_rsrc(A_.y, (int64_t)N * NBY);
     const auto dor = buf_rsrc(A_.dout, OP == OP_CHEB && A_.dout ? (int64_t)N * NBY : 0);
-    const float fc1 = (float)c1, fc2 = (float)c2;
-    auto load_face = [&](int p, float (&v)[4][3]) {
+    const T fc1 = (T)c1, fc2 = (T)c2;
+    auto load_face = [&](int p, T (&v)[4][3]) {
         const uint32_t pb = (uint32_t)min(max(p, 0), (int)NZ - 1) * PL * NBY;
 #pragma unroll
         for (int q = 0; q < 4; ++q) bld3(xr, pb + fo[q], v[q]);
@@ -539,18 +555,18 @@ __global__ __launch_bounds__(SF_TX * SF_TY) __attribute__((amdgpu_waves_per_eu(4
     // (with weight 0 for an element outside the grid, applied where the
     // layer is used, so that nothing waits for the load when it is issued)
     struct Face {
-        float v[4][3];
-        float E, w;
+        T v[4][3];
+        T E, w;
     };
     auto fetch_face = [&](int l, Face& F) {
         load_face(l + 1, F.v);
         const uint32_t lz = (uint32_t)min(max(l, 0), nz - 1);
-        F.E = bld<float>(er, (lz * EP + ecix) * (uint32_t)sizeof(float));
-        F.w = (ecol && l >= 0 && l < nz) ? 1.f : 0.f;
+        F.E = bld<T>(er, (lz * EP + ecix) * (uint32_t)sizeof(T));
+        F.w = (ecol && l >= 0 && l < nz) ? T(1) : T(0);
     };
     // finishing operands of the owned node in plane l
     struct Fin {
-        float b[3], dv[6], din[3];
+        T b[3], dv[6], din[3];
         uint32_t m;
     };
     auto node_of = [&](int l) { return (uint32_t)min(max(l, 0), (int)NZ - 1) * PL + own_col; };
@@ -559,7 +575,7 @@ __global__ __launch_bounds__(SF_TX * SF_TY) __attribute__((amdgpu_waves_per_eu(4
         if (OP != OP_APPLY) bld3(brs, nd * NBY, f.b);
         if (OP == OP_SMOOTH || OP == OP_CHEB) {
 #pragma unroll
-            for (int e = 0; e < 6; ++e) f.dv[e] = bld<float>(dr, ((uint32_t)e * N + nd) * (uint32_t)sizeof(float));
+            for (int e = 0; e < 6; ++e) f.dv[e] = bld<T>(dr, ((uint32_t)e * N + nd) * (uint32_t)sizeof(T));
         }
         if (OP == OP_CHEB) bld3(inr, nd * NBY, f.din);
         f.m = __builtin_amdgcn_raw_buffer_load_b8(mr, nd, 0, 0);
@@ -567,21 +583,21 @@ __global__ __launch_bounds__(SF_TX * SF_TY) __attribute__((amdgpu_waves_per_eu(4
     // element layer l from its top face S and the bottom face's modes fb:
     // the plane-l face modes pm (this layer's bottom plus the layer below's
     // top, st), and st, fb for the next layer
-    float fb[4][3], st[4][3];
-    auto layer = [&](const float (&v)[4][3], float Ee, float (&pm)[4][3]) {
-        float ft[4][3];
+    T fb[4][3], st[4][3];
+    auto layer = [&](const T (&v)[4][3], T Ee, T (&pm)[4][3]) {
+        T ft[4][3];
         sf_face_modes(v, ft);
-        float md[8][3], o[8][3];
+        T md[8][3], o[8][3];
 #pragma unroll
         for (int q = 0; q < 4; ++q)
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 md[q][c] = Ee * (ft[q][c] + fb[q][c]);
                 md[q + 4][c] = Ee * (ft[q][c] - fb[q][c]);
-                o[q][c] = 0.f;
-                o[q + 4][c] = 0.f;
+                o[q][c] = T(0);
+                o[q + 4][c] = T(0);
             }
-        sf_couple<0>(cf, md, o);
+        sf_couple<0, T>(cf, md, o);
 #pragma unroll
         for (int q = 0; q < 4; ++q)
 #pragma unroll
@@ -591,11 +607,11 @@ __global__ __launch_bounds__(SF_TX * SF_TY) __attribute__((amdgpu_waves_per_eu(4
                 fb[q][c] = ft[q][c];
             }
     };
-    float xo[3];        // the owned node's value in the plane being finished
+    T xo[3];            // the owned node's value in the plane being finished
     Face FA, FB;
     {
         // layer k0 - 1: only its top-face outputs (plane k0) are kept
-        float v0[4][3];
+        T v0[4][3];
         load_face(k0 - 1, v0);
         fetch_face(k0 - 1, FA);
         fetch_face(k0, FB);
@@ -603,15 +619,15 @@ __global__ __launch_bounds__(SF_TX * SF_TY) __attribute__((amdgpu_waves_per_eu(4
 #pragma unroll
         for (int q = 0; q < 4; ++q)
 #pragma unroll
-            for (int c = 0; c < 3; ++c) st[q][c] = 0.f;
-        float v[4][3];
+            for (int c = 0; c < 3; ++c) st[q][c] = T(0);
+        T v[4][3];
 #pragma unroll
         for (int q = 0; q < 4; ++q)
 #pragma unroll
             for (int c = 0; c < 3; ++c) v[q][c] = FA.v[q][c];
-        const float Ee = FA.E * FA.w;
+        const T Ee = FA.E * FA.w;
         fetch_face(k0 + 1, FA);
-        float pm[4][3];
+        T pm[4][3];
         layer(v, Ee, pm);
 #pragma unroll
         for (int c = 0; c < 3; ++c) xo[c] = v[3][c];
@@ -621,25 +637,26 @@ __global__ __launch_bounds__(SF_TX * SF_TY) __attribute__((amdgpu_waves_per_eu(4
     // as soon as it is read, without copies of loads in flight); the
     // finishing operands are issued before that refill, so that waiting for
     // them after the layer's arithmetic leaves the refill in flight
+    double dots[2] = {0.0, 0.0};
     auto step = [&](int l, Face& S) {
-        float v[4][3];
+        T v[4][3];
 #pragma unroll
         for (int q = 0; q < 4; ++q)
 #pragma unroll
             for (int c = 0; c < 3; ++c) v[q][c] = S.v[q][c];
-        const float Ee = S.E * S.w;
+        const T Ee = S.E * S.w;
         Fin fin;
         fetch_fin(l, fin);
         __builtin_amdgcn_sched_barrier(0);          // keep the issue order
         fetch_face(l + 2, S);
-        float pm[4][3];
+        T pm[4][3];
         layer(v, Ee, pm);
         __builtin_amdgcn_sched_barrier(0);          // the finishing operands are read below
         const int buf = (l - k0) & 1;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            const float P = pm[0][c] + pm[2][c], Q = pm[0][c] - pm[2][c];
-            const float R = pm[1][c] + pm[3][c], U = pm[1][c] - pm[3][c];
+            const T P = pm[0][c] + pm[2][c], Q = pm[0][c] - pm[2][c];
+            const T R = pm[1][c] + pm[3][c], U = pm[1][c] - pm[3][c];
             cv[buf][0][c][t] = Q - U;
             cv[buf][1][c][t] = Q + U;
             cv[buf][2][c][t] = P - R;
@@ -649,27 +666,28 @@ __global__ __launch_bounds__(SF_TX * SF_TY) __attribute__((amdgpu_waves_per_eu(4
         // the four columns' corner values at the owned node (threads that own
         // none read their own slots instead, and store nothing)
         const int t1 = own ? t + 1 : t, t16 = own ? t + SF_TX : t, t17 = own ? t + SF_TX + 1 : t;
-        float kx[3];
+        T kx[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c)
             kx[c] = ((cv[buf][3][c][t] + cv[buf][2][c][t1]) + cv[buf][1][c][t16]) + cv[buf][0][c][t17];
 #pragma unroll
         for (int c = 0; c < 3; ++c)
             if (fin.m & (1u << c)) kx[c] = xo[c];           // unit row of a supported dof
-        float yv[3], dn[3] = {0.f, 0.f, 0.f};
-        if (OP == OP_APPLY) {
+        const bool live = own && l < k1;
+        T yv[3], dn[3] = {T(0), T(0), T(0)};
+        if (OP == OP_APPLY || OP == OP_QDOT) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) yv[c] = kx[c];
         } else if (OP == OP_RESID) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) yv[c] = fin.b[c] - kx[c];
         } else {
-            float rr[3];
+            T rr[3];
 #pragma unroll
             for (int c = 0; c < 3; ++c) rr[c] = fin.b[c] - kx[c];
 #pragma unroll
             for (int r = 0; r < 3; ++r) {
-                float s = 0.f;
+                T s = T(0);
 #pragma unroll
                 for (int c = 0; c < 3; ++c) s += fin.dv[sym_at(r, c, 3)] * rr[c];
                 if (OP == OP_SMOOTH) {
@@ -680,10 +698,20 @@ __global__ __launch_bounds__(SF_TX * SF_TY) __attribute__((amdgpu_waves_per_eu(4
                 }
             }
         }
-        const uint32_t so = own && l < k1 ? node_of(l) * NBY : 0xfffffff0u;
-        typedef float f3 __attribute__((ext_vector_type(3)));
-        __builtin_amdgcn_raw_buffer_store_b96(f3{yv[0], yv[1], yv[2]}, yr, so, 0, 0);
-        if (OP == OP_CHEB) __builtin_amdgcn_raw_buffer_store_b96(f3{dn[0], dn[1], dn[2]}, dor, so, 0, 0);
+        if (OP == OP_QDOT) {
+            // p^T q and p^T r (b holds r) over the owned nodes of the range
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                dots[0] += live ? (double)xo[c] * (double)kx[c] : 0.0;
+                dots[1] += live ? (double)xo[c] * (double)fin.b[c] : 0.0;
+            }
+        }
+        // the dropped stores' offset stays past any descriptor's end (at most
+        // 2^31 - 1 bytes) also after the 16 bytes the FP64 form adds for its
+        // third value, without wrapping around 2^32
+        const uint32_t so = live ? node_of(l) * NBY : 0xfffff000u;
+        bst3(yr, so, yv);
+        if (OP == OP_CHEB) bst3(dor, so, dn);
 #pragma unroll
         for (int c = 0; c < 3; ++c) xo[c] = v[3][c];
     };
@@ -692,15 +720,45 @@ __global__ __launch_bounds__(SF_TX * SF_TY) __attribute__((amdgpu_waves_per_eu(4
         step(l, FB);
         step(l + 1, FA);
     }
+    if (OP == OP_QDOT) block_reduce_store<2>(dots, A_.partials);
+}
+
+template <int OP, int NB>
+__global__ __launch_bounds__(SF_TX * SF_TY) __attribute__((amdgpu_waves_per_eu(4))) void k_fine3sf(
+    const Pack<OpA<float>, NB> pk, const SfCoef<float> cf, int nx, int ny, int nz, int tiles_x, int tiles_y,
+    int zlen, float omega, double c1, double c2) {
+    __shared__ float cv[2][4][3][SF_TX * SF_TY];
+    fine3sf_body<float, OP, NB>(pk, cf, nx, ny, nz, tiles_x, tiles_y, zlen, omega, c1, c2, cv);
+}
+
+template <int OP, int NB>
+__global__ __launch_bounds__(SF_TX * SF_TY) void k_fine3sf64(const Pack<OpA<double>, NB> pk, const SfCoef<double> cf,
+                                                             int nx, int ny, int nz, int tiles_x, int tiles_y,
+                                                             int zlen, double omega, double c1, double c2) {
+    __shared__ double cv[2][4][3][SF_TX * SF_TY];
+    fine3sf_body<double, OP, NB>(pk, cf, nx, ny, nz, tiles_x, tiles_y, zlen, omega, c1, c2, cv);
 }
 
 static int sf_tiles(int nn, int per) { return (nn + per - 1) / per; }
 
-// node planes per workgroup: enough workgroups for about four per compute
-// unit (each is four waves), one extra element layer per workgroup
-static int sf_zlen(int tiles, int nz_nodes) {
-    const int chunks = std::max(1, std::min(nz_nodes, 1024 / std::max(1, tiles)));
+// node planes per workgroup: enough workgroups for the chip's resident slots
+// (four per compute unit in FP32, two in FP64 for its registers), one extra
+// element layer per workgroup
+static int sf_zlen(int tiles, int nz_nodes, int slots) {
+    const int chunks = std::max(1, std::min(nz_nodes, slots / std::max(1, tiles)));
     return (int)ceil_div(nz_nodes, chunks);
+}
+
+// the tensor form's grid for the fine level of h (false: the level takes
+// another form): tiles in x and y, node planes per workgroup, workgroups
+static bool sf_grid(const tm_hierarchy* h, bool fp32, int& tx, int& ty, int& zl, int& nb) {
+    const Level& F = h->lv[0];
+    if (F.dim != 3 || !h->opt.fine_tensor || !h->sf_ok || (fp32 && h->opt.fine_mfma)) return false;
+    tx = sf_tiles(F.nn[0], SF_NX);
+    ty = sf_tiles(F.nn[1], SF_NY);
+    zl = h->opt.fine_tensor >= 2 ? h->opt.fine_tensor : sf_zlen(tx * ty, F.nn[2], fp32 ? 1024 : 512);
+    nb = (int)(tx * ty * ceil_div(F.nn[2], zl));
+    return true;
 }
 
 // 3D FP32 on the matrix cores, two nodes stacked in z per lane as in
@@ -985,7 +1043,13 @@ __global__ __launch_bounds__(WG) void k_fine2(const Pack<OpA<T>, NB> pk, const K
     if (OP == OP_QDOT) block_reduce_store<2>(dots, partials);
 }
 
-int fine_op_blocks(const tm_hierarchy* h) { return (int)grid_for(h->lv[0].n_nodes); }
+// workgroups of the FP64 operator with partial sums (q = K~p), i.e. the
+// partial sums it leaves per lane
+int fine_op_blocks(const tm_hierarchy* h) {
+    int tx, ty, zl, nb;
+    if (sf_grid(h, false, tx, ty, zl, nb)) return nb;
+    return (int)grid_for(h->lv[0].n_nodes);
+}
 
 template <typename T>
 static const T* pick_E(const Level& L);
@@ -1029,15 +1093,20 @@ static void fine_launch(const LaneIO* L, int n, T omega, double c1, double c2, h
         a.dout = (T*)L[q].dout;
     }
     const dim3 blk(WG);
-    if constexpr (std::is_same<T, float>::value && !MI && OP != OP_QDOT) {
-        if (F.dim == 3 && h->opt.fine_tensor && h->sf_ok && !h->opt.fine_mfma) {
-            const int tx = sf_tiles(F.nn[0], SF_NX), ty = sf_tiles(F.nn[1], SF_NY);
-            const int zl = h->opt.fine_tensor >= 2 ? h->opt.fine_tensor : sf_zlen(tx * ty, F.nn[2]);
-            const dim3 g((unsigned)(tx * ty * ceil_div(F.nn[2], zl)), n);
-            hipLaunchKernelGGL((k_fine3sf<OP, NB>), g, dim3(SF_TX * SF_TY), 0, s, pk, h->sf32, F.nel[0], F.nel[1],
-                               F.nel[2], tx, ty, zl, omega, c1, c2);
+    if constexpr (!MI && (std::is_same<T, double>::value || OP != OP_QDOT)) {
+        int tx, ty, zl, nb;
+        if (sf_grid(h, std::is_same<T, float>::value, tx, ty, zl, nb)) {
+            const dim3 g((unsigned)nb, n), bk(SF_TX * SF_TY);
+            if constexpr (std::is_same<T, float>::value)
+                hipLaunchKernelGGL((k_fine3sf<OP, NB>), g, bk, 0, s, pk, h->sf32, F.nel[0], F.nel[1], F.nel[2], tx,
+                                   ty, zl, omega, c1, c2);
+            else
+                hipLaunchKernelGGL((k_fine3sf64<OP, NB>), g, bk, 0, s, pk, h->sf64, F.nel[0], F.nel[1], F.nel[2],
+                                   tx, ty, zl, omega, c1, c2);
             return;
         }
+    }
+    if constexpr (std::is_same<T, float>::value && !MI && OP != OP_QDOT) {
         if (F.dim == 3) {
             const int64_t nt = (int64_t)F.nn[0] * F.nn[1] * ((F.nn[2] + 1) / 2);
             const dim3 g(grid_for(nt), n);

@@ -355,6 +355,7 @@ struct tm_hierarchy {
     tmi::KeVals<double> kc64{};       // KE symmetry-class values (fine operator arguments)
     tmi::KeVals<float> kc32{};
     tmi::SfCoef<float> sf32{};        // 3D KE in the tensor form (fine operator arguments)
+    tmi::SfCoef<double> sf64{};
     bool sf_ok = false;               // KE has the tensor form's structure
     double* ainv = nullptr;        // inverse of the coarsest operator (FP64, dense)
     float* ainv32 = nullptr;

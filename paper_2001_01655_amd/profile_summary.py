@@ -24,8 +24,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 COPY_BYTES = 256 << 20
 CLASSES = {
-    0: dict(match=["k_fine3<double, 3, false, 1>"], source=["kernels_fine.hip", "tm_device.h"],
-            what="fine operator FP64 (q = K~p, outer loop)"),
+    0: dict(match=["k_fine3sf64<3, 1>"], source=["kernels_fine.hip", "tm_device.h"],
+            what="fine operator FP64, tensor-product form (q = K~p, outer loop)"),
     1: dict(match=["k_fine3sf<1, 1>", "k_fine3sf<2, 1>", "k_fine3sf<4, 1>"],
             source=["kernels_fine.hip", "tm_device.h"],
             what="fine operator FP32, tensor-product form (V-cycle smoothing / residual)"),
