@@ -608,49 +608,45 @@ __device__ __forceinline__ void fine3sf_body(const Pack<OpA<T>, NB>& pk, const S
             }
     };
     T xo[3];            // the owned node's value in the plane being finished
-    Face FA, FB;
+    // the operands of one step: layer l's top face and modulus, and the
+    // finishing operands of node plane l
+    struct Ops {
+        Face f;
+        Fin n;
+    };
+    auto fetch = [&](int l, Ops& o) {
+        fetch_fin(l, o.n);
+        fetch_face(l, o.f);
+    };
+    Ops OA, OB;
     {
         // layer k0 - 1: only its top-face outputs (plane k0) are kept
         T v0[4][3];
         load_face(k0 - 1, v0);
-        fetch_face(k0 - 1, FA);
-        fetch_face(k0, FB);
+        Face F0;
+        fetch_face(k0 - 1, F0);
+        fetch(k0, OA);
         sf_face_modes(v0, fb);
 #pragma unroll
         for (int q = 0; q < 4; ++q)
 #pragma unroll
             for (int c = 0; c < 3; ++c) st[q][c] = T(0);
-        T v[4][3];
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) v[q][c] = FA.v[q][c];
-        const T Ee = FA.E * FA.w;
-        fetch_face(k0 + 1, FA);
         T pm[4][3];
-        layer(v, Ee, pm);
+        layer(F0.v, F0.E * F0.w, pm);
 #pragma unroll
-        for (int c = 0; c < 3; ++c) xo[c] = v[3][c];
+        for (int c = 0; c < 3; ++c) xo[c] = F0.v[3][c];
     }
-    // plane l from layer l (operand set S, refilled with layer l + 2: two
-    // sets alternate, the march being unrolled by two, so a set is refilled
-    // as soon as it is read, without copies of loads in flight); the
-    // finishing operands are issued before that refill, so that waiting for
-    // them after the layer's arithmetic leaves the refill in flight
+    // plane l from the operands C fetched during the previous step, while
+    // those of plane l + 1 are fetched into N (two sets alternate, the march
+    // being unrolled by two, so no set is copied while its loads are in
+    // flight and every load has a whole step to arrive)
     double dots[2] = {0.0, 0.0};
-    auto step = [&](int l, Face& S) {
-        T v[4][3];
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) v[q][c] = S.v[q][c];
-        const T Ee = S.E * S.w;
-        Fin fin;
-        fetch_fin(l, fin);
-        __builtin_amdgcn_sched_barrier(0);          // keep the issue order
-        fetch_face(l + 2, S);
+    auto step = [&](int l, const Ops& C, Ops& N) {
+        fetch(l + 1, N);
+        __builtin_amdgcn_sched_barrier(0);          // keep the next step's loads first
+        const Fin& fin = C.n;
         T pm[4][3];
-        layer(v, Ee, pm);
+        layer(C.f.v, C.f.E * C.f.w, pm);
         __builtin_amdgcn_sched_barrier(0);          // the finishing operands are read below
         const int buf = (l - k0) & 1;
 #pragma unroll
@@ -713,12 +709,12 @@ __device__ __forceinline__ void fine3sf_body(const Pack<OpA<T>, NB>& pk, const S
         bst3(yr, so, yv);
         if (OP == OP_CHEB) bst3(dor, so, dn);
 #pragma unroll
-        for (int c = 0; c < 3; ++c) xo[c] = v[3][c];
+        for (int c = 0; c < 3; ++c) xo[c] = C.f.v[3][c];
     };
     // an even number of steps (a last one past the range stores nothing)
     for (int l = k0; l < k1; l += 2) {
-        step(l, FB);
-        step(l + 1, FA);
+        step(l, OA, OB);
+        step(l + 1, OB, OA);
     }
     if (OP == OP_QDOT) block_reduce_store<2>(dots, A_.partials);
 }
@@ -754,6 +750,10 @@ static int sf_zlen(int tiles, int nz_nodes, int slots) {
 static bool sf_grid(const tm_hierarchy* h, bool fp32, int& tx, int& ty, int& zl, int& nb) {
     const Level& F = h->lv[0];
     if (F.dim != 3 || !h->opt.fine_tensor || !h->sf_ok || (fp32 && h->opt.fine_mfma)) return false;
+    // the form reaches the block inverse (six arrays of n_nodes) through a
+    // buffer descriptor with 32-bit offsets; setup keeps the vectors below
+    // 2 GiB, and an FP64 inverse of a grid beyond that takes the node gather
+    if ((int64_t)6 * F.n_nodes * (fp32 ? 4 : 8) >= ((int64_t)1 << 31)) return false;
     tx = sf_tiles(F.nn[0], SF_NX);
     ty = sf_tiles(F.nn[1], SF_NY);
     zl = h->opt.fine_tensor >= 2 ? h->opt.fine_tensor : sf_zlen(tx * ty, F.nn[2], fp32 ? 1024 : 512);
