@@ -106,7 +106,11 @@ typedef struct {
                               level size (levels of at least 256 workgroups of nodes take the
                               large-level kernel, smaller ones the latency-bound form); 1: the
                               large-level kernel on every level; 2: the small-level form on
-                              every level.  Same operator either way                        */
+                              every level; 3: as 0, but level 1 of a 3D grid with even element
+                              counts in the FP32 V-cycle applied from the fine moduli (the
+                              Galerkin product element by element in the tensor-product form,
+                              no stored stencil read; slower than the stored stencil on the
+                              grids measured).  Same operator either way                    */
     int32_t sa_lds;         /* aggregation setup: 0 (default) keeps a Galerkin product row's sums,
                               an aggregate's Gram-Schmidt rows and a prolongator row's blocks in
                               LDS when they fit; 1: never (block by block, in device memory).

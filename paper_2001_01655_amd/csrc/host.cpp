@@ -339,7 +339,7 @@ static void check_opts(const tm_options* o) {
     if (o->max_iters < 1) fail(TM_ERR_ARG, "max_iters must be >= 1");
     if (o->check_every < 0) fail(TM_ERR_ARG, "check_every must be >= 0");
     if (o->fine_mfma != 0 && o->fine_mfma != 1) fail(TM_ERR_ARG, "fine_mfma must be 0 or 1");
-    if (o->stencil_kernel < 0 || o->stencil_kernel > 2) fail(TM_ERR_ARG, "stencil_kernel must be 0, 1 or 2");
+    if (o->stencil_kernel < 0 || o->stencil_kernel > 3) fail(TM_ERR_ARG, "stencil_kernel must be 0, 1, 2 or 3");
     if (o->sa_lds < 0 || o->sa_lds > 1) fail(TM_ERR_ARG, "sa_lds must be 0 or 1");
     if (o->fine_tensor < 0 || o->fine_tensor > 4096) fail(TM_ERR_ARG, "fine_tensor must be in 0..4096");
     if (o->n_levels > 0 && o->n_geometric > o->n_levels) fail(TM_ERR_ARG, "n_geometric > n_levels");
@@ -446,7 +446,7 @@ static void alloc_level_geo(tm_hierarchy* h, Level& L, int l) {
         L.nst = dim == 3 ? 27 : 9;
         L.st64 = halloc<double>(h, (size_t)L.nst * bb * L.n_nodes);
         L.nq = (L.nst - 1) / 2 * bb + dim * (dim + 1) / 2;
-        L.op_kernel = h->opt.stencil_kernel;
+        L.op_kernel = h->opt.stencil_kernel == 3 ? 0 : h->opt.stencil_kernel;    // 3: level 1 aside, by size
         L.stc64 = halloc<double>(h, (size_t)L.nq * L.n_nodes);
         L.stc32 = halloc<float>(h, (size_t)L.nq * L.n_nodes);
     }
@@ -1065,7 +1065,7 @@ static std::string shape_key(const tm_hierarchy* h) {
     put(&h->nc, sizeof(h->nc));
     put(h->kc64.k, sizeof(h->kc64.k));
     for (const Level& L : h->lv) {
-        const int li[] = {L.kind, L.bs, L.nel[0], L.nel[1], L.nel[2], (int)L.xfer_bsr, L.op_kernel};
+        const int li[] = {L.kind, L.bs, L.nel[0], L.nel[1], L.nel[2], (int)L.xfer_bsr, L.op_kernel, L.subf ? 1 : 0};
         put(li, sizeof(li));
         put(&L.n, sizeof(L.n));
     }
@@ -1745,6 +1745,30 @@ tm_status tm_setup(const tm_mesh* mesh, const tm_material* mat, const double* rh
         std::vector<uint8_t> nm(n_nodes, 0);
         for (int64_t d : fixed) nm[d / dim] |= (uint8_t)(1u << (d % dim));
         TM_HIP(hipMemcpyAsync(h->lv[0].nmask, nm.data(), n_nodes, hipMemcpyHostToDevice, s));
+        // level 1 in the tensor form (stencil_kernel 3): 3D, fine element counts
+        // even (each level-1 element holds 2 x 2 x 2 fine ones), the form's KE
+        // structure
+        std::vector<uint8_t> subf;
+        if (dim == 3 && plan.Lg > 1 && h->sf_ok && opts->stencil_kernel == 3 &&
+            mesh->nel[0] % 2 == 0 && mesh->nel[1] % 2 == 0 && mesh->nel[2] % 2 == 0) {
+            const Level& C1 = h->lv[1];
+            const int64_t NX = mesh->nel[0] + 1, PLf = NX * (mesh->nel[1] + 1);
+            subf.assign((size_t)level_elems(C1, 3), 0);
+            for (int cz = 0; cz < C1.nel[2]; ++cz)
+                for (int cy = 0; cy < C1.nel[1]; ++cy)
+                    for (int cx = 0; cx < C1.nel[0]; ++cx) {
+                        uint8_t f = 0;
+                        for (int k = 0; k < 8; ++k)
+                            for (int c = 0; c < 8; ++c) {
+                                const int64_t fx = 2 * cx + (k & 1) + (c & 1), fy = 2 * cy + ((k >> 1) & 1) + ((c >> 1) & 1),
+                                              fz = 2 * cz + (k >> 2) + (c >> 2);
+                                if (nm[fz * PLf + fy * NX + fx]) f |= (uint8_t)(1u << k);
+                            }
+                        subf[((size_t)cz * C1.nel[1] + cy) * C1.nel[0] + cx] = f;
+                    }
+            h->lv[1].subf = halloc<uint8_t>(h, subf.size());
+            TM_HIP(hipMemcpyAsync(h->lv[1].subf, subf.data(), subf.size(), hipMemcpyHostToDevice, s));
+        }
         const int nd = dim * (1 << dim);
         if (plan.Lg > 1) h->elem_a = halloc<double>(h, (size_t)level_elems(h->lv[1], dim) * nd * nd);
         if (plan.Lg > 2) h->elem_b = halloc<double>(h, (size_t)level_elems(h->lv[2], dim) * nd * nd);

@@ -810,6 +810,12 @@ template <typename T>
 void launch_stencil_op_b(int level, int op, const LaneIO* L, int n, T omega, double c1, double c2,
                          hipStream_t s) {
     if (n < 1) return;
+    if constexpr (std::is_same<T, float>::value) {
+        if (level == 1 && L[0].h->lv[1].subf) {
+            launch_coarse1_tensor_b<T>(op, L, n, omega, c1, c2, s);
+            return;
+        }
+    }
     const int dim = L[0].h->lv[level].dim;
     for (int q0 = 0; q0 < n; q0 += MAXB) {
         const int m = std::min(MAXB, n - q0);

@@ -502,8 +502,80 @@ __device__ __forceinline__ void bst3(__amdgpu_buffer_rsrc_t r, uint32_t off, con
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v[2]), r, off + 16, 0, 0);
 }
 
+// Level 1 in the tensor form.  With every fine element count even, each
+// level-1 element holds 2 x 2 x 2 fine elements, and the Galerkin product is
+// the sum over them of P_k^T (E_k M_k KE M_k) P_k (P_k the trilinear
+// interpolation from the element's corners to sub-element k's, M_k the
+// supports).  Per axis, in sum / difference modes, P_k maps (sigma, delta) to
+// (sigma -+ delta / 2, delta / 2) for the lower / upper half, and its
+// transpose maps output modes back as (sigma, (delta -+ sigma) / 2); the
+// sub-element's modes then take the 45 couplings like a fine element.
+template <int A, typename T>
+__device__ __forceinline__ void sf_half(T (&m)[8][3], int h) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+        if (!((i >> A) & 1)) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const T d = m[i | (1 << A)][c] * T(0.5);
+                m[i][c] = h ? m[i][c] + d : m[i][c] - d;
+                m[i | (1 << A)][c] = d;
+            }
+        }
+}
+template <int A, typename T>
+__device__ __forceinline__ void sf_half_t(T (&m)[8][3], int h) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+        if (!((i >> A) & 1)) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const T sg = m[i][c], dl = m[i | (1 << A)][c];
+                m[i | (1 << A)][c] = (h ? dl + sg : dl - sg) * T(0.5);
+            }
+        }
+}
+// a sub-element with supported dofs: modes to corner values (corner index
+// lx | ly << 1 | lz << 2), supported components zeroed, back to modes; IN
+// selects the input side (values = F^-1 modes, modes = F values) or the output
+// side (values = F^T modes, modes = F^-T values)
+template <bool IN, typename T>
+__device__ __forceinline__ void sf_mask(T (&m)[8][3], const uint32_t (&mk)[8]) {
+#pragma unroll
+    for (int A = 0; A < 3; ++A)
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+            if (!((i >> A) & 1)) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const T a = m[i][c], b = m[i | (1 << A)][c];
+                    m[i][c] = IN ? (a - b) * T(0.5) : a - b;
+                    m[i | (1 << A)][c] = IN ? (a + b) * T(0.5) : a + b;
+                }
+            }
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            if ((mk[i] >> c) & 1u) m[i][c] = T(0);
+#pragma unroll
+    for (int A = 0; A < 3; ++A)
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+            if (!((i >> A) & 1)) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const T a = m[i][c], b = m[i | (1 << A)][c];
+                    m[i][c] = IN ? a + b : (a + b) * T(0.5);
+                    m[i | (1 << A)][c] = IN ? b - a : (b - a) * T(0.5);
+                }
+            }
+}
+
 // cv: the plane's corner values per element column, two buffers (LDS)
-template <typename T, int OP, int NB>
+// GAL: level 1 in the tensor form (nx, ny, nz its element counts; E, nm the
+// fine level's moduli and supports; no supports on level 1 itself)
+template <typename T, int OP, int NB, bool GAL = false>
 __device__ __forceinline__ void fine3sf_body(const Pack<OpA<T>, NB>& pk, const SfCoef<T>& cf, int nx, int ny,
                                              int nz, int tiles_x, int tiles_y, int zlen, T omega, double c1,
                                              double c2, T (&cv)[2][4][3][SF_TX * SF_TY]) {
@@ -538,8 +610,11 @@ __device__ __forceinline__ void fine3sf_body(const Pack<OpA<T>, NB>& pk, const S
     // the range) gets an offset past the descriptor's end, which the hardware
     // drops; with no direction output the direction descriptor is empty.
     const auto xr = buf_rsrc(A_.x, (int64_t)N * NBY);
-    const auto er = buf_rsrc(A_.E, (int64_t)EP * nz * sizeof(T));
-    const auto mr = buf_rsrc(A_.nm, (int64_t)N);
+    const auto er = buf_rsrc(A_.E, (int64_t)EP * nz * (GAL ? 8 : 1) * sizeof(T));
+    const auto mr = buf_rsrc(A_.nm, GAL ? (int64_t)(2 * nx + 1) * (2 * ny + 1) * (2 * nz + 1) : (int64_t)N);
+    const auto fr = buf_rsrc(A_.sub, GAL ? (int64_t)EP * nz : 0);
+    // GAL: the clamped element column (every index stays in bounds)
+    const uint32_t exc = (uint32_t)min(max(ex, 0), nx - 1), eyc = (uint32_t)min(max(ey, 0), ny - 1);
     const auto brs = buf_rsrc(A_.b, OP == OP_APPLY ? 0 : (int64_t)N * NBY);
     const auto dr = buf_rsrc(A_.dinv, OP == OP_SMOOTH || OP == OP_CHEB ? (int64_t)6 * N * sizeof(T) : 0);
     const auto inr = buf_rsrc(A_.din, OP == OP_CHEB ? (int64_t)N * NBY : 0);
@@ -556,12 +631,26 @@ __device__ __forceinline__ void fine3sf_body(const Pack<OpA<T>, NB>& pk, const S
     // layer is used, so that nothing waits for the load when it is issued)
     struct Face {
         T v[4][3];
-        T E, w;
+        T E[GAL ? 8 : 1], w;
+        uint32_t f;     // GAL: sub-element support flags
     };
     auto fetch_face = [&](int l, Face& F) {
         load_face(l + 1, F.v);
         const uint32_t lz = (uint32_t)min(max(l, 0), nz - 1);
-        F.E = bld<T>(er, (lz * EP + ecix) * (uint32_t)sizeof(T));
+        if constexpr (GAL) {
+            // the eight fine moduli, two consecutive ones per (z, y) pair
+            const uint32_t FX = 2u * (uint32_t)nx, FP = FX * 2u * (uint32_t)ny;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                T e2[2];
+                bld2(er, (((2u * lz + (q >> 1)) * FP) + (2u * eyc + (q & 1)) * FX + 2u * exc) * (uint32_t)sizeof(T), e2);
+                F.E[2 * q] = e2[0];
+                F.E[2 * q + 1] = e2[1];
+            }
+            F.f = __builtin_amdgcn_raw_buffer_load_b8(fr, lz * EP + eyc * (uint32_t)nx + exc, 0, 0);
+        } else {
+            F.E[0] = bld<T>(er, (lz * EP + ecix) * (uint32_t)sizeof(T));
+        }
         F.w = (ecol && l >= 0 && l < nz) ? T(1) : T(0);
     };
     // finishing operands of the owned node in plane l
@@ -578,26 +667,80 @@ __device__ __forceinline__ void fine3sf_body(const Pack<OpA<T>, NB>& pk, const S
             for (int e = 0; e < 6; ++e) f.dv[e] = bld<T>(dr, ((uint32_t)e * N + nd) * (uint32_t)sizeof(T));
         }
         if (OP == OP_CHEB) bld3(inr, nd * NBY, f.din);
-        f.m = __builtin_amdgcn_raw_buffer_load_b8(mr, nd, 0, 0);
+        f.m = GAL ? 0u : __builtin_amdgcn_raw_buffer_load_b8(mr, nd, 0, 0);
     };
     // element layer l from its top face S and the bottom face's modes fb:
     // the plane-l face modes pm (this layer's bottom plus the layer below's
     // top, st), and st, fb for the next layer
     T fb[4][3], st[4][3];
-    auto layer = [&](const T (&v)[4][3], T Ee, T (&pm)[4][3]) {
+    // GAL: the supports of sub-element k's corners (fine nodes, clamped)
+    auto sub_masks = [&](int l, int k, uint32_t (&mk)[8]) {
+        const uint32_t FNX = 2u * (uint32_t)nx + 1u, FPL = FNX * (2u * (uint32_t)ny + 1u);
+        const uint32_t lz = (uint32_t)min(max(l, 0), nz - 1);
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const uint32_t fx = 2u * exc + (k & 1) + (c & 1), fy = 2u * eyc + ((k >> 1) & 1) + ((c >> 1) & 1);
+            const uint32_t fz = 2u * lz + (k >> 2) + (c >> 2);
+            mk[c] = __builtin_amdgcn_raw_buffer_load_b8(mr, fz * FPL + fy * FNX + fx, 0, 0);
+        }
+    };
+    auto layer = [&](int l, const T (&v)[4][3], const Face& F, T (&pm)[4][3]) {
         T ft[4][3];
         sf_face_modes(v, ft);
         T md[8][3], o[8][3];
+        const T Ee = F.E[0] * F.w;
 #pragma unroll
         for (int q = 0; q < 4; ++q)
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                md[q][c] = Ee * (ft[q][c] + fb[q][c]);
-                md[q + 4][c] = Ee * (ft[q][c] - fb[q][c]);
+                md[q][c] = GAL ? ft[q][c] + fb[q][c] : Ee * (ft[q][c] + fb[q][c]);
+                md[q + 4][c] = GAL ? ft[q][c] - fb[q][c] : Ee * (ft[q][c] - fb[q][c]);
                 o[q][c] = T(0);
                 o[q + 4][c] = T(0);
             }
-        sf_couple<0, T>(cf, md, o);
+        if constexpr (GAL) {
+            // the eight sub-elements, in a fixed order (x fastest), one at a
+            // time (unrolled, their registers would not fit)
+#pragma unroll 1
+            for (int k = 0; k < 8; ++k) {
+                T mf[8][3], of[8][3];
+#pragma unroll
+                for (int i = 0; i < 8; ++i)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        mf[i][c] = md[i][c];
+                        of[i][c] = T(0);
+                    }
+                sf_half<0>(mf, k & 1);
+                sf_half<1>(mf, (k >> 1) & 1);
+                sf_half<2>(mf, k >> 2);
+                const bool msk = (F.f >> k) & 1u;
+                uint32_t mk[8];
+                if (msk) {
+                    sub_masks(l, k, mk);
+                    sf_mask<true>(mf, mk);
+                }
+                T ek = F.E[0];
+#pragma unroll
+                for (int q = 1; q < 8; ++q) ek = k == q ? F.E[q] : ek;
+                ek *= F.w;
+#pragma unroll
+                for (int i = 0; i < 8; ++i)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) mf[i][c] *= ek;
+                sf_couple<0, T>(cf, mf, of);
+                if (msk) sf_mask<false>(of, mk);
+                sf_half_t<0>(of, k & 1);
+                sf_half_t<1>(of, (k >> 1) & 1);
+                sf_half_t<2>(of, k >> 2);
+#pragma unroll
+                for (int i = 0; i < 8; ++i)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) o[i][c] += of[i][c];
+            }
+        } else {
+            sf_couple<0, T>(cf, md, o);
+        }
 #pragma unroll
         for (int q = 0; q < 4; ++q)
 #pragma unroll
@@ -625,28 +768,26 @@ __device__ __forceinline__ void fine3sf_body(const Pack<OpA<T>, NB>& pk, const S
         load_face(k0 - 1, v0);
         Face F0;
         fetch_face(k0 - 1, F0);
-        fetch(k0, OA);
+        if (!GAL) fetch(k0, OA);
         sf_face_modes(v0, fb);
 #pragma unroll
         for (int q = 0; q < 4; ++q)
 #pragma unroll
             for (int c = 0; c < 3; ++c) st[q][c] = T(0);
         T pm[4][3];
-        layer(F0.v, F0.E * F0.w, pm);
+        layer(k0 - 1, F0.v, F0, pm);
 #pragma unroll
         for (int c = 0; c < 3; ++c) xo[c] = F0.v[3][c];
     }
-    // plane l from the operands C fetched during the previous step, while
-    // those of plane l + 1 are fetched into N (two sets alternate, the march
-    // being unrolled by two, so no set is copied while its loads are in
-    // flight and every load has a whole step to arrive)
+    // plane l from the operands C, fetched during the previous step while the
+    // next ones go to the other set (two sets alternate, the march being
+    // unrolled by two, so no set is copied while its loads are in flight and
+    // every load has a whole step to arrive)
     double dots[2] = {0.0, 0.0};
-    auto step = [&](int l, const Ops& C, Ops& N) {
-        fetch(l + 1, N);
-        __builtin_amdgcn_sched_barrier(0);          // keep the next step's loads first
+    auto step = [&](int l, const Ops& C) {
         const Fin& fin = C.n;
         T pm[4][3];
-        layer(C.f.v, C.f.E * C.f.w, pm);
+        layer(l, C.f.v, C.f, pm);
         __builtin_amdgcn_sched_barrier(0);          // the finishing operands are read below
         const int buf = (l - k0) & 1;
 #pragma unroll
@@ -711,10 +852,23 @@ __device__ __forceinline__ void fine3sf_body(const Pack<OpA<T>, NB>& pk, const S
 #pragma unroll
         for (int c = 0; c < 3; ++c) xo[c] = C.f.v[3][c];
     };
-    // an even number of steps (a last one past the range stores nothing)
-    for (int l = k0; l < k1; l += 2) {
-        step(l, OA, OB);
-        step(l + 1, OB, OA);
+    if constexpr (GAL) {
+        // level 1 is bound by its arithmetic: each step fetches its own operands
+        for (int l = k0; l < k1; ++l) {
+            Ops C;
+            fetch(l, C);
+            step(l, C);
+        }
+    } else {
+        // an even number of steps (a last one past the range stores nothing)
+        for (int l = k0; l < k1; l += 2) {
+            fetch(l + 1, OB);
+            __builtin_amdgcn_sched_barrier(0);      // keep the next step's loads first
+            step(l, OA);
+            fetch(l + 2, OA);
+            __builtin_amdgcn_sched_barrier(0);
+            step(l + 1, OB);
+        }
     }
     if (OP == OP_QDOT) block_reduce_store<2>(dots, A_.partials);
 }
@@ -725,6 +879,14 @@ __global__ __launch_bounds__(SF_TX * SF_TY) __attribute__((amdgpu_waves_per_eu(4
     int zlen, float omega, double c1, double c2) {
     __shared__ float cv[2][4][3][SF_TX * SF_TY];
     fine3sf_body<float, OP, NB>(pk, cf, nx, ny, nz, tiles_x, tiles_y, zlen, omega, c1, c2, cv);
+}
+
+template <typename T, int OP, int NB>
+__global__ __launch_bounds__(SF_TX * SF_TY) void k_coarse1sf(const Pack<OpA<T>, NB> pk, const SfCoef<T> cf, int nx,
+                                                             int ny, int nz, int tiles_x, int tiles_y, int zlen,
+                                                             T omega, double c1, double c2) {
+    __shared__ T cv[2][4][3][SF_TX * SF_TY];
+    fine3sf_body<T, OP, NB, true>(pk, cf, nx, ny, nz, tiles_x, tiles_y, zlen, omega, c1, c2, cv);
 }
 
 template <int OP, int NB>
@@ -1042,6 +1204,64 @@ __global__ __launch_bounds__(WG) void k_fine2(const Pack<OpA<T>, NB> pk, const K
     if (live) finish_store<T, 2, OP>(node, acc, xo, mo, fin, y, omega, dots, ch);
     if (OP == OP_QDOT) block_reduce_store<2>(dots, partials);
 }
+
+// level 1 in the tensor form for lanes L[0..n) (n <= NB): the lanes' own
+// level-1 vectors and block inverses, their fine moduli and supports
+template <typename T>
+static const SfCoef<T>& pick_sf(const tm_hierarchy* h);
+template <>
+const SfCoef<float>& pick_sf<float>(const tm_hierarchy* h) { return h->sf32; }
+template <>
+const SfCoef<double>& pick_sf<double>(const tm_hierarchy* h) { return h->sf64; }
+
+template <typename T, int OP, int NB>
+static void coarse1_launch(const LaneIO* L, int n, T omega, double c1, double c2, hipStream_t s) {
+    const tm_hierarchy* h = L[0].h;
+    const Level& C1 = h->lv[1];
+    Pack<OpA<T>, NB> pk{};
+    for (int q = 0; q < n; ++q) {
+        const Level& F = L[q].h->lv[0];
+        const Level& V = L[q].h->lv[1];
+        OpA<T>& a = pk.a[q];
+        a.E = pick_E<T>(F);
+        a.nm = F.nmask;
+        a.sub = V.subf;
+        a.x = (const T*)L[q].x;
+        a.b = (const T*)L[q].b;
+        a.y = (T*)L[q].y;
+        a.dinv = pick_dinv<T>(V);
+        a.done = L[q].done;
+        a.din = (const T*)L[q].din;
+        a.dout = (T*)L[q].dout;
+    }
+    const int tx = sf_tiles(C1.nn[0], SF_NX), ty = sf_tiles(C1.nn[1], SF_NY);
+    const int zl = sf_zlen(tx * ty, C1.nn[2], 512);
+    const dim3 g((unsigned)(tx * ty * ceil_div(C1.nn[2], zl)), n), bk(SF_TX * SF_TY);
+    hipLaunchKernelGGL((k_coarse1sf<T, OP, NB>), g, bk, 0, s, pk, pick_sf<T>(h), C1.nel[0], C1.nel[1], C1.nel[2], tx,
+                       ty, zl, omega, c1, c2);
+}
+
+template <typename T, int OP>
+static void coarse1_dispatch(const LaneIO* L, int n, T omega, double c1, double c2, hipStream_t s) {
+    for (int q0 = 0; q0 < n; q0 += MAXB) {
+        const int m = std::min(MAXB, n - q0);
+        if (m == 1) coarse1_launch<T, OP, 1>(L + q0, 1, omega, c1, c2, s);
+        else coarse1_launch<T, OP, MAXB>(L + q0, m, omega, c1, c2, s);
+    }
+}
+
+template <typename T>
+void launch_coarse1_tensor_b(int op, const LaneIO* L, int n, T omega, double c1, double c2, hipStream_t s) {
+    if (n < 1) return;
+    switch (op) {
+        case OP_APPLY: coarse1_dispatch<T, OP_APPLY>(L, n, omega, c1, c2, s); break;
+        case OP_RESID: coarse1_dispatch<T, OP_RESID>(L, n, omega, c1, c2, s); break;
+        case OP_SMOOTH: coarse1_dispatch<T, OP_SMOOTH>(L, n, omega, c1, c2, s); break;
+        case OP_CHEB: coarse1_dispatch<T, OP_CHEB>(L, n, omega, c1, c2, s); break;
+        default: fail(TM_ERR_ARG, "level-1 tensor form: no partial sums");
+    }
+}
+template void launch_coarse1_tensor_b<float>(int, const LaneIO*, int, float, double, double, hipStream_t);
 
 // workgroups of the FP64 operator with partial sums (q = K~p), i.e. the
 // partial sums it leaves per lane

@@ -193,6 +193,7 @@ struct OpA {
     const T* din;        // Chebyshev step: previous direction (or the iterate) ...
     T* dout;             // ... and the new direction (NULL: not kept)
     const T* xc;         // fused prolongation: the coarse level's correction
+    const uint8_t* sub;  // level 1 in the tensor form: sub-element support flags
 };
 template <typename T>
 struct RestrictA {
@@ -274,6 +275,11 @@ struct Level {
     // neighbours' stored ones
     int nq = 0;
     int op_kernel = 0;            // stencil operator kernel: 0 by size, 1 large-level, 2 small-level
+    // level 1 applied matrix-free in the tensor form (Galerkin product of the
+    // fine elements, which an even fine grid nests two per axis in each
+    // element): subf[element] bit k set <=> fine sub-element k (x, y, z bits)
+    // has a supported dof
+    uint8_t* subf = nullptr;
     double* stc64 = nullptr;
     float* stc32 = nullptr;
     // aggregation level operator
@@ -480,6 +486,10 @@ template <typename T>
 void launch_fine_op_b(int op, bool mask_in, const LaneIO* L, int n, T omega, double c1, double c2, hipStream_t s);
 template <typename T>
 void launch_stencil_op_b(int level, int op, const LaneIO* L, int n, T omega, double c1, double c2, hipStream_t s);
+// level 1 in the tensor form (the level's subf set; FP32 V-cycle): the
+// operator from the fine moduli and supports instead of the stored stencil
+template <typename T>
+void launch_coarse1_tensor_b(int op, const LaneIO* L, int n, T omega, double c1, double c2, hipStream_t s);
 template <typename T>
 void launch_restrict_b(int fine_level, const LaneIO* L, int n, T omega, hipStream_t s);
 template <typename T>

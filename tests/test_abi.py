@@ -63,7 +63,7 @@ def _setup_status(nel=(8, 4), nu=0.3, Emin=1e-9, E0=1.0, dofs=(0, 1), **opts):
     (dict(adapt_iters=-1), "adapt_iters"),
     (dict(cheb_warm_steps=-1), "cheb_warm_steps"),
     (dict(cheb_warm_steps=13), "cheb_warm_steps"),
-    (dict(stencil_kernel=3), "stencil_kernel"),
+    (dict(stencil_kernel=4), "stencil_kernel"),
     (dict(sa_lds=2), "sa_lds"),
     (dict(fine_tensor=-1), "fine_tensor"),
 ])
