@@ -115,15 +115,16 @@ typedef struct {
                               an aggregate's Gram-Schmidt rows and a prolongator row's blocks in
                               LDS when they fit; 1: never (block by block, in device memory).
                               The levels are bitwise the same either way                     */
-    int32_t fine_tensor;    /* form of the FP32 3D fine operator in the V-cycle: 1 (default) the
-                              tensor-product form: in per-axis sum / difference modes of an
-                              element's corner values KE has 45 couplings instead of 576
-                              entries; a workgroup marches 16 x 16 element columns up a range of
-                              node planes and adds each node's corner values through LDS;
-                              n >= 2: the same with n node planes per workgroup (default: from
-                              the grid's size); 0: the node gather (27 neighbours, KE class
-                              values).  fine_mfma = 1 takes precedence.  Same operator; only
-                              the rounding differs                                            */
+    int32_t fine_tensor;    /* form of the 3D fine operators (FP32 in the V-cycle, FP64 for the
+                              outer q = K~p and the FP64 V-cycle): 1 (default) the tensor-product
+                              form: in per-axis sum / difference modes of an element's corner
+                              values KE has 45 couplings instead of 576 entries; a workgroup
+                              marches 32 x 8 element columns up a range of node planes and adds
+                              each node's corner values through LDS; n >= 2: the same with n
+                              node planes per workgroup (default: from the grid's size); 0: the
+                              node gather (27 neighbours, KE class values).  fine_mfma = 1 takes
+                              precedence for the FP32 operator.  Same operator; only the
+                              rounding differs                                                */
 } tm_options;
 
 /* Source of a hierarchy's device memory (levels, solve states, work vectors,
