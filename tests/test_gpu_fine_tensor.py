@@ -1,7 +1,7 @@
 """The 3D fine operator in the tensor-product form (option fine_tensor):
 the matrix-free operator K~ = sum_e E_e KE of Sec. 3.1, with KE applied as 45
 couplings between per-axis sum / difference modes of an element's corner
-values, element columns marched up node planes in 16 x 16 blocks.
+values, element columns marched up node planes in 32 x 8 blocks.
 
 Checked through the V-cycle (every smoothing step and residual of the fine
 level runs this operator) against the oracle's V-cycle and against the node
