@@ -438,7 +438,9 @@ __global__ __launch_bounds__(WG) void k_fine3z2(const Pack<OpA<T>, NB> pk, const
     if (live && two) finish_store<T, 3, OP>(nd1, acc1, xo1, m1, fin1, y, omega, dots, ch);
 }
 
-// 3D FP32 in the tensor-product form (SfSlots).  A workgroup owns a tile of
+// 3D fine operator in the tensor-product form (SfSlots), FP32 for the V-cycle
+// and FP64 for the outer q = K~p (with its partial sums) and the FP64 V-cycle.
+// A workgroup owns a tile of
 // SF_NX x SF_NY node columns and a range of node planes; its SF_TX x SF_TY threads
 // are the element columns around the tile (one ring beyond it, so every owned
 // node has all of its elements), each marching up its column one element
@@ -455,7 +457,9 @@ __global__ __launch_bounds__(WG) void k_fine3z2(const Pack<OpA<T>, NB> pk, const
 //   of its four element columns (own column first, then +x, +y, +x+y) and
 //   finishes as the node-gather form does.
 // An element outside the grid has modulus zero; the corner loads of such
-// columns read clamped in-grid nodes, so every value stays finite.
+// columns read clamped in-grid nodes, so every value stays finite.  The tile
+// is 32 x 8 columns: wider rows coalesce better, narrower tiles repeat more
+// columns in their halo ring.
 constexpr int SF_TX = 32, SF_TY = 8;                // element columns per tile
 constexpr int SF_NX = SF_TX - 1, SF_NY = SF_TY - 1;  // owned node columns per tile
 
@@ -899,12 +903,27 @@ __global__ __launch_bounds__(SF_TX * SF_TY) void k_fine3sf64(const Pack<OpA<doub
 
 static int sf_tiles(int nn, int per) { return (nn + per - 1) / per; }
 
-// node planes per workgroup: enough workgroups for the chip's resident slots
-// (four per compute unit in FP32, two in FP64 for its registers), one extra
-// element layer per workgroup
+// node planes per workgroup.  The grid runs in rounds of `slots` resident
+// workgroups (four per compute unit in FP32, two in FP64 for its registers);
+// each workgroup also recomputes one element layer below its range.  Take the
+// number of plane ranges whose grid fills its last round best, weighed by that
+// extra layer (fill x planes / (planes + 1)), the fewest ranges on a tie.
 static int sf_zlen(int tiles, int nz_nodes, int slots) {
-    const int chunks = std::max(1, std::min(nz_nodes, slots / std::max(1, tiles)));
-    return (int)ceil_div(nz_nodes, chunks);
+    tiles = std::max(1, tiles);
+    int best_c = 1;
+    double best = -1.0;
+    const int cmax = std::max(1, std::min(nz_nodes, 8 * slots / tiles));
+    for (int c = 1; c <= cmax; ++c) {
+        const int zl = (int)ceil_div(nz_nodes, c);
+        const int64_t w = (int64_t)tiles * ceil_div(nz_nodes, zl);
+        const double fill = (double)w / (double)(ceil_div(w, slots) * slots);
+        const double eff = fill * zl / (zl + 1.0);
+        if (eff > best + 1e-12) {
+            best = eff;
+            best_c = c;
+        }
+    }
+    return (int)ceil_div(nz_nodes, best_c);
 }
 
 // the tensor form's grid for the fine level of h (false: the level takes
