@@ -170,6 +170,14 @@ def vcycle_mix(smoother, nu):
     return pre + [(False, False, False)] + post
 
 
+def fine_prolong_fused(H, p, args):
+    """True where the fine level's first post-smoothing step carries the
+    prolongation from level 1 (3D, FP32 tensor form, level 1 geometric, every
+    element count even): that launch counts with the fine FP32 operator."""
+    return (p.dim == 3 and args.fine_tensor != 0 and not args.fine_mfma and H.num_levels() >= 2
+            and H.level_info(1)["kind"] == 1 and all(n % 2 == 0 for n in p.nel))
+
+
 def algorithmic(cls, H, p, args):
     """(flops, bytes) one launch of the class must do, averaged over the
     launches of a V-cycle: the operator's own arithmetic and each operand read
@@ -187,6 +195,10 @@ def algorithmic(cls, H, p, args):
         # x, b (r), y per node, modulus per element, support mask per node,
         # plus the smoother's operands (V-cycle launches only)
         byts = 3 * dim * w * n_nodes + w * n_el + n_nodes + (0 if cls == 0 else extra(w) * n_nodes)
+        if cls == 1 and fine_prolong_fused(H, p, args):
+            # the first post-smoothing step also reads the level-1 correction
+            n1 = H.level_info(1)["n_rows"]
+            byts += w * n1 / len(mix)
         return flops, byts
     # level-1 operator, stored in symmetric form: the blocks towards the upper
     # half of the neighbours plus the diagonal block's upper triangle; the

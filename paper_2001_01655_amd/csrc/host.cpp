@@ -791,9 +791,11 @@ static void vcycle_b(const VLane<T>* lanes, int n, hipStream_t s, bool first_don
     for (int l = L - 2; l >= 0; --l) {
         std::vector<T*>& x = xr[l];
         std::vector<T*>& t = tr[l];
-        // small geometric levels below a geometric level take the prolongation
-        // inside their first post-smoothing step
-        const bool fused = stencil_pro_ok(h0, l);
+        // small geometric levels below a geometric level, and the 3D fine level
+        // in the FP32 tensor form, take the prolongation inside their first
+        // post-smoothing step
+        const bool fine_fused = l == 0 && std::is_same<T, float>::value && fine_pro_ok(h0);
+        const bool fused = fine_fused || stencil_pro_ok(h0, l);
         if (!fused) {
             for (int q = 0; q < n; ++q) {
                 io[q].x = xr[l + 1][q];
@@ -816,7 +818,13 @@ static void vcycle_b(const VLane<T>* lanes, int n, hipStream_t s, bool first_don
                     io[q].din = nullptr;
                     io[q].dout = cheb && npost > 1 ? lanes[q].V->d[l] : nullptr;
                 }
-                launch_stencil_pro_b<T>(l, cheb ? OP_CHEB : OP_SMOOTH, io.data(), n, (T)h0->opt.omega, c1, c2, s);
+                if (fine_fused) {
+                    hipEvent_t e0 = nullptr;
+                    timed_begin(h0, 1, s, &e0);
+                    launch_fine_pro_b(cheb ? OP_CHEB : OP_SMOOTH, io.data(), n, (float)h0->opt.omega, c1, c2, s);
+                    timed_end(h0, 1, s, e0);
+                } else
+                    launch_stencil_pro_b<T>(l, cheb ? OP_CHEB : OP_SMOOTH, io.data(), n, (T)h0->opt.omega, c1, c2, s);
                 for (int q = 0; q < n; ++q) io[q].xc = nullptr;
             } else {
                 smooth(l, k, false, k == npost - 1, x, dst);

@@ -578,8 +578,12 @@ __device__ __forceinline__ void sf_mask(T (&m)[8][3], const uint32_t (&mk)[8]) {
 
 // cv: the plane's corner values per element column, two buffers (LDS)
 // GAL: level 1 in the tensor form (nx, ny, nz its element counts; E, nm the
-// fine level's moduli and supports; no supports on level 1 itself)
-template <typename T, int OP, int NB, bool GAL = false>
+// fine level's moduli and supports; no supports on level 1 itself).
+// PRO: the iterate is x + P~ xc (xc the level-1 correction, P~ the trilinear
+// prolongation with the supported dofs left out, fine counts even), formed
+// as each face is loaded: the first post-smoothing step with the prolongation
+// in it (nothing stores x + P~ xc itself)
+template <typename T, int OP, int NB, bool GAL = false, bool PRO = false>
 __device__ __forceinline__ void fine3sf_body(const Pack<OpA<T>, NB>& pk, const SfCoef<T>& cf, int nx, int ny,
                                              int nz, int tiles_x, int tiles_y, int zlen, T omega, double c1,
                                              double c2, T (&cv)[2][4][3][SF_TX * SF_TY]) {
@@ -621,14 +625,83 @@ __device__ __forceinline__ void fine3sf_body(const Pack<OpA<T>, NB>& pk, const S
     const uint32_t exc = (uint32_t)min(max(ex, 0), nx - 1), eyc = (uint32_t)min(max(ey, 0), ny - 1);
     const auto brs = buf_rsrc(A_.b, OP == OP_APPLY ? 0 : (int64_t)N * NBY);
     const auto dr = buf_rsrc(A_.dinv, OP == OP_SMOOTH || OP == OP_CHEB ? (int64_t)6 * N * sizeof(T) : 0);
-    const auto inr = buf_rsrc(A_.din, OP == OP_CHEB ? (int64_t)N * NBY : 0);
+    const auto inr = buf_rsrc(A_.din, OP == OP_CHEB && A_.din ? (int64_t)N * NBY : 0);
     const auto yr = buf_rsrc(A_.y, (int64_t)N * NBY);
     const auto dor = buf_rsrc(A_.dout, OP == OP_CHEB && A_.dout ? (int64_t)N * NBY : 0);
     const T fc1 = (T)c1, fc2 = (T)c2;
+    // PRO: the level-1 nodes around the column (two per axis, clamped)
+    const uint32_t CX = (uint32_t)nx / 2u + 1u, CY = (uint32_t)ny / 2u + 1u, CZ = (uint32_t)nz / 2u + 1u;
+    const auto cr = buf_rsrc(A_.xc, PRO ? (int64_t)CX * CY * CZ * NBY : 0);
+    const uint32_t ax = ix0 >> 1, ay = iy0 >> 1;
+    const uint32_t cxo[2] = {ax, (uint32_t)min(ax + 1u, CX - 1u)}, cyo[2] = {ay, (uint32_t)min(ay + 1u, CY - 1u)};
+    // weight of the lower level-1 node per axis at the column's two node
+    // positions (the upper one takes the rest): odd positions lie halfway,
+    // even ones on a level-1 node
+    T ux[2], uy[2];
+#pragma unroll
+    for (int lq = 0; lq < 2; ++lq) {
+        const uint32_t i = lq ? ix1 : ix0, j = lq ? iy1 : iy0;
+        ux[lq] = (i & 1u) ? T(0.5) : ((i >> 1) == ax ? T(1) : T(0));
+        uy[lq] = (j & 1u) ? T(0.5) : ((j >> 1) == ay ? T(1) : T(0));
+    }
+    // the four level-1 nodes of the column in level-1 plane a (clamped), and
+    // their interpolation to the face's corners in x and y
+    auto pro_plane = [&](int a, T (&cc)[2][2][3]) {
+        const uint32_t az = (uint32_t)min(a, (int)CZ - 1);
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int x = 0; x < 2; ++x) bld3(cr, ((az * CY + cyo[y]) * CX + cxo[x]) * NBY, cc[y][x]);
+    };
+    auto pro_xy = [&](const T (&cc)[2][2][3], T (&s)[4][3]) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const T u = ux[q & 1];
+                const T r0 = cc[0][1][c] + u * (cc[0][0][c] - cc[0][1][c]);
+                const T r1 = cc[1][1][c] + u * (cc[1][0][c] - cc[1][1][c]);
+                s[q][c] = r1 + uy[q >> 1] * (r0 - r1);
+            }
+    };
+    // PRO: the correction at the face's corners on level-1 plane za, and the
+    // level-1 values of plane za + 1
+    T sa[4][3], cb[2][2][3];
+    int za = -2;
     auto load_face = [&](int p, T (&v)[4][3]) {
-        const uint32_t pb = (uint32_t)min(max(p, 0), (int)NZ - 1) * PL * NBY;
+        const uint32_t pc = (uint32_t)min(max(p, 0), (int)NZ - 1);
+        const uint32_t pb = pc * PL * NBY;
 #pragma unroll
         for (int q = 0; q < 4; ++q) bld3(xr, pb + fo[q], v[q]);
+        if constexpr (PRO) {
+            // the march takes the planes in order, so each level-1 plane is
+            // loaded once: plane a + 1 as soon as the march reaches plane a
+            const int az = (int)(pc >> 1);
+            if (az != za) {
+                if (az == za + 1) {
+                    pro_xy(cb, sa);
+                } else {
+                    T c0[2][2][3];
+                    pro_plane(az, c0);
+                    pro_xy(c0, sa);
+                }
+                pro_plane(az + 1, cb);
+                za = az;
+            }
+            T sb[4][3];
+            pro_xy(cb, sb);
+            const T hz = (pc & 1u) ? T(0.5) : T(0);
+            uint32_t mk[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) mk[q] = __builtin_amdgcn_raw_buffer_load_b8(mr, pc * PL + fo[q] / NBY, 0, 0);
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const T a = sa[q][c] + hz * (sb[q][c] - sa[q][c]);
+                    v[q][c] += ((mk[q] >> c) & 1u) ? T(0) : a;
+                }
+        }
     };
     // operands of element layer l: its top face's corners and its modulus
     // (with weight 0 for an element outside the grid, applied where the
@@ -772,7 +845,7 @@ __device__ __forceinline__ void fine3sf_body(const Pack<OpA<T>, NB>& pk, const S
         load_face(k0 - 1, v0);
         Face F0;
         fetch_face(k0 - 1, F0);
-        if (!GAL) fetch(k0, OA);
+        if (!GAL && !PRO) fetch(k0, OA);
         sf_face_modes(v0, fb);
 #pragma unroll
         for (int q = 0; q < 4; ++q)
@@ -856,8 +929,9 @@ __device__ __forceinline__ void fine3sf_body(const Pack<OpA<T>, NB>& pk, const S
 #pragma unroll
         for (int c = 0; c < 3; ++c) xo[c] = C.f.v[3][c];
     };
-    if constexpr (GAL) {
-        // level 1 is bound by its arithmetic: each step fetches its own operands
+    if constexpr (GAL || PRO) {
+        // level 1 is bound by its arithmetic, and the prolonged iterate needs
+        // its loads at once: each step fetches its own operands
         for (int l = k0; l < k1; ++l) {
             Ops C;
             fetch(l, C);
@@ -883,6 +957,14 @@ __global__ __launch_bounds__(SF_TX * SF_TY) __attribute__((amdgpu_waves_per_eu(4
     int zlen, float omega, double c1, double c2) {
     __shared__ float cv[2][4][3][SF_TX * SF_TY];
     fine3sf_body<float, OP, NB>(pk, cf, nx, ny, nz, tiles_x, tiles_y, zlen, omega, c1, c2, cv);
+}
+
+template <int OP, int NB>
+__global__ __launch_bounds__(SF_TX * SF_TY) __attribute__((amdgpu_waves_per_eu(4))) void k_fine3sf_pro(const Pack<OpA<float>, NB> pk, const SfCoef<float> cf,
+                                                               int nx, int ny, int nz, int tiles_x, int tiles_y,
+                                                               int zlen, float omega, double c1, double c2) {
+    __shared__ float cv[2][4][3][SF_TX * SF_TY];
+    fine3sf_body<float, OP, NB, false, true>(pk, cf, nx, ny, nz, tiles_x, tiles_y, zlen, omega, c1, c2, cv);
 }
 
 template <typename T, int OP, int NB>
@@ -1222,6 +1304,56 @@ __global__ __launch_bounds__(WG) void k_fine2(const Pack<OpA<T>, NB> pk, const K
     double dots[2] = {0.0, 0.0};
     if (live) finish_store<T, 2, OP>(node, acc, xo, mo, fin, y, omega, dots, ch);
     if (OP == OP_QDOT) block_reduce_store<2>(dots, partials);
+}
+
+// the first post-smoothing step of the fine level with the prolongation from
+// level 1 in it: 3D, the FP32 tensor form, level 1 geometric and every fine
+// element count even (level-1 node I sits on fine node 2I)
+bool fine_pro_ok(const tm_hierarchy* h) {
+    int tx, ty, zl, nb;
+    if (h->lv.size() < 2 || h->lv[1].kind != TM_LEVEL_GEOMETRIC) return false;
+    if (!sf_grid(h, true, tx, ty, zl, nb)) return false;
+    const Level& F = h->lv[0];
+    return F.nel[0] % 2 == 0 && F.nel[1] % 2 == 0 && F.nel[2] % 2 == 0;
+}
+
+template <int OP, int NB>
+static void fine_pro_launch(const LaneIO* L, int n, float omega, double c1, double c2, hipStream_t s) {
+    const tm_hierarchy* h = L[0].h;
+    const Level& F = h->lv[0];
+    Pack<OpA<float>, NB> pk{};
+    for (int q = 0; q < n; ++q) {
+        const Level& Lq = L[q].h->lv[0];
+        OpA<float>& a = pk.a[q];
+        a.E = Lq.E32;
+        a.nm = Lq.nmask;
+        a.x = (const float*)L[q].x;
+        a.xc = (const float*)L[q].xc;
+        a.b = (const float*)L[q].b;
+        a.y = (float*)L[q].y;
+        a.dinv = Lq.dinv32;
+        a.done = L[q].done;
+        a.din = (const float*)L[q].din;
+        a.dout = (float*)L[q].dout;
+    }
+    int tx, ty, zl, nb;
+    sf_grid(h, true, tx, ty, zl, nb);
+    hipLaunchKernelGGL((k_fine3sf_pro<OP, NB>), dim3((unsigned)nb, n), dim3(SF_TX * SF_TY), 0, s, pk, h->sf32,
+                       F.nel[0], F.nel[1], F.nel[2], tx, ty, zl, omega, c1, c2);
+}
+
+void launch_fine_pro_b(int op, const LaneIO* L, int n, float omega, double c1, double c2, hipStream_t s) {
+    if (op != OP_SMOOTH && op != OP_CHEB) fail(TM_ERR_ARG, "fused prolongation: smoothing steps only");
+    for (int q0 = 0; q0 < n; q0 += MAXB) {
+        const int m = std::min(MAXB, n - q0);
+        if (op == OP_CHEB) {
+            if (m == 1) fine_pro_launch<OP_CHEB, 1>(L + q0, 1, omega, c1, c2, s);
+            else fine_pro_launch<OP_CHEB, MAXB>(L + q0, m, omega, c1, c2, s);
+        } else {
+            if (m == 1) fine_pro_launch<OP_SMOOTH, 1>(L + q0, 1, omega, c1, c2, s);
+            else fine_pro_launch<OP_SMOOTH, MAXB>(L + q0, m, omega, c1, c2, s);
+        }
+    }
 }
 
 // level 1 in the tensor form for lanes L[0..n) (n <= NB): the lanes' own

@@ -498,6 +498,10 @@ void launch_prolong_b(int fine_level, const LaneIO* L, int n, hipStream_t s);
 // OP_CHEB from the prolonged iterate) of a small geometric level whose coarse
 // level is geometric too; stencil_pro_ok says whether level l qualifies
 bool stencil_pro_ok(const tm_hierarchy* h, int level);
+// the same on the 3D fine level in the FP32 tensor form (fine_pro_ok says
+// whether h qualifies: level 1 geometric, even fine element counts)
+bool fine_pro_ok(const tm_hierarchy* h);
+void launch_fine_pro_b(int op, const LaneIO* L, int n, float omega, double c1, double c2, hipStream_t s);
 template <typename T>
 void launch_stencil_pro_b(int level, int op, const LaneIO* L, int n, T omega, double c1, double c2, hipStream_t s);
 template <typename T>

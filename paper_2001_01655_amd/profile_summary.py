@@ -26,9 +26,11 @@ COPY_BYTES = 256 << 20
 CLASSES = {
     0: dict(match=["k_fine3sf64<3, 1>"], source=["kernels_fine.hip", "tm_device.h"],
             what="fine operator FP64, tensor-product form (q = K~p, outer loop)"),
-    1: dict(match=["k_fine3sf<1, 1>", "k_fine3sf<2, 1>", "k_fine3sf<4, 1>"],
+    1: dict(match=["k_fine3sf<1, 1>", "k_fine3sf<2, 1>", "k_fine3sf<4, 1>", "k_fine3sf_pro<2, 1>",
+                   "k_fine3sf_pro<4, 1>"],
             source=["kernels_fine.hip", "tm_device.h"],
-            what="fine operator FP32, tensor-product form (V-cycle smoothing / residual)"),
+            what="fine operator FP32, tensor-product form (V-cycle smoothing / residual; the first "
+                 "post-smoothing step takes the prolongation in it)"),
     2: dict(match=["k_stencil_op<float, 3, 1, 4, 1>", "k_stencil_op<float, 3, 2, 4, 1>",
                    "k_stencil_op<float, 3, 4, 4, 1>"],
             source=["kernels_coarse.hip", "tm_device.h"], what="level-1 stencil operator FP32 (V-cycle)",
