@@ -44,6 +44,8 @@ def workload_label(wl, args, levels, coarsest):
     s = wl["desc"]
     if wl["levels"] is not None:
         s += f", {levels}-level GMG (coarsest {coarsest} dofs)"
+    if getattr(args, "n_geometric", None) is not None:
+        s += f", {args.n_geometric} geometric levels before the aggregation"
     w = wl["opts"].get("omega", 0.5)
     sm = f"block Jacobi w={w:g}" if args.smoother == "jacobi" else f"Chebyshev on [{args.cheb_lower:g}, 1.1] x lambda"
     return s + f", {sm} {args.sweeps}/{args.sweeps}, rtol 1e-8"
@@ -81,6 +83,8 @@ def parse():
     ap.add_argument("--served-warm-steps", type=int, default=4,
                     help="power steps of a design update's Chebyshev estimate, from the previous vector (0: 12 cold)")
     ap.add_argument("--levels", type=int, default=None, help="multigrid levels (default: the workload's)")
+    ap.add_argument("--n-geometric", type=int, default=None,
+                    help="geometric levels before smoothed aggregation (hybrid workloads; default: the workload's)")
     ap.add_argument("--smoother", default=None, choices=sorted(SMOOTHERS),
                     help="default: the workload's (chebyshev, block Jacobi for the MBB half-beam)")
     ap.add_argument("--sweeps", type=int, default=None, help="pre- and post-smoothing sweeps (default: the workload's, 2)")
@@ -666,6 +670,10 @@ def main():
     f = torch.tensor(p.loads[0], device="cuda")
     rtol = 1e-8
     opts = dict(wl["opts"])
+    if args.n_geometric is not None:
+        if "n_geometric" not in opts:
+            sys.exit("--n-geometric applies to the hybrid workloads only")
+        opts["n_geometric"] = args.n_geometric
     if wl["levels"] is not None:
         opts["n_levels"] = args.levels or wl["levels"]
 
