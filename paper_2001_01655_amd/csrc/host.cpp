@@ -747,6 +747,10 @@ static void vcycle_b(const VLane<T>* lanes, int n, hipStream_t s, bool first_don
         }
         level_op_b<T>(l, cheb ? OP_CHEB : OP_SMOOTH, io.data(), n, s, c1, c2);
     };
+    // a geometric transfer to the coarsest level is restricted inside the
+    // coarsest solve's launch
+    const bool tail_fused = restrict_solve_ok(h0);
+    std::vector<T*> rlast(n, nullptr);
     for (int l = 0; l < L - 1; ++l) {
         std::vector<T*>& x = xr[l];
         std::vector<T*>& t = tr[l];
@@ -774,6 +778,10 @@ static void vcycle_b(const VLane<T>* lanes, int n, hipStream_t s, bool first_don
             io[q].dout = nullptr;
         }
         level_op_b<T>(l, OP_RESID, io.data(), n, s);
+        if (l == L - 2 && tail_fused) {
+            for (int q = 0; q < n; ++q) rlast[q] = t[q];
+            break;
+        }
         for (int q = 0; q < n; ++q) {
             io[q].x = t[q];
             io[q].y = vb<T>(*lanes[q].V, l + 1);
@@ -783,11 +791,14 @@ static void vcycle_b(const VLane<T>* lanes, int n, hipStream_t s, bool first_don
         for (int q = 0; q < n; ++q) io[q].y2 = nullptr;
     }
     for (int q = 0; q < n; ++q) {
-        io[q].x = vb<T>(*lanes[q].V, L - 1);
+        io[q].x = tail_fused ? rlast[q] : vb<T>(*lanes[q].V, L - 1);
         io[q].y = vx<T>(*lanes[q].V, L - 1);
         xr[L - 1][q] = vx<T>(*lanes[q].V, L - 1);
     }
-    launch_dense_solve_b<T>(io.data(), n, s);
+    if (tail_fused)
+        launch_restrict_solve_b<T>(io.data(), n, s);
+    else
+        launch_dense_solve_b<T>(io.data(), n, s);
     for (int l = L - 2; l >= 0; --l) {
         std::vector<T*>& x = xr[l];
         std::vector<T*>& t = tr[l];

@@ -984,6 +984,137 @@ void launch_restrict_b(int fl, const LaneIO* L, int n, T omega, hipStream_t s) {
 template void launch_restrict_b<double>(int, const LaneIO*, int, double, hipStream_t);
 template void launch_restrict_b<float>(int, const LaneIO*, int, float, hipStream_t);
 
+// The last restriction and the coarsest solve in one launch: every workgroup
+// forms the whole coarsest right-hand side b_c = P~^T r_f (the gather of
+// k_restrict, per coarse node) in LDS, then four rows of x_c = A_c^-1 b_c,
+// one wave per row in the coarsest solve's summation order.
+template <typename T>
+struct RsolveA {
+    const T* rf;
+    const uint8_t* nm;
+    const double* Ainv;
+    T* x;
+    const int* done;
+};
+
+constexpr int RS_MAX = 4096;     // coarsest dofs (the dense factorisation's limit)
+
+template <typename T, int DIM, bool MASK, int NB>
+__global__ __launch_bounds__(WG) void k_restrict_solve(const Pack<RsolveA<T>, NB> pk, int fnx, int fny, int fnz,
+                                                       int cnx, int cny, int cnz, int nc) {
+    const RsolveA<T>& A_ = lane_of(pk);
+    if (A_.done && *A_.done) return;
+    __shared__ double bsh[RS_MAX];
+    const int CX = cnx + 1, CY = cny + 1, CZ = cnz + 1;
+    const int Nc = CX * CY * (DIM == 3 ? CZ : 1);
+    const int FX = fnx + 1, FY = fny + 1, FZ = fnz + 1;
+    const int64_t Nf = (int64_t)FX * FY * (DIM == 3 ? FZ : 1);
+    const auto rr = buf_rsrc(A_.rf, Nf * DIM * sizeof(T));
+    constexpr int NS = DIM == 3 ? 27 : 9;
+    for (int node = threadIdx.x; node < Nc; node += WG) {
+        const int I = node % CX, J = (node / CX) % CY, K = DIM == 3 ? node / (CX * CY) : 0;
+        T v[NS][DIM], w[NS];
+        uint8_t m[NS];
+#pragma unroll
+        for (int q = 0; q < NS; ++q) {
+            const int dx = q % 3 - 1, dy = (q / 3) % 3 - 1, dz = DIM == 3 ? q / 9 - 1 : 0;
+            const int gi = min(max(coarse_pos(I, fnx) + dx, 0), FX - 1);
+            const int gj = min(max(coarse_pos(J, fny) + dy, 0), FY - 1);
+            const int gk = DIM == 3 ? min(max(coarse_pos(K, fnz) + dz, 0), FZ - 1) : 0;
+            const uint32_t f = (uint32_t)(DIM == 3 ? (gk * FY + gj) * FX + gi : gj * FX + gi);
+            w[q] = restrict_w<T>(I, dx, fnx) * restrict_w<T>(J, dy, fny) * (DIM == 3 ? restrict_w<T>(K, dz, fnz) : T(1));
+            if constexpr (DIM == 3) {
+                bld3(rr, f * (uint32_t)(3 * sizeof(T)), v[q]);
+            } else {
+#pragma unroll
+                for (int c = 0; c < DIM; ++c) v[q][c] = bld<T>(rr, (DIM * f + c) * (uint32_t)sizeof(T));
+            }
+            m[q] = MASK ? A_.nm[f] : (uint8_t)0;
+        }
+        T acc[DIM] = {};
+#pragma unroll
+        for (int q = 0; q < NS; ++q)
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) acc[c] += ((m[q] >> c) & 1u) ? T(0) : w[q] * v[q][c];
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) bsh[DIM * node + c] = (double)acc[c];
+    }
+    __syncthreads();
+    const int row = (int)blockIdx.x * (WG / 64) + (int)(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (row >= nc) return;
+    const double* Ar = A_.Ainv + (int64_t)row * nc;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int c = lane;
+    for (; c + 192 < nc; c += 256) {
+        a0 += Ar[c] * bsh[c];
+        a1 += Ar[c + 64] * bsh[c + 64];
+        a2 += Ar[c + 128] * bsh[c + 128];
+        a3 += Ar[c + 192] * bsh[c + 192];
+    }
+    if (c < nc) a0 += Ar[c] * bsh[c];
+    if (c + 64 < nc) a1 += Ar[c + 64] * bsh[c + 64];
+    if (c + 128 < nc) a2 += Ar[c + 128] * bsh[c + 128];
+    double a = (a0 + a1) + (a2 + a3);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) a += __shfl_down(a, o, 64);
+    if (lane == 0) A_.x[row] = (T)a;
+}
+
+bool restrict_solve_ok(const tm_hierarchy* h) {
+    const int L = (int)h->lv.size();
+    if (L < 2 || h->lv[L - 2].xfer_bsr || h->nc > RS_MAX) return false;
+    const Level& c = h->lv[L - 1];
+    return (c.kind == TM_LEVEL_GEOMETRIC) && c.n == h->nc;
+}
+
+template <typename T, int DIM, bool MASK, int NB>
+static void restrict_solve_launch(const LaneIO* L, int n, hipStream_t s) {
+    const tm_hierarchy* h = L[0].h;
+    const int nl = (int)h->lv.size();
+    const Level& fine = h->lv[nl - 2];
+    const Level& coarse = h->lv[nl - 1];
+    Pack<RsolveA<T>, NB> pk{};
+    for (int q = 0; q < n; ++q) {
+        RsolveA<T>& a = pk.a[q];
+        a.rf = (const T*)L[q].x;
+        a.nm = MASK ? L[q].h->lv[nl - 2].nmask : nullptr;
+        a.Ainv = L[q].h->ainv;
+        a.x = (T*)L[q].y;
+        a.done = L[q].done;
+    }
+    const int nc = (int)h->nc;
+    const int fz = DIM == 3 ? fine.nel[2] : 0, cz = DIM == 3 ? coarse.nel[2] : 0;
+    hipLaunchKernelGGL((k_restrict_solve<T, DIM, MASK, NB>), dim3((unsigned)ceil_div(nc, WG / 64), n), dim3(WG), 0, s,
+                       pk, fine.nel[0], fine.nel[1], fz, coarse.nel[0], coarse.nel[1], cz, nc);
+}
+
+// x_c = A_c^-1 P~^T r_f for lanes L (x: the residual of the level above the
+// coarsest, y: the coarsest correction), where restrict_solve_ok holds
+template <typename T>
+void launch_restrict_solve_b(const LaneIO* L, int n, hipStream_t s) {
+    if (n < 1) return;
+    const tm_hierarchy* h = L[0].h;
+    if (!restrict_solve_ok(h)) fail(TM_ERR_ARG, "fused coarsest restriction: not a geometric coarsest transfer");
+    const int nl = (int)h->lv.size();
+    const int dim = h->lv[nl - 2].dim;
+    const bool mask = h->lv[nl - 2].kind == TM_LEVEL_FINE;
+    for (int q0 = 0; q0 < n; q0 += MAXB) {
+        const int m = std::min(MAXB, n - q0);
+#define TM_RS(D, M)                                                   \
+    if (m == 1) restrict_solve_launch<T, D, M, 1>(L + q0, 1, s);      \
+    else restrict_solve_launch<T, D, M, MAXB>(L + q0, m, s);
+        if (dim == 3) {
+            if (mask) { TM_RS(3, true) } else { TM_RS(3, false) }
+        } else {
+            if (mask) { TM_RS(2, true) } else { TM_RS(2, false) }
+        }
+#undef TM_RS
+    }
+}
+template void launch_restrict_solve_b<double>(const LaneIO*, int, hipStream_t);
+template void launch_restrict_solve_b<float>(const LaneIO*, int, hipStream_t);
+
 // prolongation x_f += M P x_c: fine node i interpolates from the coarse nodes
 // around it (1, 2, 4 or 8 of them), weights 1 or 1/2 per axis.
 template <typename T, int DIM, int NB>

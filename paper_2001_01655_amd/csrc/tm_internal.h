@@ -492,6 +492,11 @@ template <typename T>
 void launch_coarse1_tensor_b(int op, const LaneIO* L, int n, T omega, double c1, double c2, hipStream_t s);
 template <typename T>
 void launch_restrict_b(int fine_level, const LaneIO* L, int n, T omega, hipStream_t s);
+// the last restriction and the coarsest solve in one launch (geometric
+// transfer to a dense coarsest level)
+bool restrict_solve_ok(const tm_hierarchy* h);
+template <typename T>
+void launch_restrict_solve_b(const LaneIO* L, int n, hipStream_t s);
 template <typename T>
 void launch_prolong_b(int fine_level, const LaneIO* L, int n, hipStream_t s);
 // prolongation fused into the first post-smoothing step (op OP_SMOOTH or
