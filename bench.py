@@ -243,7 +243,9 @@ def roofline_entry(cls, launches, total_ms, H, p, args):
     tp = os.path.join(ROOT, "profiles", f"traffic_class{cls}.json")
     if os.path.exists(tp):
         t = json.load(open(tp))
-        if t.get("source_sha") == src_hash(KERNEL_SOURCES[cls]) and t.get("mix") == [args.smoother, args.sweeps]:
+        # (the summaries are taken on the default workload, the 3D cantilever)
+        if (t.get("source_sha") == src_hash(KERNEL_SOURCES[cls]) and t.get("mix") == [args.smoother, args.sweeps]
+                and args.workload == t.get("workload", "cantilever3d")):
             e["traffic"] = t.get("bytes_per_launch")
             e["traffic_ratio_to_algorithmic"] = round(t["bytes_per_launch"] / byts, 3)
     return e
